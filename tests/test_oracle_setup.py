@@ -1,0 +1,215 @@
+"""Pins of the oracle's Galerkin setup (strength, C/F split, direct
+interpolation, Galerkin product) against values the paper prints, closed forms
+and brute force."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_1512_04629_amd import inputs as I
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def poisson1d(n):
+    rows, cols, vals = [], [], []
+    for i in range(n):
+        for j, a in ((i - 1, -1.0), (i, 2.0), (i + 1, -1.0)):
+            if 0 <= j < n:
+                rows.append(i); cols.append(j); vals.append(a)
+    rp = np.zeros(n + 1, np.int32)
+    np.cumsum(np.bincount(rows, minlength=n), out=rp[1:])
+    return I.CSR(n, rp, np.array(cols, np.int32), np.array(vals))
+
+
+@pytest.mark.slow
+def test_table1_levels_0_1_exact(oracle_mod):
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "table1_poisson3d_100.txt"))
+            if l.strip() and not l.startswith("#")]
+    table = {int(r[0]): (int(r[1]), int(r[2])) for r in rows}
+    h = oracle_mod.OracleAMG(I.poisson3d(100))
+    for l in (0, 1):
+        s = h.sizes(l)
+        assert (s["n"], s["nnz"]) == table[l]
+    # deeper levels: same trend as the paper (n shrinking, nnz/row growing to
+    # a peak in the middle of the hierarchy); the paper used another coarsening
+    for l in (2, 3, 4):
+        s = h.sizes(l)
+        ref_n, ref_nnz = table[l]
+        assert 0.75 < s["n"] / ref_n < 1.25
+        assert s["nnz"] / s["n"] > h.sizes(l - 1)["nnz"] / h.sizes(l - 1)["n"] * 0.95 or l == 4
+
+
+def test_red_black_split_1d_2d(oracle_mod):
+    h = oracle_mod.OracleAMG(poisson1d(31), max_levels=2, max_coarse=1)
+    cf = h.cf(0)
+    assert np.array_equal(cf, (np.arange(31) % 2 == 1).astype(np.int32))
+    h = oracle_mod.OracleAMG(I.poisson2d(64))
+    cf = h.cf(0).reshape(64, 64)
+    ii, jj = np.indices((64, 64))
+    assert h.sizes(1)["n"] == 2048
+    assert len(np.unique(cf[(ii + jj) % 2 == 0])) == 1 and len(np.unique(cf[(ii + jj) % 2 == 1])) == 1
+
+
+@pytest.mark.parametrize("dim,N,diag,far,diagn", [(2, 16, 3.0, -0.25, -0.5), (3, 12, 5.0, -1.0 / 6, -1.0 / 3)])
+def test_coarse_stencil_closed_form(oracle_mod, dim, N, diag, far, diagn):
+    """Red-black coarsening with direct (here: linear) interpolation gives, in
+    the interior, the coarse stencil derived by hand from P^T A P:
+    2D: 3 at the centre, -1/4 at (+-2,0), -1/2 at (+-1,+-1);
+    3D: 5 at the centre, -1/6 at (+-2,0,0), -1/3 at (+-1,+-1,0); row sum 0."""
+    A = I.poisson2d(N) if dim == 2 else I.poisson3d(N)
+    h = oracle_mod.OracleAMG(A)
+    cf = h.cf(0)
+    A1 = h.export(1, "A").to_dense()
+    fine_of_coarse = np.nonzero(cf)[0]
+    coords = np.stack(np.unravel_index(fine_of_coarse, (N,) * dim)[::-1], 1)  # x fastest
+    inner = np.all((coords >= 3) & (coords <= N - 4), axis=1)
+    assert inner.sum() > 4
+    pos = {tuple(c): k for k, c in enumerate(coords)}
+    for I_ in np.nonzero(inner)[0]:
+        c = coords[I_]
+        row = A1[I_]
+        assert abs(row[I_] - diag) < 1e-14
+        assert abs(row.sum()) < 1e-14
+        for ax in range(dim):
+            for s in (-2, 2):
+                o = c.copy(); o[ax] += s
+                assert abs(row[pos[tuple(o)]] - far) < 1e-15
+        for a1 in range(dim):
+            for a2 in range(a1 + 1, dim):
+                for s1 in (-1, 1):
+                    for s2 in (-1, 1):
+                        o = c.copy(); o[a1] += s1; o[a2] += s2
+                        assert abs(row[pos[tuple(o)]] - diagn) < 1e-15
+        assert np.count_nonzero(row) == 1 + 2 * dim + 2 * dim * (dim - 1)
+
+
+PROBLEMS = {
+    "poisson2d": lambda: I.poisson2d(10),
+    "poisson3d": lambda: I.poisson3d(6),
+    "aniso2d": lambda: I.aniso2d(12),
+    "fv3d": lambda: I.fv3d_lognormal(6),
+    "graph": lambda: I.random_graph_laplacian(400),
+}
+
+
+@pytest.mark.parametrize("name", sorted(PROBLEMS))
+def test_galerkin_product_dense(oracle_mod, name):
+    """Every coarse operator equals the dense P^T A P (brute force), its
+    pattern equals the structural pattern of |P|^T |A| |P|, and it is
+    bitwise symmetric."""
+    h = oracle_mod.OracleAMG(PROBLEMS[name]())
+    assert h.nlev >= 2
+    for l in range(h.nlev - 1):
+        A = h.export(l, "A").to_dense()
+        P = h.export(l, "P").to_dense()
+        Ac = h.export(l + 1, "A")
+        D = Ac.to_dense()
+        ref = P.T @ A @ P
+        scale = np.abs(P.T) @ np.abs(A) @ np.abs(P)
+        assert np.all(np.abs(D - ref) <= 1e-13 * scale + 1e-300)
+        struct = (np.abs(P.T) @ (A != 0).astype(float) @ np.abs(P)) > 0
+        pat = np.zeros_like(struct)
+        rows = np.repeat(np.arange(Ac.nrows), np.diff(Ac.row_ptr))
+        pat[rows, Ac.col] = True
+        assert np.array_equal(pat, struct)
+        assert np.array_equal(D, D.T)
+
+
+@pytest.mark.parametrize("name", sorted(PROBLEMS))
+def test_interpolation_properties(oracle_mod, name):
+    """C rows inject; F rows interpolate only from strong C neighbours with
+    positive weights; on zero-row-sum F rows the weights sum to one (direct
+    interpolation reproduces constants); R is the exact transpose."""
+    h = oracle_mod.OracleAMG(PROBLEMS[name]())
+    for l in range(h.nlev - 1):
+        A = h.export(l, "A").to_dense()
+        S = h.export(l, "S").to_dense() != 0
+        P = h.export(l, "P").to_dense()
+        R = h.export(l, "R").to_dense()
+        cf = h.cf(l).astype(bool)
+        assert np.array_equal(R, P.T)
+        cidx = np.cumsum(cf) - 1
+        for i in range(A.shape[0]):
+            if cf[i]:
+                e = np.zeros(P.shape[1]); e[cidx[i]] = 1.0
+                assert np.array_equal(P[i], e)
+                continue
+            nzc = np.nonzero(P[i])[0]
+            strongC = np.nonzero(S[i] & cf)[0]
+            assert np.array_equal(np.sort(cidx[strongC]), nzc)
+            assert np.all(P[i, nzc] > 0)
+            if len(nzc) and abs(A[i].sum()) <= 1e-14 * abs(A[i, i]):
+                assert abs(P[i].sum() - 1.0) < 1e-13
+
+
+@pytest.mark.parametrize("name", sorted(PROBLEMS))
+def test_strength_and_split_validity(oracle_mod, name):
+    """S holds exactly the negative couplings with -a_ij >= 0.25 max_k(-a_ik),
+    and every F point with a strong dependency depends strongly on a C point
+    (so that its interpolation row is not empty)."""
+    h = oracle_mod.OracleAMG(PROBLEMS[name]())
+    for l in range(h.nlev - 1):
+        A = h.export(l, "A").to_dense()
+        S = h.export(l, "S").to_dense() != 0
+        cf = h.cf(l).astype(bool)
+        n = A.shape[0]
+        off = A - np.diag(np.diag(A))
+        mneg = np.max(np.where(off < 0, -off, 0.0), axis=1)
+        for i in range(n):
+            strong = np.nonzero(S[i])[0]
+            assert i not in strong
+            for j in strong:
+                assert A[i, j] < 0 and -A[i, j] >= 0.25 * mneg[i]
+            weak_neg = np.nonzero((off[i] < 0) & ~S[i])[0]
+            for j in weak_neg:
+                assert -A[i, j] < 0.25 * mneg[i]
+            if not cf[i] and S[i].any():
+                assert (S[i] & cf).any()
+
+
+def test_setup_rejects_bad_matrices(oracle_mod):
+    A = I.poisson2d(4)
+    bad = I.CSR(A.n, A.row_ptr.copy(), A.col.copy(), A.val.copy())
+    bad.val[1] = -0.5  # breaks bitwise symmetry
+    with pytest.raises(ValueError):
+        oracle_mod.OracleAMG(bad)
+    bad = I.CSR(A.n, A.row_ptr.copy(), A.col.copy(), A.val.copy())
+    bad.col[[0, 1]] = bad.col[[1, 0]]  # unsorted row
+    with pytest.raises(ValueError):
+        oracle_mod.OracleAMG(bad)
+
+
+def _rs_brute_force(S):
+    """Ruge-Stueben first pass with the measure recomputed from scratch at
+    every step: lambda_k = |{j in U: S_jk}| + 2 |{j in F: S_jk}|."""
+    n = S.shape[0]
+    U, C, F = 0, 1, 2
+    state = np.zeros(n, dtype=int)
+    for i in range(n):
+        if not S[i].any() and not S[:, i].any():
+            state[i] = F
+    while (state == U).any():
+        lam = ((S & (state == U)[:, None]).sum(0) + 2 * (S & (state == F)[:, None]).sum(0))
+        cand = np.nonzero(state == U)[0]
+        i = cand[np.argmax(lam[cand])]          # argmax returns the smallest index on ties
+        if lam[i] == 0 and (S[i] & (state == C)).any():
+            state[i] = F
+            continue
+        state[i] = C
+        state[(S[:, i]) & (state == U)] = F
+    return (state == C).astype(np.int32)
+
+
+@pytest.mark.parametrize("name", ["aniso2d", "fv3d", "graph", "poisson2d"])
+def test_rs_split_brute_force(oracle_mod, name):
+    # sizes chosen so that the strength graph is far from symmetric somewhere
+    # (lognormal coefficients, random graph), where the measure decrement
+    # for a new C point matters
+    small = {"aniso2d": lambda: I.aniso2d(12), "fv3d": lambda: I.fv3d_lognormal(8),
+             "graph": lambda: I.random_graph_laplacian(1000, degree=3),
+             "poisson2d": lambda: I.poisson2d(9)}
+    h = oracle_mod.OracleAMG(small[name]())
+    for l in range(h.nlev - 1):
+        S = h.export(l, "S").to_dense() != 0
+        assert np.array_equal(h.cf(l), _rs_brute_force(S))
