@@ -1,0 +1,253 @@
+"""Benchmark: sparsified AMG-PCG on the 3D Poisson problem, one MI355X.
+
+One step = the whole hot path on resident inputs: Sparse Galerkin
+sparsification of every coarse level (keep set + diagonal lumping, from the
+retained Galerkin operators) followed by an adaptive AMG-preconditioned CG
+solve to a 1e-8 relative residual (with reintroduction when the windowed
+convergence factor exceeds 0.5).  The Galerkin setup is a host-side
+prerequisite done once before timing (reported as setup_s).
+
+    python bench.py [--steps K] [--warmup W] [--gamma G] [--no-cpu-baseline]
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1512_04629_amd", "csrc", "kernels.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def launch_bytes(h, kernel: str, level: int) -> int:
+    """Algorithmic HBM bytes of one launch: FP64 values, int32 indices, each
+    array entry counted once (a gathered vector is counted as n entries)."""
+    li = h.level_info(level)
+    n, nnz_hat, nc, nnz_p = li["n"], li["nnz_hat"], li["n_coarse"], li["nnz_P"]
+    nnz_a = li["nnz"]
+    if kernel in ("JACOBI", "JACOBI_ZERO"):
+        return 12 * nnz_hat + 4 * (n + 1) + 32 * n
+    if kernel == "RESIDUAL":
+        nz = nnz_a if level == 0 else nnz_hat
+        return 12 * nz + 4 * (n + 1) + 24 * n
+    if kernel == "SPMV_DOT":
+        return 12 * nnz_a + 4 * (n + 1) + 16 * n
+    if kernel == "RESTRICT":
+        return 12 * nnz_p + 4 * (nc + 1) + 8 * n + 8 * nc
+    if kernel == "INTERP":
+        return 12 * nnz_p + 4 * (n + 1) + 8 * nc + 16 * n
+    return 0
+
+
+def kernel_source_sha() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def traffic_for(kernel: str, level: int):
+    """HBM bytes per launch from committed rocprofv3 counter runs, or None if
+    there are none for this kernel or the kernel source changed since."""
+    try:
+        data = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if data.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    ent = data.get("kernels", {}).get(f"{kernel}@{level}")
+    if not ent:
+        return None
+    return ent.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--N", type=int, default=128, help="grid side of the 3D Poisson problem")
+    ap.add_argument("--gamma", type=float, default=0.1, help="drop tolerance on levels >= 2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: this build has no multi-GPU path "
+              f"(--gpus {args.gpus} requested). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1512_04629_amd import amg
+    from paper_1512_04629_amd import inputs as I
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a ROCm GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    N = args.N
+    A = I.poisson3d(N)
+    b_host = I.rhs(A.n, 2)
+    b = torch.as_tensor(b_host).cuda()
+    x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    solve_kw = dict(method=amg.PCG, tol=1e-8, maxit=200, adaptive=True, k=3, s=1, rho_max=0.5,
+                    gamma_min=0.01)
+    log(f"[bench] setup 3D Poisson {N}^3 (n={A.n}, nnz={A.nnz})")
+    t0 = time.perf_counter()
+    h = amg.Hierarchy(A)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    log(f"[bench] setup done in {setup_s:.2f} s, {h.nlev} levels")
+
+    def step(gamma):
+        h.sparsify(gamma, 2)
+        x.zero_()
+        return h.solve(b, x, **solve_kw)
+
+    # sparsified vs Galerkin: time-to-1e-8 per gamma
+    compare = {}
+    for gamma in (0.0, 0.01, 0.1):
+        for _ in range(2):
+            res = step(gamma)
+        torch.cuda.synchronize()
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            res = step(gamma)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / reps * 1e3
+        compare[str(gamma)] = dict(
+            ms_to_1e8=round(ms, 3), iters=res.iters, reintroductions=res.reintroductions,
+            relres=res.relres, converged=res.converged,
+            nnz_per_level=[h.level_info(l)["nnz_hat"] for l in range(h.nlev)],
+            gamma_after=[h.gamma(l) for l in range(h.nlev)],
+            bytes_per_vcycle=h.bytes_per_cycle())
+        log(f"[bench] gamma={gamma}: {ms:.2f} ms, {res.iters} iters, relres {res.relres:.2e}")
+
+    # find the dominant kernel (class, level) by HIP-event time over one step
+    h.profile_enable(True)
+    step(args.gamma)
+    best = None
+    for kern in ("JACOBI", "JACOBI_ZERO", "RESIDUAL", "RESTRICT", "INTERP", "SPMV_DOT"):
+        for l in range(h.nlev):
+            cnt, ms = h.profile_read(kern, l)
+            if cnt and (best is None or ms > best[2]):
+                best = (kern, l, ms, cnt)
+    h.profile_enable(False)
+    dom_kernel, dom_level = best[0], best[1]
+    log(f"[bench] dominant kernel {dom_kernel} on level {dom_level}")
+
+    # timed region: K steps, the dominant kernel bracketed by HIP events
+    for _ in range(args.warmup):
+        step(args.gamma)
+    torch.cuda.synchronize()
+    h.profile_enable(True, dom_kernel, dom_level)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = step(args.gamma)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    cnt, ms_total = h.profile_read(dom_kernel, dom_level)
+    h.profile_enable(False)
+    ms_per_step = elapsed / args.steps * 1e3
+    value = args.steps / elapsed
+    per_launch_s = ms_total / max(cnt, 1) / 1e3
+    nbytes = launch_bytes(h, dom_kernel, dom_level)
+    achieved = nbytes / per_launch_s / 1e9
+    traffic = traffic_for(dom_kernel, dom_level)
+    log(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step; {dom_kernel}@{dom_level}: "
+        f"{per_launch_s * 1e6:.1f} us/launch, {achieved:.0f} GB/s")
+
+    # SpMV bandwidth of the fine-level operator (the CG product A p)
+    h.profile_enable(True, "SPMV_DOT", 0)
+    step(args.gamma)
+    c2, m2 = h.profile_read("SPMV_DOT", 0)
+    h.profile_enable(False)
+    spmv_gbs = launch_bytes(h, "SPMV_DOT", 0) / (m2 / c2 / 1e3) / 1e9 if c2 else None
+
+    out = {
+        "metric": "solves/s to 1e-8 relative residual (Sparse Galerkin sparsify + adaptive AMG-PCG); "
+                  "time-to-1e-8 sparsified vs Galerkin; SpMV HBM GB/s",
+        "value": round(value, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"3D Poisson 7-point FD {N}^3 (n={A.n}, nnz={A.nnz}), RHS uniform[-1,1] seed 2; "
+                        f"RS theta=0.25, direct interpolation, coarsen to <50 rows; Sparse Galerkin "
+                        f"gamma={args.gamma} on levels>=2 with diagonal lumping; V(1,1) Jacobi "
+                        f"omega=2/3; adaptive AMG-PCG (k=3, s=1, rho_max=0.5) to 1e-8",
+            "levels": h.nlev,
+            "gamma": args.gamma,
+        },
+        "iters": res.iters,
+        "relres": res.relres,
+        "setup_s": round(setup_s, 3),
+        "time_to_1e8_ms": compare,
+        "speedup_vs_galerkin": round(compare["0.0"]["ms_to_1e8"] / compare[str(args.gamma)]["ms_to_1e8"], 4)
+        if str(args.gamma) in compare else None,
+        "spmv_gbs_level0": round(spmv_gbs, 1) if spmv_gbs else None,
+        "roofline": {
+            "bound": "hbm",
+            "kernel": f"{dom_kernel} level {dom_level}",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "bytes_per_launch": nbytes,
+            "us_per_launch": round(per_launch_s * 1e6, 3),
+            "launches": cnt,
+        },
+    }
+
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        log("[bench] CPU baseline: oracle setup (untimed) ...")
+        o = O.OracleAMG(A)
+        steps_done = 0
+        t0 = time.perf_counter()
+        while steps_done < args.cpu_steps:
+            o.sparsify_from(args.gamma, 2)
+            o.solve(b_host, method=O.PCG, tol=1e-8, maxit=200, adaptive=True, k=3, s=1)
+            steps_done += 1
+            if time.perf_counter() - t0 > 30.0:
+                break
+        cpu_s = time.perf_counter() - t0
+        out["cpu_baseline"] = {
+            "value": round(steps_done / cpu_s, 5),
+            "unit": "solves/s",
+            "cores": 1,
+            "kind": "oracle",
+            "sample": f"{steps_done} full steps (sparsify gamma={args.gamma} + adaptive PCG to 1e-8) "
+                      f"of the same {N}^3 workload, single-threaded C oracle, setup excluded",
+        }
+        log(f"[bench] CPU baseline {steps_done / cpu_s:.4f} solves/s")
+
+    h.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,214 @@
+/*
+ * amg.h -- C ABI of the MI355X sparsified-AMG library (libamg355.so).
+ *
+ * Method: Bienz, Falgout, Gropp, Olson, Schroder, "Reducing Parallel
+ * Communication in Algebraic Multigrid through Sparsification".  The library
+ * solves A x = b for a symmetric positive definite A (Section 1) in two
+ * phases: a setup that builds the Galerkin hierarchy (Section 2, amg_setup)
+ * and retains it, a sparsification post-pass over the coarse operators
+ * (Section 3, Sparse Galerkin, with the diagonal lumping of Algorithm 3b,
+ * Section 3.1), and a solve phase (Section 2, amg_solve V-cycle; used alone
+ * or as the preconditioner of CG) with the adaptive reintroduction of
+ * Section 6 (adaptive_solve).
+ *
+ * Conventions for every entry point:
+ *  - No C++ exception crosses the ABI; every call returns an amg_status.
+ *  - Matrices are CSR with int32 row pointers (n+1), int32 column indices
+ *    sorted ascending within each row, and float64 values.
+ *  - "Device" pointers are HIP device memory on the GPU that was current
+ *    when the handle was created; all device work is issued on the handle's
+ *    stream.  "Host" pointers are ordinary host memory.
+ *  - A handle is not thread safe.  Distinct handles are independent.
+ *  - A failed call leaves the previously built hierarchy usable: new
+ *    sparsified operators are built first and swapped in afterwards.
+ *  - On failure amg_last_error(h) describes the cause.
+ */
+#ifndef AMG355_AMG_H
+#define AMG355_AMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct amg_ctx* amg_handle;
+
+typedef enum {
+    AMG_OK = 0,
+    AMG_NOTHING_TO_REINTRODUCE = 1, /* informational: every coarse gamma is already 0 */
+    AMG_ERR_INVALID_ARG = -1,       /* NULL pointer, n <= 0, gamma NaN or outside [0,1], bad params */
+    AMG_ERR_BAD_MATRIX = -2,        /* unsorted/duplicate/out-of-range column, missing or
+                                       non-positive diagonal, non-finite value, not bitwise symmetric */
+    AMG_ERR_OUT_OF_MEMORY = -3,     /* the allocator returned NULL */
+    AMG_ERR_DEVICE = -4,            /* a HIP call failed */
+    AMG_ERR_NOT_CONVERGED = -5,     /* maxit reached; x holds the last iterate, info is filled */
+    AMG_ERR_BREAKDOWN = -6,         /* non-finite residual, or p^T A p <= 0 in CG */
+    AMG_ERR_STATE = -7              /* call out of order (e.g. on a destroyed or failed handle) */
+} amg_status;
+
+/* Device-memory allocator.  alloc returns device memory of at least `bytes`
+   usable on `stream`, or NULL.  free releases a block returned by alloc.
+   Passing NULL for both uses hipMalloc / hipFree.  The Python binding passes
+   PyTorch's caching allocator. */
+typedef void* (*amg_alloc_fn)(size_t bytes, void* stream, void* user);
+typedef void (*amg_free_fn)(void* ptr, size_t bytes, void* stream, void* user);
+
+/* Setup parameters (Section 2, amg_setup inputs; strength and interpolation
+   formulas are the classical Ruge-Stueben ones the paper cites). */
+typedef struct {
+    double theta;        /* strength threshold, default 0.25 */
+    int32_t max_coarse;  /* coarsen while n > max_coarse (max_size), default 49 */
+    int32_t max_levels;  /* at most this many levels, default 25 */
+    double omega;        /* weighted-Jacobi weight, default 2/3 */
+    int32_t nu_pre;      /* pre-smoothing sweeps, default 1 */
+    int32_t nu_post;     /* post-smoothing sweeps, default 1 */
+} amg_setup_params;
+
+enum { AMG_STATIONARY = 0, AMG_PCG = 1 };
+
+/* Solve parameters (Section 6, adaptive_solve inputs k, s, tol and the
+   gamma floor gamma_min). */
+typedef struct {
+    int32_t method;      /* AMG_STATIONARY or AMG_PCG, default AMG_PCG */
+    double rtol;         /* converged when ||r|| <= rtol ||r0||, default 1e-8 */
+    int32_t maxit;       /* default 200 */
+    int32_t adaptive;    /* 0/1: windowed reintroduction, default 0 */
+    int32_t k;           /* iterations per convergence window, default 3 */
+    int32_t s;           /* levels updated per reintroduction, default 1 */
+    double rho_max;      /* reintroduce when the window factor exceeds this, default 0.5 */
+    double gamma_min;    /* new gamma below this becomes 0, default 0.01 */
+} amg_solve_params;
+
+typedef struct {
+    int32_t iters;            /* iterations taken (all windows) */
+    int32_t restarts;         /* CG restarts after a hierarchy change */
+    int32_t reintroductions;  /* calls of the gamma ladder that changed the hierarchy */
+    int32_t converged;        /* 1 if ||r|| <= rtol ||r0|| */
+    double relres;            /* true ||b - A x|| / ||b - A x0|| at exit */
+    double rho_avg;           /* relres^(1/iters) */
+} amg_solve_info;
+
+void amg_setup_params_default(amg_setup_params* p);
+void amg_solve_params_default(amg_solve_params* p);
+
+/* Build the Galerkin hierarchy of A_0 (Section 2, amg_setup without the
+   optional sparsify, as Section 3's sparse_hybrid_setup prescribes).
+   row_ptr/col/val: host arrays of A_0, copied; the caller keeps them.
+   params: NULL for defaults.  stream: hipStream_t for all device work
+   (NULL = default stream).  alloc/free/user: device allocator (both NULL or
+   both set).  On success *out holds a new handle with every coarse gamma 0
+   (sparsified operators equal the Galerkin ones). */
+amg_status amg_setup_from_csr(int64_t n, const int32_t* row_ptr, const int32_t* col,
+                              const double* val, const amg_setup_params* params,
+                              void* stream, amg_alloc_fn alloc, amg_free_fn free_fn,
+                              void* user, amg_handle* out);
+
+/* Sparse Galerkin sparsification with diagonal lumping (Algorithm 3 keep set,
+   Algorithm 3b loop) of every level l >= first_level (first_level >= 1) with
+   drop tolerance gamma in [0, 1]; levels below first_level get gamma 0.  The
+   minimal pattern M_l and the row maxima of A_l are computed on the first
+   call and cached; the result replaces the sparsified operators. */
+amg_status amg_sparsify(amg_handle h, double gamma, int32_t first_level);
+
+/* Same, with one tolerance per level: gamma[l] for l = 0 .. count-1
+   (gamma[0] is ignored: A_0 is never sparsified; levels >= count get 0). */
+amg_status amg_sparsify_levels(amg_handle h, const double* gamma, int32_t count);
+
+/* Reintroduction (Section 6, adaptive_solve and its Example): find the
+   finest coarse level with gamma > 0 and, on it and the next s-1 levels,
+   set gamma <- gamma/10 (0 if gamma/10 < gamma_min), re-sparsifying them
+   from the retained Galerkin operators.  *first_changed_level (nullable)
+   receives that level, or -1 with AMG_NOTHING_TO_REINTRODUCE. */
+amg_status amg_reintroduce(amg_handle h, int32_t s, double gamma_min,
+                           int32_t* first_changed_level);
+
+/* Solve A_0 x = b.  b, x: device arrays of n doubles; x holds x0 on entry
+   and the result on exit.  Stationary: x <- V(b, x) per iteration.  PCG:
+   Hestenes-Stiefel CG preconditioned by one V-cycle z = V(r, 0), stop test on
+   the recursively updated residual.  With params->adaptive, every k
+   iterations the true residual is formed; if the window factor
+   (||r_end||/||r_start||)^(1/k) exceeds rho_max and some coarse gamma > 0,
+   amg_reintroduce(h, s, gamma_min) is applied, x reverts to the window start
+   if the window diverged, and CG restarts.  params NULL = defaults.  info
+   (nullable) is filled on every return that ran iterations.  hist (nullable,
+   host, maxit+1 doubles) receives ||r_0|| and the residual norm after each
+   iteration. */
+amg_status amg_solve(amg_handle h, const double* b, double* x, const amg_solve_params* params,
+                     amg_solve_info* info, double* hist);
+
+/* One V-cycle (Section 2, amg_solve) in place: x <- V(b, x); device arrays. */
+amg_status amg_vcycle(amg_handle h, const double* b, double* x);
+
+/* Single steps of the V-cycle on level l, device arrays (for component
+   checks and for callers composing their own cycles):
+     AMG_OP_RESIDUAL     out = b - Ahat_l x                 (in = b)
+     AMG_OP_JACOBI       out = x + omega D^-1 (b - Ahat_l x) (in = b)
+     AMG_OP_RESTRICT     out = P_l^T in        (out has n_{l+1} entries)
+     AMG_OP_INTERPOLATE  out = x + P_l in      (in has n_{l+1} entries)
+     AMG_OP_COARSE_SOLVE out = Ahat_L^-1 in    (l ignored)
+     AMG_OP_SPMV_A       out = A_l x           (Galerkin operator)
+     AMG_OP_SPMV_AHAT    out = Ahat_l x                                   */
+enum {
+    AMG_OP_RESIDUAL = 0, AMG_OP_JACOBI = 1, AMG_OP_RESTRICT = 2, AMG_OP_INTERPOLATE = 3,
+    AMG_OP_COARSE_SOLVE = 4, AMG_OP_SPMV_A = 5, AMG_OP_SPMV_AHAT = 6
+};
+amg_status amg_level_op(amg_handle h, int32_t level, int32_t op, const double* in,
+                        const double* x, double* out);
+
+amg_status amg_num_levels(amg_handle h, int32_t* nlev);
+
+/* Sizes of level l; any output pointer may be NULL.  bytes = algorithmic HBM
+   bytes of one V-cycle's work on this level (relaxation, residual and
+   transfers with the current sparsified operator). */
+amg_status amg_get_level(amg_handle h, int32_t l, int64_t* n, int64_t* nnz_galerkin,
+                         int64_t* nnz_sparse, int64_t* nnz_p, int64_t* n_coarse,
+                         double* gamma, int64_t* bytes);
+
+/* Copy an operator of level l into caller-allocated host arrays sized from
+   amg_get_level: row_ptr (rows+1), col and val (nnz).  which: AMG_MAT_A
+   (Galerkin A_l), AMG_MAT_AHAT (sparsified), AMG_MAT_P (P_l, n_l x n_{l+1}),
+   AMG_MAT_R (R_l = P_l^T). */
+enum { AMG_MAT_A = 0, AMG_MAT_AHAT = 1, AMG_MAT_P = 2, AMG_MAT_R = 3 };
+amg_status amg_export_level(amg_handle h, int32_t l, int32_t which, int32_t* row_ptr,
+                            int32_t* col, double* val);
+
+/* Per-nonzero flags of A_l (host array of nnz_galerkin bytes): AMG_MASK_M
+   the minimal pattern M_l, AMG_MASK_KEEP the keep decision of the last
+   sparsification of level l.  Levels >= 1, after a sparsify call. */
+enum { AMG_MASK_M = 0, AMG_MASK_KEEP = 1 };
+amg_status amg_export_mask(amg_handle h, int32_t l, int32_t which, uint8_t* out);
+
+/* Per-row vectors of level l (host array of n_l doubles): AMG_VEC_ROWMAX
+   m_i = max_{k!=i} |a_ik| of A_l (after a sparsify call), AMG_VEC_DINV
+   1/diag(Ahat_l). */
+enum { AMG_VEC_ROWMAX = 0, AMG_VEC_DINV = 1 };
+amg_status amg_export_vector(amg_handle h, int32_t l, int32_t which, double* out);
+
+/* C/F split of level l < L (host array of n_l ints, 1 = C). */
+amg_status amg_export_split(amg_handle h, int32_t l, int32_t* cf);
+
+/* Kernel timing with HIP events on the handle's stream.  While enabled,
+   every launch of a kernel of class kernel_class (-1: every class) on level
+   `level` (-1: every level) is bracketed by a pair of events;
+   amg_profile_read returns the number of bracketed launches and their summed
+   duration in milliseconds since the last amg_profile_enable call.  Classes:
+   AMG_K_*.  Enabling resets the counters; enable = 0 stops timing. */
+enum {
+    AMG_K_JACOBI = 0, AMG_K_JACOBI_ZERO = 1, AMG_K_RESIDUAL = 2, AMG_K_RESTRICT = 3,
+    AMG_K_INTERP = 4, AMG_K_COARSE = 5, AMG_K_SPMV_DOT = 6, AMG_K_VECTOR = 7,
+    AMG_K_SPARSIFY = 8, AMG_K_NUM = 9
+};
+amg_status amg_profile_enable(amg_handle h, int32_t enable, int32_t kernel_class, int32_t level);
+amg_status amg_profile_read(amg_handle h, int32_t kernel_class, int32_t level, int64_t* count,
+                            double* total_ms);
+
+void amg_destroy(amg_handle h);
+const char* amg_status_string(amg_status s);
+const char* amg_last_error(amg_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AMG355_AMG_H */

@@ -177,6 +177,7 @@ class OracleAMG:
 
     def sparsify(self, gammas) -> None:
         g = np.zeros(self.nlev, np.float64)
+        gammas = list(gammas)[: self.nlev]
         g[: len(gammas)] = gammas
         rc = self._lib.or_sparsify(self._h, g)
         if rc != OK:

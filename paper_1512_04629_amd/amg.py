@@ -1,0 +1,307 @@
+"""Python binding of libamg355 (the C ABI declared in include/amg.h).
+
+Argument marshalling only: every step of setup upload, sparsification and
+solve runs in the library.  Device arrays are torch CUDA tensors (float64,
+contiguous); device memory owned by the library comes from PyTorch's caching
+allocator through the ABI's allocator callback, and all work is issued on
+the torch stream current when the hierarchy is created.
+
+The library must be built (``python -m paper_1512_04629_amd.build``); there is
+no fallback path: loading fails loudly if the shared object is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libamg355.so")
+
+OK, NOTHING_TO_REINTRODUCE = 0, 1
+STATIONARY, PCG = 0, 1
+MAT = {"A": 0, "AHAT": 1, "P": 2, "R": 3}
+MASK = {"M": 0, "KEEP": 1}
+VEC = {"ROWMAX": 0, "DINV": 1}
+OP = {"RESIDUAL": 0, "JACOBI": 1, "RESTRICT": 2, "INTERPOLATE": 3, "COARSE_SOLVE": 4,
+      "SPMV_A": 5, "SPMV_AHAT": 6}
+KERNEL = {"JACOBI": 0, "JACOBI_ZERO": 1, "RESIDUAL": 2, "RESTRICT": 3, "INTERP": 4,
+          "COARSE": 5, "SPMV_DOT": 6, "VECTOR": 7, "SPARSIFY": 8}
+
+# every symbol include/amg.h declares
+ABI_SYMBOLS = (
+    "amg_setup_params_default", "amg_solve_params_default", "amg_setup_from_csr",
+    "amg_sparsify", "amg_sparsify_levels", "amg_reintroduce", "amg_solve", "amg_vcycle",
+    "amg_level_op", "amg_num_levels", "amg_get_level", "amg_export_level", "amg_export_mask",
+    "amg_export_vector", "amg_export_split", "amg_profile_enable", "amg_profile_read",
+    "amg_destroy", "amg_status_string", "amg_last_error",
+)
+
+
+class AmgError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class SetupParams(C.Structure):
+    _fields_ = [("theta", C.c_double), ("max_coarse", C.c_int32), ("max_levels", C.c_int32),
+                ("omega", C.c_double), ("nu_pre", C.c_int32), ("nu_post", C.c_int32)]
+
+
+class SolveParams(C.Structure):
+    _fields_ = [("method", C.c_int32), ("rtol", C.c_double), ("maxit", C.c_int32),
+                ("adaptive", C.c_int32), ("k", C.c_int32), ("s", C.c_int32),
+                ("rho_max", C.c_double), ("gamma_min", C.c_double)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("reintroductions", C.c_int32),
+                ("converged", C.c_int32), ("relres", C.c_double), ("rho_avg", C.c_double)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+
+_lib = None
+
+
+def load_library():
+    """Loads libamg355.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1512_04629_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, i64, f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    P = C.POINTER
+    lib.amg_setup_params_default.argtypes = [P(SetupParams)]
+    lib.amg_solve_params_default.argtypes = [P(SolveParams)]
+    lib.amg_setup_from_csr.argtypes = [i64, vp, vp, vp, P(SetupParams), vp, ALLOC_FN, FREE_FN, vp, P(vp)]
+    lib.amg_sparsify.argtypes = [vp, f64, i32]
+    lib.amg_sparsify_levels.argtypes = [vp, vp, i32]
+    lib.amg_reintroduce.argtypes = [vp, i32, f64, P(i32)]
+    lib.amg_solve.argtypes = [vp, vp, vp, P(SolveParams), P(SolveInfo), vp]
+    lib.amg_vcycle.argtypes = [vp, vp, vp]
+    lib.amg_level_op.argtypes = [vp, i32, i32, vp, vp, vp]
+    lib.amg_num_levels.argtypes = [vp, P(i32)]
+    lib.amg_get_level.argtypes = [vp, i32, P(i64), P(i64), P(i64), P(i64), P(i64), P(f64), P(i64)]
+    lib.amg_export_level.argtypes = [vp, i32, i32, vp, vp, vp]
+    lib.amg_export_mask.argtypes = [vp, i32, i32, vp]
+    lib.amg_export_vector.argtypes = [vp, i32, i32, vp]
+    lib.amg_export_split.argtypes = [vp, i32, vp]
+    lib.amg_profile_enable.argtypes = [vp, i32, i32, i32]
+    lib.amg_profile_read.argtypes = [vp, i32, i32, P(i64), P(f64)]
+    lib.amg_destroy.argtypes = [vp]
+    lib.amg_destroy.restype = None
+    lib.amg_status_string.argtypes = [C.c_int]
+    lib.amg_status_string.restype = C.c_char_p
+    lib.amg_last_error.argtypes = [vp]
+    lib.amg_last_error.restype = C.c_char_p
+    for name in ("amg_setup_from_csr", "amg_sparsify", "amg_sparsify_levels", "amg_reintroduce",
+                 "amg_solve", "amg_vcycle", "amg_level_op", "amg_num_levels", "amg_get_level",
+                 "amg_export_level", "amg_export_mask", "amg_export_vector", "amg_export_split",
+                 "amg_profile_enable", "amg_profile_read"):
+        getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("libamg355 needs a ROCm GPU (torch.cuda.is_available() is False)")
+    return torch
+
+
+@C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+def _torch_alloc(nbytes, stream, user):
+    import torch
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+    except Exception:       # reported to the library as NULL -> out of memory
+        return None
+
+
+@C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+def _torch_free(ptr, nbytes, stream, user):
+    import torch
+    if ptr:
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+
+@dataclass
+class SolveResult:
+    status: int
+    iters: int
+    restarts: int
+    reintroductions: int
+    converged: bool
+    relres: float
+    rho_avg: float
+    hist: np.ndarray
+
+
+def _dptr(t, n=None, name="array"):
+    torch = _torch()
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous float64 CUDA tensor")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} entries, expected {n}")
+    return C.c_void_p(t.data_ptr())
+
+
+class Hierarchy:
+    """A device-resident AMG hierarchy (one amg_handle)."""
+
+    def __init__(self, A, theta=0.25, max_coarse=49, max_levels=25, omega=2.0 / 3.0,
+                 nu_pre=1, nu_post=1, torch_allocator=True):
+        torch = _torch()
+        lib = load_library()
+        self._lib = lib
+        self.n = int(A.n)
+        rp = np.ascontiguousarray(A.row_ptr, np.int32)
+        ci = np.ascontiguousarray(A.col, np.int32)
+        v = np.ascontiguousarray(A.val, np.float64)
+        sp = SetupParams(float(theta), int(max_coarse), int(max_levels), float(omega),
+                         int(nu_pre), int(nu_post))
+        self.stream = torch.cuda.current_stream()
+        h = C.c_void_p()
+        alloc = _torch_alloc if torch_allocator else ALLOC_FN()
+        free = _torch_free if torch_allocator else FREE_FN()
+        st = lib.amg_setup_from_csr(self.n, rp.ctypes.data, ci.ctypes.data, v.ctypes.data,
+                                    C.byref(sp), C.c_void_p(self.stream.cuda_stream), alloc, free,
+                                    None, C.byref(h))
+        if st != OK:
+            raise AmgError(st, lib.amg_last_error(None).decode())
+        self._h = h
+        nl = C.c_int32()
+        self._check(lib.amg_num_levels(h, C.byref(nl)))
+        self.nlev = nl.value
+
+    # -- plumbing --------------------------------------------------------
+    def _check(self, st, allowed=(OK,)):
+        if st not in allowed:
+            raise AmgError(st, self._lib.amg_last_error(self._h).decode() or
+                           self._lib.amg_status_string(st).decode())
+        return st
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.amg_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- sparsification ------------------------------------------------------
+    def sparsify(self, gamma: float, first_level: int = 2):
+        self._check(self._lib.amg_sparsify(self._h, float(gamma), int(first_level)))
+
+    def sparsify_levels(self, gammas):
+        g = np.ascontiguousarray(gammas, np.float64)
+        self._check(self._lib.amg_sparsify_levels(self._h, g.ctypes.data, len(g)))
+
+    def reintroduce(self, s: int = 1, gamma_min: float = 0.01):
+        first = C.c_int32(-1)
+        st = self._check(self._lib.amg_reintroduce(self._h, int(s), float(gamma_min), C.byref(first)),
+                         allowed=(OK, NOTHING_TO_REINTRODUCE))
+        return st, first.value
+
+    # -- solve -------------------------------------------------------------
+    def solve(self, b, x, method=PCG, tol=1e-8, maxit=200, adaptive=False, k=3, s=1,
+              rho_max=0.5, gamma_min=0.01, raise_on_error=False) -> SolveResult:
+        p = SolveParams(int(method), float(tol), int(maxit), int(bool(adaptive)), int(k), int(s),
+                        float(rho_max), float(gamma_min))
+        info = SolveInfo()
+        hist = np.full(maxit + 1, np.nan)
+        st = self._lib.amg_solve(self._h, _dptr(b, self.n, "b"), _dptr(x, self.n, "x"), C.byref(p),
+                                 C.byref(info), hist.ctypes.data)
+        if st not in (OK, -5, -6) or raise_on_error:
+            self._check(st)
+        return SolveResult(st, info.iters, info.restarts, info.reintroductions, bool(info.converged),
+                           info.relres, info.rho_avg, hist[: info.iters + 1].copy())
+
+    def vcycle(self, b, x):
+        self._check(self._lib.amg_vcycle(self._h, _dptr(b, self.n, "b"), _dptr(x, self.n, "x")))
+
+    def level_op(self, level: int, op: str, inp=None, x=None, out=None):
+        args = [C.c_void_p(t.data_ptr()) if t is not None else None for t in (inp, x, out)]
+        for t, name in ((inp, "in"), (x, "x"), (out, "out")):
+            if t is not None:
+                _dptr(t, None, name)
+        self._check(self._lib.amg_level_op(self._h, int(level), OP[op], *args))
+
+    # -- inspection ---------------------------------------------------------
+    def level_info(self, l: int) -> dict:
+        vals = [C.c_int64() for _ in range(5)]
+        g = C.c_double()
+        by = C.c_int64()
+        self._check(self._lib.amg_get_level(self._h, int(l), *[C.byref(v) for v in vals],
+                                            C.byref(g), C.byref(by)))
+        n, nnz, nnz_hat, nnz_p, nc = (v.value for v in vals)
+        return dict(n=n, nnz=nnz, nnz_hat=nnz_hat, nnz_P=nnz_p, n_coarse=nc, gamma=g.value,
+                    bytes=by.value)
+
+    def export(self, l: int, which: str):
+        s = self.level_info(l)
+        if which in ("A", "AHAT"):
+            nr, nc, nnz = s["n"], s["n"], s["nnz"] if which == "A" else s["nnz_hat"]
+        elif which == "P":
+            nr, nc, nnz = s["n"], s["n_coarse"], s["nnz_P"]
+        else:
+            nr, nc, nnz = s["n_coarse"], s["n"], s["nnz_P"]
+        rp = np.zeros(nr + 1, np.int32)
+        ci = np.zeros(max(nnz, 1), np.int32)
+        v = np.zeros(max(nnz, 1), np.float64)
+        self._check(self._lib.amg_export_level(self._h, int(l), MAT[which], rp.ctypes.data,
+                                               ci.ctypes.data, v.ctypes.data))
+        return nr, nc, rp, ci[:nnz].copy(), v[:nnz].copy()
+
+    def mask(self, l: int, which: str) -> np.ndarray:
+        nnz = self.level_info(l)["nnz"]
+        out = np.zeros(max(nnz, 1), np.uint8)
+        self._check(self._lib.amg_export_mask(self._h, int(l), MASK[which], out.ctypes.data))
+        return out[:nnz]
+
+    def vector(self, l: int, which: str) -> np.ndarray:
+        out = np.zeros(self.level_info(l)["n"], np.float64)
+        self._check(self._lib.amg_export_vector(self._h, int(l), VEC[which], out.ctypes.data))
+        return out
+
+    def split(self, l: int) -> np.ndarray:
+        out = np.zeros(self.level_info(l)["n"], np.int32)
+        self._check(self._lib.amg_export_split(self._h, int(l), out.ctypes.data))
+        return out
+
+    def gamma(self, l: int) -> float:
+        return self.level_info(l)["gamma"]
+
+    def bytes_per_cycle(self) -> int:
+        return sum(self.level_info(l)["bytes"] for l in range(self.nlev))
+
+    # -- kernel timing ---------------------------------------------------------
+    def profile_enable(self, on: bool = True, kernel: str | None = None, level: int = -1):
+        """Times launches of one kernel class (None: all) on one level (-1: all)."""
+        kc = -1 if kernel is None else KERNEL[kernel]
+        self._check(self._lib.amg_profile_enable(self._h, int(bool(on)), kc, int(level)))
+
+    def profile_read(self, kernel: str, level: int):
+        cnt = C.c_int64()
+        ms = C.c_double()
+        self._check(self._lib.amg_profile_read(self._h, KERNEL[kernel], int(level), C.byref(cnt),
+                                               C.byref(ms)))
+        return cnt.value, ms.value

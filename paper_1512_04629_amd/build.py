@@ -1,0 +1,69 @@
+"""Builds libamg355.so (HIP kernels for gfx950 + host setup + C ABI) in-tree.
+
+    python -m paper_1512_04629_amd.build
+
+Device code is compiled by hipcc for gfx950 only, with packed FP32
+instructions disabled; the host-side Galerkin setup is compiled by g++ with
+floating-point contraction off so that its summation order is exactly the
+one written in the source.
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+BUILD = os.path.join(PKG, "_build")
+LIB = os.path.join(PKG, "libamg355.so")
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-I", os.path.join(ROOT, "include"), "-Wno-unused-result"]
+HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math",
+              "-I", os.path.join(ROOT, "include")]
+
+
+def _run_all(cmds, verbose):
+    procs = []
+    for cmd in cmds:
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
+    failed = []
+    for cmd, p in procs:
+        out, _ = p.communicate()
+        text = out.decode(errors="replace")
+        if p.returncode != 0:
+            failed.append((cmd, text))
+        elif verbose and text.strip():
+            print(text)
+    if failed:
+        for cmd, text in failed:
+            sys.stderr.write(" ".join(cmd) + "\n" + text + "\n")
+        raise RuntimeError("building libamg355 failed")
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    objs = []
+    cmds = []
+    for src in ("kernels.hip", "amg_lib.hip"):
+        obj = os.path.join(BUILD, src.replace(".hip", ".o"))
+        cmds.append([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
+    obj = os.path.join(BUILD, "host_setup.o")
+    cmds.append(["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, "host_setup.cpp"), "-o", obj])
+    objs.append(obj)
+    _run_all(cmds, verbose)
+    tmp = LIB + ".tmp"
+    _run_all([[HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"]], verbose)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

@@ -1,0 +1,1123 @@
+// Device hierarchy, sparsification pipeline, V-cycle, outer iterations and
+// the C ABI of libamg355.
+//
+//   setup       Section 2 (amg_setup) on the host, uploaded once; the
+//               Galerkin operators A_l are retained on the device.
+//   sparsify    Section 3 (sparse_hybrid_setup, Sparse Galerkin) with the
+//               Algorithm 3 keep set and the diagonal lumping of Algorithm 3b,
+//               entirely in device kernels (minimal pattern, row maxima, keep
+//               flags, scan, compaction with lumping).
+//   reintroduce Section 6 (adaptive_solve): gamma ladder on s levels and
+//               re-sparsification from the retained A_l.
+//   solve       Section 2 (amg_solve V-cycle), stationary or as the CG
+//               preconditioner, with the windowed adaptive control of
+//               Section 6.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/amg.h"
+#include "host_setup.hpp"
+#include "kernels.hpp"
+
+using namespace amg355;
+
+namespace {
+
+struct AmgFailure {
+    amg_status status;
+    std::string what;
+};
+
+#define HIP_CHECK(expr)                                                                          \
+    do {                                                                                         \
+        hipError_t e_ = (expr);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            throw AmgFailure{AMG_ERR_DEVICE, std::string(#expr) + " failed: " + hipGetErrorString(e_)}; \
+    } while (0)
+
+constexpr int kMaxDenseCoarse = 4096;
+
+// device scalar slots
+enum : int { S_RZ0 = 0, S_RZ1 = 1, S_PQ = 2, S_NR2 = 3, S_FLAG = 4, S_NRT = 5, S_DOT = 6, S_COUNT = 8 };
+
+struct DevMat {
+    int rows = 0, cols = 0;
+    int64_t nnz = 0;
+    int32_t* rp = nullptr;
+    int32_t* ci = nullptr;
+    double* v = nullptr;
+    int width = 8;
+    CsrView view() const { return CsrView{rp, ci, v, rows}; }
+};
+
+struct DevLevel {
+    int n = 0;
+    DevMat A;             // Galerkin operator (retained)
+    DevMat Ah;            // sparsified operator; aliases A while ah_alias
+    bool ah_alias = true;
+    DevMat P, R;          // l < L
+    int32_t* c_points = nullptr;  // fine index of each coarse point of level l+1
+    int nc = 0;
+    double* dinv = nullptr;       // 1 / diag(Ah)
+    uint8_t* in_m = nullptr;      // minimal pattern flags (l >= 1)
+    uint8_t* keep = nullptr;      // keep flags of the last sparsification
+    double* rowmax = nullptr;     // m_i of A
+    bool have_m = false;
+    bool keep_valid = false;
+    double gamma = 0.0;
+    double *b = nullptr, *x = nullptr, *xt = nullptr, *r = nullptr;
+    std::vector<int32_t> split;
+};
+
+struct ProfAcc {
+    int64_t count = 0;
+    double ms = 0.0;
+};
+
+struct PendingEvent {
+    int kind, level;
+    hipEvent_t start, stop;
+};
+
+}  // namespace
+
+struct amg_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    amg_alloc_fn alloc_fn = nullptr;
+    amg_free_fn free_fn = nullptr;
+    void* user = nullptr;
+    std::unordered_map<void*, size_t> blocks;
+    amg_setup_params sp{};
+    std::vector<DevLevel> lv;
+    int nL = 0;
+    double* coarse_inv = nullptr;
+    double* scal = nullptr;
+    unsigned* counter = nullptr;
+    double* partials = nullptr;
+    int partial_cap = 0;
+    double* pinned = nullptr;
+    int32_t* scan_scratch = nullptr;
+    int32_t* cnt = nullptr;
+    int* missing = nullptr;
+    double *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_q = nullptr;
+    double *xw = nullptr, *rt = nullptr;
+    std::string last_error;
+    bool profiling = false;
+    int prof_kind = -1, prof_level = -1;
+    std::vector<PendingEvent> pending;
+    std::vector<hipEvent_t> event_pool;
+    std::vector<ProfAcc> prof;   // [kind * max_levels + level]
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// memory
+// ---------------------------------------------------------------------------
+void* dalloc(amg_ctx* h, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    void* p = nullptr;
+    if (h->alloc_fn) {
+        p = h->alloc_fn(bytes, (void*)h->stream, h->user);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        p = nullptr;
+    }
+    if (!p) throw AmgFailure{AMG_ERR_OUT_OF_MEMORY, "device allocation of " + std::to_string(bytes) + " bytes failed"};
+    h->blocks[p] = bytes;
+    return p;
+}
+
+template <class T>
+T* dalloc_n(amg_ctx* h, int64_t n) {
+    return static_cast<T*>(dalloc(h, sizeof(T) * (size_t)std::max<int64_t>(n, 1)));
+}
+
+void dfree(amg_ctx* h, void* p) {
+    if (!p) return;
+    auto it = h->blocks.find(p);
+    size_t bytes = it == h->blocks.end() ? 0 : it->second;
+    if (it != h->blocks.end()) h->blocks.erase(it);
+    if (h->free_fn) h->free_fn(p, bytes, (void*)h->stream, h->user);
+    else (void)hipFree(p);
+}
+
+void free_mat(amg_ctx* h, DevMat& m) {
+    dfree(h, m.rp);
+    dfree(h, m.ci);
+    dfree(h, m.v);
+    m = DevMat{};
+}
+
+template <class T>
+void upload(amg_ctx* h, T* dst, const T* src, int64_t n) {
+    if (n > 0) HIP_CHECK(hipMemcpyAsync(dst, src, sizeof(T) * (size_t)n, hipMemcpyHostToDevice, h->stream));
+}
+
+template <class T>
+void download(amg_ctx* h, T* dst, const T* src, int64_t n) {
+    if (n > 0) HIP_CHECK(hipMemcpyAsync(dst, src, sizeof(T) * (size_t)n, hipMemcpyDeviceToHost, h->stream));
+}
+
+void sync(amg_ctx* h) { HIP_CHECK(hipStreamSynchronize(h->stream)); }
+
+void check_launch() {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) throw AmgFailure{AMG_ERR_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e)};
+}
+
+DevMat upload_mat(amg_ctx* h, const HostCsr& m) {
+    DevMat d;
+    d.rows = m.rows;
+    d.cols = m.cols;
+    d.nnz = m.nnz();
+    d.rp = dalloc_n<int32_t>(h, d.rows + 1);
+    d.ci = dalloc_n<int32_t>(h, d.nnz);
+    d.v = dalloc_n<double>(h, d.nnz);
+    upload(h, d.rp, m.ptr.data(), d.rows + 1);
+    upload(h, d.ci, m.idx.data(), d.nnz);
+    upload(h, d.v, m.val.data(), d.nnz);
+    d.width = pick_width(d.rows ? (double)d.nnz / d.rows : 1.0);
+    return d;
+}
+
+HostCsr download_mat(amg_ctx* h, const DevMat& d) {
+    HostCsr m;
+    m.rows = d.rows;
+    m.cols = d.cols;
+    m.ptr.resize(d.rows + 1);
+    m.idx.resize(d.nnz);
+    m.val.resize(d.nnz);
+    download(h, m.ptr.data(), d.rp, d.rows + 1);
+    download(h, m.idx.data(), d.ci, d.nnz);
+    download(h, m.val.data(), d.v, d.nnz);
+    sync(h);
+    return m;
+}
+
+// ---------------------------------------------------------------------------
+// profiling: events around launches of one kernel class on one level
+// ---------------------------------------------------------------------------
+struct ProfScope {
+    amg_ctx* h;
+    int kind, level;
+    hipEvent_t stop = nullptr;
+    ProfScope(amg_ctx* hh, int k, int l) : h(hh), kind(k), level(l) {
+        if (!h->profiling) return;
+        if ((h->prof_kind >= 0 && h->prof_kind != k) || (h->prof_level >= 0 && h->prof_level != l)) return;
+        hipEvent_t start = take_event();
+        stop = take_event();
+        HIP_CHECK(hipEventRecord(start, h->stream));
+        h->pending.push_back(PendingEvent{kind, level, start, stop});
+    }
+    ~ProfScope() {
+        if (stop) (void)hipEventRecord(stop, h->stream);
+    }
+    hipEvent_t take_event() {
+        if (!h->event_pool.empty()) {
+            hipEvent_t e = h->event_pool.back();
+            h->event_pool.pop_back();
+            return e;
+        }
+        hipEvent_t e;
+        HIP_CHECK(hipEventCreate(&e));
+        return e;
+    }
+};
+
+void prof_collect(amg_ctx* h) {
+    if (h->pending.empty()) return;
+    sync(h);
+    const int ml = std::max(1, (int)h->lv.size());
+    for (auto& pe : h->pending) {
+        float ms = 0.f;
+        HIP_CHECK(hipEventElapsedTime(&ms, pe.start, pe.stop));
+        size_t idx = (size_t)pe.kind * ml + std::min(pe.level, ml - 1);
+        if (idx < h->prof.size()) {
+            h->prof[idx].count += 1;
+            h->prof[idx].ms += ms;
+        }
+        h->event_pool.push_back(pe.start);
+        h->event_pool.push_back(pe.stop);
+    }
+    h->pending.clear();
+}
+
+// ---------------------------------------------------------------------------
+// launches
+// ---------------------------------------------------------------------------
+DotTarget dot_to(amg_ctx* h, int slot) { return DotTarget{h->partials, h->counter, h->scal + slot}; }
+
+void row_op(amg_ctx* h, int kind, int level, RowOp op, const DevMat& m, const double* g,
+            const double* u, const double* dinv, double* y, double* y2, int dot_slot) {
+    ProfScope ps(h, kind, level);
+    DotTarget dt = dot_slot >= 0 ? dot_to(h, dot_slot) : DotTarget{nullptr, nullptr, nullptr};
+    launch_row_op(op, m.width, m.view(), g, u, dinv, h->sp.omega, y, y2, dt, h->stream);
+    check_launch();
+}
+
+// ---------------------------------------------------------------------------
+// coarse-level dense inverse (host factorization, applied by a device kernel)
+// ---------------------------------------------------------------------------
+bool dense_inverse(int n, std::vector<double>& a, std::vector<double>& inv) {
+    // Cholesky A = L L^T, then inv = L^-T L^-1; Gauss-Jordan with partial
+    // pivoting if a pivot is not positive.
+    std::vector<double> L(a.size(), 0.0);
+    bool spd = true;
+    for (int j = 0; j < n && spd; ++j) {
+        double d = a[(size_t)j * n + j];
+        for (int k = 0; k < j; ++k) d -= L[(size_t)j * n + k] * L[(size_t)j * n + k];
+        if (!(d > 0.0)) { spd = false; break; }
+        const double ljj = std::sqrt(d);
+        L[(size_t)j * n + j] = ljj;
+        for (int i = j + 1; i < n; ++i) {
+            double t = a[(size_t)i * n + j];
+            for (int k = 0; k < j; ++k) t -= L[(size_t)i * n + k] * L[(size_t)j * n + k];
+            L[(size_t)i * n + j] = t / ljj;
+        }
+    }
+    inv.assign((size_t)n * n, 0.0);
+    if (spd) {
+        // columns of L^-1 by forward substitution, then inv = L^-T L^-1
+        std::vector<double> Li((size_t)n * n, 0.0);
+        for (int c = 0; c < n; ++c) {
+            for (int i = c; i < n; ++i) {
+                double t = (i == c) ? 1.0 : 0.0;
+                for (int k = c; k < i; ++k) t -= L[(size_t)i * n + k] * Li[(size_t)k * n + c];
+                Li[(size_t)i * n + c] = t / L[(size_t)i * n + i];
+            }
+        }
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                double t = 0.0;
+                for (int k = std::max(i, j); k < n; ++k) t += Li[(size_t)k * n + i] * Li[(size_t)k * n + j];
+                inv[(size_t)i * n + j] = t;
+            }
+        return true;
+    }
+    std::vector<double> m = a;
+    for (int i = 0; i < n; ++i) inv[(size_t)i * n + i] = 1.0;
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int i = c + 1; i < n; ++i)
+            if (std::fabs(m[(size_t)i * n + c]) > std::fabs(m[(size_t)piv * n + c])) piv = i;
+        if (m[(size_t)piv * n + c] == 0.0) return false;
+        if (piv != c)
+            for (int j = 0; j < n; ++j) {
+                std::swap(m[(size_t)c * n + j], m[(size_t)piv * n + j]);
+                std::swap(inv[(size_t)c * n + j], inv[(size_t)piv * n + j]);
+            }
+        const double d = m[(size_t)c * n + c];
+        for (int j = 0; j < n; ++j) { m[(size_t)c * n + j] /= d; inv[(size_t)c * n + j] /= d; }
+        for (int i = 0; i < n; ++i) {
+            if (i == c) continue;
+            const double f = m[(size_t)i * n + c];
+            if (f == 0.0) continue;
+            for (int j = 0; j < n; ++j) {
+                m[(size_t)i * n + j] -= f * m[(size_t)c * n + j];
+                inv[(size_t)i * n + j] -= f * inv[(size_t)c * n + j];
+            }
+        }
+    }
+    return true;
+}
+
+void refresh_coarse_inverse(amg_ctx* h) {
+    DevLevel& c = h->lv.back();
+    HostCsr m = download_mat(h, c.Ah);
+    const int n = m.rows;
+    std::vector<double> a((size_t)n * n, 0.0), inv;
+    for (int i = 0; i < n; ++i)
+        for (int p = m.ptr[i]; p < m.ptr[i + 1]; ++p) a[(size_t)i * n + m.idx[p]] = m.val[p];
+    if (!dense_inverse(n, a, inv))
+        throw AmgFailure{AMG_ERR_BAD_MATRIX, "coarsest operator is singular"};
+    if (!h->coarse_inv || h->nL != n) {
+        dfree(h, h->coarse_inv);
+        h->coarse_inv = dalloc_n<double>(h, (int64_t)n * n);
+    }
+    h->nL = n;
+    upload(h, h->coarse_inv, inv.data(), (int64_t)n * n);
+    sync(h);
+}
+
+// ---------------------------------------------------------------------------
+// sparsification (device)
+// ---------------------------------------------------------------------------
+void ensure_minimal_pattern(amg_ctx* h, int l) {
+    DevLevel& c = h->lv[l];
+    if (c.have_m) return;
+    DevLevel& f = h->lv[l - 1];
+    if (!c.in_m) c.in_m = dalloc_n<uint8_t>(h, c.A.nnz);
+    if (!c.keep) c.keep = dalloc_n<uint8_t>(h, c.A.nnz);
+    if (!c.rowmax) c.rowmax = dalloc_n<double>(h, c.n);
+    {
+        ProfScope ps(h, AMG_K_SPARSIFY, l);
+        launch_fill_u8(c.A.nnz, c.in_m, 0, h->stream);
+        launch_fill_u32(1, reinterpret_cast<unsigned*>(h->missing), 0u, h->stream);
+        launch_mark_minimal_pattern(c.n, f.c_points, f.A.rp, f.A.ci, f.P.rp, f.P.ci, c.A.rp, c.A.ci,
+                                    c.in_m, h->missing, h->stream);
+        launch_row_max(c.A.width, c.A.view(), c.rowmax, h->stream);
+        check_launch();
+    }
+    int missing = 0;
+    download(h, &missing, h->missing, 1);
+    sync(h);
+    if (missing) throw AmgFailure{AMG_ERR_BAD_MATRIX, "minimal pattern of level " + std::to_string(l) + " is not inside the Galerkin pattern"};
+    c.have_m = true;
+}
+
+struct NewOperator {
+    int level;
+    double gamma;
+    bool alias;
+    DevMat m;
+    double* dinv;
+};
+
+NewOperator build_sparsified(amg_ctx* h, int l, double gamma) {
+    DevLevel& c = h->lv[l];
+    NewOperator out{l, gamma, gamma == 0.0, DevMat{}, nullptr};
+    out.dinv = dalloc_n<double>(h, c.n);
+    if (out.alias) {
+        ProfScope ps(h, AMG_K_SPARSIFY, l);
+        launch_inverse_diagonal(c.A.view(), out.dinv, h->stream);
+        check_launch();
+        return out;
+    }
+    ensure_minimal_pattern(h, l);
+    int32_t* rp = dalloc_n<int32_t>(h, c.n + 1);
+    {
+        ProfScope ps(h, AMG_K_SPARSIFY, l);
+        launch_keep_count(c.A.width, c.A.view(), c.in_m, c.rowmax, gamma, c.keep, h->cnt, h->stream);
+        launch_exclusive_scan(c.n, h->cnt, rp, h->scan_scratch, h->stream);
+        check_launch();
+    }
+    int32_t total = 0;
+    download(h, &total, rp + c.n, 1);
+    sync(h);
+    out.m.rows = out.m.cols = c.n;
+    out.m.nnz = total;
+    out.m.rp = rp;
+    out.m.ci = dalloc_n<int32_t>(h, total);
+    out.m.v = dalloc_n<double>(h, total);
+    out.m.width = pick_width((double)total / std::max(1, c.n));
+    {
+        ProfScope ps(h, AMG_K_SPARSIFY, l);
+        launch_compact_lump(c.A.width, c.A.view(), c.keep, rp, out.m.ci, out.m.v, out.dinv, h->stream);
+        check_launch();
+    }
+    return out;
+}
+
+// Rebuilds the sparsified operators of the given levels at the given
+// tolerances.  All new operators are built before any is swapped in.
+void sparsify_levels(amg_ctx* h, const std::vector<std::pair<int, double>>& todo) {
+    std::vector<NewOperator> built;
+    try {
+        for (auto& t : todo) built.push_back(build_sparsified(h, t.first, t.second));
+        sync(h);
+    } catch (...) {
+        for (auto& b : built) {
+            if (!b.alias) free_mat(h, b.m);
+            dfree(h, b.dinv);
+        }
+        throw;
+    }
+    bool coarse_changed = false;
+    for (auto& b : built) {
+        DevLevel& c = h->lv[b.level];
+        if (!c.ah_alias) free_mat(h, c.Ah);
+        dfree(h, c.dinv);
+        c.ah_alias = b.alias;
+        c.Ah = b.alias ? c.A : b.m;
+        c.dinv = b.dinv;
+        c.gamma = b.gamma;
+        c.keep_valid = !b.alias;
+        if (b.level == (int)h->lv.size() - 1) coarse_changed = true;
+    }
+    if (coarse_changed) refresh_coarse_inverse(h);
+}
+
+// ---------------------------------------------------------------------------
+// V-cycle (Section 2, amg_solve): weighted Jacobi pre/post smoothing,
+// restriction of the residual with R = P^T, coarsest dense solve,
+// interpolation and correction.  zero0: the level-0 iterate is zero on
+// entry.  dot_slot >= 0: accumulate b0 . x0 (the CG inner product r.z) into
+// that scalar slot.  The result is left in x0.
+// ---------------------------------------------------------------------------
+void jacobi_sweeps(amg_ctx* h, int l, const DevMat& m, const double* dinv, const double* b,
+                   double*& cur, double*& alt, int sweeps, int dot_slot_last) {
+    for (int s = 0; s < sweeps; ++s) {
+        const bool last = s == sweeps - 1;
+        if (last && dot_slot_last >= 0)
+            row_op(h, AMG_K_JACOBI, l, kJacobiDot, m, cur, b, dinv, alt, nullptr, dot_slot_last);
+        else
+            row_op(h, AMG_K_JACOBI, l, kJacobi, m, cur, b, dinv, alt, nullptr, -1);
+        std::swap(cur, alt);
+    }
+}
+
+void vcycle(amg_ctx* h, const double* b0, double* x0, bool zero0, int dot_slot) {
+    const int L = (int)h->lv.size() - 1;
+    const int pre = h->sp.nu_pre, post = h->sp.nu_post;
+    if (L == 0) {
+        ProfScope ps(h, AMG_K_COARSE, 0);
+        launch_dense_matvec(h->nL, h->coarse_inv, b0, x0, h->stream);
+        check_launch();
+        if (dot_slot >= 0) launch_dot(h->lv[0].n, b0, x0, dot_to(h, dot_slot), h->stream);
+        return;
+    }
+    std::vector<double*> cur(L + 1), alt(L + 1);
+    for (int l = 0; l < L; ++l) {
+        DevLevel& v = h->lv[l];
+        const double* b = l == 0 ? b0 : v.b;
+        cur[l] = l == 0 ? x0 : v.x;
+        alt[l] = v.xt;
+        const bool zero = l == 0 ? zero0 : true;
+        // every sweep after the first zero-guess one swaps the buffers; with
+        // a zero initial iterate start in the buffer that makes the result
+        // land in x0 on level 0
+        const int swaps = (zero ? std::max(pre - 1, 0) : pre) + post;
+        if (l == 0 && zero && (swaps & 1)) std::swap(cur[0], alt[0]);
+        bool have_resid = false;
+        if (zero) {
+            if (pre == 0) {
+                launch_fill_f64(v.n, cur[l], 0.0, h->stream);
+                launch_copy(v.n, v.r, b, h->stream);
+                have_resid = true;
+            } else if (pre == 1) {
+                row_op(h, AMG_K_JACOBI_ZERO, l, kZeroJacobiResid, v.Ah, nullptr, b, v.dinv, v.r, cur[l], -1);
+                have_resid = true;
+            } else {
+                launch_scaled_copy(v.n, cur[l], v.dinv, b, h->sp.omega, h->stream);
+                jacobi_sweeps(h, l, v.Ah, v.dinv, b, cur[l], alt[l], pre - 1, -1);
+            }
+        } else {
+            jacobi_sweeps(h, l, v.Ah, v.dinv, b, cur[l], alt[l], pre, -1);
+        }
+        if (!have_resid) row_op(h, AMG_K_RESIDUAL, l, kResid, v.Ah, cur[l], b, nullptr, v.r, nullptr, -1);
+        DevLevel& nx = h->lv[l + 1];
+        row_op(h, AMG_K_RESTRICT, l, kSpmv, v.R, v.r, nullptr, nullptr, nx.b, nullptr, -1);
+    }
+    {
+        DevLevel& c = h->lv[L];
+        ProfScope ps(h, AMG_K_COARSE, L);
+        launch_dense_matvec(h->nL, h->coarse_inv, c.b, c.x, h->stream);
+        check_launch();
+        cur[L] = c.x;
+    }
+    for (int l = L - 1; l >= 0; --l) {
+        DevLevel& v = h->lv[l];
+        const double* b = l == 0 ? b0 : v.b;
+        row_op(h, AMG_K_INTERP, l, kSpmvAdd, v.P, cur[l + 1], cur[l], nullptr, cur[l], nullptr, -1);
+        const int dslot = (l == 0) ? dot_slot : -1;
+        jacobi_sweeps(h, l, v.Ah, v.dinv, b, cur[l], alt[l], post, dslot);
+        if (l == 0) {
+            if (cur[0] != x0) launch_copy(v.n, x0, cur[0], h->stream);
+            if (post == 0 && dot_slot >= 0) launch_dot(v.n, b0, x0, dot_to(h, dot_slot), h->stream);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// outer iterations
+// ---------------------------------------------------------------------------
+void ensure_solve_buffers(amg_ctx* h) {
+    const int n = h->lv[0].n;
+    if (!h->cg_r) h->cg_r = dalloc_n<double>(h, n);
+    if (!h->cg_z) h->cg_z = dalloc_n<double>(h, n);
+    if (!h->cg_p) h->cg_p = dalloc_n<double>(h, n);
+    if (!h->cg_q) h->cg_q = dalloc_n<double>(h, n);
+    if (!h->xw) h->xw = dalloc_n<double>(h, n);
+    if (!h->rt) h->rt = dalloc_n<double>(h, n);
+}
+
+// reads the scalar slots into host memory
+const double* read_scalars(amg_ctx* h) {
+    download(h, h->pinned, h->scal, S_COUNT);
+    sync(h);
+    return h->pinned;
+}
+
+amg_status do_reintroduce(amg_ctx* h, int s, double gamma_min, int* first) {
+    int ls = -1;
+    for (int l = 1; l < (int)h->lv.size(); ++l)
+        if (h->lv[l].gamma > 0.0) { ls = l; break; }
+    if (first) *first = ls;
+    if (ls < 0) return AMG_NOTHING_TO_REINTRODUCE;
+    std::vector<std::pair<int, double>> todo;
+    for (int l = ls; l < ls + s && l < (int)h->lv.size(); ++l) {
+        double g = h->lv[l].gamma / 10.0;
+        if (!(g >= gamma_min)) g = 0.0;
+        todo.emplace_back(l, g);
+    }
+    sparsify_levels(h, todo);
+    return AMG_OK;
+}
+
+amg_status solve(amg_ctx* h, const double* b, double* x, const amg_solve_params& p,
+                 amg_solve_info* info_out, double* hist) {
+    ensure_solve_buffers(h);
+    DevLevel& f = h->lv[0];
+    const int n = f.n;
+    const DevMat& A = f.A;
+    const bool pcg = p.method == AMG_PCG;
+    amg_solve_info info{0, 0, 0, 0, 0.0, 0.0};
+    amg_status st = AMG_ERR_NOT_CONVERGED;
+    double* r = h->cg_r;
+    launch_fill_f64(S_COUNT, h->scal, 0.0, h->stream);
+    row_op(h, AMG_K_RESIDUAL, 0, kResidNorm, A, x, b, nullptr, r, nullptr, S_NR2);
+    const double nr0 = std::sqrt(read_scalars(h)[S_NR2]);
+    if (hist) hist[0] = nr0;
+    double nws = nr0;
+    int inwin = 0;
+    int rz_slot = S_RZ0;
+    if (!std::isfinite(nr0)) {
+        st = AMG_ERR_BREAKDOWN;
+    } else if (nr0 == 0.0) {
+        info.converged = 1;
+        st = AMG_OK;
+    } else {
+        launch_copy(n, h->xw, x, h->stream);
+        if (pcg) {
+            vcycle(h, r, h->cg_z, true, rz_slot);
+            launch_copy(n, h->cg_p, h->cg_z, h->stream);
+        }
+        while (info.iters < p.maxit) {
+            if (pcg) {
+                row_op(h, AMG_K_SPMV_DOT, 0, kSpmvDot, A, h->cg_p, nullptr, nullptr, h->cg_q, nullptr, S_PQ);
+                {
+                    ProfScope ps(h, AMG_K_VECTOR, 0);
+                    launch_cg_update_xr(n, x, r, h->cg_p, h->cg_q, h->scal, rz_slot, S_PQ, h->scal + S_FLAG,
+                                        dot_to(h, S_NR2), h->stream);
+                    check_launch();
+                }
+            } else {
+                vcycle(h, b, x, false, -1);
+                row_op(h, AMG_K_RESIDUAL, 0, kResidNorm, A, x, b, nullptr, r, nullptr, S_NR2);
+            }
+            const double* sc = read_scalars(h);
+            if (pcg && sc[S_FLAG] != 0.0) { st = AMG_ERR_BREAKDOWN; break; }
+            const double nr = std::sqrt(sc[S_NR2]);
+            info.iters++;
+            inwin++;
+            if (hist) hist[info.iters] = nr;
+            if (!std::isfinite(nr)) { st = AMG_ERR_BREAKDOWN; break; }
+            if (nr <= p.rtol * nr0) { info.converged = 1; st = AMG_OK; break; }
+            bool restart = false;
+            if (p.adaptive && inwin == p.k) {
+                row_op(h, AMG_K_RESIDUAL, 0, kResidNorm, A, x, b, nullptr, h->rt, nullptr, S_NRT);
+                double nrt = std::sqrt(read_scalars(h)[S_NRT]);
+                const double rho = std::pow(nrt / nws, 1.0 / (double)p.k);
+                bool any = false;
+                for (size_t l = 1; l < h->lv.size(); ++l) any = any || h->lv[l].gamma > 0.0;
+                if (rho > p.rho_max && any) {
+                    int first = -1;
+                    amg_status rs = do_reintroduce(h, p.s, p.gamma_min, &first);
+                    if (rs < 0) { st = rs; break; }
+                    info.reintroductions++;
+                    if (nrt > nws) {
+                        launch_copy(n, x, h->xw, h->stream);
+                        row_op(h, AMG_K_RESIDUAL, 0, kResidNorm, A, x, b, nullptr, r, nullptr, S_NRT);
+                        nrt = std::sqrt(read_scalars(h)[S_NRT]);
+                    } else {
+                        launch_copy(n, r, h->rt, h->stream);
+                    }
+                    restart = true;
+                }
+                launch_copy(n, h->xw, x, h->stream);
+                nws = nrt;
+                inwin = 0;
+            }
+            if (pcg) {
+                const int new_slot = rz_slot == S_RZ0 ? S_RZ1 : S_RZ0;
+                vcycle(h, r, h->cg_z, true, new_slot);
+                if (restart) {
+                    info.restarts++;
+                    launch_copy(n, h->cg_p, h->cg_z, h->stream);
+                } else {
+                    ProfScope ps(h, AMG_K_VECTOR, 0);
+                    launch_cg_update_p(n, h->cg_p, h->cg_z, h->scal, new_slot, rz_slot, h->stream);
+                    check_launch();
+                }
+                rz_slot = new_slot;
+            } else if (restart) {
+                info.restarts++;
+            }
+        }
+    }
+    row_op(h, AMG_K_RESIDUAL, 0, kResidNorm, A, x, b, nullptr, r, nullptr, S_NRT);
+    const double nrf = std::sqrt(read_scalars(h)[S_NRT]);
+    info.relres = nr0 > 0.0 ? nrf / nr0 : 0.0;
+    info.rho_avg = (info.iters > 0 && info.relres > 0.0) ? std::pow(info.relres, 1.0 / info.iters) : 0.0;
+    if (info_out) *info_out = info;
+    prof_collect(h);
+    return st;
+}
+
+// ---------------------------------------------------------------------------
+// setup
+// ---------------------------------------------------------------------------
+void setup(amg_ctx* h, int64_t n, const int32_t* row_ptr, const int32_t* col, const double* val) {
+    HostCsr a;
+    a.rows = a.cols = (int)n;
+    if (row_ptr[0] != 0 || row_ptr[n] < 0) throw AmgFailure{AMG_ERR_BAD_MATRIX, "row_ptr must start at 0"};
+    for (int64_t i = 0; i < n; ++i)
+        if (row_ptr[i + 1] < row_ptr[i]) throw AmgFailure{AMG_ERR_BAD_MATRIX, "row_ptr is not non-decreasing"};
+    const int64_t nnz = row_ptr[n];
+    a.ptr.assign(row_ptr, row_ptr + n + 1);
+    a.idx.assign(col, col + nnz);
+    a.val.assign(val, val + nnz);
+    std::string why;
+    if (!check_input_matrix(a, why)) throw AmgFailure{AMG_ERR_BAD_MATRIX, why};
+    SetupConfig cfg;
+    cfg.theta = h->sp.theta;
+    cfg.max_coarse = h->sp.max_coarse;
+    cfg.max_levels = h->sp.max_levels;
+    std::vector<HostLevel> hl;
+    if (!build_galerkin_hierarchy(a, cfg, hl, why)) throw AmgFailure{AMG_ERR_BAD_MATRIX, why};
+    if (hl.back().A.rows > kMaxDenseCoarse)
+        throw AmgFailure{AMG_ERR_INVALID_ARG, "coarsest level has " + std::to_string(hl.back().A.rows) +
+                                                  " rows; the dense coarse solve allows at most " +
+                                                  std::to_string(kMaxDenseCoarse)};
+    const int L = (int)hl.size() - 1;
+    h->lv.resize(hl.size());
+    int partial_need = vector_launch_blocks(std::max(1, (int)n));
+    for (int l = 0; l <= L; ++l) {
+        DevLevel& d = h->lv[l];
+        HostLevel& s = hl[l];
+        d.n = s.A.rows;
+        d.A = upload_mat(h, s.A);
+        d.Ah = d.A;
+        d.ah_alias = true;
+        d.dinv = dalloc_n<double>(h, d.n);
+        launch_inverse_diagonal(d.A.view(), d.dinv, h->stream);
+        partial_need = std::max(partial_need, row_launch_blocks(d.n, d.A.width));
+        if (l < L) {
+            d.P = upload_mat(h, s.P);
+            d.R = upload_mat(h, s.R);
+            d.nc = (int)s.c_points.size();
+            d.c_points = dalloc_n<int32_t>(h, d.nc);
+            upload(h, d.c_points, s.c_points.data(), d.nc);
+            d.split = s.split;
+            partial_need = std::max(partial_need, row_launch_blocks(d.P.rows, d.P.width));
+            partial_need = std::max(partial_need, row_launch_blocks(d.R.rows, d.R.width));
+        }
+        if (l > 0) d.b = dalloc_n<double>(h, d.n);
+        if (l > 0) d.x = dalloc_n<double>(h, d.n);
+        d.xt = dalloc_n<double>(h, d.n);
+        d.r = dalloc_n<double>(h, d.n);
+    }
+    // sparsified-operator widths are chosen per build; partial buffers cover
+    // every width for the largest level
+    partial_need = std::max(partial_need, row_launch_blocks(h->lv[0].n, 4));
+    h->partial_cap = partial_need;
+    h->partials = dalloc_n<double>(h, partial_need);
+    h->counter = dalloc_n<unsigned>(h, 1);
+    h->scal = dalloc_n<double>(h, S_COUNT);
+    h->missing = dalloc_n<int>(h, 1);
+    int nmax = 0;
+    for (auto& d : h->lv) nmax = std::max(nmax, d.n);
+    h->cnt = dalloc_n<int32_t>(h, nmax + 1);
+    h->scan_scratch = dalloc_n<int32_t>(h, scan_scratch_ints(nmax));
+    launch_fill_u32(1, h->counter, 0u, h->stream);
+    launch_fill_f64(S_COUNT, h->scal, 0.0, h->stream);
+    check_launch();
+    HIP_CHECK(hipHostMalloc((void**)&h->pinned, sizeof(double) * S_COUNT, hipHostMallocDefault));
+    sync(h);
+    refresh_coarse_inverse(h);
+    h->prof.assign((size_t)AMG_K_NUM * h->lv.size(), ProfAcc{});
+}
+
+void destroy(amg_ctx* h) {
+    if (!h) return;
+    (void)hipStreamSynchronize(h->stream);
+    for (auto& d : h->lv) {
+        if (!d.ah_alias) free_mat(h, d.Ah);
+        free_mat(h, d.A);
+        free_mat(h, d.P);
+        free_mat(h, d.R);
+        dfree(h, d.c_points);
+        dfree(h, d.dinv);
+        dfree(h, d.in_m);
+        dfree(h, d.keep);
+        dfree(h, d.rowmax);
+        dfree(h, d.b);
+        dfree(h, d.x);
+        dfree(h, d.xt);
+        dfree(h, d.r);
+    }
+    for (void* p : {(void*)h->coarse_inv, (void*)h->scal, (void*)h->counter, (void*)h->partials,
+                    (void*)h->scan_scratch, (void*)h->cnt, (void*)h->missing, (void*)h->cg_r,
+                    (void*)h->cg_z, (void*)h->cg_p, (void*)h->cg_q, (void*)h->xw, (void*)h->rt})
+        dfree(h, p);
+    if (h->pinned) (void)hipHostFree(h->pinned);
+    for (auto& pe : h->pending) {
+        (void)hipEventDestroy(pe.start);
+        (void)hipEventDestroy(pe.stop);
+    }
+    for (auto e : h->event_pool) (void)hipEventDestroy(e);
+    delete h;
+}
+
+template <class F>
+amg_status guarded(amg_ctx* h, F&& f) {
+    try {
+        return f();
+    } catch (const AmgFailure& e) {
+        if (h) h->last_error = e.what;
+        return e.status;
+    } catch (const std::bad_alloc&) {
+        if (h) h->last_error = "host allocation failed";
+        return AMG_ERR_OUT_OF_MEMORY;
+    } catch (const std::exception& e) {
+        if (h) h->last_error = e.what();
+        return AMG_ERR_DEVICE;
+    } catch (...) {
+        if (h) h->last_error = "unknown failure";
+        return AMG_ERR_DEVICE;
+    }
+}
+
+bool valid_gamma(double g) { return g >= 0.0 && g <= 1.0; }
+
+// failure message of the last amg_setup_from_csr on this thread that failed
+std::string& setup_error() {
+    static thread_local std::string msg;
+    return msg;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+void amg_setup_params_default(amg_setup_params* p) {
+    if (!p) return;
+    p->theta = 0.25;
+    p->max_coarse = 49;
+    p->max_levels = 25;
+    p->omega = 2.0 / 3.0;
+    p->nu_pre = 1;
+    p->nu_post = 1;
+}
+
+void amg_solve_params_default(amg_solve_params* p) {
+    if (!p) return;
+    p->method = AMG_PCG;
+    p->rtol = 1e-8;
+    p->maxit = 200;
+    p->adaptive = 0;
+    p->k = 3;
+    p->s = 1;
+    p->rho_max = 0.5;
+    p->gamma_min = 0.01;
+}
+
+amg_status amg_setup_from_csr(int64_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
+                              const amg_setup_params* params, void* stream, amg_alloc_fn alloc,
+                              amg_free_fn free_fn, void* user, amg_handle* out) {
+    if (!out) return AMG_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (n <= 0 || n > INT32_MAX - 1 || !row_ptr || !col || !val) return AMG_ERR_INVALID_ARG;
+    if ((alloc == nullptr) != (free_fn == nullptr)) return AMG_ERR_INVALID_ARG;
+    amg_setup_params sp;
+    amg_setup_params_default(&sp);
+    if (params) sp = *params;
+    if (!(sp.theta > 0.0 && sp.theta <= 1.0) || sp.max_coarse < 1 || sp.max_levels < 1 ||
+        !(sp.omega > 0.0 && sp.omega < 2.0) || sp.nu_pre < 0 || sp.nu_post < 0)
+        return AMG_ERR_INVALID_ARG;
+    amg_ctx* h = new (std::nothrow) amg_ctx();
+    if (!h) return AMG_ERR_OUT_OF_MEMORY;
+    h->stream = (hipStream_t)stream;
+    h->alloc_fn = alloc;
+    h->free_fn = free_fn;
+    h->user = user;
+    h->sp = sp;
+    amg_status st = guarded(h, [&] {
+        HIP_CHECK(hipGetDevice(&h->device));
+        setup(h, n, row_ptr, col, val);
+        return AMG_OK;
+    });
+    if (st != AMG_OK) {
+        setup_error() = h->last_error;
+        destroy(h);
+        return st;
+    }
+    *out = h;
+    return AMG_OK;
+}
+
+amg_status amg_sparsify(amg_handle h, double gamma, int32_t first_level) {
+    if (!h || h->lv.empty()) return AMG_ERR_STATE;
+    if (!valid_gamma(gamma) || first_level < 1) {
+        h->last_error = "gamma must lie in [0, 1] and first_level must be >= 1";
+        return AMG_ERR_INVALID_ARG;
+    }
+    return guarded(h, [&] {
+        std::vector<std::pair<int, double>> todo;
+        for (int l = 1; l < (int)h->lv.size(); ++l) todo.emplace_back(l, l >= first_level ? gamma : 0.0);
+        sparsify_levels(h, todo);
+        prof_collect(h);
+        return AMG_OK;
+    });
+}
+
+amg_status amg_sparsify_levels(amg_handle h, const double* gamma, int32_t count) {
+    if (!h || h->lv.empty()) return AMG_ERR_STATE;
+    if (!gamma || count < 0) return AMG_ERR_INVALID_ARG;
+    for (int l = 1; l < count; ++l)
+        if (!valid_gamma(gamma[l])) {
+            h->last_error = "gamma[" + std::to_string(l) + "] outside [0, 1]";
+            return AMG_ERR_INVALID_ARG;
+        }
+    return guarded(h, [&] {
+        std::vector<std::pair<int, double>> todo;
+        for (int l = 1; l < (int)h->lv.size(); ++l) todo.emplace_back(l, l < count ? gamma[l] : 0.0);
+        sparsify_levels(h, todo);
+        prof_collect(h);
+        return AMG_OK;
+    });
+}
+
+amg_status amg_reintroduce(amg_handle h, int32_t s, double gamma_min, int32_t* first_changed_level) {
+    if (!h || h->lv.empty()) return AMG_ERR_STATE;
+    if (s < 1 || !(gamma_min >= 0.0)) return AMG_ERR_INVALID_ARG;
+    return guarded(h, [&] {
+        int first = -1;
+        amg_status st = do_reintroduce(h, s, gamma_min, &first);
+        if (first_changed_level) *first_changed_level = first;
+        prof_collect(h);
+        return st;
+    });
+}
+
+amg_status amg_solve(amg_handle h, const double* b, double* x, const amg_solve_params* params,
+                     amg_solve_info* info, double* hist) {
+    if (!h || h->lv.empty()) return AMG_ERR_STATE;
+    if (!b || !x) return AMG_ERR_INVALID_ARG;
+    amg_solve_params p;
+    amg_solve_params_default(&p);
+    if (params) p = *params;
+    if ((p.method != AMG_PCG && p.method != AMG_STATIONARY) || p.maxit < 0 || !(p.rtol >= 0.0) ||
+        (p.adaptive && (p.k < 1 || p.s < 1))) {
+        h->last_error = "invalid solve parameters";
+        return AMG_ERR_INVALID_ARG;
+    }
+    return guarded(h, [&] { return solve(h, b, x, p, info, hist); });
+}
+
+amg_status amg_vcycle(amg_handle h, const double* b, double* x) {
+    if (!h || h->lv.empty()) return AMG_ERR_STATE;
+    if (!b || !x) return AMG_ERR_INVALID_ARG;
+    return guarded(h, [&] {
+        vcycle(h, b, x, false, -1);
+        prof_collect(h);
+        return AMG_OK;
+    });
+}
+
+amg_status amg_level_op(amg_handle h, int32_t level, int32_t op, const double* in, const double* x,
+                        double* out) {
+    if (!h || h->lv.empty()) return AMG_ERR_STATE;
+    const int L = (int)h->lv.size() - 1;
+    if (op == AMG_OP_COARSE_SOLVE) level = L;
+    if (level < 0 || level > L || !out) return AMG_ERR_INVALID_ARG;
+    return guarded(h, [&] {
+        DevLevel& v = h->lv[level];
+        switch (op) {
+            case AMG_OP_RESIDUAL:
+                if (!in || !x) return AMG_ERR_INVALID_ARG;
+                row_op(h, AMG_K_RESIDUAL, level, kResid, v.Ah, x, in, nullptr, out, nullptr, -1);
+                break;
+            case AMG_OP_JACOBI:
+                if (!in || !x || x == out) return AMG_ERR_INVALID_ARG;
+                row_op(h, AMG_K_JACOBI, level, kJacobi, v.Ah, x, in, v.dinv, out, nullptr, -1);
+                break;
+            case AMG_OP_RESTRICT:
+                if (level == L || !in) return AMG_ERR_INVALID_ARG;
+                row_op(h, AMG_K_RESTRICT, level, kSpmv, v.R, in, nullptr, nullptr, out, nullptr, -1);
+                break;
+            case AMG_OP_INTERPOLATE:
+                if (level == L || !in || !x) return AMG_ERR_INVALID_ARG;
+                row_op(h, AMG_K_INTERP, level, kSpmvAdd, v.P, in, x, nullptr, out, nullptr, -1);
+                break;
+            case AMG_OP_COARSE_SOLVE: {
+                if (!in) return AMG_ERR_INVALID_ARG;
+                ProfScope ps(h, AMG_K_COARSE, L);
+                launch_dense_matvec(h->nL, h->coarse_inv, in, out, h->stream);
+                check_launch();
+                break;
+            }
+            case AMG_OP_SPMV_A:
+                if (!x) return AMG_ERR_INVALID_ARG;
+                row_op(h, AMG_K_RESIDUAL, level, kSpmv, v.A, x, nullptr, nullptr, out, nullptr, -1);
+                break;
+            case AMG_OP_SPMV_AHAT:
+                if (!x) return AMG_ERR_INVALID_ARG;
+                row_op(h, AMG_K_RESIDUAL, level, kSpmv, v.Ah, x, nullptr, nullptr, out, nullptr, -1);
+                break;
+            default:
+                return AMG_ERR_INVALID_ARG;
+        }
+        return AMG_OK;
+    });
+}
+
+amg_status amg_num_levels(amg_handle h, int32_t* nlev) {
+    if (!h || h->lv.empty()) return AMG_ERR_STATE;
+    if (!nlev) return AMG_ERR_INVALID_ARG;
+    *nlev = (int32_t)h->lv.size();
+    return AMG_OK;
+}
+
+static int64_t level_bytes(const amg_ctx* h, int l) {
+    // algorithmic bytes of one zero-guess V-cycle's work on level l: FP64
+    // values, int32 indices, every vector entry counted once per kernel
+    const DevLevel& v = h->lv[l];
+    const int L = (int)h->lv.size() - 1;
+    const int64_t n = v.n;
+    if (l == L) return 8 * n * n + 16 * n;
+    const int64_t nnz = v.Ah.nnz, nc = v.nc;
+    int64_t b = 0;
+    b += 12 * nnz + 4 * (n + 1) + 32 * n;                 // zero-guess sweep fused with residual
+    b += 12 * v.R.nnz + 4 * (nc + 1) + 8 * n + 8 * nc;    // restriction
+    b += 12 * v.P.nnz + 4 * (n + 1) + 8 * nc + 16 * n;    // interpolation and correction
+    b += 12 * nnz + 4 * (n + 1) + 32 * n;                 // post-smoothing sweep
+    return b;
+}
+
+amg_status amg_get_level(amg_handle h, int32_t l, int64_t* n, int64_t* nnz_galerkin, int64_t* nnz_sparse,
+                         int64_t* nnz_p, int64_t* n_coarse, double* gamma, int64_t* bytes) {
+    if (!h || h->lv.empty()) return AMG_ERR_STATE;
+    if (l < 0 || l >= (int)h->lv.size()) return AMG_ERR_INVALID_ARG;
+    const DevLevel& v = h->lv[l];
+    if (n) *n = v.n;
+    if (nnz_galerkin) *nnz_galerkin = v.A.nnz;
+    if (nnz_sparse) *nnz_sparse = v.Ah.nnz;
+    if (nnz_p) *nnz_p = v.P.nnz;
+    if (n_coarse) *n_coarse = v.nc;
+    if (gamma) *gamma = v.gamma;
+    if (bytes) *bytes = level_bytes(h, l);
+    return AMG_OK;
+}
+
+amg_status amg_export_level(amg_handle h, int32_t l, int32_t which, int32_t* row_ptr, int32_t* col,
+                            double* val) {
+    if (!h || h->lv.empty()) return AMG_ERR_STATE;
+    if (l < 0 || l >= (int)h->lv.size()) return AMG_ERR_INVALID_ARG;
+    return guarded(h, [&] {
+        const DevLevel& v = h->lv[l];
+        const DevMat* m = which == AMG_MAT_A ? &v.A : which == AMG_MAT_AHAT ? &v.Ah
+                        : which == AMG_MAT_P ? &v.P : which == AMG_MAT_R ? &v.R : nullptr;
+        if (!m || !m->rp) return AMG_ERR_INVALID_ARG;
+        if (row_ptr) download(h, row_ptr, m->rp, m->rows + 1);
+        if (col) download(h, col, m->ci, m->nnz);
+        if (val) download(h, val, m->v, m->nnz);
+        sync(h);
+        return AMG_OK;
+    });
+}
+
+amg_status amg_export_mask(amg_handle h, int32_t l, int32_t which, uint8_t* out) {
+    if (!h || h->lv.empty()) return AMG_ERR_STATE;
+    if (l < 1 || l >= (int)h->lv.size() || !out) return AMG_ERR_INVALID_ARG;
+    return guarded(h, [&] {
+        DevLevel& v = h->lv[l];
+        if (which == AMG_MASK_M) {
+            ensure_minimal_pattern(h, l);
+            download(h, out, v.in_m, v.A.nnz);
+        } else if (which == AMG_MASK_KEEP) {
+            if (v.keep_valid) download(h, out, v.keep, v.A.nnz);
+            else std::memset(out, 1, (size_t)v.A.nnz);
+        } else {
+            return AMG_ERR_INVALID_ARG;
+        }
+        sync(h);
+        return AMG_OK;
+    });
+}
+
+amg_status amg_export_vector(amg_handle h, int32_t l, int32_t which, double* out) {
+    if (!h || h->lv.empty()) return AMG_ERR_STATE;
+    if (l < 0 || l >= (int)h->lv.size() || !out) return AMG_ERR_INVALID_ARG;
+    return guarded(h, [&] {
+        DevLevel& v = h->lv[l];
+        if (which == AMG_VEC_ROWMAX) {
+            if (l < 1) return AMG_ERR_INVALID_ARG;
+            ensure_minimal_pattern(h, l);
+            download(h, out, v.rowmax, v.n);
+        } else if (which == AMG_VEC_DINV) {
+            download(h, out, v.dinv, v.n);
+        } else {
+            return AMG_ERR_INVALID_ARG;
+        }
+        sync(h);
+        return AMG_OK;
+    });
+}
+
+amg_status amg_export_split(amg_handle h, int32_t l, int32_t* cf) {
+    if (!h || h->lv.empty()) return AMG_ERR_STATE;
+    if (l < 0 || l >= (int)h->lv.size() - 1 || !cf) return AMG_ERR_INVALID_ARG;
+    std::memcpy(cf, h->lv[l].split.data(), sizeof(int32_t) * h->lv[l].split.size());
+    return AMG_OK;
+}
+
+amg_status amg_profile_enable(amg_handle h, int32_t enable, int32_t kernel_class, int32_t level) {
+    if (!h || h->lv.empty()) return AMG_ERR_STATE;
+    if (kernel_class < -1 || kernel_class >= AMG_K_NUM || level < -1 || level >= (int)h->lv.size())
+        return AMG_ERR_INVALID_ARG;
+    return guarded(h, [&] {
+        prof_collect(h);
+        h->profiling = enable != 0;
+        h->prof_kind = kernel_class;
+        h->prof_level = level;
+        for (auto& p : h->prof) p = ProfAcc{};
+        return AMG_OK;
+    });
+}
+
+amg_status amg_profile_read(amg_handle h, int32_t kernel_class, int32_t level, int64_t* count,
+                            double* total_ms) {
+    if (!h || h->lv.empty()) return AMG_ERR_STATE;
+    if (kernel_class < 0 || kernel_class >= AMG_K_NUM || level < 0 || level >= (int)h->lv.size())
+        return AMG_ERR_INVALID_ARG;
+    return guarded(h, [&] {
+        prof_collect(h);
+        const ProfAcc& a = h->prof[(size_t)kernel_class * h->lv.size() + level];
+        if (count) *count = a.count;
+        if (total_ms) *total_ms = a.ms;
+        return AMG_OK;
+    });
+}
+
+void amg_destroy(amg_handle h) { destroy(h); }
+
+const char* amg_status_string(amg_status s) {
+    switch (s) {
+        case AMG_OK: return "ok";
+        case AMG_NOTHING_TO_REINTRODUCE: return "nothing to reintroduce: every coarse gamma is 0";
+        case AMG_ERR_INVALID_ARG: return "invalid argument";
+        case AMG_ERR_BAD_MATRIX: return "matrix violates the input contract";
+        case AMG_ERR_OUT_OF_MEMORY: return "out of device memory";
+        case AMG_ERR_DEVICE: return "HIP error";
+        case AMG_ERR_NOT_CONVERGED: return "not converged within maxit";
+        case AMG_ERR_BREAKDOWN: return "breakdown (non-finite residual or p'Ap <= 0)";
+        case AMG_ERR_STATE: return "invalid state";
+    }
+    return "unknown status";
+}
+
+const char* amg_last_error(amg_handle h) { return h ? h->last_error.c_str() : setup_error().c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,47 @@
+// Host-side Galerkin setup of the AMG hierarchy (Section 2, amg_setup, run
+// without the optional sparsify step as Section 3's sparse_hybrid_setup does).
+// The hierarchy is built once on the host in deterministic order and then
+// uploaded; everything after setup runs in device kernels.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace amg355 {
+
+struct HostCsr {
+    int rows = 0, cols = 0;
+    std::vector<int32_t> ptr;   // rows + 1
+    std::vector<int32_t> idx;   // sorted ascending per row
+    std::vector<double> val;
+    int64_t nnz() const { return ptr.empty() ? 0 : ptr.back(); }
+};
+
+struct HostLevel {
+    HostCsr A;                       // Galerkin operator A_l
+    HostCsr P;                       // interpolation P_l (empty on the coarsest level)
+    HostCsr R;                       // R_l = P_l^T
+    std::vector<int32_t> split;      // 1 = C point, 0 = F point (empty on the coarsest level)
+    std::vector<int32_t> c_points;   // fine index of each coarse point, ascending
+};
+
+struct SetupConfig {
+    double theta = 0.25;
+    int max_coarse = 49;
+    int max_levels = 25;
+};
+
+// Checks the input contract: square, int32 CSR with sorted unique in-range
+// columns, finite values, a positive stored diagonal, bitwise symmetry.
+bool check_input_matrix(const HostCsr& a, std::string& why);
+
+// Builds the Galerkin hierarchy of a (levels[0].A == a).  Returns false and
+// sets why on failure.
+bool build_galerkin_hierarchy(const HostCsr& a, const SetupConfig& cfg,
+                              std::vector<HostLevel>& levels, std::string& why);
+
+// R = P^T by counting sort (rows of R list the rows of P in ascending order).
+HostCsr transpose_csr(const HostCsr& p);
+
+}  // namespace amg355

@@ -1,0 +1,599 @@
+// Device kernels of the sparsified-AMG hot path for gfx950 (CDNA4, wave64).
+//
+// Nothing here is a dense contraction, so no MFMA: every kernel is bound by
+// HBM bandwidth (or launch latency on the small coarse levels).  The CSR row
+// kernel assigns W lanes (a subgroup of the 64-lane wavefront) to a row, with
+// W the power of two nearest the mean row length, so that the lanes of a
+// wavefront read consecutive nonzeros; the row sum is reduced with lane
+// shuffles and the epilogue (residual, Jacobi update, dot products) is fused
+// into the same pass so that every vector is read once.
+#include "kernels.hpp"
+
+#include <algorithm>
+#include <cmath>
+
+namespace amg355 {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kXcds = 8;            // MI355X: 8 accelerator complex dies, each with its own L2
+constexpr int kRowGridCap = 8192;   // row kernels loop over tiles beyond this many blocks
+
+// Workgroups are handed to the XCDs round-robin.  Remap so that XCD x works on
+// a contiguous range of logical blocks: neighbouring rows gather neighbouring
+// entries of x, which then stay in one L2.  The grid is a multiple of 8.
+__device__ __forceinline__ int xcd_logical_block() {
+    const int per = gridDim.x / kXcds;
+    return (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+}
+
+int round_up8(int b) { return (b + kXcds - 1) / kXcds * kXcds; }
+
+template <int W>
+__device__ __forceinline__ double sub_sum(double v) {
+#pragma unroll
+    for (int o = W / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, W);
+    return v;
+}
+
+template <int W>
+__device__ __forceinline__ double sub_max(double v) {
+#pragma unroll
+    for (int o = W / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, W));
+    return v;
+}
+
+template <int W>
+__device__ __forceinline__ int sub_sum_int(int v) {
+#pragma unroll
+    for (int o = W / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, W);
+    return v;
+}
+
+// Block-wide sum of v; the total is valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double* lds) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int wid = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) lds[wid] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0) {
+        t = lds[0];
+#pragma unroll
+        for (int w = 1; w < kBlock / 64; ++w) t += lds[w];
+    }
+    __syncthreads();
+    return t;
+}
+
+// Deterministic grid reduction: every block stores its partial; the block
+// that finishes last sums the partials in index order and resets the counter.
+__device__ void grid_sum_finish(double v, const DotTarget& dot, int lb, int nblocks) {
+    __shared__ double lds[kBlock / 64];
+    __shared__ int is_last;
+    double t = block_sum(v, lds);
+    if (threadIdx.x == 0) {
+        dot.partials[lb] = t;
+        __threadfence();
+        unsigned prev = atomicAdd(dot.counter, 1u);
+        is_last = (prev == (unsigned)(nblocks - 1));
+    }
+    __syncthreads();
+    if (!is_last) return;
+    __threadfence();
+    double s = 0.0;
+    // each thread sums a contiguous slice, slices combined in thread order
+    const int per = (nblocks + kBlock - 1) / kBlock;
+    const int lo = threadIdx.x * per;
+    const int hi = min(nblocks, lo + per);
+    for (int i = lo; i < hi; ++i) s += dot.partials[i];
+    __shared__ double slice[kBlock];
+    slice[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tot = 0.0;
+        for (int i = 0; i < kBlock; ++i) tot += slice[i];
+        *dot.result = tot;
+        *dot.counter = 0u;
+    }
+}
+
+template <int OP>
+constexpr bool op_has_dot() {
+    return OP == kResidNorm || OP == kJacobiDot || OP == kSpmvDot;
+}
+
+template <int W, int OP>
+__global__ __launch_bounds__(kBlock) void row_kernel(CsrView a, const double* __restrict__ g,
+                                                     const double* u, const double* __restrict__ dinv,
+                                                     double omega, double* y, double* y2,
+                                                     DotTarget dot, int ntiles) {
+    constexpr int kRowsPerBlock = kBlock / W;
+    const int lb = xcd_logical_block();
+    const int sub = threadIdx.x / W;
+    const int lane = threadIdx.x & (W - 1);
+    double contrib = 0.0;
+    for (int tile = lb; tile < ntiles; tile += gridDim.x) {
+        const int row = tile * kRowsPerBlock + sub;
+        const bool active = row < a.rows;
+        double s = 0.0;
+        if (active) {
+            const int beg = a.rp[row], end = a.rp[row + 1];
+            for (int p = beg + lane; p < end; p += W) {
+                const int j = a.ci[p];
+                double gj;
+                if constexpr (OP == kZeroJacobiResid) gj = omega * (dinv[j] * u[j]);
+                else gj = g[j];
+                s += a.v[p] * gj;
+            }
+        }
+        s = sub_sum<W>(s);
+        if (active && lane == 0) {
+            if constexpr (OP == kSpmv) {
+                y[row] = s;
+            } else if constexpr (OP == kSpmvAdd) {
+                y[row] = u[row] + s;
+            } else if constexpr (OP == kResid || OP == kResidNorm) {
+                const double r = u[row] - s;
+                y[row] = r;
+                if constexpr (OP == kResidNorm) contrib += r * r;
+            } else if constexpr (OP == kJacobi || OP == kJacobiDot) {
+                const double ui = u[row];
+                const double xn = g[row] + omega * dinv[row] * (ui - s);
+                y[row] = xn;
+                if constexpr (OP == kJacobiDot) contrib += ui * xn;
+            } else if constexpr (OP == kZeroJacobiResid) {
+                const double ui = u[row];
+                y2[row] = omega * (dinv[row] * ui);
+                y[row] = ui - s;
+            } else if constexpr (OP == kSpmvDot) {
+                y[row] = s;
+                contrib += g[row] * s;
+            }
+        }
+    }
+    if constexpr (op_has_dot<OP>()) grid_sum_finish(contrib, dot, lb, gridDim.x);
+}
+
+template <int W>
+void launch_row_w(RowOp op, const CsrView& a, const double* g, const double* u, const double* dinv,
+                  double omega, double* y, double* y2, DotTarget dot, hipStream_t st) {
+    constexpr int kRowsPerBlock = kBlock / W;
+    const int ntiles = std::max(1, (a.rows + kRowsPerBlock - 1) / kRowsPerBlock);
+    const int grid = round_up8(std::min(ntiles, kRowGridCap));
+    switch (op) {
+#define AMG_ROW_CASE(OPV)                                                                      \
+    case OPV:                                                                                  \
+        hipLaunchKernelGGL((row_kernel<W, OPV>), dim3(grid), dim3(kBlock), 0, st, a, g, u, dinv, \
+                           omega, y, y2, dot, ntiles);                                         \
+        break;
+        AMG_ROW_CASE(kSpmv)
+        AMG_ROW_CASE(kSpmvAdd)
+        AMG_ROW_CASE(kResid)
+        AMG_ROW_CASE(kResidNorm)
+        AMG_ROW_CASE(kJacobi)
+        AMG_ROW_CASE(kJacobiDot)
+        AMG_ROW_CASE(kZeroJacobiResid)
+        AMG_ROW_CASE(kSpmvDot)
+#undef AMG_ROW_CASE
+        default: break;
+    }
+}
+
+// ---- vector kernels --------------------------------------------------------
+
+constexpr int kVecGrid = 2048;
+
+int vec_grid(int n) { return std::max(1, std::min(kVecGrid, (n + kBlock - 1) / kBlock)); }
+
+__global__ __launch_bounds__(kBlock) void cg_update_xr_kernel(int n, double* __restrict__ x,
+                                                              double* __restrict__ r,
+                                                              const double* __restrict__ p,
+                                                              const double* __restrict__ q,
+                                                              const double* scal, int i_num,
+                                                              int i_den, double* flag, DotTarget dot) {
+    const double num = scal[i_num], den = scal[i_den];
+    const bool ok = den > 0.0 && std::isfinite(den);
+    double contrib = 0.0;
+    if (ok) {
+        const double alpha = num / den;
+        for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+            x[i] = x[i] + alpha * p[i];
+            const double ri = r[i] - alpha * q[i];
+            r[i] = ri;
+            contrib += ri * ri;
+        }
+    } else if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *flag = 1.0;
+    }
+    grid_sum_finish(contrib, dot, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(kBlock) void cg_update_p_kernel(int n, double* __restrict__ p,
+                                                             const double* __restrict__ z,
+                                                             const double* scal, int i_num, int i_den) {
+    const double beta = scal[i_num] / scal[i_den];
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
+        p[i] = z[i] + beta * p[i];
+}
+
+__global__ __launch_bounds__(kBlock) void scaled_copy_kernel(int n, double* __restrict__ y,
+                                                             const double* __restrict__ dinv,
+                                                             const double* __restrict__ x, double omega) {
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
+        y[i] = omega * (dinv[i] * x[i]);
+}
+
+__global__ __launch_bounds__(kBlock) void copy_kernel(int n, double* __restrict__ y,
+                                                      const double* __restrict__ x) {
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) y[i] = x[i];
+}
+
+__global__ __launch_bounds__(kBlock) void fill_u8_kernel(int64_t n, uint8_t* p, uint8_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        p[i] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void fill_u32_kernel(int64_t n, unsigned* p, unsigned v) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        p[i] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void fill_f64_kernel(int64_t n, double* p, double v) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        p[i] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void dot_kernel(int n, const double* __restrict__ a,
+                                                     const double* __restrict__ b, DotTarget dot) {
+    double s = 0.0;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) s += a[i] * b[i];
+    grid_sum_finish(s, dot, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(kBlock) void dense_matvec_kernel(int n, const double* __restrict__ ainv,
+                                                              const double* __restrict__ b,
+                                                              double* __restrict__ y) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    const double* row = ainv + (size_t)i * n;
+    for (int j = 0; j < n; ++j) s += row[j] * b[j];
+    y[i] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void inverse_diagonal_kernel(CsrView a, double* __restrict__ dinv) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= a.rows) return;
+    double d = 0.0;
+    for (int p = a.rp[i]; p < a.rp[i + 1]; ++p)
+        if (a.ci[p] == i) d = a.v[p];
+    dinv[i] = 1.0 / d;
+}
+
+// ---- sparsification kernels --------------------------------------------------
+
+__device__ __forceinline__ int find_in_row(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                           int row, int col) {
+    int lo = rp[row], hi = rp[row + 1] - 1;
+    while (lo <= hi) {
+        const int mid = (lo + hi) >> 1;
+        const int c = ci[mid];
+        if (c == col) return mid;
+        if (c < col) lo = mid + 1;
+        else hi = mid - 1;
+    }
+    return -1;
+}
+
+__global__ __launch_bounds__(kBlock) void mark_minimal_pattern_kernel(
+    int nc, const int32_t* __restrict__ c_points, const int32_t* __restrict__ afine_rp,
+    const int32_t* __restrict__ afine_ci, const int32_t* __restrict__ p_rp,
+    const int32_t* __restrict__ p_ci, const int32_t* __restrict__ ac_rp,
+    const int32_t* __restrict__ ac_ci, uint8_t* in_m, int* missing) {
+    const int I = blockIdx.x * kBlock + threadIdx.x;
+    if (I >= nc) return;
+    const int f = c_points[I];
+    for (int p = afine_rp[f]; p < afine_rp[f + 1]; ++p) {
+        const int l = afine_ci[p];
+        for (int q = p_rp[l]; q < p_rp[l + 1]; ++q) {
+            const int J = p_ci[q];
+            const int a = find_in_row(ac_rp, ac_ci, I, J);
+            const int b = find_in_row(ac_rp, ac_ci, J, I);
+            if (a < 0 || b < 0) {
+                *missing = 1;
+                continue;
+            }
+            in_m[a] = 1;
+            in_m[b] = 1;
+        }
+    }
+}
+
+template <int W>
+__global__ __launch_bounds__(kBlock) void row_max_kernel(CsrView a, double* __restrict__ m) {
+    const int row = blockIdx.x * (kBlock / W) + threadIdx.x / W;
+    const int lane = threadIdx.x & (W - 1);
+    double mx = 0.0;
+    if (row < a.rows)
+        for (int p = a.rp[row] + lane; p < a.rp[row + 1]; p += W)
+            if (a.ci[p] != row) mx = fmax(mx, fabs(a.v[p]));
+    mx = sub_max<W>(mx);
+    if (row < a.rows && lane == 0) m[row] = mx;
+}
+
+template <int W>
+__global__ __launch_bounds__(kBlock) void keep_count_kernel(CsrView a, const uint8_t* __restrict__ in_m,
+                                                            const double* __restrict__ m, double gamma,
+                                                            uint8_t* __restrict__ keep,
+                                                            int32_t* __restrict__ cnt) {
+    const int row = blockIdx.x * (kBlock / W) + threadIdx.x / W;
+    const int lane = threadIdx.x & (W - 1);
+    int c = 0;
+    if (row < a.rows) {
+        // fl(gamma * m_i): one rounding, compared as is (no contraction is possible in a compare)
+        const double ti = gamma * m[row];
+        for (int p = a.rp[row] + lane; p < a.rp[row + 1]; p += W) {
+            const int j = a.ci[p];
+            const double av = fabs(a.v[p]);
+            const double tj = gamma * m[j];
+            const bool k = (j == row) || in_m[p] || av >= ti || av >= tj;
+            keep[p] = k ? 1 : 0;
+            c += k ? 1 : 0;
+        }
+    }
+    c = sub_sum_int<W>(c);
+    if (row < a.rows && lane == 0) cnt[row] = c;
+}
+
+template <int W>
+__global__ __launch_bounds__(kBlock) void compact_lump_kernel(CsrView a, const uint8_t* __restrict__ keep,
+                                                              const int32_t* __restrict__ new_rp,
+                                                              int32_t* __restrict__ new_ci,
+                                                              double* __restrict__ new_v,
+                                                              double* __restrict__ dinv) {
+    const int row = blockIdx.x * (kBlock / W) + threadIdx.x / W;
+    const int lane = threadIdx.x & (W - 1);
+    const int shift = (threadIdx.x & 63) & ~(W - 1);
+    const unsigned long long lanes_below = (lane == 0) ? 0ull : ((1ull << lane) - 1ull);
+    double dropped = 0.0, diag = 0.0;
+    int diag_pos = -1;
+    int written = 0;
+    const int beg = row < a.rows ? a.rp[row] : 0;
+    const int end = row < a.rows ? a.rp[row + 1] : 0;
+    const int out0 = row < a.rows ? new_rp[row] : 0;
+    for (int base = beg; base < end; base += W) {
+        const int p = base + lane;
+        bool k = false;
+        int j = -1;
+        double v = 0.0;
+        if (p < end) {
+            j = a.ci[p];
+            v = a.v[p];
+            k = keep[p] != 0;
+        }
+        unsigned long long bits = __ballot(k);
+        bits = (W == 64) ? bits : ((bits >> shift) & ((1ull << (W & 63)) - 1ull));
+        if (k) {
+            const int w = out0 + written + __popcll(bits & lanes_below);
+            new_ci[w] = j;
+            new_v[w] = v;
+            if (j == row) { diag_pos = w; diag = v; }
+        } else if (p < end && j != row) {
+            dropped += v;
+        }
+        written += __popcll(bits);
+    }
+    dropped = sub_sum<W>(dropped);
+    if (diag_pos >= 0) {
+        const double d = diag + dropped;
+        new_v[diag_pos] = d;
+        dinv[row] = 1.0 / d;
+    }
+}
+
+// exclusive scan: 1024 items per block in pass 1 and 3
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kBlock * kScanItems;
+
+__device__ __forceinline__ int block_exclusive_scan_int(int v, int* lds, int* total) {
+    // Hillis-Steele over the block in LDS
+    lds[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < kBlock; o <<= 1) {
+        const int t = threadIdx.x >= o ? lds[threadIdx.x - o] : 0;
+        __syncthreads();
+        lds[threadIdx.x] += t;
+        __syncthreads();
+    }
+    const int incl = lds[threadIdx.x];
+    *total = lds[kBlock - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ __launch_bounds__(kBlock) void scan_pass1_kernel(int n, const int32_t* __restrict__ cnt,
+                                                            int32_t* __restrict__ bsum) {
+    __shared__ int lds[kBlock];
+    const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) s += (base + k < n) ? cnt[base + k] : 0;
+    int tot;
+    block_exclusive_scan_int(s, lds, &tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(1024) void scan_pass2_kernel(int nb, int32_t* bsum) {
+    __shared__ int lds[1024];
+    const int per = (nb + 1023) / 1024;
+    const int lo = threadIdx.x * per, hi = min(nb, lo + per);
+    int s = 0;
+    for (int i = lo; i < hi; ++i) s += bsum[i];
+    lds[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const int t = threadIdx.x >= o ? lds[threadIdx.x - o] : 0;
+        __syncthreads();
+        lds[threadIdx.x] += t;
+        __syncthreads();
+    }
+    int run = lds[threadIdx.x] - s;
+    for (int i = lo; i < hi; ++i) {
+        const int v = bsum[i];
+        bsum[i] = run;
+        run += v;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void scan_pass3_kernel(int n, const int32_t* __restrict__ cnt,
+                                                            const int32_t* __restrict__ boff,
+                                                            int32_t* __restrict__ out) {
+    __shared__ int lds[kBlock];
+    const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    int v[kScanItems];
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = (base + k < n) ? cnt[base + k] : 0;
+        s += v[k];
+    }
+    int tot;
+    int run = block_exclusive_scan_int(s, lds, &tot) + boff[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < n) out[base + k] = run;
+        run += v[k];
+        if (base + k == n - 1) out[n] = run;
+    }
+}
+
+}  // namespace
+
+int pick_width(double mean) {
+    if (mean <= 4.5) return 4;
+    if (mean <= 9.0) return 8;
+    if (mean <= 20.0) return 16;
+    if (mean <= 48.0) return 32;
+    return 64;
+}
+
+int row_launch_blocks(int rows, int width) {
+    const int rpb = kBlock / width;
+    const int ntiles = std::max(1, (rows + rpb - 1) / rpb);
+    return round_up8(std::min(ntiles, kRowGridCap));
+}
+
+void launch_row_op(RowOp op, int width, const CsrView& a, const double* g, const double* u,
+                   const double* dinv, double omega, double* y, double* y2, DotTarget dot,
+                   hipStream_t st) {
+    switch (width) {
+        case 4: launch_row_w<4>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
+        case 8: launch_row_w<8>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
+        case 16: launch_row_w<16>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
+        case 32: launch_row_w<32>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
+        default: launch_row_w<64>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
+    }
+}
+
+void launch_cg_update_xr(int n, double* x, double* r, const double* p, const double* q,
+                         const double* scal, int i_num, int i_den, double* flag, DotTarget dot,
+                         hipStream_t st) {
+    hipLaunchKernelGGL(cg_update_xr_kernel, dim3(vec_grid(n)), dim3(kBlock), 0, st, n, x, r, p, q,
+                       scal, i_num, i_den, flag, dot);
+}
+
+void launch_cg_update_p(int n, double* p, const double* z, const double* scal, int i_num,
+                        int i_den, hipStream_t st) {
+    hipLaunchKernelGGL(cg_update_p_kernel, dim3(vec_grid(n)), dim3(kBlock), 0, st, n, p, z, scal,
+                       i_num, i_den);
+}
+
+void launch_scaled_copy(int n, double* y, const double* dinv, const double* x, double omega,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(scaled_copy_kernel, dim3(vec_grid(n)), dim3(kBlock), 0, st, n, y, dinv, x, omega);
+}
+
+void launch_copy(int n, double* y, const double* x, hipStream_t st) {
+    hipLaunchKernelGGL(copy_kernel, dim3(vec_grid(n)), dim3(kBlock), 0, st, n, y, x);
+}
+
+void launch_fill_u8(int64_t n, uint8_t* p, uint8_t v, hipStream_t st) {
+    const int g = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (n + kBlock - 1) / kBlock));
+    hipLaunchKernelGGL(fill_u8_kernel, dim3(g), dim3(kBlock), 0, st, n, p, v);
+}
+
+void launch_fill_u32(int64_t n, unsigned* p, unsigned v, hipStream_t st) {
+    const int g = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (n + kBlock - 1) / kBlock));
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(g), dim3(kBlock), 0, st, n, p, v);
+}
+
+void launch_fill_f64(int64_t n, double* p, double v, hipStream_t st) {
+    const int g = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (n + kBlock - 1) / kBlock));
+    hipLaunchKernelGGL(fill_f64_kernel, dim3(g), dim3(kBlock), 0, st, n, p, v);
+}
+
+void launch_dot(int n, const double* a, const double* b, DotTarget dot, hipStream_t st) {
+    hipLaunchKernelGGL(dot_kernel, dim3(vec_grid(n)), dim3(kBlock), 0, st, n, a, b, dot);
+}
+
+int vector_launch_blocks(int n) { return vec_grid(n); }
+
+void launch_dense_matvec(int n, const double* ainv, const double* b, double* y, hipStream_t st) {
+    hipLaunchKernelGGL(dense_matvec_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, n,
+                       ainv, b, y);
+}
+
+void launch_inverse_diagonal(const CsrView& a, double* dinv, hipStream_t st) {
+    hipLaunchKernelGGL(inverse_diagonal_kernel, dim3((a.rows + kBlock - 1) / kBlock), dim3(kBlock), 0,
+                       st, a, dinv);
+}
+
+void launch_mark_minimal_pattern(int nc, const int32_t* c_points, const int32_t* afine_rp,
+                                 const int32_t* afine_ci, const int32_t* p_rp,
+                                 const int32_t* p_ci, const int32_t* ac_rp, const int32_t* ac_ci,
+                                 uint8_t* in_m, int* missing, hipStream_t st) {
+    hipLaunchKernelGGL(mark_minimal_pattern_kernel, dim3((nc + kBlock - 1) / kBlock), dim3(kBlock), 0,
+                       st, nc, c_points, afine_rp, afine_ci, p_rp, p_ci, ac_rp, ac_ci, in_m, missing);
+}
+
+#define AMG_WIDTH_SWITCH(width, KERNEL, ...)                                                   \
+    do {                                                                                       \
+        switch (width) {                                                                       \
+            case 4: hipLaunchKernelGGL(KERNEL<4>, dim3((a.rows + kBlock / 4 - 1) / (kBlock / 4)), dim3(kBlock), 0, st, __VA_ARGS__); break;    \
+            case 8: hipLaunchKernelGGL(KERNEL<8>, dim3((a.rows + kBlock / 8 - 1) / (kBlock / 8)), dim3(kBlock), 0, st, __VA_ARGS__); break;    \
+            case 16: hipLaunchKernelGGL(KERNEL<16>, dim3((a.rows + kBlock / 16 - 1) / (kBlock / 16)), dim3(kBlock), 0, st, __VA_ARGS__); break; \
+            case 32: hipLaunchKernelGGL(KERNEL<32>, dim3((a.rows + kBlock / 32 - 1) / (kBlock / 32)), dim3(kBlock), 0, st, __VA_ARGS__); break; \
+            default: hipLaunchKernelGGL(KERNEL<64>, dim3((a.rows + kBlock / 64 - 1) / (kBlock / 64)), dim3(kBlock), 0, st, __VA_ARGS__); break; \
+        }                                                                                      \
+    } while (0)
+
+void launch_row_max(int width, const CsrView& a, double* m, hipStream_t st) {
+    if (a.rows <= 0) return;
+    AMG_WIDTH_SWITCH(width, row_max_kernel, a, m);
+}
+
+void launch_keep_count(int width, const CsrView& a, const uint8_t* in_m, const double* m,
+                       double gamma, uint8_t* keep, int32_t* cnt, hipStream_t st) {
+    if (a.rows <= 0) return;
+    AMG_WIDTH_SWITCH(width, keep_count_kernel, a, in_m, m, gamma, keep, cnt);
+}
+
+void launch_compact_lump(int width, const CsrView& a, const uint8_t* keep, const int32_t* new_rp,
+                         int32_t* new_ci, double* new_v, double* dinv, hipStream_t st) {
+    if (a.rows <= 0) return;
+    AMG_WIDTH_SWITCH(width, compact_lump_kernel, a, keep, new_rp, new_ci, new_v, dinv);
+}
+
+int64_t scan_scratch_ints(int n) { return (int64_t)(n + kScanTile - 1) / kScanTile + 1; }
+
+void launch_exclusive_scan(int n, const int32_t* cnt, int32_t* out, int32_t* scratch,
+                           hipStream_t st) {
+    const int nb = std::max(1, (n + kScanTile - 1) / kScanTile);
+    hipLaunchKernelGGL(scan_pass1_kernel, dim3(nb), dim3(kBlock), 0, st, n, cnt, scratch);
+    hipLaunchKernelGGL(scan_pass2_kernel, dim3(1), dim3(1024), 0, st, nb, scratch);
+    hipLaunchKernelGGL(scan_pass3_kernel, dim3(nb), dim3(kBlock), 0, st, n, cnt, scratch, out);
+}
+
+}  // namespace amg355

@@ -1,0 +1,96 @@
+// Device kernels of the sparsified-AMG hot path (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace amg355 {
+
+// Read-only view of a device CSR matrix.
+struct CsrView {
+    const int32_t* rp;
+    const int32_t* ci;
+    const double* v;
+    int rows;
+};
+
+// Epilogues of the CSR row kernel.  s_i = sum_j a_ij g_j (for kZeroJacobiResid
+// the gathered value is omega * dinv_j * u_j).
+enum RowOp : int {
+    kSpmv = 0,            // y_i = s_i
+    kSpmvAdd = 1,         // y_i = u_i + s_i                 (interpolate and correct)
+    kResid = 2,           // y_i = u_i - s_i                 (residual)
+    kResidNorm = 3,       // kResid, dot += y_i^2
+    kJacobi = 4,          // y_i = g_i + omega dinv_i (u_i - s_i)
+    kJacobiDot = 5,       // kJacobi, dot += u_i y_i
+    kZeroJacobiResid = 6, // y2_i = omega dinv_i u_i, y_i = u_i - s_i   (x0 = 0 sweep fused with residual)
+    kSpmvDot = 7,         // y_i = s_i, dot += g_i s_i
+    kNumRowOps = 8
+};
+
+// Deterministic two-level reduction target: per-block partials, a completion
+// counter and the slot that receives the final sum.
+struct DotTarget {
+    double* partials;     // >= number of blocks of the launch
+    unsigned* counter;    // zero before the launch; the last block resets it
+    double* result;       // receives the sum
+};
+
+// Lanes per row for a matrix with the given mean row length.
+int pick_width(double mean_row_len);
+
+// Number of blocks a row launch with this width uses (for partial buffers).
+int row_launch_blocks(int rows, int width);
+
+void launch_row_op(RowOp op, int width, const CsrView& a, const double* g, const double* u,
+                   const double* dinv, double omega, double* y, double* y2, DotTarget dot,
+                   hipStream_t st);
+
+// ---- vector kernels -----------------------------------------------------
+// x += alpha p; r -= alpha q; dot -> |r|^2, with alpha = scal[i_num]/scal[i_den].
+// If scal[i_den] is not positive and finite, nothing is updated and *flag = 1.0.
+void launch_cg_update_xr(int n, double* x, double* r, const double* p, const double* q,
+                         const double* scal, int i_num, int i_den, double* flag, DotTarget dot,
+                         hipStream_t st);
+// p = z + beta p with beta = scal[i_num]/scal[i_den]; if restart, p = z.
+void launch_cg_update_p(int n, double* p, const double* z, const double* scal, int i_num,
+                        int i_den, hipStream_t st);
+// y = omega dinv x (zero-guess smoothing of one sweep without residual)
+void launch_scaled_copy(int n, double* y, const double* dinv, const double* x, double omega,
+                        hipStream_t st);
+void launch_copy(int n, double* y, const double* x, hipStream_t st);
+void launch_fill_f64(int64_t n, double* p, double v, hipStream_t st);
+// dot -> sum_i a_i b_i
+void launch_dot(int n, const double* a, const double* b, DotTarget dot, hipStream_t st);
+// number of blocks of a vector-kernel launch over n entries (for partial buffers)
+int vector_launch_blocks(int n);
+void launch_fill_u8(int64_t n, uint8_t* p, uint8_t v, hipStream_t st);
+void launch_fill_u32(int64_t n, unsigned* p, unsigned v, hipStream_t st);
+// y = Ainv b for a dense row-major n x n inverse
+void launch_dense_matvec(int n, const double* ainv, const double* b, double* y, hipStream_t st);
+// dinv_i = 1 / a_ii
+void launch_inverse_diagonal(const CsrView& a, double* dinv, hipStream_t st);
+
+// ---- sparsification kernels ----------------------------------------------
+// Marks M_l: for coarse row I with fine point f = c_points[I], every column J
+// of P rows l' in row f of A_{l-1} gives (I,J) and (J,I) in A_l.
+void launch_mark_minimal_pattern(int nc, const int32_t* c_points, const int32_t* afine_rp,
+                                 const int32_t* afine_ci, const int32_t* p_rp,
+                                 const int32_t* p_ci, const int32_t* ac_rp, const int32_t* ac_ci,
+                                 uint8_t* in_m, int* missing, hipStream_t st);
+// m_i = max_{k != i} |a_ik|
+void launch_row_max(int width, const CsrView& a, double* m, hipStream_t st);
+// keep flags and per-row kept counts for tolerance gamma
+void launch_keep_count(int width, const CsrView& a, const uint8_t* in_m, const double* m,
+                       double gamma, uint8_t* keep, int32_t* cnt, hipStream_t st);
+// exclusive scan of cnt[0..n) into out[0..n], out[n] = total; scratch >= scan_scratch_ints(n)
+int64_t scan_scratch_ints(int n);
+void launch_exclusive_scan(int n, const int32_t* cnt, int32_t* out, int32_t* scratch,
+                           hipStream_t st);
+// compaction of the kept entries with the dropped ones added to the diagonal
+void launch_compact_lump(int width, const CsrView& a, const uint8_t* keep,
+                         const int32_t* new_rp, int32_t* new_ci, double* new_v, double* dinv,
+                         hipStream_t st);
+
+}  // namespace amg355
