@@ -11,8 +11,10 @@ no fallback path: loading fails loudly if the shared object is missing.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 from dataclasses import dataclass
 
 import numpy as np
@@ -117,20 +119,42 @@ def _torch():
     return torch
 
 
+_torch_mem = {}
+
+
 @C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
 def _torch_alloc(nbytes, stream, user):
-    import torch
     try:
-        return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+        if not _torch_mem:
+            import torch
+            _torch_mem["alloc"] = torch.cuda.caching_allocator_alloc
+            _torch_mem["free"] = torch.cuda.caching_allocator_delete
+        return _torch_mem["alloc"](int(nbytes), stream=int(stream or 0))
     except Exception:       # reported to the library as NULL -> out of memory
         return None
 
 
 @C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
 def _torch_free(ptr, nbytes, stream, user):
-    import torch
-    if ptr:
-        torch.cuda.caching_allocator_delete(int(ptr))
+    free = _torch_mem.get("free")
+    if ptr and free is not None:
+        try:
+            free(int(ptr))
+        except Exception:   # interpreter shutdown: the process releases the memory
+            pass
+
+
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    """Destroys the handles still alive before the interpreter tears torch down."""
+    for h in list(_live):
+        try:
+            h.close()
+        except Exception:
+            pass
 
 
 @dataclass
@@ -178,6 +202,7 @@ class Hierarchy:
         if st != OK:
             raise AmgError(st, lib.amg_last_error(None).decode())
         self._h = h
+        _live.add(self)
         nl = C.c_int32()
         self._check(lib.amg_num_levels(h, C.byref(nl)))
         self.nlev = nl.value

@@ -60,7 +60,8 @@ def build(verbose: bool = False) -> str:
     objs.append(obj)
     _run_all(cmds, verbose)
     tmp = LIB + ".tmp"
-    _run_all([[HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"]], verbose)
+    _run_all([[HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-Wl,-z,defs", "-o", tmp, *objs,
+                  "-lpthread"]], verbose)
     os.replace(tmp, LIB)
     return LIB
 

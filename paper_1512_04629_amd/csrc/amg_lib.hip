@@ -49,19 +49,22 @@ enum : int { S_RZ0 = 0, S_RZ1 = 1, S_PQ = 2, S_NR2 = 3, S_FLAG = 4, S_NRT = 5, S
 
 struct DevMat {
     int rows = 0, cols = 0;
-    int64_t nnz = 0;
+    int64_t nnz = 0;          // number of stored entries (valid when nnz_known)
+    int64_t shape_nnz = 0;    // entry count the launch configuration is chosen for
+    bool nnz_known = true;
     int32_t* rp = nullptr;
     int32_t* ci = nullptr;
     double* v = nullptr;
     int width = 8;
-    CsrView view() const { return CsrView{rp, ci, v, rows}; }
+    CsrView view() const { return CsrView{rp, ci, v, rows, rows ? (double)shape_nnz / rows : 1.0}; }
 };
 
 struct DevLevel {
     int n = 0;
     DevMat A;             // Galerkin operator (retained)
-    DevMat Ah;            // sparsified operator; aliases A while ah_alias
+    DevMat Ah;            // operator the cycle uses: A while ah_alias, else Ahs
     bool ah_alias = true;
+    DevMat Ahs;           // storage of the sparsified operator, capacity nnz(A)
     DevMat P, R;          // l < L
     int32_t* c_points = nullptr;  // fine index of each coarse point of level l+1
     int nc = 0;
@@ -100,7 +103,6 @@ struct amg_ctx {
     int nL = 0;
     double* coarse_inv = nullptr;
     double* scal = nullptr;
-    unsigned* counter = nullptr;
     double* partials = nullptr;
     int partial_cap = 0;
     double* pinned = nullptr;
@@ -110,6 +112,7 @@ struct amg_ctx {
     double *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_q = nullptr;
     double *xw = nullptr, *rt = nullptr;
     std::string last_error;
+    bool check_singular = false;   // a device inversion wrote h->missing
     bool profiling = false;
     int prof_kind = -1, prof_level = -1;
     std::vector<PendingEvent> pending;
@@ -184,6 +187,7 @@ DevMat upload_mat(amg_ctx* h, const HostCsr& m) {
     upload(h, d.rp, m.ptr.data(), d.rows + 1);
     upload(h, d.ci, m.idx.data(), d.nnz);
     upload(h, d.v, m.val.data(), d.nnz);
+    d.shape_nnz = d.nnz;
     d.width = pick_width(d.rows ? (double)d.nnz / d.rows : 1.0);
     return d;
 }
@@ -253,12 +257,12 @@ void prof_collect(amg_ctx* h) {
 // ---------------------------------------------------------------------------
 // launches
 // ---------------------------------------------------------------------------
-DotTarget dot_to(amg_ctx* h, int slot) { return DotTarget{h->partials, h->counter, h->scal + slot}; }
+DotTarget dot_to(amg_ctx* h, int slot) { return DotTarget{h->partials, h->scal + slot}; }
 
 void row_op(amg_ctx* h, int kind, int level, RowOp op, const DevMat& m, const double* g,
             const double* u, const double* dinv, double* y, double* y2, int dot_slot) {
     ProfScope ps(h, kind, level);
-    DotTarget dt = dot_slot >= 0 ? dot_to(h, dot_slot) : DotTarget{nullptr, nullptr, nullptr};
+    DotTarget dt = dot_slot >= 0 ? dot_to(h, dot_slot) : DotTarget{nullptr, nullptr};
     launch_row_op(op, m.width, m.view(), g, u, dinv, h->sp.omega, y, y2, dt, h->stream);
     check_launch();
 }
@@ -329,20 +333,42 @@ bool dense_inverse(int n, std::vector<double>& a, std::vector<double>& inv) {
     return true;
 }
 
+// Number of stored entries of a sparsified operator: kept on the device by
+// the scan and read back only when asked for.
+int64_t operator_nnz(amg_ctx* h, DevMat& m) {
+    if (!m.nnz_known) {
+        int32_t total = 0;
+        download(h, &total, m.rp + m.rows, 1);
+        sync(h);
+        m.nnz = total;
+        m.nnz_known = true;
+    }
+    return m.nnz;
+}
+
 void refresh_coarse_inverse(amg_ctx* h) {
     DevLevel& c = h->lv.back();
-    HostCsr m = download_mat(h, c.Ah);
-    const int n = m.rows;
-    std::vector<double> a((size_t)n * n, 0.0), inv;
-    for (int i = 0; i < n; ++i)
-        for (int p = m.ptr[i]; p < m.ptr[i + 1]; ++p) a[(size_t)i * n + m.idx[p]] = m.val[p];
-    if (!dense_inverse(n, a, inv))
-        throw AmgFailure{AMG_ERR_BAD_MATRIX, "coarsest operator is singular"};
+    const int n = c.n;
     if (!h->coarse_inv || h->nL != n) {
         dfree(h, h->coarse_inv);
         h->coarse_inv = dalloc_n<double>(h, (int64_t)n * n);
     }
     h->nL = n;
+    if (n <= dense_invert_max()) {
+        // on the device, stream ordered after the operator it inverts
+        launch_fill_u32(1, reinterpret_cast<unsigned*>(h->missing), 0u, h->stream);
+        launch_dense_invert(c.Ah.view(), h->coarse_inv, h->missing, h->stream);
+        check_launch();
+        h->check_singular = true;
+        return;
+    }
+    operator_nnz(h, c.Ah);
+    HostCsr m = download_mat(h, c.Ah);
+    std::vector<double> a((size_t)n * n, 0.0), inv;
+    for (int i = 0; i < n; ++i)
+        for (int p = m.ptr[i]; p < m.ptr[i + 1]; ++p) a[(size_t)i * n + m.idx[p]] = m.val[p];
+    if (!dense_inverse(n, a, inv))
+        throw AmgFailure{AMG_ERR_BAD_MATRIX, "coarsest operator is singular"};
     upload(h, h->coarse_inv, inv.data(), (int64_t)n * n);
     sync(h);
 }
@@ -373,74 +399,52 @@ void ensure_minimal_pattern(amg_ctx* h, int l) {
     c.have_m = true;
 }
 
-struct NewOperator {
-    int level;
-    double gamma;
-    bool alias;
-    DevMat m;
-    double* dinv;
-};
-
-NewOperator build_sparsified(amg_ctx* h, int l, double gamma) {
-    DevLevel& c = h->lv[l];
-    NewOperator out{l, gamma, gamma == 0.0, DevMat{}, nullptr};
-    out.dinv = dalloc_n<double>(h, c.n);
-    if (out.alias) {
-        ProfScope ps(h, AMG_K_SPARSIFY, l);
-        launch_inverse_diagonal(c.A.view(), out.dinv, h->stream);
-        check_launch();
-        return out;
-    }
-    ensure_minimal_pattern(h, l);
-    int32_t* rp = dalloc_n<int32_t>(h, c.n + 1);
-    {
-        ProfScope ps(h, AMG_K_SPARSIFY, l);
-        launch_keep_count(c.A.width, c.A.view(), c.in_m, c.rowmax, gamma, c.keep, h->cnt, h->stream);
-        launch_exclusive_scan(c.n, h->cnt, rp, h->scan_scratch, h->stream);
-        check_launch();
-    }
-    int32_t total = 0;
-    download(h, &total, rp + c.n, 1);
-    sync(h);
-    out.m.rows = out.m.cols = c.n;
-    out.m.nnz = total;
-    out.m.rp = rp;
-    out.m.ci = dalloc_n<int32_t>(h, total);
-    out.m.v = dalloc_n<double>(h, total);
-    out.m.width = pick_width((double)total / std::max(1, c.n));
-    {
-        ProfScope ps(h, AMG_K_SPARSIFY, l);
-        launch_compact_lump(c.A.width, c.A.view(), c.keep, rp, out.m.ci, out.m.v, out.dinv, h->stream);
-        check_launch();
-    }
-    return out;
-}
-
 // Rebuilds the sparsified operators of the given levels at the given
-// tolerances.  All new operators are built before any is swapped in.
+// tolerances, asynchronously on the handle's stream.  The storage of a
+// sparsified operator is allocated once with the capacity of the Galerkin
+// operator, so after the first call nothing is allocated and nothing waits
+// for the device; any allocation happens before a level is modified.
 void sparsify_levels(amg_ctx* h, const std::vector<std::pair<int, double>>& todo) {
-    std::vector<NewOperator> built;
-    try {
-        for (auto& t : todo) built.push_back(build_sparsified(h, t.first, t.second));
-        sync(h);
-    } catch (...) {
-        for (auto& b : built) {
-            if (!b.alias) free_mat(h, b.m);
-            dfree(h, b.dinv);
+    for (auto& t : todo) {
+        DevLevel& c = h->lv[t.first];
+        if (t.second == 0.0) continue;
+        ensure_minimal_pattern(h, t.first);
+        if (!c.Ahs.rp) {
+            c.Ahs.rows = c.Ahs.cols = c.n;
+            c.Ahs.rp = dalloc_n<int32_t>(h, c.n + 1);
+            c.Ahs.ci = dalloc_n<int32_t>(h, c.A.nnz);
+            c.Ahs.v = dalloc_n<double>(h, c.A.nnz);
+            c.Ahs.shape_nnz = c.A.nnz;
+            c.Ahs.width = c.A.width;
         }
-        throw;
     }
     bool coarse_changed = false;
-    for (auto& b : built) {
-        DevLevel& c = h->lv[b.level];
-        if (!c.ah_alias) free_mat(h, c.Ah);
-        dfree(h, c.dinv);
-        c.ah_alias = b.alias;
-        c.Ah = b.alias ? c.A : b.m;
-        c.dinv = b.dinv;
-        c.gamma = b.gamma;
-        c.keep_valid = !b.alias;
-        if (b.level == (int)h->lv.size() - 1) coarse_changed = true;
+    for (auto& t : todo) {
+        const int l = t.first;
+        const double gamma = t.second;
+        DevLevel& c = h->lv[l];
+        ProfScope ps(h, AMG_K_SPARSIFY, l);
+        if (gamma == 0.0) {
+            if (!c.ah_alias) {
+                c.Ah = c.A;
+                c.ah_alias = true;
+                launch_inverse_diagonal(c.A.view(), c.dinv, h->stream);
+                if (l == (int)h->lv.size() - 1) coarse_changed = true;
+            }
+            c.gamma = 0.0;
+            c.keep_valid = false;
+        } else {
+            launch_keep_count(c.A.width, c.A.view(), c.in_m, c.rowmax, gamma, c.keep, h->cnt, h->stream);
+            launch_exclusive_scan(c.n, h->cnt, c.Ahs.rp, h->scan_scratch, h->stream);
+            launch_compact_lump(c.A.width, c.A.view(), c.keep, c.Ahs.rp, c.Ahs.ci, c.Ahs.v, c.dinv, h->stream);
+            c.Ahs.nnz_known = false;
+            c.Ah = c.Ahs;
+            c.ah_alias = false;
+            c.gamma = gamma;
+            c.keep_valid = true;
+            if (l == (int)h->lv.size() - 1) coarse_changed = true;
+        }
+        check_launch();
     }
     if (coarse_changed) refresh_coarse_inverse(h);
 }
@@ -464,7 +468,21 @@ void jacobi_sweeps(amg_ctx* h, int l, const DevMat& m, const double* dinv, const
     }
 }
 
-void vcycle(amg_ctx* h, const double* b0, double* x0, bool zero0, int dot_slot) {
+enum class Guess { kNonzero, kZero, kPrescaled };
+
+// Buffer that receives the zero-guess smoothing sweep omega D^-1 b of level
+// l: on level 0 chosen so that after all later sweeps (each swaps buffers)
+// the result lands in x0.
+double* zero_start(amg_ctx* h, int l, double* x0) {
+    if (l > 0) return h->lv[l].x;
+    const int swaps = std::max(h->sp.nu_pre - 1, 0) + h->sp.nu_post;
+    return (swaps & 1) ? h->lv[0].xt : x0;
+}
+
+// guess0: kNonzero -- x0 holds the iterate; kZero -- the iterate is zero;
+// kPrescaled -- the iterate is zero and zero_start(h, 0, x0) already holds
+// the first sweep omega D^-1 b0 (written by the CG update).
+void vcycle(amg_ctx* h, const double* b0, double* x0, Guess guess0, int dot_slot) {
     const int L = (int)h->lv.size() - 1;
     const int pre = h->sp.nu_pre, post = h->sp.nu_post;
     if (L == 0) {
@@ -478,33 +496,37 @@ void vcycle(amg_ctx* h, const double* b0, double* x0, bool zero0, int dot_slot) 
     for (int l = 0; l < L; ++l) {
         DevLevel& v = h->lv[l];
         const double* b = l == 0 ? b0 : v.b;
-        cur[l] = l == 0 ? x0 : v.x;
-        alt[l] = v.xt;
-        const bool zero = l == 0 ? zero0 : true;
-        // every sweep after the first zero-guess one swaps the buffers; with
-        // a zero initial iterate start in the buffer that makes the result
-        // land in x0 on level 0
-        const int swaps = (zero ? std::max(pre - 1, 0) : pre) + post;
-        if (l == 0 && zero && (swaps & 1)) std::swap(cur[0], alt[0]);
+        const bool zero = l > 0 || guess0 != Guess::kNonzero;
+        // on coarse levels the restriction has already written omega D^-1 b
+        const bool prescaled = pre >= 1 && (l > 0 || guess0 == Guess::kPrescaled);
+        cur[l] = zero ? zero_start(h, l, x0) : x0;
+        alt[l] = cur[l] == v.xt ? (l == 0 ? x0 : v.x) : v.xt;
         bool have_resid = false;
         if (zero) {
             if (pre == 0) {
                 launch_fill_f64(v.n, cur[l], 0.0, h->stream);
                 launch_copy(v.n, v.r, b, h->stream);
                 have_resid = true;
-            } else if (pre == 1) {
+            } else if (pre == 1 && !prescaled) {
                 row_op(h, AMG_K_JACOBI_ZERO, l, kZeroJacobiResid, v.Ah, nullptr, b, v.dinv, v.r, cur[l], -1);
                 have_resid = true;
             } else {
-                launch_scaled_copy(v.n, cur[l], v.dinv, b, h->sp.omega, h->stream);
+                if (!prescaled) launch_scaled_copy(v.n, cur[l], v.dinv, b, h->sp.omega, h->stream);
                 jacobi_sweeps(h, l, v.Ah, v.dinv, b, cur[l], alt[l], pre - 1, -1);
             }
         } else {
             jacobi_sweeps(h, l, v.Ah, v.dinv, b, cur[l], alt[l], pre, -1);
         }
-        if (!have_resid) row_op(h, AMG_K_RESIDUAL, l, kResid, v.Ah, cur[l], b, nullptr, v.r, nullptr, -1);
+        if (!have_resid) {
+            const int kind = (zero && pre == 1) ? AMG_K_JACOBI_ZERO : AMG_K_RESIDUAL;
+            row_op(h, kind, l, kResid, v.Ah, cur[l], b, nullptr, v.r, nullptr, -1);
+        }
         DevLevel& nx = h->lv[l + 1];
-        row_op(h, AMG_K_RESTRICT, l, kSpmv, v.R, v.r, nullptr, nullptr, nx.b, nullptr, -1);
+        if (pre >= 1 && l + 1 < L)
+            row_op(h, AMG_K_RESTRICT, l, kSpmvScale, v.R, v.r, nullptr, nx.dinv, nx.b,
+                   zero_start(h, l + 1, nullptr), -1);
+        else
+            row_op(h, AMG_K_RESTRICT, l, kSpmv, v.R, v.r, nullptr, nullptr, nx.b, nullptr, -1);
     }
     {
         DevLevel& c = h->lv[L];
@@ -574,7 +596,13 @@ amg_status solve(amg_ctx* h, const double* b, double* x, const amg_solve_params&
     double* r = h->cg_r;
     launch_fill_f64(S_COUNT, h->scal, 0.0, h->stream);
     row_op(h, AMG_K_RESIDUAL, 0, kResidNorm, A, x, b, nullptr, r, nullptr, S_NR2);
+    int singular = 0;
+    if (h->check_singular) download(h, &singular, h->missing, 1);
     const double nr0 = std::sqrt(read_scalars(h)[S_NR2]);
+    if (h->check_singular) {
+        h->check_singular = false;
+        if (singular) throw AmgFailure{AMG_ERR_BAD_MATRIX, "coarsest operator is singular"};
+    }
     if (hist) hist[0] = nr0;
     double nws = nr0;
     int inwin = 0;
@@ -587,7 +615,7 @@ amg_status solve(amg_ctx* h, const double* b, double* x, const amg_solve_params&
     } else {
         launch_copy(n, h->xw, x, h->stream);
         if (pcg) {
-            vcycle(h, r, h->cg_z, true, rz_slot);
+            vcycle(h, r, h->cg_z, Guess::kZero, rz_slot);
             launch_copy(n, h->cg_p, h->cg_z, h->stream);
         }
         while (info.iters < p.maxit) {
@@ -595,12 +623,14 @@ amg_status solve(amg_ctx* h, const double* b, double* x, const amg_solve_params&
                 row_op(h, AMG_K_SPMV_DOT, 0, kSpmvDot, A, h->cg_p, nullptr, nullptr, h->cg_q, nullptr, S_PQ);
                 {
                     ProfScope ps(h, AMG_K_VECTOR, 0);
+                    // also forms the next preconditioner's zero-guess sweep omega D^-1 r
                     launch_cg_update_xr(n, x, r, h->cg_p, h->cg_q, h->scal, rz_slot, S_PQ, h->scal + S_FLAG,
-                                        dot_to(h, S_NR2), h->stream);
+                                        dot_to(h, S_NR2), f.dinv, h->sp.omega,
+                                        h->sp.nu_pre >= 1 ? zero_start(h, 0, h->cg_z) : nullptr, h->stream);
                     check_launch();
                 }
             } else {
-                vcycle(h, b, x, false, -1);
+                vcycle(h, b, x, Guess::kNonzero, -1);
                 row_op(h, AMG_K_RESIDUAL, 0, kResidNorm, A, x, b, nullptr, r, nullptr, S_NR2);
             }
             const double* sc = read_scalars(h);
@@ -638,7 +668,8 @@ amg_status solve(amg_ctx* h, const double* b, double* x, const amg_solve_params&
             }
             if (pcg) {
                 const int new_slot = rz_slot == S_RZ0 ? S_RZ1 : S_RZ0;
-                vcycle(h, r, h->cg_z, true, new_slot);
+                // after a restart r was rebuilt, so the prescaled sweep is stale
+                vcycle(h, r, h->cg_z, restart ? Guess::kZero : Guess::kPrescaled, new_slot);
                 if (restart) {
                     info.restarts++;
                     launch_copy(n, h->cg_p, h->cg_z, h->stream);
@@ -717,17 +748,15 @@ void setup(amg_ctx* h, int64_t n, const int32_t* row_ptr, const int32_t* col, co
     }
     // sparsified-operator widths are chosen per build; partial buffers cover
     // every width for the largest level
-    partial_need = std::max(partial_need, row_launch_blocks(h->lv[0].n, 4));
+    partial_need = std::max(partial_need, max_row_launch_blocks());
     h->partial_cap = partial_need;
     h->partials = dalloc_n<double>(h, partial_need);
-    h->counter = dalloc_n<unsigned>(h, 1);
     h->scal = dalloc_n<double>(h, S_COUNT);
     h->missing = dalloc_n<int>(h, 1);
     int nmax = 0;
     for (auto& d : h->lv) nmax = std::max(nmax, d.n);
     h->cnt = dalloc_n<int32_t>(h, nmax + 1);
     h->scan_scratch = dalloc_n<int32_t>(h, scan_scratch_ints(nmax));
-    launch_fill_u32(1, h->counter, 0u, h->stream);
     launch_fill_f64(S_COUNT, h->scal, 0.0, h->stream);
     check_launch();
     HIP_CHECK(hipHostMalloc((void**)&h->pinned, sizeof(double) * S_COUNT, hipHostMallocDefault));
@@ -740,7 +769,7 @@ void destroy(amg_ctx* h) {
     if (!h) return;
     (void)hipStreamSynchronize(h->stream);
     for (auto& d : h->lv) {
-        if (!d.ah_alias) free_mat(h, d.Ah);
+        free_mat(h, d.Ahs);
         free_mat(h, d.A);
         free_mat(h, d.P);
         free_mat(h, d.R);
@@ -754,7 +783,7 @@ void destroy(amg_ctx* h) {
         dfree(h, d.xt);
         dfree(h, d.r);
     }
-    for (void* p : {(void*)h->coarse_inv, (void*)h->scal, (void*)h->counter, (void*)h->partials,
+    for (void* p : {(void*)h->coarse_inv, (void*)h->scal, (void*)h->partials,
                     (void*)h->scan_scratch, (void*)h->cnt, (void*)h->missing, (void*)h->cg_r,
                     (void*)h->cg_z, (void*)h->cg_p, (void*)h->cg_q, (void*)h->xw, (void*)h->rt})
         dfree(h, p);
@@ -920,7 +949,7 @@ amg_status amg_vcycle(amg_handle h, const double* b, double* x) {
     if (!h || h->lv.empty()) return AMG_ERR_STATE;
     if (!b || !x) return AMG_ERR_INVALID_ARG;
     return guarded(h, [&] {
-        vcycle(h, b, x, false, -1);
+        vcycle(h, b, x, Guess::kNonzero, -1);
         prof_collect(h);
         return AMG_OK;
     });
@@ -980,14 +1009,14 @@ amg_status amg_num_levels(amg_handle h, int32_t* nlev) {
     return AMG_OK;
 }
 
-static int64_t level_bytes(const amg_ctx* h, int l) {
+static int64_t level_bytes(amg_ctx* h, int l) {
     // algorithmic bytes of one zero-guess V-cycle's work on level l: FP64
     // values, int32 indices, every vector entry counted once per kernel
-    const DevLevel& v = h->lv[l];
+    DevLevel& v = h->lv[l];
     const int L = (int)h->lv.size() - 1;
     const int64_t n = v.n;
     if (l == L) return 8 * n * n + 16 * n;
-    const int64_t nnz = v.Ah.nnz, nc = v.nc;
+    const int64_t nnz = operator_nnz(h, v.Ah), nc = v.nc;
     int64_t b = 0;
     b += 12 * nnz + 4 * (n + 1) + 32 * n;                 // zero-guess sweep fused with residual
     b += 12 * v.R.nnz + 4 * (nc + 1) + 8 * n + 8 * nc;    // restriction
@@ -1000,15 +1029,17 @@ amg_status amg_get_level(amg_handle h, int32_t l, int64_t* n, int64_t* nnz_galer
                          int64_t* nnz_p, int64_t* n_coarse, double* gamma, int64_t* bytes) {
     if (!h || h->lv.empty()) return AMG_ERR_STATE;
     if (l < 0 || l >= (int)h->lv.size()) return AMG_ERR_INVALID_ARG;
-    const DevLevel& v = h->lv[l];
-    if (n) *n = v.n;
-    if (nnz_galerkin) *nnz_galerkin = v.A.nnz;
-    if (nnz_sparse) *nnz_sparse = v.Ah.nnz;
-    if (nnz_p) *nnz_p = v.P.nnz;
-    if (n_coarse) *n_coarse = v.nc;
-    if (gamma) *gamma = v.gamma;
-    if (bytes) *bytes = level_bytes(h, l);
-    return AMG_OK;
+    return guarded(h, [&] {
+        DevLevel& v = h->lv[l];
+        if (n) *n = v.n;
+        if (nnz_galerkin) *nnz_galerkin = v.A.nnz;
+        if (nnz_sparse) *nnz_sparse = operator_nnz(h, v.Ah);
+        if (nnz_p) *nnz_p = v.P.nnz;
+        if (n_coarse) *n_coarse = v.nc;
+        if (gamma) *gamma = v.gamma;
+        if (bytes) *bytes = level_bytes(h, l);
+        return AMG_OK;
+    });
 }
 
 amg_status amg_export_level(amg_handle h, int32_t l, int32_t which, int32_t* row_ptr, int32_t* col,
@@ -1016,10 +1047,11 @@ amg_status amg_export_level(amg_handle h, int32_t l, int32_t which, int32_t* row
     if (!h || h->lv.empty()) return AMG_ERR_STATE;
     if (l < 0 || l >= (int)h->lv.size()) return AMG_ERR_INVALID_ARG;
     return guarded(h, [&] {
-        const DevLevel& v = h->lv[l];
-        const DevMat* m = which == AMG_MAT_A ? &v.A : which == AMG_MAT_AHAT ? &v.Ah
-                        : which == AMG_MAT_P ? &v.P : which == AMG_MAT_R ? &v.R : nullptr;
+        DevLevel& v = h->lv[l];
+        DevMat* m = which == AMG_MAT_A ? &v.A : which == AMG_MAT_AHAT ? &v.Ah
+                  : which == AMG_MAT_P ? &v.P : which == AMG_MAT_R ? &v.R : nullptr;
         if (!m || !m->rp) return AMG_ERR_INVALID_ARG;
+        operator_nnz(h, *m);
         if (row_ptr) download(h, row_ptr, m->rp, m->rows + 1);
         if (col) download(h, col, m->ci, m->nnz);
         if (val) download(h, val, m->v, m->nnz);

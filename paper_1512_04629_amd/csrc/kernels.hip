@@ -17,14 +17,40 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kXcds = 8;            // MI355X: 8 accelerator complex dies, each with its own L2
-constexpr int kRowGridCap = 8192;   // row kernels loop over tiles beyond this many blocks
+constexpr int kRowGridCap = 4096;   // row kernels loop over tiles beyond this many blocks
+
+// Tuning knobs (compile-time): lanes-per-row thresholds are scaled by
+// AMG_WIDTH_SCALE (1 = the power of two nearest the mean row length),
+// AMG_RIF is the number of row tiles in flight per subgroup, AMG_MIN_WIDTH the
+// narrowest subgroup, AMG_USE_STREAM selects the LDS-staged kernel (-1: by
+// matrix shape, 0: never, 1: always), AMG_XCD_REMAP toggles
+// the XCD-contiguous block order.
+#ifndef AMG_WIDTH_SCALE
+#define AMG_WIDTH_SCALE 0.5
+#endif
+#ifndef AMG_RIF
+#define AMG_RIF 1
+#endif
+#ifndef AMG_MIN_WIDTH
+#define AMG_MIN_WIDTH 1
+#endif
+#ifndef AMG_USE_STREAM
+#define AMG_USE_STREAM -1
+#endif
+#ifndef AMG_XCD_REMAP
+#define AMG_XCD_REMAP 1
+#endif
 
 // Workgroups are handed to the XCDs round-robin.  Remap so that XCD x works on
 // a contiguous range of logical blocks: neighbouring rows gather neighbouring
 // entries of x, which then stay in one L2.  The grid is a multiple of 8.
 __device__ __forceinline__ int xcd_logical_block() {
+#if AMG_XCD_REMAP
     const int per = gridDim.x / kXcds;
     return (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+#else
+    return blockIdx.x;
+#endif
 }
 
 int round_up8(int b) { return (b + kXcds - 1) / kXcds * kXcds; }
@@ -67,41 +93,48 @@ __device__ __forceinline__ double block_sum(double v, double* lds) {
     return t;
 }
 
-// Deterministic grid reduction: every block stores its partial; the block
-// that finishes last sums the partials in index order and resets the counter.
-__device__ void grid_sum_finish(double v, const DotTarget& dot, int lb, int nblocks) {
+// Deterministic grid reduction, first pass: every block stores its partial
+// sum; dot_finish_kernel adds the partials in index order.  (A single-pass
+// last-block scheme would need an agent-scope release fence per block, which
+// on gfx950 writes back the XCD's L2 and stalls the block.)
+__device__ __forceinline__ void store_block_partial(double v, double* partials, int lb) {
     __shared__ double lds[kBlock / 64];
-    __shared__ int is_last;
-    double t = block_sum(v, lds);
-    if (threadIdx.x == 0) {
-        dot.partials[lb] = t;
-        __threadfence();
-        unsigned prev = atomicAdd(dot.counter, 1u);
-        is_last = (prev == (unsigned)(nblocks - 1));
-    }
-    __syncthreads();
-    if (!is_last) return;
-    __threadfence();
-    double s = 0.0;
-    // each thread sums a contiguous slice, slices combined in thread order
-    const int per = (nblocks + kBlock - 1) / kBlock;
-    const int lo = threadIdx.x * per;
-    const int hi = min(nblocks, lo + per);
-    for (int i = lo; i < hi; ++i) s += dot.partials[i];
+    const double t = block_sum(v, lds);
+    if (threadIdx.x == 0) partials[lb] = t;
+}
+
+__global__ __launch_bounds__(kBlock) void dot_finish_kernel(int nparts, const double* __restrict__ partials,
+                                                            double* __restrict__ result) {
     __shared__ double slice[kBlock];
+    const int per = (nparts + kBlock - 1) / kBlock;
+    const int lo = threadIdx.x * per;
+    const int hi = min(nparts, lo + per);
+    double s = 0.0;
+    for (int i = lo; i < hi; ++i) s += partials[i];
     slice[threadIdx.x] = s;
     __syncthreads();
     if (threadIdx.x == 0) {
         double tot = 0.0;
         for (int i = 0; i < kBlock; ++i) tot += slice[i];
-        *dot.result = tot;
-        *dot.counter = 0u;
+        *result = tot;
     }
+}
+
+void finish_dot(const DotTarget& dot, int nparts, hipStream_t st) {
+    hipLaunchKernelGGL(dot_finish_kernel, dim3(1), dim3(kBlock), 0, st, nparts, dot.partials, dot.result);
 }
 
 template <int OP>
 constexpr bool op_has_dot() {
     return OP == kResidNorm || OP == kJacobiDot || OP == kSpmvDot;
+}
+
+// Rows in flight per subgroup: the loads of R row tiles are issued before
+// any of them is consumed, so that each lane has R independent
+// (row pointer -> column/value -> gathered entry) chains outstanding.
+template <int W>
+constexpr int rows_in_flight() {
+    return W <= 16 ? AMG_RIF : 1;
 }
 
 template <int W, int OP>
@@ -110,58 +143,91 @@ __global__ __launch_bounds__(kBlock) void row_kernel(CsrView a, const double* __
                                                      double omega, double* y, double* y2,
                                                      DotTarget dot, int ntiles) {
     constexpr int kRowsPerBlock = kBlock / W;
+    constexpr int R = rows_in_flight<W>();
     const int lb = xcd_logical_block();
     const int sub = threadIdx.x / W;
     const int lane = threadIdx.x & (W - 1);
     double contrib = 0.0;
-    for (int tile = lb; tile < ntiles; tile += gridDim.x) {
-        const int row = tile * kRowsPerBlock + sub;
-        const bool active = row < a.rows;
-        double s = 0.0;
-        if (active) {
-            const int beg = a.rp[row], end = a.rp[row + 1];
-            for (int p = beg + lane; p < end; p += W) {
+    for (int t0 = lb * R; t0 < ntiles; t0 += gridDim.x * R) {
+        int row[R], beg[R], end[R];
+        double s[R], ui[R], gi[R], di[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            row[k] = (t0 + k) * kRowsPerBlock + sub;
+            const bool act = row[k] < a.rows;
+            beg[k] = act ? a.rp[row[k]] : 0;
+            end[k] = act ? a.rp[row[k] + 1] : 0;
+            ui[k] = gi[k] = di[k] = 0.0;
+            if (act && lane == 0) {
+                if constexpr (OP != kSpmv && OP != kSpmvDot && OP != kSpmvScale) ui[k] = u[row[k]];
+                if constexpr (OP == kJacobi || OP == kJacobiDot || OP == kSpmvDot) gi[k] = g[row[k]];
+                if constexpr (OP == kJacobi || OP == kJacobiDot || OP == kZeroJacobiResid || OP == kSpmvScale)
+                    di[k] = dinv[row[k]];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            s[k] = 0.0;
+            const int p = beg[k] + lane;
+            if (p < end[k]) {
                 const int j = a.ci[p];
                 double gj;
                 if constexpr (OP == kZeroJacobiResid) gj = omega * (dinv[j] * u[j]);
                 else gj = g[j];
-                s += a.v[p] * gj;
+                s[k] = a.v[p] * gj;
             }
         }
-        s = sub_sum<W>(s);
-        if (active && lane == 0) {
-            if constexpr (OP == kSpmv) {
-                y[row] = s;
-            } else if constexpr (OP == kSpmvAdd) {
-                y[row] = u[row] + s;
-            } else if constexpr (OP == kResid || OP == kResidNorm) {
-                const double r = u[row] - s;
-                y[row] = r;
-                if constexpr (OP == kResidNorm) contrib += r * r;
-            } else if constexpr (OP == kJacobi || OP == kJacobiDot) {
-                const double ui = u[row];
-                const double xn = g[row] + omega * dinv[row] * (ui - s);
-                y[row] = xn;
-                if constexpr (OP == kJacobiDot) contrib += ui * xn;
-            } else if constexpr (OP == kZeroJacobiResid) {
-                const double ui = u[row];
-                y2[row] = omega * (dinv[row] * ui);
-                y[row] = ui - s;
-            } else if constexpr (OP == kSpmvDot) {
-                y[row] = s;
-                contrib += g[row] * s;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            for (int p = beg[k] + lane + W; p < end[k]; p += W) {
+                const int j = a.ci[p];
+                double gj;
+                if constexpr (OP == kZeroJacobiResid) gj = omega * (dinv[j] * u[j]);
+                else gj = g[j];
+                s[k] += a.v[p] * gj;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const double sk = sub_sum<W>(s[k]);
+            if (row[k] < a.rows && lane == 0) {
+                const int r = row[k];
+                if constexpr (OP == kSpmv) {
+                    y[r] = sk;
+                } else if constexpr (OP == kSpmvAdd) {
+                    y[r] = ui[k] + sk;
+                } else if constexpr (OP == kResid || OP == kResidNorm) {
+                    const double rr = ui[k] - sk;
+                    y[r] = rr;
+                    if constexpr (OP == kResidNorm) contrib += rr * rr;
+                } else if constexpr (OP == kJacobi || OP == kJacobiDot) {
+                    const double xn = gi[k] + omega * di[k] * (ui[k] - sk);
+                    y[r] = xn;
+                    if constexpr (OP == kJacobiDot) contrib += ui[k] * xn;
+                } else if constexpr (OP == kZeroJacobiResid) {
+                    y2[r] = omega * (di[k] * ui[k]);
+                    y[r] = ui[k] - sk;
+                } else if constexpr (OP == kSpmvDot) {
+                    y[r] = sk;
+                    contrib += gi[k] * sk;
+                } else if constexpr (OP == kSpmvScale) {
+                    y[r] = sk;
+                    y2[r] = omega * (di[k] * sk);
+                }
             }
         }
     }
-    if constexpr (op_has_dot<OP>()) grid_sum_finish(contrib, dot, lb, gridDim.x);
+    if constexpr (op_has_dot<OP>()) store_block_partial(contrib, dot.partials, lb);
 }
 
 template <int W>
 void launch_row_w(RowOp op, const CsrView& a, const double* g, const double* u, const double* dinv,
                   double omega, double* y, double* y2, DotTarget dot, hipStream_t st) {
     constexpr int kRowsPerBlock = kBlock / W;
+    constexpr int R = rows_in_flight<W>();
     const int ntiles = std::max(1, (a.rows + kRowsPerBlock - 1) / kRowsPerBlock);
-    const int grid = round_up8(std::min(ntiles, kRowGridCap));
+    const int groups = (ntiles + R - 1) / R;
+    const int grid = round_up8(std::min(groups, kRowGridCap));
     switch (op) {
 #define AMG_ROW_CASE(OPV)                                                                      \
     case OPV:                                                                                  \
@@ -176,10 +242,116 @@ void launch_row_w(RowOp op, const CsrView& a, const double* g, const double* u, 
         AMG_ROW_CASE(kJacobiDot)
         AMG_ROW_CASE(kZeroJacobiResid)
         AMG_ROW_CASE(kSpmvDot)
+        AMG_ROW_CASE(kSpmvScale)
 #undef AMG_ROW_CASE
         default: break;
     }
+    if (op == kResidNorm || op == kJacobiDot || op == kSpmvDot) finish_dot(dot, grid, st);
 }
+
+// CSR-stream variant: a block owns RB consecutive rows; its threads load the
+// block's nonzeros with coalesced loads, multiply by the gathered entries and
+// park the products in LDS; then 256/RB lanes per row add the row's products.
+constexpr int kStreamCap = 2048;   // products staged per pass (16 KB of LDS)
+
+template <int RB, int OP>
+__global__ __launch_bounds__(kBlock) void stream_kernel(CsrView a, const double* __restrict__ g,
+                                                        const double* u, const double* __restrict__ dinv,
+                                                        double omega, double* y, double* y2,
+                                                        DotTarget dot, int nblk) {
+    constexpr int W2 = kBlock / RB;
+    __shared__ double prod[kStreamCap];
+    const int lb = xcd_logical_block();
+    const int lane = threadIdx.x & (W2 - 1);
+    double contrib = 0.0;
+    for (int blk = lb; blk < nblk; blk += gridDim.x) {
+        const int r0 = blk * RB;
+        const int r1 = min(r0 + RB, a.rows);
+        const int p0 = a.rp[r0], p1 = a.rp[r1];
+        const int r = r0 + (int)threadIdx.x / W2;
+        const bool act = r < r1;
+        const int rb = act ? a.rp[r] : 0, re = act ? a.rp[r + 1] : 0;
+        double ui = 0.0, gi = 0.0, di = 0.0;
+        if (act && lane == 0) {
+            if constexpr (OP != kSpmv && OP != kSpmvDot && OP != kSpmvScale) ui = u[r];
+            if constexpr (OP == kJacobi || OP == kJacobiDot || OP == kSpmvDot) gi = g[r];
+            if constexpr (OP == kJacobi || OP == kJacobiDot || OP == kZeroJacobiResid || OP == kSpmvScale)
+                di = dinv[r];
+        }
+        double s = 0.0;
+        for (int c0 = p0; c0 < p1; c0 += kStreamCap) {
+            const int c1 = min(c0 + kStreamCap, p1);
+#pragma unroll
+            for (int k = 0; k < kStreamCap / kBlock; ++k) {
+                const int p = c0 + k * kBlock + (int)threadIdx.x;
+                if (p < c1) {
+                    const int j = a.ci[p];
+                    double gj;
+                    if constexpr (OP == kZeroJacobiResid) gj = omega * (dinv[j] * u[j]);
+                    else gj = g[j];
+                    prod[p - c0] = a.v[p] * gj;
+                }
+            }
+            __syncthreads();
+            const int lo = max(rb, c0), hi = min(re, c1);
+            for (int p = lo + lane; p < hi; p += W2) s += prod[p - c0];
+            __syncthreads();
+        }
+        s = sub_sum<W2>(s);
+        if (act && lane == 0) {
+            if constexpr (OP == kSpmv) {
+                y[r] = s;
+            } else if constexpr (OP == kSpmvAdd) {
+                y[r] = ui + s;
+            } else if constexpr (OP == kResid || OP == kResidNorm) {
+                const double rr = ui - s;
+                y[r] = rr;
+                if constexpr (OP == kResidNorm) contrib += rr * rr;
+            } else if constexpr (OP == kJacobi || OP == kJacobiDot) {
+                const double xn = gi + omega * di * (ui - s);
+                y[r] = xn;
+                if constexpr (OP == kJacobiDot) contrib += ui * xn;
+            } else if constexpr (OP == kZeroJacobiResid) {
+                y2[r] = omega * (di * ui);
+                y[r] = ui - s;
+            } else if constexpr (OP == kSpmvDot) {
+                y[r] = s;
+                contrib += gi * s;
+            } else if constexpr (OP == kSpmvScale) {
+                y[r] = s;
+                y2[r] = omega * (di * s);
+            }
+        }
+    }
+    if constexpr (op_has_dot<OP>()) store_block_partial(contrib, dot.partials, lb);
+}
+
+template <int RB>
+void launch_stream_rb(RowOp op, const CsrView& a, const double* g, const double* u, const double* dinv,
+                      double omega, double* y, double* y2, DotTarget dot, hipStream_t st) {
+    const int nblk = std::max(1, (a.rows + RB - 1) / RB);
+    const int grid = round_up8(std::min(nblk, kRowGridCap));
+    switch (op) {
+#define AMG_STREAM_CASE(OPV)                                                                      \
+    case OPV:                                                                                     \
+        hipLaunchKernelGGL((stream_kernel<RB, OPV>), dim3(grid), dim3(kBlock), 0, st, a, g, u, dinv, \
+                           omega, y, y2, dot, nblk);                                              \
+        break;
+        AMG_STREAM_CASE(kSpmv)
+        AMG_STREAM_CASE(kSpmvAdd)
+        AMG_STREAM_CASE(kResid)
+        AMG_STREAM_CASE(kResidNorm)
+        AMG_STREAM_CASE(kJacobi)
+        AMG_STREAM_CASE(kJacobiDot)
+        AMG_STREAM_CASE(kZeroJacobiResid)
+        AMG_STREAM_CASE(kSpmvDot)
+        AMG_STREAM_CASE(kSpmvScale)
+#undef AMG_STREAM_CASE
+        default: break;
+    }
+    if (op == kResidNorm || op == kJacobiDot || op == kSpmvDot) finish_dot(dot, grid, st);
+}
+
 
 // ---- vector kernels --------------------------------------------------------
 
@@ -192,7 +364,9 @@ __global__ __launch_bounds__(kBlock) void cg_update_xr_kernel(int n, double* __r
                                                               const double* __restrict__ p,
                                                               const double* __restrict__ q,
                                                               const double* scal, int i_num,
-                                                              int i_den, double* flag, DotTarget dot) {
+                                                              int i_den, double* flag, DotTarget dot,
+                                                              const double* __restrict__ dinv,
+                                                              double omega, double* __restrict__ zs) {
     const double num = scal[i_num], den = scal[i_den];
     const bool ok = den > 0.0 && std::isfinite(den);
     double contrib = 0.0;
@@ -202,12 +376,13 @@ __global__ __launch_bounds__(kBlock) void cg_update_xr_kernel(int n, double* __r
             x[i] = x[i] + alpha * p[i];
             const double ri = r[i] - alpha * q[i];
             r[i] = ri;
+            if (zs) zs[i] = omega * (dinv[i] * ri);
             contrib += ri * ri;
         }
     } else if (blockIdx.x == 0 && threadIdx.x == 0) {
         *flag = 1.0;
     }
-    grid_sum_finish(contrib, dot, blockIdx.x, gridDim.x);
+    store_block_partial(contrib, dot.partials, blockIdx.x);
 }
 
 __global__ __launch_bounds__(kBlock) void cg_update_p_kernel(int n, double* __restrict__ p,
@@ -249,7 +424,7 @@ __global__ __launch_bounds__(kBlock) void dot_kernel(int n, const double* __rest
                                                      const double* __restrict__ b, DotTarget dot) {
     double s = 0.0;
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) s += a[i] * b[i];
-    grid_sum_finish(s, dot, blockIdx.x, gridDim.x);
+    store_block_partial(s, dot.partials, blockIdx.x);
 }
 
 __global__ __launch_bounds__(kBlock) void dense_matvec_kernel(int n, const double* __restrict__ ainv,
@@ -264,12 +439,15 @@ __global__ __launch_bounds__(kBlock) void dense_matvec_kernel(int n, const doubl
 }
 
 __global__ __launch_bounds__(kBlock) void inverse_diagonal_kernel(CsrView a, double* __restrict__ dinv) {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= a.rows) return;
+    constexpr int W = 8;
+    const int i = blockIdx.x * (kBlock / W) + threadIdx.x / W;
+    const int lane = threadIdx.x & (W - 1);
     double d = 0.0;
-    for (int p = a.rp[i]; p < a.rp[i + 1]; ++p)
-        if (a.ci[p] == i) d = a.v[p];
-    dinv[i] = 1.0 / d;
+    if (i < a.rows)
+        for (int p = a.rp[i] + lane; p < a.rp[i + 1]; p += W)
+            if (a.ci[p] == i) d = a.v[p];
+    d = sub_sum<W>(d);          // exactly one lane holds the diagonal
+    if (i < a.rows && lane == 0) dinv[i] = 1.0 / d;
 }
 
 // ---- sparsification kernels --------------------------------------------------
@@ -393,6 +571,66 @@ __global__ __launch_bounds__(kBlock) void compact_lump_kernel(CsrView a, const u
     }
 }
 
+// Inverse of the dense coarsest operator (n <= kDenseInvMax) by Gauss-Jordan
+// elimination with partial pivoting in LDS, one block.  *singular = 1 if a
+// pivot is zero.
+constexpr int kDenseInvMax = 64;
+
+__global__ __launch_bounds__(kBlock) void dense_invert_kernel(CsrView a, double* __restrict__ inv,
+                                                              int* singular) {
+    __shared__ double M[kDenseInvMax][kDenseInvMax + 1];
+    __shared__ double V[kDenseInvMax][kDenseInvMax + 1];
+    __shared__ int piv;
+    const int n = a.rows;
+    for (int t = threadIdx.x; t < n * n; t += kBlock) {
+        const int i = t / n, j = t % n;
+        M[i][j] = 0.0;
+        V[i][j] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += kBlock)
+        for (int p = a.rp[i]; p < a.rp[i + 1]; ++p) M[i][a.ci[p]] = a.v[p];
+    __syncthreads();
+    for (int c = 0; c < n; ++c) {
+        if (threadIdx.x == 0) {
+            int best = c;
+            for (int i = c + 1; i < n; ++i)
+                if (fabs(M[i][c]) > fabs(M[best][c])) best = i;
+            piv = best;
+            if (M[best][c] == 0.0) *singular = 1;
+        }
+        __syncthreads();
+        const int pr = piv;
+        if (pr != c)
+            for (int j = threadIdx.x; j < n; j += kBlock) {
+                const double t1 = M[c][j]; M[c][j] = M[pr][j]; M[pr][j] = t1;
+                const double t2 = V[c][j]; V[c][j] = V[pr][j]; V[pr][j] = t2;
+            }
+        __syncthreads();
+        const double d = M[c][c];
+        __syncthreads();
+        for (int j = threadIdx.x; j < n; j += kBlock) {
+            M[c][j] = M[c][j] / d;
+            V[c][j] = V[c][j] / d;
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < n * n; t += kBlock) {
+            const int i = t / n, j = t % n;
+            if (i == c) continue;
+            const double f = M[i][c];
+            if (j != c) {
+                M[i][j] -= f * M[c][j];
+            }
+            V[i][j] -= f * V[c][j];
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += kBlock)
+            if (i != c) M[i][c] = 0.0;
+        __syncthreads();
+    }
+    for (int t = threadIdx.x; t < n * n; t += kBlock) inv[t] = V[t / n][t % n];
+}
+
 // exclusive scan: 1024 items per block in pass 1 and 3
 constexpr int kScanItems = 4;
 constexpr int kScanTile = kBlock * kScanItems;
@@ -469,26 +707,67 @@ __global__ __launch_bounds__(kBlock) void scan_pass3_kernel(int n, const int32_t
     }
 }
 
+// rows per block: the largest power of two whose mean nonzero count fits one pass
+int stream_rows_per_block(double mean) {
+    int rb = 256;
+    while (rb > 16 && rb * mean > 0.85 * kStreamCap) rb /= 2;
+    return rb;
+}
+
+// The LDS-staged kernel wins on the large fine-level operators with short
+// rows (measured on the 128^3 hierarchy: A_0, A_1, P_0, R_0, R_1); with long
+// rows or too few row blocks to fill 256 CUs the subgroup kernel wins.
+bool use_stream_kernel(const CsrView& a) {
+#if AMG_USE_STREAM >= 0
+    return AMG_USE_STREAM != 0;
+#else
+    const int rb = stream_rows_per_block(a.mean_row);
+    return a.mean_row <= 24.0 && (a.rows + rb - 1) / rb >= 1024;
+#endif
+}
+
+void launch_stream_any(RowOp op, const CsrView& a, const double* g, const double* u, const double* dinv,
+                       double omega, double* y, double* y2, DotTarget dot, hipStream_t st) {
+    switch (stream_rows_per_block(a.mean_row)) {
+        case 256: launch_stream_rb<256>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
+        case 128: launch_stream_rb<128>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
+        case 64: launch_stream_rb<64>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
+        case 32: launch_stream_rb<32>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
+        default: launch_stream_rb<16>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
+    }
+}
+
 }  // namespace
 
+// Lanes per row: the power of two nearest (in log scale) to AMG_WIDTH_SCALE
+// times the mean row length, i.e. about two nonzeros per lane.  Measured on
+// the Poisson hierarchies this beats one nonzero per lane (more subgroups
+// and shuffles per byte) and four (fewer independent loads per wavefront).
 int pick_width(double mean) {
-    if (mean <= 4.5) return 4;
-    if (mean <= 9.0) return 8;
-    if (mean <= 20.0) return 16;
-    if (mean <= 48.0) return 32;
-    return 64;
+    const double t = std::max(mean * AMG_WIDTH_SCALE, 1.0);
+    int w = 1 << (int)std::lround(std::log2(t));
+    return std::max(AMG_MIN_WIDTH, std::min(64, w));
 }
+
+int max_row_launch_blocks() { return kRowGridCap; }
 
 int row_launch_blocks(int rows, int width) {
     const int rpb = kBlock / width;
+    const int R = width <= 16 ? AMG_RIF : 1;
     const int ntiles = std::max(1, (rows + rpb - 1) / rpb);
-    return round_up8(std::min(ntiles, kRowGridCap));
+    return round_up8(std::min((ntiles + R - 1) / R, kRowGridCap));
 }
 
 void launch_row_op(RowOp op, int width, const CsrView& a, const double* g, const double* u,
                    const double* dinv, double omega, double* y, double* y2, DotTarget dot,
                    hipStream_t st) {
+    if (use_stream_kernel(a)) {
+        launch_stream_any(op, a, g, u, dinv, omega, y, y2, dot, st);
+        return;
+    }
     switch (width) {
+        case 1: launch_row_w<1>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
+        case 2: launch_row_w<2>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
         case 4: launch_row_w<4>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
         case 8: launch_row_w<8>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
         case 16: launch_row_w<16>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
@@ -499,9 +778,10 @@ void launch_row_op(RowOp op, int width, const CsrView& a, const double* g, const
 
 void launch_cg_update_xr(int n, double* x, double* r, const double* p, const double* q,
                          const double* scal, int i_num, int i_den, double* flag, DotTarget dot,
-                         hipStream_t st) {
+                         const double* dinv, double omega, double* zs, hipStream_t st) {
     hipLaunchKernelGGL(cg_update_xr_kernel, dim3(vec_grid(n)), dim3(kBlock), 0, st, n, x, r, p, q,
-                       scal, i_num, i_den, flag, dot);
+                       scal, i_num, i_den, flag, dot, dinv, omega, zs);
+    finish_dot(dot, vec_grid(n), st);
 }
 
 void launch_cg_update_p(int n, double* p, const double* z, const double* scal, int i_num,
@@ -536,6 +816,7 @@ void launch_fill_f64(int64_t n, double* p, double v, hipStream_t st) {
 
 void launch_dot(int n, const double* a, const double* b, DotTarget dot, hipStream_t st) {
     hipLaunchKernelGGL(dot_kernel, dim3(vec_grid(n)), dim3(kBlock), 0, st, n, a, b, dot);
+    finish_dot(dot, vec_grid(n), st);
 }
 
 int vector_launch_blocks(int n) { return vec_grid(n); }
@@ -546,8 +827,8 @@ void launch_dense_matvec(int n, const double* ainv, const double* b, double* y, 
 }
 
 void launch_inverse_diagonal(const CsrView& a, double* dinv, hipStream_t st) {
-    hipLaunchKernelGGL(inverse_diagonal_kernel, dim3((a.rows + kBlock - 1) / kBlock), dim3(kBlock), 0,
-                       st, a, dinv);
+    hipLaunchKernelGGL(inverse_diagonal_kernel, dim3((a.rows + kBlock / 8 - 1) / (kBlock / 8)), dim3(kBlock),
+                       0, st, a, dinv);
 }
 
 void launch_mark_minimal_pattern(int nc, const int32_t* c_points, const int32_t* afine_rp,
@@ -584,6 +865,12 @@ void launch_compact_lump(int width, const CsrView& a, const uint8_t* keep, const
                          int32_t* new_ci, double* new_v, double* dinv, hipStream_t st) {
     if (a.rows <= 0) return;
     AMG_WIDTH_SWITCH(width, compact_lump_kernel, a, keep, new_rp, new_ci, new_v, dinv);
+}
+
+int dense_invert_max() { return kDenseInvMax; }
+
+void launch_dense_invert(const CsrView& a, double* inv, int* singular, hipStream_t st) {
+    hipLaunchKernelGGL(dense_invert_kernel, dim3(1), dim3(kBlock), 0, st, a, inv, singular);
 }
 
 int64_t scan_scratch_ints(int n) { return (int64_t)(n + kScanTile - 1) / kScanTile + 1; }

@@ -13,6 +13,7 @@ struct CsrView {
     const int32_t* ci;
     const double* v;
     int rows;
+    double mean_row;   // nnz / rows, host side launch configuration only
 };
 
 // Epilogues of the CSR row kernel.  s_i = sum_j a_ij g_j (for kZeroJacobiResid
@@ -26,33 +27,39 @@ enum RowOp : int {
     kJacobiDot = 5,       // kJacobi, dot += u_i y_i
     kZeroJacobiResid = 6, // y2_i = omega dinv_i u_i, y_i = u_i - s_i   (x0 = 0 sweep fused with residual)
     kSpmvDot = 7,         // y_i = s_i, dot += g_i s_i
-    kNumRowOps = 8
+    kSpmvScale = 8,       // y_i = s_i, y2_i = omega dinv_i s_i   (restriction that also forms
+                          //                                        the next level's zero-guess sweep)
+    kNumRowOps = 9
 };
 
-// Deterministic two-level reduction target: per-block partials, a completion
-// counter and the slot that receives the final sum.
+// Deterministic two-level reduction target: per-block partials (summed in
+// block order by a one-block finishing kernel) and the slot that receives
+// the final sum.
 struct DotTarget {
     double* partials;     // >= number of blocks of the launch
-    unsigned* counter;    // zero before the launch; the last block resets it
     double* result;       // receives the sum
 };
 
 // Lanes per row for a matrix with the given mean row length.
 int pick_width(double mean_row_len);
 
-// Number of blocks a row launch with this width uses (for partial buffers).
+// Number of blocks a row launch with this width uses (for partial buffers),
+// and the most any row launch uses.
 int row_launch_blocks(int rows, int width);
+int max_row_launch_blocks();
 
 void launch_row_op(RowOp op, int width, const CsrView& a, const double* g, const double* u,
                    const double* dinv, double omega, double* y, double* y2, DotTarget dot,
                    hipStream_t st);
 
 // ---- vector kernels -----------------------------------------------------
-// x += alpha p; r -= alpha q; dot -> |r|^2, with alpha = scal[i_num]/scal[i_den].
-// If scal[i_den] is not positive and finite, nothing is updated and *flag = 1.0.
+// x += alpha p; r -= alpha q; dot -> |r|^2, with alpha = scal[i_num]/scal[i_den];
+// if zs is not null also zs = omega dinv r (the next V-cycle's zero-guess
+// sweep).  If scal[i_den] is not positive and finite, nothing is updated and
+// *flag = 1.0.
 void launch_cg_update_xr(int n, double* x, double* r, const double* p, const double* q,
                          const double* scal, int i_num, int i_den, double* flag, DotTarget dot,
-                         hipStream_t st);
+                         const double* dinv, double omega, double* zs, hipStream_t st);
 // p = z + beta p with beta = scal[i_num]/scal[i_den]; if restart, p = z.
 void launch_cg_update_p(int n, double* p, const double* z, const double* scal, int i_num,
                         int i_den, hipStream_t st);
@@ -69,6 +76,10 @@ void launch_fill_u8(int64_t n, uint8_t* p, uint8_t v, hipStream_t st);
 void launch_fill_u32(int64_t n, unsigned* p, unsigned v, hipStream_t st);
 // y = Ainv b for a dense row-major n x n inverse
 void launch_dense_matvec(int n, const double* ainv, const double* b, double* y, hipStream_t st);
+// inverse of a dense n x n operator given in CSR (n <= dense_invert_max()),
+// Gauss-Jordan with partial pivoting; *singular set to 1 on a zero pivot
+int dense_invert_max();
+void launch_dense_invert(const CsrView& a, double* inv, int* singular, hipStream_t st);
 // dinv_i = 1 / a_ii
 void launch_inverse_diagonal(const CsrView& a, double* dinv, hipStream_t st);
 
