@@ -43,6 +43,9 @@ struct AmgFailure {
     } while (0)
 
 constexpr int kMaxDenseCoarse = 4096;
+// CSR index and value arrays carry this many spare entries so that kernels
+// may read whole 16-byte packs at the end of a matrix
+constexpr int kCsrPad = 4;
 
 // device scalar slots
 enum : int { S_RZ0 = 0, S_RZ1 = 1, S_PQ = 2, S_NR2 = 3, S_FLAG = 4, S_NRT = 5, S_DOT = 6, S_COUNT = 8 };
@@ -182,8 +185,8 @@ DevMat upload_mat(amg_ctx* h, const HostCsr& m) {
     d.cols = m.cols;
     d.nnz = m.nnz();
     d.rp = dalloc_n<int32_t>(h, d.rows + 1);
-    d.ci = dalloc_n<int32_t>(h, d.nnz);
-    d.v = dalloc_n<double>(h, d.nnz);
+    d.ci = dalloc_n<int32_t>(h, d.nnz + kCsrPad);
+    d.v = dalloc_n<double>(h, d.nnz + kCsrPad);
     upload(h, d.rp, m.ptr.data(), d.rows + 1);
     upload(h, d.ci, m.idx.data(), d.nnz);
     upload(h, d.v, m.val.data(), d.nnz);
@@ -412,8 +415,8 @@ void sparsify_levels(amg_ctx* h, const std::vector<std::pair<int, double>>& todo
         if (!c.Ahs.rp) {
             c.Ahs.rows = c.Ahs.cols = c.n;
             c.Ahs.rp = dalloc_n<int32_t>(h, c.n + 1);
-            c.Ahs.ci = dalloc_n<int32_t>(h, c.A.nnz);
-            c.Ahs.v = dalloc_n<double>(h, c.A.nnz);
+            c.Ahs.ci = dalloc_n<int32_t>(h, c.A.nnz + kCsrPad);
+            c.Ahs.v = dalloc_n<double>(h, c.A.nnz + kCsrPad);
             c.Ahs.shape_nnz = c.A.nnz;
             c.Ahs.width = c.A.width;
         }
