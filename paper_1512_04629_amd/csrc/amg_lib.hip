@@ -473,6 +473,21 @@ void jacobi_sweeps(amg_ctx* h, int l, const DevMat& m, const double* dinv, const
 
 enum class Guess { kNonzero, kZero, kPrescaled };
 
+// First level handled by the single-workgroup coarse tail: the finest level
+// >= 1 with at most kTailRows rows, if it is above the coarsest; 0 = no tail.
+// The tail implements V(1,1) only.
+#ifndef AMG_TAIL_ROWS
+#define AMG_TAIL_ROWS 256
+#endif
+constexpr int kTailRows = AMG_TAIL_ROWS;
+int tail_start(const amg_ctx* h) {
+    const int L = (int)h->lv.size() - 1;
+    if (h->sp.nu_pre != 1 || h->sp.nu_post != 1 || L < 2) return 0;
+    for (int l = 1; l < L; ++l)
+        if (h->lv[l].n <= kTailRows) return (L - l + 1 <= kTailMaxLevels) ? l : 0;
+    return 0;
+}
+
 // Buffer that receives the zero-guess smoothing sweep omega D^-1 b of level
 // l: on level 0 chosen so that after all later sweeps (each swaps buffers)
 // the result lands in x0.
@@ -496,7 +511,9 @@ void vcycle(amg_ctx* h, const double* b0, double* x0, Guess guess0, int dot_slot
         return;
     }
     std::vector<double*> cur(L + 1), alt(L + 1);
-    for (int l = 0; l < L; ++l) {
+    const int tail = tail_start(h);
+    const int down_end = tail > 0 ? tail : L;
+    for (int l = 0; l < down_end; ++l) {
         DevLevel& v = h->lv[l];
         const double* b = l == 0 ? b0 : v.b;
         const bool zero = l > 0 || guess0 != Guess::kNonzero;
@@ -531,14 +548,38 @@ void vcycle(amg_ctx* h, const double* b0, double* x0, Guess guess0, int dot_slot
         else
             row_op(h, AMG_K_RESTRICT, l, kSpmv, v.R, v.r, nullptr, nullptr, nx.b, nullptr, -1);
     }
-    {
+    if (tail > 0) {
+        // levels tail..L in one workgroup; the level-tail result lands in its xt
+        TailArgs ta{};
+        ta.count = L - tail + 1;
+        ta.coarse_inv = h->coarse_inv;
+        ta.omega = h->sp.omega;
+        for (int k = 0; k < ta.count; ++k) {
+            DevLevel& v = h->lv[tail + k];
+            TailLevel& t = ta.lv[k];
+            t.A = v.Ah.view();
+            if (tail + k < L) {
+                t.R = v.R.view();
+                t.P = v.P.view();
+            }
+            t.dinv = v.dinv;
+            t.b = v.b;
+            t.x = v.x;
+            t.xt = v.xt;
+            t.r = v.r;
+        }
+        ProfScope ps(h, AMG_K_COARSE, tail);
+        launch_coarse_tail(ta, h->stream);
+        check_launch();
+        cur[tail] = h->lv[tail].xt;
+    } else {
         DevLevel& c = h->lv[L];
         ProfScope ps(h, AMG_K_COARSE, L);
         launch_dense_matvec(h->nL, h->coarse_inv, c.b, c.x, h->stream);
         check_launch();
         cur[L] = c.x;
     }
-    for (int l = L - 1; l >= 0; --l) {
+    for (int l = down_end - 1; l >= 0; --l) {
         DevLevel& v = h->lv[l];
         const double* b = l == 0 ? b0 : v.b;
         row_op(h, AMG_K_INTERP, l, kSpmvAdd, v.P, cur[l + 1], cur[l], nullptr, cur[l], nullptr, -1);

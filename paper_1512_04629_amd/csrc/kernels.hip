@@ -699,6 +699,69 @@ __global__ __launch_bounds__(kBlock) void dense_invert_kernel(CsrView a, double*
     for (int t = threadIdx.x; t < n * n; t += kBlock) inv[t] = V[t / n][t % n];
 }
 
+// Single-workgroup tail of the V-cycle (see kernels.hpp).  Rows are handled
+// by 8-lane subgroups; every step ends with a workgroup barrier, which also
+// makes the step's global writes visible to the next step.
+constexpr int kTailBlock = 1024;
+constexpr int kTailW = 8;
+
+template <int OPT>
+__device__ __forceinline__ void tail_rows(const CsrView& a, const double* __restrict__ g,
+                                          const double* u, const double* __restrict__ dinv,
+                                          double omega, double* y, double* y2) {
+    // OPT 0: y = u - A g        (residual)
+    // OPT 1: y = A g, y2 = omega dinv y   (restriction writing the prescaled sweep)
+    // OPT 2: y = A g            (restriction onto the coarsest level)
+    // OPT 3: y = u + A g        (interpolation and correction, in place)
+    // OPT 4: y = g + omega dinv (u - A g)   (post-smoothing sweep)
+    const int lane = threadIdx.x & (kTailW - 1);
+    for (int row0 = threadIdx.x / kTailW; row0 < a.rows; row0 += kTailBlock / kTailW) {
+        const int row = row0;
+        double s = 0.0;
+        for (int p = a.rp[row] + lane; p < a.rp[row + 1]; p += kTailW) s += a.v[p] * g[a.ci[p]];
+        s = sub_sum<kTailW>(s);
+        if (lane == 0) {
+            if constexpr (OPT == 0) y[row] = u[row] - s;
+            else if constexpr (OPT == 1) { y[row] = s; y2[row] = omega * (dinv[row] * s); }
+            else if constexpr (OPT == 2) y[row] = s;
+            else if constexpr (OPT == 3) y[row] = u[row] + s;
+            else y[row] = g[row] + omega * dinv[row] * (u[row] - s);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kTailBlock) void coarse_tail_kernel(TailArgs t) {
+    const int last = t.count - 1;
+    for (int k = 0; k < last; ++k) {
+        const TailLevel& L = t.lv[k];
+        tail_rows<0>(L.A, L.x, L.b, nullptr, t.omega, L.r, nullptr);
+        __syncthreads();
+        const TailLevel& N = t.lv[k + 1];
+        if (k + 1 < last) tail_rows<1>(L.R, L.r, nullptr, N.dinv, t.omega, N.b, N.x);
+        else tail_rows<2>(L.R, L.r, nullptr, nullptr, t.omega, N.b, nullptr);
+        __syncthreads();
+    }
+    {
+        const TailLevel& C = t.lv[last];
+        const int n = C.A.rows;
+        for (int i = threadIdx.x; i < n; i += kTailBlock) {
+            double s = 0.0;
+            const double* row = t.coarse_inv + (size_t)i * n;
+            for (int j = 0; j < n; ++j) s += row[j] * C.b[j];
+            C.x[i] = s;
+        }
+        __syncthreads();
+    }
+    for (int k = last - 1; k >= 0; --k) {
+        const TailLevel& L = t.lv[k];
+        const double* xc = (k + 1 == last) ? t.lv[k + 1].x : t.lv[k + 1].xt;
+        tail_rows<3>(L.P, xc, L.x, nullptr, t.omega, L.x, nullptr);
+        __syncthreads();
+        tail_rows<4>(L.A, L.x, L.b, L.dinv, t.omega, L.xt, nullptr);
+        __syncthreads();
+    }
+}
+
 // exclusive scan: 1024 items per block in pass 1 and 3
 constexpr int kScanItems = 4;
 constexpr int kScanTile = kBlock * kScanItems;
@@ -951,6 +1014,10 @@ void launch_compact_lump(int width, const CsrView& a, const uint8_t* keep, const
 }
 
 int dense_invert_max() { return kDenseInvMax; }
+
+void launch_coarse_tail(const TailArgs& t, hipStream_t st) {
+    hipLaunchKernelGGL(coarse_tail_kernel, dim3(1), dim3(kTailBlock), 0, st, t);
+}
 
 void launch_dense_invert(const CsrView& a, double* inv, int* singular, hipStream_t st) {
     hipLaunchKernelGGL(dense_invert_kernel, dim3(1), dim3(kBlock), 0, st, a, inv, singular);

@@ -83,6 +83,28 @@ void launch_dense_invert(const CsrView& a, double* inv, int* singular, hipStream
 // dinv_i = 1 / a_ii
 void launch_inverse_diagonal(const CsrView& a, double* dinv, hipStream_t st);
 
+// ---- coarse tail: the V-cycle below a level in one workgroup ---------------
+// Levels t..L of a V(1,1) cycle with zero initial guesses: down (residual of
+// the prescaled sweep, restriction writing the next level's prescaled sweep),
+// coarsest dense solve, up (interpolation + post-smoothing).  Level k of the
+// tail is lv[k]; lv[count-1] is the coarsest.  On entry lv[0].b holds the
+// right-hand side and lv[0].x the first sweep omega D^-1 b; on exit the
+// level-t result is in lv[0].xt.
+constexpr int kTailMaxLevels = 12;
+struct TailLevel {
+    CsrView A;           // sparsified operator of the level
+    CsrView R, P;        // restriction to / interpolation from the next level
+    const double* dinv;
+    double *b, *x, *xt, *r;
+};
+struct TailArgs {
+    TailLevel lv[kTailMaxLevels];
+    int count;
+    const double* coarse_inv;
+    double omega;
+};
+void launch_coarse_tail(const TailArgs& t, hipStream_t st);
+
 // ---- sparsification kernels ----------------------------------------------
 // Marks M_l: for coarse row I with fine point f = c_points[I], every column J
 // of P rows l' in row f of A_{l-1} gives (I,J) and (J,I) in A_l.
