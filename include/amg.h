@@ -79,6 +79,12 @@ typedef struct {
     int32_t s;           /* levels updated per reintroduction, default 1 */
     double rho_max;      /* reintroduce when the window factor exceeds this, default 0.5 */
     double gamma_min;    /* new gamma below this becomes 0, default 0.01 */
+    int32_t precision;   /* 64 (default): the V-cycle in FP64.  32: the V-cycle in FP32
+                            (operator values, vectors and accumulation; the coarsest
+                            inverse stays FP64) as the preconditioner of FP64 CG, or as
+                            the correction of FP64 iterative refinement for
+                            AMG_STATIONARY; residuals, dot products and the stop test
+                            stay FP64 */
 } amg_solve_params;
 
 typedef struct {
@@ -140,6 +146,12 @@ amg_status amg_solve(amg_handle h, const double* b, double* x, const amg_solve_p
 
 /* One V-cycle (Section 2, amg_solve) in place: x <- V(b, x); device arrays. */
 amg_status amg_vcycle(amg_handle h, const double* b, double* x);
+
+/* The same cycle in FP32 (values, vectors, accumulation; FP64 coarsest
+   inverse): x <- V32(b, x), device float arrays.  The first call builds the
+   FP32 copies of the hierarchy's values; later sparsify/reintroduce calls
+   keep them current. */
+amg_status amg_vcycle32(amg_handle h, const float* b, float* x);
 
 /* Single steps of the V-cycle on level l, device arrays (for component
    checks and for callers composing their own cycles):

@@ -35,7 +35,7 @@ KERNEL = {"JACOBI": 0, "JACOBI_ZERO": 1, "RESIDUAL": 2, "RESTRICT": 3, "INTERP":
 # every symbol include/amg.h declares
 ABI_SYMBOLS = (
     "amg_setup_params_default", "amg_solve_params_default", "amg_setup_from_csr",
-    "amg_sparsify", "amg_sparsify_levels", "amg_reintroduce", "amg_solve", "amg_vcycle",
+    "amg_sparsify", "amg_sparsify_levels", "amg_reintroduce", "amg_solve", "amg_vcycle", "amg_vcycle32",
     "amg_level_op", "amg_num_levels", "amg_get_level", "amg_export_level", "amg_export_mask",
     "amg_export_vector", "amg_export_split", "amg_profile_enable", "amg_profile_read",
     "amg_destroy", "amg_status_string", "amg_last_error",
@@ -56,7 +56,7 @@ class SetupParams(C.Structure):
 class SolveParams(C.Structure):
     _fields_ = [("method", C.c_int32), ("rtol", C.c_double), ("maxit", C.c_int32),
                 ("adaptive", C.c_int32), ("k", C.c_int32), ("s", C.c_int32),
-                ("rho_max", C.c_double), ("gamma_min", C.c_double)]
+                ("rho_max", C.c_double), ("gamma_min", C.c_double), ("precision", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -88,6 +88,7 @@ def load_library():
     lib.amg_reintroduce.argtypes = [vp, i32, f64, P(i32)]
     lib.amg_solve.argtypes = [vp, vp, vp, P(SolveParams), P(SolveInfo), vp]
     lib.amg_vcycle.argtypes = [vp, vp, vp]
+    lib.amg_vcycle32.argtypes = [vp, vp, vp]
     lib.amg_level_op.argtypes = [vp, i32, i32, vp, vp, vp]
     lib.amg_num_levels.argtypes = [vp, P(i32)]
     lib.amg_get_level.argtypes = [vp, i32, P(i64), P(i64), P(i64), P(i64), P(i64), P(f64), P(i64)]
@@ -104,7 +105,7 @@ def load_library():
     lib.amg_last_error.argtypes = [vp]
     lib.amg_last_error.restype = C.c_char_p
     for name in ("amg_setup_from_csr", "amg_sparsify", "amg_sparsify_levels", "amg_reintroduce",
-                 "amg_solve", "amg_vcycle", "amg_level_op", "amg_num_levels", "amg_get_level",
+                 "amg_solve", "amg_vcycle", "amg_vcycle32", "amg_level_op", "amg_num_levels", "amg_get_level",
                  "amg_export_level", "amg_export_mask", "amg_export_vector", "amg_export_split",
                  "amg_profile_enable", "amg_profile_read"):
         getattr(lib, name).restype = C.c_int
@@ -248,9 +249,10 @@ class Hierarchy:
 
     # -- solve -------------------------------------------------------------
     def solve(self, b, x, method=PCG, tol=1e-8, maxit=200, adaptive=False, k=3, s=1,
-              rho_max=0.5, gamma_min=0.01, raise_on_error=False) -> SolveResult:
+              rho_max=0.5, gamma_min=0.01, precision=64, raise_on_error=False) -> SolveResult:
+        """precision=32 runs the V-cycle in FP32 inside the FP64 iteration."""
         p = SolveParams(int(method), float(tol), int(maxit), int(bool(adaptive)), int(k), int(s),
-                        float(rho_max), float(gamma_min))
+                        float(rho_max), float(gamma_min), int(precision))
         info = SolveInfo()
         hist = np.full(maxit + 1, np.nan)
         st = self._lib.amg_solve(self._h, _dptr(b, self.n, "b"), _dptr(x, self.n, "x"), C.byref(p),
@@ -262,6 +264,15 @@ class Hierarchy:
 
     def vcycle(self, b, x):
         self._check(self._lib.amg_vcycle(self._h, _dptr(b, self.n, "b"), _dptr(x, self.n, "x")))
+
+    def vcycle32(self, b, x):
+        """One FP32 V-cycle x <- V32(b, x) on float32 CUDA tensors."""
+        torch = _torch()
+        for t, name in ((b, "b"), (x, "x")):
+            if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32
+                    and t.is_contiguous() and t.numel() == self.n):
+                raise TypeError(f"{name} must be a contiguous float32 CUDA tensor of {self.n} entries")
+        self._check(self._lib.amg_vcycle32(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr())))
 
     def level_op(self, level: int, op: str, inp=None, x=None, out=None):
         args = [C.c_void_p(t.data_ptr()) if t is not None else None for t in (inp, x, out)]

@@ -80,6 +80,14 @@ struct DevLevel {
     double gamma = 0.0;
     double *b = nullptr, *x = nullptr, *xt = nullptr, *r = nullptr;
     std::vector<int32_t> split;
+    // FP32 mirror for the single-precision V-cycle (indices shared with the
+    // FP64 operators; allocated on the first FP32 solve)
+    float* A32 = nullptr;
+    float* Ahs32 = nullptr;
+    float* P32 = nullptr;
+    float* R32 = nullptr;
+    float* dinv32 = nullptr;
+    float *b32 = nullptr, *x32 = nullptr, *xt32 = nullptr, *r32 = nullptr;
 };
 
 struct ProfAcc {
@@ -114,6 +122,8 @@ struct amg_ctx {
     int* missing = nullptr;
     double *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_q = nullptr;
     double *xw = nullptr, *rt = nullptr;
+    bool fp32 = false;
+    float *cg_r32 = nullptr, *cg_z32 = nullptr;
     std::string last_error;
     bool check_singular = false;   // a device inversion wrote h->missing
     bool profiling = false;
@@ -270,6 +280,14 @@ void row_op(amg_ctx* h, int kind, int level, RowOp op, const DevMat& m, const do
     check_launch();
 }
 
+void row_op(amg_ctx* h, int kind, int level, RowOp op, const DevMat& m, const float* vals, const float* g,
+            const float* u, const float* dinv, float* y, float* y2) {
+    ProfScope ps(h, kind, level);
+    const CsrView32 a32{m.rp, m.ci, vals, m.rows, m.view().mean_row};
+    launch_row_op(op, m.width, a32, g, u, dinv, (float)h->sp.omega, y, y2, h->stream);
+    check_launch();
+}
+
 // ---------------------------------------------------------------------------
 // coarse-level dense inverse (host factorization, applied by a device kernel)
 // ---------------------------------------------------------------------------
@@ -420,6 +438,7 @@ void sparsify_levels(amg_ctx* h, const std::vector<std::pair<int, double>>& todo
             c.Ahs.shape_nnz = c.A.nnz;
             c.Ahs.width = c.A.width;
         }
+        if (h->fp32 && !c.Ahs32) c.Ahs32 = dalloc_n<float>(h, c.A.nnz + kCsrPad);
     }
     bool coarse_changed = false;
     for (auto& t : todo) {
@@ -431,7 +450,7 @@ void sparsify_levels(amg_ctx* h, const std::vector<std::pair<int, double>>& todo
             if (!c.ah_alias) {
                 c.Ah = c.A;
                 c.ah_alias = true;
-                launch_inverse_diagonal(c.A.view(), c.dinv, h->stream);
+                launch_inverse_diagonal(c.A.view(), c.dinv, h->fp32 ? c.dinv32 : nullptr, h->stream);
                 if (l == (int)h->lv.size() - 1) coarse_changed = true;
             }
             c.gamma = 0.0;
@@ -439,7 +458,8 @@ void sparsify_levels(amg_ctx* h, const std::vector<std::pair<int, double>>& todo
         } else {
             launch_keep_count(c.A.width, c.A.view(), c.in_m, c.rowmax, gamma, c.keep, h->cnt, h->stream);
             launch_exclusive_scan(c.n, h->cnt, c.Ahs.rp, h->scan_scratch, h->stream);
-            launch_compact_lump(c.A.width, c.A.view(), c.keep, c.Ahs.rp, c.Ahs.ci, c.Ahs.v, c.dinv, h->stream);
+            launch_compact_lump(c.A.width, c.A.view(), c.keep, c.Ahs.rp, c.Ahs.ci, c.Ahs.v, c.dinv,
+                                h->fp32 ? c.Ahs32 : nullptr, h->fp32 ? c.dinv32 : nullptr, h->stream);
             c.Ahs.nnz_known = false;
             c.Ah = c.Ahs;
             c.ah_alias = false;
@@ -455,18 +475,66 @@ void sparsify_levels(amg_ctx* h, const std::vector<std::pair<int, double>>& todo
 // ---------------------------------------------------------------------------
 // V-cycle (Section 2, amg_solve): weighted Jacobi pre/post smoothing,
 // restriction of the residual with R = P^T, coarsest dense solve,
-// interpolation and correction.  zero0: the level-0 iterate is zero on
-// entry.  dot_slot >= 0: accumulate b0 . x0 (the CG inner product r.z) into
-// that scalar slot.  The result is left in x0.
+// interpolation and correction.  Written once for both precisions: FP64
+// (the method as stated) and FP32 (values, vectors and accumulation in single
+// precision, used as a preconditioner of FP64 iterations; the coarsest solve
+// keeps its FP64 inverse).
 // ---------------------------------------------------------------------------
-void jacobi_sweeps(amg_ctx* h, int l, const DevMat& m, const double* dinv, const double* b,
-                   double*& cur, double*& alt, int sweeps, int dot_slot_last) {
+
+// the per-level arrays of one precision
+template <class T>
+struct LevelView {
+    int n = 0;
+    const DevMat* Ah = nullptr;
+    const DevMat* P = nullptr;
+    const DevMat* R = nullptr;
+    const T *ahv = nullptr, *pv = nullptr, *rv = nullptr, *dinv = nullptr;
+    T *b = nullptr, *x = nullptr, *xt = nullptr, *r = nullptr;
+};
+
+LevelView<double> level_view(amg_ctx* h, int l, double*) {
+    DevLevel& v = h->lv[l];
+    LevelView<double> o;
+    o.n = v.n;
+    o.Ah = &v.Ah; o.P = &v.P; o.R = &v.R;
+    o.ahv = v.Ah.v; o.pv = v.P.v; o.rv = v.R.v; o.dinv = v.dinv;
+    o.b = v.b; o.x = v.x; o.xt = v.xt; o.r = v.r;
+    return o;
+}
+
+LevelView<float> level_view(amg_ctx* h, int l, float*) {
+    DevLevel& v = h->lv[l];
+    LevelView<float> o;
+    o.n = v.n;
+    o.Ah = &v.Ah; o.P = &v.P; o.R = &v.R;
+    o.ahv = v.ah_alias ? v.A32 : v.Ahs32;
+    o.pv = v.P32; o.rv = v.R32; o.dinv = v.dinv32;
+    o.b = v.b32; o.x = v.x32; o.xt = v.xt32; o.r = v.r32;
+    return o;
+}
+
+void row_op_t(amg_ctx* h, int kind, int l, RowOp op, const DevMat& m, const double*, const double* g,
+              const double* u, const double* dinv, double* y, double* y2, int dot_slot) {
+    row_op(h, kind, l, op, m, g, u, dinv, y, y2, dot_slot);
+}
+
+void row_op_t(amg_ctx* h, int kind, int l, RowOp op, const DevMat& m, const float* vals, const float* g,
+              const float* u, const float* dinv, float* y, float* y2, int) {
+    row_op(h, kind, l, op, m, vals, g, u, dinv, y, y2);
+}
+
+void fill_t(int64_t n, double* p, amg_ctx* h) { launch_fill_f64(n, p, 0.0, h->stream); }
+void fill_t(int64_t n, float* p, amg_ctx* h) { launch_fill_f32(n, p, 0.0f, h->stream); }
+
+template <class T>
+void jacobi_sweeps(amg_ctx* h, int l, const LevelView<T>& v, const T* b, T*& cur, T*& alt, int sweeps,
+                   int dot_slot_last) {
     for (int s = 0; s < sweeps; ++s) {
         const bool last = s == sweeps - 1;
         if (last && dot_slot_last >= 0)
-            row_op(h, AMG_K_JACOBI, l, kJacobiDot, m, cur, b, dinv, alt, nullptr, dot_slot_last);
+            row_op_t(h, AMG_K_JACOBI, l, kJacobiDot, *v.Ah, v.ahv, cur, b, v.dinv, alt, nullptr, dot_slot_last);
         else
-            row_op(h, AMG_K_JACOBI, l, kJacobi, m, cur, b, dinv, alt, nullptr, -1);
+            row_op_t(h, AMG_K_JACOBI, l, kJacobi, *v.Ah, v.ahv, cur, b, v.dinv, alt, nullptr, -1);
         std::swap(cur, alt);
     }
 }
@@ -491,76 +559,84 @@ int tail_start(const amg_ctx* h) {
 // Buffer that receives the zero-guess smoothing sweep omega D^-1 b of level
 // l: on level 0 chosen so that after all later sweeps (each swaps buffers)
 // the result lands in x0.
-double* zero_start(amg_ctx* h, int l, double* x0) {
-    if (l > 0) return h->lv[l].x;
+template <class T>
+T* zero_start(amg_ctx* h, int l, T* x0) {
+    LevelView<T> v = level_view(h, l, (T*)nullptr);
+    if (l > 0) return v.x;
     const int swaps = std::max(h->sp.nu_pre - 1, 0) + h->sp.nu_post;
-    return (swaps & 1) ? h->lv[0].xt : x0;
+    return (swaps & 1) ? v.xt : x0;
 }
 
 // guess0: kNonzero -- x0 holds the iterate; kZero -- the iterate is zero;
 // kPrescaled -- the iterate is zero and zero_start(h, 0, x0) already holds
-// the first sweep omega D^-1 b0 (written by the CG update).
-void vcycle(amg_ctx* h, const double* b0, double* x0, Guess guess0, int dot_slot) {
+// the first sweep omega D^-1 b0 (written by the CG update).  dot_slot >= 0
+// (FP64 only): accumulate b0 . x0 (the CG inner product r.z) into that slot.
+// The result is left in x0.
+template <class T>
+void vcycle(amg_ctx* h, const T* b0, T* x0, Guess guess0, int dot_slot) {
     const int L = (int)h->lv.size() - 1;
     const int pre = h->sp.nu_pre, post = h->sp.nu_post;
+    const T omega = (T)h->sp.omega;
     if (L == 0) {
         ProfScope ps(h, AMG_K_COARSE, 0);
         launch_dense_matvec(h->nL, h->coarse_inv, b0, x0, h->stream);
         check_launch();
-        if (dot_slot >= 0) launch_dot(h->lv[0].n, b0, x0, dot_to(h, dot_slot), h->stream);
+        if constexpr (sizeof(T) == 8)
+            if (dot_slot >= 0) launch_dot(h->lv[0].n, b0, x0, dot_to(h, dot_slot), h->stream);
         return;
     }
-    std::vector<double*> cur(L + 1), alt(L + 1);
+    std::vector<T*> cur(L + 1), alt(L + 1);
     const int tail = tail_start(h);
     const int down_end = tail > 0 ? tail : L;
     for (int l = 0; l < down_end; ++l) {
-        DevLevel& v = h->lv[l];
-        const double* b = l == 0 ? b0 : v.b;
+        LevelView<T> v = level_view(h, l, (T*)nullptr);
+        const T* b = l == 0 ? b0 : v.b;
         const bool zero = l > 0 || guess0 != Guess::kNonzero;
         // on coarse levels the restriction has already written omega D^-1 b
         const bool prescaled = pre >= 1 && (l > 0 || guess0 == Guess::kPrescaled);
-        cur[l] = zero ? zero_start(h, l, x0) : x0;
+        cur[l] = zero ? zero_start<T>(h, l, x0) : x0;
         alt[l] = cur[l] == v.xt ? (l == 0 ? x0 : v.x) : v.xt;
         bool have_resid = false;
         if (zero) {
             if (pre == 0) {
-                launch_fill_f64(v.n, cur[l], 0.0, h->stream);
+                fill_t(v.n, cur[l], h);
                 launch_copy(v.n, v.r, b, h->stream);
                 have_resid = true;
             } else if (pre == 1 && !prescaled) {
-                row_op(h, AMG_K_JACOBI_ZERO, l, kZeroJacobiResid, v.Ah, nullptr, b, v.dinv, v.r, cur[l], -1);
+                row_op_t(h, AMG_K_JACOBI_ZERO, l, kZeroJacobiResid, *v.Ah, v.ahv, nullptr, b, v.dinv, v.r,
+                         cur[l], -1);
                 have_resid = true;
             } else {
-                if (!prescaled) launch_scaled_copy(v.n, cur[l], v.dinv, b, h->sp.omega, h->stream);
-                jacobi_sweeps(h, l, v.Ah, v.dinv, b, cur[l], alt[l], pre - 1, -1);
+                if (!prescaled) launch_scaled_copy(v.n, cur[l], v.dinv, b, omega, h->stream);
+                jacobi_sweeps<T>(h, l, v, b, cur[l], alt[l], pre - 1, -1);
             }
         } else {
-            jacobi_sweeps(h, l, v.Ah, v.dinv, b, cur[l], alt[l], pre, -1);
+            jacobi_sweeps<T>(h, l, v, b, cur[l], alt[l], pre, -1);
         }
         if (!have_resid) {
             const int kind = (zero && pre == 1) ? AMG_K_JACOBI_ZERO : AMG_K_RESIDUAL;
-            row_op(h, kind, l, kResid, v.Ah, cur[l], b, nullptr, v.r, nullptr, -1);
+            row_op_t(h, kind, l, kResid, *v.Ah, v.ahv, cur[l], b, nullptr, v.r, nullptr, -1);
         }
-        DevLevel& nx = h->lv[l + 1];
+        LevelView<T> nx = level_view(h, l + 1, (T*)nullptr);
         if (pre >= 1 && l + 1 < L)
-            row_op(h, AMG_K_RESTRICT, l, kSpmvScale, v.R, v.r, nullptr, nx.dinv, nx.b,
-                   zero_start(h, l + 1, nullptr), -1);
+            row_op_t(h, AMG_K_RESTRICT, l, kSpmvScale, *v.R, v.rv, v.r, nullptr, nx.dinv, nx.b,
+                     zero_start<T>(h, l + 1, nullptr), -1);
         else
-            row_op(h, AMG_K_RESTRICT, l, kSpmv, v.R, v.r, nullptr, nullptr, nx.b, nullptr, -1);
+            row_op_t(h, AMG_K_RESTRICT, l, kSpmv, *v.R, v.rv, v.r, nullptr, nullptr, nx.b, nullptr, -1);
     }
     if (tail > 0) {
         // levels tail..L in one workgroup; the level-tail result lands in its xt
-        TailArgs ta{};
+        TailArgs<T> ta{};
         ta.count = L - tail + 1;
         ta.coarse_inv = h->coarse_inv;
-        ta.omega = h->sp.omega;
+        ta.omega = omega;
         for (int k = 0; k < ta.count; ++k) {
-            DevLevel& v = h->lv[tail + k];
-            TailLevel& t = ta.lv[k];
-            t.A = v.Ah.view();
+            LevelView<T> v = level_view(h, tail + k, (T*)nullptr);
+            TailLevel<T>& t = ta.lv[k];
+            t.A = CsrT<T>{v.Ah->rp, v.Ah->ci, v.ahv, v.Ah->rows, 0.0};
             if (tail + k < L) {
-                t.R = v.R.view();
-                t.P = v.P.view();
+                t.R = CsrT<T>{v.R->rp, v.R->ci, v.rv, v.R->rows, 0.0};
+                t.P = CsrT<T>{v.P->rp, v.P->ci, v.pv, v.P->rows, 0.0};
             }
             t.dinv = v.dinv;
             t.b = v.b;
@@ -571,25 +647,62 @@ void vcycle(amg_ctx* h, const double* b0, double* x0, Guess guess0, int dot_slot
         ProfScope ps(h, AMG_K_COARSE, tail);
         launch_coarse_tail(ta, h->stream);
         check_launch();
-        cur[tail] = h->lv[tail].xt;
+        cur[tail] = level_view(h, tail, (T*)nullptr).xt;
     } else {
-        DevLevel& c = h->lv[L];
+        LevelView<T> c = level_view(h, L, (T*)nullptr);
         ProfScope ps(h, AMG_K_COARSE, L);
         launch_dense_matvec(h->nL, h->coarse_inv, c.b, c.x, h->stream);
         check_launch();
         cur[L] = c.x;
     }
     for (int l = down_end - 1; l >= 0; --l) {
-        DevLevel& v = h->lv[l];
-        const double* b = l == 0 ? b0 : v.b;
-        row_op(h, AMG_K_INTERP, l, kSpmvAdd, v.P, cur[l + 1], cur[l], nullptr, cur[l], nullptr, -1);
+        LevelView<T> v = level_view(h, l, (T*)nullptr);
+        const T* b = l == 0 ? b0 : v.b;
+        row_op_t(h, AMG_K_INTERP, l, kSpmvAdd, *v.P, v.pv, cur[l + 1], cur[l], nullptr, cur[l], nullptr, -1);
         const int dslot = (l == 0) ? dot_slot : -1;
-        jacobi_sweeps(h, l, v.Ah, v.dinv, b, cur[l], alt[l], post, dslot);
+        jacobi_sweeps<T>(h, l, v, b, cur[l], alt[l], post, dslot);
         if (l == 0) {
             if (cur[0] != x0) launch_copy(v.n, x0, cur[0], h->stream);
-            if (post == 0 && dot_slot >= 0) launch_dot(v.n, b0, x0, dot_to(h, dot_slot), h->stream);
+            if constexpr (sizeof(T) == 8)
+                if (post == 0 && dot_slot >= 0) launch_dot(v.n, b0, x0, dot_to(h, dot_slot), h->stream);
         }
     }
+}
+
+// FP32 copies of every operator's values, of dinv, and FP32 work vectors
+void ensure_fp32(amg_ctx* h) {
+    if (h->fp32) return;
+    const int L = (int)h->lv.size() - 1;
+    for (int l = 0; l <= L; ++l) {
+        DevLevel& v = h->lv[l];
+        v.A32 = dalloc_n<float>(h, v.A.nnz + kCsrPad);
+        v.dinv32 = dalloc_n<float>(h, v.n);
+        if (v.Ahs.rp) v.Ahs32 = dalloc_n<float>(h, v.A.nnz + kCsrPad);
+        if (l < L) {
+            v.P32 = dalloc_n<float>(h, v.P.nnz + kCsrPad);
+            v.R32 = dalloc_n<float>(h, v.R.nnz + kCsrPad);
+        }
+        if (l > 0) {
+            v.b32 = dalloc_n<float>(h, v.n);
+            v.x32 = dalloc_n<float>(h, v.n);
+        }
+        v.xt32 = dalloc_n<float>(h, v.n);
+        v.r32 = dalloc_n<float>(h, v.n);
+    }
+    h->cg_r32 = dalloc_n<float>(h, h->lv[0].n);
+    h->cg_z32 = dalloc_n<float>(h, h->lv[0].n);
+    for (int l = 0; l <= L; ++l) {
+        DevLevel& v = h->lv[l];
+        launch_narrow(v.A.nnz, v.A32, v.A.v, h->stream);
+        launch_narrow(v.n, v.dinv32, v.dinv, h->stream);
+        if (v.Ahs32) launch_narrow(v.A.nnz, v.Ahs32, v.Ahs.v, h->stream);   // capacity; entries past nnz unused
+        if (l < L) {
+            launch_narrow(v.P.nnz, v.P32, v.P.v, h->stream);
+            launch_narrow(v.R.nnz, v.R32, v.R.v, h->stream);
+        }
+    }
+    check_launch();
+    h->fp32 = true;
 }
 
 // ---------------------------------------------------------------------------
@@ -628,6 +741,22 @@ amg_status do_reintroduce(amg_ctx* h, int s, double gamma_min, int* first) {
     return AMG_OK;
 }
 
+// z = V(r, 0) for CG, with r.z accumulated into dot_slot.  Mixed: the cycle
+// runs on r32 = (float) r (written by the CG update, or here when the guess is
+// kZero) and z = (double) z32.
+void precondition(amg_ctx* h, bool mixed, Guess guess, int dot_slot) {
+    const int n = h->lv[0].n;
+    if (!mixed) {
+        vcycle<double>(h, h->cg_r, h->cg_z, guess, dot_slot);
+        return;
+    }
+    if (guess == Guess::kZero) launch_narrow(n, h->cg_r32, h->cg_r, h->stream);
+    vcycle<float>(h, h->cg_r32, h->cg_z32, guess, -1);
+    ProfScope ps(h, AMG_K_VECTOR, 0);
+    launch_widen_dot(n, h->cg_z, h->cg_z32, h->cg_r, dot_to(h, dot_slot), h->stream);
+    check_launch();
+}
+
 amg_status solve(amg_ctx* h, const double* b, double* x, const amg_solve_params& p,
                  amg_solve_info* info_out, double* hist) {
     ensure_solve_buffers(h);
@@ -635,6 +764,10 @@ amg_status solve(amg_ctx* h, const double* b, double* x, const amg_solve_params&
     const int n = f.n;
     const DevMat& A = f.A;
     const bool pcg = p.method == AMG_PCG;
+    // FP32 V-cycle as the preconditioner (PCG) or as the correction of
+    // iterative refinement (stationary); everything else stays FP64
+    const bool mixed = p.precision == 32;
+    if (mixed) ensure_fp32(h);
     amg_solve_info info{0, 0, 0, 0, 0.0, 0.0};
     amg_status st = AMG_ERR_NOT_CONVERGED;
     double* r = h->cg_r;
@@ -659,7 +792,7 @@ amg_status solve(amg_ctx* h, const double* b, double* x, const amg_solve_params&
     } else {
         launch_copy(n, h->xw, x, h->stream);
         if (pcg) {
-            vcycle(h, r, h->cg_z, Guess::kZero, rz_slot);
+            precondition(h, mixed, Guess::kZero, rz_slot);
             launch_copy(n, h->cg_p, h->cg_z, h->stream);
         }
         while (info.iters < p.maxit) {
@@ -668,13 +801,23 @@ amg_status solve(amg_ctx* h, const double* b, double* x, const amg_solve_params&
                 {
                     ProfScope ps(h, AMG_K_VECTOR, 0);
                     // also forms the next preconditioner's zero-guess sweep omega D^-1 r
+                    const bool pre1 = h->sp.nu_pre >= 1;
                     launch_cg_update_xr(n, x, r, h->cg_p, h->cg_q, h->scal, rz_slot, S_PQ, h->scal + S_FLAG,
                                         dot_to(h, S_NR2), f.dinv, h->sp.omega,
-                                        h->sp.nu_pre >= 1 ? zero_start(h, 0, h->cg_z) : nullptr, h->stream);
+                                        (!mixed && pre1) ? zero_start<double>(h, 0, h->cg_z) : nullptr,
+                                        mixed ? h->cg_r32 : nullptr, f.dinv32,
+                                        (mixed && pre1) ? zero_start<float>(h, 0, h->cg_z32) : nullptr,
+                                        h->stream);
                     check_launch();
                 }
+            } else if (mixed) {
+                // iterative refinement: x += V32(r, 0) with r the current true residual
+                launch_narrow(n, h->cg_r32, r, h->stream);
+                vcycle<float>(h, h->cg_r32, h->cg_z32, Guess::kZero, -1);
+                launch_add_widened(n, x, h->cg_z32, h->stream);
+                row_op(h, AMG_K_RESIDUAL, 0, kResidNorm, A, x, b, nullptr, r, nullptr, S_NR2);
             } else {
-                vcycle(h, b, x, Guess::kNonzero, -1);
+                vcycle<double>(h, b, x, Guess::kNonzero, -1);
                 row_op(h, AMG_K_RESIDUAL, 0, kResidNorm, A, x, b, nullptr, r, nullptr, S_NR2);
             }
             const double* sc = read_scalars(h);
@@ -713,7 +856,7 @@ amg_status solve(amg_ctx* h, const double* b, double* x, const amg_solve_params&
             if (pcg) {
                 const int new_slot = rz_slot == S_RZ0 ? S_RZ1 : S_RZ0;
                 // after a restart r was rebuilt, so the prescaled sweep is stale
-                vcycle(h, r, h->cg_z, restart ? Guess::kZero : Guess::kPrescaled, new_slot);
+                precondition(h, mixed, restart ? Guess::kZero : Guess::kPrescaled, new_slot);
                 if (restart) {
                     info.restarts++;
                     launch_copy(n, h->cg_p, h->cg_z, h->stream);
@@ -773,7 +916,7 @@ void setup(amg_ctx* h, int64_t n, const int32_t* row_ptr, const int32_t* col, co
         d.Ah = d.A;
         d.ah_alias = true;
         d.dinv = dalloc_n<double>(h, d.n);
-        launch_inverse_diagonal(d.A.view(), d.dinv, h->stream);
+        launch_inverse_diagonal(d.A.view(), d.dinv, nullptr, h->stream);
         partial_need = std::max(partial_need, row_launch_blocks(d.n, d.A.width));
         if (l < L) {
             d.P = upload_mat(h, s.P);
@@ -826,7 +969,12 @@ void destroy(amg_ctx* h) {
         dfree(h, d.x);
         dfree(h, d.xt);
         dfree(h, d.r);
+        for (void* q : {(void*)d.A32, (void*)d.Ahs32, (void*)d.P32, (void*)d.R32, (void*)d.dinv32,
+                        (void*)d.b32, (void*)d.x32, (void*)d.xt32, (void*)d.r32})
+            dfree(h, q);
     }
+    dfree(h, h->cg_r32);
+    dfree(h, h->cg_z32);
     for (void* p : {(void*)h->coarse_inv, (void*)h->scal, (void*)h->partials,
                     (void*)h->scan_scratch, (void*)h->cnt, (void*)h->missing, (void*)h->cg_r,
                     (void*)h->cg_z, (void*)h->cg_p, (void*)h->cg_q, (void*)h->xw, (void*)h->rt})
@@ -894,6 +1042,7 @@ void amg_solve_params_default(amg_solve_params* p) {
     p->s = 1;
     p->rho_max = 0.5;
     p->gamma_min = 0.01;
+    p->precision = 64;
 }
 
 amg_status amg_setup_from_csr(int64_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
@@ -982,7 +1131,7 @@ amg_status amg_solve(amg_handle h, const double* b, double* x, const amg_solve_p
     amg_solve_params_default(&p);
     if (params) p = *params;
     if ((p.method != AMG_PCG && p.method != AMG_STATIONARY) || p.maxit < 0 || !(p.rtol >= 0.0) ||
-        (p.adaptive && (p.k < 1 || p.s < 1))) {
+        (p.adaptive && (p.k < 1 || p.s < 1)) || (p.precision != 64 && p.precision != 32)) {
         h->last_error = "invalid solve parameters";
         return AMG_ERR_INVALID_ARG;
     }
@@ -993,7 +1142,18 @@ amg_status amg_vcycle(amg_handle h, const double* b, double* x) {
     if (!h || h->lv.empty()) return AMG_ERR_STATE;
     if (!b || !x) return AMG_ERR_INVALID_ARG;
     return guarded(h, [&] {
-        vcycle(h, b, x, Guess::kNonzero, -1);
+        vcycle<double>(h, b, x, Guess::kNonzero, -1);
+        prof_collect(h);
+        return AMG_OK;
+    });
+}
+
+amg_status amg_vcycle32(amg_handle h, const float* b, float* x) {
+    if (!h || h->lv.empty()) return AMG_ERR_STATE;
+    if (!b || !x) return AMG_ERR_INVALID_ARG;
+    return guarded(h, [&] {
+        ensure_fp32(h);
+        vcycle<float>(h, b, x, Guess::kNonzero, -1);
         prof_collect(h);
         return AMG_OK;
     });

@@ -63,6 +63,7 @@ constexpr int kRowGridCap = AMG_ROW_GRID_CAP;   // row kernels loop over tiles b
 // non-temporally so that they do not evict the gathered vector from L2.
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef double v2d __attribute__((ext_vector_type(2)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 
 template <class T>
 __device__ __forceinline__ T stream_ld(const T* p) {
@@ -87,8 +88,8 @@ __device__ __forceinline__ int xcd_logical_block() {
 
 int round_up8(int b) { return (b + kXcds - 1) / kXcds * kXcds; }
 
-template <int W>
-__device__ __forceinline__ double sub_sum(double v) {
+template <int W, class T>
+__device__ __forceinline__ T sub_sum(T v) {
 #pragma unroll
     for (int o = W / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, W);
     return v;
@@ -169,10 +170,10 @@ constexpr int rows_in_flight() {
     return W <= 16 ? AMG_RIF : 1;
 }
 
-template <int W, int OP>
-__global__ __launch_bounds__(kBlock) void row_kernel(CsrView a, const double* __restrict__ g,
-                                                     const double* u, const double* __restrict__ dinv,
-                                                     double omega, double* y, double* y2,
+template <class T, int W, int OP>
+__global__ __launch_bounds__(kBlock) void row_kernel(CsrT<T> a, const T* __restrict__ g,
+                                                     const T* u, const T* __restrict__ dinv,
+                                                     T omega, T* y, T* y2,
                                                      DotTarget dot, int ntiles) {
     constexpr int kRowsPerBlock = kBlock / W;
     constexpr int R = rows_in_flight<W>();
@@ -182,14 +183,14 @@ __global__ __launch_bounds__(kBlock) void row_kernel(CsrView a, const double* __
     double contrib = 0.0;
     for (int t0 = lb * R; t0 < ntiles; t0 += gridDim.x * R) {
         int row[R], beg[R], end[R];
-        double s[R], ui[R], gi[R], di[R];
+        T s[R], ui[R], gi[R], di[R];
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             row[k] = (t0 + k) * kRowsPerBlock + sub;
             const bool act = row[k] < a.rows;
             beg[k] = act ? a.rp[row[k]] : 0;
             end[k] = act ? a.rp[row[k] + 1] : 0;
-            ui[k] = gi[k] = di[k] = 0.0;
+            ui[k] = gi[k] = di[k] = T(0);
             if (act && lane == 0) {
                 if constexpr (OP != kSpmv && OP != kSpmvDot && OP != kSpmvScale) ui[k] = u[row[k]];
                 if constexpr (OP == kJacobi || OP == kJacobiDot || OP == kSpmvDot) gi[k] = g[row[k]];
@@ -200,7 +201,7 @@ __global__ __launch_bounds__(kBlock) void row_kernel(CsrView a, const double* __
         // first chunk of every tile, branch-free (an empty slot re-loads the
         // row's first entry or entry 0) so that all loads are in flight together
         int jk[R];
-        double vk[R], gk[R];
+        T vk[R], gk[R];
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             const int p = beg[k] + lane;
@@ -215,12 +216,12 @@ __global__ __launch_bounds__(kBlock) void row_kernel(CsrView a, const double* __
             else gk[k] = g[j];
         }
 #pragma unroll
-        for (int k = 0; k < R; ++k) s[k] = (beg[k] + lane < end[k]) ? vk[k] * gk[k] : 0.0;
+        for (int k = 0; k < R; ++k) s[k] = (beg[k] + lane < end[k]) ? vk[k] * gk[k] : T(0);
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             for (int p = beg[k] + lane + W; p < end[k]; p += W) {
                 const int j = a.ci[p];
-                double gj;
+                T gj;
                 if constexpr (OP == kZeroJacobiResid) gj = omega * (dinv[j] * u[j]);
                 else gj = g[j];
                 s[k] += a.v[p] * gj;
@@ -228,7 +229,7 @@ __global__ __launch_bounds__(kBlock) void row_kernel(CsrView a, const double* __
         }
 #pragma unroll
         for (int k = 0; k < R; ++k) {
-            const double sk = sub_sum<W>(s[k]);
+            const T sk = sub_sum<W>(s[k]);
             if (row[k] < a.rows && lane == 0) {
                 const int r = row[k];
                 if constexpr (OP == kSpmv) {
@@ -236,19 +237,19 @@ __global__ __launch_bounds__(kBlock) void row_kernel(CsrView a, const double* __
                 } else if constexpr (OP == kSpmvAdd) {
                     y[r] = ui[k] + sk;
                 } else if constexpr (OP == kResid || OP == kResidNorm) {
-                    const double rr = ui[k] - sk;
+                    const T rr = ui[k] - sk;
                     y[r] = rr;
-                    if constexpr (OP == kResidNorm) contrib += rr * rr;
+                    if constexpr (OP == kResidNorm) contrib += (double)rr * (double)rr;
                 } else if constexpr (OP == kJacobi || OP == kJacobiDot) {
-                    const double xn = gi[k] + omega * di[k] * (ui[k] - sk);
+                    const T xn = gi[k] + omega * di[k] * (ui[k] - sk);
                     y[r] = xn;
-                    if constexpr (OP == kJacobiDot) contrib += ui[k] * xn;
+                    if constexpr (OP == kJacobiDot) contrib += (double)ui[k] * (double)xn;
                 } else if constexpr (OP == kZeroJacobiResid) {
                     y2[r] = omega * (di[k] * ui[k]);
                     y[r] = ui[k] - sk;
                 } else if constexpr (OP == kSpmvDot) {
                     y[r] = sk;
-                    contrib += gi[k] * sk;
+                    contrib += (double)gi[k] * (double)sk;
                 } else if constexpr (OP == kSpmvScale) {
                     y[r] = sk;
                     y2[r] = omega * (di[k] * sk);
@@ -259,9 +260,9 @@ __global__ __launch_bounds__(kBlock) void row_kernel(CsrView a, const double* __
     if constexpr (op_has_dot<OP>()) store_block_partial(contrib, dot.partials, lb);
 }
 
-template <int W>
-void launch_row_w(RowOp op, const CsrView& a, const double* g, const double* u, const double* dinv,
-                  double omega, double* y, double* y2, DotTarget dot, hipStream_t st) {
+template <class T, int W>
+void launch_row_w(RowOp op, const CsrT<T>& a, const T* g, const T* u, const T* dinv,
+                  T omega, T* y, T* y2, DotTarget dot, hipStream_t st) {
     constexpr int kRowsPerBlock = kBlock / W;
     constexpr int R = rows_in_flight<W>();
     const int ntiles = std::max(1, (a.rows + kRowsPerBlock - 1) / kRowsPerBlock);
@@ -270,7 +271,7 @@ void launch_row_w(RowOp op, const CsrView& a, const double* g, const double* u, 
     switch (op) {
 #define AMG_ROW_CASE(OPV)                                                                      \
     case OPV:                                                                                  \
-        hipLaunchKernelGGL((row_kernel<W, OPV>), dim3(grid), dim3(kBlock), 0, st, a, g, u, dinv, \
+        hipLaunchKernelGGL((row_kernel<T, W, OPV>), dim3(grid), dim3(kBlock), 0, st, a, g, u, dinv, \
                            omega, y, y2, dot, ntiles);                                         \
         break;
         AMG_ROW_CASE(kSpmv)
@@ -293,13 +294,13 @@ void launch_row_w(RowOp op, const CsrView& a, const double* g, const double* u, 
 // park the products in LDS; then 256/RB lanes per row add the row's products.
 constexpr int kStreamCap = AMG_STREAM_CAP;   // products staged per pass (16 KB of LDS)
 
-template <int RB, int OP, bool VEC4>
-__global__ __launch_bounds__(kBlock) void stream_kernel(CsrView a, const double* __restrict__ g,
-                                                        const double* u, const double* __restrict__ dinv,
-                                                        double omega, double* y, double* y2,
+template <class T, int RB, int OP, bool VEC4>
+__global__ __launch_bounds__(kBlock) void stream_kernel(CsrT<T> a, const T* __restrict__ g,
+                                                        const T* u, const T* __restrict__ dinv,
+                                                        T omega, T* y, T* y2,
                                                         DotTarget dot, int nblk) {
     constexpr int W2 = kBlock / RB;
-    __shared__ double prod[kStreamCap];
+    __shared__ T prod[kStreamCap];
     const int lb = xcd_logical_block();
     const int lane = threadIdx.x & (W2 - 1);
     double contrib = 0.0;
@@ -310,14 +311,14 @@ __global__ __launch_bounds__(kBlock) void stream_kernel(CsrView a, const double*
         const int r = r0 + (int)threadIdx.x / W2;
         const bool act = r < r1;
         const int rb = act ? a.rp[r] : 0, re = act ? a.rp[r + 1] : 0;
-        double ui = 0.0, gi = 0.0, di = 0.0;
+        T ui = T(0), gi = T(0), di = T(0);
         if (act && lane == 0) {
             if constexpr (OP != kSpmv && OP != kSpmvDot && OP != kSpmvScale) ui = u[r];
             if constexpr (OP == kJacobi || OP == kJacobiDot || OP == kSpmvDot) gi = g[r];
             if constexpr (OP == kJacobi || OP == kJacobiDot || OP == kZeroJacobiResid || OP == kSpmvScale)
                 di = dinv[r];
         }
-        double s = 0.0;
+        T s = T(0);
         for (int c0 = p0; c0 < p1; c0 += kStreamCap) {
             const int c1 = min(c0 + kStreamCap, p1);
             if constexpr (VEC4) {
@@ -330,16 +331,22 @@ __global__ __launch_bounds__(kBlock) void stream_kernel(CsrView a, const double*
                     const int q = base + 4 * (k * kBlock + (int)threadIdx.x);
                     if (q < c1) {
                         const v4i cj = stream_ld(reinterpret_cast<const v4i*>(a.ci + q));
-                        const v2d v01 = stream_ld(reinterpret_cast<const v2d*>(a.v + q));
-                        const v2d v23 = stream_ld(reinterpret_cast<const v2d*>(a.v + q + 2));
+                        T vv[4];
+                        if constexpr (sizeof(T) == 8) {
+                            const v2d v01 = stream_ld(reinterpret_cast<const v2d*>(a.v + q));
+                            const v2d v23 = stream_ld(reinterpret_cast<const v2d*>(a.v + q + 2));
+                            vv[0] = v01.x; vv[1] = v01.y; vv[2] = v23.x; vv[3] = v23.y;
+                        } else {
+                            const v4f v0123 = stream_ld(reinterpret_cast<const v4f*>(a.v + q));
+                            vv[0] = v0123.x; vv[1] = v0123.y; vv[2] = v0123.z; vv[3] = v0123.w;
+                        }
                         const int jj[4] = {cj.x, cj.y, cj.z, cj.w};
-                        const double vv[4] = {v01.x, v01.y, v23.x, v23.y};
 #pragma unroll
                         for (int e = 0; e < 4; ++e) {
                             const int p = q + e;
                             if (p >= c0 && p < c1) {
                                 const int j = jj[e];
-                                double gj;
+                                T gj;
                                 if constexpr (OP == kZeroJacobiResid) gj = omega * (dinv[j] * u[j]);
                                 else gj = g[j];
                                 prod[p - c0] = vv[e] * gj;
@@ -353,7 +360,7 @@ __global__ __launch_bounds__(kBlock) void stream_kernel(CsrView a, const double*
                     const int p = c0 + k * kBlock + (int)threadIdx.x;
                     if (p < c1) {
                         const int j = stream_ld(a.ci + p);
-                        double gj;
+                        T gj;
                         if constexpr (OP == kZeroJacobiResid) gj = omega * (dinv[j] * u[j]);
                         else gj = g[j];
                         prod[p - c0] = stream_ld(a.v + p) * gj;
@@ -372,19 +379,19 @@ __global__ __launch_bounds__(kBlock) void stream_kernel(CsrView a, const double*
             } else if constexpr (OP == kSpmvAdd) {
                 y[r] = ui + s;
             } else if constexpr (OP == kResid || OP == kResidNorm) {
-                const double rr = ui - s;
+                const T rr = ui - s;
                 y[r] = rr;
-                if constexpr (OP == kResidNorm) contrib += rr * rr;
+                if constexpr (OP == kResidNorm) contrib += (double)rr * (double)rr;
             } else if constexpr (OP == kJacobi || OP == kJacobiDot) {
-                const double xn = gi + omega * di * (ui - s);
+                const T xn = gi + omega * di * (ui - s);
                 y[r] = xn;
-                if constexpr (OP == kJacobiDot) contrib += ui * xn;
+                if constexpr (OP == kJacobiDot) contrib += (double)ui * (double)xn;
             } else if constexpr (OP == kZeroJacobiResid) {
                 y2[r] = omega * (di * ui);
                 y[r] = ui - s;
             } else if constexpr (OP == kSpmvDot) {
                 y[r] = s;
-                contrib += gi * s;
+                contrib += (double)gi * (double)s;
             } else if constexpr (OP == kSpmvScale) {
                 y[r] = s;
                 y2[r] = omega * (di * s);
@@ -394,15 +401,15 @@ __global__ __launch_bounds__(kBlock) void stream_kernel(CsrView a, const double*
     if constexpr (op_has_dot<OP>()) store_block_partial(contrib, dot.partials, lb);
 }
 
-template <int RB, bool VEC4>
-void launch_stream_rb(RowOp op, const CsrView& a, const double* g, const double* u, const double* dinv,
-                      double omega, double* y, double* y2, DotTarget dot, hipStream_t st) {
+template <class T, int RB, bool VEC4>
+void launch_stream_rb(RowOp op, const CsrT<T>& a, const T* g, const T* u, const T* dinv,
+                      T omega, T* y, T* y2, DotTarget dot, hipStream_t st) {
     const int nblk = std::max(1, (a.rows + RB - 1) / RB);
     const int grid = round_up8(std::min(nblk, std::min(kRowGridCap, AMG_STREAM_GRID_CAP)));
     switch (op) {
 #define AMG_STREAM_CASE(OPV)                                                                      \
     case OPV:                                                                                     \
-        hipLaunchKernelGGL((stream_kernel<RB, OPV, VEC4>), dim3(grid), dim3(kBlock), 0, st, a, g, u, dinv, \
+        hipLaunchKernelGGL((stream_kernel<T, RB, OPV, VEC4>), dim3(grid), dim3(kBlock), 0, st, a, g, u, dinv, \
                            omega, y, y2, dot, nblk);                                              \
         break;
         AMG_STREAM_CASE(kSpmv)
@@ -434,17 +441,26 @@ __global__ __launch_bounds__(kBlock) void cg_update_xr_kernel(int n, double* __r
                                                               const double* scal, int i_num,
                                                               int i_den, double* flag, DotTarget dot,
                                                               const double* __restrict__ dinv,
-                                                              double omega, double* __restrict__ zs) {
+                                                              double omega, double* __restrict__ zs,
+                                                              float* __restrict__ r32,
+                                                              const float* __restrict__ dinv32,
+                                                              float* __restrict__ zs32) {
     const double num = scal[i_num], den = scal[i_den];
     const bool ok = den > 0.0 && std::isfinite(den);
     double contrib = 0.0;
     if (ok) {
         const double alpha = num / den;
+        const float omega32 = (float)omega;
         for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
             x[i] = x[i] + alpha * p[i];
             const double ri = r[i] - alpha * q[i];
             r[i] = ri;
             if (zs) zs[i] = omega * (dinv[i] * ri);
+            if (r32) {
+                const float rf = (float)ri;
+                r32[i] = rf;
+                if (zs32) zs32[i] = omega32 * (dinv32[i] * rf);
+            }
             contrib += ri * ri;
         }
     } else if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -483,6 +499,62 @@ __global__ __launch_bounds__(kBlock) void fill_u32_kernel(int64_t n, unsigned* p
         p[i] = v;
 }
 
+__global__ __launch_bounds__(kBlock) void narrow_kernel(int64_t n, float* __restrict__ y,
+                                                        const double* __restrict__ x) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        y[i] = (float)x[i];
+}
+
+// y = (double) x, dot += u . y   (the FP32 preconditioner output entering FP64 CG)
+__global__ __launch_bounds__(kBlock) void widen_dot_kernel(int n, double* __restrict__ y,
+                                                           const float* __restrict__ x,
+                                                           const double* __restrict__ u, DotTarget dot) {
+    double s = 0.0;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        const double v = (double)x[i];
+        y[i] = v;
+        s += u[i] * v;
+    }
+    store_block_partial(s, dot.partials, blockIdx.x);
+}
+
+// x += (double) e   (iterative refinement with an FP32 correction)
+__global__ __launch_bounds__(kBlock) void add_widened_kernel(int n, double* __restrict__ x,
+                                                             const float* __restrict__ e) {
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) x[i] = x[i] + (double)e[i];
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void scaled_copy_t_kernel(int n, T* __restrict__ y,
+                                                               const T* __restrict__ dinv,
+                                                               const T* __restrict__ x, T omega) {
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
+        y[i] = omega * (dinv[i] * x[i]);
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void copy_t_kernel(int n, T* __restrict__ y, const T* __restrict__ x) {
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) y[i] = x[i];
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void fill_t_kernel(int64_t n, T* p, T v) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        p[i] = v;
+}
+
+// y = Ainv b with the FP64 inverse of the coarsest operator; FP32 in and out
+__global__ __launch_bounds__(kBlock) void dense_matvec_mixed_kernel(int n, const double* __restrict__ ainv,
+                                                                    const float* __restrict__ b,
+                                                                    float* __restrict__ y) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    const double* row = ainv + (size_t)i * n;
+    for (int j = 0; j < n; ++j) s += row[j] * (double)b[j];
+    y[i] = (float)s;
+}
+
 __global__ __launch_bounds__(kBlock) void fill_f64_kernel(int64_t n, double* p, double v) {
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
         p[i] = v;
@@ -506,7 +578,8 @@ __global__ __launch_bounds__(kBlock) void dense_matvec_kernel(int n, const doubl
     y[i] = s;
 }
 
-__global__ __launch_bounds__(kBlock) void inverse_diagonal_kernel(CsrView a, double* __restrict__ dinv) {
+__global__ __launch_bounds__(kBlock) void inverse_diagonal_kernel(CsrView a, double* __restrict__ dinv,
+                                                                  float* __restrict__ dinv32) {
     constexpr int W = 8;
     const int i = blockIdx.x * (kBlock / W) + threadIdx.x / W;
     const int lane = threadIdx.x & (W - 1);
@@ -515,7 +588,10 @@ __global__ __launch_bounds__(kBlock) void inverse_diagonal_kernel(CsrView a, dou
         for (int p = a.rp[i] + lane; p < a.rp[i + 1]; p += W)
             if (a.ci[p] == i) d = a.v[p];
     d = sub_sum<W>(d);          // exactly one lane holds the diagonal
-    if (i < a.rows && lane == 0) dinv[i] = 1.0 / d;
+    if (i < a.rows && lane == 0) {
+        dinv[i] = 1.0 / d;
+        if (dinv32) dinv32[i] = (float)(1.0 / d);
+    }
 }
 
 // ---- sparsification kernels --------------------------------------------------
@@ -598,7 +674,9 @@ __global__ __launch_bounds__(kBlock) void compact_lump_kernel(CsrView a, const u
                                                               const int32_t* __restrict__ new_rp,
                                                               int32_t* __restrict__ new_ci,
                                                               double* __restrict__ new_v,
-                                                              double* __restrict__ dinv) {
+                                                              double* __restrict__ dinv,
+                                                              float* __restrict__ new_v32,
+                                                              float* __restrict__ dinv32) {
     const int row = blockIdx.x * (kBlock / W) + threadIdx.x / W;
     const int lane = threadIdx.x & (W - 1);
     const int shift = (threadIdx.x & 63) & ~(W - 1);
@@ -625,6 +703,7 @@ __global__ __launch_bounds__(kBlock) void compact_lump_kernel(CsrView a, const u
             const int w = out0 + written + __popcll(bits & lanes_below);
             new_ci[w] = j;
             new_v[w] = v;
+            if (new_v32) new_v32[w] = (float)v;
             if (j == row) { diag_pos = w; diag = v; }
         } else if (p < end && j != row) {
             dropped += v;
@@ -636,6 +715,10 @@ __global__ __launch_bounds__(kBlock) void compact_lump_kernel(CsrView a, const u
         const double d = diag + dropped;
         new_v[diag_pos] = d;
         dinv[row] = 1.0 / d;
+        if (new_v32) {
+            new_v32[diag_pos] = (float)d;
+            dinv32[row] = (float)(1.0 / d);
+        }
     }
 }
 
@@ -705,10 +788,10 @@ __global__ __launch_bounds__(kBlock) void dense_invert_kernel(CsrView a, double*
 constexpr int kTailBlock = 1024;
 constexpr int kTailW = 8;
 
-template <int OPT>
-__device__ __forceinline__ void tail_rows(const CsrView& a, const double* __restrict__ g,
-                                          const double* u, const double* __restrict__ dinv,
-                                          double omega, double* y, double* y2) {
+template <class T, int OPT>
+__device__ __forceinline__ void tail_rows(const CsrT<T>& a, const T* __restrict__ g,
+                                          const T* u, const T* __restrict__ dinv,
+                                          T omega, T* y, T* y2) {
     // OPT 0: y = u - A g        (residual)
     // OPT 1: y = A g, y2 = omega dinv y   (restriction writing the prescaled sweep)
     // OPT 2: y = A g            (restriction onto the coarsest level)
@@ -717,7 +800,7 @@ __device__ __forceinline__ void tail_rows(const CsrView& a, const double* __rest
     const int lane = threadIdx.x & (kTailW - 1);
     for (int row0 = threadIdx.x / kTailW; row0 < a.rows; row0 += kTailBlock / kTailW) {
         const int row = row0;
-        double s = 0.0;
+        T s = T(0);
         for (int p = a.rp[row] + lane; p < a.rp[row + 1]; p += kTailW) s += a.v[p] * g[a.ci[p]];
         s = sub_sum<kTailW>(s);
         if (lane == 0) {
@@ -730,34 +813,35 @@ __device__ __forceinline__ void tail_rows(const CsrView& a, const double* __rest
     }
 }
 
-__global__ __launch_bounds__(kTailBlock) void coarse_tail_kernel(TailArgs t) {
+template <class T>
+__global__ __launch_bounds__(kTailBlock) void coarse_tail_kernel(TailArgs<T> t) {
     const int last = t.count - 1;
     for (int k = 0; k < last; ++k) {
-        const TailLevel& L = t.lv[k];
-        tail_rows<0>(L.A, L.x, L.b, nullptr, t.omega, L.r, nullptr);
+        const TailLevel<T>& L = t.lv[k];
+        tail_rows<T, 0>(L.A, L.x, L.b, nullptr, t.omega, L.r, nullptr);
         __syncthreads();
-        const TailLevel& N = t.lv[k + 1];
-        if (k + 1 < last) tail_rows<1>(L.R, L.r, nullptr, N.dinv, t.omega, N.b, N.x);
-        else tail_rows<2>(L.R, L.r, nullptr, nullptr, t.omega, N.b, nullptr);
+        const TailLevel<T>& N = t.lv[k + 1];
+        if (k + 1 < last) tail_rows<T, 1>(L.R, L.r, nullptr, N.dinv, t.omega, N.b, N.x);
+        else tail_rows<T, 2>(L.R, L.r, nullptr, nullptr, t.omega, N.b, nullptr);
         __syncthreads();
     }
     {
-        const TailLevel& C = t.lv[last];
+        const TailLevel<T>& C = t.lv[last];
         const int n = C.A.rows;
         for (int i = threadIdx.x; i < n; i += kTailBlock) {
             double s = 0.0;
             const double* row = t.coarse_inv + (size_t)i * n;
-            for (int j = 0; j < n; ++j) s += row[j] * C.b[j];
-            C.x[i] = s;
+            for (int j = 0; j < n; ++j) s += row[j] * (double)C.b[j];
+            C.x[i] = (T)s;
         }
         __syncthreads();
     }
     for (int k = last - 1; k >= 0; --k) {
-        const TailLevel& L = t.lv[k];
-        const double* xc = (k + 1 == last) ? t.lv[k + 1].x : t.lv[k + 1].xt;
-        tail_rows<3>(L.P, xc, L.x, nullptr, t.omega, L.x, nullptr);
+        const TailLevel<T>& L = t.lv[k];
+        const T* xc = (k + 1 == last) ? t.lv[k + 1].x : t.lv[k + 1].xt;
+        tail_rows<T, 3>(L.P, xc, L.x, nullptr, t.omega, L.x, nullptr);
         __syncthreads();
-        tail_rows<4>(L.A, L.x, L.b, L.dinv, t.omega, L.xt, nullptr);
+        tail_rows<T, 4>(L.A, L.x, L.b, L.dinv, t.omega, L.xt, nullptr);
         __syncthreads();
     }
 }
@@ -848,7 +932,8 @@ int stream_rows_per_block(double mean) {
 // The LDS-staged kernel wins on the large fine-level operators with short
 // rows (measured on the 128^3 hierarchy: A_0, A_1, P_0, R_0, R_1); with long
 // rows or too few row blocks to fill 256 CUs the subgroup kernel wins.
-bool use_stream_kernel(const CsrView& a) {
+template <class T>
+bool use_stream_kernel(const CsrT<T>& a) {
 #if AMG_USE_STREAM >= 0
     return AMG_USE_STREAM != 0;
 #else
@@ -859,27 +944,28 @@ bool use_stream_kernel(const CsrView& a) {
 
 // 16-byte packed loads pay off on the operators with the shortest rows
 // (measured: A_0, P_l, R_0 gain 5-8%; the 19-point A_1 loses).
-template <bool VEC4>
-void launch_stream_v(RowOp op, const CsrView& a, const double* g, const double* u, const double* dinv,
-                     double omega, double* y, double* y2, DotTarget dot, hipStream_t st) {
+template <class T, bool VEC4>
+void launch_stream_v(RowOp op, const CsrT<T>& a, const T* g, const T* u, const T* dinv,
+                     T omega, T* y, T* y2, DotTarget dot, hipStream_t st) {
     switch (stream_rows_per_block(a.mean_row)) {
-        case 256: launch_stream_rb<256, VEC4>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
-        case 128: launch_stream_rb<128, VEC4>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
-        case 64: launch_stream_rb<64, VEC4>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
-        case 32: launch_stream_rb<32, VEC4>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
-        default: launch_stream_rb<16, VEC4>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
+        case 256: launch_stream_rb<T, 256, VEC4>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
+        case 128: launch_stream_rb<T, 128, VEC4>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
+        case 64: launch_stream_rb<T, 64, VEC4>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
+        case 32: launch_stream_rb<T, 32, VEC4>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
+        default: launch_stream_rb<T, 16, VEC4>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
     }
 }
 
-void launch_stream_any(RowOp op, const CsrView& a, const double* g, const double* u, const double* dinv,
-                       double omega, double* y, double* y2, DotTarget dot, hipStream_t st) {
+template <class T>
+void launch_stream_any(RowOp op, const CsrT<T>& a, const T* g, const T* u, const T* dinv,
+                       T omega, T* y, T* y2, DotTarget dot, hipStream_t st) {
 #if AMG_VEC4 >= 0
     constexpr bool kForce = AMG_VEC4 != 0;
-    if (kForce) launch_stream_v<true>(op, a, g, u, dinv, omega, y, y2, dot, st);
-    else launch_stream_v<false>(op, a, g, u, dinv, omega, y, y2, dot, st);
+    if (kForce) launch_stream_v<T, true>(op, a, g, u, dinv, omega, y, y2, dot, st);
+    else launch_stream_v<T, false>(op, a, g, u, dinv, omega, y, y2, dot, st);
 #else
-    if (a.mean_row <= 10.0) launch_stream_v<true>(op, a, g, u, dinv, omega, y, y2, dot, st);
-    else launch_stream_v<false>(op, a, g, u, dinv, omega, y, y2, dot, st);
+    if (a.mean_row <= 10.0) launch_stream_v<T, true>(op, a, g, u, dinv, omega, y, y2, dot, st);
+    else launch_stream_v<T, false>(op, a, g, u, dinv, omega, y, y2, dot, st);
 #endif
 }
 
@@ -904,29 +990,41 @@ int row_launch_blocks(int rows, int width) {
     return round_up8(std::min((ntiles + R - 1) / R, kRowGridCap));
 }
 
-void launch_row_op(RowOp op, int width, const CsrView& a, const double* g, const double* u,
-                   const double* dinv, double omega, double* y, double* y2, DotTarget dot,
-                   hipStream_t st) {
+template <class T>
+void launch_row_op_t(RowOp op, int width, const CsrT<T>& a, const T* g, const T* u,
+                     const T* dinv, T omega, T* y, T* y2, DotTarget dot, hipStream_t st) {
     if (use_stream_kernel(a)) {
         launch_stream_any(op, a, g, u, dinv, omega, y, y2, dot, st);
         return;
     }
     switch (width) {
-        case 1: launch_row_w<1>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
-        case 2: launch_row_w<2>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
-        case 4: launch_row_w<4>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
-        case 8: launch_row_w<8>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
-        case 16: launch_row_w<16>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
-        case 32: launch_row_w<32>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
-        default: launch_row_w<64>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
+        case 1: launch_row_w<T, 1>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
+        case 2: launch_row_w<T, 2>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
+        case 4: launch_row_w<T, 4>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
+        case 8: launch_row_w<T, 8>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
+        case 16: launch_row_w<T, 16>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
+        case 32: launch_row_w<T, 32>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
+        default: launch_row_w<T, 64>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
     }
+}
+
+void launch_row_op(RowOp op, int width, const CsrView& a, const double* g, const double* u,
+                   const double* dinv, double omega, double* y, double* y2, DotTarget dot,
+                   hipStream_t st) {
+    launch_row_op_t<double>(op, width, a, g, u, dinv, omega, y, y2, dot, st);
+}
+
+void launch_row_op(RowOp op, int width, const CsrView32& a, const float* g, const float* u,
+                   const float* dinv, float omega, float* y, float* y2, hipStream_t st) {
+    launch_row_op_t<float>(op, width, a, g, u, dinv, omega, y, y2, DotTarget{nullptr, nullptr}, st);
 }
 
 void launch_cg_update_xr(int n, double* x, double* r, const double* p, const double* q,
                          const double* scal, int i_num, int i_den, double* flag, DotTarget dot,
-                         const double* dinv, double omega, double* zs, hipStream_t st) {
+                         const double* dinv, double omega, double* zs, float* r32,
+                         const float* dinv32, float* zs32, hipStream_t st) {
     hipLaunchKernelGGL(cg_update_xr_kernel, dim3(vec_grid(n)), dim3(kBlock), 0, st, n, x, r, p, q,
-                       scal, i_num, i_den, flag, dot, dinv, omega, zs);
+                       scal, i_num, i_den, flag, dot, dinv, omega, zs, r32, dinv32, zs32);
     finish_dot(dot, vec_grid(n), st);
 }
 
@@ -955,6 +1053,38 @@ void launch_fill_u32(int64_t n, unsigned* p, unsigned v, hipStream_t st) {
     hipLaunchKernelGGL(fill_u32_kernel, dim3(g), dim3(kBlock), 0, st, n, p, v);
 }
 
+void launch_narrow(int64_t n, float* y, const double* x, hipStream_t st) {
+    const int g = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (n + kBlock - 1) / kBlock));
+    hipLaunchKernelGGL(narrow_kernel, dim3(g), dim3(kBlock), 0, st, n, y, x);
+}
+
+void launch_widen_dot(int n, double* y, const float* x, const double* u, DotTarget dot, hipStream_t st) {
+    hipLaunchKernelGGL(widen_dot_kernel, dim3(vec_grid(n)), dim3(kBlock), 0, st, n, y, x, u, dot);
+    finish_dot(dot, vec_grid(n), st);
+}
+
+void launch_add_widened(int n, double* x, const float* e, hipStream_t st) {
+    hipLaunchKernelGGL(add_widened_kernel, dim3(vec_grid(n)), dim3(kBlock), 0, st, n, x, e);
+}
+
+void launch_scaled_copy(int n, float* y, const float* dinv, const float* x, float omega, hipStream_t st) {
+    hipLaunchKernelGGL(scaled_copy_t_kernel<float>, dim3(vec_grid(n)), dim3(kBlock), 0, st, n, y, dinv, x, omega);
+}
+
+void launch_copy(int n, float* y, const float* x, hipStream_t st) {
+    hipLaunchKernelGGL(copy_t_kernel<float>, dim3(vec_grid(n)), dim3(kBlock), 0, st, n, y, x);
+}
+
+void launch_fill_f32(int64_t n, float* p, float v, hipStream_t st) {
+    const int g = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (n + kBlock - 1) / kBlock));
+    hipLaunchKernelGGL(fill_t_kernel<float>, dim3(g), dim3(kBlock), 0, st, n, p, v);
+}
+
+void launch_dense_matvec(int n, const double* ainv, const float* b, float* y, hipStream_t st) {
+    hipLaunchKernelGGL(dense_matvec_mixed_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, n,
+                       ainv, b, y);
+}
+
 void launch_fill_f64(int64_t n, double* p, double v, hipStream_t st) {
     const int g = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (n + kBlock - 1) / kBlock));
     hipLaunchKernelGGL(fill_f64_kernel, dim3(g), dim3(kBlock), 0, st, n, p, v);
@@ -972,9 +1102,9 @@ void launch_dense_matvec(int n, const double* ainv, const double* b, double* y, 
                        ainv, b, y);
 }
 
-void launch_inverse_diagonal(const CsrView& a, double* dinv, hipStream_t st) {
+void launch_inverse_diagonal(const CsrView& a, double* dinv, float* dinv32, hipStream_t st) {
     hipLaunchKernelGGL(inverse_diagonal_kernel, dim3((a.rows + kBlock / 8 - 1) / (kBlock / 8)), dim3(kBlock),
-                       0, st, a, dinv);
+                       0, st, a, dinv, dinv32);
 }
 
 void launch_mark_minimal_pattern(int nc, const int32_t* c_points, const int32_t* afine_rp,
@@ -1008,15 +1138,20 @@ void launch_keep_count(int width, const CsrView& a, const uint8_t* in_m, const d
 }
 
 void launch_compact_lump(int width, const CsrView& a, const uint8_t* keep, const int32_t* new_rp,
-                         int32_t* new_ci, double* new_v, double* dinv, hipStream_t st) {
+                         int32_t* new_ci, double* new_v, double* dinv, float* new_v32, float* dinv32,
+                         hipStream_t st) {
     if (a.rows <= 0) return;
-    AMG_WIDTH_SWITCH(width, compact_lump_kernel, a, keep, new_rp, new_ci, new_v, dinv);
+    AMG_WIDTH_SWITCH(width, compact_lump_kernel, a, keep, new_rp, new_ci, new_v, dinv, new_v32, dinv32);
 }
 
 int dense_invert_max() { return kDenseInvMax; }
 
-void launch_coarse_tail(const TailArgs& t, hipStream_t st) {
-    hipLaunchKernelGGL(coarse_tail_kernel, dim3(1), dim3(kTailBlock), 0, st, t);
+void launch_coarse_tail(const TailArgs<double>& t, hipStream_t st) {
+    hipLaunchKernelGGL(coarse_tail_kernel<double>, dim3(1), dim3(kTailBlock), 0, st, t);
+}
+
+void launch_coarse_tail(const TailArgs<float>& t, hipStream_t st) {
+    hipLaunchKernelGGL(coarse_tail_kernel<float>, dim3(1), dim3(kTailBlock), 0, st, t);
 }
 
 void launch_dense_invert(const CsrView& a, double* inv, int* singular, hipStream_t st) {

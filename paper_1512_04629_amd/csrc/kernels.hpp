@@ -7,14 +7,17 @@
 
 namespace amg355 {
 
-// Read-only view of a device CSR matrix.
-struct CsrView {
+// Read-only view of a device CSR matrix with values of type T.
+template <class T>
+struct CsrT {
     const int32_t* rp;
     const int32_t* ci;
-    const double* v;
+    const T* v;
     int rows;
     double mean_row;   // nnz / rows, host side launch configuration only
 };
+using CsrView = CsrT<double>;
+using CsrView32 = CsrT<float>;
 
 // Epilogues of the CSR row kernel.  s_i = sum_j a_ij g_j (for kZeroJacobiResid
 // the gathered value is omega * dinv_j * u_j).
@@ -51,15 +54,21 @@ int max_row_launch_blocks();
 void launch_row_op(RowOp op, int width, const CsrView& a, const double* g, const double* u,
                    const double* dinv, double omega, double* y, double* y2, DotTarget dot,
                    hipStream_t st);
+// single precision: values, vectors and accumulation in FP32 (no dot ops)
+void launch_row_op(RowOp op, int width, const CsrView32& a, const float* g, const float* u,
+                   const float* dinv, float omega, float* y, float* y2, hipStream_t st);
 
 // ---- vector kernels -----------------------------------------------------
 // x += alpha p; r -= alpha q; dot -> |r|^2, with alpha = scal[i_num]/scal[i_den];
 // if zs is not null also zs = omega dinv r (the next V-cycle's zero-guess
 // sweep).  If scal[i_den] is not positive and finite, nothing is updated and
 // *flag = 1.0.
+// With r32 not null also r32 = (float) r and zs32 = omega dinv32 r32 (the
+// FP32 preconditioner's right-hand side and zero-guess sweep).
 void launch_cg_update_xr(int n, double* x, double* r, const double* p, const double* q,
                          const double* scal, int i_num, int i_den, double* flag, DotTarget dot,
-                         const double* dinv, double omega, double* zs, hipStream_t st);
+                         const double* dinv, double omega, double* zs, float* r32,
+                         const float* dinv32, float* zs32, hipStream_t st);
 // p = z + beta p with beta = scal[i_num]/scal[i_den]; if restart, p = z.
 void launch_cg_update_p(int n, double* p, const double* z, const double* scal, int i_num,
                         int i_den, hipStream_t st);
@@ -81,7 +90,17 @@ void launch_dense_matvec(int n, const double* ainv, const double* b, double* y, 
 int dense_invert_max();
 void launch_dense_invert(const CsrView& a, double* inv, int* singular, hipStream_t st);
 // dinv_i = 1 / a_ii
-void launch_inverse_diagonal(const CsrView& a, double* dinv, hipStream_t st);
+// (and its FP32 rounding when dinv32 is not null)
+void launch_inverse_diagonal(const CsrView& a, double* dinv, float* dinv32, hipStream_t st);
+// same as launch_dense_matvec with FP32 vectors (inverse and accumulation FP64)
+void launch_dense_matvec(int n, const double* ainv, const float* b, float* y, hipStream_t st);
+// precision conversions and FP32 vector helpers
+void launch_narrow(int64_t n, float* y, const double* x, hipStream_t st);
+void launch_widen_dot(int n, double* y, const float* x, const double* u, DotTarget dot, hipStream_t st);
+void launch_add_widened(int n, double* x, const float* e, hipStream_t st);
+void launch_scaled_copy(int n, float* y, const float* dinv, const float* x, float omega, hipStream_t st);
+void launch_copy(int n, float* y, const float* x, hipStream_t st);
+void launch_fill_f32(int64_t n, float* p, float v, hipStream_t st);
 
 // ---- coarse tail: the V-cycle below a level in one workgroup ---------------
 // Levels t..L of a V(1,1) cycle with zero initial guesses: down (residual of
@@ -91,19 +110,22 @@ void launch_inverse_diagonal(const CsrView& a, double* dinv, hipStream_t st);
 // right-hand side and lv[0].x the first sweep omega D^-1 b; on exit the
 // level-t result is in lv[0].xt.
 constexpr int kTailMaxLevels = 12;
+template <class T>
 struct TailLevel {
-    CsrView A;           // sparsified operator of the level
-    CsrView R, P;        // restriction to / interpolation from the next level
-    const double* dinv;
-    double *b, *x, *xt, *r;
+    CsrT<T> A;           // sparsified operator of the level
+    CsrT<T> R, P;        // restriction to / interpolation from the next level
+    const T* dinv;
+    T *b, *x, *xt, *r;
 };
+template <class T>
 struct TailArgs {
-    TailLevel lv[kTailMaxLevels];
+    TailLevel<T> lv[kTailMaxLevels];
     int count;
-    const double* coarse_inv;
-    double omega;
+    const double* coarse_inv;   // FP64 in both precisions
+    T omega;
 };
-void launch_coarse_tail(const TailArgs& t, hipStream_t st);
+void launch_coarse_tail(const TailArgs<double>& t, hipStream_t st);
+void launch_coarse_tail(const TailArgs<float>& t, hipStream_t st);
 
 // ---- sparsification kernels ----------------------------------------------
 // Marks M_l: for coarse row I with fine point f = c_points[I], every column J
@@ -122,8 +144,9 @@ int64_t scan_scratch_ints(int n);
 void launch_exclusive_scan(int n, const int32_t* cnt, int32_t* out, int32_t* scratch,
                            hipStream_t st);
 // compaction of the kept entries with the dropped ones added to the diagonal
+// (new_v32/dinv32 not null: also the FP32 copies)
 void launch_compact_lump(int width, const CsrView& a, const uint8_t* keep,
                          const int32_t* new_rp, int32_t* new_ci, double* new_v, double* dinv,
-                         hipStream_t st);
+                         float* new_v32, float* dinv32, hipStream_t st);
 
 }  // namespace amg355

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def header_functions():
     text = open(os.path.join(ROOT, "include", "amg.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(amg_[a-z_]+)\s*\(", text)) - {"amg_alloc_fn", "amg_free_fn"})
+    return sorted(set(re.findall(r"\b(amg_[a-z0-9_]+)\s*\(", text)) - {"amg_alloc_fn", "amg_free_fn"})
 
 
 def test_header_and_binding_agree():
