@@ -153,6 +153,34 @@ amg_status amg_vcycle(amg_handle h, const double* b, double* x);
    keep them current. */
 amg_status amg_vcycle32(amg_handle h, const float* b, float* x);
 
+/* Several right-hand sides at once: A X = B for nrhs columns (1 <= nrhs <=
+   16) with iterative refinement, X_c <- X_c + V(B_c - A X_c, 0) per column
+   (the Section 2 V-cycle as the correction, the residual always in FP64),
+   every cycle step applied to all columns in one pass over each operator.
+   b, x: device FP64 arrays of n x nrhs entries, row-major (entry (i, c) at
+   i*nrhs + c), 16-byte aligned; x holds the initial guesses and receives the
+   solutions.  params: method must be AMG_STATIONARY and adaptive 0;
+   precision 64, or 32 for a correction cycle in FP32 values, vectors and
+   accumulation (FP64 coarsest inverse); NULL = defaults with those two
+   fields.  Iterates until every column has ||r_c|| <= rtol ||r0_c|| (columns
+   with r0_c = 0 count as converged at once) or maxit.  info (nullable):
+   iters of the whole block, relres the largest column ratio.  col_iters
+   (nullable, host, nrhs): the first iteration at which column c met the
+   tolerance, -1 if it never did.  col_relres (nullable, host, nrhs): the
+   final ||r_c|| / ||r0_c||.  Errors: AMG_ERR_INVALID_ARG for other
+   parameters or misaligned arrays, AMG_ERR_NOT_CONVERGED after maxit,
+   AMG_ERR_BREAKDOWN on a non-finite residual.  nrhs other than 4, 8, 16 is
+   padded internally to the next of them (extra device copies of b and x). */
+amg_status amg_solve_block(amg_handle h, int32_t nrhs, const double* b, double* x,
+                           const amg_solve_params* params, amg_solve_info* info,
+                           int32_t* col_iters, double* col_relres);
+
+/* One V-cycle on nrhs = 4, 8 or 16 columns in place: X <- V(B, X), device
+   arrays laid out as for amg_solve_block (16-byte aligned); FP64 and FP32
+   (values, vectors, accumulation; FP64 coarsest inverse) versions. */
+amg_status amg_vcycle_block(amg_handle h, int32_t nrhs, const double* b, double* x);
+amg_status amg_vcycle_block32(amg_handle h, int32_t nrhs, const float* b, float* x);
+
 /* Single steps of the V-cycle on level l, device arrays (for component
    checks and for callers composing their own cycles):
      AMG_OP_RESIDUAL     out = b - Ahat_l x                 (in = b)

@@ -36,7 +36,7 @@ KERNEL = {"JACOBI": 0, "JACOBI_ZERO": 1, "RESIDUAL": 2, "RESTRICT": 3, "INTERP":
 ABI_SYMBOLS = (
     "amg_setup_params_default", "amg_solve_params_default", "amg_setup_from_csr",
     "amg_sparsify", "amg_sparsify_levels", "amg_reintroduce", "amg_solve", "amg_vcycle", "amg_vcycle32",
-    "amg_level_op", "amg_num_levels", "amg_get_level", "amg_export_level", "amg_export_mask",
+    "amg_solve_block", "amg_vcycle_block", "amg_vcycle_block32", "amg_level_op", "amg_num_levels", "amg_get_level", "amg_export_level", "amg_export_mask",
     "amg_export_vector", "amg_export_split", "amg_profile_enable", "amg_profile_read",
     "amg_destroy", "amg_status_string", "amg_last_error",
 )
@@ -89,6 +89,9 @@ def load_library():
     lib.amg_solve.argtypes = [vp, vp, vp, P(SolveParams), P(SolveInfo), vp]
     lib.amg_vcycle.argtypes = [vp, vp, vp]
     lib.amg_vcycle32.argtypes = [vp, vp, vp]
+    lib.amg_solve_block.argtypes = [vp, i32, vp, vp, P(SolveParams), P(SolveInfo), vp, vp]
+    lib.amg_vcycle_block.argtypes = [vp, i32, vp, vp]
+    lib.amg_vcycle_block32.argtypes = [vp, i32, vp, vp]
     lib.amg_level_op.argtypes = [vp, i32, i32, vp, vp, vp]
     lib.amg_num_levels.argtypes = [vp, P(i32)]
     lib.amg_get_level.argtypes = [vp, i32, P(i64), P(i64), P(i64), P(i64), P(i64), P(f64), P(i64)]
@@ -105,7 +108,8 @@ def load_library():
     lib.amg_last_error.argtypes = [vp]
     lib.amg_last_error.restype = C.c_char_p
     for name in ("amg_setup_from_csr", "amg_sparsify", "amg_sparsify_levels", "amg_reintroduce",
-                 "amg_solve", "amg_vcycle", "amg_vcycle32", "amg_level_op", "amg_num_levels", "amg_get_level",
+                 "amg_solve", "amg_vcycle", "amg_vcycle32", "amg_solve_block", "amg_vcycle_block",
+                 "amg_vcycle_block32", "amg_level_op", "amg_num_levels", "amg_get_level",
                  "amg_export_level", "amg_export_mask", "amg_export_vector", "amg_export_split",
                  "amg_profile_enable", "amg_profile_read"):
         getattr(lib, name).restype = C.c_int
@@ -156,6 +160,16 @@ def _close_all():
             h.close()
         except Exception:
             pass
+
+
+@dataclass
+class BlockSolveResult:
+    status: int
+    iters: int
+    converged: bool
+    relres: float
+    col_iters: np.ndarray
+    col_relres: np.ndarray
 
 
 @dataclass
@@ -273,6 +287,39 @@ class Hierarchy:
                     and t.is_contiguous() and t.numel() == self.n):
                 raise TypeError(f"{name} must be a contiguous float32 CUDA tensor of {self.n} entries")
         self._check(self._lib.amg_vcycle32(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr())))
+
+    def _block(self, t, name, dtype, nrhs=None):
+        torch = _torch()
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()
+                and t.dim() == 2 and t.shape[0] == self.n and (nrhs is None or t.shape[1] == nrhs)):
+            raise TypeError(f"{name} must be a contiguous {dtype} CUDA tensor of shape ({self.n}, nrhs)")
+        return C.c_void_p(t.data_ptr())
+
+    def solve_block(self, b, x, method=PCG, tol=1e-10, maxit=200, precision=32,
+                    raise_on_error=False) -> BlockSolveResult:
+        """Solves all columns of the (n, nrhs) float64 blocks b, x at once: PCG
+        per column, or (method=STATIONARY) iterative refinement; precision=32
+        runs the V-cycle in FP32."""
+        torch = _torch()
+        nrhs = int(b.shape[1]) if b.dim() == 2 else 0
+        pb, px = self._block(b, "b", torch.float64), self._block(x, "x", torch.float64, nrhs)
+        p = SolveParams(int(method), float(tol), int(maxit), 0, 3, 1, 0.5, 0.01, int(precision))
+        info = SolveInfo()
+        ci = np.full(max(nrhs, 1), -2, np.int32)
+        cr = np.full(max(nrhs, 1), np.nan)
+        st = self._lib.amg_solve_block(self._h, nrhs, pb, px, C.byref(p), C.byref(info),
+                                       ci.ctypes.data, cr.ctypes.data)
+        if st not in (OK, -5, -6) or raise_on_error:
+            self._check(st)
+        return BlockSolveResult(st, info.iters, bool(info.converged), info.relres, ci[:nrhs].copy(),
+                                cr[:nrhs].copy())
+
+    def vcycle_block(self, b, x):
+        """One V-cycle X <- V(B, X) on (n, 4|8|16) blocks, float64 or float32."""
+        torch = _torch()
+        fn = self._lib.amg_vcycle_block if b.dtype == torch.float64 else self._lib.amg_vcycle_block32
+        nrhs = int(b.shape[1]) if b.dim() == 2 else 0
+        self._check(fn(self._h, nrhs, self._block(b, "b", b.dtype), self._block(x, "x", b.dtype, nrhs)))
 
     def level_op(self, level: int, op: str, inp=None, x=None, out=None):
         args = [C.c_void_p(t.data_ptr()) if t is not None else None for t in (inp, x, out)]

@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "../../include/amg.h"
+#include "block_kernels.hpp"
 #include "host_setup.hpp"
 #include "kernels.hpp"
 
@@ -48,7 +49,11 @@ constexpr int kMaxDenseCoarse = 4096;
 constexpr int kCsrPad = 4;
 
 // device scalar slots
-enum : int { S_RZ0 = 0, S_RZ1 = 1, S_PQ = 2, S_NR2 = 3, S_FLAG = 4, S_NRT = 5, S_DOT = 6, S_COUNT = 8 };
+// Block solves use 16 slots per quantity: squared residual norms (S_BLOCK),
+// r.z of two iterations (S_BRZ0, S_BRZ1), p.Ap (S_BPQ), active flags (S_BACT).
+enum : int { S_RZ0 = 0, S_RZ1 = 1, S_PQ = 2, S_NR2 = 3, S_FLAG = 4, S_NRT = 5, S_DOT = 6, S_BLOCK = 8,
+             S_BRZ0 = 24, S_BRZ1 = 40, S_BPQ = 56, S_BACT = 72, S_COUNT = 88 };
+constexpr int kMaxBlockRhs = 16;
 
 struct DevMat {
     int rows = 0, cols = 0;
@@ -90,6 +95,16 @@ struct DevLevel {
     float *b32 = nullptr, *x32 = nullptr, *xt32 = nullptr, *r32 = nullptr;
 };
 
+// work blocks of the multi-right-hand-side cycle in one precision: K-wide
+// (row-interleaved) per level; rhs is the level-0 right-hand side of a
+// correction cycle
+template <class T>
+struct BlockBufs {
+    int k = 0;
+    std::vector<T*> b, x, xt, r;
+    T* rhs = nullptr;
+};
+
 struct ProfAcc {
     int64_t count = 0;
     double ms = 0.0;
@@ -124,6 +139,13 @@ struct amg_ctx {
     double *xw = nullptr, *rt = nullptr;
     bool fp32 = false;
     float *cg_r32 = nullptr, *cg_z32 = nullptr;
+    BlockBufs<double> blk64;
+    BlockBufs<float> blk32;
+    double* blk_partials = nullptr;
+    double *blk_b = nullptr, *blk_x = nullptr;   // K-wide copies when nrhs is not a block width
+    int bcg_k = 0;                               // block CG vectors (FP64, K wide)
+    double *bcg_r = nullptr, *bcg_p = nullptr, *bcg_q = nullptr, *bcg_z = nullptr;
+    int blk_pack_k = 0;
     std::string last_error;
     bool check_singular = false;   // a device inversion wrote h->missing
     bool profiling = false;
@@ -881,6 +903,378 @@ amg_status solve(amg_ctx* h, const double* b, double* x, const amg_solve_params&
 }
 
 // ---------------------------------------------------------------------------
+// multiple right-hand sides: the V-cycle applied to an n x K block (K columns
+// row-interleaved), iterative refinement with the residual in FP64
+// ---------------------------------------------------------------------------
+BlockBufs<double>& block_bufs(amg_ctx* h, double*) { return h->blk64; }
+BlockBufs<float>& block_bufs(amg_ctx* h, float*) { return h->blk32; }
+
+template <class T>
+void free_block_bufs(amg_ctx* h, BlockBufs<T>& bb) {
+    for (auto* v : {&bb.b, &bb.x, &bb.xt, &bb.r})
+        for (T* p : *v) dfree(h, p);
+    bb.b.clear(); bb.x.clear(); bb.xt.clear(); bb.r.clear();
+    dfree(h, bb.rhs);
+    bb.rhs = nullptr;
+    bb.k = 0;
+}
+
+// per-level K-wide work blocks of precision T (reallocated for a wider K)
+template <class T>
+BlockBufs<T>& ensure_block(amg_ctx* h, int k) {
+    BlockBufs<T>& bb = block_bufs(h, (T*)nullptr);
+    if (!h->blk_partials) h->blk_partials = dalloc_n<double>(h, block_partials_needed());
+    if (bb.k >= k) return bb;
+    free_block_bufs(h, bb);
+    const int L = (int)h->lv.size() - 1;
+    bb.b.assign(L + 1, nullptr);
+    bb.x.assign(L + 1, nullptr);
+    bb.xt.assign(L + 1, nullptr);
+    bb.r.assign(L + 1, nullptr);
+    for (int l = 0; l <= L; ++l) {
+        const int64_t cnt = (int64_t)h->lv[l].n * k;
+        if (l > 0) bb.b[l] = dalloc_n<T>(h, cnt);
+        bb.x[l] = dalloc_n<T>(h, cnt);
+        bb.xt[l] = dalloc_n<T>(h, cnt);
+        bb.r[l] = dalloc_n<T>(h, cnt);
+    }
+    bb.rhs = dalloc_n<T>(h, (int64_t)h->lv[0].n * k);
+    bb.k = k;
+    return bb;
+}
+
+template <class T>
+void block_op_t(amg_ctx* h, int kind, int l, BlockOp op, int k, const DevMat& m, const T* vals, const T* g,
+                const T* u, const T* dinv, T* y, T* y2, double* acc) {
+    ProfScope ps(h, kind, l);
+    launch_block_op(op, k, CsrT<T>{m.rp, m.ci, vals, m.rows, 0.0}, g, u, dinv, (T)h->sp.omega, y, y2, acc,
+                    h->stream);
+    check_launch();
+}
+
+ColumnDots cols_to(amg_ctx* h, int slot) { return ColumnDots{h->blk_partials, h->scal + slot}; }
+
+// Where the level-0 result of a block cycle goes: added to the FP64 block acc
+// (refinement), or written to the FP64 block z64 with the column dots
+// r64 . z64 (CG); neither: left in a buffer of the cycle's precision.
+struct BlockSink {
+    double* acc = nullptr;
+    double* z64 = nullptr;
+    const double* r64 = nullptr;
+    ColumnDots dot{};
+};
+
+// One V-cycle on K columns.  guess0: kNonzero -- bb.x[0] holds the iterate;
+// kPrescaled -- the iterate is zero and bb.x[0] holds omega D^-1 b0.  The
+// last level-0 sweep delivers the result to sink (then nullptr is returned);
+// without a sink the buffer holding the result is returned.
+template <class T>
+T* vcycle_block(amg_ctx* h, int k, const T* b0, Guess guess0, const BlockSink& sink) {
+    const bool to_sink = sink.acc || sink.z64;
+    BlockBufs<T>& bb = block_bufs(h, (T*)nullptr);
+    const int L = (int)h->lv.size() - 1;
+    const int pre = h->sp.nu_pre, post = h->sp.nu_post;
+    // a level-0 result held in x (precision T) handed to the sink
+    auto deliver = [&](const T* x) {
+        ProfScope ps(h, AMG_K_VECTOR, 0);
+        if (sink.acc) launch_block_accumulate((int64_t)h->lv[0].n * k, sink.acc, x, h->stream);
+        else launch_block_widen_dot(h->lv[0].n, k, x, sink.z64, sink.r64, sink.dot, h->stream);
+        check_launch();
+    };
+    if (L == 0) {
+        {
+            ProfScope ps(h, AMG_K_COARSE, 0);
+            launch_block_dense_matvec(h->nL, k, h->coarse_inv, b0, bb.xt[0], h->stream);
+            check_launch();
+        }
+        if (!to_sink) return bb.xt[0];
+        deliver(bb.xt[0]);
+        return nullptr;
+    }
+    std::vector<T*> cur(L + 1), alt(L + 1);
+    auto sweep = [&](int l, const LevelView<T>& v, const T* b, bool last0) {
+        if (last0 && sink.acc) {
+            block_op_t<T>(h, AMG_K_JACOBI, l, kBJacobiAccum, k, *v.Ah, v.ahv, cur[l], b, v.dinv, nullptr,
+                          nullptr, sink.acc);
+        } else if (last0 && sink.z64) {
+            ProfScope ps(h, AMG_K_JACOBI, l);
+            launch_block_sweep_widen_dot(k, CsrT<T>{v.Ah->rp, v.Ah->ci, v.ahv, v.Ah->rows, 0.0}, cur[l], b, v.dinv,
+                                         (T)h->sp.omega, sink.z64, sink.r64, sink.dot, h->stream);
+            check_launch();
+        } else {
+            block_op_t<T>(h, AMG_K_JACOBI, l, kBJacobi, k, *v.Ah, v.ahv, cur[l], b, v.dinv, alt[l], nullptr,
+                          nullptr);
+            std::swap(cur[l], alt[l]);
+        }
+    };
+    for (int l = 0; l < L; ++l) {
+        LevelView<T> v = level_view(h, l, (T*)nullptr);
+        const int64_t cnt = (int64_t)v.n * k;
+        const T* b = l == 0 ? b0 : bb.b[l];
+        cur[l] = bb.x[l];
+        alt[l] = bb.xt[l];
+        const bool zero = l > 0 || guess0 != Guess::kNonzero;
+        if (zero && pre == 0) {
+            fill_t(cnt, cur[l], h);
+            launch_copy((int)cnt, bb.r[l], b, h->stream);
+            check_launch();
+        } else {
+            // a zero iterate arrives with its first sweep already formed
+            for (int s = zero ? 1 : 0; s < pre; ++s) sweep(l, v, b, false);
+            const int kind = (zero && pre == 1) ? AMG_K_JACOBI_ZERO : AMG_K_RESIDUAL;
+            block_op_t<T>(h, kind, l, kBResid, k, *v.Ah, v.ahv, cur[l], b, nullptr, bb.r[l], nullptr, nullptr);
+        }
+        LevelView<T> nx = level_view(h, l + 1, (T*)nullptr);
+        if (pre >= 1 && l + 1 < L)
+            block_op_t<T>(h, AMG_K_RESTRICT, l, kBSpmvScale, k, *v.R, v.rv, bb.r[l], nullptr, nx.dinv, bb.b[l + 1],
+                          bb.x[l + 1], nullptr);
+        else
+            block_op_t<T>(h, AMG_K_RESTRICT, l, kBSpmv, k, *v.R, v.rv, bb.r[l], nullptr, nullptr, bb.b[l + 1],
+                          nullptr, nullptr);
+    }
+    {
+        ProfScope ps(h, AMG_K_COARSE, L);
+        launch_block_dense_matvec(h->nL, k, h->coarse_inv, bb.b[L], bb.x[L], h->stream);
+        check_launch();
+        cur[L] = bb.x[L];
+    }
+    for (int l = L - 1; l >= 0; --l) {
+        LevelView<T> v = level_view(h, l, (T*)nullptr);
+        const T* b = l == 0 ? b0 : bb.b[l];
+        block_op_t<T>(h, AMG_K_INTERP, l, kBSpmvAdd, k, *v.P, v.pv, cur[l + 1], cur[l], nullptr, cur[l], nullptr,
+                      nullptr);
+        for (int s = 0; s < post; ++s) sweep(l, v, b, l == 0 && to_sink && s == post - 1);
+    }
+    if (!to_sink) return cur[0];
+    if (post == 0) deliver(cur[0]);
+    return nullptr;
+}
+
+// outer residual r = b - A_0 x (FP64) of all K columns into bb.rhs (precision
+// T) with the next cycle's first sweep omega D^-1 r in bb.x[0] (and r itself
+// into r64 when not null); squared column norms into the slots S_BLOCK..
+template <class T>
+void block_outer(amg_ctx* h, int k, const double* b, const double* x, double* r64 = nullptr) {
+    BlockBufs<T>& bb = block_bufs(h, (T*)nullptr);
+    DevLevel& f = h->lv[0];
+    LevelView<T> v = level_view(h, 0, (T*)nullptr);
+    ProfScope ps(h, AMG_K_RESIDUAL, 0);
+    launch_block_outer_residual(k, f.A.view(), x, b, v.dinv, (T)h->sp.omega, bb.rhs, bb.x[0], r64,
+                                cols_to(h, S_BLOCK), h->stream);
+    check_launch();
+}
+
+// Iterative refinement x_c += V(b_c - A x_c, 0) on all K columns together;
+// nrhs columns are real (the others are zero padding).
+template <class T>
+amg_status solve_block(amg_ctx* h, int k, int nrhs, const double* b, double* x, const amg_solve_params& p,
+                       amg_solve_info* info_out, int32_t* col_iters, double* col_relres) {
+    if constexpr (sizeof(T) == 4) ensure_fp32(h);
+    BlockBufs<T>& bb = ensure_block<T>(h, k);
+    amg_solve_info info{0, 0, 0, 0, 0.0, 0.0};
+    amg_status st = AMG_ERR_NOT_CONVERGED;
+    launch_fill_f64(S_COUNT, h->scal, 0.0, h->stream);
+    block_outer<T>(h, k, b, x);
+    int singular = 0;
+    if (h->check_singular) download(h, &singular, h->missing, 1);
+    const double* sc = read_scalars(h);
+    if (h->check_singular) {
+        h->check_singular = false;
+        if (singular) throw AmgFailure{AMG_ERR_BAD_MATRIX, "coarsest operator is singular"};
+    }
+    double nr0[kMaxBlockRhs], rel[kMaxBlockRhs];
+    int first[kMaxBlockRhs];
+    bool finite = true;
+    for (int c = 0; c < nrhs; ++c) {
+        nr0[c] = std::sqrt(sc[S_BLOCK + c]);
+        finite = finite && std::isfinite(nr0[c]);
+        rel[c] = 1.0;
+        first[c] = nr0[c] == 0.0 ? 0 : -1;
+        if (nr0[c] == 0.0) rel[c] = 0.0;
+    }
+    auto all_done = [&] {
+        for (int c = 0; c < nrhs; ++c)
+            if (first[c] < 0) return false;
+        return true;
+    };
+    if (!finite) {
+        st = AMG_ERR_BREAKDOWN;
+    } else if (all_done()) {
+        st = AMG_OK;
+        info.converged = 1;
+    } else {
+        while (info.iters < p.maxit) {
+            BlockSink sink;
+            sink.acc = x;
+            vcycle_block<T>(h, k, bb.rhs, Guess::kPrescaled, sink);
+            block_outer<T>(h, k, b, x);
+            sc = read_scalars(h);
+            info.iters++;
+            bool bad = false;
+            for (int c = 0; c < nrhs; ++c) {
+                const double nr = std::sqrt(sc[S_BLOCK + c]);
+                bad = bad || !std::isfinite(nr);
+                if (nr0[c] > 0.0) rel[c] = nr / nr0[c];
+                if (first[c] < 0 && nr <= p.rtol * nr0[c]) first[c] = info.iters;
+            }
+            if (bad) { st = AMG_ERR_BREAKDOWN; break; }
+            if (all_done()) { st = AMG_OK; info.converged = 1; break; }
+        }
+    }
+    double worst = 0.0;
+    for (int c = 0; c < nrhs; ++c) {
+        worst = std::max(worst, rel[c]);
+        if (col_iters) col_iters[c] = first[c];
+        if (col_relres) col_relres[c] = rel[c];
+    }
+    info.relres = worst;
+    info.rho_avg = (info.iters > 0 && worst > 0.0) ? std::pow(worst, 1.0 / info.iters) : 0.0;
+    if (info_out) *info_out = info;
+    prof_collect(h);
+    return st;
+}
+
+void ensure_block_cg(amg_ctx* h, int k) {
+    if (h->bcg_k >= k) return;
+    for (double** q : {&h->bcg_r, &h->bcg_p, &h->bcg_q, &h->bcg_z}) {
+        dfree(h, *q);
+        *q = nullptr;
+    }
+    const int64_t cnt = (int64_t)h->lv[0].n * k;
+    h->bcg_r = dalloc_n<double>(h, cnt);
+    h->bcg_p = dalloc_n<double>(h, cnt);
+    h->bcg_q = dalloc_n<double>(h, cnt);
+    h->bcg_z = dalloc_n<double>(h, cnt);
+    h->bcg_k = k;
+}
+
+// per-column active flags (1 = still iterating) to the device, staged in the
+// pinned buffer (read_scalars later reads the same values back)
+void upload_active(amg_ctx* h, const bool* active, int k) {
+    for (int c = 0; c < k; ++c) h->pinned[S_BACT + c] = active[c] ? 1.0 : 0.0;
+    HIP_CHECK(hipMemcpyAsync(h->scal + S_BACT, h->pinned + S_BACT, sizeof(double) * k, hipMemcpyHostToDevice,
+                             h->stream));
+}
+
+// Preconditioned CG on every column at once (Section 5 PCG with the Section 2
+// V-cycle as preconditioner): the FP64 iterates and column scalars stay on the
+// device; one cycle of precision T and one FP64 product A p per iteration
+// serve all columns.  A column stops changing once it meets the tolerance.
+template <class T>
+amg_status solve_block_pcg(amg_ctx* h, int k, int nrhs, const double* b, double* x, const amg_solve_params& p,
+                           amg_solve_info* info_out, int32_t* col_iters, double* col_relres) {
+    if constexpr (sizeof(T) == 4) ensure_fp32(h);
+    BlockBufs<T>& bb = ensure_block<T>(h, k);
+    ensure_block_cg(h, k);
+    DevLevel& f = h->lv[0];
+    const int n = f.n;
+    LevelView<T> v0 = level_view(h, 0, (T*)nullptr);
+    const T omega = (T)h->sp.omega;
+    amg_solve_info info{0, 0, 0, 0, 0.0, 0.0};
+    amg_status st = AMG_ERR_NOT_CONVERGED;
+    launch_fill_f64(S_COUNT, h->scal, 0.0, h->stream);
+    block_outer<T>(h, k, b, x, h->bcg_r);
+    int singular = 0;
+    if (h->check_singular) download(h, &singular, h->missing, 1);
+    const double* sc = read_scalars(h);
+    if (h->check_singular) {
+        h->check_singular = false;
+        if (singular) throw AmgFailure{AMG_ERR_BAD_MATRIX, "coarsest operator is singular"};
+    }
+    double nr0[kMaxBlockRhs], rel[kMaxBlockRhs];
+    int first[kMaxBlockRhs];
+    bool active[kMaxBlockRhs] = {};
+    bool finite = true;
+    int nactive = 0;
+    for (int c = 0; c < nrhs; ++c) {
+        nr0[c] = std::sqrt(sc[S_BLOCK + c]);
+        finite = finite && std::isfinite(nr0[c]);
+        first[c] = nr0[c] == 0.0 ? 0 : -1;
+        rel[c] = nr0[c] == 0.0 ? 0.0 : 1.0;
+        active[c] = nr0[c] > 0.0;
+        nactive += active[c];
+    }
+    auto precondition = [&](int slot) {
+        BlockSink sink;
+        sink.z64 = h->bcg_z;
+        sink.r64 = h->bcg_r;
+        sink.dot = cols_to(h, slot);
+        vcycle_block<T>(h, k, bb.rhs, Guess::kPrescaled, sink);
+    };
+    if (!finite) {
+        st = AMG_ERR_BREAKDOWN;
+    } else if (nactive == 0) {
+        st = AMG_OK;
+        info.converged = 1;
+    } else {
+        upload_active(h, active, k);
+        int rz = S_BRZ0;
+        precondition(rz);
+        launch_block_cg_update_p(n, k, h->bcg_p, h->bcg_z, h->scal, rz, rz, S_BACT, true, h->stream);
+        check_launch();
+        while (info.iters < p.maxit) {
+            {
+                ProfScope ps(h, AMG_K_SPMV_DOT, 0);
+                launch_block_spmv_dot(k, f.A.view(), h->bcg_p, h->bcg_q, cols_to(h, S_BPQ), h->stream);
+                check_launch();
+            }
+            {
+                ProfScope ps(h, AMG_K_VECTOR, 0);
+                launch_block_cg_update_xr(n, k, x, h->bcg_r, h->bcg_p, h->bcg_q, h->scal, rz, S_BPQ, S_BACT,
+                                          h->scal + S_FLAG, v0.dinv, omega, bb.rhs, bb.x[0], cols_to(h, S_BLOCK),
+                                          h->stream);
+                check_launch();
+            }
+            sc = read_scalars(h);
+            info.iters++;
+            if (sc[S_FLAG] != 0.0) { st = AMG_ERR_BREAKDOWN; break; }
+            bool bad = false, changed = false;
+            for (int c = 0; c < nrhs; ++c) {
+                if (!active[c]) continue;
+                const double nr = std::sqrt(sc[S_BLOCK + c]);
+                bad = bad || !std::isfinite(nr);
+                rel[c] = nr / nr0[c];
+                if (nr <= p.rtol * nr0[c]) {
+                    first[c] = info.iters;
+                    active[c] = false;
+                    changed = true;
+                    --nactive;
+                }
+            }
+            if (bad) { st = AMG_ERR_BREAKDOWN; break; }
+            if (nactive == 0) { st = AMG_OK; info.converged = 1; break; }
+            if (changed) upload_active(h, active, k);
+            const int next = rz == S_BRZ0 ? S_BRZ1 : S_BRZ0;
+            precondition(next);
+            {
+                ProfScope ps(h, AMG_K_VECTOR, 0);
+                launch_block_cg_update_p(n, k, h->bcg_p, h->bcg_z, h->scal, next, rz, S_BACT, false, h->stream);
+                check_launch();
+            }
+            rz = next;
+        }
+    }
+    // final true residual of every column
+    if (info.iters > 0) {
+        block_outer<T>(h, k, b, x);
+        sc = read_scalars(h);
+        for (int c = 0; c < nrhs; ++c)
+            if (nr0[c] > 0.0) rel[c] = std::sqrt(sc[S_BLOCK + c]) / nr0[c];
+    }
+    double worst = 0.0;
+    for (int c = 0; c < nrhs; ++c) {
+        worst = std::max(worst, rel[c]);
+        if (col_iters) col_iters[c] = first[c];
+        if (col_relres) col_relres[c] = rel[c];
+    }
+    info.relres = worst;
+    info.rho_avg = (info.iters > 0 && worst > 0.0) ? std::pow(worst, 1.0 / info.iters) : 0.0;
+    if (info_out) *info_out = info;
+    prof_collect(h);
+    return st;
+}
+
+// ---------------------------------------------------------------------------
 // setup
 // ---------------------------------------------------------------------------
 void setup(amg_ctx* h, int64_t n, const int32_t* row_ptr, const int32_t* col, const double* val) {
@@ -975,6 +1369,12 @@ void destroy(amg_ctx* h) {
     }
     dfree(h, h->cg_r32);
     dfree(h, h->cg_z32);
+    free_block_bufs(h, h->blk64);
+    free_block_bufs(h, h->blk32);
+    dfree(h, h->blk_partials);
+    dfree(h, h->blk_b);
+    dfree(h, h->blk_x);
+    for (void* q : {(void*)h->bcg_r, (void*)h->bcg_p, (void*)h->bcg_q, (void*)h->bcg_z}) dfree(h, q);
     for (void* p : {(void*)h->coarse_inv, (void*)h->scal, (void*)h->partials,
                     (void*)h->scan_scratch, (void*)h->cnt, (void*)h->missing, (void*)h->cg_r,
                     (void*)h->cg_z, (void*)h->cg_p, (void*)h->cg_q, (void*)h->xw, (void*)h->rt})
@@ -1013,6 +1413,27 @@ bool valid_gamma(double g) { return g >= 0.0 && g <= 1.0; }
 std::string& setup_error() {
     static thread_local std::string msg;
     return msg;
+}
+
+template <class T>
+amg_status vcycle_block_abi(amg_handle h, int32_t nrhs, const T* b, T* x) {
+    if (!h || h->lv.empty()) return AMG_ERR_STATE;
+    const int64_t n = h->lv[0].n;
+    if (!b || !x || (nrhs != 4 && nrhs != 8 && nrhs != 16) || n * nrhs > INT32_MAX ||
+        (((uintptr_t)b | (uintptr_t)x) & 15) != 0) {
+        h->last_error = "nrhs must be 4, 8 or 16 and the blocks 16-byte aligned";
+        return AMG_ERR_INVALID_ARG;
+    }
+    return guarded(h, [&] {
+        if constexpr (sizeof(T) == 4) ensure_fp32(h);
+        BlockBufs<T>& bb = ensure_block<T>(h, nrhs);
+        launch_copy((int)(n * nrhs), bb.x[0], x, h->stream);
+        T* res = vcycle_block<T>(h, nrhs, b, Guess::kNonzero, BlockSink{});
+        launch_copy((int)(n * nrhs), x, res, h->stream);
+        check_launch();
+        prof_collect(h);
+        return AMG_OK;
+    });
 }
 
 }  // namespace
@@ -1157,6 +1578,66 @@ amg_status amg_vcycle32(amg_handle h, const float* b, float* x) {
         prof_collect(h);
         return AMG_OK;
     });
+}
+
+amg_status amg_solve_block(amg_handle h, int32_t nrhs, const double* b, double* x, const amg_solve_params* params,
+                           amg_solve_info* info, int32_t* col_iters, double* col_relres) {
+    if (!h || h->lv.empty()) return AMG_ERR_STATE;
+    amg_solve_params p;
+    amg_solve_params_default(&p);
+    if (params) p = *params;
+    const int64_t n = h->lv[0].n;
+    if (!b || !x || nrhs < 1 || nrhs > kMaxBlockRhs || n * block_width(nrhs) > INT32_MAX ||
+        (p.method != AMG_STATIONARY && p.method != AMG_PCG) || p.adaptive || p.maxit < 0 || !(p.rtol >= 0.0) ||
+        (p.precision != 64 && p.precision != 32)) {
+        h->last_error = "invalid block solve arguments (1 <= nrhs <= 16, not adaptive)";
+        return AMG_ERR_INVALID_ARG;
+    }
+    const int k = block_width(nrhs);
+    if (k == nrhs && (((uintptr_t)b | (uintptr_t)x) & 15) != 0) {
+        h->last_error = "block vectors must be 16-byte aligned";
+        return AMG_ERR_INVALID_ARG;
+    }
+    return guarded(h, [&] {
+        const double* bk = b;
+        double* xk = x;
+        if (k != nrhs) {
+            // K-wide copies with zero columns nrhs..K-1
+            if (h->blk_pack_k < k) {
+                dfree(h, h->blk_b);
+                dfree(h, h->blk_x);
+                h->blk_b = h->blk_x = nullptr;
+                h->blk_b = dalloc_n<double>(h, n * k);
+                h->blk_x = dalloc_n<double>(h, n * k);
+                h->blk_pack_k = k;
+            }
+            launch_block_pack((int)n, nrhs, k, b, h->blk_b, h->stream);
+            launch_block_pack((int)n, nrhs, k, x, h->blk_x, h->stream);
+            check_launch();
+            bk = h->blk_b;
+            xk = h->blk_x;
+        }
+        amg_status st;
+        if (p.method == AMG_PCG)
+            st = p.precision == 32 ? solve_block_pcg<float>(h, k, nrhs, bk, xk, p, info, col_iters, col_relres)
+                                   : solve_block_pcg<double>(h, k, nrhs, bk, xk, p, info, col_iters, col_relres);
+        else
+            st = p.precision == 32 ? solve_block<float>(h, k, nrhs, bk, xk, p, info, col_iters, col_relres)
+                                   : solve_block<double>(h, k, nrhs, bk, xk, p, info, col_iters, col_relres);
+        if (k != nrhs) {
+            launch_block_unpack((int)n, nrhs, k, xk, x, h->stream);
+            check_launch();
+        }
+        return st;
+    });
+}
+
+amg_status amg_vcycle_block(amg_handle h, int32_t nrhs, const double* b, double* x) {
+    return vcycle_block_abi<double>(h, nrhs, b, x);
+}
+
+amg_status amg_vcycle_block32(amg_handle h, int32_t nrhs, const float* b, float* x) {
+    return vcycle_block_abi<float>(h, nrhs, b, x);
 }
 
 amg_status amg_level_op(amg_handle h, int32_t level, int32_t op, const double* in, const double* x,

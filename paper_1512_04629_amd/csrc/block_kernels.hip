@@ -1,0 +1,639 @@
+// Multi-right-hand-side kernels of the V-cycle (gfx950, wave64).
+//
+// K columns row-interleaved: the K values that a row gathers from row j of a
+// block are one contiguous run of K * sizeof(T) bytes.  A row is served by
+// K * sizeof(T) / 16 lanes, each holding 16 bytes of columns (4 FP32 or 2
+// FP64), so that every gather is a 16-byte load and the matrix entries of the
+// row (column index and value, same address in those lanes) are read once for
+// all K columns.  Bandwidth-bound like the single-vector kernels: per nonzero
+// 8 (FP32) or 12 (FP64) bytes of matrix against K values of gathered vector,
+// most of which come from cache because neighbouring rows share columns.
+#include "block_kernels.hpp"
+
+#include <algorithm>
+
+namespace amg355 {
+namespace {
+
+constexpr int kBlk = 256;
+constexpr int kXcd = 8;          // accelerator complex dies, each with its own L2
+constexpr int kGridCap = 4096;   // row tiles beyond this many workgroups are looped over
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
+
+template <class T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+    using type = v4f;
+    static constexpr int n = 4;
+};
+template <>
+struct Vec16<double> {
+    using type = v2d;
+    static constexpr int n = 2;
+};
+
+// workgroups go to the dies round-robin; give each die a contiguous range of
+// row tiles so that the rows it gathers for stay in its L2 (grid multiple of 8)
+__device__ __forceinline__ int logical_block() {
+    const int per = gridDim.x / kXcd;
+    return (blockIdx.x % kXcd) * per + blockIdx.x / kXcd;
+}
+
+int round8(int b) { return (b + kXcd - 1) / kXcd * kXcd; }
+
+template <class VT, class T>
+__device__ __forceinline__ VT ld16(const T* p) {
+    return *reinterpret_cast<const VT*>(p);
+}
+
+template <class VT, class T>
+__device__ __forceinline__ void st16(T* p, const VT& v) {
+    *reinterpret_cast<VT*>(p) = v;
+}
+
+// acc[0..V) += (double) v
+__device__ __forceinline__ void add_to_fp64(double* acc, const v4f& v) {
+    v2d a = ld16<v2d>(acc), b = ld16<v2d>(acc + 2);
+    a.x += (double)v.x;
+    a.y += (double)v.y;
+    b.x += (double)v.z;
+    b.y += (double)v.w;
+    st16(acc, a);
+    st16(acc + 2, b);
+}
+
+__device__ __forceinline__ void add_to_fp64(double* acc, const v2d& v) {
+    v2d a = ld16<v2d>(acc);
+    a += v;
+    st16(acc, a);
+}
+
+// s = sum_p a_ip G[j_p, c0 .. c0+V) over the row [beg, end), two independent
+// accumulation chains so that two gathers are in flight per lane
+template <class T, int K>
+__device__ __forceinline__ typename Vec16<T>::type row_gather_sum(const CsrT<T>& a, const T* __restrict__ g,
+                                                                  int beg, int end, int c0) {
+    using VT = typename Vec16<T>::type;
+    VT s0{}, s1{};
+    int p = beg;
+    for (; p + 1 < end; p += 2) {
+        const int j0 = a.ci[p], j1 = a.ci[p + 1];
+        const T v0 = a.v[p], v1 = a.v[p + 1];
+        const VT g0 = ld16<VT>(g + j0 * K + c0);
+        const VT g1 = ld16<VT>(g + j1 * K + c0);
+        s0 += v0 * g0;
+        s1 += v1 * g1;
+    }
+    if (p < end) s0 += a.v[p] * ld16<VT>(g + a.ci[p] * K + c0);
+    return s0 + s1;
+}
+
+template <class T, int K, int OP>
+__global__ __launch_bounds__(kBlk) void block_row_kernel(CsrT<T> a, const T* __restrict__ g, const T* u,
+                                                         const T* __restrict__ dinv, T omega, T* y,
+                                                         T* __restrict__ y2, double* acc, int ntiles) {
+    using VT = typename Vec16<T>::type;
+    constexpr int V = Vec16<T>::n;
+    constexpr int LPR = K / V;          // lanes per row
+    constexpr int RPT = kBlk / LPR;     // rows per tile
+    const int lb = logical_block();
+    const int sub = threadIdx.x / LPR;
+    const int c0 = (threadIdx.x % LPR) * V;
+    for (int t = lb; t < ntiles; t += gridDim.x) {
+        const int i = t * RPT + sub;
+        if (i >= a.rows) break;
+        const VT s = row_gather_sum<T, K>(a, g, a.rp[i], a.rp[i + 1], c0);
+        const int o = i * K + c0;
+        if constexpr (OP == kBSpmv) {
+            st16(y + o, s);
+        } else if constexpr (OP == kBSpmvScale) {
+            st16(y + o, s);
+            st16(y2 + o, omega * (dinv[i] * s));
+        } else if constexpr (OP == kBSpmvAdd) {
+            st16(y + o, ld16<VT>(u + o) + s);
+        } else if constexpr (OP == kBResid) {
+            st16(y + o, ld16<VT>(u + o) - s);
+        } else {
+            const VT xn = ld16<VT>(g + o) + omega * dinv[i] * (ld16<VT>(u + o) - s);
+            if constexpr (OP == kBJacobi) st16(y + o, xn);
+            else add_to_fp64(acc + o, xn);
+        }
+    }
+}
+
+// Per-column sums over a workgroup.  Each thread holds V consecutive columns
+// c0..c0+V-1 of its rows; threads holding the same columns are LPR = K / V
+// lanes apart.  Writes partials[lb * K + c] (fixed reduction order).
+template <int K, int V>
+__device__ __forceinline__ void store_column_partials(double (&v)[V], double* __restrict__ partials, int lb) {
+    constexpr int LPR = K / V;
+    __shared__ double lds[kBlk / 64][K];
+#pragma unroll
+    for (int off = LPR; off < 64; off <<= 1)
+#pragma unroll
+        for (int e = 0; e < V; ++e) v[e] += __shfl_xor(v[e], off, 64);
+    const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+    if (lane < LPR)
+#pragma unroll
+        for (int e = 0; e < V; ++e) lds[w][lane * V + e] = v[e];
+    __syncthreads();
+    if ((int)threadIdx.x < K) {
+        double tot = lds[0][threadIdx.x];
+#pragma unroll
+        for (int k = 1; k < kBlk / 64; ++k) tot += lds[k][threadIdx.x];
+        partials[lb * K + threadIdx.x] = tot;
+    }
+}
+
+// r = b - A x in FP64 for K columns; rt = (T) r, zt = omega dinvt rt, and r
+// itself when r64 is not null; per workgroup partial sums of r_c^2 per
+// column into partials[lb * K + c]
+template <class T, int K>
+__global__ __launch_bounds__(kBlk) void block_outer_kernel(CsrView a, const double* __restrict__ x,
+                                                           const double* __restrict__ b,
+                                                           const T* __restrict__ dinvt, T omega,
+                                                           T* __restrict__ rt, T* __restrict__ zt,
+                                                           double* __restrict__ r64,
+                                                           double* __restrict__ partials, int ntiles) {
+    constexpr int LPR = K / 2;
+    constexpr int RPT = kBlk / LPR;
+    const int lb = logical_block();
+    const int sub = threadIdx.x / LPR;
+    const int c0 = (threadIdx.x % LPR) * 2;
+    double n0 = 0.0, n1 = 0.0;
+    for (int t = lb; t < ntiles; t += gridDim.x) {
+        const int i = t * RPT + sub;
+        if (i >= a.rows) break;
+        const v2d s = row_gather_sum<double, K>(a, x, a.rp[i], a.rp[i + 1], c0);
+        const int o = i * K + c0;
+        const v2d r = ld16<v2d>(b + o) - s;
+        n0 += r.x * r.x;
+        n1 += r.y * r.y;
+        if (r64) st16(r64 + o, r);
+        const T d = dinvt[i];
+        const T r0 = (T)r.x, r1 = (T)r.y;
+        rt[o] = r0;
+        rt[o + 1] = r1;
+        zt[o] = omega * (d * r0);
+        zt[o + 1] = omega * (d * r1);
+    }
+    double nn[2] = {n0, n1};
+    store_column_partials<K, 2>(nn, partials, lb);
+}
+
+// out[c] = sum over workgroups of partials[b * K + c], in a fixed order
+template <int K>
+__global__ __launch_bounds__(kBlk) void block_norm_finish_kernel(int nparts, const double* __restrict__ partials,
+                                                                 double* __restrict__ out) {
+    constexpr int S = kBlk / K;
+    __shared__ double slice[kBlk];
+    const int c = threadIdx.x % K, sl = threadIdx.x / K;
+    double s = 0.0;
+    for (int b = sl; b < nparts; b += S) s += partials[b * K + c];
+    slice[threadIdx.x] = s;
+    __syncthreads();
+    if ((int)threadIdx.x < K) {
+        double t = 0.0;
+        for (int k = 0; k < S; ++k) t += slice[k * K + threadIdx.x];
+        out[threadIdx.x] = t;
+    }
+}
+
+// q = A p (FP64) with per-column partials of p_c . q_c
+template <int K>
+__global__ __launch_bounds__(kBlk) void block_spmv_dot_kernel(CsrView a, const double* __restrict__ p,
+                                                              double* __restrict__ q,
+                                                              double* __restrict__ partials, int ntiles) {
+    constexpr int LPR = K / 2;
+    constexpr int RPT = kBlk / LPR;
+    const int lb = logical_block();
+    const int sub = threadIdx.x / LPR;
+    const int c0 = (threadIdx.x % LPR) * 2;
+    double d[2] = {0.0, 0.0};
+    for (int t = lb; t < ntiles; t += gridDim.x) {
+        const int i = t * RPT + sub;
+        if (i >= a.rows) break;
+        const v2d s = row_gather_sum<double, K>(a, p, a.rp[i], a.rp[i + 1], c0);
+        const int o = i * K + c0;
+        st16(q + o, s);
+        const v2d pi = ld16<v2d>(p + o);
+        d[0] += pi.x * s.x;
+        d[1] += pi.y * s.y;
+    }
+    store_column_partials<K, 2>(d, partials, lb);
+}
+
+// Per-column CG update of x and r (FP64): alpha_c = scal[i_num+c] /
+// scal[i_den+c] for the columns with scal[i_act+c] != 0; a column whose
+// denominator is not positive and finite is left unchanged and raises *flag.
+// Also rt = (T) r, zt = omega dinvt rt (the preconditioner's right-hand side
+// and first sweep) and partials of |r_c|^2.
+template <class T, int K>
+__global__ __launch_bounds__(kBlk) void block_cg_xr_kernel(int n, double* __restrict__ x, double* __restrict__ r,
+                                                           const double* __restrict__ p,
+                                                           const double* __restrict__ q,
+                                                           const double* __restrict__ scal, int i_num, int i_den,
+                                                           int i_act, double* flag, const T* __restrict__ dinvt,
+                                                           T omega, T* __restrict__ rt, T* __restrict__ zt,
+                                                           double* __restrict__ partials, int ntiles) {
+    constexpr int LPR = K / 2;
+    constexpr int RPT = kBlk / LPR;
+    const int lb = logical_block();
+    const int sub = threadIdx.x / LPR;
+    const int c0 = (threadIdx.x % LPR) * 2;
+    double alpha[2];
+    bool upd[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const double num = scal[i_num + c0 + e], den = scal[i_den + c0 + e];
+        const bool act = scal[i_act + c0 + e] != 0.0;
+        const bool ok = den > 0.0 && isfinite(den);
+        upd[e] = act && ok;
+        alpha[e] = upd[e] ? num / den : 0.0;
+        if (act && !ok && blockIdx.x == 0 && threadIdx.x < LPR) *flag = 1.0;
+    }
+    double nr[2] = {0.0, 0.0};
+    for (int t = lb; t < ntiles; t += gridDim.x) {
+        const int i = t * RPT + sub;
+        if (i >= n) break;
+        const int o = i * K + c0;
+        v2d xi = ld16<v2d>(x + o), ri = ld16<v2d>(r + o);
+        if (upd[0] || upd[1]) {
+            // frozen columns keep x and r bit for bit (p may hold anything there)
+            const v2d pi = ld16<v2d>(p + o), qi = ld16<v2d>(q + o);
+            if (upd[0]) {
+                xi.x = xi.x + alpha[0] * pi.x;
+                ri.x = ri.x - alpha[0] * qi.x;
+            }
+            if (upd[1]) {
+                xi.y = xi.y + alpha[1] * pi.y;
+                ri.y = ri.y - alpha[1] * qi.y;
+            }
+            st16(x + o, xi);
+            st16(r + o, ri);
+        }
+        nr[0] += ri.x * ri.x;
+        nr[1] += ri.y * ri.y;
+        const T d = dinvt[i];
+        const T r0 = (T)ri.x, r1 = (T)ri.y;
+        rt[o] = r0;
+        rt[o + 1] = r1;
+        zt[o] = omega * (d * r0);
+        zt[o + 1] = omega * (d * r1);
+    }
+    store_column_partials<K, 2>(nr, partials, lb);
+}
+
+// p = z + beta_c p with beta_c = scal[i_num+c] / scal[i_den+c] for the
+// columns with scal[i_act+c] != 0; on a restart p = z in every column
+template <int K>
+__global__ __launch_bounds__(kBlk) void block_cg_p_kernel(int n, double* __restrict__ p,
+                                                          const double* __restrict__ z,
+                                                          const double* __restrict__ scal, int i_num, int i_den,
+                                                          int i_act, int restart) {
+    constexpr int LPR = K / 2;
+    constexpr int RPT = kBlk / LPR;
+    const int sub = threadIdx.x / LPR;
+    const int c0 = (threadIdx.x % LPR) * 2;
+    double beta[2];
+    bool act[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        act[e] = scal[i_act + c0 + e] != 0.0;
+        beta[e] = restart ? 0.0 : scal[i_num + c0 + e] / scal[i_den + c0 + e];
+    }
+    const int ntiles = (n + RPT - 1) / RPT;
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int i = t * RPT + sub;
+        if (i >= n) break;
+        const int o = i * K + c0;
+        const v2d zi = ld16<v2d>(z + o);
+        v2d pi = ld16<v2d>(p + o);
+        if (restart || act[0]) pi.x = restart ? zi.x : zi.x + beta[0] * pi.x;
+        if (restart || act[1]) pi.y = restart ? zi.y : zi.y + beta[1] * pi.y;
+        st16(p + o, pi);
+    }
+}
+
+// Last level-0 sweep of the preconditioner: z64 = (double)(G + omega dinv
+// (U - A G)) with per-column partials of r64_c . z64_c
+template <class T, int K>
+__global__ __launch_bounds__(kBlk) void block_sweep_widen_dot_kernel(CsrT<T> a, const T* __restrict__ g,
+                                                                     const T* __restrict__ u,
+                                                                     const T* __restrict__ dinv, T omega,
+                                                                     double* __restrict__ z64,
+                                                                     const double* __restrict__ r64,
+                                                                     double* __restrict__ partials, int ntiles) {
+    using VT = typename Vec16<T>::type;
+    constexpr int V = Vec16<T>::n;
+    constexpr int LPR = K / V;
+    constexpr int RPT = kBlk / LPR;
+    const int lb = logical_block();
+    const int sub = threadIdx.x / LPR;
+    const int c0 = (threadIdx.x % LPR) * V;
+    double d[V];
+#pragma unroll
+    for (int e = 0; e < V; ++e) d[e] = 0.0;
+    for (int t = lb; t < ntiles; t += gridDim.x) {
+        const int i = t * RPT + sub;
+        if (i >= a.rows) break;
+        const VT s = row_gather_sum<T, K>(a, g, a.rp[i], a.rp[i + 1], c0);
+        const int o = i * K + c0;
+        const VT xn = ld16<VT>(g + o) + omega * dinv[i] * (ld16<VT>(u + o) - s);
+#pragma unroll
+        for (int e = 0; e < V; e += 2) {
+            const v2d ze = {(double)xn[e], (double)xn[e + 1]};
+            st16(z64 + o + e, ze);
+            const v2d re = ld16<v2d>(r64 + o + e);
+            d[e] += re.x * ze.x;
+            d[e + 1] += re.y * ze.y;
+        }
+    }
+    store_column_partials<K, V>(d, partials, lb);
+}
+
+// z64 = (double) x with partials of r64_c . z64_c (a cycle without post-smoothing)
+template <class T, int K>
+__global__ __launch_bounds__(kBlk) void block_widen_dot_kernel(int n, const T* __restrict__ x,
+                                                               double* __restrict__ z64,
+                                                               const double* __restrict__ r64,
+                                                               double* __restrict__ partials, int ntiles) {
+    constexpr int LPR = K / 2;
+    constexpr int RPT = kBlk / LPR;
+    const int lb = logical_block();
+    const int sub = threadIdx.x / LPR;
+    const int c0 = (threadIdx.x % LPR) * 2;
+    double d[2] = {0.0, 0.0};
+    for (int t = lb; t < ntiles; t += gridDim.x) {
+        const int i = t * RPT + sub;
+        if (i >= n) break;
+        const int o = i * K + c0;
+        const v2d ze = {(double)x[o], (double)x[o + 1]};
+        st16(z64 + o, ze);
+        const v2d re = ld16<v2d>(r64 + o);
+        d[0] += re.x * ze.x;
+        d[1] += re.y * ze.y;
+    }
+    store_column_partials<K, 2>(d, partials, lb);
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlk) void block_dense_kernel(int n, int k, const double* __restrict__ ainv,
+                                                           const T* __restrict__ b, T* __restrict__ y) {
+    const int idx = blockIdx.x * kBlk + threadIdx.x;
+    if (idx >= n * k) return;
+    const int i = idx / k, c = idx % k;
+    const double* row = ainv + (size_t)i * n;
+    double s = 0.0;
+    for (int j = 0; j < n; ++j) s += row[j] * (double)b[j * k + c];
+    y[idx] = (T)s;
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlk) void block_accumulate_kernel(int64_t count, double* __restrict__ x,
+                                                                const T* __restrict__ e) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x; i < count; i += (int64_t)gridDim.x * kBlk)
+        x[i] = x[i] + (double)e[i];
+}
+
+__global__ __launch_bounds__(kBlk) void block_pack_kernel(int n, int nrhs, int k, const double* __restrict__ src,
+                                                          double* __restrict__ dst) {
+    const int64_t total = (int64_t)n * k;
+    for (int64_t q = (int64_t)blockIdx.x * kBlk + threadIdx.x; q < total; q += (int64_t)gridDim.x * kBlk) {
+        const int64_t i = q / k;
+        const int c = (int)(q % k);
+        dst[q] = c < nrhs ? src[i * nrhs + c] : 0.0;
+    }
+}
+
+__global__ __launch_bounds__(kBlk) void block_unpack_kernel(int n, int nrhs, int k, const double* __restrict__ src,
+                                                            double* __restrict__ dst) {
+    const int64_t total = (int64_t)n * nrhs;
+    for (int64_t q = (int64_t)blockIdx.x * kBlk + threadIdx.x; q < total; q += (int64_t)gridDim.x * kBlk) {
+        const int64_t i = q / nrhs;
+        const int c = (int)(q % nrhs);
+        dst[q] = src[i * k + c];
+    }
+}
+
+int elem_grid(int64_t count) {
+    return (int)std::max<int64_t>(1, std::min<int64_t>(2048, (count + kBlk - 1) / kBlk));
+}
+
+template <class T, int K>
+void block_op_k(BlockOp op, const CsrT<T>& a, const T* g, const T* u, const T* dinv, T omega, T* y, T* y2,
+                double* acc, hipStream_t st) {
+    constexpr int LPR = K / Vec16<T>::n;
+    constexpr int RPT = kBlk / LPR;
+    const int ntiles = std::max(1, (a.rows + RPT - 1) / RPT);
+    const int grid = round8(std::min(ntiles, kGridCap));
+    switch (op) {
+#define AMG_BLOCK_CASE(OPV)                                                                             \
+    case OPV:                                                                                           \
+        hipLaunchKernelGGL((block_row_kernel<T, K, OPV>), dim3(grid), dim3(kBlk), 0, st, a, g, u, dinv, \
+                           omega, y, y2, acc, ntiles);                                                  \
+        break;
+        AMG_BLOCK_CASE(kBSpmv)
+        AMG_BLOCK_CASE(kBSpmvScale)
+        AMG_BLOCK_CASE(kBSpmvAdd)
+        AMG_BLOCK_CASE(kBResid)
+        AMG_BLOCK_CASE(kBJacobi)
+        AMG_BLOCK_CASE(kBJacobiAccum)
+#undef AMG_BLOCK_CASE
+        default: break;
+    }
+}
+
+template <class T>
+void block_op(BlockOp op, int k, const CsrT<T>& a, const T* g, const T* u, const T* dinv, T omega, T* y,
+              T* y2, double* acc, hipStream_t st) {
+    if (k == 4) block_op_k<T, 4>(op, a, g, u, dinv, omega, y, y2, acc, st);
+    else if (k == 8) block_op_k<T, 8>(op, a, g, u, dinv, omega, y, y2, acc, st);
+    else block_op_k<T, 16>(op, a, g, u, dinv, omega, y, y2, acc, st);
+}
+
+// launch shape of the kernels that give a row K * 8 / 16 lanes (FP64 columns)
+template <int K>
+int fp64_tiles(int rows) {
+    constexpr int RPT = kBlk / (K / 2);
+    return std::max(1, (rows + RPT - 1) / RPT);
+}
+
+template <int K>
+void finish(int grid, const ColumnDots& dot, hipStream_t st) {
+    hipLaunchKernelGGL((block_norm_finish_kernel<K>), dim3(1), dim3(kBlk), 0, st, grid, dot.partials, dot.result);
+}
+
+// calls f.template operator()<K>() with the compile-time width
+template <class F>
+void with_width(int k, F&& f) {
+    if (k == 4) f.template operator()<4>();
+    else if (k == 8) f.template operator()<8>();
+    else f.template operator()<16>();
+}
+
+template <class T>
+void outer(int k, const CsrView& a, const double* x, const double* b, const T* dinvt, T omega, T* rt, T* zt,
+           double* r64, ColumnDots dot, hipStream_t st) {
+    with_width(k, [&]<int K>() {
+        const int ntiles = fp64_tiles<K>(a.rows);
+        const int grid = round8(std::min(ntiles, kGridCap));
+        hipLaunchKernelGGL((block_outer_kernel<T, K>), dim3(grid), dim3(kBlk), 0, st, a, x, b, dinvt, omega, rt,
+                           zt, r64, dot.partials, ntiles);
+        finish<K>(grid, dot, st);
+    });
+}
+
+template <class T>
+void cg_xr(int n, int k, double* x, double* r, const double* p, const double* q, const double* scal, int i_num,
+           int i_den, int i_act, double* flag, const T* dinvt, T omega, T* rt, T* zt, ColumnDots norms,
+           hipStream_t st) {
+    with_width(k, [&]<int K>() {
+        const int ntiles = fp64_tiles<K>(n);
+        const int grid = round8(std::min(ntiles, kGridCap));
+        hipLaunchKernelGGL((block_cg_xr_kernel<T, K>), dim3(grid), dim3(kBlk), 0, st, n, x, r, p, q, scal, i_num,
+                           i_den, i_act, flag, dinvt, omega, rt, zt, norms.partials, ntiles);
+        finish<K>(grid, norms, st);
+    });
+}
+
+template <class T>
+void sweep_widen_dot(int k, const CsrT<T>& a, const T* g, const T* u, const T* dinv, T omega, double* z64,
+                     const double* r64, ColumnDots dot, hipStream_t st) {
+    with_width(k, [&]<int K>() {
+        constexpr int RPT = kBlk / (K / Vec16<T>::n);
+        const int ntiles = std::max(1, (a.rows + RPT - 1) / RPT);
+        const int grid = round8(std::min(ntiles, kGridCap));
+        hipLaunchKernelGGL((block_sweep_widen_dot_kernel<T, K>), dim3(grid), dim3(kBlk), 0, st, a, g, u, dinv,
+                           omega, z64, r64, dot.partials, ntiles);
+        finish<K>(grid, dot, st);
+    });
+}
+
+template <class T>
+void widen_dot(int n, int k, const T* x, double* z64, const double* r64, ColumnDots dot, hipStream_t st) {
+    with_width(k, [&]<int K>() {
+        const int ntiles = fp64_tiles<K>(n);
+        const int grid = round8(std::min(ntiles, kGridCap));
+        hipLaunchKernelGGL((block_widen_dot_kernel<T, K>), dim3(grid), dim3(kBlk), 0, st, n, x, z64, r64,
+                           dot.partials, ntiles);
+        finish<K>(grid, dot, st);
+    });
+}
+
+}  // namespace
+
+int block_width(int nrhs) { return nrhs <= 4 ? 4 : (nrhs <= 8 ? 8 : 16); }
+
+int block_partials_needed() { return kGridCap * 16; }
+
+void launch_block_op(BlockOp op, int k, const CsrT<double>& a, const double* g, const double* u,
+                     const double* dinv, double omega, double* y, double* y2, double* acc, hipStream_t st) {
+    block_op<double>(op, k, a, g, u, dinv, omega, y, y2, acc, st);
+}
+
+void launch_block_op(BlockOp op, int k, const CsrT<float>& a, const float* g, const float* u,
+                     const float* dinv, float omega, float* y, float* y2, double* acc, hipStream_t st) {
+    block_op<float>(op, k, a, g, u, dinv, omega, y, y2, acc, st);
+}
+
+void launch_block_outer_residual(int k, const CsrView& a, const double* x, const double* b,
+                                 const double* dinvt, double omega, double* rt, double* zt, double* r64,
+                                 ColumnDots norms2, hipStream_t st) {
+    outer<double>(k, a, x, b, dinvt, omega, rt, zt, r64, norms2, st);
+}
+
+void launch_block_outer_residual(int k, const CsrView& a, const double* x, const double* b,
+                                 const float* dinvt, float omega, float* rt, float* zt, double* r64,
+                                 ColumnDots norms2, hipStream_t st) {
+    outer<float>(k, a, x, b, dinvt, omega, rt, zt, r64, norms2, st);
+}
+
+void launch_block_spmv_dot(int k, const CsrView& a, const double* p, double* q, ColumnDots dot, hipStream_t st) {
+    with_width(k, [&]<int K>() {
+        const int ntiles = fp64_tiles<K>(a.rows);
+        const int grid = round8(std::min(ntiles, kGridCap));
+        hipLaunchKernelGGL((block_spmv_dot_kernel<K>), dim3(grid), dim3(kBlk), 0, st, a, p, q, dot.partials,
+                           ntiles);
+        finish<K>(grid, dot, st);
+    });
+}
+
+void launch_block_cg_update_xr(int n, int k, double* x, double* r, const double* p, const double* q,
+                               const double* scal, int i_num, int i_den, int i_act, double* flag,
+                               const double* dinvt, double omega, double* rt, double* zt, ColumnDots norms,
+                               hipStream_t st) {
+    cg_xr<double>(n, k, x, r, p, q, scal, i_num, i_den, i_act, flag, dinvt, omega, rt, zt, norms, st);
+}
+
+void launch_block_cg_update_xr(int n, int k, double* x, double* r, const double* p, const double* q,
+                               const double* scal, int i_num, int i_den, int i_act, double* flag,
+                               const float* dinvt, float omega, float* rt, float* zt, ColumnDots norms,
+                               hipStream_t st) {
+    cg_xr<float>(n, k, x, r, p, q, scal, i_num, i_den, i_act, flag, dinvt, omega, rt, zt, norms, st);
+}
+
+void launch_block_cg_update_p(int n, int k, double* p, const double* z, const double* scal, int i_num,
+                              int i_den, int i_act, bool restart, hipStream_t st) {
+    with_width(k, [&]<int K>() {
+        const int grid = std::min(fp64_tiles<K>(n), kGridCap);
+        hipLaunchKernelGGL((block_cg_p_kernel<K>), dim3(grid), dim3(kBlk), 0, st, n, p, z, scal, i_num, i_den,
+                           i_act, restart ? 1 : 0);
+    });
+}
+
+void launch_block_sweep_widen_dot(int k, const CsrT<double>& a, const double* g, const double* u,
+                                  const double* dinv, double omega, double* z64, const double* r64,
+                                  ColumnDots dot, hipStream_t st) {
+    sweep_widen_dot<double>(k, a, g, u, dinv, omega, z64, r64, dot, st);
+}
+
+void launch_block_sweep_widen_dot(int k, const CsrT<float>& a, const float* g, const float* u,
+                                  const float* dinv, float omega, double* z64, const double* r64,
+                                  ColumnDots dot, hipStream_t st) {
+    sweep_widen_dot<float>(k, a, g, u, dinv, omega, z64, r64, dot, st);
+}
+
+void launch_block_widen_dot(int n, int k, const double* x, double* z64, const double* r64, ColumnDots dot,
+                            hipStream_t st) {
+    widen_dot<double>(n, k, x, z64, r64, dot, st);
+}
+
+void launch_block_widen_dot(int n, int k, const float* x, double* z64, const double* r64, ColumnDots dot,
+                            hipStream_t st) {
+    widen_dot<float>(n, k, x, z64, r64, dot, st);
+}
+
+void launch_block_dense_matvec(int n, int k, const double* ainv, const double* b, double* y,
+                               hipStream_t st) {
+    hipLaunchKernelGGL(block_dense_kernel<double>, dim3((n * k + kBlk - 1) / kBlk), dim3(kBlk), 0, st, n, k,
+                       ainv, b, y);
+}
+
+void launch_block_dense_matvec(int n, int k, const double* ainv, const float* b, float* y, hipStream_t st) {
+    hipLaunchKernelGGL(block_dense_kernel<float>, dim3((n * k + kBlk - 1) / kBlk), dim3(kBlk), 0, st, n, k,
+                       ainv, b, y);
+}
+
+void launch_block_accumulate(int64_t count, double* x, const float* e, hipStream_t st) {
+    hipLaunchKernelGGL(block_accumulate_kernel<float>, dim3(elem_grid(count)), dim3(kBlk), 0, st, count, x, e);
+}
+
+void launch_block_accumulate(int64_t count, double* x, const double* e, hipStream_t st) {
+    hipLaunchKernelGGL(block_accumulate_kernel<double>, dim3(elem_grid(count)), dim3(kBlk), 0, st, count, x, e);
+}
+
+void launch_block_pack(int n, int nrhs, int k, const double* src, double* dst, hipStream_t st) {
+    hipLaunchKernelGGL(block_pack_kernel, dim3(elem_grid((int64_t)n * k)), dim3(kBlk), 0, st, n, nrhs, k, src,
+                       dst);
+}
+
+void launch_block_unpack(int n, int nrhs, int k, const double* src, double* dst, hipStream_t st) {
+    hipLaunchKernelGGL(block_unpack_kernel, dim3(elem_grid((int64_t)n * nrhs)), dim3(kBlk), 0, st, n, nrhs, k,
+                       src, dst);
+}
+
+}  // namespace amg355
