@@ -34,10 +34,12 @@ extern "C" {
 #endif
 
 typedef struct amg_ctx* amg_handle;
+typedef struct amg_batch_ctx* amg_batch;
 
 typedef enum {
     AMG_OK = 0,
     AMG_NOTHING_TO_REINTRODUCE = 1, /* informational: every coarse gamma is already 0 */
+    AMG_NOT_READY = 2,              /* informational: amg_batch_poll without waiting, step still running */
     AMG_ERR_INVALID_ARG = -1,       /* NULL pointer, n <= 0, gamma NaN or outside [0,1], bad params */
     AMG_ERR_BAD_MATRIX = -2,        /* unsorted/duplicate/out-of-range column, missing or
                                        non-positive diagonal, non-finite value, not bitwise symmetric */
@@ -243,6 +245,65 @@ enum {
 amg_status amg_profile_enable(amg_handle h, int32_t enable, int32_t kernel_class, int32_t level);
 amg_status amg_profile_read(amg_handle h, int32_t kernel_class, int32_t level, int64_t* count,
                             double* total_ms);
+
+/* ---- continuous batching -------------------------------------------------
+   A batch engine serves a stream of right-hand sides on one hierarchy: up to
+   `slots` (4, 8 or 16) of them are solved together by PCG (Section 5, with
+   the Section 2 V-cycle as the preconditioner, one CG recurrence per slot and
+   every kernel launch shared by all slots), and a slot that finishes can take
+   a new right-hand side at the next step while the others keep iterating.  A
+   slot's arithmetic does not depend on the other slots or on which slot it
+   occupies: its result is bitwise the one amg_solve_block (method PCG, same
+   slot count and precision, x0 = 0) gives for that right-hand side.  All
+   device work goes to the handle's stream.  While a batch exists, the
+   handle's solve, cycle and sparsify entry points return AMG_ERR_STATE. */
+
+/* Device bytes amg_batch_create would allocate for this handle (block work
+   space, CG vectors, FP32 copies of the hierarchy if not made yet). */
+amg_status amg_batch_bytes(amg_handle h, int32_t slots, int32_t precision, int64_t* bytes);
+
+/* Creates the batch engine of h.  precision 32: the V-cycle in FP32 (values,
+   vectors, accumulation) preconditioning FP64 CG; 64: all FP64.  A slot
+   finishes when ||r|| <= rtol ||b|| (x0 = 0) or after maxit iterations.
+   AMG_ERR_STATE if h already has a batch. */
+amg_status amg_batch_create(amg_handle h, int32_t slots, int32_t precision, double rtol, int32_t maxit,
+                            amg_batch* out);
+
+/* Copies rhs (device, n doubles) into a free slot; its solve starts at the
+   next step.  *slot receives the slot index.  AMG_ERR_STATE if no slot is
+   free (a finished slot is free again after amg_batch_collect). */
+amg_status amg_batch_submit(amg_batch b, const double* rhs, int32_t* slot);
+
+/* Enqueues one iteration of every active slot (starting the submitted ones)
+   and returns without waiting; *launched (nullable) = 0 if no slot had work.
+   AMG_ERR_STATE if the previous step has not been completed by
+   amg_batch_poll. */
+amg_status amg_batch_step(amg_batch b, int32_t* launched);
+
+/* Completes the last step: wait != 0 blocks until it has run; wait == 0
+   returns AMG_NOT_READY if it is still running.  finished (nullable, host,
+   slots entries) receives 1 for each slot that finished in this step
+   (converged, broke down or reached maxit).  AMG_OK if no step was pending. */
+amg_status amg_batch_poll(amg_batch b, int32_t wait, int32_t* finished);
+
+/* Copies the solution of a finished slot into x (device, n doubles; enqueued
+   on the handle's stream) and frees the slot.  iters, relres (the CG
+   residual ratio ||r||/||b|| when it stopped) and status (AMG_OK,
+   AMG_ERR_NOT_CONVERGED or AMG_ERR_BREAKDOWN) are nullable.  AMG_ERR_STATE
+   if the slot has not finished. */
+amg_status amg_batch_collect(amg_batch b, int32_t slot, double* x, int32_t* iters, double* relres,
+                             int32_t* status);
+
+/* Per-slot state (host, slots entries): 0 free, 1 submitted, 2 iterating,
+   3 finished and not yet collected. */
+amg_status amg_batch_slots(amg_batch b, int32_t* state);
+
+/* Waits for pending work, frees the engine and its work space. */
+void amg_batch_destroy(amg_batch b);
+
+/* Device bytes currently allocated by the handle (hierarchy, sparsified
+   operators, FP32 copies, work space). */
+amg_status amg_device_bytes(amg_handle h, int64_t* bytes);
 
 void amg_destroy(amg_handle h);
 const char* amg_status_string(amg_status s);

@@ -22,7 +22,7 @@ import numpy as np
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libamg355.so")
 
-OK, NOTHING_TO_REINTRODUCE = 0, 1
+OK, NOTHING_TO_REINTRODUCE, NOT_READY = 0, 1, 2
 STATIONARY, PCG = 0, 1
 MAT = {"A": 0, "AHAT": 1, "P": 2, "R": 3}
 MASK = {"M": 0, "KEEP": 1}
@@ -36,7 +36,9 @@ KERNEL = {"JACOBI": 0, "JACOBI_ZERO": 1, "RESIDUAL": 2, "RESTRICT": 3, "INTERP":
 ABI_SYMBOLS = (
     "amg_setup_params_default", "amg_solve_params_default", "amg_setup_from_csr",
     "amg_sparsify", "amg_sparsify_levels", "amg_reintroduce", "amg_solve", "amg_vcycle", "amg_vcycle32",
-    "amg_solve_block", "amg_vcycle_block", "amg_vcycle_block32", "amg_level_op", "amg_num_levels", "amg_get_level", "amg_export_level", "amg_export_mask",
+    "amg_solve_block", "amg_vcycle_block", "amg_vcycle_block32", "amg_batch_bytes", "amg_batch_create",
+    "amg_batch_submit", "amg_batch_step", "amg_batch_poll", "amg_batch_collect", "amg_batch_slots",
+    "amg_batch_destroy", "amg_device_bytes", "amg_level_op", "amg_num_levels", "amg_get_level", "amg_export_level", "amg_export_mask",
     "amg_export_vector", "amg_export_split", "amg_profile_enable", "amg_profile_read",
     "amg_destroy", "amg_status_string", "amg_last_error",
 )
@@ -92,6 +94,16 @@ def load_library():
     lib.amg_solve_block.argtypes = [vp, i32, vp, vp, P(SolveParams), P(SolveInfo), vp, vp]
     lib.amg_vcycle_block.argtypes = [vp, i32, vp, vp]
     lib.amg_vcycle_block32.argtypes = [vp, i32, vp, vp]
+    lib.amg_batch_bytes.argtypes = [vp, i32, i32, P(i64)]
+    lib.amg_batch_create.argtypes = [vp, i32, i32, f64, i32, P(vp)]
+    lib.amg_batch_submit.argtypes = [vp, vp, P(i32)]
+    lib.amg_batch_step.argtypes = [vp, P(i32)]
+    lib.amg_batch_poll.argtypes = [vp, i32, vp]
+    lib.amg_batch_collect.argtypes = [vp, i32, vp, P(i32), P(f64), P(i32)]
+    lib.amg_batch_slots.argtypes = [vp, vp]
+    lib.amg_batch_destroy.argtypes = [vp]
+    lib.amg_batch_destroy.restype = None
+    lib.amg_device_bytes.argtypes = [vp, P(i64)]
     lib.amg_level_op.argtypes = [vp, i32, i32, vp, vp, vp]
     lib.amg_num_levels.argtypes = [vp, P(i32)]
     lib.amg_get_level.argtypes = [vp, i32, P(i64), P(i64), P(i64), P(i64), P(i64), P(f64), P(i64)]
@@ -109,7 +121,9 @@ def load_library():
     lib.amg_last_error.restype = C.c_char_p
     for name in ("amg_setup_from_csr", "amg_sparsify", "amg_sparsify_levels", "amg_reintroduce",
                  "amg_solve", "amg_vcycle", "amg_vcycle32", "amg_solve_block", "amg_vcycle_block",
-                 "amg_vcycle_block32", "amg_level_op", "amg_num_levels", "amg_get_level",
+                 "amg_vcycle_block32", "amg_batch_bytes", "amg_batch_create", "amg_batch_submit",
+                 "amg_batch_step", "amg_batch_poll", "amg_batch_collect", "amg_batch_slots", "amg_device_bytes",
+                 "amg_level_op", "amg_num_levels", "amg_get_level",
                  "amg_export_level", "amg_export_mask", "amg_export_vector", "amg_export_split",
                  "amg_profile_enable", "amg_profile_read"):
         getattr(lib, name).restype = C.c_int
@@ -230,10 +244,27 @@ class Hierarchy:
         return st
 
     def close(self):
+        b = getattr(self, "_batch", None)
+        if b is not None:
+            b.close()
         h = getattr(self, "_h", None)
         if h is not None and h.value:
             self._lib.amg_destroy(h)
         self._h = None
+
+    def device_bytes(self) -> int:
+        v = C.c_int64()
+        self._check(self._lib.amg_device_bytes(self._h, C.byref(v)))
+        return v.value
+
+    def batch_bytes(self, slots=16, precision=32) -> int:
+        v = C.c_int64()
+        self._check(self._lib.amg_batch_bytes(self._h, int(slots), int(precision), C.byref(v)))
+        return v.value
+
+    def batch(self, slots=16, precision=32, tol=1e-10, maxit=300) -> "Batch":
+        """The continuous-batching engine of this hierarchy (at most one)."""
+        return Batch(self, slots, precision, tol, maxit)
 
     def __del__(self):
         try:
@@ -388,3 +419,70 @@ class Hierarchy:
         self._check(self._lib.amg_profile_read(self._h, KERNEL[kernel], int(level), C.byref(cnt),
                                                C.byref(ms)))
         return cnt.value, ms.value
+
+
+class Batch:
+    """Continuous-batching engine on one hierarchy (amg_batch): up to `slots`
+    right-hand sides are solved together by PCG and a finished slot takes a
+    new right-hand side at the next step."""
+
+    FREE, SUBMITTED, ITERATING, FINISHED = 0, 1, 2, 3
+
+    def __init__(self, hier: Hierarchy, slots=16, precision=32, tol=1e-10, maxit=300):
+        if getattr(hier, "_batch", None) is not None:
+            raise AmgError(-7, "the hierarchy already has a batch engine")
+        self._lib = hier._lib
+        self.hier = hier
+        self.slots = int(slots)
+        self.precision = int(precision)
+        b = C.c_void_p()
+        hier._check(self._lib.amg_batch_create(hier._h, self.slots, self.precision, float(tol), int(maxit),
+                                               C.byref(b)))
+        self._b = b
+        hier._batch = self
+        self._fin = np.zeros(self.slots, np.int32)
+
+    def _check(self, st, allowed=(OK,)):
+        return self.hier._check(st, allowed)
+
+    def close(self):
+        b = getattr(self, "_b", None)
+        if b is not None and b.value:
+            self._lib.amg_batch_destroy(b)
+        self._b = None
+        if getattr(self.hier, "_batch", None) is self:
+            self.hier._batch = None
+
+    def submit(self, rhs) -> int:
+        """Copies rhs (float64 CUDA tensor of n entries) into a free slot."""
+        slot = C.c_int32(-1)
+        self._check(self._lib.amg_batch_submit(self._b, _dptr(rhs, self.hier.n, "rhs"), C.byref(slot)))
+        return slot.value
+
+    def step(self) -> bool:
+        """Enqueues one iteration of every active slot; False if there was no work."""
+        launched = C.c_int32(0)
+        self._check(self._lib.amg_batch_step(self._b, C.byref(launched)))
+        return bool(launched.value)
+
+    def poll(self, wait=True):
+        """Completes the last step: the list of slots that finished in it, or
+        None (wait=False) while it is still running."""
+        st = self._check(self._lib.amg_batch_poll(self._b, int(bool(wait)), self._fin.ctypes.data),
+                         allowed=(OK, NOT_READY))
+        if st == NOT_READY:
+            return None
+        return [int(c) for c in np.nonzero(self._fin)[0]]
+
+    def collect(self, slot: int, x):
+        """Copies a finished slot's solution into x (float64 CUDA tensor, on the
+        hierarchy's stream) and frees the slot: (iterations, relres, status)."""
+        it, rr, st = C.c_int32(), C.c_double(), C.c_int32()
+        self._check(self._lib.amg_batch_collect(self._b, int(slot), _dptr(x, self.hier.n, "x"), C.byref(it),
+                                                C.byref(rr), C.byref(st)))
+        return it.value, rr.value, st.value
+
+    def states(self) -> np.ndarray:
+        out = np.zeros(self.slots, np.int32)
+        self._check(self._lib.amg_batch_slots(self._b, out.ctypes.data))
+        return out

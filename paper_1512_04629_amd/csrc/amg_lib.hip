@@ -50,9 +50,12 @@ constexpr int kCsrPad = 4;
 
 // device scalar slots
 // Block solves use 16 slots per quantity: squared residual norms (S_BLOCK),
-// r.z of two iterations (S_BRZ0, S_BRZ1), p.Ap (S_BPQ), active flags (S_BACT).
+// r.z of two iterations (S_BRZ0, S_BRZ1), p.Ap (S_BPQ), active flags (S_BACT),
+// squared norms of freshly loaded right-hand sides (S_BNR0), load flags
+// (S_BLOAD), breakdown flags (S_BFLAG).
 enum : int { S_RZ0 = 0, S_RZ1 = 1, S_PQ = 2, S_NR2 = 3, S_FLAG = 4, S_NRT = 5, S_DOT = 6, S_BLOCK = 8,
-             S_BRZ0 = 24, S_BRZ1 = 40, S_BPQ = 56, S_BACT = 72, S_COUNT = 88 };
+             S_BRZ0 = 24, S_BRZ1 = 40, S_BPQ = 56, S_BACT = 72, S_BNR0 = 88, S_BLOAD = 104, S_BFLAG = 120,
+             S_COUNT = 136 };
 constexpr int kMaxBlockRhs = 16;
 
 struct DevMat {
@@ -117,6 +120,8 @@ struct PendingEvent {
 
 }  // namespace
 
+struct amg_batch_ctx;
+
 struct amg_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -143,6 +148,7 @@ struct amg_ctx {
     BlockBufs<float> blk32;
     double* blk_partials = nullptr;
     double *blk_b = nullptr, *blk_x = nullptr;   // K-wide copies when nrhs is not a block width
+    amg_batch_ctx* batch = nullptr;              // the continuous-batching engine, if any
     int bcg_k = 0;                               // block CG vectors (FP64, K wide)
     double *bcg_r = nullptr, *bcg_p = nullptr, *bcg_q = nullptr, *bcg_z = nullptr;
     int blk_pack_k = 0;
@@ -1210,7 +1216,7 @@ amg_status solve_block_pcg(amg_ctx* h, int k, int nrhs, const double* b, double*
         upload_active(h, active, k);
         int rz = S_BRZ0;
         precondition(rz);
-        launch_block_cg_update_p(n, k, h->bcg_p, h->bcg_z, h->scal, rz, rz, S_BACT, true, h->stream);
+        launch_block_cg_update_p(n, k, h->bcg_p, h->bcg_z, h->scal, rz, rz, S_BACT, -1, true, h->stream);
         check_launch();
         while (info.iters < p.maxit) {
             {
@@ -1221,14 +1227,15 @@ amg_status solve_block_pcg(amg_ctx* h, int k, int nrhs, const double* b, double*
             {
                 ProfScope ps(h, AMG_K_VECTOR, 0);
                 launch_block_cg_update_xr(n, k, x, h->bcg_r, h->bcg_p, h->bcg_q, h->scal, rz, S_BPQ, S_BACT,
-                                          h->scal + S_FLAG, v0.dinv, omega, bb.rhs, bb.x[0], cols_to(h, S_BLOCK),
-                                          h->stream);
+                                          h->scal + S_BFLAG, v0.dinv, omega, bb.rhs, bb.x[0],
+                                          cols_to(h, S_BLOCK), h->stream);
                 check_launch();
             }
             sc = read_scalars(h);
             info.iters++;
-            if (sc[S_FLAG] != 0.0) { st = AMG_ERR_BREAKDOWN; break; }
             bool bad = false, changed = false;
+            for (int c = 0; c < nrhs; ++c) bad = bad || sc[S_BFLAG + c] != 0.0;
+            if (bad) { st = AMG_ERR_BREAKDOWN; break; }
             for (int c = 0; c < nrhs; ++c) {
                 if (!active[c]) continue;
                 const double nr = std::sqrt(sc[S_BLOCK + c]);
@@ -1248,7 +1255,8 @@ amg_status solve_block_pcg(amg_ctx* h, int k, int nrhs, const double* b, double*
             precondition(next);
             {
                 ProfScope ps(h, AMG_K_VECTOR, 0);
-                launch_block_cg_update_p(n, k, h->bcg_p, h->bcg_z, h->scal, next, rz, S_BACT, false, h->stream);
+                launch_block_cg_update_p(n, k, h->bcg_p, h->bcg_z, h->scal, next, rz, S_BACT, -1, false,
+                                         h->stream);
                 check_launch();
             }
             rz = next;
@@ -1272,6 +1280,179 @@ amg_status solve_block_pcg(amg_ctx* h, int k, int nrhs, const double* b, double*
     if (info_out) *info_out = info;
     prof_collect(h);
     return st;
+}
+
+// ---------------------------------------------------------------------------
+// continuous batching: slots of a block PCG that start and finish on their
+// own while the other slots keep iterating
+// ---------------------------------------------------------------------------
+enum SlotState : int { kSlotFree = 0, kSlotPending = 1, kSlotActive = 2, kSlotDone = 3 };
+
+// device bytes of the FP32 copies ensure_fp32 allocates
+int64_t fp32_mirror_bytes(const amg_ctx* h) {
+    const int L = (int)h->lv.size() - 1;
+    int64_t b = 0;
+    for (int l = 0; l <= L; ++l) {
+        const DevLevel& v = h->lv[l];
+        b += 4 * (v.A.nnz + kCsrPad) + 4 * (int64_t)v.n;
+        if (v.Ahs.rp) b += 4 * (v.A.nnz + kCsrPad);
+        if (l < L) b += 4 * (v.P.nnz + kCsrPad) + 4 * (v.R.nnz + kCsrPad);
+        b += 4 * (int64_t)v.n * (l > 0 ? 4 : 2);
+    }
+    return b + 8 * (int64_t)h->lv[0].n;
+}
+
+// device bytes a batch of k slots allocates beyond the hierarchy
+int64_t batch_bytes(const amg_ctx* h, int k, int precision) {
+    const int64_t vs = precision == 32 ? 4 : 8;
+    const int64_t n0 = h->lv[0].n;
+    int64_t b = 6 * 8 * n0 * k;                          // B, X and the CG vectors r, p, q, z
+    for (size_t l = 0; l < h->lv.size(); ++l)
+        b += vs * k * (int64_t)h->lv[l].n * (l > 0 ? 4 : 3);   // cycle blocks b, x, xt, r
+    b += vs * k * n0 + 8 * (int64_t)block_partials_needed();
+    if (precision == 32 && !h->fp32) b += fp32_mirror_bytes(h);
+    return b;
+}
+
+}  // namespace
+
+struct amg_batch_ctx {
+    amg_ctx* h = nullptr;
+    int k = 0, precision = 32, maxit = 0;
+    double rtol = 0.0;
+    double* B = nullptr;          // n x k right-hand sides of the slots
+    double* X = nullptr;          // n x k iterates
+    double* down = nullptr;       // pinned: the scalar slots after the last step
+    double* up = nullptr;         // pinned: active flags [0, 16), load flags [16, 32)
+    hipEvent_t done = nullptr;
+    bool in_flight = false;
+    int rz = S_BRZ0;
+    int state[kMaxBlockRhs] = {};
+    int iters[kMaxBlockRhs] = {};
+    int status[kMaxBlockRhs] = {};
+    bool loaded[kMaxBlockRhs] = {};   // started by the step in flight
+    double nr0[kMaxBlockRhs] = {};
+    double rel[kMaxBlockRhs] = {};
+};
+
+namespace {
+
+template <class T>
+void batch_step(amg_batch_ctx* e) {
+    amg_ctx* h = e->h;
+    const int k = e->k;
+    BlockBufs<T>& bb = block_bufs(h, (T*)nullptr);
+    DevLevel& f = h->lv[0];
+    const int n = f.n;
+    LevelView<T> v0 = level_view(h, 0, (T*)nullptr);
+    const T omega = (T)h->sp.omega;
+    bool any_load = false;
+    for (int c = 0; c < k; ++c) {
+        e->loaded[c] = e->state[c] == kSlotPending;
+        if (e->loaded[c]) {
+            e->state[c] = kSlotActive;
+            e->iters[c] = 0;
+            any_load = true;
+        }
+        e->up[c] = e->state[c] == kSlotActive ? 1.0 : 0.0;
+        e->up[kMaxBlockRhs + c] = e->loaded[c] ? 1.0 : 0.0;
+    }
+    HIP_CHECK(hipMemcpyAsync(h->scal + S_BACT, e->up, sizeof(double) * k, hipMemcpyHostToDevice, h->stream));
+    HIP_CHECK(hipMemcpyAsync(h->scal + S_BLOAD, e->up + kMaxBlockRhs, sizeof(double) * k, hipMemcpyHostToDevice,
+                             h->stream));
+    launch_fill_f64(k, h->scal + S_BFLAG, 0.0, h->stream);
+    if (any_load) {
+        ProfScope ps(h, AMG_K_VECTOR, 0);
+        launch_block_load_columns(n, k, h->scal, S_BLOAD, e->B, e->X, h->bcg_r, v0.dinv, omega, bb.rhs, bb.x[0],
+                                  cols_to(h, S_BNR0), h->stream);
+        check_launch();
+    }
+    const int next = e->rz == S_BRZ0 ? S_BRZ1 : S_BRZ0;
+    BlockSink sink;
+    sink.z64 = h->bcg_z;
+    sink.r64 = h->bcg_r;
+    sink.dot = cols_to(h, next);
+    vcycle_block<T>(h, k, bb.rhs, Guess::kPrescaled, sink);
+    {
+        ProfScope ps(h, AMG_K_VECTOR, 0);
+        launch_block_cg_update_p(n, k, h->bcg_p, h->bcg_z, h->scal, next, e->rz, S_BACT, S_BLOAD, false,
+                                 h->stream);
+        check_launch();
+    }
+    {
+        ProfScope ps(h, AMG_K_SPMV_DOT, 0);
+        launch_block_spmv_dot(k, f.A.view(), h->bcg_p, h->bcg_q, cols_to(h, S_BPQ), h->stream);
+        check_launch();
+    }
+    {
+        ProfScope ps(h, AMG_K_VECTOR, 0);
+        launch_block_cg_update_xr(n, k, e->X, h->bcg_r, h->bcg_p, h->bcg_q, h->scal, next, S_BPQ, S_BACT,
+                                  h->scal + S_BFLAG, v0.dinv, omega, bb.rhs, bb.x[0], cols_to(h, S_BLOCK),
+                                  h->stream);
+        check_launch();
+    }
+    HIP_CHECK(hipMemcpyAsync(e->down, h->scal, sizeof(double) * S_COUNT, hipMemcpyDeviceToHost, h->stream));
+    HIP_CHECK(hipEventRecord(e->done, h->stream));
+    e->rz = next;
+    e->in_flight = true;
+}
+
+// slot bookkeeping after a completed step
+void batch_finish_step(amg_batch_ctx* e, int32_t* finished) {
+    const double* sc = e->down;
+    for (int c = 0; c < e->k; ++c) {
+        if (finished) finished[c] = 0;
+        if (e->state[c] != kSlotActive) continue;
+        if (e->loaded[c]) {
+            e->nr0[c] = std::sqrt(sc[S_BNR0 + c]);
+            if (e->nr0[c] == 0.0) {
+                // zero right-hand side: the load wrote the exact solution x = 0
+                e->state[c] = kSlotDone;
+                e->status[c] = AMG_OK;
+                e->rel[c] = 0.0;
+                if (finished) finished[c] = 1;
+                continue;
+            }
+        }
+        e->iters[c]++;
+        const double nr = std::sqrt(sc[S_BLOCK + c]);
+        e->rel[c] = nr / e->nr0[c];
+        int st = -100;
+        if (sc[S_BFLAG + c] != 0.0 || !std::isfinite(nr) || !std::isfinite(e->nr0[c])) st = AMG_ERR_BREAKDOWN;
+        else if (nr <= e->rtol * e->nr0[c]) st = AMG_OK;
+        else if (e->iters[c] >= e->maxit) st = AMG_ERR_NOT_CONVERGED;
+        if (st != -100) {
+            e->state[c] = kSlotDone;
+            e->status[c] = st;
+            if (finished) finished[c] = 1;
+        }
+    }
+    e->in_flight = false;
+}
+
+void destroy_batch(amg_batch_ctx* e) {
+    if (!e) return;
+    amg_ctx* h = e->h;
+    if (h) {
+        (void)hipStreamSynchronize(h->stream);
+        dfree(h, e->B);
+        dfree(h, e->X);
+        // the block work space goes with the batch, so that its bytes are free again
+        free_block_bufs(h, h->blk64);
+        free_block_bufs(h, h->blk32);
+        for (double** q : {&h->bcg_r, &h->bcg_p, &h->bcg_q, &h->bcg_z}) {
+            dfree(h, *q);
+            *q = nullptr;
+        }
+        h->bcg_k = 0;
+        dfree(h, h->blk_partials);
+        h->blk_partials = nullptr;
+        h->batch = nullptr;
+    }
+    if (e->down) (void)hipHostFree(e->down);
+    if (e->up) (void)hipHostFree(e->up);
+    if (e->done) (void)hipEventDestroy(e->done);
+    delete e;
 }
 
 // ---------------------------------------------------------------------------
@@ -1349,6 +1530,7 @@ void setup(amg_ctx* h, int64_t n, const int32_t* row_ptr, const int32_t* col, co
 void destroy(amg_ctx* h) {
     if (!h) return;
     (void)hipStreamSynchronize(h->stream);
+    if (h->batch) destroy_batch(h->batch);
     for (auto& d : h->lv) {
         free_mat(h, d.Ahs);
         free_mat(h, d.A);
@@ -1417,7 +1599,7 @@ std::string& setup_error() {
 
 template <class T>
 amg_status vcycle_block_abi(amg_handle h, int32_t nrhs, const T* b, T* x) {
-    if (!h || h->lv.empty()) return AMG_ERR_STATE;
+    if (!h || h->lv.empty() || h->batch) return AMG_ERR_STATE;
     const int64_t n = h->lv[0].n;
     if (!b || !x || (nrhs != 4 && nrhs != 8 && nrhs != 16) || n * nrhs > INT32_MAX ||
         (((uintptr_t)b | (uintptr_t)x) & 15) != 0) {
@@ -1501,7 +1683,7 @@ amg_status amg_setup_from_csr(int64_t n, const int32_t* row_ptr, const int32_t* 
 }
 
 amg_status amg_sparsify(amg_handle h, double gamma, int32_t first_level) {
-    if (!h || h->lv.empty()) return AMG_ERR_STATE;
+    if (!h || h->lv.empty() || h->batch) return AMG_ERR_STATE;
     if (!valid_gamma(gamma) || first_level < 1) {
         h->last_error = "gamma must lie in [0, 1] and first_level must be >= 1";
         return AMG_ERR_INVALID_ARG;
@@ -1516,7 +1698,7 @@ amg_status amg_sparsify(amg_handle h, double gamma, int32_t first_level) {
 }
 
 amg_status amg_sparsify_levels(amg_handle h, const double* gamma, int32_t count) {
-    if (!h || h->lv.empty()) return AMG_ERR_STATE;
+    if (!h || h->lv.empty() || h->batch) return AMG_ERR_STATE;
     if (!gamma || count < 0) return AMG_ERR_INVALID_ARG;
     for (int l = 1; l < count; ++l)
         if (!valid_gamma(gamma[l])) {
@@ -1533,7 +1715,7 @@ amg_status amg_sparsify_levels(amg_handle h, const double* gamma, int32_t count)
 }
 
 amg_status amg_reintroduce(amg_handle h, int32_t s, double gamma_min, int32_t* first_changed_level) {
-    if (!h || h->lv.empty()) return AMG_ERR_STATE;
+    if (!h || h->lv.empty() || h->batch) return AMG_ERR_STATE;
     if (s < 1 || !(gamma_min >= 0.0)) return AMG_ERR_INVALID_ARG;
     return guarded(h, [&] {
         int first = -1;
@@ -1546,7 +1728,7 @@ amg_status amg_reintroduce(amg_handle h, int32_t s, double gamma_min, int32_t* f
 
 amg_status amg_solve(amg_handle h, const double* b, double* x, const amg_solve_params* params,
                      amg_solve_info* info, double* hist) {
-    if (!h || h->lv.empty()) return AMG_ERR_STATE;
+    if (!h || h->lv.empty() || h->batch) return AMG_ERR_STATE;
     if (!b || !x) return AMG_ERR_INVALID_ARG;
     amg_solve_params p;
     amg_solve_params_default(&p);
@@ -1560,7 +1742,7 @@ amg_status amg_solve(amg_handle h, const double* b, double* x, const amg_solve_p
 }
 
 amg_status amg_vcycle(amg_handle h, const double* b, double* x) {
-    if (!h || h->lv.empty()) return AMG_ERR_STATE;
+    if (!h || h->lv.empty() || h->batch) return AMG_ERR_STATE;
     if (!b || !x) return AMG_ERR_INVALID_ARG;
     return guarded(h, [&] {
         vcycle<double>(h, b, x, Guess::kNonzero, -1);
@@ -1570,7 +1752,7 @@ amg_status amg_vcycle(amg_handle h, const double* b, double* x) {
 }
 
 amg_status amg_vcycle32(amg_handle h, const float* b, float* x) {
-    if (!h || h->lv.empty()) return AMG_ERR_STATE;
+    if (!h || h->lv.empty() || h->batch) return AMG_ERR_STATE;
     if (!b || !x) return AMG_ERR_INVALID_ARG;
     return guarded(h, [&] {
         ensure_fp32(h);
@@ -1582,7 +1764,7 @@ amg_status amg_vcycle32(amg_handle h, const float* b, float* x) {
 
 amg_status amg_solve_block(amg_handle h, int32_t nrhs, const double* b, double* x, const amg_solve_params* params,
                            amg_solve_info* info, int32_t* col_iters, double* col_relres) {
-    if (!h || h->lv.empty()) return AMG_ERR_STATE;
+    if (!h || h->lv.empty() || h->batch) return AMG_ERR_STATE;
     amg_solve_params p;
     amg_solve_params_default(&p);
     if (params) p = *params;
@@ -1642,7 +1824,7 @@ amg_status amg_vcycle_block32(amg_handle h, int32_t nrhs, const float* b, float*
 
 amg_status amg_level_op(amg_handle h, int32_t level, int32_t op, const double* in, const double* x,
                         double* out) {
-    if (!h || h->lv.empty()) return AMG_ERR_STATE;
+    if (!h || h->lv.empty() || h->batch) return AMG_ERR_STATE;
     const int L = (int)h->lv.size() - 1;
     if (op == AMG_OP_COARSE_SOLVE) level = L;
     if (level < 0 || level > L || !out) return AMG_ERR_INVALID_ARG;
@@ -1818,12 +2000,163 @@ amg_status amg_profile_read(amg_handle h, int32_t kernel_class, int32_t level, i
     });
 }
 
+amg_status amg_batch_bytes(amg_handle h, int32_t slots, int32_t precision, int64_t* bytes) {
+    if (!h || h->lv.empty()) return AMG_ERR_STATE;
+    if (!bytes || (slots != 4 && slots != 8 && slots != 16) || (precision != 32 && precision != 64))
+        return AMG_ERR_INVALID_ARG;
+    *bytes = batch_bytes(h, slots, precision);
+    return AMG_OK;
+}
+
+amg_status amg_batch_create(amg_handle h, int32_t slots, int32_t precision, double rtol, int32_t maxit,
+                            amg_batch* out) {
+    if (!out) return AMG_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!h || h->lv.empty() || h->batch) return AMG_ERR_STATE;
+    if ((slots != 4 && slots != 8 && slots != 16) || (precision != 32 && precision != 64) || !(rtol >= 0.0) ||
+        maxit < 1 || (int64_t)h->lv[0].n * slots > INT32_MAX) {
+        h->last_error = "invalid batch parameters (slots 4, 8 or 16; precision 32 or 64; maxit >= 1)";
+        return AMG_ERR_INVALID_ARG;
+    }
+    amg_batch_ctx* e = new (std::nothrow) amg_batch_ctx();
+    if (!e) return AMG_ERR_OUT_OF_MEMORY;
+    e->h = h;
+    e->k = slots;
+    e->precision = precision;
+    e->rtol = rtol;
+    e->maxit = maxit;
+    amg_status st = guarded(h, [&] {
+        const int64_t cnt = (int64_t)h->lv[0].n * slots;
+        if (precision == 32) {
+            ensure_fp32(h);
+            ensure_block<float>(h, slots);
+        } else {
+            ensure_block<double>(h, slots);
+        }
+        ensure_block_cg(h, slots);
+        e->B = dalloc_n<double>(h, cnt);
+        e->X = dalloc_n<double>(h, cnt);
+        // p must be finite in every column before its first use
+        launch_fill_f64(cnt, h->bcg_p, 0.0, h->stream);
+        launch_fill_f64(cnt, e->X, 0.0, h->stream);
+        check_launch();
+        HIP_CHECK(hipHostMalloc((void**)&e->down, sizeof(double) * S_COUNT, hipHostMallocDefault));
+        HIP_CHECK(hipHostMalloc((void**)&e->up, sizeof(double) * 2 * kMaxBlockRhs, hipHostMallocDefault));
+        HIP_CHECK(hipEventCreateWithFlags(&e->done, hipEventDisableTiming));
+        h->batch = e;
+        return AMG_OK;
+    });
+    if (st != AMG_OK) {
+        h->batch = e;
+        destroy_batch(e);
+        return st;
+    }
+    *out = e;
+    return AMG_OK;
+}
+
+amg_status amg_batch_submit(amg_batch b, const double* rhs, int32_t* slot) {
+    if (!b) return AMG_ERR_STATE;
+    if (!rhs) return AMG_ERR_INVALID_ARG;
+    amg_ctx* h = b->h;
+    int c = 0;
+    while (c < b->k && b->state[c] != kSlotFree) ++c;
+    if (c == b->k) {
+        h->last_error = "no free slot";
+        return AMG_ERR_STATE;
+    }
+    return guarded(h, [&] {
+        launch_block_column_in(h->lv[0].n, b->k, c, rhs, b->B, h->stream);
+        check_launch();
+        b->state[c] = kSlotPending;
+        b->iters[c] = 0;
+        b->rel[c] = 1.0;
+        if (slot) *slot = c;
+        return AMG_OK;
+    });
+}
+
+amg_status amg_batch_step(amg_batch b, int32_t* launched) {
+    if (!b) return AMG_ERR_STATE;
+    if (launched) *launched = 0;
+    if (b->in_flight) {
+        b->h->last_error = "the previous step has not been completed by amg_batch_poll";
+        return AMG_ERR_STATE;
+    }
+    bool work = false;
+    for (int c = 0; c < b->k; ++c) work = work || b->state[c] == kSlotPending || b->state[c] == kSlotActive;
+    if (!work) return AMG_OK;
+    return guarded(b->h, [&] {
+        if (b->precision == 32) batch_step<float>(b);
+        else batch_step<double>(b);
+        if (launched) *launched = 1;
+        return AMG_OK;
+    });
+}
+
+amg_status amg_batch_poll(amg_batch b, int32_t wait, int32_t* finished) {
+    if (!b) return AMG_ERR_STATE;
+    if (!b->in_flight) {
+        if (finished) std::fill(finished, finished + b->k, 0);
+        return AMG_OK;
+    }
+    return guarded(b->h, [&] {
+        if (wait) {
+            HIP_CHECK(hipEventSynchronize(b->done));
+        } else {
+            const hipError_t q = hipEventQuery(b->done);
+            if (q == hipErrorNotReady) return AMG_NOT_READY;
+            HIP_CHECK(q);
+        }
+        batch_finish_step(b, finished);
+        return AMG_OK;
+    });
+}
+
+amg_status amg_batch_collect(amg_batch b, int32_t slot, double* x, int32_t* iters, double* relres,
+                             int32_t* status) {
+    if (!b) return AMG_ERR_STATE;
+    if (slot < 0 || slot >= b->k || !x) return AMG_ERR_INVALID_ARG;
+    if (b->state[slot] != kSlotDone) {
+        b->h->last_error = "slot has not finished";
+        return AMG_ERR_STATE;
+    }
+    return guarded(b->h, [&] {
+        launch_block_column_out(b->h->lv[0].n, b->k, slot, b->X, x, b->h->stream);
+        check_launch();
+        if (iters) *iters = b->iters[slot];
+        if (relres) *relres = b->rel[slot];
+        if (status) *status = b->status[slot];
+        b->state[slot] = kSlotFree;
+        return AMG_OK;
+    });
+}
+
+amg_status amg_batch_slots(amg_batch b, int32_t* state) {
+    if (!b) return AMG_ERR_STATE;
+    if (!state) return AMG_ERR_INVALID_ARG;
+    for (int c = 0; c < b->k; ++c) state[c] = b->state[c];
+    return AMG_OK;
+}
+
+void amg_batch_destroy(amg_batch b) { destroy_batch(b); }
+
+amg_status amg_device_bytes(amg_handle h, int64_t* bytes) {
+    if (!h || h->lv.empty()) return AMG_ERR_STATE;
+    if (!bytes) return AMG_ERR_INVALID_ARG;
+    int64_t t = 0;
+    for (const auto& kv : h->blocks) t += (int64_t)kv.second;
+    *bytes = t;
+    return AMG_OK;
+}
+
 void amg_destroy(amg_handle h) { destroy(h); }
 
 const char* amg_status_string(amg_status s) {
     switch (s) {
         case AMG_OK: return "ok";
         case AMG_NOTHING_TO_REINTRODUCE: return "nothing to reintroduce: every coarse gamma is 0";
+        case AMG_NOT_READY: return "not ready: the batch step is still running";
         case AMG_ERR_INVALID_ARG: return "invalid argument";
         case AMG_ERR_BAD_MATRIX: return "matrix violates the input contract";
         case AMG_ERR_OUT_OF_MEMORY: return "out of device memory";

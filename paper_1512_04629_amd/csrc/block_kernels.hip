@@ -228,7 +228,7 @@ __global__ __launch_bounds__(kBlk) void block_spmv_dot_kernel(CsrView a, const d
 
 // Per-column CG update of x and r (FP64): alpha_c = scal[i_num+c] /
 // scal[i_den+c] for the columns with scal[i_act+c] != 0; a column whose
-// denominator is not positive and finite is left unchanged and raises *flag.
+// denominator is not positive and finite is left unchanged and sets flags[c] = 1.
 // Also rt = (T) r, zt = omega dinvt rt (the preconditioner's right-hand side
 // and first sweep) and partials of |r_c|^2.
 template <class T, int K>
@@ -236,7 +236,7 @@ __global__ __launch_bounds__(kBlk) void block_cg_xr_kernel(int n, double* __rest
                                                            const double* __restrict__ p,
                                                            const double* __restrict__ q,
                                                            const double* __restrict__ scal, int i_num, int i_den,
-                                                           int i_act, double* flag, const T* __restrict__ dinvt,
+                                                           int i_act, double* flags, const T* __restrict__ dinvt,
                                                            T omega, T* __restrict__ rt, T* __restrict__ zt,
                                                            double* __restrict__ partials, int ntiles) {
     constexpr int LPR = K / 2;
@@ -253,7 +253,7 @@ __global__ __launch_bounds__(kBlk) void block_cg_xr_kernel(int n, double* __rest
         const bool ok = den > 0.0 && isfinite(den);
         upd[e] = act && ok;
         alpha[e] = upd[e] ? num / den : 0.0;
-        if (act && !ok && blockIdx.x == 0 && threadIdx.x < LPR) *flag = 1.0;
+        if (act && !ok && blockIdx.x == 0 && threadIdx.x < LPR) flags[c0 + e] = 1.0;
     }
     double nr[2] = {0.0, 0.0};
     for (int t = lb; t < ntiles; t += gridDim.x) {
@@ -288,23 +288,26 @@ __global__ __launch_bounds__(kBlk) void block_cg_xr_kernel(int n, double* __rest
 }
 
 // p = z + beta_c p with beta_c = scal[i_num+c] / scal[i_den+c] for the
-// columns with scal[i_act+c] != 0; on a restart p = z in every column
+// columns with scal[i_act+c] != 0; p = z (a fresh start) in every column if
+// restart_all, else in the columns with scal[i_restart+c] != 0
 template <int K>
 __global__ __launch_bounds__(kBlk) void block_cg_p_kernel(int n, double* __restrict__ p,
                                                           const double* __restrict__ z,
                                                           const double* __restrict__ scal, int i_num, int i_den,
-                                                          int i_act, int restart) {
+                                                          int i_act, int i_restart, int restart_all) {
     constexpr int LPR = K / 2;
     constexpr int RPT = kBlk / LPR;
     const int sub = threadIdx.x / LPR;
     const int c0 = (threadIdx.x % LPR) * 2;
     double beta[2];
-    bool act[2];
+    bool upd[2], fresh[2];
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
-        act[e] = scal[i_act + c0 + e] != 0.0;
-        beta[e] = restart ? 0.0 : scal[i_num + c0 + e] / scal[i_den + c0 + e];
+        fresh[e] = restart_all || (i_restart >= 0 && scal[i_restart + c0 + e] != 0.0);
+        upd[e] = fresh[e] || scal[i_act + c0 + e] != 0.0;
+        beta[e] = fresh[e] ? 0.0 : scal[i_num + c0 + e] / scal[i_den + c0 + e];
     }
+    if (!upd[0] && !upd[1]) return;
     const int ntiles = (n + RPT - 1) / RPT;
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int i = t * RPT + sub;
@@ -312,10 +315,66 @@ __global__ __launch_bounds__(kBlk) void block_cg_p_kernel(int n, double* __restr
         const int o = i * K + c0;
         const v2d zi = ld16<v2d>(z + o);
         v2d pi = ld16<v2d>(p + o);
-        if (restart || act[0]) pi.x = restart ? zi.x : zi.x + beta[0] * pi.x;
-        if (restart || act[1]) pi.y = restart ? zi.y : zi.y + beta[1] * pi.y;
+        if (upd[0]) pi.x = fresh[0] ? zi.x : zi.x + beta[0] * pi.x;
+        if (upd[1]) pi.y = fresh[1] ? zi.y : zi.y + beta[1] * pi.y;
         st16(p + o, pi);
     }
+}
+
+// A fresh start of the columns with scal[i_load+c] != 0: x_c = 0, r_c = b_c,
+// rt_c = (T) b_c, zt_c = omega dinvt rt_c (the first sweep of the cycle), and
+// per-workgroup partials of |b_c|^2 (same row partition and order as the
+// outer residual, whose norm of b - A 0 they reproduce)
+template <class T, int K>
+__global__ __launch_bounds__(kBlk) void block_load_kernel(int n, const double* __restrict__ scal, int i_load,
+                                                          const double* __restrict__ b, double* __restrict__ x,
+                                                          double* __restrict__ r, const T* __restrict__ dinvt,
+                                                          T omega, T* __restrict__ rt, T* __restrict__ zt,
+                                                          double* __restrict__ partials, int ntiles) {
+    constexpr int LPR = K / 2;
+    constexpr int RPT = kBlk / LPR;
+    const int lb = logical_block();
+    const int sub = threadIdx.x / LPR;
+    const int c0 = (threadIdx.x % LPR) * 2;
+    const bool ld0 = scal[i_load + c0] != 0.0, ld1 = scal[i_load + c0 + 1] != 0.0;
+    double nn[2] = {0.0, 0.0};
+    if (ld0 || ld1) {
+        for (int t = lb; t < ntiles; t += gridDim.x) {
+            const int i = t * RPT + sub;
+            if (i >= n) break;
+            const int o = i * K + c0;
+            const v2d bi = ld16<v2d>(b + o);
+            const T d = dinvt[i];
+            if (ld0) {
+                x[o] = 0.0;
+                r[o] = bi.x;
+                nn[0] += bi.x * bi.x;
+                const T b0 = (T)bi.x;
+                rt[o] = b0;
+                zt[o] = omega * (d * b0);
+            }
+            if (ld1) {
+                x[o + 1] = 0.0;
+                r[o + 1] = bi.y;
+                nn[1] += bi.y * bi.y;
+                const T b1 = (T)bi.y;
+                rt[o + 1] = b1;
+                zt[o + 1] = omega * (d * b1);
+            }
+        }
+    }
+    store_column_partials<K, 2>(nn, partials, lb);
+}
+
+// column c of a K-wide block to / from a plain vector
+__global__ __launch_bounds__(kBlk) void block_column_in_kernel(int n, int k, int c, const double* __restrict__ v,
+                                                               double* __restrict__ blk) {
+    for (int i = blockIdx.x * kBlk + threadIdx.x; i < n; i += gridDim.x * kBlk) blk[(size_t)i * k + c] = v[i];
+}
+
+__global__ __launch_bounds__(kBlk) void block_column_out_kernel(int n, int k, int c, const double* __restrict__ blk,
+                                                                double* __restrict__ v) {
+    for (int i = blockIdx.x * kBlk + threadIdx.x; i < n; i += gridDim.x * kBlk) v[i] = blk[(size_t)i * k + c];
 }
 
 // Last level-0 sweep of the preconditioner: z64 = (double)(G + omega dinv
@@ -489,13 +548,13 @@ void outer(int k, const CsrView& a, const double* x, const double* b, const T* d
 
 template <class T>
 void cg_xr(int n, int k, double* x, double* r, const double* p, const double* q, const double* scal, int i_num,
-           int i_den, int i_act, double* flag, const T* dinvt, T omega, T* rt, T* zt, ColumnDots norms,
+           int i_den, int i_act, double* flags, const T* dinvt, T omega, T* rt, T* zt, ColumnDots norms,
            hipStream_t st) {
     with_width(k, [&]<int K>() {
         const int ntiles = fp64_tiles<K>(n);
         const int grid = round8(std::min(ntiles, kGridCap));
         hipLaunchKernelGGL((block_cg_xr_kernel<T, K>), dim3(grid), dim3(kBlk), 0, st, n, x, r, p, q, scal, i_num,
-                           i_den, i_act, flag, dinvt, omega, rt, zt, norms.partials, ntiles);
+                           i_den, i_act, flags, dinvt, omega, rt, zt, norms.partials, ntiles);
         finish<K>(grid, norms, st);
     });
 }
@@ -563,26 +622,58 @@ void launch_block_spmv_dot(int k, const CsrView& a, const double* p, double* q, 
 }
 
 void launch_block_cg_update_xr(int n, int k, double* x, double* r, const double* p, const double* q,
-                               const double* scal, int i_num, int i_den, int i_act, double* flag,
+                               const double* scal, int i_num, int i_den, int i_act, double* flags,
                                const double* dinvt, double omega, double* rt, double* zt, ColumnDots norms,
                                hipStream_t st) {
-    cg_xr<double>(n, k, x, r, p, q, scal, i_num, i_den, i_act, flag, dinvt, omega, rt, zt, norms, st);
+    cg_xr<double>(n, k, x, r, p, q, scal, i_num, i_den, i_act, flags, dinvt, omega, rt, zt, norms, st);
 }
 
 void launch_block_cg_update_xr(int n, int k, double* x, double* r, const double* p, const double* q,
-                               const double* scal, int i_num, int i_den, int i_act, double* flag,
+                               const double* scal, int i_num, int i_den, int i_act, double* flags,
                                const float* dinvt, float omega, float* rt, float* zt, ColumnDots norms,
                                hipStream_t st) {
-    cg_xr<float>(n, k, x, r, p, q, scal, i_num, i_den, i_act, flag, dinvt, omega, rt, zt, norms, st);
+    cg_xr<float>(n, k, x, r, p, q, scal, i_num, i_den, i_act, flags, dinvt, omega, rt, zt, norms, st);
 }
 
 void launch_block_cg_update_p(int n, int k, double* p, const double* z, const double* scal, int i_num,
-                              int i_den, int i_act, bool restart, hipStream_t st) {
+                              int i_den, int i_act, int i_restart, bool restart_all, hipStream_t st) {
     with_width(k, [&]<int K>() {
         const int grid = std::min(fp64_tiles<K>(n), kGridCap);
         hipLaunchKernelGGL((block_cg_p_kernel<K>), dim3(grid), dim3(kBlk), 0, st, n, p, z, scal, i_num, i_den,
-                           i_act, restart ? 1 : 0);
+                           i_act, i_restart, restart_all ? 1 : 0);
     });
+}
+
+template <class T>
+void load_columns(int n, int k, const double* scal, int i_load, const double* b, double* x, double* r,
+                  const T* dinvt, T omega, T* rt, T* zt, ColumnDots norms, hipStream_t st) {
+    with_width(k, [&]<int K>() {
+        const int ntiles = fp64_tiles<K>(n);
+        const int grid = round8(std::min(ntiles, kGridCap));
+        hipLaunchKernelGGL((block_load_kernel<T, K>), dim3(grid), dim3(kBlk), 0, st, n, scal, i_load, b, x, r,
+                           dinvt, omega, rt, zt, norms.partials, ntiles);
+        finish<K>(grid, norms, st);
+    });
+}
+
+void launch_block_load_columns(int n, int k, const double* scal, int i_load, const double* b, double* x,
+                               double* r, const double* dinvt, double omega, double* rt, double* zt,
+                               ColumnDots norms, hipStream_t st) {
+    load_columns<double>(n, k, scal, i_load, b, x, r, dinvt, omega, rt, zt, norms, st);
+}
+
+void launch_block_load_columns(int n, int k, const double* scal, int i_load, const double* b, double* x,
+                               double* r, const float* dinvt, float omega, float* rt, float* zt,
+                               ColumnDots norms, hipStream_t st) {
+    load_columns<float>(n, k, scal, i_load, b, x, r, dinvt, omega, rt, zt, norms, st);
+}
+
+void launch_block_column_in(int n, int k, int c, const double* v, double* blk, hipStream_t st) {
+    hipLaunchKernelGGL(block_column_in_kernel, dim3(elem_grid(n)), dim3(kBlk), 0, st, n, k, c, v, blk);
+}
+
+void launch_block_column_out(int n, int k, int c, const double* blk, double* v, hipStream_t st) {
+    hipLaunchKernelGGL(block_column_out_kernel, dim3(elem_grid(n)), dim3(kBlk), 0, st, n, k, c, blk, v);
 }
 
 void launch_block_sweep_widen_dot(int k, const CsrT<double>& a, const double* g, const double* u,

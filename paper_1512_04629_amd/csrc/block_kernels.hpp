@@ -68,19 +68,33 @@ void launch_block_outer_residual(int k, const CsrView& a, const double* x, const
 void launch_block_spmv_dot(int k, const CsrView& a, const double* p, double* q, ColumnDots dot, hipStream_t st);
 // alpha_c = scal[i_num+c] / scal[i_den+c]; x += alpha p; r -= alpha q;
 // norms[c] = |r_c|^2; rt = (T) r and zt = omega dinvt rt.  A column whose
-// denominator is not positive and finite is left unchanged and sets *flag = 1.
+// denominator is not positive and finite is left unchanged and sets
+// flags[c] = 1.
 void launch_block_cg_update_xr(int n, int k, double* x, double* r, const double* p, const double* q,
-                               const double* scal, int i_num, int i_den, int i_act, double* flag,
+                               const double* scal, int i_num, int i_den, int i_act, double* flags,
                                const double* dinvt, double omega, double* rt, double* zt, ColumnDots norms,
                                hipStream_t st);
 void launch_block_cg_update_xr(int n, int k, double* x, double* r, const double* p, const double* q,
-                               const double* scal, int i_num, int i_den, int i_act, double* flag,
+                               const double* scal, int i_num, int i_den, int i_act, double* flags,
                                const float* dinvt, float omega, float* rt, float* zt, ColumnDots norms,
                                hipStream_t st);
 // p = z + beta_c p with beta_c = scal[i_num+c] / scal[i_den+c] on active
-// columns; p = z in every column if restart
+// columns; p = z in every column if restart_all, else in the columns with
+// scal[i_restart+c] != 0 (i_restart < 0: none)
 void launch_block_cg_update_p(int n, int k, double* p, const double* z, const double* scal, int i_num,
-                              int i_den, int i_act, bool restart, hipStream_t st);
+                              int i_den, int i_act, int i_restart, bool restart_all, hipStream_t st);
+// Fresh start of the columns with scal[i_load+c] != 0: x_c = 0, r_c = b_c,
+// rt_c = (T) b_c, zt_c = omega dinvt rt_c, norms[c] = |b_c|^2 (other columns
+// untouched; their norms are 0)
+void launch_block_load_columns(int n, int k, const double* scal, int i_load, const double* b, double* x,
+                               double* r, const double* dinvt, double omega, double* rt, double* zt,
+                               ColumnDots norms, hipStream_t st);
+void launch_block_load_columns(int n, int k, const double* scal, int i_load, const double* b, double* x,
+                               double* r, const float* dinvt, float omega, float* rt, float* zt,
+                               ColumnDots norms, hipStream_t st);
+// column c of a K-wide block from / to a plain vector of n entries
+void launch_block_column_in(int n, int k, int c, const double* v, double* blk, hipStream_t st);
+void launch_block_column_out(int n, int k, int c, const double* blk, double* v, hipStream_t st);
 // The preconditioner's last level-0 sweep z64 = (double)(G + omega dinv (U - A G))
 // with dot[c] = r64_c . z64_c (the CG inner product r.z)
 void launch_block_sweep_widen_dot(int k, const CsrT<double>& a, const double* g, const double* u,

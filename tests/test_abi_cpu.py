@@ -36,7 +36,7 @@ def test_defaults_and_status_strings():
     pp = amg.SolveParams()
     lib.amg_solve_params_default(C.byref(pp))
     assert (pp.method, pp.rtol, pp.maxit, pp.k, pp.s, pp.rho_max, pp.gamma_min) == (1, 1e-8, 200, 3, 1, 0.5, 0.01)
-    for st in (0, 1, -1, -2, -3, -4, -5, -6, -7):
+    for st in (0, 1, 2, -1, -2, -3, -4, -5, -6, -7):
         assert lib.amg_status_string(st)
 
 
