@@ -92,11 +92,16 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the per-gamma time-to-solution comparison (short profiler runs)")
-    ap.add_argument("--workload", default="poisson3d", choices=("poisson3d", "aniso2d", "fv3d"),
+    ap.add_argument("--budget-gb", type=float, default=32.0,
+                    help="serve: HBM budget for resident hierarchies plus batch engines (GiB)")
+    ap.add_argument("--requests", type=int, default=512, help="serve: number of requests")
+    ap.add_argument("--workload", default="poisson3d", choices=("poisson3d", "aniso2d", "fv3d", "serve"),
                     help="poisson3d: the headline 3D Poisson FP64 AMG-PCG run; aniso2d: rotated "
                          "anisotropic Q1 1024^2, FP32-preconditioned vs FP64 PCG to 1e-10; fv3d: "
                          "lognormal-coefficient FV 192^3 with 16 right-hand sides per launch, FP32 "
-                         "correction cycle in FP64 iterative refinement to 1e-10")
+                         "correction cycle in FP64 iterative refinement to 1e-10; serve: 512 requests "
+                         "over 14 resident hierarchies, continuous batching, FP32-preconditioned vs "
+                         "FP64 PCG to 1e-10")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -118,6 +123,8 @@ def main():
         return bench_aniso(args)
     if args.workload == "fv3d":
         return bench_fv3d(args)
+    if args.workload == "serve":
+        return bench_serve(args)
     N = args.N
     A = I.poisson3d(N)
     b_host = I.rhs(A.n, 2)
@@ -520,6 +527,149 @@ def bench_fv3d(args):
         out["oracle_rel_err_col0"] = float(np.linalg.norm(Xh[:, 0] - xo) / np.linalg.norm(xo))
         log(f"[bench] CPU baseline {1.0 / cpu_s:.4f} solves/s")
     h.close()
+    print(json.dumps(out), flush=True)
+
+
+SERVE_LADDER = {
+    "poisson2d": (100, 224, 500, 1000, 1414),
+    "poisson3d": (22, 47, 100, 126),
+    "aniso2d": (100, 224, 500, 1000, 1414),
+}
+
+
+def serve_requests(count):
+    """(family, N) and right-hand-side seed of each request: family uniform
+    over the three, size uniform over the family's ladder (SplitMix64 stream
+    5), right-hand side seed 1000 + i."""
+    from paper_1512_04629_amd import inputs as I
+    fams = sorted(SERVE_LADDER)
+    z = I.splitmix64(5, 2 * count)
+    out = []
+    for i in range(count):
+        fam = fams[int(z[2 * i] % 3)]
+        lad = SERVE_LADDER[fam]
+        out.append((fam, lad[int(z[2 * i + 1] % len(lad))], 1000 + i))
+    return out
+
+
+def bench_serve(args):
+    """Continuous-batching serving: requests for 14 (family, size) problems
+    with n from 1e4 to 2e6, each hierarchy built once and resident, batch
+    engines of 16 slots admitted against an HBM budget.  Capacity (all
+    requests queued at once) of the FP32-preconditioned and the FP64 batched
+    path; then Poisson arrivals at 0.8 x the FP64 capacity, served by both
+    and by one-at-a-time FP64 PCG: solves/s and p50/p99 latency."""
+    import numpy as np
+    import scipy.sparse as S
+    import torch
+
+    from paper_1512_04629_amd import amg
+    from paper_1512_04629_amd import inputs as I
+    from paper_1512_04629_amd.serve import Request, SolveServer, percentile
+
+    gens = {"poisson2d": I.poisson2d, "poisson3d": I.poisson3d, "aniso2d": I.aniso2d}
+    spec = serve_requests(args.requests)
+    keys = sorted({(f, N) for f, N, _ in spec})
+    log(f"[bench] serve: {args.requests} requests over {len(keys)} problems")
+    problems = {f"{f}_{N}": gens[f](N) for f, N in keys}
+    budget = int(args.budget_gb * (1 << 30))
+    t0 = time.perf_counter()
+    srv = SolveServer(problems, hbm_budget=budget, slots=16, precision=32, tol=1e-10, maxit=300, gamma=0.01)
+    setup_s = time.perf_counter() - t0
+    log(f"[bench] {len(problems)} hierarchies built in {setup_s:.1f} s, {srv.device_bytes() / 2**30:.2f} GiB")
+    rhs = [torch.as_tensor(I.rhs(problems[f"{f}_{N}"].n, seed)).cuda() for f, N, seed in spec]
+    outs = [torch.zeros(b.numel(), dtype=torch.float64, device="cuda") for b in rhs]
+    torch.cuda.synchronize()
+    log("[bench] right-hand sides resident")
+
+    def requests(arrivals):
+        return [Request(i, f"{f}_{N}", rhs[i], float(arrivals[i]), x=outs[i].zero_())
+                for i, (f, N, _) in enumerate(spec)]
+
+    def serve(precision, arrivals):
+        srv.close_engines()
+        srv.precision = precision
+        reqs = requests(arrivals)
+        st = srv.run(reqs)
+        bad = [r.rid for r in reqs if r.status != 0]
+        lat = st.latencies
+        return reqs, dict(solves_per_s=round(len(reqs) / st.makespan, 3), makespan_s=round(st.makespan, 4),
+                          p50_ms=round(percentile(lat, 50) * 1e3, 3), p99_ms=round(percentile(lat, 99) * 1e3, 3),
+                          steps=st.steps, engines_created=st.engines_created, engines_evicted=st.engines_evicted,
+                          peak_gib=round(st.peak_bytes / 2**30, 3), failed=len(bad),
+                          iters_mean=round(float(np.mean([r.iters for r in reqs])), 2))
+
+    zero = np.zeros(args.requests)
+    serve(32, zero)                                   # warm-up: engines, FP32 copies, allocator
+    cap = {}
+    for prec in (64, 32):
+        _, cap[prec] = serve(prec, zero)
+        log(f"[bench] capacity fp{prec}: {cap[prec]['solves_per_s']:.1f} solves/s, "
+            f"p99 {cap[prec]['p99_ms']:.1f} ms")
+    lam = 0.8 * cap[64]["solves_per_s"]
+    gaps = -np.log(1.0 - I.uniform01(6, args.requests)) / lam
+    arrivals = np.cumsum(gaps) - gaps[0]
+    open_loop = {}
+    for prec in (64, 32):
+        reqs, open_loop[f"fp{prec}_batched"] = serve(prec, arrivals)
+        log(f"[bench] lambda={lam:.1f}/s fp{prec} batched: p50 {open_loop[f'fp{prec}_batched']['p50_ms']:.2f} ms, "
+            f"p99 {open_loop[f'fp{prec}_batched']['p99_ms']:.2f} ms")
+    # accuracy of a sample of the FP32 results, on the host in FP64
+    worst = 0.0
+    for r in reqs[:: max(1, args.requests // 32)]:
+        A = problems[r.key]
+        Sp = S.csr_matrix((A.val, A.col, A.row_ptr), shape=(A.n, A.n))
+        b = r.b.cpu().numpy()
+        worst = max(worst, float(np.linalg.norm(b - Sp @ r.x.cpu().numpy()) / np.linalg.norm(b)))
+    seq_reqs = requests(arrivals)
+    st = srv.run_sequential(seq_reqs, precision=64)
+    open_loop["fp64_one_at_a_time"] = dict(
+        solves_per_s=round(len(seq_reqs) / st.makespan, 3), makespan_s=round(st.makespan, 4),
+        p50_ms=round(percentile(st.latencies, 50) * 1e3, 3), p99_ms=round(percentile(st.latencies, 99) * 1e3, 3),
+        failed=sum(r.status != 0 for r in seq_reqs))
+    log(f"[bench] one-at-a-time fp64: p50 {open_loop['fp64_one_at_a_time']['p50_ms']:.2f} ms, "
+        f"p99 {open_loop['fp64_one_at_a_time']['p99_ms']:.2f} ms")
+    out = {
+        "metric": "solves/s to 1e-10 and p50/p99 latency, continuous-batching server (FP32 V-cycle "
+                  "preconditioning FP64 CG vs FP64)",
+        "value": cap[32]["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": round(cap[32]["makespan_s"] * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 cycle in f64 CG", "data": "synthetic",
+        "config": {"workload": f"{args.requests} requests, family uniform over 2D 5-point / 3D 7-point / 2D "
+                               f"rotated anisotropic Q1, size uniform over N in {SERVE_LADDER} (n 1e4..2e6), "
+                               f"RHS uniform[-1,1] seed 1000+i; Sparse Galerkin gamma=0.01; 16-slot engines; "
+                               f"PCG to 1e-10; HBM budget {args.budget_gb} GiB",
+                   "problems": len(problems)},
+        "capacity": {f"fp{p}_batched": cap[p] for p in (64, 32)},
+        "arrival_rate_per_s": round(lam, 3),
+        "open_loop": open_loop,
+        "fp32_capacity_speedup": round(cap[32]["solves_per_s"] / cap[64]["solves_per_s"], 4),
+        "true_relres_max_sample": worst,
+        "setup_s": round(setup_s, 2),
+        "resident_gib": round(srv.device_bytes() / 2**30, 3),
+    }
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        log("[bench] CPU baseline: oracle PCG on the requests in order (setups untimed) ...")
+        oracles, solved, cpu_s = {}, 0, 0.0
+        for i, (f, N, seed) in enumerate(spec):
+            key = f"{f}_{N}"
+            if key not in oracles:
+                o = O.OracleAMG(problems[key])
+                o.sparsify([0.0, 0.0] + [0.01] * (o.nlev - 2))
+                oracles[key] = o
+            b = rhs[i].cpu().numpy()
+            t1 = time.perf_counter()
+            oracles[key].solve(b, method=O.PCG, tol=1e-10, maxit=300)
+            cpu_s += time.perf_counter() - t1
+            solved += 1
+            if cpu_s > 20.0:
+                break
+        out["cpu_baseline"] = {"value": round(solved / cpu_s, 4), "unit": "solves/s", "cores": 1, "kind": "oracle",
+                               "sample": f"the first {solved} requests in order, FP64 AMG-PCG to 1e-10, "
+                                         f"single-threaded C oracle, setups excluded"}
+        log(f"[bench] CPU baseline {solved / cpu_s:.3f} solves/s over {solved} requests")
+    srv.close()
     print(json.dumps(out), flush=True)
 
 

@@ -265,20 +265,26 @@ amg_status amg_batch_bytes(amg_handle h, int32_t slots, int32_t precision, int64
 /* Creates the batch engine of h.  precision 32: the V-cycle in FP32 (values,
    vectors, accumulation) preconditioning FP64 CG; 64: all FP64.  A slot
    finishes when ||r|| <= rtol ||b|| (x0 = 0) or after maxit iterations.
-   AMG_ERR_STATE if h already has a batch. */
+   flags: AMG_BATCH_GRAPHS replays each iteration as a captured HIP graph
+   (same kernels, same results; ignored on the null stream and while
+   profiling is enabled).  AMG_ERR_STATE if h already has a batch. */
+enum { AMG_BATCH_GRAPHS = 1 };
 amg_status amg_batch_create(amg_handle h, int32_t slots, int32_t precision, double rtol, int32_t maxit,
-                            amg_batch* out);
+                            int32_t flags, amg_batch* out);
 
 /* Copies rhs (device, n doubles) into a free slot; its solve starts at the
    next step.  *slot receives the slot index.  AMG_ERR_STATE if no slot is
    free (a finished slot is free again after amg_batch_collect). */
 amg_status amg_batch_submit(amg_batch b, const double* rhs, int32_t* slot);
 
-/* Enqueues one iteration of every active slot (starting the submitted ones)
-   and returns without waiting; *launched (nullable) = 0 if no slot had work.
-   AMG_ERR_STATE if the previous step has not been completed by
-   amg_batch_poll. */
-amg_status amg_batch_step(amg_batch b, int32_t* launched);
+/* Enqueues `iters` (>= 1) iterations of every active slot, the submitted
+   slots starting in the first, and returns without waiting; *launched
+   (nullable) = 0 if no slot had work.  The stop test runs on the device after
+   every iteration, so a slot stops at its own convergence iteration whatever
+   `iters` is (later iterations of the step leave it unchanged); new slots
+   can start only at a step boundary.  AMG_ERR_STATE if the previous step has
+   not been completed by amg_batch_poll. */
+amg_status amg_batch_step(amg_batch b, int32_t iters, int32_t* launched);
 
 /* Completes the last step: wait != 0 blocks until it has run; wait == 0
    returns AMG_NOT_READY if it is still running.  finished (nullable, host,

@@ -95,9 +95,9 @@ def load_library():
     lib.amg_vcycle_block.argtypes = [vp, i32, vp, vp]
     lib.amg_vcycle_block32.argtypes = [vp, i32, vp, vp]
     lib.amg_batch_bytes.argtypes = [vp, i32, i32, P(i64)]
-    lib.amg_batch_create.argtypes = [vp, i32, i32, f64, i32, P(vp)]
+    lib.amg_batch_create.argtypes = [vp, i32, i32, f64, i32, i32, P(vp)]
     lib.amg_batch_submit.argtypes = [vp, vp, P(i32)]
-    lib.amg_batch_step.argtypes = [vp, P(i32)]
+    lib.amg_batch_step.argtypes = [vp, i32, P(i32)]
     lib.amg_batch_poll.argtypes = [vp, i32, vp]
     lib.amg_batch_collect.argtypes = [vp, i32, vp, P(i32), P(f64), P(i32)]
     lib.amg_batch_slots.argtypes = [vp, vp]
@@ -262,9 +262,9 @@ class Hierarchy:
         self._check(self._lib.amg_batch_bytes(self._h, int(slots), int(precision), C.byref(v)))
         return v.value
 
-    def batch(self, slots=16, precision=32, tol=1e-10, maxit=300) -> "Batch":
+    def batch(self, slots=16, precision=32, tol=1e-10, maxit=300, graphs=True) -> "Batch":
         """The continuous-batching engine of this hierarchy (at most one)."""
-        return Batch(self, slots, precision, tol, maxit)
+        return Batch(self, slots, precision, tol, maxit, graphs)
 
     def __del__(self):
         try:
@@ -428,7 +428,7 @@ class Batch:
 
     FREE, SUBMITTED, ITERATING, FINISHED = 0, 1, 2, 3
 
-    def __init__(self, hier: Hierarchy, slots=16, precision=32, tol=1e-10, maxit=300):
+    def __init__(self, hier: Hierarchy, slots=16, precision=32, tol=1e-10, maxit=300, graphs=True):
         if getattr(hier, "_batch", None) is not None:
             raise AmgError(-7, "the hierarchy already has a batch engine")
         self._lib = hier._lib
@@ -437,7 +437,7 @@ class Batch:
         self.precision = int(precision)
         b = C.c_void_p()
         hier._check(self._lib.amg_batch_create(hier._h, self.slots, self.precision, float(tol), int(maxit),
-                                               C.byref(b)))
+                                               1 if graphs else 0, C.byref(b)))
         self._b = b
         hier._batch = self
         self._fin = np.zeros(self.slots, np.int32)
@@ -459,10 +459,11 @@ class Batch:
         self._check(self._lib.amg_batch_submit(self._b, _dptr(rhs, self.hier.n, "rhs"), C.byref(slot)))
         return slot.value
 
-    def step(self) -> bool:
-        """Enqueues one iteration of every active slot; False if there was no work."""
+    def step(self, iters: int = 1) -> bool:
+        """Enqueues `iters` iterations of every active slot; False if there was
+        no work."""
         launched = C.c_int32(0)
-        self._check(self._lib.amg_batch_step(self._b, C.byref(launched)))
+        self._check(self._lib.amg_batch_step(self._b, int(iters), C.byref(launched)))
         return bool(launched.value)
 
     def poll(self, wait=True):

@@ -51,11 +51,12 @@ constexpr int kCsrPad = 4;
 // device scalar slots
 // Block solves use 16 slots per quantity: squared residual norms (S_BLOCK),
 // r.z of two iterations (S_BRZ0, S_BRZ1), p.Ap (S_BPQ), active flags (S_BACT),
-// squared norms of freshly loaded right-hand sides (S_BNR0), load flags
-// (S_BLOAD), breakdown flags (S_BFLAG).
+// |b|^2 of each batch slot (S_BNR0), load flags (S_BLOAD), breakdown flags
+// (S_BFLAG), |b|^2 of freshly loaded columns (S_BNEW), and the batch slots'
+// iteration counts, states and residual ratios (S_BITER, S_BSTAT, S_BREL).
 enum : int { S_RZ0 = 0, S_RZ1 = 1, S_PQ = 2, S_NR2 = 3, S_FLAG = 4, S_NRT = 5, S_DOT = 6, S_BLOCK = 8,
              S_BRZ0 = 24, S_BRZ1 = 40, S_BPQ = 56, S_BACT = 72, S_BNR0 = 88, S_BLOAD = 104, S_BFLAG = 120,
-             S_COUNT = 136 };
+             S_BNEW = 136, S_BITER = 152, S_BSTAT = 168, S_BREL = 184, S_COUNT = 200 };
 constexpr int kMaxBlockRhs = 16;
 
 struct DevMat {
@@ -1320,6 +1321,10 @@ struct amg_batch_ctx {
     amg_ctx* h = nullptr;
     int k = 0, precision = 32, maxit = 0;
     double rtol = 0.0;
+    bool graphs = false;          // replay captured iterations
+    // one captured iteration per (r.z slot parity, with / without loads)
+    hipGraph_t graph[2][2] = {};
+    hipGraphExec_t exec[2][2] = {};
     double* B = nullptr;          // n x k right-hand sides of the slots
     double* X = nullptr;          // n x k iterates
     double* down = nullptr;       // pinned: the scalar slots after the last step
@@ -1337,8 +1342,10 @@ struct amg_batch_ctx {
 
 namespace {
 
+// One PCG iteration of every active slot from r.z slot `rz` to `next`; with
+// `load` the submitted slots start in it (x = 0, r = b, fresh direction).
 template <class T>
-void batch_step(amg_batch_ctx* e) {
+void batch_iteration(amg_batch_ctx* e, bool load, int rz, int next) {
     amg_ctx* h = e->h;
     const int k = e->k;
     BlockBufs<T>& bb = block_bufs(h, (T*)nullptr);
@@ -1346,6 +1353,69 @@ void batch_step(amg_batch_ctx* e) {
     const int n = f.n;
     LevelView<T> v0 = level_view(h, 0, (T*)nullptr);
     const T omega = (T)h->sp.omega;
+    const int i_load = load ? S_BLOAD : -1;
+    if (load) {
+        ProfScope ps(h, AMG_K_VECTOR, 0);
+        launch_block_load_columns(n, k, h->scal, S_BLOAD, e->B, e->X, h->bcg_r, v0.dinv, omega, bb.rhs, bb.x[0],
+                                  cols_to(h, S_BNEW), h->stream);
+        check_launch();
+    }
+    BlockSink sink;
+    sink.z64 = h->bcg_z;
+    sink.r64 = h->bcg_r;
+    sink.dot = cols_to(h, next);
+    vcycle_block<T>(h, k, bb.rhs, Guess::kPrescaled, sink);
+    {
+        ProfScope ps(h, AMG_K_VECTOR, 0);
+        launch_block_cg_update_p(n, k, h->bcg_p, h->bcg_z, h->scal, next, rz, S_BACT, i_load, false, h->stream);
+        check_launch();
+    }
+    {
+        ProfScope ps(h, AMG_K_SPMV_DOT, 0);
+        launch_block_spmv_dot(k, f.A.view(), h->bcg_p, h->bcg_q, cols_to(h, S_BPQ), h->stream);
+        check_launch();
+    }
+    {
+        ProfScope ps(h, AMG_K_VECTOR, 0);
+        launch_block_cg_update_xr(n, k, e->X, h->bcg_r, h->bcg_p, h->bcg_q, h->scal, next, S_BPQ, S_BACT,
+                                  h->scal + S_BFLAG, v0.dinv, omega, bb.rhs, bb.x[0], cols_to(h, S_BLOCK),
+                                  h->stream);
+        launch_block_converge(k, h->scal, S_BACT, S_BLOCK, S_BNR0, S_BFLAG, S_BITER, S_BSTAT, S_BREL, i_load,
+                              S_BNEW, e->rtol, e->maxit, h->stream);
+        check_launch();
+    }
+}
+
+// the captured form of batch_iteration(load, rz, next), made on first use
+template <class T>
+hipGraphExec_t batch_graph(amg_batch_ctx* e, bool load, int rz, int next) {
+    const int par = rz == S_BRZ0 ? 0 : 1;
+    hipGraphExec_t& ex = e->exec[par][load ? 1 : 0];
+    if (ex) return ex;
+    hipGraph_t& g = e->graph[par][load ? 1 : 0];
+    hipStream_t st = e->h->stream;
+    HIP_CHECK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    try {
+        batch_iteration<T>(e, load, rz, next);
+    } catch (...) {
+        hipGraph_t partial = nullptr;
+        (void)hipStreamEndCapture(st, &partial);
+        if (partial) (void)hipGraphDestroy(partial);
+        throw;
+    }
+    HIP_CHECK(hipStreamEndCapture(st, &g));
+    HIP_CHECK(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+    return ex;
+}
+
+// Enqueues `iters` PCG iterations of every active slot, the slots submitted
+// since the last step starting in the first one.  Each iteration ends with
+// the device-side stop test, so a slot stops at exactly its own convergence
+// iteration however many iterations a step holds.
+template <class T>
+void batch_step(amg_batch_ctx* e, int iters) {
+    amg_ctx* h = e->h;
+    const int k = e->k;
     bool any_load = false;
     for (int c = 0; c < k; ++c) {
         e->loaded[c] = e->state[c] == kSlotPending;
@@ -1361,71 +1431,33 @@ void batch_step(amg_batch_ctx* e) {
     HIP_CHECK(hipMemcpyAsync(h->scal + S_BLOAD, e->up + kMaxBlockRhs, sizeof(double) * k, hipMemcpyHostToDevice,
                              h->stream));
     launch_fill_f64(k, h->scal + S_BFLAG, 0.0, h->stream);
-    if (any_load) {
-        ProfScope ps(h, AMG_K_VECTOR, 0);
-        launch_block_load_columns(n, k, h->scal, S_BLOAD, e->B, e->X, h->bcg_r, v0.dinv, omega, bb.rhs, bb.x[0],
-                                  cols_to(h, S_BNR0), h->stream);
-        check_launch();
-    }
-    const int next = e->rz == S_BRZ0 ? S_BRZ1 : S_BRZ0;
-    BlockSink sink;
-    sink.z64 = h->bcg_z;
-    sink.r64 = h->bcg_r;
-    sink.dot = cols_to(h, next);
-    vcycle_block<T>(h, k, bb.rhs, Guess::kPrescaled, sink);
-    {
-        ProfScope ps(h, AMG_K_VECTOR, 0);
-        launch_block_cg_update_p(n, k, h->bcg_p, h->bcg_z, h->scal, next, e->rz, S_BACT, S_BLOAD, false,
-                                 h->stream);
-        check_launch();
-    }
-    {
-        ProfScope ps(h, AMG_K_SPMV_DOT, 0);
-        launch_block_spmv_dot(k, f.A.view(), h->bcg_p, h->bcg_q, cols_to(h, S_BPQ), h->stream);
-        check_launch();
-    }
-    {
-        ProfScope ps(h, AMG_K_VECTOR, 0);
-        launch_block_cg_update_xr(n, k, e->X, h->bcg_r, h->bcg_p, h->bcg_q, h->scal, next, S_BPQ, S_BACT,
-                                  h->scal + S_BFLAG, v0.dinv, omega, bb.rhs, bb.x[0], cols_to(h, S_BLOCK),
-                                  h->stream);
-        check_launch();
+    // graphs replay the same launches; event timing needs them issued one by one
+    const bool graphs = e->graphs && !h->profiling;
+    for (int it = 0; it < iters; ++it) {
+        const bool load = it == 0 && any_load;
+        const int next = e->rz == S_BRZ0 ? S_BRZ1 : S_BRZ0;
+        if (graphs) HIP_CHECK(hipGraphLaunch(batch_graph<T>(e, load, e->rz, next), h->stream));
+        else batch_iteration<T>(e, load, e->rz, next);
+        e->rz = next;
     }
     HIP_CHECK(hipMemcpyAsync(e->down, h->scal, sizeof(double) * S_COUNT, hipMemcpyDeviceToHost, h->stream));
     HIP_CHECK(hipEventRecord(e->done, h->stream));
-    e->rz = next;
     e->in_flight = true;
 }
 
-// slot bookkeeping after a completed step
+// slot bookkeeping after a completed step, from the states the device wrote
 void batch_finish_step(amg_batch_ctx* e, int32_t* finished) {
     const double* sc = e->down;
     for (int c = 0; c < e->k; ++c) {
         if (finished) finished[c] = 0;
         if (e->state[c] != kSlotActive) continue;
-        if (e->loaded[c]) {
-            e->nr0[c] = std::sqrt(sc[S_BNR0 + c]);
-            if (e->nr0[c] == 0.0) {
-                // zero right-hand side: the load wrote the exact solution x = 0
-                e->state[c] = kSlotDone;
-                e->status[c] = AMG_OK;
-                e->rel[c] = 0.0;
-                if (finished) finished[c] = 1;
-                continue;
-            }
-        }
-        e->iters[c]++;
-        const double nr = std::sqrt(sc[S_BLOCK + c]);
-        e->rel[c] = nr / e->nr0[c];
-        int st = -100;
-        if (sc[S_BFLAG + c] != 0.0 || !std::isfinite(nr) || !std::isfinite(e->nr0[c])) st = AMG_ERR_BREAKDOWN;
-        else if (nr <= e->rtol * e->nr0[c]) st = AMG_OK;
-        else if (e->iters[c] >= e->maxit) st = AMG_ERR_NOT_CONVERGED;
-        if (st != -100) {
-            e->state[c] = kSlotDone;
-            e->status[c] = st;
-            if (finished) finished[c] = 1;
-        }
+        e->iters[c] = (int)sc[S_BITER + c];
+        e->rel[c] = sc[S_BREL + c];
+        if (sc[S_BACT + c] != 0.0) continue;
+        const int st = (int)sc[S_BSTAT + c];
+        e->status[c] = st == 1 ? AMG_OK : st == 2 ? AMG_ERR_NOT_CONVERGED : AMG_ERR_BREAKDOWN;
+        e->state[c] = kSlotDone;
+        if (finished) finished[c] = 1;
     }
     e->in_flight = false;
 }
@@ -1449,6 +1481,11 @@ void destroy_batch(amg_batch_ctx* e) {
         h->blk_partials = nullptr;
         h->batch = nullptr;
     }
+    for (int p = 0; p < 2; ++p)
+        for (int l = 0; l < 2; ++l) {
+            if (e->exec[p][l]) (void)hipGraphExecDestroy(e->exec[p][l]);
+            if (e->graph[p][l]) (void)hipGraphDestroy(e->graph[p][l]);
+        }
     if (e->down) (void)hipHostFree(e->down);
     if (e->up) (void)hipHostFree(e->up);
     if (e->done) (void)hipEventDestroy(e->done);
@@ -2009,7 +2046,7 @@ amg_status amg_batch_bytes(amg_handle h, int32_t slots, int32_t precision, int64
 }
 
 amg_status amg_batch_create(amg_handle h, int32_t slots, int32_t precision, double rtol, int32_t maxit,
-                            amg_batch* out) {
+                            int32_t flags, amg_batch* out) {
     if (!out) return AMG_ERR_INVALID_ARG;
     *out = nullptr;
     if (!h || h->lv.empty() || h->batch) return AMG_ERR_STATE;
@@ -2025,6 +2062,8 @@ amg_status amg_batch_create(amg_handle h, int32_t slots, int32_t precision, doub
     e->precision = precision;
     e->rtol = rtol;
     e->maxit = maxit;
+    // stream capture needs a stream other than the null stream
+    e->graphs = (flags & AMG_BATCH_GRAPHS) != 0 && h->stream != nullptr;
     amg_status st = guarded(h, [&] {
         const int64_t cnt = (int64_t)h->lv[0].n * slots;
         if (precision == 32) {
@@ -2076,9 +2115,10 @@ amg_status amg_batch_submit(amg_batch b, const double* rhs, int32_t* slot) {
     });
 }
 
-amg_status amg_batch_step(amg_batch b, int32_t* launched) {
+amg_status amg_batch_step(amg_batch b, int32_t iters, int32_t* launched) {
     if (!b) return AMG_ERR_STATE;
     if (launched) *launched = 0;
+    if (iters < 1) return AMG_ERR_INVALID_ARG;
     if (b->in_flight) {
         b->h->last_error = "the previous step has not been completed by amg_batch_poll";
         return AMG_ERR_STATE;
@@ -2087,8 +2127,8 @@ amg_status amg_batch_step(amg_batch b, int32_t* launched) {
     for (int c = 0; c < b->k; ++c) work = work || b->state[c] == kSlotPending || b->state[c] == kSlotActive;
     if (!work) return AMG_OK;
     return guarded(b->h, [&] {
-        if (b->precision == 32) batch_step<float>(b);
-        else batch_step<double>(b);
+        if (b->precision == 32) batch_step<float>(b, iters);
+        else batch_step<double>(b, iters);
         if (launched) *launched = 1;
         return AMG_OK;
     });

@@ -439,6 +439,47 @@ __global__ __launch_bounds__(kBlk) void block_widen_dot_kernel(int n, const T* _
     store_column_partials<K, 2>(d, partials, lb);
 }
 
+// Device-side bookkeeping of the batch slots after an iteration (one
+// workgroup): for every active column, count the iteration and stop the
+// column when its residual meets the tolerance (||r|| <= rtol ||b||), its CG
+// denominator broke down, the residual is not finite, or maxit is reached.
+// A column loaded in this iteration (scal[i_load+c] != 0, i_load >= 0) first
+// takes its |b|^2 from scal[i_new+c] into scal[i_nr0+c] and has its counter
+// reset; with a zero right-hand side it stops at once with x = 0.  State per
+// column: scal[i_stat+c] = 0 running, 1 converged, 2 maxit reached,
+// 3 breakdown; scal[i_rel+c] = ||r|| / ||b|| after the iteration.
+__global__ __launch_bounds__(64) void block_converge_kernel(int k, double* __restrict__ scal, int i_act,
+                                                            int i_norm, int i_nr0, int i_flag, int i_iter,
+                                                            int i_stat, int i_rel, int i_load, int i_new,
+                                                            double rtol, int maxit) {
+    const int c = threadIdx.x;
+    if (c >= k || scal[i_act + c] == 0.0) return;
+    if (i_load >= 0 && scal[i_load + c] != 0.0) {
+        scal[i_nr0 + c] = scal[i_new + c];
+        scal[i_iter + c] = 0.0;
+        scal[i_stat + c] = 0.0;
+    }
+    const double n0 = sqrt(scal[i_nr0 + c]);
+    if (n0 == 0.0) {
+        scal[i_act + c] = 0.0;
+        scal[i_stat + c] = 1.0;
+        scal[i_rel + c] = 0.0;
+        return;
+    }
+    const double it = scal[i_iter + c] + 1.0;
+    scal[i_iter + c] = it;
+    const double nr = sqrt(scal[i_norm + c]);
+    double stat = 0.0;
+    if (scal[i_flag + c] != 0.0 || !isfinite(nr) || !isfinite(n0)) stat = 3.0;
+    else if (nr <= rtol * n0) stat = 1.0;
+    else if (it >= (double)maxit) stat = 2.0;
+    scal[i_rel + c] = nr / n0;
+    if (stat != 0.0) {
+        scal[i_stat + c] = stat;
+        scal[i_act + c] = 0.0;
+    }
+}
+
 template <class T>
 __global__ __launch_bounds__(kBlk) void block_dense_kernel(int n, int k, const double* __restrict__ ainv,
                                                            const T* __restrict__ b, T* __restrict__ y) {
@@ -666,6 +707,12 @@ void launch_block_load_columns(int n, int k, const double* scal, int i_load, con
                                double* r, const float* dinvt, float omega, float* rt, float* zt,
                                ColumnDots norms, hipStream_t st) {
     load_columns<float>(n, k, scal, i_load, b, x, r, dinvt, omega, rt, zt, norms, st);
+}
+
+void launch_block_converge(int k, double* scal, int i_act, int i_norm, int i_nr0, int i_flag, int i_iter, int i_stat,
+                           int i_rel, int i_load, int i_new, double rtol, int maxit, hipStream_t st) {
+    hipLaunchKernelGGL(block_converge_kernel, dim3(1), dim3(64), 0, st, k, scal, i_act, i_norm, i_nr0, i_flag,
+                       i_iter, i_stat, i_rel, i_load, i_new, rtol, maxit);
 }
 
 void launch_block_column_in(int n, int k, int c, const double* v, double* blk, hipStream_t st) {

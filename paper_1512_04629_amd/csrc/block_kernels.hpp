@@ -92,6 +92,14 @@ void launch_block_load_columns(int n, int k, const double* scal, int i_load, con
 void launch_block_load_columns(int n, int k, const double* scal, int i_load, const double* b, double* x,
                                double* r, const float* dinvt, float omega, float* rt, float* zt,
                                ColumnDots norms, hipStream_t st);
+// Slot bookkeeping after an iteration, on the device: for active columns
+// count the iteration and stop a column whose ||r|| <= rtol ||b|| (state 1),
+// that reached maxit (2) or broke down (3).  Columns loaded in the iteration
+// (i_load >= 0) first take |b|^2 from scal[i_new+c] and a reset counter; a
+// zero right-hand side stops at once (state 1, 0 iterations).  Updates the
+// active flags; scal[i_rel+c] = ||r|| / ||b||.
+void launch_block_converge(int k, double* scal, int i_act, int i_norm, int i_nr0, int i_flag, int i_iter, int i_stat,
+                           int i_rel, int i_load, int i_new, double rtol, int maxit, hipStream_t st);
 // column c of a K-wide block from / to a plain vector of n entries
 void launch_block_column_in(int n, int k, int c, const double* v, double* blk, hipStream_t st);
 void launch_block_column_out(int n, int k, int c, const double* blk, double* v, hipStream_t st);

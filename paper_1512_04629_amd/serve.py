@@ -60,9 +60,16 @@ class ServeStats:
 
 class SolveServer:
     def __init__(self, problems: dict, hbm_budget: int, slots: int = 16, precision: int = 32,
-                 tol: float = 1e-10, maxit: int = 300, gamma: float = 0.01):
+                 tol: float = 1e-10, maxit: int = 300, gamma: float = 0.01, step_target_s: float = 1.5e-3,
+                 max_iters_per_step: int = 8, graphs: bool = True):
         torch = amg._torch()
         self.slots, self.precision, self.tol, self.maxit = int(slots), int(precision), float(tol), int(maxit)
+        # iterations per engine step: as many as fit in step_target_s (so that
+        # small problems are not bound by host round trips), at most
+        # max_iters_per_step (new requests join only at step boundaries)
+        self.step_target_s, self.max_iters = float(step_target_s), int(max_iters_per_step)
+        self.graphs = bool(graphs)
+        self.iter_time: dict = {}
         self.budget = int(hbm_budget)
         self.hier, self.streams = {}, {}
         for key, A in problems.items():
@@ -104,7 +111,7 @@ class SolveServer:
             return None
         torch = amg._torch()
         with torch.cuda.stream(self.streams[key]):
-            self.engines[key] = h.batch(self.slots, self.precision, self.tol, self.maxit)
+            self.engines[key] = h.batch(self.slots, self.precision, self.tol, self.maxit, self.graphs)
         self.last_used[key] = time.perf_counter()
         self.stats.engines_created += 1
         self.stats.max_live_engines = max(self.stats.max_live_engines, len(self.engines))
@@ -136,7 +143,7 @@ class SolveServer:
         order = sorted(requests, key=lambda r: (r.arrival, r.rid))
         queues = collections.defaultdict(collections.deque)
         owner = {}                       # (key, slot) -> request
-        in_flight = set()
+        in_flight = {}                   # key -> (launch time, iterations)
         remaining, nxt = len(order), 0
         t0 = time.perf_counter()
         while remaining:
@@ -157,8 +164,12 @@ class SolveServer:
                     r.admitted = now
                     free -= 1
             for key, eng in self.engines.items():
-                if key not in in_flight and eng.step():
-                    in_flight.add(key)
+                if key in in_flight:
+                    continue
+                est = self.iter_time.get(key)
+                iters = 1 if est is None else max(1, min(self.max_iters, int(self.step_target_s / est)))
+                if eng.step(iters):
+                    in_flight[key] = (time.perf_counter(), iters)
                     self.last_used[key] = time.perf_counter()
                     self.stats.steps += 1
             progressed = False
@@ -167,7 +178,10 @@ class SolveServer:
                 fin = eng.poll(wait=False)
                 if fin is None:
                     continue
-                in_flight.discard(key)
+                t_launch, iters = in_flight.pop(key)
+                per = (time.perf_counter() - t_launch) / iters
+                old = self.iter_time.get(key)
+                self.iter_time[key] = per if old is None else 0.5 * (old + per)
                 progressed = True
                 t_done = time.perf_counter() - t0
                 for slot in fin:

@@ -194,3 +194,45 @@ def test_batch_bytes_match_allocations(lib):
             # the FP32 copies stay with the hierarchy
             assert h.batch_bytes(16, 32) < predicted
     h.close()
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+def test_graph_replays_and_multi_iteration_steps_equal_eager(lib, precision):
+    """The same submissions served with captured iterations and several
+    iterations per step give the bits of eager single-iteration steps."""
+    from paper_1512_04629_amd import amg
+    A = I.aniso2d(48)
+    stream = torch.cuda.Stream()          # captured graphs need a stream other than the null stream
+    with torch.cuda.stream(stream):
+        h = amg.Hierarchy(A)
+    torch.cuda.synchronize()
+    bs = [torch.as_tensor(I.rhs(A.n, 70 + i)).cuda() for i in range(10)]
+    torch.cuda.synchronize()
+
+    def serve(graphs, iters):
+        with torch.cuda.stream(stream):
+            eng = h.batch(slots=4, precision=precision, tol=1e-10, maxit=200, graphs=graphs)
+        out, queue, owner = {}, list(range(len(bs))), {}
+        while len(out) < len(bs):
+            while queue and (eng.states() == 0).any():
+                i = queue.pop(0)
+                owner[eng.submit(bs[i])] = i
+            assert eng.step(iters)
+            torch.cuda.synchronize()               # eager work between replays
+            for c in eng.poll(wait=True):
+                x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+                torch.cuda.synchronize()
+                it, rr, st = eng.collect(c, x)
+                assert st == 0
+                out[owner.pop(c)] = (it, x)
+        eng.close()
+        torch.cuda.synchronize()
+        return out
+
+    ref = serve(False, 1)
+    for graphs, iters in ((True, 1), (True, 3), (False, 4), (True, 7)):
+        got = serve(graphs, iters)
+        for i in range(len(bs)):
+            assert got[i][0] == ref[i][0]
+            assert got[i][1].cpu().numpy().tobytes() == ref[i][1].cpu().numpy().tobytes(), (graphs, iters, i)
+    h.close()
