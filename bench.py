@@ -593,11 +593,20 @@ def bench_serve(args):
         st = srv.run(reqs)
         bad = [r.rid for r in reqs if r.status != 0]
         lat = st.latencies
+        per_key = {}
+        for key in sorted({r.key for r in reqs}):
+            rs = [r for r in reqs if r.key == key]
+            occ = st.occupancy.get(key, [0, 1])
+            per_key[key] = dict(count=len(rs), p50_ms=round(percentile([r.latency for r in rs], 50) * 1e3, 2),
+                                p99_ms=round(percentile([r.latency for r in rs], 99) * 1e3, 2),
+                                service_ms=round(float(np.mean([r.done - r.admitted for r in rs])) * 1e3, 2),
+                                iters=round(float(np.mean([r.iters for r in rs])), 1),
+                                slot_occupancy=round(occ[0] / max(occ[1], 1), 2))
         return reqs, dict(solves_per_s=round(len(reqs) / st.makespan, 3), makespan_s=round(st.makespan, 4),
                           p50_ms=round(percentile(lat, 50) * 1e3, 3), p99_ms=round(percentile(lat, 99) * 1e3, 3),
                           steps=st.steps, engines_created=st.engines_created, engines_evicted=st.engines_evicted,
                           peak_gib=round(st.peak_bytes / 2**30, 3), failed=len(bad),
-                          iters_mean=round(float(np.mean([r.iters for r in reqs])), 2))
+                          iters_mean=round(float(np.mean([r.iters for r in reqs])), 2), per_problem=per_key)
 
     zero = np.zeros(args.requests)
     serve(32, zero)                                   # warm-up: engines, FP32 copies, allocator

@@ -51,12 +51,14 @@ constexpr int kCsrPad = 4;
 // device scalar slots
 // Block solves use 16 slots per quantity: squared residual norms (S_BLOCK),
 // r.z of two iterations (S_BRZ0, S_BRZ1), p.Ap (S_BPQ), active flags (S_BACT),
-// |b|^2 of each batch slot (S_BNR0), load flags (S_BLOAD), breakdown flags
+// load flags (S_BLOAD), the number of leading columns the block kernels
+// compute (S_LIVE, one slot, right after the load flags so that one copy
+// sets all three), |b|^2 of each batch slot (S_BNR0), breakdown flags
 // (S_BFLAG), |b|^2 of freshly loaded columns (S_BNEW), and the batch slots'
 // iteration counts, states and residual ratios (S_BITER, S_BSTAT, S_BREL).
 enum : int { S_RZ0 = 0, S_RZ1 = 1, S_PQ = 2, S_NR2 = 3, S_FLAG = 4, S_NRT = 5, S_DOT = 6, S_BLOCK = 8,
-             S_BRZ0 = 24, S_BRZ1 = 40, S_BPQ = 56, S_BACT = 72, S_BNR0 = 88, S_BLOAD = 104, S_BFLAG = 120,
-             S_BNEW = 136, S_BITER = 152, S_BSTAT = 168, S_BREL = 184, S_COUNT = 200 };
+             S_BRZ0 = 24, S_BRZ1 = 40, S_BPQ = 56, S_BACT = 72, S_BLOAD = 88, S_LIVE = 104, S_BNR0 = 112,
+             S_BFLAG = 128, S_BNEW = 144, S_BITER = 160, S_BSTAT = 176, S_BREL = 192, S_COUNT = 208 };
 constexpr int kMaxBlockRhs = 16;
 
 struct DevMat {
@@ -944,8 +946,12 @@ BlockBufs<T>& ensure_block(amg_ctx* h, int k) {
         bb.x[l] = dalloc_n<T>(h, cnt);
         bb.xt[l] = dalloc_n<T>(h, cnt);
         bb.r[l] = dalloc_n<T>(h, cnt);
+        // columns outside the live prefix are never written: keep them finite
+        for (T* q : {bb.b[l], bb.x[l], bb.xt[l], bb.r[l]})
+            if (q) fill_t(cnt, q, h);
     }
     bb.rhs = dalloc_n<T>(h, (int64_t)h->lv[0].n * k);
+    fill_t((int64_t)h->lv[0].n * k, bb.rhs, h);
     bb.k = k;
     return bb;
 }
@@ -955,7 +961,7 @@ void block_op_t(amg_ctx* h, int kind, int l, BlockOp op, int k, const DevMat& m,
                 const T* u, const T* dinv, T* y, T* y2, double* acc) {
     ProfScope ps(h, kind, l);
     launch_block_op(op, k, CsrT<T>{m.rp, m.ci, vals, m.rows, 0.0}, g, u, dinv, (T)h->sp.omega, y, y2, acc,
-                    h->stream);
+                    h->stream, h->scal + S_LIVE);
     check_launch();
 }
 
@@ -985,13 +991,13 @@ T* vcycle_block(amg_ctx* h, int k, const T* b0, Guess guess0, const BlockSink& s
     auto deliver = [&](const T* x) {
         ProfScope ps(h, AMG_K_VECTOR, 0);
         if (sink.acc) launch_block_accumulate((int64_t)h->lv[0].n * k, sink.acc, x, h->stream);
-        else launch_block_widen_dot(h->lv[0].n, k, x, sink.z64, sink.r64, sink.dot, h->stream);
+        else launch_block_widen_dot(h->lv[0].n, k, x, sink.z64, sink.r64, sink.dot, h->stream, h->scal + S_LIVE);
         check_launch();
     };
     if (L == 0) {
         {
             ProfScope ps(h, AMG_K_COARSE, 0);
-            launch_block_dense_matvec(h->nL, k, h->coarse_inv, b0, bb.xt[0], h->stream);
+            launch_block_dense_matvec(h->nL, k, h->coarse_inv, b0, bb.xt[0], h->stream, h->scal + S_LIVE);
             check_launch();
         }
         if (!to_sink) return bb.xt[0];
@@ -1006,7 +1012,8 @@ T* vcycle_block(amg_ctx* h, int k, const T* b0, Guess guess0, const BlockSink& s
         } else if (last0 && sink.z64) {
             ProfScope ps(h, AMG_K_JACOBI, l);
             launch_block_sweep_widen_dot(k, CsrT<T>{v.Ah->rp, v.Ah->ci, v.ahv, v.Ah->rows, 0.0}, cur[l], b, v.dinv,
-                                         (T)h->sp.omega, sink.z64, sink.r64, sink.dot, h->stream);
+                                         (T)h->sp.omega, sink.z64, sink.r64, sink.dot, h->stream,
+                                         h->scal + S_LIVE);
             check_launch();
         } else {
             block_op_t<T>(h, AMG_K_JACOBI, l, kBJacobi, k, *v.Ah, v.ahv, cur[l], b, v.dinv, alt[l], nullptr,
@@ -1041,7 +1048,7 @@ T* vcycle_block(amg_ctx* h, int k, const T* b0, Guess guess0, const BlockSink& s
     }
     {
         ProfScope ps(h, AMG_K_COARSE, L);
-        launch_block_dense_matvec(h->nL, k, h->coarse_inv, bb.b[L], bb.x[L], h->stream);
+        launch_block_dense_matvec(h->nL, k, h->coarse_inv, bb.b[L], bb.x[L], h->stream, h->scal + S_LIVE);
         check_launch();
         cur[L] = bb.x[L];
     }
@@ -1067,7 +1074,7 @@ void block_outer(amg_ctx* h, int k, const double* b, const double* x, double* r6
     LevelView<T> v = level_view(h, 0, (T*)nullptr);
     ProfScope ps(h, AMG_K_RESIDUAL, 0);
     launch_block_outer_residual(k, f.A.view(), x, b, v.dinv, (T)h->sp.omega, bb.rhs, bb.x[0], r64,
-                                cols_to(h, S_BLOCK), h->stream);
+                                cols_to(h, S_BLOCK), h->stream, h->scal + S_LIVE);
     check_launch();
 }
 
@@ -1081,6 +1088,7 @@ amg_status solve_block(amg_ctx* h, int k, int nrhs, const double* b, double* x, 
     amg_solve_info info{0, 0, 0, 0, 0.0, 0.0};
     amg_status st = AMG_ERR_NOT_CONVERGED;
     launch_fill_f64(S_COUNT, h->scal, 0.0, h->stream);
+    launch_fill_f64(1, h->scal + S_LIVE, (double)nrhs, h->stream);
     block_outer<T>(h, k, b, x);
     int singular = 0;
     if (h->check_singular) download(h, &singular, h->missing, 1);
@@ -1152,6 +1160,7 @@ void ensure_block_cg(amg_ctx* h, int k) {
     h->bcg_p = dalloc_n<double>(h, cnt);
     h->bcg_q = dalloc_n<double>(h, cnt);
     h->bcg_z = dalloc_n<double>(h, cnt);
+    for (double* q : {h->bcg_r, h->bcg_p, h->bcg_q, h->bcg_z}) launch_fill_f64(cnt, q, 0.0, h->stream);
     h->bcg_k = k;
 }
 
@@ -1180,6 +1189,7 @@ amg_status solve_block_pcg(amg_ctx* h, int k, int nrhs, const double* b, double*
     amg_solve_info info{0, 0, 0, 0, 0.0, 0.0};
     amg_status st = AMG_ERR_NOT_CONVERGED;
     launch_fill_f64(S_COUNT, h->scal, 0.0, h->stream);
+    launch_fill_f64(1, h->scal + S_LIVE, (double)nrhs, h->stream);
     block_outer<T>(h, k, b, x, h->bcg_r);
     int singular = 0;
     if (h->check_singular) download(h, &singular, h->missing, 1);
@@ -1217,19 +1227,21 @@ amg_status solve_block_pcg(amg_ctx* h, int k, int nrhs, const double* b, double*
         upload_active(h, active, k);
         int rz = S_BRZ0;
         precondition(rz);
-        launch_block_cg_update_p(n, k, h->bcg_p, h->bcg_z, h->scal, rz, rz, S_BACT, -1, true, h->stream);
+        launch_block_cg_update_p(n, k, h->bcg_p, h->bcg_z, h->scal, rz, rz, S_BACT, -1, true, h->stream,
+                                 h->scal + S_LIVE);
         check_launch();
         while (info.iters < p.maxit) {
             {
                 ProfScope ps(h, AMG_K_SPMV_DOT, 0);
-                launch_block_spmv_dot(k, f.A.view(), h->bcg_p, h->bcg_q, cols_to(h, S_BPQ), h->stream);
+                launch_block_spmv_dot(k, f.A.view(), h->bcg_p, h->bcg_q, cols_to(h, S_BPQ), h->stream,
+                                      h->scal + S_LIVE);
                 check_launch();
             }
             {
                 ProfScope ps(h, AMG_K_VECTOR, 0);
                 launch_block_cg_update_xr(n, k, x, h->bcg_r, h->bcg_p, h->bcg_q, h->scal, rz, S_BPQ, S_BACT,
                                           h->scal + S_BFLAG, v0.dinv, omega, bb.rhs, bb.x[0],
-                                          cols_to(h, S_BLOCK), h->stream);
+                                          cols_to(h, S_BLOCK), h->stream, h->scal + S_LIVE);
                 check_launch();
             }
             sc = read_scalars(h);
@@ -1257,7 +1269,7 @@ amg_status solve_block_pcg(amg_ctx* h, int k, int nrhs, const double* b, double*
             {
                 ProfScope ps(h, AMG_K_VECTOR, 0);
                 launch_block_cg_update_p(n, k, h->bcg_p, h->bcg_z, h->scal, next, rz, S_BACT, -1, false,
-                                         h->stream);
+                                         h->stream, h->scal + S_LIVE);
                 check_launch();
             }
             rz = next;
@@ -1328,7 +1340,7 @@ struct amg_batch_ctx {
     double* B = nullptr;          // n x k right-hand sides of the slots
     double* X = nullptr;          // n x k iterates
     double* down = nullptr;       // pinned: the scalar slots after the last step
-    double* up = nullptr;         // pinned: active flags [0, 16), load flags [16, 32)
+    double* up = nullptr;         // pinned: active flags [0, 16), load flags [16, 32), live columns [32]
     hipEvent_t done = nullptr;
     bool in_flight = false;
     int rz = S_BRZ0;
@@ -1367,19 +1379,20 @@ void batch_iteration(amg_batch_ctx* e, bool load, int rz, int next) {
     vcycle_block<T>(h, k, bb.rhs, Guess::kPrescaled, sink);
     {
         ProfScope ps(h, AMG_K_VECTOR, 0);
-        launch_block_cg_update_p(n, k, h->bcg_p, h->bcg_z, h->scal, next, rz, S_BACT, i_load, false, h->stream);
+        launch_block_cg_update_p(n, k, h->bcg_p, h->bcg_z, h->scal, next, rz, S_BACT, i_load, false, h->stream,
+                                 h->scal + S_LIVE);
         check_launch();
     }
     {
         ProfScope ps(h, AMG_K_SPMV_DOT, 0);
-        launch_block_spmv_dot(k, f.A.view(), h->bcg_p, h->bcg_q, cols_to(h, S_BPQ), h->stream);
+        launch_block_spmv_dot(k, f.A.view(), h->bcg_p, h->bcg_q, cols_to(h, S_BPQ), h->stream, h->scal + S_LIVE);
         check_launch();
     }
     {
         ProfScope ps(h, AMG_K_VECTOR, 0);
         launch_block_cg_update_xr(n, k, e->X, h->bcg_r, h->bcg_p, h->bcg_q, h->scal, next, S_BPQ, S_BACT,
                                   h->scal + S_BFLAG, v0.dinv, omega, bb.rhs, bb.x[0], cols_to(h, S_BLOCK),
-                                  h->stream);
+                                  h->stream, h->scal + S_LIVE);
         launch_block_converge(k, h->scal, S_BACT, S_BLOCK, S_BNR0, S_BFLAG, S_BITER, S_BSTAT, S_BREL, i_load,
                               S_BNEW, e->rtol, e->maxit, h->stream);
         check_launch();
@@ -1417,18 +1430,23 @@ void batch_step(amg_batch_ctx* e, int iters) {
     amg_ctx* h = e->h;
     const int k = e->k;
     bool any_load = false;
-    for (int c = 0; c < k; ++c) {
-        e->loaded[c] = e->state[c] == kSlotPending;
+    int live = 0;
+    for (int c = 0; c < kMaxBlockRhs; ++c) {
+        e->loaded[c] = c < k && e->state[c] == kSlotPending;
         if (e->loaded[c]) {
             e->state[c] = kSlotActive;
             e->iters[c] = 0;
             any_load = true;
         }
-        e->up[c] = e->state[c] == kSlotActive ? 1.0 : 0.0;
+        const bool act = c < k && e->state[c] == kSlotActive;
+        if (act) live = c + 1;
+        e->up[c] = act ? 1.0 : 0.0;
         e->up[kMaxBlockRhs + c] = e->loaded[c] ? 1.0 : 0.0;
     }
-    HIP_CHECK(hipMemcpyAsync(h->scal + S_BACT, e->up, sizeof(double) * k, hipMemcpyHostToDevice, h->stream));
-    HIP_CHECK(hipMemcpyAsync(h->scal + S_BLOAD, e->up + kMaxBlockRhs, sizeof(double) * k, hipMemcpyHostToDevice,
+    // slots past the last iterating one are not computed
+    e->up[2 * kMaxBlockRhs] = (double)live;
+    static_assert(S_BLOAD == S_BACT + kMaxBlockRhs && S_LIVE == S_BLOAD + kMaxBlockRhs, "slot layout");
+    HIP_CHECK(hipMemcpyAsync(h->scal + S_BACT, e->up, sizeof(double) * (2 * kMaxBlockRhs + 1), hipMemcpyHostToDevice,
                              h->stream));
     launch_fill_f64(k, h->scal + S_BFLAG, 0.0, h->stream);
     // graphs replay the same launches; event timing needs them issued one by one
@@ -1646,6 +1664,7 @@ amg_status vcycle_block_abi(amg_handle h, int32_t nrhs, const T* b, T* x) {
     return guarded(h, [&] {
         if constexpr (sizeof(T) == 4) ensure_fp32(h);
         BlockBufs<T>& bb = ensure_block<T>(h, nrhs);
+        launch_fill_f64(1, h->scal + S_LIVE, (double)nrhs, h->stream);
         launch_copy((int)(n * nrhs), bb.x[0], x, h->stream);
         T* res = vcycle_block<T>(h, nrhs, b, Guess::kNonzero, BlockSink{});
         launch_copy((int)(n * nrhs), x, res, h->stream);
@@ -2080,7 +2099,7 @@ amg_status amg_batch_create(amg_handle h, int32_t slots, int32_t precision, doub
         launch_fill_f64(cnt, e->X, 0.0, h->stream);
         check_launch();
         HIP_CHECK(hipHostMalloc((void**)&e->down, sizeof(double) * S_COUNT, hipHostMallocDefault));
-        HIP_CHECK(hipHostMalloc((void**)&e->up, sizeof(double) * 2 * kMaxBlockRhs, hipHostMallocDefault));
+        HIP_CHECK(hipHostMalloc((void**)&e->up, sizeof(double) * (2 * kMaxBlockRhs + 1), hipHostMallocDefault));
         HIP_CHECK(hipEventCreateWithFlags(&e->done, hipEventDisableTiming));
         h->batch = e;
         return AMG_OK;

@@ -94,7 +94,8 @@ __device__ __forceinline__ typename Vec16<T>::type row_gather_sum(const CsrT<T>&
 template <class T, int K, int OP>
 __global__ __launch_bounds__(kBlk) void block_row_kernel(CsrT<T> a, const T* __restrict__ g, const T* u,
                                                          const T* __restrict__ dinv, T omega, T* y,
-                                                         T* __restrict__ y2, double* acc, int ntiles) {
+                                                         T* __restrict__ y2, double* acc, int ntiles,
+                                                         const double* __restrict__ live) {
     using VT = typename Vec16<T>::type;
     constexpr int V = Vec16<T>::n;
     constexpr int LPR = K / V;          // lanes per row
@@ -102,6 +103,7 @@ __global__ __launch_bounds__(kBlk) void block_row_kernel(CsrT<T> a, const T* __r
     const int lb = logical_block();
     const int sub = threadIdx.x / LPR;
     const int c0 = (threadIdx.x % LPR) * V;
+    if (live && c0 >= (int)*live) return;   // columns past the live prefix are left as they are
     for (int t = lb; t < ntiles; t += gridDim.x) {
         const int i = t * RPT + sub;
         if (i >= a.rows) break;
@@ -157,14 +159,16 @@ __global__ __launch_bounds__(kBlk) void block_outer_kernel(CsrView a, const doub
                                                            const T* __restrict__ dinvt, T omega,
                                                            T* __restrict__ rt, T* __restrict__ zt,
                                                            double* __restrict__ r64,
-                                                           double* __restrict__ partials, int ntiles) {
+                                                           double* __restrict__ partials, int ntiles,
+                                                           const double* __restrict__ live) {
     constexpr int LPR = K / 2;
     constexpr int RPT = kBlk / LPR;
     const int lb = logical_block();
     const int sub = threadIdx.x / LPR;
     const int c0 = (threadIdx.x % LPR) * 2;
+    const int nt = (live && c0 >= (int)*live) ? 0 : ntiles;
     double n0 = 0.0, n1 = 0.0;
-    for (int t = lb; t < ntiles; t += gridDim.x) {
+    for (int t = lb; t < nt; t += gridDim.x) {
         const int i = t * RPT + sub;
         if (i >= a.rows) break;
         const v2d s = row_gather_sum<double, K>(a, x, a.rp[i], a.rp[i + 1], c0);
@@ -206,14 +210,16 @@ __global__ __launch_bounds__(kBlk) void block_norm_finish_kernel(int nparts, con
 template <int K>
 __global__ __launch_bounds__(kBlk) void block_spmv_dot_kernel(CsrView a, const double* __restrict__ p,
                                                               double* __restrict__ q,
-                                                              double* __restrict__ partials, int ntiles) {
+                                                              double* __restrict__ partials, int ntiles,
+                                                              const double* __restrict__ live) {
     constexpr int LPR = K / 2;
     constexpr int RPT = kBlk / LPR;
     const int lb = logical_block();
     const int sub = threadIdx.x / LPR;
     const int c0 = (threadIdx.x % LPR) * 2;
+    const int nt = (live && c0 >= (int)*live) ? 0 : ntiles;
     double d[2] = {0.0, 0.0};
-    for (int t = lb; t < ntiles; t += gridDim.x) {
+    for (int t = lb; t < nt; t += gridDim.x) {
         const int i = t * RPT + sub;
         if (i >= a.rows) break;
         const v2d s = row_gather_sum<double, K>(a, p, a.rp[i], a.rp[i + 1], c0);
@@ -238,12 +244,14 @@ __global__ __launch_bounds__(kBlk) void block_cg_xr_kernel(int n, double* __rest
                                                            const double* __restrict__ scal, int i_num, int i_den,
                                                            int i_act, double* flags, const T* __restrict__ dinvt,
                                                            T omega, T* __restrict__ rt, T* __restrict__ zt,
-                                                           double* __restrict__ partials, int ntiles) {
+                                                           double* __restrict__ partials, int ntiles,
+                                                           const double* __restrict__ live) {
     constexpr int LPR = K / 2;
     constexpr int RPT = kBlk / LPR;
     const int lb = logical_block();
     const int sub = threadIdx.x / LPR;
     const int c0 = (threadIdx.x % LPR) * 2;
+    const int nt = (live && c0 >= (int)*live) ? 0 : ntiles;
     double alpha[2];
     bool upd[2];
 #pragma unroll
@@ -256,7 +264,7 @@ __global__ __launch_bounds__(kBlk) void block_cg_xr_kernel(int n, double* __rest
         if (act && !ok && blockIdx.x == 0 && threadIdx.x < LPR) flags[c0 + e] = 1.0;
     }
     double nr[2] = {0.0, 0.0};
-    for (int t = lb; t < ntiles; t += gridDim.x) {
+    for (int t = lb; t < nt; t += gridDim.x) {
         const int i = t * RPT + sub;
         if (i >= n) break;
         const int o = i * K + c0;
@@ -294,11 +302,13 @@ template <int K>
 __global__ __launch_bounds__(kBlk) void block_cg_p_kernel(int n, double* __restrict__ p,
                                                           const double* __restrict__ z,
                                                           const double* __restrict__ scal, int i_num, int i_den,
-                                                          int i_act, int i_restart, int restart_all) {
+                                                          int i_act, int i_restart, int restart_all,
+                                                          const double* __restrict__ live) {
     constexpr int LPR = K / 2;
     constexpr int RPT = kBlk / LPR;
     const int sub = threadIdx.x / LPR;
     const int c0 = (threadIdx.x % LPR) * 2;
+    if (live && c0 >= (int)*live) return;
     double beta[2];
     bool upd[2], fresh[2];
 #pragma unroll
@@ -385,7 +395,8 @@ __global__ __launch_bounds__(kBlk) void block_sweep_widen_dot_kernel(CsrT<T> a, 
                                                                      const T* __restrict__ dinv, T omega,
                                                                      double* __restrict__ z64,
                                                                      const double* __restrict__ r64,
-                                                                     double* __restrict__ partials, int ntiles) {
+                                                                     double* __restrict__ partials, int ntiles,
+                                                                     const double* __restrict__ live) {
     using VT = typename Vec16<T>::type;
     constexpr int V = Vec16<T>::n;
     constexpr int LPR = K / V;
@@ -393,10 +404,11 @@ __global__ __launch_bounds__(kBlk) void block_sweep_widen_dot_kernel(CsrT<T> a, 
     const int lb = logical_block();
     const int sub = threadIdx.x / LPR;
     const int c0 = (threadIdx.x % LPR) * V;
+    const int nt = (live && c0 >= (int)*live) ? 0 : ntiles;
     double d[V];
 #pragma unroll
     for (int e = 0; e < V; ++e) d[e] = 0.0;
-    for (int t = lb; t < ntiles; t += gridDim.x) {
+    for (int t = lb; t < nt; t += gridDim.x) {
         const int i = t * RPT + sub;
         if (i >= a.rows) break;
         const VT s = row_gather_sum<T, K>(a, g, a.rp[i], a.rp[i + 1], c0);
@@ -419,14 +431,16 @@ template <class T, int K>
 __global__ __launch_bounds__(kBlk) void block_widen_dot_kernel(int n, const T* __restrict__ x,
                                                                double* __restrict__ z64,
                                                                const double* __restrict__ r64,
-                                                               double* __restrict__ partials, int ntiles) {
+                                                               double* __restrict__ partials, int ntiles,
+                                                               const double* __restrict__ live) {
     constexpr int LPR = K / 2;
     constexpr int RPT = kBlk / LPR;
     const int lb = logical_block();
     const int sub = threadIdx.x / LPR;
     const int c0 = (threadIdx.x % LPR) * 2;
+    const int nt = (live && c0 >= (int)*live) ? 0 : ntiles;
     double d[2] = {0.0, 0.0};
-    for (int t = lb; t < ntiles; t += gridDim.x) {
+    for (int t = lb; t < nt; t += gridDim.x) {
         const int i = t * RPT + sub;
         if (i >= n) break;
         const int o = i * K + c0;
@@ -482,10 +496,12 @@ __global__ __launch_bounds__(64) void block_converge_kernel(int k, double* __res
 
 template <class T>
 __global__ __launch_bounds__(kBlk) void block_dense_kernel(int n, int k, const double* __restrict__ ainv,
-                                                           const T* __restrict__ b, T* __restrict__ y) {
+                                                           const T* __restrict__ b, T* __restrict__ y,
+                                                           const double* __restrict__ live) {
     const int idx = blockIdx.x * kBlk + threadIdx.x;
     if (idx >= n * k) return;
     const int i = idx / k, c = idx % k;
+    if (live && c >= (int)*live) return;
     const double* row = ainv + (size_t)i * n;
     double s = 0.0;
     for (int j = 0; j < n; ++j) s += row[j] * (double)b[j * k + c];
@@ -525,7 +541,7 @@ int elem_grid(int64_t count) {
 
 template <class T, int K>
 void block_op_k(BlockOp op, const CsrT<T>& a, const T* g, const T* u, const T* dinv, T omega, T* y, T* y2,
-                double* acc, hipStream_t st) {
+                double* acc, const double* live, hipStream_t st) {
     constexpr int LPR = K / Vec16<T>::n;
     constexpr int RPT = kBlk / LPR;
     const int ntiles = std::max(1, (a.rows + RPT - 1) / RPT);
@@ -534,7 +550,7 @@ void block_op_k(BlockOp op, const CsrT<T>& a, const T* g, const T* u, const T* d
 #define AMG_BLOCK_CASE(OPV)                                                                             \
     case OPV:                                                                                           \
         hipLaunchKernelGGL((block_row_kernel<T, K, OPV>), dim3(grid), dim3(kBlk), 0, st, a, g, u, dinv, \
-                           omega, y, y2, acc, ntiles);                                                  \
+                           omega, y, y2, acc, ntiles, live);                                            \
         break;
         AMG_BLOCK_CASE(kBSpmv)
         AMG_BLOCK_CASE(kBSpmvScale)
@@ -549,10 +565,10 @@ void block_op_k(BlockOp op, const CsrT<T>& a, const T* g, const T* u, const T* d
 
 template <class T>
 void block_op(BlockOp op, int k, const CsrT<T>& a, const T* g, const T* u, const T* dinv, T omega, T* y,
-              T* y2, double* acc, hipStream_t st) {
-    if (k == 4) block_op_k<T, 4>(op, a, g, u, dinv, omega, y, y2, acc, st);
-    else if (k == 8) block_op_k<T, 8>(op, a, g, u, dinv, omega, y, y2, acc, st);
-    else block_op_k<T, 16>(op, a, g, u, dinv, omega, y, y2, acc, st);
+              T* y2, double* acc, const double* live, hipStream_t st) {
+    if (k == 4) block_op_k<T, 4>(op, a, g, u, dinv, omega, y, y2, acc, live, st);
+    else if (k == 8) block_op_k<T, 8>(op, a, g, u, dinv, omega, y, y2, acc, live, st);
+    else block_op_k<T, 16>(op, a, g, u, dinv, omega, y, y2, acc, live, st);
 }
 
 // launch shape of the kernels that give a row K * 8 / 16 lanes (FP64 columns)
@@ -577,12 +593,12 @@ void with_width(int k, F&& f) {
 
 template <class T>
 void outer(int k, const CsrView& a, const double* x, const double* b, const T* dinvt, T omega, T* rt, T* zt,
-           double* r64, ColumnDots dot, hipStream_t st) {
+           double* r64, ColumnDots dot, const double* live, hipStream_t st) {
     with_width(k, [&]<int K>() {
         const int ntiles = fp64_tiles<K>(a.rows);
         const int grid = round8(std::min(ntiles, kGridCap));
         hipLaunchKernelGGL((block_outer_kernel<T, K>), dim3(grid), dim3(kBlk), 0, st, a, x, b, dinvt, omega, rt,
-                           zt, r64, dot.partials, ntiles);
+                           zt, r64, dot.partials, ntiles, live);
         finish<K>(grid, dot, st);
     });
 }
@@ -590,36 +606,37 @@ void outer(int k, const CsrView& a, const double* x, const double* b, const T* d
 template <class T>
 void cg_xr(int n, int k, double* x, double* r, const double* p, const double* q, const double* scal, int i_num,
            int i_den, int i_act, double* flags, const T* dinvt, T omega, T* rt, T* zt, ColumnDots norms,
-           hipStream_t st) {
+           const double* live, hipStream_t st) {
     with_width(k, [&]<int K>() {
         const int ntiles = fp64_tiles<K>(n);
         const int grid = round8(std::min(ntiles, kGridCap));
         hipLaunchKernelGGL((block_cg_xr_kernel<T, K>), dim3(grid), dim3(kBlk), 0, st, n, x, r, p, q, scal, i_num,
-                           i_den, i_act, flags, dinvt, omega, rt, zt, norms.partials, ntiles);
+                           i_den, i_act, flags, dinvt, omega, rt, zt, norms.partials, ntiles, live);
         finish<K>(grid, norms, st);
     });
 }
 
 template <class T>
 void sweep_widen_dot(int k, const CsrT<T>& a, const T* g, const T* u, const T* dinv, T omega, double* z64,
-                     const double* r64, ColumnDots dot, hipStream_t st) {
+                     const double* r64, ColumnDots dot, const double* live, hipStream_t st) {
     with_width(k, [&]<int K>() {
         constexpr int RPT = kBlk / (K / Vec16<T>::n);
         const int ntiles = std::max(1, (a.rows + RPT - 1) / RPT);
         const int grid = round8(std::min(ntiles, kGridCap));
         hipLaunchKernelGGL((block_sweep_widen_dot_kernel<T, K>), dim3(grid), dim3(kBlk), 0, st, a, g, u, dinv,
-                           omega, z64, r64, dot.partials, ntiles);
+                           omega, z64, r64, dot.partials, ntiles, live);
         finish<K>(grid, dot, st);
     });
 }
 
 template <class T>
-void widen_dot(int n, int k, const T* x, double* z64, const double* r64, ColumnDots dot, hipStream_t st) {
+void widen_dot(int n, int k, const T* x, double* z64, const double* r64, ColumnDots dot, const double* live,
+               hipStream_t st) {
     with_width(k, [&]<int K>() {
         const int ntiles = fp64_tiles<K>(n);
         const int grid = round8(std::min(ntiles, kGridCap));
         hipLaunchKernelGGL((block_widen_dot_kernel<T, K>), dim3(grid), dim3(kBlk), 0, st, n, x, z64, r64,
-                           dot.partials, ntiles);
+                           dot.partials, ntiles, live);
         finish<K>(grid, dot, st);
     });
 }
@@ -631,33 +648,36 @@ int block_width(int nrhs) { return nrhs <= 4 ? 4 : (nrhs <= 8 ? 8 : 16); }
 int block_partials_needed() { return kGridCap * 16; }
 
 void launch_block_op(BlockOp op, int k, const CsrT<double>& a, const double* g, const double* u,
-                     const double* dinv, double omega, double* y, double* y2, double* acc, hipStream_t st) {
-    block_op<double>(op, k, a, g, u, dinv, omega, y, y2, acc, st);
+                     const double* dinv, double omega, double* y, double* y2, double* acc, hipStream_t st,
+                     const double* live) {
+    block_op<double>(op, k, a, g, u, dinv, omega, y, y2, acc, live, st);
 }
 
 void launch_block_op(BlockOp op, int k, const CsrT<float>& a, const float* g, const float* u,
-                     const float* dinv, float omega, float* y, float* y2, double* acc, hipStream_t st) {
-    block_op<float>(op, k, a, g, u, dinv, omega, y, y2, acc, st);
+                     const float* dinv, float omega, float* y, float* y2, double* acc, hipStream_t st,
+                     const double* live) {
+    block_op<float>(op, k, a, g, u, dinv, omega, y, y2, acc, live, st);
 }
 
 void launch_block_outer_residual(int k, const CsrView& a, const double* x, const double* b,
                                  const double* dinvt, double omega, double* rt, double* zt, double* r64,
-                                 ColumnDots norms2, hipStream_t st) {
-    outer<double>(k, a, x, b, dinvt, omega, rt, zt, r64, norms2, st);
+                                 ColumnDots norms2, hipStream_t st, const double* live) {
+    outer<double>(k, a, x, b, dinvt, omega, rt, zt, r64, norms2, live, st);
 }
 
 void launch_block_outer_residual(int k, const CsrView& a, const double* x, const double* b,
                                  const float* dinvt, float omega, float* rt, float* zt, double* r64,
-                                 ColumnDots norms2, hipStream_t st) {
-    outer<float>(k, a, x, b, dinvt, omega, rt, zt, r64, norms2, st);
+                                 ColumnDots norms2, hipStream_t st, const double* live) {
+    outer<float>(k, a, x, b, dinvt, omega, rt, zt, r64, norms2, live, st);
 }
 
-void launch_block_spmv_dot(int k, const CsrView& a, const double* p, double* q, ColumnDots dot, hipStream_t st) {
+void launch_block_spmv_dot(int k, const CsrView& a, const double* p, double* q, ColumnDots dot, hipStream_t st,
+                           const double* live) {
     with_width(k, [&]<int K>() {
         const int ntiles = fp64_tiles<K>(a.rows);
         const int grid = round8(std::min(ntiles, kGridCap));
         hipLaunchKernelGGL((block_spmv_dot_kernel<K>), dim3(grid), dim3(kBlk), 0, st, a, p, q, dot.partials,
-                           ntiles);
+                           ntiles, live);
         finish<K>(grid, dot, st);
     });
 }
@@ -665,23 +685,24 @@ void launch_block_spmv_dot(int k, const CsrView& a, const double* p, double* q, 
 void launch_block_cg_update_xr(int n, int k, double* x, double* r, const double* p, const double* q,
                                const double* scal, int i_num, int i_den, int i_act, double* flags,
                                const double* dinvt, double omega, double* rt, double* zt, ColumnDots norms,
-                               hipStream_t st) {
-    cg_xr<double>(n, k, x, r, p, q, scal, i_num, i_den, i_act, flags, dinvt, omega, rt, zt, norms, st);
+                               hipStream_t st, const double* live) {
+    cg_xr<double>(n, k, x, r, p, q, scal, i_num, i_den, i_act, flags, dinvt, omega, rt, zt, norms, live, st);
 }
 
 void launch_block_cg_update_xr(int n, int k, double* x, double* r, const double* p, const double* q,
                                const double* scal, int i_num, int i_den, int i_act, double* flags,
                                const float* dinvt, float omega, float* rt, float* zt, ColumnDots norms,
-                               hipStream_t st) {
-    cg_xr<float>(n, k, x, r, p, q, scal, i_num, i_den, i_act, flags, dinvt, omega, rt, zt, norms, st);
+                               hipStream_t st, const double* live) {
+    cg_xr<float>(n, k, x, r, p, q, scal, i_num, i_den, i_act, flags, dinvt, omega, rt, zt, norms, live, st);
 }
 
 void launch_block_cg_update_p(int n, int k, double* p, const double* z, const double* scal, int i_num,
-                              int i_den, int i_act, int i_restart, bool restart_all, hipStream_t st) {
+                              int i_den, int i_act, int i_restart, bool restart_all, hipStream_t st,
+                              const double* live) {
     with_width(k, [&]<int K>() {
         const int grid = std::min(fp64_tiles<K>(n), kGridCap);
         hipLaunchKernelGGL((block_cg_p_kernel<K>), dim3(grid), dim3(kBlk), 0, st, n, p, z, scal, i_num, i_den,
-                           i_act, i_restart, restart_all ? 1 : 0);
+                           i_act, i_restart, restart_all ? 1 : 0, live);
     });
 }
 
@@ -725,35 +746,36 @@ void launch_block_column_out(int n, int k, int c, const double* blk, double* v, 
 
 void launch_block_sweep_widen_dot(int k, const CsrT<double>& a, const double* g, const double* u,
                                   const double* dinv, double omega, double* z64, const double* r64,
-                                  ColumnDots dot, hipStream_t st) {
-    sweep_widen_dot<double>(k, a, g, u, dinv, omega, z64, r64, dot, st);
+                                  ColumnDots dot, hipStream_t st, const double* live) {
+    sweep_widen_dot<double>(k, a, g, u, dinv, omega, z64, r64, dot, live, st);
 }
 
 void launch_block_sweep_widen_dot(int k, const CsrT<float>& a, const float* g, const float* u,
                                   const float* dinv, float omega, double* z64, const double* r64,
-                                  ColumnDots dot, hipStream_t st) {
-    sweep_widen_dot<float>(k, a, g, u, dinv, omega, z64, r64, dot, st);
+                                  ColumnDots dot, hipStream_t st, const double* live) {
+    sweep_widen_dot<float>(k, a, g, u, dinv, omega, z64, r64, dot, live, st);
 }
 
 void launch_block_widen_dot(int n, int k, const double* x, double* z64, const double* r64, ColumnDots dot,
-                            hipStream_t st) {
-    widen_dot<double>(n, k, x, z64, r64, dot, st);
+                            hipStream_t st, const double* live) {
+    widen_dot<double>(n, k, x, z64, r64, dot, live, st);
 }
 
 void launch_block_widen_dot(int n, int k, const float* x, double* z64, const double* r64, ColumnDots dot,
-                            hipStream_t st) {
-    widen_dot<float>(n, k, x, z64, r64, dot, st);
+                            hipStream_t st, const double* live) {
+    widen_dot<float>(n, k, x, z64, r64, dot, live, st);
 }
 
 void launch_block_dense_matvec(int n, int k, const double* ainv, const double* b, double* y,
-                               hipStream_t st) {
+                               hipStream_t st, const double* live) {
     hipLaunchKernelGGL(block_dense_kernel<double>, dim3((n * k + kBlk - 1) / kBlk), dim3(kBlk), 0, st, n, k,
-                       ainv, b, y);
+                       ainv, b, y, live);
 }
 
-void launch_block_dense_matvec(int n, int k, const double* ainv, const float* b, float* y, hipStream_t st) {
+void launch_block_dense_matvec(int n, int k, const double* ainv, const float* b, float* y, hipStream_t st,
+                               const double* live) {
     hipLaunchKernelGGL(block_dense_kernel<float>, dim3((n * k + kBlk - 1) / kBlk), dim3(kBlk), 0, st, n, k,
-                       ainv, b, y);
+                       ainv, b, y, live);
 }
 
 void launch_block_accumulate(int64_t count, double* x, const float* e, hipStream_t st) {

@@ -27,6 +27,12 @@ enum BlockOp : int {
 };
 
 // Block width (columns held per row) used for nrhs right-hand sides: 4, 8 or 16.
+//
+// Every launcher below that takes `live` computes only the leading columns
+// when it is not null: *live (a device double) is the number of leading
+// columns that matter, and lanes whose columns all lie past it do nothing
+// (those columns keep whatever they held; their dot products are 0).  It is
+// read on the device, so captured launches follow later changes of it.
 int block_width(int nrhs);
 // Most partial sums any block reduction writes (for the partials buffer).
 int block_partials_needed();
@@ -37,10 +43,12 @@ int block_partials_needed();
 // the sweep's result added to it.
 void launch_block_op(BlockOp op, int k, const CsrT<double>& a, const double* g, const double* u,
                      const double* dinv, double omega, double* y, double* y2, double* acc,
-                     hipStream_t st);
+                     hipStream_t st,
+                     const double* live = nullptr);
 void launch_block_op(BlockOp op, int k, const CsrT<float>& a, const float* g, const float* u,
                      const float* dinv, float omega, float* y, float* y2, double* acc,
-                     hipStream_t st);
+                     hipStream_t st,
+                     const double* live = nullptr);
 
 // Deterministic per-column reductions: per-workgroup partials (>=
 // block_partials_needed() doubles) summed in a fixed order into result[0..K).
@@ -55,17 +63,20 @@ struct ColumnDots {
 // sum_i r_ic^2 per column.
 void launch_block_outer_residual(int k, const CsrView& a, const double* x, const double* b,
                                  const double* dinvt, double omega, double* rt, double* zt, double* r64,
-                                 ColumnDots norms2, hipStream_t st);
+                                 ColumnDots norms2, hipStream_t st,
+                                 const double* live = nullptr);
 void launch_block_outer_residual(int k, const CsrView& a, const double* x, const double* b,
                                  const float* dinvt, float omega, float* rt, float* zt, double* r64,
-                                 ColumnDots norms2, hipStream_t st);
+                                 ColumnDots norms2, hipStream_t st,
+                                 const double* live = nullptr);
 
 // ---- conjugate gradients on every column at once (FP64 iterates) -----------
 // Column c's scalars live in scal[i + c].  Columns with scal[i_act + c] == 0
 // are frozen (converged): their x, r and p are not changed.
 
 // q = A p (FP64) with dot[c] = p_c . q_c
-void launch_block_spmv_dot(int k, const CsrView& a, const double* p, double* q, ColumnDots dot, hipStream_t st);
+void launch_block_spmv_dot(int k, const CsrView& a, const double* p, double* q, ColumnDots dot, hipStream_t st,
+                           const double* live = nullptr);
 // alpha_c = scal[i_num+c] / scal[i_den+c]; x += alpha p; r -= alpha q;
 // norms[c] = |r_c|^2; rt = (T) r and zt = omega dinvt rt.  A column whose
 // denominator is not positive and finite is left unchanged and sets
@@ -73,16 +84,19 @@ void launch_block_spmv_dot(int k, const CsrView& a, const double* p, double* q, 
 void launch_block_cg_update_xr(int n, int k, double* x, double* r, const double* p, const double* q,
                                const double* scal, int i_num, int i_den, int i_act, double* flags,
                                const double* dinvt, double omega, double* rt, double* zt, ColumnDots norms,
-                               hipStream_t st);
+                               hipStream_t st,
+                               const double* live = nullptr);
 void launch_block_cg_update_xr(int n, int k, double* x, double* r, const double* p, const double* q,
                                const double* scal, int i_num, int i_den, int i_act, double* flags,
                                const float* dinvt, float omega, float* rt, float* zt, ColumnDots norms,
-                               hipStream_t st);
+                               hipStream_t st,
+                               const double* live = nullptr);
 // p = z + beta_c p with beta_c = scal[i_num+c] / scal[i_den+c] on active
 // columns; p = z in every column if restart_all, else in the columns with
 // scal[i_restart+c] != 0 (i_restart < 0: none)
 void launch_block_cg_update_p(int n, int k, double* p, const double* z, const double* scal, int i_num,
-                              int i_den, int i_act, int i_restart, bool restart_all, hipStream_t st);
+                              int i_den, int i_act, int i_restart, bool restart_all, hipStream_t st,
+                              const double* live = nullptr);
 // Fresh start of the columns with scal[i_load+c] != 0: x_c = 0, r_c = b_c,
 // rt_c = (T) b_c, zt_c = omega dinvt rt_c, norms[c] = |b_c|^2 (other columns
 // untouched; their norms are 0)
@@ -107,22 +121,28 @@ void launch_block_column_out(int n, int k, int c, const double* blk, double* v, 
 // with dot[c] = r64_c . z64_c (the CG inner product r.z)
 void launch_block_sweep_widen_dot(int k, const CsrT<double>& a, const double* g, const double* u,
                                   const double* dinv, double omega, double* z64, const double* r64,
-                                  ColumnDots dot, hipStream_t st);
+                                  ColumnDots dot, hipStream_t st,
+                                  const double* live = nullptr);
 void launch_block_sweep_widen_dot(int k, const CsrT<float>& a, const float* g, const float* u,
                                   const float* dinv, float omega, double* z64, const double* r64,
-                                  ColumnDots dot, hipStream_t st);
+                                  ColumnDots dot, hipStream_t st,
+                                  const double* live = nullptr);
 // z64 = (double) x with dot[c] = r64_c . z64_c
 void launch_block_widen_dot(int n, int k, const double* x, double* z64, const double* r64, ColumnDots dot,
-                            hipStream_t st);
+                            hipStream_t st,
+                            const double* live = nullptr);
 void launch_block_widen_dot(int n, int k, const float* x, double* z64, const double* r64, ColumnDots dot,
-                            hipStream_t st);
+                            hipStream_t st,
+                            const double* live = nullptr);
 
 // Y = Ainv B for the FP64 dense inverse of the coarsest operator (n x n) and
 // K-wide blocks; accumulation in FP64.
 void launch_block_dense_matvec(int n, int k, const double* ainv, const double* b, double* y,
-                               hipStream_t st);
+                               hipStream_t st,
+                               const double* live = nullptr);
 void launch_block_dense_matvec(int n, int k, const double* ainv, const float* b, float* y,
-                               hipStream_t st);
+                               hipStream_t st,
+                               const double* live = nullptr);
 
 // X += (double) E over n * k entries
 void launch_block_accumulate(int64_t count, double* x, const float* e, hipStream_t st);

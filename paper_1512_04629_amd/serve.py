@@ -1,9 +1,11 @@
 """Continuous-batching solve server on one GPU.
 
 Requests (a problem key and a right-hand side) arrive over time.  Every
-problem's hierarchy is built once, sparsified, and kept resident, each on a
-HIP stream of its own so that work for different problems overlaps on the
-device.  A problem with waiting requests gets a batch engine (``amg_batch``
+problem's hierarchy is built once, sparsified, and kept resident.  Problems
+are grouped by size onto a few HIP streams (as many as the runtime has
+hardware queues by default), so that work for problems of different sizes
+overlaps on the device and the launches of a small problem never wait in a
+hardware queue behind the long kernels of a large one.  A problem with waiting requests gets a batch engine (``amg_batch``
 in the C ABI): up to ``slots`` right-hand sides are solved together by PCG,
 one CG recurrence per slot, and a slot that finishes takes the next waiting
 request at the next iteration while the other slots keep iterating.  A
@@ -56,12 +58,13 @@ class ServeStats:
     peak_bytes: int = 0
     waits_for_budget: int = 0
     latencies: list = field(default_factory=list)
+    occupancy: dict = field(default_factory=dict)    # key -> [occupied slot-steps, steps]
 
 
 class SolveServer:
     def __init__(self, problems: dict, hbm_budget: int, slots: int = 16, precision: int = 32,
                  tol: float = 1e-10, maxit: int = 300, gamma: float = 0.01, step_target_s: float = 1.5e-3,
-                 max_iters_per_step: int = 8, graphs: bool = True):
+                 max_iters_per_step: int = 8, graphs: bool = True, stream_groups: int = 4):
         torch = amg._torch()
         self.slots, self.precision, self.tol, self.maxit = int(slots), int(precision), float(tol), int(maxit)
         # iterations per engine step: as many as fit in step_target_s (so that
@@ -72,10 +75,13 @@ class SolveServer:
         self.iter_time: dict = {}
         self.budget = int(hbm_budget)
         self.hier, self.streams = {}, {}
-        for key, A in problems.items():
-            s = torch.cuda.Stream()
+        by_size = sorted(problems, key=lambda k: (problems[k].n, k))
+        groups = max(1, min(int(stream_groups), len(by_size)))
+        pool = [torch.cuda.Stream() for _ in range(groups)]
+        for rank, key in enumerate(by_size):
+            s = pool[rank * groups // len(by_size)]
             with torch.cuda.stream(s):
-                h = amg.Hierarchy(A)
+                h = amg.Hierarchy(problems[key])
                 if gamma > 0:
                     h.sparsify(gamma, 2)
             self.hier[key], self.streams[key] = h, s
@@ -168,7 +174,11 @@ class SolveServer:
                     continue
                 est = self.iter_time.get(key)
                 iters = 1 if est is None else max(1, min(self.max_iters, int(self.step_target_s / est)))
+                busy = int(((eng.states() == amg.Batch.SUBMITTED) | (eng.states() == amg.Batch.ITERATING)).sum())
                 if eng.step(iters):
+                    occ = self.stats.occupancy.setdefault(key, [0, 0])
+                    occ[0] += busy * iters
+                    occ[1] += iters
                     in_flight[key] = (time.perf_counter(), iters)
                     self.last_used[key] = time.perf_counter()
                     self.stats.steps += 1
