@@ -15,14 +15,14 @@
  *              Section 3, algorithm sparse_hybrid_setup, prescribes.
  *   sparsify   Section 2.1, Algorithm 3 (first loop: minimal pattern M and
  *              keep set N) with the diagonal-lumping loop of Algorithm 3b
- *              (Section 3.1), Sparse Galerkin variant (M from the Galerkin
- *              A_{l-1}).
+ *              (Section 3.1); Sparse Galerkin (M from the Galerkin A_{l-1})
+ *              or Hybrid Galerkin (M from the sparsified \hat A_{l-1}).
  *   solve      Section 2, algorithm amg_solve (V-cycle); Section 6,
  *              algorithm adaptive_solve (windowed reintroduction).
  *
- * Readings where the paper is silent or garbled (strength formula, RS split,
- * direct interpolation, canonical summation order, gamma ladder, window
- * rules) are listed in the design doc; each function names the one it follows.
+ * Where the paper is silent or garbled (strength formula, RS split, direct
+ * interpolation, canonical summation order, gamma ladder, window rules) the
+ * comment above each function states the reading it implements.
  */
 #include <math.h>
 #include <stdint.h>
@@ -60,6 +60,7 @@ typedef struct {
 typedef struct {
     int nlev;
     Level *lv;
+    int hybrid;     /* 0: Sparse Galerkin, 1: Hybrid Galerkin (Section 3)   */
     double omega;
     int nu_pre, nu_post;
     /* coarsest-level dense factor */
@@ -538,7 +539,7 @@ static void coarse_solve(const Hier *h, const double *b, double *x) {
 /* than max_levels levels exist; stop if the split yields no C point or     */
 /* only C points.                                                           */
 /* ------------------------------------------------------------------------ */
-static int build_M(Hier *h, int l);
+static int build_M(Hier *h, int l, const Mat *fine_op);
 
 void or_free(Hier *h);
 
@@ -582,7 +583,7 @@ int or_setup(int n, const int *rp, const int *ci, const double *v, double theta,
         long nnz = lv->A.rp[lv->A.nr];
         lv->keep = (unsigned char *)malloc((size_t)(nnz > 0 ? nnz : 1));
         memset(lv->keep, 1, (size_t)(nnz > 0 ? nnz : 1));
-        if (l >= 1 && (rc = build_M(h, l))) return rc;
+        if (l >= 1 && (rc = build_M(h, l, &h->lv[l - 1].A))) return rc;
     }
     h->b = (double **)calloc((size_t)h->nlev, sizeof(double *));
     h->x = (double **)calloc((size_t)h->nlev, sizeof(double *));
@@ -600,23 +601,25 @@ int or_setup(int n, const int *rp, const int *ci, const double *v, double theta,
 
 /* ------------------------------------------------------------------------ */
 /* Minimal sparsity pattern (Algorithm 3, first line after form-injection): */
-/* M = edges(Phat^T A P + P^T A Phat) with A = A_{l-1} Galerkin (Sparse      */
-/* Galerkin) and Phat the injection onto the C points.  Row I of Phat^T A P  */
-/* is the union over l' in row c(I) of A of the columns of row l' of P;      */
-/* P^T A Phat is its transpose.  Structural pattern, stored as one flag per */
-/* nonzero of A_l.                                                          */
+/* M = edges(Phat^T A P + P^T A Phat) with Phat the injection onto the C     */
+/* points and A the finer operator: the Galerkin A_{l-1} for Sparse Galerkin */
+/* and the sparsified \hat A_{l-1} for Hybrid Galerkin (Section 3, the two  */
+/* sparsify calls of sparse_hybrid_setup).  Row I of Phat^T A P is the union */
+/* over l' in row c(I) of A of the columns of row l' of P; P^T A Phat is its */
+/* transpose.  Structural pattern, stored as one flag per nonzero of A_l.   */
 /* ------------------------------------------------------------------------ */
-static int build_M(Hier *h, int l) {
+static int build_M(Hier *h, int l, const Mat *fine_op) {
     Level *fine = &h->lv[l - 1];
     Level *lv = &h->lv[l];
     long nnz = lv->A.rp[lv->A.nr];
+    free(lv->inM);
     lv->inM = (unsigned char *)calloc((size_t)(nnz > 0 ? nnz : 1), 1);
     if (!lv->inM) return OR_ENOMEM;
-    for (int f = 0; f < fine->A.nr; ++f) {
+    for (int f = 0; f < fine_op->nr; ++f) {
         if (!fine->cf[f]) continue;
         int I = fine->cidx[f];
-        for (int p = fine->A.rp[f]; p < fine->A.rp[f + 1]; ++p) {
-            int lp = fine->A.ci[p];
+        for (int p = fine_op->rp[f]; p < fine_op->rp[f + 1]; ++p) {
+            int lp = fine_op->ci[p];
             for (int q = fine->P.rp[lp]; q < fine->P.rp[lp + 1]; ++q) {
                 int J = fine->P.ci[q];
                 long a = find_pos(&lv->A, I, J);
@@ -701,10 +704,25 @@ int or_sparsify(Hier *h, const double *gamma) {
     for (int l = 1; l < h->nlev; ++l)
         if (!(gamma[l] >= 0.0 && gamma[l] <= 1.0)) return OR_EINVAL;
     for (int l = 1; l < h->nlev; ++l) {
-        int rc = sparsify_level(h, l, gamma[l]);
-        if (rc) return rc;
+        int rc = 0;
+        /* Hybrid Galerkin: M_l from \hat A_{l-1}, which the previous pass of
+           this loop has just produced (finest level first) */
+        if (h->hybrid && (rc = build_M(h, l, &h->lv[l - 1].Ah))) return rc;
+        if ((rc = sparsify_level(h, l, gamma[l]))) return rc;
     }
     return coarse_factor(h);
+}
+
+/* Selects Sparse (0) or Hybrid (1) Galerkin for later sparsify and
+   reintroduce calls and rebuilds every M_l from the current operators. */
+int or_set_method(Hier *h, int hybrid) {
+    if (hybrid != 0 && hybrid != 1) return OR_EINVAL;
+    h->hybrid = hybrid;
+    for (int l = 1; l < h->nlev; ++l) {
+        int rc = build_M(h, l, hybrid ? &h->lv[l - 1].Ah : &h->lv[l - 1].A);
+        if (rc) return rc;
+    }
+    return OR_OK;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -719,11 +737,19 @@ int or_reintroduce(Hier *h, int s, double gamma_min, int *first_changed) {
         if (h->lv[l].gamma > 0.0) { ls = l; break; }
     if (first_changed) *first_changed = ls;
     if (ls < 0) return OR_NOTHING;
-    for (int l = ls; l < ls + s && l < h->nlev; ++l) {
-        double g = h->lv[l].gamma / 10.0;
-        if (!(g >= gamma_min)) g = 0.0;
-        int rc = sparsify_level(h, l, g);
-        if (rc) return rc;
+    for (int l = ls; l < h->nlev; ++l) {
+        int rc = 0;
+        double g = h->lv[l].gamma;
+        if (l < ls + s) {
+            g = g / 10.0;
+            if (!(g >= gamma_min)) g = 0.0;
+        } else if (!h->hybrid || g == 0.0) {
+            continue;
+        }
+        /* Hybrid Galerkin: a coarser level's M depends on the operator just
+           changed, so every coarser sparsified level is redone at its gamma */
+        if (h->hybrid && (rc = build_M(h, l, &h->lv[l - 1].Ah))) return rc;
+        if ((rc = sparsify_level(h, l, g))) return rc;
     }
     return coarse_factor(h);
 }

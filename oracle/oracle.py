@@ -69,6 +69,7 @@ def _load():
         lib.or_export_rowmax.argtypes = [P, C.c_int, dp]
         lib.or_sparsify.argtypes = [P, dp]
         lib.or_reintroduce.argtypes = [P, C.c_int, C.c_double, C.POINTER(C.c_int)]
+        lib.or_set_method.argtypes = [P, C.c_int]
         lib.or_vcycle.argtypes = [P, dp, dp]
         lib.or_level_op.argtypes = [P, C.c_int, C.c_int, dp, dp, dp]
         lib.or_solve.argtypes = [P, dp, dp, C.c_int, C.c_double, C.c_int, C.c_int, C.c_int,
@@ -185,6 +186,13 @@ class OracleAMG:
 
     def sparsify_from(self, gamma: float, first_level: int = 2) -> None:
         self.sparsify([0.0 if l < first_level else gamma for l in range(self.nlev)])
+
+    def set_method(self, hybrid: bool) -> None:
+        """Sparse Galerkin (False) or Hybrid Galerkin (True) for later sparsify /
+        reintroduce calls (Section 3, sparse_hybrid_setup)."""
+        rc = self._lib.or_set_method(self._h, int(bool(hybrid)))
+        if rc != OK:
+            raise ValueError(f"set_method status {rc}")
 
     def reintroduce(self, s: int = 1, gamma_min: float = 0.01):
         first = C.c_int(-1)

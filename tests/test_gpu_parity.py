@@ -1,6 +1,6 @@
 """Parity of the HIP path (through the C ABI) with the CPU oracle.
 
-Bars (derivations in the design doc):
+Bars:
   * setup, C/F split, P, R, A_l, minimal pattern M, row maxima, keep flags,
     sparsified pattern and kept off-diagonal values: bit-exact;
   * lumped diagonal: |d_gpu - d_or| <= 1e-13 (|a_ii| + sum_dropped |a_ij|);
