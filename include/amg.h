@@ -124,6 +124,17 @@ amg_status amg_sparsify(amg_handle h, double gamma, int32_t first_level);
    (gamma[0] is ignored: A_0 is never sparsified; levels >= count get 0). */
 amg_status amg_sparsify_levels(amg_handle h, const double* gamma, int32_t count);
 
+/* Selects the sparsification method for later amg_sparsify,
+   amg_sparsify_levels, amg_reintroduce and adaptive solves (Section 3,
+   sparse_hybrid_setup).  AMG_SPARSE_GALERKIN (default): the minimal pattern
+   M_l comes from the Galerkin A_{l-1}.  AMG_HYBRID_GALERKIN: from the
+   sparsified \hat A_{l-1} (levels are sparsified finest first, and a
+   reintroduction also redoes every coarser sparsified level at its gamma,
+   since its M depends on the finer operator).  The hierarchy is not changed
+   until the next sparsify. */
+enum { AMG_SPARSE_GALERKIN = 0, AMG_HYBRID_GALERKIN = 1 };
+amg_status amg_set_method(amg_handle h, int32_t method);
+
 /* Reintroduction (Section 6, adaptive_solve and its Example): find the
    finest coarse level with gamma > 0 and, on it and the next s-1 levels,
    set gamma <- gamma/10 (0 if gamma/10 < gamma_min), re-sparsifying them

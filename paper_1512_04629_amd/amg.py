@@ -35,7 +35,8 @@ KERNEL = {"JACOBI": 0, "JACOBI_ZERO": 1, "RESIDUAL": 2, "RESTRICT": 3, "INTERP":
 # every symbol include/amg.h declares
 ABI_SYMBOLS = (
     "amg_setup_params_default", "amg_solve_params_default", "amg_setup_from_csr",
-    "amg_sparsify", "amg_sparsify_levels", "amg_reintroduce", "amg_solve", "amg_vcycle", "amg_vcycle32",
+    "amg_sparsify", "amg_sparsify_levels", "amg_set_method", "amg_reintroduce", "amg_solve", "amg_vcycle",
+    "amg_vcycle32",
     "amg_solve_block", "amg_vcycle_block", "amg_vcycle_block32", "amg_batch_bytes", "amg_batch_create",
     "amg_batch_submit", "amg_batch_step", "amg_batch_poll", "amg_batch_collect", "amg_batch_slots",
     "amg_batch_destroy", "amg_device_bytes", "amg_level_op", "amg_num_levels", "amg_get_level", "amg_export_level", "amg_export_mask",
@@ -88,6 +89,7 @@ def load_library():
     lib.amg_sparsify.argtypes = [vp, f64, i32]
     lib.amg_sparsify_levels.argtypes = [vp, vp, i32]
     lib.amg_reintroduce.argtypes = [vp, i32, f64, P(i32)]
+    lib.amg_set_method.argtypes = [vp, i32]
     lib.amg_solve.argtypes = [vp, vp, vp, P(SolveParams), P(SolveInfo), vp]
     lib.amg_vcycle.argtypes = [vp, vp, vp]
     lib.amg_vcycle32.argtypes = [vp, vp, vp]
@@ -119,7 +121,7 @@ def load_library():
     lib.amg_status_string.restype = C.c_char_p
     lib.amg_last_error.argtypes = [vp]
     lib.amg_last_error.restype = C.c_char_p
-    for name in ("amg_setup_from_csr", "amg_sparsify", "amg_sparsify_levels", "amg_reintroduce",
+    for name in ("amg_setup_from_csr", "amg_sparsify", "amg_sparsify_levels", "amg_set_method", "amg_reintroduce",
                  "amg_solve", "amg_vcycle", "amg_vcycle32", "amg_solve_block", "amg_vcycle_block",
                  "amg_vcycle_block32", "amg_batch_bytes", "amg_batch_create", "amg_batch_submit",
                  "amg_batch_step", "amg_batch_poll", "amg_batch_collect", "amg_batch_slots", "amg_device_bytes",
@@ -285,6 +287,11 @@ class Hierarchy:
     def sparsify_levels(self, gammas):
         g = np.ascontiguousarray(gammas, np.float64)
         self._check(self._lib.amg_sparsify_levels(self._h, g.ctypes.data, len(g)))
+
+    def set_method(self, hybrid: bool) -> None:
+        """Sparse Galerkin (False, default) or Hybrid Galerkin (True) for later
+        sparsify / reintroduce calls."""
+        self._check(self._lib.amg_set_method(self._h, 1 if hybrid else 0))
 
     def reintroduce(self, s: int = 1, gamma_min: float = 0.01):
         first = C.c_int32(-1)

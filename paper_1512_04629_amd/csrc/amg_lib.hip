@@ -87,6 +87,7 @@ struct DevLevel {
     uint8_t* keep = nullptr;      // keep flags of the last sparsification
     double* rowmax = nullptr;     // m_i of A
     bool have_m = false;
+    bool m_hybrid = false;        // in_m currently holds the Hybrid Galerkin pattern
     bool keep_valid = false;
     double gamma = 0.0;
     double *b = nullptr, *x = nullptr, *xt = nullptr, *r = nullptr;
@@ -152,6 +153,7 @@ struct amg_ctx {
     double* blk_partials = nullptr;
     double *blk_b = nullptr, *blk_x = nullptr;   // K-wide copies when nrhs is not a block width
     amg_batch_ctx* batch = nullptr;              // the continuous-batching engine, if any
+    int method = AMG_SPARSE_GALERKIN;            // which finer operator the minimal pattern uses
     int bcg_k = 0;                               // block CG vectors (FP64, K wide)
     double *bcg_r = nullptr, *bcg_p = nullptr, *bcg_q = nullptr, *bcg_z = nullptr;
     int blk_pack_k = 0;
@@ -451,6 +453,25 @@ void ensure_minimal_pattern(amg_ctx* h, int l) {
     c.have_m = true;
 }
 
+// Minimal pattern of level l from the finer operator the method prescribes
+// (Section 3, sparse_hybrid_setup): the Galerkin A_{l-1} (Sparse Galerkin)
+// or the current sparsified \hat A_{l-1} (Hybrid Galerkin), asynchronously.
+// The pattern of \hat A_{l-1} lies inside that of A_{l-1}, so this pattern
+// lies inside the Sparse Galerkin one, which ensure_minimal_pattern checked.
+void mark_minimal_pattern(amg_ctx* h, int l, bool hybrid) {
+    ensure_minimal_pattern(h, l);
+    DevLevel& c = h->lv[l];
+    if (!hybrid && !c.m_hybrid) return;
+    DevLevel& f = h->lv[l - 1];
+    const DevMat& fine = hybrid ? f.Ah : f.A;
+    ProfScope ps(h, AMG_K_SPARSIFY, l);
+    launch_fill_u8(c.A.nnz, c.in_m, 0, h->stream);
+    launch_mark_minimal_pattern(c.n, f.c_points, fine.rp, fine.ci, f.P.rp, f.P.ci, c.A.rp, c.A.ci, c.in_m,
+                                h->missing, h->stream);
+    check_launch();
+    c.m_hybrid = hybrid;
+}
+
 // Rebuilds the sparsified operators of the given levels at the given
 // tolerances, asynchronously on the handle's stream.  The storage of a
 // sparsified operator is allocated once with the capacity of the Galerkin
@@ -487,6 +508,9 @@ void sparsify_levels(amg_ctx* h, const std::vector<std::pair<int, double>>& todo
             c.gamma = 0.0;
             c.keep_valid = false;
         } else {
+            // levels are processed finest first, so a Hybrid pattern sees the
+            // finer operator this call has just rebuilt
+            mark_minimal_pattern(h, l, h->method == AMG_HYBRID_GALERKIN);
             launch_keep_count(c.A.width, c.A.view(), c.in_m, c.rowmax, gamma, c.keep, h->cnt, h->stream);
             launch_exclusive_scan(c.n, h->cnt, c.Ahs.rp, h->scan_scratch, h->stream);
             launch_compact_lump(c.A.width, c.A.view(), c.keep, c.Ahs.rp, c.Ahs.ci, c.Ahs.v, c.dinv,
@@ -763,10 +787,16 @@ amg_status do_reintroduce(amg_ctx* h, int s, double gamma_min, int* first) {
     if (first) *first = ls;
     if (ls < 0) return AMG_NOTHING_TO_REINTRODUCE;
     std::vector<std::pair<int, double>> todo;
-    for (int l = ls; l < ls + s && l < (int)h->lv.size(); ++l) {
-        double g = h->lv[l].gamma / 10.0;
-        if (!(g >= gamma_min)) g = 0.0;
-        todo.emplace_back(l, g);
+    for (int l = ls; l < (int)h->lv.size(); ++l) {
+        if (l < ls + s) {
+            double g = h->lv[l].gamma / 10.0;
+            if (!(g >= gamma_min)) g = 0.0;
+            todo.emplace_back(l, g);
+        } else if (h->method == AMG_HYBRID_GALERKIN && h->lv[l].gamma > 0.0) {
+            // Hybrid Galerkin: this level's minimal pattern depends on the
+            // finer operator just changed, so it is redone at its gamma
+            todo.emplace_back(l, h->lv[l].gamma);
+        }
     }
     sparsify_levels(h, todo);
     return AMG_OK;
@@ -1770,6 +1800,13 @@ amg_status amg_sparsify_levels(amg_handle h, const double* gamma, int32_t count)
     });
 }
 
+amg_status amg_set_method(amg_handle h, int32_t method) {
+    if (!h || h->lv.empty() || h->batch) return AMG_ERR_STATE;
+    if (method != AMG_SPARSE_GALERKIN && method != AMG_HYBRID_GALERKIN) return AMG_ERR_INVALID_ARG;
+    h->method = method;
+    return AMG_OK;
+}
+
 amg_status amg_reintroduce(amg_handle h, int32_t s, double gamma_min, int32_t* first_changed_level) {
     if (!h || h->lv.empty() || h->batch) return AMG_ERR_STATE;
     if (s < 1 || !(gamma_min >= 0.0)) return AMG_ERR_INVALID_ARG;
@@ -1989,7 +2026,7 @@ amg_status amg_export_mask(amg_handle h, int32_t l, int32_t which, uint8_t* out)
     return guarded(h, [&] {
         DevLevel& v = h->lv[l];
         if (which == AMG_MASK_M) {
-            ensure_minimal_pattern(h, l);
+            mark_minimal_pattern(h, l, h->method == AMG_HYBRID_GALERKIN);
             download(h, out, v.in_m, v.A.nnz);
         } else if (which == AMG_MASK_KEEP) {
             if (v.keep_valid) download(h, out, v.keep, v.A.nnz);
