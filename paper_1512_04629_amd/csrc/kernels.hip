@@ -55,8 +55,11 @@ constexpr int kRowGridCap = AMG_ROW_GRID_CAP;   // row kernels loop over tiles b
 #ifndef AMG_VEC4
 #define AMG_VEC4 -1
 #endif
+// LDS-staged kernels: 2048 workgroups = 8 resident workgroups on each of the
+// 256 compute units, one full wave of the machine; measured best against
+// 1024, 3072 and 4096 (which leave a partial second wave).
 #ifndef AMG_STREAM_GRID_CAP
-#define AMG_STREAM_GRID_CAP 4096
+#define AMG_STREAM_GRID_CAP 2048
 #endif
 
 // Matrix entries are streamed once per launch; with AMG_NT they are loaded
