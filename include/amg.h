@@ -113,6 +113,23 @@ amg_status amg_setup_from_csr(int64_t n, const int32_t* row_ptr, const int32_t* 
                               void* stream, amg_alloc_fn alloc, amg_free_fn free_fn,
                               void* user, amg_handle* out);
 
+/* The method of non-Galerkin coarse grids (Section 2.1; amg_setup with its
+   optional sparsify): as amg_setup_from_csr, but each coarse product
+   A_l = P_{l-1}^T A_{l-1} P_{l-1} is sparsified as soon as it is formed, with
+   tolerance gamma[l] (l < count; 0 past the end; gamma[0] is ignored), the
+   minimal pattern from the hierarchy's finer operator, the keep set of
+   Algorithm 3 and diagonal lumping (Algorithm 3b), and it replaces the
+   product: the next level's strength, split, interpolation and product are
+   built from it.  The Galerkin operators are not kept, so nothing can be
+   reintroduced into them; the Sparse/Hybrid Galerkin post-pass (amg_sparsify)
+   and reintroduction still apply on top, relative to these operators.
+   gamma: host array, each entry in [0, 1]. */
+amg_status amg_setup_nongalerkin_from_csr(int64_t n, const int32_t* row_ptr, const int32_t* col,
+                                          const double* val, const amg_setup_params* params,
+                                          const double* gamma, int32_t count, void* stream,
+                                          amg_alloc_fn alloc, amg_free_fn free_fn, void* user,
+                                          amg_handle* out);
+
 /* Sparse Galerkin sparsification with diagonal lumping (Algorithm 3 keep set,
    Algorithm 3b loop) of every level l >= first_level (first_level >= 1) with
    drop tolerance gamma in [0, 1]; levels below first_level get gamma 0.  The

@@ -540,12 +540,18 @@ static void coarse_solve(const Hier *h, const double *b, double *x) {
 /* only C points.                                                           */
 /* ------------------------------------------------------------------------ */
 static int build_M(Hier *h, int l, const Mat *fine_op);
+static int sparsify_level(Hier *h, int l, double gamma);
+static int nongalerkin_level(Hier *h, int l, double gamma);
 
 void or_free(Hier *h);
 
+/* ng_gamma (nullable, ng_count entries): the method of non-Galerkin coarse
+   grids (Section 2.1; amg_setup with its optional sparsify): right after its
+   Galerkin product, A_{l+1} is sparsified with tolerance ng_gamma[l+1] and
+   replaces the product, so the next level is built from it. */
 int or_setup(int n, const int *rp, const int *ci, const double *v, double theta,
              int max_coarse, int max_levels, double omega, int nu_pre, int nu_post,
-             Hier **out) {
+             const double *ng_gamma, int ng_count, Hier **out) {
     *out = NULL;
     if (n <= 0 || !rp || !ci || !v || max_levels < 1 || max_coarse < 1) return OR_EINVAL;
     int rc = validate(n, rp, ci, v);
@@ -573,6 +579,11 @@ int or_setup(int n, const int *rp, const int *ci, const double *v, double theta,
         if ((rc = direct_interp(&cur->A, &cur->S, cur->cf, cur->cidx, nc, &cur->P))) return rc;
         if ((rc = mat_transpose(&cur->P, &cur->R))) return rc;
         if ((rc = galerkin(&cur->A, &cur->P, &cur->R, &h->lv[L + 1].A))) return rc;
+        if (ng_gamma) {
+            double g = L + 1 < ng_count ? ng_gamma[L + 1] : 0.0;
+            if (!(g >= 0.0 && g <= 1.0)) return OR_EINVAL;
+            if (g > 0.0 && (rc = nongalerkin_level(h, L + 1, g))) return rc;
+        }
         ++L;
     }
     h->nlev = L + 1;
@@ -695,6 +706,26 @@ static int sparsify_level(Hier *h, int l, double gamma) {
     mat_free(&lv->Ah);
     lv->Ah = nh;
     lv->gamma = gamma;
+    return OR_OK;
+}
+
+/* Non-Galerkin coarse grid: sparsify the product A_l just formed (minimal
+   pattern from the hierarchy's finer operator A_{l-1}, keep set of Algorithm
+   3, diagonal lumping of Algorithm 3b) and let the result be A_l itself. */
+static int nongalerkin_level(Hier *h, int l, double gamma) {
+    Level *lv = &h->lv[l];
+    long nnz = lv->A.rp[lv->A.nr];
+    int rc = build_M(h, l, &h->lv[l - 1].A);
+    if (rc) return rc;
+    lv->keep = (unsigned char *)malloc((size_t)(nnz > 0 ? nnz : 1));
+    if (!lv->keep) return OR_ENOMEM;
+    if ((rc = sparsify_level(h, l, gamma))) return rc;
+    mat_free(&lv->A);
+    lv->A = lv->Ah;
+    memset(&lv->Ah, 0, sizeof(Mat));
+    free(lv->keep); free(lv->inM); free(lv->rowmax);
+    lv->keep = NULL; lv->inM = NULL; lv->rowmax = NULL;
+    lv->gamma = 0.0;
     return OR_OK;
 }
 

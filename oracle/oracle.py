@@ -55,7 +55,7 @@ def _load():
         up = np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")
         lp = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
         lib.or_setup.argtypes = [C.c_int, ip, ip, dp, C.c_double, C.c_int, C.c_int, C.c_double,
-                                 C.c_int, C.c_int, C.POINTER(P)]
+                                 C.c_int, C.c_int, C.c_void_p, C.c_int, C.POINTER(P)]
         lib.or_setup.restype = C.c_int
         lib.or_free.argtypes = [P]
         lib.or_num_levels.argtypes = [P]
@@ -109,16 +109,22 @@ class OracleAMG:
     """Oracle hierarchy: Galerkin setup, Sparse Galerkin sparsify, solves."""
 
     def __init__(self, A, theta=0.25, max_coarse=49, max_levels=25, omega=2.0 / 3.0,
-                 nu_pre=1, nu_post=1):
+                 nu_pre=1, nu_post=1, nongalerkin_gamma=None):
+        """nongalerkin_gamma: per-level tolerances of the method of non-Galerkin
+        coarse grids (each coarse product sparsified during setup); None for the
+        Galerkin hierarchy."""
         lib = _load()
         self._lib = lib
         self.n = int(A.n)
         h = C.c_void_p()
+        ng = None if nongalerkin_gamma is None else np.ascontiguousarray(nongalerkin_gamma, np.float64)
         rc = lib.or_setup(self.n, np.ascontiguousarray(A.row_ptr, np.int32),
                           np.ascontiguousarray(A.col, np.int32),
                           np.ascontiguousarray(A.val, np.float64),
                           float(theta), int(max_coarse), int(max_levels), float(omega),
-                          int(nu_pre), int(nu_post), C.byref(h))
+                          int(nu_pre), int(nu_post),
+                          None if ng is None else ng.ctypes.data_as(C.c_void_p), 0 if ng is None else len(ng),
+                          C.byref(h))
         if rc != OK:
             raise ValueError(f"oracle setup failed with status {rc}")
         self._h = h

@@ -35,6 +35,7 @@ KERNEL = {"JACOBI": 0, "JACOBI_ZERO": 1, "RESIDUAL": 2, "RESTRICT": 3, "INTERP":
 # every symbol include/amg.h declares
 ABI_SYMBOLS = (
     "amg_setup_params_default", "amg_solve_params_default", "amg_setup_from_csr",
+    "amg_setup_nongalerkin_from_csr",
     "amg_sparsify", "amg_sparsify_levels", "amg_set_method", "amg_reintroduce", "amg_solve", "amg_vcycle",
     "amg_vcycle32",
     "amg_solve_block", "amg_vcycle_block", "amg_vcycle_block32", "amg_batch_bytes", "amg_batch_create",
@@ -86,6 +87,8 @@ def load_library():
     lib.amg_setup_params_default.argtypes = [P(SetupParams)]
     lib.amg_solve_params_default.argtypes = [P(SolveParams)]
     lib.amg_setup_from_csr.argtypes = [i64, vp, vp, vp, P(SetupParams), vp, ALLOC_FN, FREE_FN, vp, P(vp)]
+    lib.amg_setup_nongalerkin_from_csr.argtypes = [i64, vp, vp, vp, P(SetupParams), vp, i32, vp, ALLOC_FN,
+                                                   FREE_FN, vp, P(vp)]
     lib.amg_sparsify.argtypes = [vp, f64, i32]
     lib.amg_sparsify_levels.argtypes = [vp, vp, i32]
     lib.amg_reintroduce.argtypes = [vp, i32, f64, P(i32)]
@@ -121,7 +124,7 @@ def load_library():
     lib.amg_status_string.restype = C.c_char_p
     lib.amg_last_error.argtypes = [vp]
     lib.amg_last_error.restype = C.c_char_p
-    for name in ("amg_setup_from_csr", "amg_sparsify", "amg_sparsify_levels", "amg_set_method", "amg_reintroduce",
+    for name in ("amg_setup_from_csr", "amg_setup_nongalerkin_from_csr", "amg_sparsify", "amg_sparsify_levels", "amg_set_method", "amg_reintroduce",
                  "amg_solve", "amg_vcycle", "amg_vcycle32", "amg_solve_block", "amg_vcycle_block",
                  "amg_vcycle_block32", "amg_batch_bytes", "amg_batch_create", "amg_batch_submit",
                  "amg_batch_step", "amg_batch_poll", "amg_batch_collect", "amg_batch_slots", "amg_device_bytes",
@@ -213,7 +216,10 @@ class Hierarchy:
     """A device-resident AMG hierarchy (one amg_handle)."""
 
     def __init__(self, A, theta=0.25, max_coarse=49, max_levels=25, omega=2.0 / 3.0,
-                 nu_pre=1, nu_post=1, torch_allocator=True):
+                 nu_pre=1, nu_post=1, torch_allocator=True, nongalerkin_gamma=None):
+        """nongalerkin_gamma: per-level tolerances of the method of non-Galerkin
+        coarse grids (each coarse product sparsified during setup); None for
+        the Galerkin hierarchy."""
         torch = _torch()
         lib = load_library()
         self._lib = lib
@@ -227,9 +233,16 @@ class Hierarchy:
         h = C.c_void_p()
         alloc = _torch_alloc if torch_allocator else ALLOC_FN()
         free = _torch_free if torch_allocator else FREE_FN()
-        st = lib.amg_setup_from_csr(self.n, rp.ctypes.data, ci.ctypes.data, v.ctypes.data,
-                                    C.byref(sp), C.c_void_p(self.stream.cuda_stream), alloc, free,
-                                    None, C.byref(h))
+        if nongalerkin_gamma is None:
+            st = lib.amg_setup_from_csr(self.n, rp.ctypes.data, ci.ctypes.data, v.ctypes.data,
+                                        C.byref(sp), C.c_void_p(self.stream.cuda_stream), alloc, free,
+                                        None, C.byref(h))
+        else:
+            ng = np.ascontiguousarray(nongalerkin_gamma, np.float64)
+            st = lib.amg_setup_nongalerkin_from_csr(self.n, rp.ctypes.data, ci.ctypes.data, v.ctypes.data,
+                                                    C.byref(sp), ng.ctypes.data, len(ng),
+                                                    C.c_void_p(self.stream.cuda_stream), alloc, free, None,
+                                                    C.byref(h))
         if st != OK:
             raise AmgError(st, lib.amg_last_error(None).decode())
         self._h = h

@@ -154,6 +154,7 @@ struct amg_ctx {
     double *blk_b = nullptr, *blk_x = nullptr;   // K-wide copies when nrhs is not a block width
     amg_batch_ctx* batch = nullptr;              // the continuous-batching engine, if any
     int method = AMG_SPARSE_GALERKIN;            // which finer operator the minimal pattern uses
+    bool nongalerkin = false;                    // coarse operators sparsified during setup
     int bcg_k = 0;                               // block CG vectors (FP64, K wide)
     double *bcg_r = nullptr, *bcg_p = nullptr, *bcg_q = nullptr, *bcg_z = nullptr;
     int blk_pack_k = 0;
@@ -1543,7 +1544,8 @@ void destroy_batch(amg_batch_ctx* e) {
 // ---------------------------------------------------------------------------
 // setup
 // ---------------------------------------------------------------------------
-void setup(amg_ctx* h, int64_t n, const int32_t* row_ptr, const int32_t* col, const double* val) {
+void setup(amg_ctx* h, int64_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
+           const std::vector<double>& nongalerkin_gamma) {
     HostCsr a;
     a.rows = a.cols = (int)n;
     if (row_ptr[0] != 0 || row_ptr[n] < 0) throw AmgFailure{AMG_ERR_BAD_MATRIX, "row_ptr must start at 0"};
@@ -1559,6 +1561,8 @@ void setup(amg_ctx* h, int64_t n, const int32_t* row_ptr, const int32_t* col, co
     cfg.theta = h->sp.theta;
     cfg.max_coarse = h->sp.max_coarse;
     cfg.max_levels = h->sp.max_levels;
+    cfg.nongalerkin_gamma = nongalerkin_gamma;
+    h->nongalerkin = !nongalerkin_gamma.empty();
     std::vector<HostLevel> hl;
     if (!build_galerkin_hierarchy(a, cfg, hl, why)) throw AmgFailure{AMG_ERR_BAD_MATRIX, why};
     if (hl.back().A.rows > kMaxDenseCoarse)
@@ -1704,6 +1708,42 @@ amg_status vcycle_block_abi(amg_handle h, int32_t nrhs, const T* b, T* x) {
     });
 }
 
+amg_status setup_abi(int64_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
+                            const amg_setup_params* params, const std::vector<double>& ng, void* stream,
+                            amg_alloc_fn alloc, amg_free_fn free_fn, void* user, amg_handle* out) {
+    if (!out) return AMG_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (n <= 0 || n > INT32_MAX - 1 || !row_ptr || !col || !val) return AMG_ERR_INVALID_ARG;
+    if ((alloc == nullptr) != (free_fn == nullptr)) return AMG_ERR_INVALID_ARG;
+    amg_setup_params sp;
+    amg_setup_params_default(&sp);
+    if (params) sp = *params;
+    if (!(sp.theta > 0.0 && sp.theta <= 1.0) || sp.max_coarse < 1 || sp.max_levels < 1 ||
+        !(sp.omega > 0.0 && sp.omega < 2.0) || sp.nu_pre < 0 || sp.nu_post < 0)
+        return AMG_ERR_INVALID_ARG;
+    for (double g : ng)
+        if (!valid_gamma(g)) return AMG_ERR_INVALID_ARG;
+    amg_ctx* h = new (std::nothrow) amg_ctx();
+    if (!h) return AMG_ERR_OUT_OF_MEMORY;
+    h->stream = (hipStream_t)stream;
+    h->alloc_fn = alloc;
+    h->free_fn = free_fn;
+    h->user = user;
+    h->sp = sp;
+    amg_status st = guarded(h, [&] {
+        HIP_CHECK(hipGetDevice(&h->device));
+        setup(h, n, row_ptr, col, val, ng);
+        return AMG_OK;
+    });
+    if (st != AMG_OK) {
+        setup_error() = h->last_error;
+        destroy(h);
+        return st;
+    }
+    *out = h;
+    return AMG_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1737,35 +1777,19 @@ void amg_solve_params_default(amg_solve_params* p) {
 amg_status amg_setup_from_csr(int64_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
                               const amg_setup_params* params, void* stream, amg_alloc_fn alloc,
                               amg_free_fn free_fn, void* user, amg_handle* out) {
-    if (!out) return AMG_ERR_INVALID_ARG;
-    *out = nullptr;
-    if (n <= 0 || n > INT32_MAX - 1 || !row_ptr || !col || !val) return AMG_ERR_INVALID_ARG;
-    if ((alloc == nullptr) != (free_fn == nullptr)) return AMG_ERR_INVALID_ARG;
-    amg_setup_params sp;
-    amg_setup_params_default(&sp);
-    if (params) sp = *params;
-    if (!(sp.theta > 0.0 && sp.theta <= 1.0) || sp.max_coarse < 1 || sp.max_levels < 1 ||
-        !(sp.omega > 0.0 && sp.omega < 2.0) || sp.nu_pre < 0 || sp.nu_post < 0)
-        return AMG_ERR_INVALID_ARG;
-    amg_ctx* h = new (std::nothrow) amg_ctx();
-    if (!h) return AMG_ERR_OUT_OF_MEMORY;
-    h->stream = (hipStream_t)stream;
-    h->alloc_fn = alloc;
-    h->free_fn = free_fn;
-    h->user = user;
-    h->sp = sp;
-    amg_status st = guarded(h, [&] {
-        HIP_CHECK(hipGetDevice(&h->device));
-        setup(h, n, row_ptr, col, val);
-        return AMG_OK;
-    });
-    if (st != AMG_OK) {
-        setup_error() = h->last_error;
-        destroy(h);
-        return st;
-    }
-    *out = h;
-    return AMG_OK;
+    return setup_abi(n, row_ptr, col, val, params, {}, stream, alloc, free_fn, user, out);
+}
+
+amg_status amg_setup_nongalerkin_from_csr(int64_t n, const int32_t* row_ptr, const int32_t* col,
+                                          const double* val, const amg_setup_params* params,
+                                          const double* gamma, int32_t count, void* stream,
+                                          amg_alloc_fn alloc, amg_free_fn free_fn, void* user,
+                                          amg_handle* out) {
+    if (out) *out = nullptr;
+    if (!gamma || count < 1) return AMG_ERR_INVALID_ARG;
+    std::vector<double> ng(gamma, gamma + count);
+    ng[0] = 0.0;    // A_0 is the given matrix
+    return setup_abi(n, row_ptr, col, val, params, ng, stream, alloc, free_fn, user, out);
 }
 
 amg_status amg_sparsify(amg_handle h, double gamma, int32_t first_level) {

@@ -346,6 +346,70 @@ bool check_input_matrix(const HostCsr& a, std::string& why) {
     return true;
 }
 
+// Sparsifies the coarse product C of the fine operator A and interpolation P
+// (coarse point I is fine point cpts[I]) with tolerance gamma: minimal pattern
+// M = edges(Phat^T A P + P^T A Phat) (structural), keep (i,j) iff i == j, in
+// M, |c_ij| >= gamma m_i or |c_ij| >= gamma m_j with m_i = max_{k!=i} |c_ik|
+// (Algorithm 3's symmetric keep set), dropped entries added to the diagonal
+// in ascending column order (Algorithm 3b).
+static bool sparsify_coarse(HostCsr& C, const HostCsr& A, const HostCsr& P, const std::vector<int32_t>& cpts,
+                            double gamma, std::string& why) {
+    const int nc = C.rows;
+    std::vector<uint8_t> in_m(C.nnz(), 0);
+    auto pos = [&](int i, int j) -> int64_t {
+        const int32_t* b = C.idx.data() + C.ptr[i];
+        const int32_t* e = C.idx.data() + C.ptr[i + 1];
+        const int32_t* it = std::lower_bound(b, e, j);
+        return (it != e && *it == j) ? (int64_t)(it - C.idx.data()) : -1;
+    };
+    for (int I = 0; I < nc; ++I) {
+        const int f = cpts[I];
+        for (int32_t p = A.ptr[f]; p < A.ptr[f + 1]; ++p) {
+            const int l = A.idx[p];
+            for (int32_t q = P.ptr[l]; q < P.ptr[l + 1]; ++q) {
+                const int J = P.idx[q];
+                const int64_t a = pos(I, J), b = pos(J, I);
+                if (a < 0 || b < 0) {
+                    why = "minimal pattern outside the coarse product";
+                    return false;
+                }
+                in_m[a] = in_m[b] = 1;
+            }
+        }
+    }
+    std::vector<double> m(nc, 0.0);
+    for (int i = 0; i < nc; ++i)
+        for (int32_t p = C.ptr[i]; p < C.ptr[i + 1]; ++p)
+            if (C.idx[p] != i) m[i] = std::max(m[i], std::fabs(C.val[p]));
+    HostCsr out;
+    out.rows = out.cols = nc;
+    out.ptr.assign(nc + 1, 0);
+    out.idx.reserve(C.idx.size());
+    out.val.reserve(C.val.size());
+    for (int i = 0; i < nc; ++i) {
+        double d = 0.0;
+        int64_t dpos = -1;
+        for (int32_t p = C.ptr[i]; p < C.ptr[i + 1]; ++p)
+            if (C.idx[p] == i) d = C.val[p];
+        for (int32_t p = C.ptr[i]; p < C.ptr[i + 1]; ++p) {
+            const int j = C.idx[p];
+            const double av = std::fabs(C.val[p]);
+            const bool keep = j == i || in_m[p] || av >= gamma * m[i] || av >= gamma * m[j];
+            if (!keep) {
+                d += C.val[p];
+                continue;
+            }
+            if (j == i) dpos = (int64_t)out.idx.size();
+            out.idx.push_back(j);
+            out.val.push_back(C.val[p]);
+        }
+        if (dpos >= 0) out.val[dpos] = d;
+        out.ptr[i + 1] = (int32_t)out.idx.size();
+    }
+    C = std::move(out);
+    return true;
+}
+
 bool build_galerkin_hierarchy(const HostCsr& a, const SetupConfig& cfg,
                               std::vector<HostLevel>& levels, std::string& why) {
     levels.clear();
@@ -370,6 +434,10 @@ bool build_galerkin_hierarchy(const HostCsr& a, const SetupConfig& cfg,
         HostCsr C = ordered_product(cur.R, T);
         if ((int64_t)C.nnz() > INT32_MAX) { why = "coarse operator exceeds int32 nonzeros"; return false; }
         if (!symmetrize(C, why)) return false;
+        const size_t lc = levels.size();   // index of the level C forms
+        if (lc < cfg.nongalerkin_gamma.size() && cfg.nongalerkin_gamma[lc] > 0.0 &&
+            !sparsify_coarse(C, cur.A, cur.P, cur.c_points, cfg.nongalerkin_gamma[lc], why))
+            return false;
         HostLevel next;
         next.A = std::move(C);
         levels.push_back(std::move(next));

@@ -30,6 +30,11 @@ struct SetupConfig {
     double theta = 0.25;
     int max_coarse = 49;
     int max_levels = 25;
+    // Method of non-Galerkin coarse grids (Section 2.1; the optional sparsify
+    // of amg_setup): when not empty, the product forming level l is
+    // sparsified right away with tolerance nongalerkin_gamma[l] (0 past the
+    // end) and replaces it, so the next level is built from it.
+    std::vector<double> nongalerkin_gamma;
 };
 
 // Checks the input contract: square, int32 CSR with sorted unique in-range
