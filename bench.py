@@ -348,11 +348,11 @@ def bench_aniso(args):
     print(json.dumps(out), flush=True)
 
 
-def block_launch_bytes(h, kernel: str, level: int, k: int, value_bytes: int) -> int:
+def block_launch_bytes(h, kernel: str, level: int, k: int, value_bytes: int, cg: bool = True) -> int:
     """Algorithmic bytes of one block launch on k columns: matrix values of
     value_bytes (4 for the FP32 cycle) plus int32 indices, each block entry
     counted once; the outer residual (RESIDUAL on level 0) reads the FP64
-    operator and FP64 x, b."""
+    operator and FP64 x, b.  cg: the block solve is PCG (else refinement)."""
     li = h.level_info(level)
     n, nnz_hat, nc, nnz_p = li["n"], li["nnz_hat"], li["n_coarse"], li["nnz_P"]
     m = value_bytes + 4
@@ -365,9 +365,9 @@ def block_launch_bytes(h, kernel: str, level: int, k: int, value_bytes: int) -> 
         # q = A p in FP64 (CG): p gathered, q written
         return 12 * li["nnz"] + 4 * (n + 1) + 16 * k * n
     if kernel == "JACOBI":
-        # level 0 (CG): the last sweep writes its result in FP64 and reads the
-        # FP64 residual for r.z
-        out = 16 if level == 0 else vb
+        # level 0: the last sweep writes z and reads the FP64 residual for r.z
+        # (CG), or adds its result to the FP64 iterate (refinement: read + write)
+        out = vb if level > 0 else (vb + 8 if cg else 16)
         return m * nnz_hat + 4 * (n + 1) + vb * n + k * n * (2 * vb + out)
     if kernel in ("JACOBI_ZERO", "RESIDUAL"):
         return m * nnz_hat + 4 * (n + 1) + k * n * 3 * vb

@@ -999,22 +999,30 @@ void block_op_t(amg_ctx* h, int kind, int l, BlockOp op, int k, const DevMat& m,
 ColumnDots cols_to(amg_ctx* h, int slot) { return ColumnDots{h->blk_partials, h->scal + slot}; }
 
 // Where the level-0 result of a block cycle goes: added to the FP64 block acc
-// (refinement), or written to the FP64 block z64 with the column dots
-// r64 . z64 (CG); neither: left in a buffer of the cycle's precision.
+// (refinement), or written to zt (cycle precision) with the column dots
+// r64 . z (CG; CG widens z exactly where it uses it); neither: left in a
+// buffer of the cycle's precision.
+template <class T>
 struct BlockSink {
     double* acc = nullptr;
-    double* z64 = nullptr;
+    T* zt = nullptr;
     const double* r64 = nullptr;
     ColumnDots dot{};
 };
+
+// the preconditioned-residual block of precision T (inside the FP64 z block)
+template <class T>
+T* block_z(amg_ctx* h) {
+    return reinterpret_cast<T*>(h->bcg_z);
+}
 
 // One V-cycle on K columns.  guess0: kNonzero -- bb.x[0] holds the iterate;
 // kPrescaled -- the iterate is zero and bb.x[0] holds omega D^-1 b0.  The
 // last level-0 sweep delivers the result to sink (then nullptr is returned);
 // without a sink the buffer holding the result is returned.
 template <class T>
-T* vcycle_block(amg_ctx* h, int k, const T* b0, Guess guess0, const BlockSink& sink) {
-    const bool to_sink = sink.acc || sink.z64;
+T* vcycle_block(amg_ctx* h, int k, const T* b0, Guess guess0, const BlockSink<T>& sink) {
+    const bool to_sink = sink.acc || sink.zt;
     BlockBufs<T>& bb = block_bufs(h, (T*)nullptr);
     const int L = (int)h->lv.size() - 1;
     const int pre = h->sp.nu_pre, post = h->sp.nu_post;
@@ -1022,7 +1030,7 @@ T* vcycle_block(amg_ctx* h, int k, const T* b0, Guess guess0, const BlockSink& s
     auto deliver = [&](const T* x) {
         ProfScope ps(h, AMG_K_VECTOR, 0);
         if (sink.acc) launch_block_accumulate((int64_t)h->lv[0].n * k, sink.acc, x, h->stream);
-        else launch_block_widen_dot(h->lv[0].n, k, x, sink.z64, sink.r64, sink.dot, h->stream, h->scal + S_LIVE);
+        else launch_block_copy_dot(h->lv[0].n, k, x, sink.zt, sink.r64, sink.dot, h->stream, h->scal + S_LIVE);
         check_launch();
     };
     if (L == 0) {
@@ -1040,11 +1048,10 @@ T* vcycle_block(amg_ctx* h, int k, const T* b0, Guess guess0, const BlockSink& s
         if (last0 && sink.acc) {
             block_op_t<T>(h, AMG_K_JACOBI, l, kBJacobiAccum, k, *v.Ah, v.ahv, cur[l], b, v.dinv, nullptr,
                           nullptr, sink.acc);
-        } else if (last0 && sink.z64) {
+        } else if (last0 && sink.zt) {
             ProfScope ps(h, AMG_K_JACOBI, l);
-            launch_block_sweep_widen_dot(k, CsrT<T>{v.Ah->rp, v.Ah->ci, v.ahv, v.Ah->rows, 0.0}, cur[l], b, v.dinv,
-                                         (T)h->sp.omega, sink.z64, sink.r64, sink.dot, h->stream,
-                                         h->scal + S_LIVE);
+            launch_block_sweep_dot(k, CsrT<T>{v.Ah->rp, v.Ah->ci, v.ahv, v.Ah->rows, 0.0}, cur[l], b, v.dinv,
+                                   (T)h->sp.omega, sink.zt, sink.r64, sink.dot, h->stream, h->scal + S_LIVE);
             check_launch();
         } else {
             block_op_t<T>(h, AMG_K_JACOBI, l, kBJacobi, k, *v.Ah, v.ahv, cur[l], b, v.dinv, alt[l], nullptr,
@@ -1150,7 +1157,7 @@ amg_status solve_block(amg_ctx* h, int k, int nrhs, const double* b, double* x, 
         info.converged = 1;
     } else {
         while (info.iters < p.maxit) {
-            BlockSink sink;
+            BlockSink<T> sink;
             sink.acc = x;
             vcycle_block<T>(h, k, bb.rhs, Guess::kPrescaled, sink);
             block_outer<T>(h, k, b, x);
@@ -1243,8 +1250,8 @@ amg_status solve_block_pcg(amg_ctx* h, int k, int nrhs, const double* b, double*
         nactive += active[c];
     }
     auto precondition = [&](int slot) {
-        BlockSink sink;
-        sink.z64 = h->bcg_z;
+        BlockSink<T> sink;
+        sink.zt = block_z<T>(h);
         sink.r64 = h->bcg_r;
         sink.dot = cols_to(h, slot);
         vcycle_block<T>(h, k, bb.rhs, Guess::kPrescaled, sink);
@@ -1258,7 +1265,7 @@ amg_status solve_block_pcg(amg_ctx* h, int k, int nrhs, const double* b, double*
         upload_active(h, active, k);
         int rz = S_BRZ0;
         precondition(rz);
-        launch_block_cg_update_p(n, k, h->bcg_p, h->bcg_z, h->scal, rz, rz, S_BACT, -1, true, h->stream,
+        launch_block_cg_update_p(n, k, h->bcg_p, block_z<T>(h), h->scal, rz, rz, S_BACT, -1, true, h->stream,
                                  h->scal + S_LIVE);
         check_launch();
         while (info.iters < p.maxit) {
@@ -1299,7 +1306,7 @@ amg_status solve_block_pcg(amg_ctx* h, int k, int nrhs, const double* b, double*
             precondition(next);
             {
                 ProfScope ps(h, AMG_K_VECTOR, 0);
-                launch_block_cg_update_p(n, k, h->bcg_p, h->bcg_z, h->scal, next, rz, S_BACT, -1, false,
+                launch_block_cg_update_p(n, k, h->bcg_p, block_z<T>(h), h->scal, next, rz, S_BACT, -1, false,
                                          h->stream, h->scal + S_LIVE);
                 check_launch();
             }
@@ -1403,15 +1410,15 @@ void batch_iteration(amg_batch_ctx* e, bool load, int rz, int next) {
                                   cols_to(h, S_BNEW), h->stream);
         check_launch();
     }
-    BlockSink sink;
-    sink.z64 = h->bcg_z;
+    BlockSink<T> sink;
+    sink.zt = block_z<T>(h);
     sink.r64 = h->bcg_r;
     sink.dot = cols_to(h, next);
     vcycle_block<T>(h, k, bb.rhs, Guess::kPrescaled, sink);
     {
         ProfScope ps(h, AMG_K_VECTOR, 0);
-        launch_block_cg_update_p(n, k, h->bcg_p, h->bcg_z, h->scal, next, rz, S_BACT, i_load, false, h->stream,
-                                 h->scal + S_LIVE);
+        launch_block_cg_update_p(n, k, h->bcg_p, block_z<T>(h), h->scal, next, rz, S_BACT, i_load, false,
+                                 h->stream, h->scal + S_LIVE);
         check_launch();
     }
     {
@@ -1700,7 +1707,7 @@ amg_status vcycle_block_abi(amg_handle h, int32_t nrhs, const T* b, T* x) {
         BlockBufs<T>& bb = ensure_block<T>(h, nrhs);
         launch_fill_f64(1, h->scal + S_LIVE, (double)nrhs, h->stream);
         launch_copy((int)(n * nrhs), bb.x[0], x, h->stream);
-        T* res = vcycle_block<T>(h, nrhs, b, Guess::kNonzero, BlockSink{});
+        T* res = vcycle_block<T>(h, nrhs, b, Guess::kNonzero, BlockSink<T>{});
         launch_copy((int)(n * nrhs), x, res, h->stream);
         check_launch();
         prof_collect(h);

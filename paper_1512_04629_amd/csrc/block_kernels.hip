@@ -340,9 +340,9 @@ __global__ __launch_bounds__(kBlk) void block_cg_xr_kernel(int n, double* __rest
 // p = z + beta_c p with beta_c = scal[i_num+c] / scal[i_den+c] for the
 // columns with scal[i_act+c] != 0; p = z (a fresh start) in every column if
 // restart_all, else in the columns with scal[i_restart+c] != 0
-template <int K>
+template <class Z, int K>
 __global__ __launch_bounds__(kBlk) void block_cg_p_kernel(int n, double* __restrict__ p,
-                                                          const double* __restrict__ z,
+                                                          const Z* __restrict__ z,
                                                           const double* __restrict__ scal, int i_num, int i_den,
                                                           int i_act, int i_restart, int restart_all,
                                                           const double* __restrict__ live) {
@@ -365,7 +365,9 @@ __global__ __launch_bounds__(kBlk) void block_cg_p_kernel(int n, double* __restr
         const int i = t * RPT + sub;
         if (i >= n) break;
         const int o = i * K + c0;
-        const v2d zi = ld16<v2d>(z + o);
+        v2d zi;
+        zi.x = (double)z[o];      // the preconditioned residual, widened exactly
+        zi.y = (double)z[o + 1];
         v2d pi = ld16<v2d>(p + o);
         if (upd[0]) pi.x = fresh[0] ? zi.x : zi.x + beta[0] * pi.x;
         if (upd[1]) pi.y = fresh[1] ? zi.y : zi.y + beta[1] * pi.y;
@@ -430,14 +432,14 @@ __global__ __launch_bounds__(kBlk) void block_column_out_kernel(int n, int k, in
     for (int i = blockIdx.x * kBlk + threadIdx.x; i < n; i += gridDim.x * kBlk) v[i] = blk[(size_t)i * k + c];
 }
 
-// Last level-0 sweep of the preconditioner: z64 = (double)(G + omega dinv
-// (U - A G)) with per-column partials of r64_c . z64_c
+// Last level-0 sweep of the preconditioner: z = G + omega dinv (U - A G) in
+// the cycle's precision, with per-column partials of r64_c . (double) z_c
 template <class T, int K>
-__global__ __launch_bounds__(kBlk) void block_sweep_widen_dot_kernel(CsrT<T> a, const T* __restrict__ g,
-                                                                     const T* __restrict__ u,
-                                                                     const T* __restrict__ dinv, T omega,
-                                                                     double* __restrict__ z64,
-                                                                     const double* __restrict__ r64,
+__global__ __launch_bounds__(kBlk) void block_sweep_dot_kernel(CsrT<T> a, const T* __restrict__ g,
+                                                               const T* __restrict__ u,
+                                                               const T* __restrict__ dinv, T omega,
+                                                               T* __restrict__ zt,
+                                                               const double* __restrict__ r64,
                                                                      double* __restrict__ partials, int ntiles,
                                                                      const double* __restrict__ live) {
     using VT = typename Vec16<T>::type;
@@ -458,23 +460,22 @@ __global__ __launch_bounds__(kBlk) void block_sweep_widen_dot_kernel(CsrT<T> a, 
         const VT s = row_gather_sum<T, K>(a, g, a.rp[i], a.rp[i + 1], c0);
         const int o = i * K + c0;
         const VT xn = ld16<VT>(g + o) + omega * dinv[i] * (ld16<VT>(u + o) - s);
+        st16(zt + o, xn);
 #pragma unroll
         for (int e = 0; e < V; e += 2) {
-            const v2d ze = {(double)xn[e], (double)xn[e + 1]};
-            st16(z64 + o + e, ze);
             const v2d re = ld16<v2d>(r64 + o + e);
-            d[e] += re.x * ze.x;
-            d[e + 1] += re.y * ze.y;
+            d[e] += re.x * (double)xn[e];
+            d[e + 1] += re.y * (double)xn[e + 1];
         }
     }
     store_column_partials<K, V>(d, partials, lb);
 }
 
-// z64 = (double) x with partials of r64_c . z64_c (a cycle without post-smoothing)
+// zt = x with partials of r64_c . (double) x_c (a cycle without post-smoothing)
 template <class T, int K>
-__global__ __launch_bounds__(kBlk) void block_widen_dot_kernel(int n, const T* __restrict__ x,
-                                                               double* __restrict__ z64,
-                                                               const double* __restrict__ r64,
+__global__ __launch_bounds__(kBlk) void block_copy_dot_kernel(int n, const T* __restrict__ x,
+                                                              T* __restrict__ zt,
+                                                              const double* __restrict__ r64,
                                                                double* __restrict__ partials, int ntiles,
                                                                const double* __restrict__ live) {
     constexpr int LPR = K / 2;
@@ -489,11 +490,12 @@ __global__ __launch_bounds__(kBlk) void block_widen_dot_kernel(int n, const T* _
         const int i = t * RPT + sub;
         if (i >= n) break;
         const int o = i * K + c0;
-        const v2d ze = {(double)x[o], (double)x[o + 1]};
-        st16(z64 + o, ze);
+        const T x0 = x[o], x1 = x[o + 1];
+        zt[o] = x0;
+        zt[o + 1] = x1;
         const v2d re = ld16<v2d>(r64 + o);
-        d[0] += re.x * ze.x;
-        d[1] += re.y * ze.y;
+        d[0] += re.x * (double)x0;
+        d[1] += re.y * (double)x1;
     }
     store_column_partials<K, 2>(d, partials, lb);
 }
@@ -662,25 +664,25 @@ void cg_xr(int n, int k, double* x, double* r, const double* p, const double* q,
 }
 
 template <class T>
-void sweep_widen_dot(int k, const CsrT<T>& a, const T* g, const T* u, const T* dinv, T omega, double* z64,
-                     const double* r64, ColumnDots dot, const double* live, hipStream_t st) {
+void sweep_dot(int k, const CsrT<T>& a, const T* g, const T* u, const T* dinv, T omega, T* zt,
+               const double* r64, ColumnDots dot, const double* live, hipStream_t st) {
     with_width(k, [&]<int K>() {
         constexpr int RPT = kBlk / (K / Vec16<T>::n);
         const int ntiles = std::max(1, (a.rows + RPT - 1) / RPT);
         const int grid = round8(std::min(ntiles, kGridCap));
-        hipLaunchKernelGGL((block_sweep_widen_dot_kernel<T, K>), dim3(grid), dim3(kBlk), 0, st, a, g, u, dinv,
-                           omega, z64, r64, dot.partials, ntiles, live);
+        hipLaunchKernelGGL((block_sweep_dot_kernel<T, K>), dim3(grid), dim3(kBlk), 0, st, a, g, u, dinv,
+                           omega, zt, r64, dot.partials, ntiles, live);
         finish<K>(grid, dot, st);
     });
 }
 
 template <class T>
-void widen_dot(int n, int k, const T* x, double* z64, const double* r64, ColumnDots dot, const double* live,
-               hipStream_t st) {
+void copy_dot(int n, int k, const T* x, T* zt, const double* r64, ColumnDots dot, const double* live,
+              hipStream_t st) {
     with_width(k, [&]<int K>() {
         const int ntiles = fp64_tiles<K>(n);
         const int grid = round8(std::min(ntiles, kGridCap));
-        hipLaunchKernelGGL((block_widen_dot_kernel<T, K>), dim3(grid), dim3(kBlk), 0, st, n, x, z64, r64,
+        hipLaunchKernelGGL((block_copy_dot_kernel<T, K>), dim3(grid), dim3(kBlk), 0, st, n, x, zt, r64,
                            dot.partials, ntiles, live);
         finish<K>(grid, dot, st);
     });
@@ -741,14 +743,26 @@ void launch_block_cg_update_xr(int n, int k, double* x, double* r, const double*
     cg_xr<float>(n, k, x, r, p, q, scal, i_num, i_den, i_act, flags, dinvt, omega, rt, zt, norms, live, st);
 }
 
+template <class Z>
+void cg_p(int n, int k, double* p, const Z* z, const double* scal, int i_num, int i_den, int i_act, int i_restart,
+          bool restart_all, hipStream_t st, const double* live) {
+    with_width(k, [&]<int K>() {
+        const int grid = std::min(fp64_tiles<K>(n), kGridCap);
+        hipLaunchKernelGGL((block_cg_p_kernel<Z, K>), dim3(grid), dim3(kBlk), 0, st, n, p, z, scal, i_num, i_den,
+                           i_act, i_restart, restart_all ? 1 : 0, live);
+    });
+}
+
 void launch_block_cg_update_p(int n, int k, double* p, const double* z, const double* scal, int i_num,
                               int i_den, int i_act, int i_restart, bool restart_all, hipStream_t st,
                               const double* live) {
-    with_width(k, [&]<int K>() {
-        const int grid = std::min(fp64_tiles<K>(n), kGridCap);
-        hipLaunchKernelGGL((block_cg_p_kernel<K>), dim3(grid), dim3(kBlk), 0, st, n, p, z, scal, i_num, i_den,
-                           i_act, i_restart, restart_all ? 1 : 0, live);
-    });
+    cg_p<double>(n, k, p, z, scal, i_num, i_den, i_act, i_restart, restart_all, st, live);
+}
+
+void launch_block_cg_update_p(int n, int k, double* p, const float* z, const double* scal, int i_num,
+                              int i_den, int i_act, int i_restart, bool restart_all, hipStream_t st,
+                              const double* live) {
+    cg_p<float>(n, k, p, z, scal, i_num, i_den, i_act, i_restart, restart_all, st, live);
 }
 
 template <class T>
@@ -789,26 +803,26 @@ void launch_block_column_out(int n, int k, int c, const double* blk, double* v, 
     hipLaunchKernelGGL(block_column_out_kernel, dim3(elem_grid(n)), dim3(kBlk), 0, st, n, k, c, blk, v);
 }
 
-void launch_block_sweep_widen_dot(int k, const CsrT<double>& a, const double* g, const double* u,
-                                  const double* dinv, double omega, double* z64, const double* r64,
-                                  ColumnDots dot, hipStream_t st, const double* live) {
-    sweep_widen_dot<double>(k, a, g, u, dinv, omega, z64, r64, dot, live, st);
+void launch_block_sweep_dot(int k, const CsrT<double>& a, const double* g, const double* u, const double* dinv,
+                            double omega, double* zt, const double* r64, ColumnDots dot, hipStream_t st,
+                            const double* live) {
+    sweep_dot<double>(k, a, g, u, dinv, omega, zt, r64, dot, live, st);
 }
 
-void launch_block_sweep_widen_dot(int k, const CsrT<float>& a, const float* g, const float* u,
-                                  const float* dinv, float omega, double* z64, const double* r64,
-                                  ColumnDots dot, hipStream_t st, const double* live) {
-    sweep_widen_dot<float>(k, a, g, u, dinv, omega, z64, r64, dot, live, st);
+void launch_block_sweep_dot(int k, const CsrT<float>& a, const float* g, const float* u, const float* dinv,
+                            float omega, float* zt, const double* r64, ColumnDots dot, hipStream_t st,
+                            const double* live) {
+    sweep_dot<float>(k, a, g, u, dinv, omega, zt, r64, dot, live, st);
 }
 
-void launch_block_widen_dot(int n, int k, const double* x, double* z64, const double* r64, ColumnDots dot,
-                            hipStream_t st, const double* live) {
-    widen_dot<double>(n, k, x, z64, r64, dot, live, st);
+void launch_block_copy_dot(int n, int k, const double* x, double* zt, const double* r64, ColumnDots dot,
+                           hipStream_t st, const double* live) {
+    copy_dot<double>(n, k, x, zt, r64, dot, live, st);
 }
 
-void launch_block_widen_dot(int n, int k, const float* x, double* z64, const double* r64, ColumnDots dot,
-                            hipStream_t st, const double* live) {
-    widen_dot<float>(n, k, x, z64, r64, dot, live, st);
+void launch_block_copy_dot(int n, int k, const float* x, float* zt, const double* r64, ColumnDots dot,
+                           hipStream_t st, const double* live) {
+    copy_dot<float>(n, k, x, zt, r64, dot, live, st);
 }
 
 void launch_block_dense_matvec(int n, int k, const double* ainv, const double* b, double* y,

@@ -93,8 +93,11 @@ void launch_block_cg_update_xr(int n, int k, double* x, double* r, const double*
                                const double* live = nullptr);
 // p = z + beta_c p with beta_c = scal[i_num+c] / scal[i_den+c] on active
 // columns; p = z in every column if restart_all, else in the columns with
-// scal[i_restart+c] != 0 (i_restart < 0: none)
+// scal[i_restart+c] != 0 (i_restart < 0: none); z in FP64 or FP32 (widened)
 void launch_block_cg_update_p(int n, int k, double* p, const double* z, const double* scal, int i_num,
+                              int i_den, int i_act, int i_restart, bool restart_all, hipStream_t st,
+                              const double* live = nullptr);
+void launch_block_cg_update_p(int n, int k, double* p, const float* z, const double* scal, int i_num,
                               int i_den, int i_act, int i_restart, bool restart_all, hipStream_t st,
                               const double* live = nullptr);
 // Fresh start of the columns with scal[i_load+c] != 0: x_c = 0, r_c = b_c,
@@ -117,23 +120,20 @@ void launch_block_converge(int k, double* scal, int i_act, int i_norm, int i_nr0
 // column c of a K-wide block from / to a plain vector of n entries
 void launch_block_column_in(int n, int k, int c, const double* v, double* blk, hipStream_t st);
 void launch_block_column_out(int n, int k, int c, const double* blk, double* v, hipStream_t st);
-// The preconditioner's last level-0 sweep z64 = (double)(G + omega dinv (U - A G))
-// with dot[c] = r64_c . z64_c (the CG inner product r.z)
-void launch_block_sweep_widen_dot(int k, const CsrT<double>& a, const double* g, const double* u,
-                                  const double* dinv, double omega, double* z64, const double* r64,
-                                  ColumnDots dot, hipStream_t st,
-                                  const double* live = nullptr);
-void launch_block_sweep_widen_dot(int k, const CsrT<float>& a, const float* g, const float* u,
-                                  const float* dinv, float omega, double* z64, const double* r64,
-                                  ColumnDots dot, hipStream_t st,
-                                  const double* live = nullptr);
-// z64 = (double) x with dot[c] = r64_c . z64_c
-void launch_block_widen_dot(int n, int k, const double* x, double* z64, const double* r64, ColumnDots dot,
-                            hipStream_t st,
+// The preconditioner's last level-0 sweep z = G + omega dinv (U - A G), kept in
+// the cycle's precision, with dot[c] = r64_c . (double) z_c (the CG inner
+// product r.z; the widening is exact)
+void launch_block_sweep_dot(int k, const CsrT<double>& a, const double* g, const double* u, const double* dinv,
+                            double omega, double* zt, const double* r64, ColumnDots dot, hipStream_t st,
                             const double* live = nullptr);
-void launch_block_widen_dot(int n, int k, const float* x, double* z64, const double* r64, ColumnDots dot,
-                            hipStream_t st,
+void launch_block_sweep_dot(int k, const CsrT<float>& a, const float* g, const float* u, const float* dinv,
+                            float omega, float* zt, const double* r64, ColumnDots dot, hipStream_t st,
                             const double* live = nullptr);
+// zt = x with dot[c] = r64_c . (double) x_c
+void launch_block_copy_dot(int n, int k, const double* x, double* zt, const double* r64, ColumnDots dot,
+                           hipStream_t st, const double* live = nullptr);
+void launch_block_copy_dot(int n, int k, const float* x, float* zt, const double* r64, ColumnDots dot,
+                           hipStream_t st, const double* live = nullptr);
 
 // Y = Ainv B for the FP64 dense inverse of the coarsest operator (n x n) and
 // K-wide blocks; accumulation in FP64.
