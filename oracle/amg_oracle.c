@@ -12,7 +12,9 @@
  *
  *   setup      Section 2, algorithm amg_setup (strength -> interpolation ->
  *              Galerkin product), run without the optional sparsify step, as
- *              Section 3, algorithm sparse_hybrid_setup, prescribes.
+ *              Section 3, algorithm sparse_hybrid_setup, prescribes; C/F
+ *              split by the Ruge-Stueben first pass or by PMIS, the parallel
+ *              aggressive coarsening Section 1 cites.
  *   sparsify   Section 2.1, Algorithm 3 (first loop: minimal pattern M and
  *              keep set N) with the diagonal-lumping loop of Algorithm 3b
  *              (Section 3.1); Sparse Galerkin (M from the Galerkin A_{l-1})
@@ -126,7 +128,7 @@ static int mat_transpose(const Mat *a, Mat *t) {
         for (int p = a->rp[i]; p < a->rp[i + 1]; ++p) {
             int q = fill[a->ci[p]]++;
             t->ci[q] = i;
-            t->v[q] = a->v[p];
+            t->v[q] = a->v ? a->v[p] : 1.0;   /* a pattern without values: ones */
         }
     free(fill);
     return OR_OK;
@@ -316,6 +318,91 @@ static int rs_split(const Mat *s, int *cf) {
     for (int i = 0; i < n; ++i) cf[i] = (state[i] == PT_C) ? 1 : 0;
     free(state); free(lam); free(newf); free(h.a); mat_free(&st);
     return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): output k >= 1 of the    */
+/* stream seeded with `seed` is the published finaliser applied to          */
+/* seed + k * 0x9E3779B97F4A7C15.  Counter based: any output on its own.    */
+/* ------------------------------------------------------------------------ */
+static uint64_t splitmix64_at(uint64_t seed, uint64_t k) {
+    uint64_t z = seed + k * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+/* ------------------------------------------------------------------------ */
+/* PMIS coarsening (the parallel aggressive coarsening of De Sterck, Yang   */
+/* and Heys that Section 1 cites).  Each point gets the weight              */
+/* w_i = lambda_i + u_i, lambda_i = #{j : S_ji = 1} and u_i in [0, 1) the    */
+/* top 53 bits of output i+1 of the SplitMix64 stream `seed`; i beats j if  */
+/* w_i > w_j, or w_i == w_j and i < j.  Points no other point depends on    */
+/* strongly (lambda_i = 0) are F from the start.  Then, in rounds until no  */
+/* point is undecided: every undecided point that beats each undecided      */
+/* point it is strongly connected to (S_ij or S_ji) becomes C, all of them  */
+/* at once; after that every undecided point that depends strongly on a C   */
+/* point becomes F.                                                         */
+/* ------------------------------------------------------------------------ */
+static int pmis_beats(const double *w, int i, int j) {
+    return w[i] > w[j] || (w[i] == w[j] && i < j);
+}
+
+/* the rounds, for given weights w (lambda_i = 0 points start as F) */
+static int pmis_rounds(const Mat *s, const Mat *st, const double *w, int *cf) {
+    int n = s->nr;
+    int *state = (int *)malloc(sizeof(int) * (size_t)n);
+    int *pick = (int *)malloc(sizeof(int) * (size_t)n);
+    if (!state || !pick) return OR_ENOMEM;
+    int undecided = 0;
+    for (int i = 0; i < n; ++i) {
+        state[i] = st->rp[i + 1] == st->rp[i] ? PT_F : PT_U;
+        undecided += state[i] == PT_U;
+    }
+    while (undecided > 0) {
+        /* independent set of local maxima among the undecided points */
+        for (int i = 0; i < n; ++i) {
+            pick[i] = 0;
+            if (state[i] != PT_U) continue;
+            int best = 1;
+            for (int p = s->rp[i]; p < s->rp[i + 1] && best; ++p) {
+                int j = s->ci[p];
+                if (state[j] == PT_U && pmis_beats(w, j, i)) best = 0;
+            }
+            for (int p = st->rp[i]; p < st->rp[i + 1] && best; ++p) {
+                int j = st->ci[p];
+                if (state[j] == PT_U && pmis_beats(w, j, i)) best = 0;
+            }
+            pick[i] = best;
+        }
+        for (int i = 0; i < n; ++i)
+            if (pick[i]) { state[i] = PT_C; --undecided; }
+        /* points that depend strongly on a C point become F */
+        for (int j = 0; j < n; ++j) {
+            if (state[j] != PT_U) continue;
+            for (int p = s->rp[j]; p < s->rp[j + 1]; ++p)
+                if (state[s->ci[p]] == PT_C) { state[j] = PT_F; --undecided; break; }
+        }
+    }
+    for (int i = 0; i < n; ++i) cf[i] = (state[i] == PT_C) ? 1 : 0;
+    free(state); free(pick);
+    return OR_OK;
+}
+
+static int pmis_split(const Mat *s, uint64_t seed, int *cf) {
+    int n = s->nr;
+    Mat st;
+    if (mat_transpose(s, &st)) return OR_ENOMEM;
+    double *w = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!w) return OR_ENOMEM;
+    for (int i = 0; i < n; ++i) {
+        int lam = st.rp[i + 1] - st.rp[i];
+        double u = (double)(splitmix64_at(seed, (uint64_t)i + 1) >> 11) * 0x1p-53;
+        w[i] = (double)lam + u;
+    }
+    int rc = pmis_rounds(s, &st, w, cf);
+    free(w); mat_free(&st);
+    return rc;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -548,12 +635,15 @@ void or_free(Hier *h);
 /* ng_gamma (nullable, ng_count entries): the method of non-Galerkin coarse
    grids (Section 2.1; amg_setup with its optional sparsify): right after its
    Galerkin product, A_{l+1} is sparsified with tolerance ng_gamma[l+1] and
-   replaces the product, so the next level is built from it. */
+   replaces the product, so the next level is built from it.
+   coarsen: 0 = Ruge-Stueben first pass, 1 = PMIS with the weights of level l
+   drawn from the SplitMix64 stream seed + l. */
 int or_setup(int n, const int *rp, const int *ci, const double *v, double theta,
              int max_coarse, int max_levels, double omega, int nu_pre, int nu_post,
-             const double *ng_gamma, int ng_count, Hier **out) {
+             const double *ng_gamma, int ng_count, int coarsen, uint64_t seed, Hier **out) {
     *out = NULL;
-    if (n <= 0 || !rp || !ci || !v || max_levels < 1 || max_coarse < 1) return OR_EINVAL;
+    if (n <= 0 || !rp || !ci || !v || max_levels < 1 || max_coarse < 1 || coarsen < 0 || coarsen > 1)
+        return OR_EINVAL;
     int rc = validate(n, rp, ci, v);
     if (rc) return rc;
     Hier *h = (Hier *)calloc(1, sizeof(Hier));
@@ -568,7 +658,8 @@ int or_setup(int n, const int *rp, const int *ci, const double *v, double theta,
         if ((rc = strength(&cur->A, theta, &cur->S))) return rc;
         cur->cf = (int *)malloc(sizeof(int) * (size_t)nl);
         cur->cidx = (int *)malloc(sizeof(int) * (size_t)nl);
-        if ((rc = rs_split(&cur->S, cur->cf))) return rc;
+        rc = coarsen == 1 ? pmis_split(&cur->S, seed + (uint64_t)L, cur->cf) : rs_split(&cur->S, cur->cf);
+        if (rc) return rc;
         int nc = 0;
         for (int i = 0; i < nl; ++i) cur->cidx[i] = cur->cf[i] ? nc++ : -1;
         if (nc == 0 || nc == nl) {
@@ -960,6 +1051,19 @@ int or_export(const Hier *h, int l, int which, int *rp, int *ci, double *v) {
     if (v) memcpy(v, m->v, sizeof(double) * (size_t)nnz);
     return OR_OK;
 }
+
+/* PMIS rounds on the strength pattern (rp, ci) of n points with the given
+   weights instead of lambda + u (lets a test choose weights that tie) */
+int or_pmis_rounds(int n, const int *rp, const int *ci, const double *w, int *cf) {
+    Mat s = {n, n, (int *)rp, (int *)ci, NULL}, st;
+    if (mat_transpose(&s, &st)) return OR_ENOMEM;
+    int rc = pmis_rounds(&s, &st, w, cf);
+    mat_free(&st);
+    return rc;
+}
+
+/* output k >= 1 of the SplitMix64 stream `seed` (the PMIS weights' source) */
+uint64_t or_splitmix64(uint64_t seed, uint64_t k) { return splitmix64_at(seed, k); }
 
 /* which: 0 = inM, 1 = keep (per nonzero of A_l) */
 int or_export_mask(const Hier *h, int l, int which, unsigned char *out) {

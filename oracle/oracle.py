@@ -41,6 +41,7 @@ class _Info(C.Structure):
 
 
 _lib = None
+COARSENINGS = {"rs": 0, "pmis": 1}
 
 
 def _load():
@@ -55,9 +56,12 @@ def _load():
         up = np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")
         lp = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
         lib.or_setup.argtypes = [C.c_int, ip, ip, dp, C.c_double, C.c_int, C.c_int, C.c_double,
-                                 C.c_int, C.c_int, C.c_void_p, C.c_int, C.POINTER(P)]
+                                 C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_int, C.c_uint64, C.POINTER(P)]
         lib.or_setup.restype = C.c_int
         lib.or_free.argtypes = [P]
+        lib.or_pmis_rounds.argtypes = [C.c_int, ip, ip, dp, ip]
+        lib.or_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
+        lib.or_splitmix64.restype = C.c_uint64
         lib.or_num_levels.argtypes = [P]
         lib.or_num_levels.restype = C.c_int
         lib.or_level_sizes.argtypes = [P, C.c_int, lp]
@@ -109,10 +113,13 @@ class OracleAMG:
     """Oracle hierarchy: Galerkin setup, Sparse Galerkin sparsify, solves."""
 
     def __init__(self, A, theta=0.25, max_coarse=49, max_levels=25, omega=2.0 / 3.0,
-                 nu_pre=1, nu_post=1, nongalerkin_gamma=None):
+                 nu_pre=1, nu_post=1, nongalerkin_gamma=None, coarsening="rs", seed=0):
         """nongalerkin_gamma: per-level tolerances of the method of non-Galerkin
         coarse grids (each coarse product sparsified during setup); None for the
-        Galerkin hierarchy."""
+        Galerkin hierarchy.  coarsening: "rs" (Ruge-Stueben first pass) or
+        "pmis" (weights of level l from the SplitMix64 stream seed + l)."""
+        if coarsening not in COARSENINGS:
+            raise ValueError(f"unknown coarsening {coarsening!r}")
         lib = _load()
         self._lib = lib
         self.n = int(A.n)
@@ -124,7 +131,7 @@ class OracleAMG:
                           float(theta), int(max_coarse), int(max_levels), float(omega),
                           int(nu_pre), int(nu_post),
                           None if ng is None else ng.ctypes.data_as(C.c_void_p), 0 if ng is None else len(ng),
-                          C.byref(h))
+                          COARSENINGS[coarsening], int(seed) & 0xFFFFFFFFFFFFFFFF, C.byref(h))
         if rc != OK:
             raise ValueError(f"oracle setup failed with status {rc}")
         self._h = h

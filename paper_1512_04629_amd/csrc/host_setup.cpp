@@ -102,7 +102,13 @@ public:
     void set(int i, int k) {
         int v = size_ + i;
         key_[v] = k;
-        for (v >>= 1; v >= 1; v >>= 1) pull(v);
+        // an ancestor depends only on its children's winners: stop where the
+        // winner of a subtree is unchanged
+        for (v >>= 1; v >= 1; v >>= 1) {
+            const int old_key = key_[v], old_who = who_[v];
+            pull(v);
+            if (key_[v] == old_key && who_[v] == old_who) break;
+        }
     }
     int top_key() const { return key_[1]; }
     int top() const { return who_[1]; }
