@@ -130,6 +130,34 @@ amg_status amg_setup_nongalerkin_from_csr(int64_t n, const int32_t* row_ptr, con
                                           amg_alloc_fn alloc, amg_free_fn free_fn, void* user,
                                           amg_handle* out);
 
+/* Build the Galerkin hierarchy on the device (Section 2, amg_setup: strength,
+   C/F split, direct interpolation, Galerkin product, every level).
+   row_ptr/col/val: DEVICE arrays of A_0 (n + 1, nnz, nnz entries) that the
+   work on `stream` may read; they are copied, and the caller keeps them.  The
+   input contract is checked on the device (AMG_ERR_BAD_MATRIX names the
+   first offending row).  coarsening:
+     AMG_COARSEN_RS    the Ruge-Stueben first pass, run on the host from the
+                       strength pattern the device builds (one download per
+                       level); the hierarchy equals amg_setup_from_csr's bit
+                       for bit;
+     AMG_COARSEN_PMIS  PMIS, the parallel aggressive coarsening Section 1
+                       cites, in rounds on the device: weights lambda_i + u_i
+                       with u_i from output i+1 of the SplitMix64 stream
+                       seed + l on level l; points no point depends on
+                       strongly start as F; each round, undecided points that
+                       beat every undecided strong neighbour (larger weight,
+                       ties to the smaller index) become C, then undecided
+                       points depending strongly on a C point become F.
+   The products are formed as listed terms sorted stably by (row, column),
+   so each entry sums its terms in the canonical order of the host setup.
+   Temporary device memory of up to ~40 bytes per product term comes from the
+   allocator.  Other arguments and the result as for amg_setup_from_csr. */
+enum { AMG_COARSEN_RS = 0, AMG_COARSEN_PMIS = 1 };
+amg_status amg_setup_device(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col,
+                            const double* val, const amg_setup_params* params, int32_t coarsening,
+                            uint64_t seed, void* stream, amg_alloc_fn alloc, amg_free_fn free_fn,
+                            void* user, amg_handle* out);
+
 /* Sparse Galerkin sparsification with diagonal lumping (Algorithm 3 keep set,
    Algorithm 3b loop) of every level l >= first_level (first_level >= 1) with
    drop tolerance gamma in [0, 1]; levels below first_level get gamma 0.  The

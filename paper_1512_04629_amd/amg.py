@@ -35,7 +35,7 @@ KERNEL = {"JACOBI": 0, "JACOBI_ZERO": 1, "RESIDUAL": 2, "RESTRICT": 3, "INTERP":
 # every symbol include/amg.h declares
 ABI_SYMBOLS = (
     "amg_setup_params_default", "amg_solve_params_default", "amg_setup_from_csr",
-    "amg_setup_nongalerkin_from_csr",
+    "amg_setup_nongalerkin_from_csr", "amg_setup_device",
     "amg_sparsify", "amg_sparsify_levels", "amg_set_method", "amg_reintroduce", "amg_solve", "amg_vcycle",
     "amg_vcycle32",
     "amg_solve_block", "amg_vcycle_block", "amg_vcycle_block32", "amg_batch_bytes", "amg_batch_create",
@@ -44,6 +44,9 @@ ABI_SYMBOLS = (
     "amg_export_vector", "amg_export_split", "amg_profile_enable", "amg_profile_read",
     "amg_destroy", "amg_status_string", "amg_last_error",
 )
+
+
+COARSENINGS = {"rs": 0, "pmis": 1}     # AMG_COARSEN_RS, AMG_COARSEN_PMIS
 
 
 class AmgError(RuntimeError):
@@ -89,6 +92,8 @@ def load_library():
     lib.amg_setup_from_csr.argtypes = [i64, vp, vp, vp, P(SetupParams), vp, ALLOC_FN, FREE_FN, vp, P(vp)]
     lib.amg_setup_nongalerkin_from_csr.argtypes = [i64, vp, vp, vp, P(SetupParams), vp, i32, vp, ALLOC_FN,
                                                    FREE_FN, vp, P(vp)]
+    lib.amg_setup_device.argtypes = [i64, i64, vp, vp, vp, P(SetupParams), i32, C.c_uint64, vp, ALLOC_FN,
+                                     FREE_FN, vp, P(vp)]
     lib.amg_sparsify.argtypes = [vp, f64, i32]
     lib.amg_sparsify_levels.argtypes = [vp, vp, i32]
     lib.amg_reintroduce.argtypes = [vp, i32, f64, P(i32)]
@@ -124,7 +129,7 @@ def load_library():
     lib.amg_status_string.restype = C.c_char_p
     lib.amg_last_error.argtypes = [vp]
     lib.amg_last_error.restype = C.c_char_p
-    for name in ("amg_setup_from_csr", "amg_setup_nongalerkin_from_csr", "amg_sparsify", "amg_sparsify_levels", "amg_set_method", "amg_reintroduce",
+    for name in ("amg_setup_from_csr", "amg_setup_nongalerkin_from_csr", "amg_setup_device", "amg_sparsify", "amg_sparsify_levels", "amg_set_method", "amg_reintroduce",
                  "amg_solve", "amg_vcycle", "amg_vcycle32", "amg_solve_block", "amg_vcycle_block",
                  "amg_vcycle_block32", "amg_batch_bytes", "amg_batch_create", "amg_batch_submit",
                  "amg_batch_step", "amg_batch_poll", "amg_batch_collect", "amg_batch_slots", "amg_device_bytes",
@@ -216,23 +221,56 @@ class Hierarchy:
     """A device-resident AMG hierarchy (one amg_handle)."""
 
     def __init__(self, A, theta=0.25, max_coarse=49, max_levels=25, omega=2.0 / 3.0,
-                 nu_pre=1, nu_post=1, torch_allocator=True, nongalerkin_gamma=None):
+                 nu_pre=1, nu_post=1, torch_allocator=True, nongalerkin_gamma=None, setup="host",
+                 coarsening="rs", seed=0):
         """nongalerkin_gamma: per-level tolerances of the method of non-Galerkin
         coarse grids (each coarse product sparsified during setup); None for
-        the Galerkin hierarchy."""
+        the Galerkin hierarchy.
+
+        setup="device": the hierarchy is built by amg_setup_device from device
+        copies of A (or from A itself when it is a tuple (n, row_ptr, col, val)
+        of CUDA tensors), with coarsening "rs" (the same hierarchy as the host
+        setup) or "pmis" (weights of level l from the SplitMix64 stream
+        seed + l)."""
+        if setup not in ("host", "device") or coarsening not in COARSENINGS:
+            raise ValueError(f"unknown setup {setup!r} or coarsening {coarsening!r}")
+        if setup == "host" and coarsening != "rs":
+            raise ValueError("PMIS coarsening runs in the device setup only")
+        if setup == "device" and nongalerkin_gamma is not None:
+            raise ValueError("the device setup builds the Galerkin hierarchy")
         torch = _torch()
         lib = load_library()
         self._lib = lib
-        self.n = int(A.n)
-        rp = np.ascontiguousarray(A.row_ptr, np.int32)
-        ci = np.ascontiguousarray(A.col, np.int32)
-        v = np.ascontiguousarray(A.val, np.float64)
         sp = SetupParams(float(theta), int(max_coarse), int(max_levels), float(omega),
                          int(nu_pre), int(nu_post))
         self.stream = torch.cuda.current_stream()
         h = C.c_void_p()
         alloc = _torch_alloc if torch_allocator else ALLOC_FN()
         free = _torch_free if torch_allocator else FREE_FN()
+        if setup == "device":
+            if isinstance(A, tuple):
+                n, rp_d, ci_d, v_d = A
+            else:
+                n = A.n
+                rp_d = torch.from_numpy(np.ascontiguousarray(A.row_ptr, np.int32)).cuda()
+                ci_d = torch.from_numpy(np.ascontiguousarray(A.col, np.int32)).cuda()
+                v_d = torch.from_numpy(np.ascontiguousarray(A.val, np.float64)).cuda()
+            if (rp_d.dtype != torch.int32 or ci_d.dtype != torch.int32 or v_d.dtype != torch.float64
+                    or not (rp_d.is_cuda and ci_d.is_cuda and v_d.is_cuda)):
+                raise ValueError("device CSR: int32 row_ptr and col, float64 values, CUDA tensors")
+            self.n = int(n)
+            st = lib.amg_setup_device(self.n, int(ci_d.numel()), rp_d.data_ptr(), ci_d.data_ptr(),
+                                      v_d.data_ptr(), C.byref(sp), COARSENINGS[coarsening],
+                                      int(seed) & 0xFFFFFFFFFFFFFFFF, C.c_void_p(self.stream.cuda_stream),
+                                      alloc, free, None, C.byref(h))
+            if st != OK:
+                raise AmgError(st, lib.amg_last_error(None).decode())
+            self._finish(h)
+            return
+        self.n = int(A.n)
+        rp = np.ascontiguousarray(A.row_ptr, np.int32)
+        ci = np.ascontiguousarray(A.col, np.int32)
+        v = np.ascontiguousarray(A.val, np.float64)
         if nongalerkin_gamma is None:
             st = lib.amg_setup_from_csr(self.n, rp.ctypes.data, ci.ctypes.data, v.ctypes.data,
                                         C.byref(sp), C.c_void_p(self.stream.cuda_stream), alloc, free,
@@ -245,10 +283,13 @@ class Hierarchy:
                                                     C.byref(h))
         if st != OK:
             raise AmgError(st, lib.amg_last_error(None).decode())
+        self._finish(h)
+
+    def _finish(self, h):
         self._h = h
         _live.add(self)
         nl = C.c_int32()
-        self._check(lib.amg_num_levels(h, C.byref(nl)))
+        self._check(self._lib.amg_num_levels(h, C.byref(nl)))
         self.nlev = nl.value
 
     # -- plumbing --------------------------------------------------------

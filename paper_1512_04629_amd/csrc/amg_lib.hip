@@ -26,6 +26,7 @@
 #include "block_kernels.hpp"
 #include "host_setup.hpp"
 #include "kernels.hpp"
+#include "setup_kernels.hpp"
 
 using namespace amg355;
 
@@ -223,19 +224,25 @@ void check_launch() {
     if (e != hipSuccess) throw AmgFailure{AMG_ERR_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e)};
 }
 
+// launch shape of a matrix with nnz stored entries
+void set_shape(DevMat& d, int64_t nnz) {
+    d.nnz = nnz;
+    d.nnz_known = true;
+    d.shape_nnz = nnz;
+    d.width = pick_width(d.rows ? (double)nnz / d.rows : 1.0);
+}
+
 DevMat upload_mat(amg_ctx* h, const HostCsr& m) {
     DevMat d;
     d.rows = m.rows;
     d.cols = m.cols;
-    d.nnz = m.nnz();
     d.rp = dalloc_n<int32_t>(h, d.rows + 1);
-    d.ci = dalloc_n<int32_t>(h, d.nnz + kCsrPad);
-    d.v = dalloc_n<double>(h, d.nnz + kCsrPad);
+    d.ci = dalloc_n<int32_t>(h, m.nnz() + kCsrPad);
+    d.v = dalloc_n<double>(h, m.nnz() + kCsrPad);
+    set_shape(d, m.nnz());
     upload(h, d.rp, m.ptr.data(), d.rows + 1);
     upload(h, d.ci, m.idx.data(), d.nnz);
     upload(h, d.v, m.val.data(), d.nnz);
-    d.shape_nnz = d.nnz;
-    d.width = pick_width(d.rows ? (double)d.nnz / d.rows : 1.0);
     return d;
 }
 
@@ -1551,6 +1558,8 @@ void destroy_batch(amg_batch_ctx* e) {
 // ---------------------------------------------------------------------------
 // setup
 // ---------------------------------------------------------------------------
+void finish_setup(amg_ctx* h);
+
 void setup(amg_ctx* h, int64_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
            const std::vector<double>& nongalerkin_gamma) {
     HostCsr a;
@@ -1578,17 +1587,11 @@ void setup(amg_ctx* h, int64_t n, const int32_t* row_ptr, const int32_t* col, co
                                                   std::to_string(kMaxDenseCoarse)};
     const int L = (int)hl.size() - 1;
     h->lv.resize(hl.size());
-    int partial_need = vector_launch_blocks(std::max(1, (int)n));
     for (int l = 0; l <= L; ++l) {
         DevLevel& d = h->lv[l];
         HostLevel& s = hl[l];
         d.n = s.A.rows;
         d.A = upload_mat(h, s.A);
-        d.Ah = d.A;
-        d.ah_alias = true;
-        d.dinv = dalloc_n<double>(h, d.n);
-        launch_inverse_diagonal(d.A.view(), d.dinv, nullptr, h->stream);
-        partial_need = std::max(partial_need, row_launch_blocks(d.n, d.A.width));
         if (l < L) {
             d.P = upload_mat(h, s.P);
             d.R = upload_mat(h, s.R);
@@ -1596,6 +1599,26 @@ void setup(amg_ctx* h, int64_t n, const int32_t* row_ptr, const int32_t* col, co
             d.c_points = dalloc_n<int32_t>(h, d.nc);
             upload(h, d.c_points, s.c_points.data(), d.nc);
             d.split = s.split;
+        }
+    }
+    finish_setup(h);
+}
+
+// everything a hierarchy needs once its levels hold A, P, R, c_points and
+// the split: 1/diag, work vectors, reduction and scan buffers, the coarsest
+// inverse
+void finish_setup(amg_ctx* h) {
+    const int L = (int)h->lv.size() - 1;
+    const int64_t n = h->lv[0].n;
+    int partial_need = vector_launch_blocks(std::max(1, (int)n));
+    for (int l = 0; l <= L; ++l) {
+        DevLevel& d = h->lv[l];
+        d.Ah = d.A;
+        d.ah_alias = true;
+        d.dinv = dalloc_n<double>(h, d.n);
+        launch_inverse_diagonal(d.A.view(), d.dinv, nullptr, h->stream);
+        partial_need = std::max(partial_need, row_launch_blocks(d.n, d.A.width));
+        if (l < L) {
             partial_need = std::max(partial_need, row_launch_blocks(d.P.rows, d.P.width));
             partial_need = std::max(partial_need, row_launch_blocks(d.R.rows, d.R.width));
         }
@@ -1621,6 +1644,317 @@ void setup(amg_ctx* h, int64_t n, const int32_t* row_ptr, const int32_t* col, co
     sync(h);
     refresh_coarse_inverse(h);
     h->prof.assign((size_t)AMG_K_NUM * h->lv.size(), ProfAcc{});
+}
+
+// ---------------------------------------------------------------------------
+// device setup (Section 2, amg_setup, with every step in device kernels)
+// ---------------------------------------------------------------------------
+// device temporaries of one setup; whatever is still held is freed on every
+// exit path, and an array that becomes part of the hierarchy is claimed
+struct SetupTemps {
+    amg_ctx* h;
+    std::vector<void*> held;
+    explicit SetupTemps(amg_ctx* hh) : h(hh) {}
+    ~SetupTemps() { rewind(0); }
+    template <class T>
+    T* get(int64_t n) {
+        T* p = dalloc_n<T>(h, n);
+        held.push_back(p);
+        return p;
+    }
+    void claim(const void* p) {
+        auto it = std::find(held.begin(), held.end(), p);
+        if (it != held.end()) held.erase(it);
+    }
+    void release(void* p) {
+        auto it = std::find(held.begin(), held.end(), p);
+        if (it != held.end()) {
+            held.erase(it);
+            dfree(h, p);
+        }
+    }
+    size_t mark() const { return held.size(); }
+    void rewind(size_t m) {
+        while (held.size() > m) {
+            dfree(h, held.back());
+            held.pop_back();
+        }
+    }
+};
+
+// bits that hold every value in [0, count)
+int bits_for(int64_t count) {
+    int b = 1;
+    while ((int64_t(1) << b) < count) ++b;
+    return b;
+}
+
+template <class T>
+T read_scalar(amg_ctx* h, const T* p) {
+    T v{};
+    download(h, &v, p, 1);
+    sync(h);
+    return v;
+}
+
+void check_setup_error(amg_ctx* h, int* err) {
+    int e[2] = {0, 0};
+    download(h, e, err, 2);
+    sync(h);
+    if (!e[0]) return;
+    static const std::pair<int, const char*> why[] = {
+        {kErrRowPtr, "row_ptr must start at 0, be non-decreasing and end at nnz"},
+        {kErrColRange, "column index out of range"},
+        {kErrColOrder, "columns not strictly ascending"},
+        {kErrNonFinite, "non-finite value"},
+        {kErrNoDiag, "missing diagonal"},
+        {kErrDiagSign, "non-positive diagonal"},
+        {kErrAsymmetric, "matrix is not bitwise symmetric"},
+        {kErrPattern, "coarse operator pattern is not structurally symmetric"}};
+    for (auto& w : why)
+        if (e[0] & w.first) {
+            std::string msg = w.second;
+            if (w.first != kErrPattern) msg += " (first offending row " + std::to_string(e[1]) + ")";
+            throw AmgFailure{AMG_ERR_BAD_MATRIX, msg};
+        }
+}
+
+void scan_int64(amg_ctx* h, SetupTemps& t, const int64_t* in, int64_t* out, int64_t m) {
+    size_t bytes = 0;
+    HIP_CHECK(scan_counts(nullptr, bytes, in, out, m, h->stream));
+    void* tmp = t.get<char>((int64_t)bytes);
+    HIP_CHECK(scan_counts(tmp, bytes, in, out, m, h->stream));
+    t.release(tmp);
+}
+
+// m terms (key = row << col_bits | col, value) in keys[0] / vals[0] (each
+// with room for m + 1 entries) -> CSR of `rows` x `cols` with every entry the
+// sum of its terms in list order; the sort is stable, so that order is the
+// order the terms were listed in
+DevMat combine_terms(amg_ctx* h, SetupTemps& t, uint64_t* keys[2], double* vals[2], int64_t m, int rows,
+                     int cols, int col_bits, int key_bits) {
+    hipStream_t st = h->stream;
+    int res = 0;
+    if (m > 0) {
+        size_t bytes = 0;
+        HIP_CHECK(sort_pairs(nullptr, bytes, keys, vals, m, key_bits, res, st));
+        void* tmp = t.get<char>((int64_t)bytes);
+        HIP_CHECK(sort_pairs(tmp, bytes, keys, vals, m, key_bits, res, st));
+        t.release(tmp);
+    }
+    const uint64_t* sk = keys[res];
+    const double* sv = vals[res];
+    uint64_t* run_keys = keys[1 - res];
+    int64_t* flags = reinterpret_cast<int64_t*>(vals[1 - res]);
+    int64_t* head = t.get<int64_t>(m + 1);
+    launch_run_heads(m, sk, flags, st);
+    scan_int64(h, t, flags, head, m);
+    const int64_t nnz = read_scalar(h, head + m);
+    if (nnz > INT32_MAX) throw AmgFailure{AMG_ERR_INVALID_ARG, "coarse operator exceeds int32 nonzeros"};
+    DevMat out;
+    out.rows = rows;
+    out.cols = cols;
+    out.rp = t.get<int32_t>(rows + 1);
+    out.ci = t.get<int32_t>(nnz + kCsrPad);
+    out.v = t.get<double>(nnz + kCsrPad);
+    set_shape(out, nnz);
+    launch_run_sums(m, sk, sv, head, col_bits, out.ci, out.v, run_keys, st);
+    launch_rowptr_from_keys(nnz, run_keys, col_bits, rows, out.rp, st);
+    check_launch();
+    t.release(head);
+    return out;
+}
+
+void claim_mat(SetupTemps& t, const DevMat& m) {
+    t.claim(m.rp);
+    t.claim(m.ci);
+    t.claim(m.v);
+}
+
+void release_mat(SetupTemps& t, DevMat& m) {
+    t.release(m.rp);
+    t.release(m.ci);
+    t.release(m.v);
+    m = DevMat{};
+}
+
+// coarsening: AMG_COARSEN_RS (the first pass on the host, from the strength
+// pattern built here) or AMG_COARSEN_PMIS (on the device, weights of level l
+// from the SplitMix64 stream seed + l)
+void setup_device(amg_ctx* h, int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col,
+                  const double* val, int coarsening, uint64_t seed) {
+    hipStream_t st = h->stream;
+    SetupTemps t(h);
+    int* err = t.get<int>(2);
+    const int err_init[2] = {0, INT32_MAX};
+    upload(h, err, err_init, 2);
+    launch_validate_csr((int)n, nnz, row_ptr, col, val, err, st);
+    check_launch();
+    check_setup_error(h, err);
+
+    h->lv.clear();
+    h->lv.emplace_back();
+    {
+        DevMat& A = h->lv[0].A;
+        A.rows = A.cols = (int)n;
+        A.rp = dalloc_n<int32_t>(h, n + 1);
+        A.ci = dalloc_n<int32_t>(h, nnz + kCsrPad);
+        A.v = dalloc_n<double>(h, nnz + kCsrPad);
+        set_shape(A, nnz);
+        HIP_CHECK(hipMemcpyAsync(A.rp, row_ptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToDevice, st));
+        HIP_CHECK(hipMemcpyAsync(A.ci, col, sizeof(int32_t) * nnz, hipMemcpyDeviceToDevice, st));
+        HIP_CHECK(hipMemcpyAsync(A.v, val, sizeof(double) * nnz, hipMemcpyDeviceToDevice, st));
+        h->lv[0].n = (int)n;
+    }
+    int32_t* scan_tmp = t.get<int32_t>(scan_scratch_ints((int)n));
+    while (h->lv.back().n > h->sp.max_coarse && (int)h->lv.size() < h->sp.max_levels) {
+        const int l = (int)h->lv.size() - 1;
+        const int nl = h->lv[l].n;
+        const DevMat A = h->lv[l].A;
+        const size_t level_mark = t.mark();
+        // strength pattern and lambda
+        int32_t* cnt = t.get<int32_t>(nl + 1);
+        int32_t* srp = t.get<int32_t>(nl + 1);
+        launch_strength_count(nl, A.rp, A.ci, A.v, h->sp.theta, cnt, st);
+        launch_exclusive_scan(nl, cnt, srp, scan_tmp, st);
+        const int32_t snnz = read_scalar(h, srp + nl);
+        int32_t* sci = t.get<int32_t>(snnz);
+        int32_t* lam = t.get<int32_t>(nl);
+        launch_fill_u32(nl, reinterpret_cast<unsigned*>(lam), 0u, st);
+        launch_strength_fill(nl, A.rp, A.ci, A.v, h->sp.theta, srp, sci, lam, st);
+        // C/F split
+        int32_t* state = t.get<int32_t>(nl);
+        if (coarsening == AMG_COARSEN_PMIS) {
+            double* w = t.get<double>(nl);
+            int32_t* mark = t.get<int32_t>(nl);
+            int32_t* left = t.get<int32_t>(1);
+            launch_pmis_init(nl, lam, seed + (uint64_t)l, w, state, mark, st);
+            // every round decides at least the undecided point of largest weight
+            for (int round = 1;; ++round) {
+                if (round > nl + 1) throw AmgFailure{AMG_ERR_DEVICE, "PMIS rounds did not finish"};
+                launch_pmis_round(nl, srp, sci, w, state, mark, round, left, st);
+                check_launch();
+                if (read_scalar(h, left) == 0) break;
+            }
+        } else {
+            HostCsr s;
+            s.rows = s.cols = nl;
+            s.ptr.resize(nl + 1);
+            s.idx.resize(snnz);
+            download(h, s.ptr.data(), srp, nl + 1);
+            download(h, s.idx.data(), sci, snnz);
+            sync(h);
+            const std::vector<int32_t> split = ruge_stueben_split(s);
+            upload(h, state, split.data(), nl);
+            sync(h);   // the host copy goes out of scope
+        }
+        // coarse numbering
+        int32_t* cidx = t.get<int32_t>(nl + 1);
+        launch_c_flags(nl, state, cnt, st);
+        launch_exclusive_scan(nl, cnt, cidx, scan_tmp, st);
+        const int32_t nc = read_scalar(h, cidx + nl);
+        if (nc == 0 || nc == nl) {
+            t.rewind(level_mark);
+            break;
+        }
+        {
+            std::vector<int32_t> cf(nl);
+            download(h, cf.data(), state, nl);
+            sync(h);
+            for (auto& c : cf) c = c == kPtC;
+            h->lv[l].split = std::move(cf);
+        }
+        h->lv[l].nc = nc;
+        h->lv[l].c_points = dalloc_n<int32_t>(h, nc);
+        launch_c_points(nl, state, cidx, h->lv[l].c_points, st);
+        // direct interpolation
+        DevMat P;
+        P.rows = nl;
+        P.cols = nc;
+        P.rp = t.get<int32_t>(nl + 1);
+        launch_interp_count(nl, srp, sci, state, cnt, st);
+        launch_exclusive_scan(nl, cnt, P.rp, scan_tmp, st);
+        const int32_t pnnz = read_scalar(h, P.rp + nl);
+        P.ci = t.get<int32_t>(pnnz + kCsrPad);
+        P.v = t.get<double>(pnnz + kCsrPad);
+        set_shape(P, pnnz);
+        launch_interp_fill(nl, A.rp, A.ci, A.v, srp, sci, state, cidx, P.rp, P.ci, P.v, st);
+        check_launch();
+        claim_mat(t, P);
+        h->lv[l].P = P;
+        const int rb = bits_for(nl), cb = bits_for(nc);
+        // R = P^T: the entries of P sorted by (column, row)
+        {
+            uint64_t* keys[2] = {t.get<uint64_t>(pnnz + 1), t.get<uint64_t>(pnnz + 1)};
+            double* vals[2] = {t.get<double>(pnnz + 1), t.get<double>(pnnz + 1)};
+            launch_transpose_keys(nl, P.rp, P.ci, P.v, rb, keys[0], vals[0], st);
+            int res = 0;
+            size_t bytes = 0;
+            HIP_CHECK(sort_pairs(nullptr, bytes, keys, vals, pnnz, rb + cb, res, st));
+            void* tmp = t.get<char>((int64_t)bytes);
+            HIP_CHECK(sort_pairs(tmp, bytes, keys, vals, pnnz, rb + cb, res, st));
+            DevMat R;
+            R.rows = nc;
+            R.cols = nl;
+            R.rp = dalloc_n<int32_t>(h, nc + 1);
+            R.ci = dalloc_n<int32_t>(h, pnnz + kCsrPad);
+            R.v = dalloc_n<double>(h, pnnz + kCsrPad);
+            set_shape(R, pnnz);
+            h->lv[l].R = R;
+            launch_unpack_keys(pnnz, keys[res], vals[res], rb, R.ci, R.v, st);
+            launch_rowptr_from_keys(pnnz, keys[res], rb, nc, R.rp, st);
+            check_launch();
+            for (void* q : {(void*)tmp, (void*)keys[0], (void*)keys[1], (void*)vals[0], (void*)vals[1]})
+                t.release(q);
+        }
+        // T = A P
+        int64_t* cnt64 = t.get<int64_t>(nl + 1);
+        int64_t* off = t.get<int64_t>(nl + 1);
+        launch_ap_count(nl, A.rp, A.ci, P.rp, cnt64, st);
+        scan_int64(h, t, cnt64, off, nl);
+        int64_t m = read_scalar(h, off + nl);
+        DevMat T;
+        {
+            uint64_t* keys[2] = {t.get<uint64_t>(m + 1), t.get<uint64_t>(m + 1)};
+            double* vals[2] = {t.get<double>(m + 1), t.get<double>(m + 1)};
+            launch_ap_expand(nl, A.rp, A.ci, A.v, P.rp, P.ci, P.v, off, cb, keys[0], vals[0], st);
+            check_launch();
+            T = combine_terms(h, t, keys, vals, m, nl, nc, cb, rb + cb);
+            for (void* q : {(void*)keys[0], (void*)keys[1], (void*)vals[0], (void*)vals[1]}) t.release(q);
+        }
+        // C = P^T T, terms of each (I, J) listed in ascending fine row
+        launch_pt_count(nl, P.rp, T.rp, cnt64, st);
+        scan_int64(h, t, cnt64, off, nl);
+        m = read_scalar(h, off + nl);
+        DevMat C;
+        {
+            uint64_t* keys[2] = {t.get<uint64_t>(m + 1), t.get<uint64_t>(m + 1)};
+            double* vals[2] = {t.get<double>(m + 1), t.get<double>(m + 1)};
+            launch_pt_expand(nl, P.rp, P.ci, P.v, T.rp, T.ci, T.v, off, cb, keys[0], vals[0], st);
+            check_launch();
+            release_mat(t, T);
+            C = combine_terms(h, t, keys, vals, m, nc, nc, cb, 2 * cb);
+            for (void* q : {(void*)keys[0], (void*)keys[1], (void*)vals[0], (void*)vals[1]}) t.release(q);
+        }
+        // A_{l+1} = (C + C^T) / 2
+        double* sym = t.get<double>(C.nnz + kCsrPad);
+        launch_symmetrize(nc, C.rp, C.ci, C.v, sym, err, st);
+        check_launch();
+        check_setup_error(h, err);
+        t.release(C.v);
+        C.v = sym;
+        claim_mat(t, C);
+        t.rewind(level_mark);
+        h->lv.emplace_back();
+        h->lv.back().A = C;
+        h->lv.back().n = nc;
+    }
+    t.rewind(0);
+    if (h->lv.back().n > kMaxDenseCoarse)
+        throw AmgFailure{AMG_ERR_INVALID_ARG, "coarsest level has " + std::to_string(h->lv.back().n) +
+                                                  " rows; the dense coarse solve allows at most " +
+                                                  std::to_string(kMaxDenseCoarse)};
+    finish_setup(h);
 }
 
 void destroy(amg_ctx* h) {
@@ -1715,12 +2049,11 @@ amg_status vcycle_block_abi(amg_handle h, int32_t nrhs, const T* b, T* x) {
     });
 }
 
-amg_status setup_abi(int64_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
-                            const amg_setup_params* params, const std::vector<double>& ng, void* stream,
-                            amg_alloc_fn alloc, amg_free_fn free_fn, void* user, amg_handle* out) {
-    if (!out) return AMG_ERR_INVALID_ARG;
-    *out = nullptr;
-    if (n <= 0 || n > INT32_MAX - 1 || !row_ptr || !col || !val) return AMG_ERR_INVALID_ARG;
+// a new handle built by `build` (which throws AmgFailure on failure); *out
+// is cleared by the caller
+template <class F>
+amg_status setup_abi(const amg_setup_params* params, void* stream, amg_alloc_fn alloc, amg_free_fn free_fn,
+                     void* user, amg_handle* out, F&& build) {
     if ((alloc == nullptr) != (free_fn == nullptr)) return AMG_ERR_INVALID_ARG;
     amg_setup_params sp;
     amg_setup_params_default(&sp);
@@ -1728,8 +2061,6 @@ amg_status setup_abi(int64_t n, const int32_t* row_ptr, const int32_t* col, cons
     if (!(sp.theta > 0.0 && sp.theta <= 1.0) || sp.max_coarse < 1 || sp.max_levels < 1 ||
         !(sp.omega > 0.0 && sp.omega < 2.0) || sp.nu_pre < 0 || sp.nu_post < 0)
         return AMG_ERR_INVALID_ARG;
-    for (double g : ng)
-        if (!valid_gamma(g)) return AMG_ERR_INVALID_ARG;
     amg_ctx* h = new (std::nothrow) amg_ctx();
     if (!h) return AMG_ERR_OUT_OF_MEMORY;
     h->stream = (hipStream_t)stream;
@@ -1739,7 +2070,7 @@ amg_status setup_abi(int64_t n, const int32_t* row_ptr, const int32_t* col, cons
     h->sp = sp;
     amg_status st = guarded(h, [&] {
         HIP_CHECK(hipGetDevice(&h->device));
-        setup(h, n, row_ptr, col, val, ng);
+        build(h);
         return AMG_OK;
     });
     if (st != AMG_OK) {
@@ -1784,7 +2115,11 @@ void amg_solve_params_default(amg_solve_params* p) {
 amg_status amg_setup_from_csr(int64_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
                               const amg_setup_params* params, void* stream, amg_alloc_fn alloc,
                               amg_free_fn free_fn, void* user, amg_handle* out) {
-    return setup_abi(n, row_ptr, col, val, params, {}, stream, alloc, free_fn, user, out);
+    if (!out) return AMG_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (n <= 0 || n > INT32_MAX - 1 || !row_ptr || !col || !val) return AMG_ERR_INVALID_ARG;
+    return setup_abi(params, stream, alloc, free_fn, user, out,
+                     [&](amg_ctx* h) { setup(h, n, row_ptr, col, val, {}); });
 }
 
 amg_status amg_setup_nongalerkin_from_csr(int64_t n, const int32_t* row_ptr, const int32_t* col,
@@ -1792,11 +2127,29 @@ amg_status amg_setup_nongalerkin_from_csr(int64_t n, const int32_t* row_ptr, con
                                           const double* gamma, int32_t count, void* stream,
                                           amg_alloc_fn alloc, amg_free_fn free_fn, void* user,
                                           amg_handle* out) {
-    if (out) *out = nullptr;
+    if (!out) return AMG_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (n <= 0 || n > INT32_MAX - 1 || !row_ptr || !col || !val) return AMG_ERR_INVALID_ARG;
     if (!gamma || count < 1) return AMG_ERR_INVALID_ARG;
     std::vector<double> ng(gamma, gamma + count);
     ng[0] = 0.0;    // A_0 is the given matrix
-    return setup_abi(n, row_ptr, col, val, params, ng, stream, alloc, free_fn, user, out);
+    for (double g : ng)
+        if (!valid_gamma(g)) return AMG_ERR_INVALID_ARG;
+    return setup_abi(params, stream, alloc, free_fn, user, out,
+                     [&](amg_ctx* h) { setup(h, n, row_ptr, col, val, ng); });
+}
+
+amg_status amg_setup_device(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col,
+                            const double* val, const amg_setup_params* params, int32_t coarsening,
+                            uint64_t seed, void* stream, amg_alloc_fn alloc, amg_free_fn free_fn, void* user,
+                            amg_handle* out) {
+    if (!out) return AMG_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (n <= 0 || n > INT32_MAX - 1 || nnz < n || nnz > INT32_MAX - 8 || !row_ptr || !col || !val)
+        return AMG_ERR_INVALID_ARG;
+    if (coarsening != AMG_COARSEN_RS && coarsening != AMG_COARSEN_PMIS) return AMG_ERR_INVALID_ARG;
+    return setup_abi(params, stream, alloc, free_fn, user, out,
+                     [&](amg_ctx* h) { setup_device(h, n, nnz, row_ptr, col, val, coarsening, seed); });
 }
 
 amg_status amg_sparsify(amg_handle h, double gamma, int32_t first_level) {

@@ -303,6 +303,8 @@ bool symmetrize(HostCsr& c, std::string& why) {
 
 }  // namespace
 
+std::vector<int32_t> ruge_stueben_split(const HostCsr& s) { return rs_first_pass(s); }
+
 HostCsr transpose_csr(const HostCsr& p) {
     HostCsr t;
     t.rows = p.cols;

@@ -49,4 +49,7 @@ bool build_galerkin_hierarchy(const HostCsr& a, const SetupConfig& cfg,
 // R = P^T by counting sort (rows of R list the rows of P in ascending order).
 HostCsr transpose_csr(const HostCsr& p);
 
+// Ruge-Stueben first-pass C/F split (1 = C) of a strength pattern.
+std::vector<int32_t> ruge_stueben_split(const HostCsr& s);
+
 }  // namespace amg355

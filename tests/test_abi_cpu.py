@@ -49,6 +49,17 @@ def test_null_handle_and_bad_arguments_are_rejected_without_a_device():
     assert lib.amg_setup_from_csr(0, None, None, None, None, None, amg.ALLOC_FN(), amg.FREE_FN(),
                                   None, C.byref(out)) == -1
     assert out.value is None
+    # device setup: sizes, NULL arrays and the coarsening are checked first
+    fake = C.c_void_p(16)
+    assert lib.amg_setup_device(0, 0, fake, fake, fake, None, 0, 0, None, amg.ALLOC_FN(), amg.FREE_FN(),
+                                None, C.byref(out)) == -1
+    assert lib.amg_setup_device(10, 5, fake, fake, fake, None, 0, 0, None, amg.ALLOC_FN(), amg.FREE_FN(),
+                                None, C.byref(out)) == -1
+    assert lib.amg_setup_device(10, 28, fake, fake, fake, None, 2, 0, None, amg.ALLOC_FN(), amg.FREE_FN(),
+                                None, C.byref(out)) == -1
+    assert lib.amg_setup_device(10, 28, None, fake, fake, None, 1, 0, None, amg.ALLOC_FN(), amg.FREE_FN(),
+                                None, C.byref(out)) == -1
+    assert out.value is None
     lib.amg_destroy(None)
 
 
