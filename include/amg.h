@@ -158,6 +158,22 @@ amg_status amg_setup_device(int64_t n, int64_t nnz, const int32_t* row_ptr, cons
                             uint64_t seed, void* stream, amg_alloc_fn alloc, amg_free_fn free_fn,
                             void* user, amg_handle* out);
 
+/* Timing of amg_setup_device's kernel classes with HIP events on the setup's
+   stream, for the whole process: while enabled, every device setup adds,
+   per class, the number of timed groups, their summed duration in
+   milliseconds and their algorithmic bytes (each array entry moved once per
+   launch; a sort of m (key, value) pairs counts 32 m, one read and one write
+   of each pair).  Enabling resets the totals; enable = 0 stops timing.
+   Classes AMG_SK_*: strength pattern, C/F split, interpolation (numbering
+   and P), transpose (R = P^T without its sort), term listing of the
+   products, sorts, combination of sorted terms into CSR, symmetrization. */
+enum {
+    AMG_SK_STRENGTH = 0, AMG_SK_SPLIT = 1, AMG_SK_INTERP = 2, AMG_SK_TRANSPOSE = 3,
+    AMG_SK_EXPAND = 4, AMG_SK_SORT = 5, AMG_SK_COMBINE = 6, AMG_SK_SYMMETRIZE = 7, AMG_SK_NUM = 8
+};
+amg_status amg_setup_profile_enable(int32_t enable);
+amg_status amg_setup_profile_read(int32_t kernel_class, int64_t* count, double* ms, double* bytes);
+
 /* Sparse Galerkin sparsification with diagonal lumping (Algorithm 3 keep set,
    Algorithm 3b loop) of every level l >= first_level (first_level >= 1) with
    drop tolerance gamma in [0, 1]; levels below first_level get gamma 0.  The

@@ -35,7 +35,7 @@ KERNEL = {"JACOBI": 0, "JACOBI_ZERO": 1, "RESIDUAL": 2, "RESTRICT": 3, "INTERP":
 # every symbol include/amg.h declares
 ABI_SYMBOLS = (
     "amg_setup_params_default", "amg_solve_params_default", "amg_setup_from_csr",
-    "amg_setup_nongalerkin_from_csr", "amg_setup_device",
+    "amg_setup_nongalerkin_from_csr", "amg_setup_device", "amg_setup_profile_enable", "amg_setup_profile_read",
     "amg_sparsify", "amg_sparsify_levels", "amg_set_method", "amg_reintroduce", "amg_solve", "amg_vcycle",
     "amg_vcycle32",
     "amg_solve_block", "amg_vcycle_block", "amg_vcycle_block32", "amg_batch_bytes", "amg_batch_create",
@@ -47,6 +47,26 @@ ABI_SYMBOLS = (
 
 
 COARSENINGS = {"rs": 0, "pmis": 1}     # AMG_COARSEN_RS, AMG_COARSEN_PMIS
+SETUP_KERNELS = ("STRENGTH", "SPLIT", "INTERP", "TRANSPOSE", "EXPAND", "SORT", "COMBINE", "SYMMETRIZE")
+
+
+def setup_profile_enable(on: bool = True):
+    """Starts (resetting the totals) or stops the process-wide timing of the
+    device setup's kernel classes."""
+    load_library().amg_setup_profile_enable(int(bool(on)))
+
+
+def setup_profile_read() -> dict:
+    """{class: (timed groups, milliseconds, algorithmic bytes)} since the last enable."""
+    lib = load_library()
+    out = {}
+    for k, name in enumerate(SETUP_KERNELS):
+        c, ms, nb = C.c_int64(), C.c_double(), C.c_double()
+        st = lib.amg_setup_profile_read(k, C.byref(c), C.byref(ms), C.byref(nb))
+        if st != OK:
+            raise AmgError(st, lib.amg_status_string(st).decode())
+        out[name] = (c.value, ms.value, nb.value)
+    return out
 
 
 class AmgError(RuntimeError):
@@ -94,6 +114,8 @@ def load_library():
                                                    FREE_FN, vp, P(vp)]
     lib.amg_setup_device.argtypes = [i64, i64, vp, vp, vp, P(SetupParams), i32, C.c_uint64, vp, ALLOC_FN,
                                      FREE_FN, vp, P(vp)]
+    lib.amg_setup_profile_enable.argtypes = [i32]
+    lib.amg_setup_profile_read.argtypes = [i32, P(i64), P(f64), P(f64)]
     lib.amg_sparsify.argtypes = [vp, f64, i32]
     lib.amg_sparsify_levels.argtypes = [vp, vp, i32]
     lib.amg_reintroduce.argtypes = [vp, i32, f64, P(i32)]
@@ -129,7 +151,8 @@ def load_library():
     lib.amg_status_string.restype = C.c_char_p
     lib.amg_last_error.argtypes = [vp]
     lib.amg_last_error.restype = C.c_char_p
-    for name in ("amg_setup_from_csr", "amg_setup_nongalerkin_from_csr", "amg_setup_device", "amg_sparsify", "amg_sparsify_levels", "amg_set_method", "amg_reintroduce",
+    for name in ("amg_setup_from_csr", "amg_setup_nongalerkin_from_csr", "amg_setup_device",
+                 "amg_setup_profile_enable", "amg_setup_profile_read", "amg_sparsify", "amg_sparsify_levels", "amg_set_method", "amg_reintroduce",
                  "amg_solve", "amg_vcycle", "amg_vcycle32", "amg_solve_block", "amg_vcycle_block",
                  "amg_vcycle_block32", "amg_batch_bytes", "amg_batch_create", "amg_batch_submit",
                  "amg_batch_step", "amg_batch_poll", "amg_batch_collect", "amg_batch_slots", "amg_device_bytes",

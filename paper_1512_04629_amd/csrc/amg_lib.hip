@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <unordered_map>
@@ -1682,6 +1683,66 @@ struct SetupTemps {
     }
 };
 
+// process-wide totals of the setup timing (amg_setup_profile_*)
+struct SetupProfile {
+    std::mutex mu;
+    bool on = false;
+    int64_t count[AMG_SK_NUM] = {};
+    double ms[AMG_SK_NUM] = {};
+    double bytes[AMG_SK_NUM] = {};
+};
+
+SetupProfile& setup_profile() {
+    static SetupProfile p;
+    return p;
+}
+
+// event pairs of one setup, added to the totals once the setup is done
+struct SetupTimer {
+    struct Rec {
+        int kind;
+        double bytes;
+        hipEvent_t start, stop;
+    };
+    hipStream_t st;
+    bool on;
+    std::vector<Rec> recs;
+    explicit SetupTimer(hipStream_t s) : st(s) {
+        std::lock_guard<std::mutex> g(setup_profile().mu);
+        on = setup_profile().on;
+    }
+    ~SetupTimer() {
+        for (auto& r : recs) {
+            (void)hipEventDestroy(r.start);
+            (void)hipEventDestroy(r.stop);
+        }
+    }
+    void begin(int kind, double bytes) {
+        if (!on) return;
+        Rec r{kind, bytes, nullptr, nullptr};
+        HIP_CHECK(hipEventCreate(&r.start));
+        HIP_CHECK(hipEventCreate(&r.stop));
+        recs.push_back(r);
+        HIP_CHECK(hipEventRecord(r.start, st));
+    }
+    void end() {
+        if (on) HIP_CHECK(hipEventRecord(recs.back().stop, st));
+    }
+    void collect() {
+        if (!on || recs.empty()) return;
+        HIP_CHECK(hipStreamSynchronize(st));
+        SetupProfile& p = setup_profile();
+        std::lock_guard<std::mutex> g(p.mu);
+        for (auto& r : recs) {
+            float ms = 0.0f;
+            HIP_CHECK(hipEventElapsedTime(&ms, r.start, r.stop));
+            p.count[r.kind] += 1;
+            p.ms[r.kind] += ms;
+            p.bytes[r.kind] += r.bytes;
+        }
+    }
+};
+
 // bits that hold every value in [0, count)
 int bits_for(int64_t count) {
     int b = 1;
@@ -1731,15 +1792,17 @@ void scan_int64(amg_ctx* h, SetupTemps& t, const int64_t* in, int64_t* out, int6
 // with room for m + 1 entries) -> CSR of `rows` x `cols` with every entry the
 // sum of its terms in list order; the sort is stable, so that order is the
 // order the terms were listed in
-DevMat combine_terms(amg_ctx* h, SetupTemps& t, uint64_t* keys[2], double* vals[2], int64_t m, int rows,
-                     int cols, int col_bits, int key_bits) {
+DevMat combine_terms(amg_ctx* h, SetupTemps& t, SetupTimer& tm, uint64_t* keys[2], double* vals[2], int64_t m,
+                     int rows, int cols, int col_bits, int key_bits) {
     hipStream_t st = h->stream;
     int res = 0;
     if (m > 0) {
         size_t bytes = 0;
         HIP_CHECK(sort_pairs(nullptr, bytes, keys, vals, m, key_bits, res, st));
         void* tmp = t.get<char>((int64_t)bytes);
+        tm.begin(AMG_SK_SORT, 32.0 * m);
         HIP_CHECK(sort_pairs(tmp, bytes, keys, vals, m, key_bits, res, st));
+        tm.end();
         t.release(tmp);
     }
     const uint64_t* sk = keys[res];
@@ -1747,8 +1810,10 @@ DevMat combine_terms(amg_ctx* h, SetupTemps& t, uint64_t* keys[2], double* vals[
     uint64_t* run_keys = keys[1 - res];
     int64_t* flags = reinterpret_cast<int64_t*>(vals[1 - res]);
     int64_t* head = t.get<int64_t>(m + 1);
+    tm.begin(AMG_SK_COMBINE, 16.0 * m + 16.0 * m);
     launch_run_heads(m, sk, flags, st);
     scan_int64(h, t, flags, head, m);
+    tm.end();
     const int64_t nnz = read_scalar(h, head + m);
     if (nnz > INT32_MAX) throw AmgFailure{AMG_ERR_INVALID_ARG, "coarse operator exceeds int32 nonzeros"};
     DevMat out;
@@ -1758,8 +1823,10 @@ DevMat combine_terms(amg_ctx* h, SetupTemps& t, uint64_t* keys[2], double* vals[
     out.ci = t.get<int32_t>(nnz + kCsrPad);
     out.v = t.get<double>(nnz + kCsrPad);
     set_shape(out, nnz);
+    tm.begin(AMG_SK_COMBINE, 24.0 * m + 20.0 * nnz + 8.0 * nnz + 4.0 * (rows + 1));
     launch_run_sums(m, sk, sv, head, col_bits, out.ci, out.v, run_keys, st);
     launch_rowptr_from_keys(nnz, run_keys, col_bits, rows, out.rp, st);
+    tm.end();
     check_launch();
     t.release(head);
     return out;
@@ -1785,6 +1852,7 @@ void setup_device(amg_ctx* h, int64_t n, int64_t nnz, const int32_t* row_ptr, co
                   const double* val, int coarsening, uint64_t seed) {
     hipStream_t st = h->stream;
     SetupTemps t(h);
+    SetupTimer tm(st);
     int* err = t.get<int>(2);
     const int err_init[2] = {0, INT32_MAX};
     upload(h, err, err_init, 2);
@@ -1811,32 +1879,42 @@ void setup_device(amg_ctx* h, int64_t n, int64_t nnz, const int32_t* row_ptr, co
         const int l = (int)h->lv.size() - 1;
         const int nl = h->lv[l].n;
         const DevMat A = h->lv[l].A;
+        const double anz = (double)A.nnz, np1 = (double)nl + 1;
         const size_t level_mark = t.mark();
         // strength pattern and lambda
         int32_t* cnt = t.get<int32_t>(nl + 1);
         int32_t* srp = t.get<int32_t>(nl + 1);
+        tm.begin(AMG_SK_STRENGTH, 12 * anz + 4 * np1 + 4.0 * nl + 8 * np1);
         launch_strength_count(nl, A.rp, A.ci, A.v, h->sp.theta, cnt, st);
         launch_exclusive_scan(nl, cnt, srp, scan_tmp, st);
+        tm.end();
         const int32_t snnz = read_scalar(h, srp + nl);
         int32_t* sci = t.get<int32_t>(snnz);
         int32_t* lam = t.get<int32_t>(nl);
+        tm.begin(AMG_SK_STRENGTH, 12 * anz + 8 * np1 + 8.0 * snnz + 8.0 * nl);
         launch_fill_u32(nl, reinterpret_cast<unsigned*>(lam), 0u, st);
         launch_strength_fill(nl, A.rp, A.ci, A.v, h->sp.theta, srp, sci, lam, st);
+        tm.end();
         // C/F split
         int32_t* state = t.get<int32_t>(nl);
         if (coarsening == AMG_COARSEN_PMIS) {
             double* w = t.get<double>(nl);
             int32_t* mark = t.get<int32_t>(nl);
             int32_t* left = t.get<int32_t>(1);
+            tm.begin(AMG_SK_SPLIT, 4.0 * nl + 16.0 * nl);
             launch_pmis_init(nl, lam, seed + (uint64_t)l, w, state, mark, st);
+            tm.end();
             // every round decides at least the undecided point of largest weight
             for (int round = 1;; ++round) {
                 if (round > nl + 1) throw AmgFailure{AMG_ERR_DEVICE, "PMIS rounds did not finish"};
+                tm.begin(AMG_SK_SPLIT, 2 * (4.0 * snnz + 4 * np1) + 36.0 * nl);
                 launch_pmis_round(nl, srp, sci, w, state, mark, round, left, st);
+                tm.end();
                 check_launch();
                 if (read_scalar(h, left) == 0) break;
             }
         } else {
+            tm.begin(AMG_SK_SPLIT, 0.0);
             HostCsr s;
             s.rows = s.cols = nl;
             s.ptr.resize(nl + 1);
@@ -1846,12 +1924,15 @@ void setup_device(amg_ctx* h, int64_t n, int64_t nnz, const int32_t* row_ptr, co
             sync(h);
             const std::vector<int32_t> split = ruge_stueben_split(s);
             upload(h, state, split.data(), nl);
+            tm.end();
             sync(h);   // the host copy goes out of scope
         }
         // coarse numbering
         int32_t* cidx = t.get<int32_t>(nl + 1);
+        tm.begin(AMG_SK_INTERP, 8.0 * nl + 8 * np1);
         launch_c_flags(nl, state, cnt, st);
         launch_exclusive_scan(nl, cnt, cidx, scan_tmp, st);
+        tm.end();
         const int32_t nc = read_scalar(h, cidx + nl);
         if (nc == 0 || nc == nl) {
             t.rewind(level_mark);
@@ -1866,19 +1947,23 @@ void setup_device(amg_ctx* h, int64_t n, int64_t nnz, const int32_t* row_ptr, co
         }
         h->lv[l].nc = nc;
         h->lv[l].c_points = dalloc_n<int32_t>(h, nc);
-        launch_c_points(nl, state, cidx, h->lv[l].c_points, st);
         // direct interpolation
         DevMat P;
         P.rows = nl;
         P.cols = nc;
         P.rp = t.get<int32_t>(nl + 1);
+        tm.begin(AMG_SK_INTERP, 4.0 * snnz + 4 * np1 + 8.0 * nl + 4 * nc + 4 * np1);
+        launch_c_points(nl, state, cidx, h->lv[l].c_points, st);
         launch_interp_count(nl, srp, sci, state, cnt, st);
         launch_exclusive_scan(nl, cnt, P.rp, scan_tmp, st);
+        tm.end();
         const int32_t pnnz = read_scalar(h, P.rp + nl);
         P.ci = t.get<int32_t>(pnnz + kCsrPad);
         P.v = t.get<double>(pnnz + kCsrPad);
         set_shape(P, pnnz);
+        tm.begin(AMG_SK_INTERP, 12 * anz + 4 * np1 + 4.0 * snnz + 4 * np1 + 8.0 * nl + 12.0 * pnnz);
         launch_interp_fill(nl, A.rp, A.ci, A.v, srp, sci, state, cidx, P.rp, P.ci, P.v, st);
+        tm.end();
         check_launch();
         claim_mat(t, P);
         h->lv[l].P = P;
@@ -1887,12 +1972,16 @@ void setup_device(amg_ctx* h, int64_t n, int64_t nnz, const int32_t* row_ptr, co
         {
             uint64_t* keys[2] = {t.get<uint64_t>(pnnz + 1), t.get<uint64_t>(pnnz + 1)};
             double* vals[2] = {t.get<double>(pnnz + 1), t.get<double>(pnnz + 1)};
+            tm.begin(AMG_SK_TRANSPOSE, 12.0 * pnnz + 4 * np1 + 16.0 * pnnz);
             launch_transpose_keys(nl, P.rp, P.ci, P.v, rb, keys[0], vals[0], st);
+            tm.end();
             int res = 0;
             size_t bytes = 0;
             HIP_CHECK(sort_pairs(nullptr, bytes, keys, vals, pnnz, rb + cb, res, st));
             void* tmp = t.get<char>((int64_t)bytes);
+            tm.begin(AMG_SK_SORT, 32.0 * pnnz);
             HIP_CHECK(sort_pairs(tmp, bytes, keys, vals, pnnz, rb + cb, res, st));
+            tm.end();
             DevMat R;
             R.rows = nc;
             R.cols = nl;
@@ -1901,8 +1990,10 @@ void setup_device(amg_ctx* h, int64_t n, int64_t nnz, const int32_t* row_ptr, co
             R.v = dalloc_n<double>(h, pnnz + kCsrPad);
             set_shape(R, pnnz);
             h->lv[l].R = R;
+            tm.begin(AMG_SK_TRANSPOSE, 16.0 * pnnz + 12.0 * pnnz + 8.0 * pnnz + 4.0 * (nc + 1));
             launch_unpack_keys(pnnz, keys[res], vals[res], rb, R.ci, R.v, st);
             launch_rowptr_from_keys(pnnz, keys[res], rb, nc, R.rp, st);
+            tm.end();
             check_launch();
             for (void* q : {(void*)tmp, (void*)keys[0], (void*)keys[1], (void*)vals[0], (void*)vals[1]})
                 t.release(q);
@@ -1910,35 +2001,45 @@ void setup_device(amg_ctx* h, int64_t n, int64_t nnz, const int32_t* row_ptr, co
         // T = A P
         int64_t* cnt64 = t.get<int64_t>(nl + 1);
         int64_t* off = t.get<int64_t>(nl + 1);
+        tm.begin(AMG_SK_EXPAND, 4 * np1 + 4 * anz + 4 * np1 + 8 * np1 + 16 * np1);
         launch_ap_count(nl, A.rp, A.ci, P.rp, cnt64, st);
         scan_int64(h, t, cnt64, off, nl);
+        tm.end();
         int64_t m = read_scalar(h, off + nl);
         DevMat T;
         {
             uint64_t* keys[2] = {t.get<uint64_t>(m + 1), t.get<uint64_t>(m + 1)};
             double* vals[2] = {t.get<double>(m + 1), t.get<double>(m + 1)};
+            tm.begin(AMG_SK_EXPAND, 12 * anz + 4 * np1 + 12.0 * pnnz + 4 * np1 + 8 * np1 + 16.0 * m);
             launch_ap_expand(nl, A.rp, A.ci, A.v, P.rp, P.ci, P.v, off, cb, keys[0], vals[0], st);
+            tm.end();
             check_launch();
-            T = combine_terms(h, t, keys, vals, m, nl, nc, cb, rb + cb);
+            T = combine_terms(h, t, tm, keys, vals, m, nl, nc, cb, rb + cb);
             for (void* q : {(void*)keys[0], (void*)keys[1], (void*)vals[0], (void*)vals[1]}) t.release(q);
         }
         // C = P^T T, terms of each (I, J) listed in ascending fine row
+        tm.begin(AMG_SK_EXPAND, 8 * np1 + 8 * np1 + 16 * np1);
         launch_pt_count(nl, P.rp, T.rp, cnt64, st);
         scan_int64(h, t, cnt64, off, nl);
+        tm.end();
         m = read_scalar(h, off + nl);
         DevMat C;
         {
             uint64_t* keys[2] = {t.get<uint64_t>(m + 1), t.get<uint64_t>(m + 1)};
             double* vals[2] = {t.get<double>(m + 1), t.get<double>(m + 1)};
+            tm.begin(AMG_SK_EXPAND, 12.0 * pnnz + 4 * np1 + 12.0 * T.nnz + 4 * np1 + 8 * np1 + 16.0 * m);
             launch_pt_expand(nl, P.rp, P.ci, P.v, T.rp, T.ci, T.v, off, cb, keys[0], vals[0], st);
+            tm.end();
             check_launch();
             release_mat(t, T);
-            C = combine_terms(h, t, keys, vals, m, nc, nc, cb, 2 * cb);
+            C = combine_terms(h, t, tm, keys, vals, m, nc, nc, cb, 2 * cb);
             for (void* q : {(void*)keys[0], (void*)keys[1], (void*)vals[0], (void*)vals[1]}) t.release(q);
         }
         // A_{l+1} = (C + C^T) / 2
         double* sym = t.get<double>(C.nnz + kCsrPad);
+        tm.begin(AMG_SK_SYMMETRIZE, 12.0 * C.nnz + 4.0 * (nc + 1) + 8.0 * C.nnz);
         launch_symmetrize(nc, C.rp, C.ci, C.v, sym, err, st);
+        tm.end();
         check_launch();
         check_setup_error(h, err);
         t.release(C.v);
@@ -1950,6 +2051,7 @@ void setup_device(amg_ctx* h, int64_t n, int64_t nnz, const int32_t* row_ptr, co
         h->lv.back().n = nc;
     }
     t.rewind(0);
+    tm.collect();
     if (h->lv.back().n > kMaxDenseCoarse)
         throw AmgFailure{AMG_ERR_INVALID_ARG, "coarsest level has " + std::to_string(h->lv.back().n) +
                                                   " rows; the dense coarse solve allows at most " +
@@ -2150,6 +2252,29 @@ amg_status amg_setup_device(int64_t n, int64_t nnz, const int32_t* row_ptr, cons
     if (coarsening != AMG_COARSEN_RS && coarsening != AMG_COARSEN_PMIS) return AMG_ERR_INVALID_ARG;
     return setup_abi(params, stream, alloc, free_fn, user, out,
                      [&](amg_ctx* h) { setup_device(h, n, nnz, row_ptr, col, val, coarsening, seed); });
+}
+
+amg_status amg_setup_profile_enable(int32_t enable) {
+    SetupProfile& p = setup_profile();
+    std::lock_guard<std::mutex> g(p.mu);
+    p.on = enable != 0;
+    if (p.on)
+        for (int k = 0; k < AMG_SK_NUM; ++k) {
+            p.count[k] = 0;
+            p.ms[k] = 0.0;
+            p.bytes[k] = 0.0;
+        }
+    return AMG_OK;
+}
+
+amg_status amg_setup_profile_read(int32_t kernel_class, int64_t* count, double* ms, double* bytes) {
+    if (kernel_class < 0 || kernel_class >= AMG_SK_NUM) return AMG_ERR_INVALID_ARG;
+    SetupProfile& p = setup_profile();
+    std::lock_guard<std::mutex> g(p.mu);
+    if (count) *count = p.count[kernel_class];
+    if (ms) *ms = p.ms[kernel_class];
+    if (bytes) *bytes = p.bytes[kernel_class];
+    return AMG_OK;
 }
 
 amg_status amg_sparsify(amg_handle h, double gamma, int32_t first_level) {
