@@ -34,31 +34,38 @@ def log(*a):
 
 
 def launch_bytes(h, kernel: str, level: int) -> int:
-    """Algorithmic HBM bytes of one launch: FP64 values, int32 indices, each
-    array entry counted once (a gathered vector is counted as n entries)."""
+    """Algorithmic HBM bytes of one launch: FP64 values, the column indices in
+    the width the kernel reads (4 bytes, or 2 where the library keeps 16-bit
+    indices; their per-row-block bases, at most a sixteenth of the row
+    pointers' bytes, are not counted), each array entry counted once (a
+    gathered vector is counted as n entries)."""
     li = h.level_info(level)
     n, nnz_hat, nc, nnz_p = li["n"], li["nnz_hat"], li["n_coarse"], li["nnz_P"]
     nnz_a = li["nnz"]
+
+    def entry(which):
+        return 8 + h.index_width(level, which)
+
     if kernel == "JACOBI":
         # x gathered, b, dinv read, x' written
-        return 12 * nnz_hat + 4 * (n + 1) + 32 * n
+        return entry("AHAT") * nnz_hat + 4 * (n + 1) + 32 * n
     if kernel == "JACOBI_ZERO":
         # zero-guess level: residual of the prescaled sweep omega D^-1 b that
         # the producer (restriction / CG update) wrote: x gathered, b read, r
         # written (the fused first-iteration form moves 8n more; counted as
         # this lower figure)
-        return 12 * nnz_hat + 4 * (n + 1) + 24 * n
+        return entry("AHAT") * nnz_hat + 4 * (n + 1) + 24 * n
     if kernel == "RESIDUAL":
-        nz = nnz_a if level == 0 else nnz_hat
-        return 12 * nz + 4 * (n + 1) + 24 * n
+        nz, e = (nnz_a, entry("A")) if level == 0 else (nnz_hat, entry("AHAT"))
+        return e * nz + 4 * (n + 1) + 24 * n
     if kernel == "SPMV_DOT":
-        return 12 * nnz_a + 4 * (n + 1) + 16 * n
+        return entry("A") * nnz_a + 4 * (n + 1) + 16 * n
     if kernel == "RESTRICT":
         # b_c = R r; below the coarsest level also x_c = omega dinv_c b_c
         extra = 16 * nc if level + 2 < h.nlev else 0
-        return 12 * nnz_p + 4 * (nc + 1) + 8 * n + 8 * nc + extra
+        return entry("R") * nnz_p + 4 * (nc + 1) + 8 * n + 8 * nc + extra
     if kernel == "INTERP":
-        return 12 * nnz_p + 4 * (n + 1) + 8 * nc + 16 * n
+        return entry("P") * nnz_p + 4 * (n + 1) + 8 * nc + 16 * n
     return 0
 
 

@@ -303,6 +303,18 @@ amg_status amg_export_vector(amg_handle h, int32_t l, int32_t which, double* out
 /* C/F split of level l < L (host array of n_l ints, 1 = C). */
 amg_status amg_export_split(amg_handle h, int32_t l, int32_t* cf);
 
+/* 16-bit column indices (enabled by default).  For every level's fixed
+   operators A_l, P_l and R_l that the LDS-staged row kernels run on, a second
+   copy of the column indices is kept as 16-bit offsets from a base per row
+   block of those kernels, when every block's columns span at most 65535 (it
+   does for banded operators, e.g. the 7-point stencil up to 181^3): the
+   kernels then move 10 instead of 12 bytes per entry.  Results are bitwise the same either way.  enable = 0 drops the
+   copies (frees their memory), 1 builds them; AMG_ERR_STATE while a batch
+   engine exists.  amg_index_width reports the bytes per column index the row
+   kernels read for matrix `which` (AMG_MAT_*) of level l: 2 or 4. */
+amg_status amg_set_compact_indices(amg_handle h, int32_t enable);
+amg_status amg_index_width(amg_handle h, int32_t l, int32_t which, int32_t* bytes);
+
 /* Kernel timing with HIP events on the handle's stream.  While enabled,
    every launch of a kernel of class kernel_class (-1: every class) on level
    `level` (-1: every level) is bracketed by a pair of events;

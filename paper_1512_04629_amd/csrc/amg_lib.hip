@@ -72,7 +72,13 @@ struct DevMat {
     int32_t* ci = nullptr;
     double* v = nullptr;
     int width = 8;
-    CsrView view() const { return CsrView{rp, ci, v, rows, rows ? (double)shape_nnz / rows : 1.0}; }
+    // 16-bit column indices for the LDS-staged kernels (null: not built)
+    uint16_t* ci16 = nullptr;
+    int32_t* cbase = nullptr;
+    int idx_rb = 0;
+    CsrView view() const {
+        return CsrView{rp, ci, v, rows, rows ? (double)shape_nnz / rows : 1.0, ci16, cbase, idx_rb};
+    }
 };
 
 struct DevLevel {
@@ -157,6 +163,7 @@ struct amg_ctx {
     amg_batch_ctx* batch = nullptr;              // the continuous-batching engine, if any
     int method = AMG_SPARSE_GALERKIN;            // which finer operator the minimal pattern uses
     bool nongalerkin = false;                    // coarse operators sparsified during setup
+    bool compact_idx = true;                     // 16-bit column indices where they fit
     int bcg_k = 0;                               // block CG vectors (FP64, K wide)
     double *bcg_r = nullptr, *bcg_p = nullptr, *bcg_q = nullptr, *bcg_z = nullptr;
     int blk_pack_k = 0;
@@ -205,6 +212,8 @@ void free_mat(amg_ctx* h, DevMat& m) {
     dfree(h, m.rp);
     dfree(h, m.ci);
     dfree(h, m.v);
+    dfree(h, m.ci16);
+    dfree(h, m.cbase);
     m = DevMat{};
 }
 
@@ -325,7 +334,7 @@ void row_op(amg_ctx* h, int kind, int level, RowOp op, const DevMat& m, const do
 void row_op(amg_ctx* h, int kind, int level, RowOp op, const DevMat& m, const float* vals, const float* g,
             const float* u, const float* dinv, float* y, float* y2) {
     ProfScope ps(h, kind, level);
-    const CsrView32 a32{m.rp, m.ci, vals, m.rows, m.view().mean_row};
+    const CsrView32 a32{m.rp, m.ci, vals, m.rows, m.view().mean_row, m.ci16, m.cbase, m.idx_rb};
     launch_row_op(op, m.width, a32, g, u, dinv, (float)h->sp.omega, y, y2, h->stream);
     check_launch();
 }
@@ -1605,6 +1614,49 @@ void setup(amg_ctx* h, int64_t n, const int32_t* row_ptr, const int32_t* col, co
     finish_setup(h);
 }
 
+// 16-bit column indices of a fixed matrix the LDS-staged kernels run on, if
+// the columns of every row block of the launch span at most 65535 (a cut of
+// 2 of the 12 bytes each entry moves)
+void drop_indices(amg_ctx* h, DevMat& m) {
+    dfree(h, m.ci16);
+    dfree(h, m.cbase);
+    m.ci16 = nullptr;
+    m.cbase = nullptr;
+    m.idx_rb = 0;
+}
+
+void compress_indices(amg_ctx* h, DevMat& m) {
+    if (!h->compact_idx || m.ci16 || m.nnz <= 0) return;
+    const int rb = stream_block_rows(m.view());
+    if (rb == 0) return;
+    const int nblk = (m.rows + rb - 1) / rb;
+    m.ci16 = dalloc_n<uint16_t>(h, m.nnz + kCsrPad);
+    m.cbase = dalloc_n<int32_t>(h, nblk);
+    m.idx_rb = rb;
+    int* wide = h->missing;
+    launch_fill_u32(1, reinterpret_cast<unsigned*>(wide), 0u, h->stream);
+    launch_compress_index(m.rows, rb, m.rp, m.ci, m.ci16, m.cbase, wide, h->stream);
+    check_launch();
+    int nwide = 0;
+    download(h, &nwide, wide, 1);
+    sync(h);
+    if (nwide > 0) drop_indices(h, m);
+}
+
+// builds or drops the 16-bit indices of every level's A, P and R (the
+// sparsified operators keep 32-bit indices)
+void set_compact_indices(amg_ctx* h, bool on) {
+    h->compact_idx = on;
+    for (auto& d : h->lv) {
+        for (DevMat* m : {&d.A, &d.P, &d.R}) {
+            if (!m->rp) continue;
+            if (on) compress_indices(h, *m);
+            else drop_indices(h, *m);
+        }
+        if (d.ah_alias) d.Ah = d.A;
+    }
+}
+
 // everything a hierarchy needs once its levels hold A, P, R, c_points and
 // the split: 1/diag, work vectors, reduction and scan buffers, the coarsest
 // inverse
@@ -1612,8 +1664,14 @@ void finish_setup(amg_ctx* h) {
     const int L = (int)h->lv.size() - 1;
     const int64_t n = h->lv[0].n;
     int partial_need = vector_launch_blocks(std::max(1, (int)n));
+    h->missing = dalloc_n<int>(h, 1);
     for (int l = 0; l <= L; ++l) {
         DevLevel& d = h->lv[l];
+        compress_indices(h, d.A);
+        if (l < L) {
+            compress_indices(h, d.P);
+            compress_indices(h, d.R);
+        }
         d.Ah = d.A;
         d.ah_alias = true;
         d.dinv = dalloc_n<double>(h, d.n);
@@ -1634,7 +1692,6 @@ void finish_setup(amg_ctx* h) {
     h->partial_cap = partial_need;
     h->partials = dalloc_n<double>(h, partial_need);
     h->scal = dalloc_n<double>(h, S_COUNT);
-    h->missing = dalloc_n<int>(h, 1);
     int nmax = 0;
     for (auto& d : h->lv) nmax = std::max(nmax, d.n);
     h->cnt = dalloc_n<int32_t>(h, nmax + 1);
@@ -2252,6 +2309,24 @@ amg_status amg_setup_device(int64_t n, int64_t nnz, const int32_t* row_ptr, cons
     if (coarsening != AMG_COARSEN_RS && coarsening != AMG_COARSEN_PMIS) return AMG_ERR_INVALID_ARG;
     return setup_abi(params, stream, alloc, free_fn, user, out,
                      [&](amg_ctx* h) { setup_device(h, n, nnz, row_ptr, col, val, coarsening, seed); });
+}
+
+amg_status amg_set_compact_indices(amg_handle h, int32_t enable) {
+    if (!h || h->lv.empty() || h->batch) return AMG_ERR_STATE;
+    return guarded(h, [&] {
+        set_compact_indices(h, enable != 0);
+        return AMG_OK;
+    });
+}
+
+amg_status amg_index_width(amg_handle h, int32_t l, int32_t which, int32_t* bytes) {
+    if (!h || h->lv.empty()) return AMG_ERR_STATE;
+    if (l < 0 || l >= (int)h->lv.size() || !bytes || which < AMG_MAT_A || which > AMG_MAT_R)
+        return AMG_ERR_INVALID_ARG;
+    const DevLevel& d = h->lv[l];
+    const DevMat& m = which == AMG_MAT_A ? d.A : which == AMG_MAT_AHAT ? d.Ah : which == AMG_MAT_P ? d.P : d.R;
+    *bytes = m.ci16 ? 2 : 4;
+    return AMG_OK;
 }
 
 amg_status amg_setup_profile_enable(int32_t enable) {

@@ -10,6 +10,7 @@
 #include "kernels.hpp"
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 
 namespace amg355 {
@@ -65,6 +66,7 @@ constexpr int kRowGridCap = AMG_ROW_GRID_CAP;   // row kernels loop over tiles b
 // Matrix entries are streamed once per launch; with AMG_NT they are loaded
 // non-temporally so that they do not evict the gathered vector from L2.
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef unsigned short v4u16 __attribute__((ext_vector_type(4)));
 typedef double v2d __attribute__((ext_vector_type(2)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
@@ -90,6 +92,13 @@ __device__ __forceinline__ int xcd_logical_block() {
 }
 
 int round_up8(int b) { return (b + kXcds - 1) / kXcds * kXcds; }
+
+// column of entry p of a row block whose 16-bit base is cb
+template <bool IDX16, class T>
+__device__ __forceinline__ int load_col(const CsrT<T>& a, int p, int cb) {
+    if constexpr (IDX16) return cb + (int)stream_ld(a.ci16 + p);
+    else return stream_ld(a.ci + p);
+}
 
 template <int W, class T>
 __device__ __forceinline__ T sub_sum(T v) {
@@ -297,7 +306,7 @@ void launch_row_w(RowOp op, const CsrT<T>& a, const T* g, const T* u, const T* d
 // park the products in LDS; then 256/RB lanes per row add the row's products.
 constexpr int kStreamCap = AMG_STREAM_CAP;   // products staged per pass (16 KB of LDS)
 
-template <class T, int RB, int OP, bool VEC4>
+template <class T, int RB, int OP, bool VEC4, bool IDX16>
 __global__ __launch_bounds__(kBlock) void stream_kernel(CsrT<T> a, const T* __restrict__ g,
                                                         const T* u, const T* __restrict__ dinv,
                                                         T omega, T* y, T* y2,
@@ -311,6 +320,7 @@ __global__ __launch_bounds__(kBlock) void stream_kernel(CsrT<T> a, const T* __re
         const int r0 = blk * RB;
         const int r1 = min(r0 + RB, a.rows);
         const int p0 = a.rp[r0], p1 = a.rp[r1];
+        const int cb = IDX16 ? a.cbase[blk] : 0;
         const int r = r0 + (int)threadIdx.x / W2;
         const bool act = r < r1;
         const int rb = act ? a.rp[r] : 0, re = act ? a.rp[r + 1] : 0;
@@ -333,7 +343,15 @@ __global__ __launch_bounds__(kBlock) void stream_kernel(CsrT<T> a, const T* __re
                 for (int k = 0; k < (kStreamCap + 3) / (4 * kBlock) + 1; ++k) {
                     const int q = base + 4 * (k * kBlock + (int)threadIdx.x);
                     if (q < c1) {
-                        const v4i cj = stream_ld(reinterpret_cast<const v4i*>(a.ci + q));
+                        int jj[4];
+                        if constexpr (IDX16) {
+                            // entries of the pack outside the block are skipped below
+                            const v4u16 cj = stream_ld(reinterpret_cast<const v4u16*>(a.ci16 + q));
+                            jj[0] = cb + cj.x; jj[1] = cb + cj.y; jj[2] = cb + cj.z; jj[3] = cb + cj.w;
+                        } else {
+                            const v4i cj = stream_ld(reinterpret_cast<const v4i*>(a.ci + q));
+                            jj[0] = cj.x; jj[1] = cj.y; jj[2] = cj.z; jj[3] = cj.w;
+                        }
                         T vv[4];
                         if constexpr (sizeof(T) == 8) {
                             const v2d v01 = stream_ld(reinterpret_cast<const v2d*>(a.v + q));
@@ -343,7 +361,6 @@ __global__ __launch_bounds__(kBlock) void stream_kernel(CsrT<T> a, const T* __re
                             const v4f v0123 = stream_ld(reinterpret_cast<const v4f*>(a.v + q));
                             vv[0] = v0123.x; vv[1] = v0123.y; vv[2] = v0123.z; vv[3] = v0123.w;
                         }
-                        const int jj[4] = {cj.x, cj.y, cj.z, cj.w};
 #pragma unroll
                         for (int e = 0; e < 4; ++e) {
                             const int p = q + e;
@@ -362,7 +379,7 @@ __global__ __launch_bounds__(kBlock) void stream_kernel(CsrT<T> a, const T* __re
                 for (int k = 0; k < kStreamCap / kBlock; ++k) {
                     const int p = c0 + k * kBlock + (int)threadIdx.x;
                     if (p < c1) {
-                        const int j = stream_ld(a.ci + p);
+                        const int j = load_col<IDX16>(a, p, cb);
                         T gj;
                         if constexpr (OP == kZeroJacobiResid) gj = omega * (dinv[j] * u[j]);
                         else gj = g[j];
@@ -419,7 +436,7 @@ __global__ __launch_bounds__(kBlock) void stream_kernel(CsrT<T> a, const T* __re
 #ifndef AMG_PIPE_E
 #define AMG_PIPE_E 2
 #endif
-template <class T, int RB, int OP>
+template <class T, int RB, int OP, bool IDX16>
 __global__ __launch_bounds__(kBlock) void stream_pipe_kernel(CsrT<T> a, const T* __restrict__ g,
                                                              const T* u, const T* __restrict__ dinv,
                                                              T omega, T* y, T* y2, DotTarget dot, int nblk) {
@@ -431,23 +448,24 @@ __global__ __launch_bounds__(kBlock) void stream_pipe_kernel(CsrT<T> a, const T*
     const int lane = threadIdx.x & (W2 - 1);
     const int rsub = (int)threadIdx.x / W2;
     double contrib = 0.0;
-    auto meta = [&](int b, int& q0, int& q1, int& rr, bool& ac, int& qb, int& qe) {
+    auto meta = [&](int b, int& q0, int& q1, int& rr, bool& ac, int& qb, int& qe, int& cbb) {
         const int r0 = b * RB;
         const int r1 = min(r0 + RB, a.rows);
         q0 = a.rp[r0];
         q1 = a.rp[r1];
+        cbb = IDX16 ? a.cbase[b] : 0;
         rr = r0 + rsub;
         ac = rr < r1;
         qb = ac ? a.rp[rr] : 0;
         qe = ac ? a.rp[rr + 1] : 0;
     };
-    auto stage = [&](int q0, int q1, int (&jj)[PE], T (&vv)[PE]) {
+    auto stage = [&](int q0, int q1, int cbb, int (&jj)[PE], T (&vv)[PE]) {
         const int c1 = min(q1, q0 + kStreamCap);
 #pragma unroll
         for (int k = 0; k < PE; ++k) {
             const int p = q0 + k * kBlock + (int)threadIdx.x;
             const bool ok = p < c1;
-            jj[k] = ok ? stream_ld(a.ci + p) : 0;
+            jj[k] = ok ? load_col<IDX16>(a, p, cbb) : 0;
             vv[k] = ok ? stream_ld(a.v + p) : T(0);
         }
     };
@@ -455,20 +473,20 @@ __global__ __launch_bounds__(kBlock) void stream_pipe_kernel(CsrT<T> a, const T*
         if constexpr (OP == kZeroJacobiResid) return omega * (dinv[j] * u[j]);
         else return g[j];
     };
-    int p0 = 0, p1 = 0, r = 0, rb = 0, re = 0;
+    int p0 = 0, p1 = 0, r = 0, rb = 0, re = 0, cb = 0;
     bool act = false;
     int jc[PE];
     T vc[PE];
     int blk = lb;
     if (blk < nblk) {
-        meta(blk, p0, p1, r, act, rb, re);
-        stage(p0, p1, jc, vc);
+        meta(blk, p0, p1, r, act, rb, re, cb);
+        stage(p0, p1, cb, jc, vc);
     }
     for (; blk < nblk; blk += gridDim.x) {
         const int nb = blk + gridDim.x;
-        int np0 = 0, np1 = 0, nr = 0, nrb = 0, nre = 0;
+        int np0 = 0, np1 = 0, nr = 0, nrb = 0, nre = 0, ncb = 0;
         bool nact = false;
-        if (nb < nblk) meta(nb, np0, np1, nr, nact, nrb, nre);
+        if (nb < nblk) meta(nb, np0, np1, nr, nact, nrb, nre, ncb);
         T ui = T(0), gi = T(0), di = T(0);
         if (act && lane == 0) {
             if constexpr (OP != kSpmv && OP != kSpmvDot && OP != kSpmvScale) ui = u[r];
@@ -486,7 +504,7 @@ __global__ __launch_bounds__(kBlock) void stream_pipe_kernel(CsrT<T> a, const T*
         int jn[PE];
         T vn[PE];
         if (nb < nblk) {
-            stage(np0, np1, jn, vn);
+            stage(np0, np1, ncb, jn, vn);
         } else {
 #pragma unroll
             for (int k = 0; k < PE; ++k) {
@@ -503,7 +521,7 @@ __global__ __launch_bounds__(kBlock) void stream_pipe_kernel(CsrT<T> a, const T*
 #pragma unroll
         for (int k = PE; k < E; ++k) {
             const int p = p0 + k * kBlock + (int)threadIdx.x;
-            if (p < c1) prod[p - p0] = stream_ld(a.v + p) * gather(stream_ld(a.ci + p));
+            if (p < c1) prod[p - p0] = stream_ld(a.v + p) * gather(load_col<IDX16>(a, p, cb));
         }
         __syncthreads();
         T s = T(0);
@@ -518,7 +536,7 @@ __global__ __launch_bounds__(kBlock) void stream_pipe_kernel(CsrT<T> a, const T*
 #pragma unroll
             for (int k = 0; k < E; ++k) {
                 const int p = c0 + k * kBlock + (int)threadIdx.x;
-                if (p < cc1) prod[p - c0] = stream_ld(a.v + p) * gather(stream_ld(a.ci + p));
+                if (p < cc1) prod[p - c0] = stream_ld(a.v + p) * gather(load_col<IDX16>(a, p, cb));
             }
             __syncthreads();
             const int lo = max(rb, c0), hi = min(re, cc1);
@@ -552,6 +570,7 @@ __global__ __launch_bounds__(kBlock) void stream_pipe_kernel(CsrT<T> a, const T*
         }
         p0 = np0;
         p1 = np1;
+        cb = ncb;
         r = nr;
         act = nact;
         rb = nrb;
@@ -565,20 +584,18 @@ __global__ __launch_bounds__(kBlock) void stream_pipe_kernel(CsrT<T> a, const T*
     if constexpr (op_has_dot<OP>()) store_block_partial(contrib, dot.partials, lb);
 }
 
-template <class T, int RB, bool VEC4>
-void launch_stream_rb(RowOp op, const CsrT<T>& a, const T* g, const T* u, const T* dinv,
-                      T omega, T* y, T* y2, DotTarget dot, hipStream_t st) {
-    const int nblk = std::max(1, (a.rows + RB - 1) / RB);
-    const int grid = round_up8(std::min(nblk, std::min(kRowGridCap, AMG_STREAM_GRID_CAP)));
+template <class T, int RB, bool VEC4, bool IDX16>
+void launch_stream_rbi(RowOp op, const CsrT<T>& a, const T* g, const T* u, const T* dinv,
+                       T omega, T* y, T* y2, DotTarget dot, int nblk, int grid, hipStream_t st) {
     switch (op) {
 #define AMG_STREAM_CASE(OPV)                                                                      \
     case OPV:                                                                                     \
         if (AMG_PIPE && !VEC4)                                                                    \
-            hipLaunchKernelGGL((stream_pipe_kernel<T, RB, OPV>), dim3(grid), dim3(kBlock), 0, st, a, g, u, \
-                               dinv, omega, y, y2, dot, nblk);                                    \
+            hipLaunchKernelGGL((stream_pipe_kernel<T, RB, OPV, IDX16>), dim3(grid), dim3(kBlock), 0, st, a, g, \
+                               u, dinv, omega, y, y2, dot, nblk);                                 \
         else                                                                                      \
-            hipLaunchKernelGGL((stream_kernel<T, RB, OPV, VEC4>), dim3(grid), dim3(kBlock), 0, st, a, g, u, \
-                               dinv, omega, y, y2, dot, nblk);                                    \
+            hipLaunchKernelGGL((stream_kernel<T, RB, OPV, VEC4, IDX16>), dim3(grid), dim3(kBlock), 0, st, a, \
+                               g, u, dinv, omega, y, y2, dot, nblk);                              \
         break;
         AMG_STREAM_CASE(kSpmv)
         AMG_STREAM_CASE(kSpmvAdd)
@@ -592,6 +609,16 @@ void launch_stream_rb(RowOp op, const CsrT<T>& a, const T* g, const T* u, const 
 #undef AMG_STREAM_CASE
         default: break;
     }
+}
+
+template <class T, int RB, bool VEC4>
+void launch_stream_rb(RowOp op, const CsrT<T>& a, const T* g, const T* u, const T* dinv,
+                      T omega, T* y, T* y2, DotTarget dot, hipStream_t st) {
+    const int nblk = std::max(1, (a.rows + RB - 1) / RB);
+    const int grid = round_up8(std::min(nblk, std::min(kRowGridCap, AMG_STREAM_GRID_CAP)));
+    if (a.ci16 && a.idx_rb == RB)
+        launch_stream_rbi<T, RB, VEC4, true>(op, a, g, u, dinv, omega, y, y2, dot, nblk, grid, st);
+    else launch_stream_rbi<T, RB, VEC4, false>(op, a, g, u, dinv, omega, y, y2, dot, nblk, grid, st);
     if (op == kResidNorm || op == kJacobiDot || op == kSpmvDot) finish_dot(dot, grid, st);
 }
 
@@ -1326,7 +1353,48 @@ void launch_dense_invert(const CsrView& a, double* inv, int* singular, hipStream
     hipLaunchKernelGGL(dense_invert_kernel, dim3(1), dim3(kBlock), 0, st, a, inv, singular);
 }
 
+// one wavefront per row block: its smallest and largest column by shuffles,
+// then the offsets
+__global__ __launch_bounds__(kBlock) void compress_index_kernel(int rows, int rb, const int32_t* __restrict__ rp,
+                                                                const int32_t* __restrict__ ci,
+                                                                uint16_t* __restrict__ ci16,
+                                                                int32_t* __restrict__ cbase, int* wide) {
+    const int nblk = (rows + rb - 1) / rb;
+    const int lane = threadIdx.x & 63;
+    const int nwaves = gridDim.x * (kBlock / 64);
+    for (int b = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); b < nblk; b += nwaves) {
+        const int r0 = b * rb, r1 = min(r0 + rb, rows);
+        const int p0 = rp[r0], p1 = rp[r1];
+        int mn = INT_MAX, mx = INT_MIN;
+        for (int p = p0 + lane; p < p1; p += 64) {
+            mn = min(mn, ci[p]);
+            mx = max(mx, ci[p]);
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            mn = min(mn, __shfl_xor(mn, o, 64));
+            mx = max(mx, __shfl_xor(mx, o, 64));
+        }
+        const bool fits = p1 == p0 || (int64_t)mx - (int64_t)mn <= 65535;
+        if (lane == 0) {
+            cbase[b] = p1 > p0 ? mn : 0;
+            if (!fits) atomicAdd(wide, 1);
+        }
+        for (int p = p0 + lane; p < p1; p += 64) ci16[p] = fits ? (uint16_t)(ci[p] - mn) : (uint16_t)0;
+    }
+}
+
 int64_t scan_scratch_ints(int n) { return (int64_t)(n + kScanTile - 1) / kScanTile + 1; }
+
+void launch_compress_index(int rows, int rb, const int32_t* rp, const int32_t* ci, uint16_t* ci16,
+                           int32_t* cbase, int* wide, hipStream_t st) {
+    const int nblk = (rows + rb - 1) / rb;
+    const int grid = std::max(1, std::min((nblk + 3) / 4, 8192));
+    hipLaunchKernelGGL(compress_index_kernel, dim3(grid), dim3(kBlock), 0, st, rows, rb, rp, ci, ci16, cbase,
+                       wide);
+}
+
+int stream_block_rows(const CsrView& a) { return use_stream_kernel(a) ? stream_rows_per_block(a.mean_row) : 0; }
 
 void launch_exclusive_scan(int n, const int32_t* cnt, int32_t* out, int32_t* scratch,
                            hipStream_t st) {

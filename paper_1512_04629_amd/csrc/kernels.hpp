@@ -15,6 +15,12 @@ struct CsrT {
     const T* v;
     int rows;
     double mean_row;   // nnz / rows, host side launch configuration only
+    // optional 16-bit form of ci read by the LDS-staged kernels: the column
+    // of an entry of row block b (rows [b idx_rb, (b + 1) idx_rb)) is
+    // cbase[b] + ci16[p]; used only by launches with idx_rb rows per block
+    const uint16_t* ci16 = nullptr;
+    const int32_t* cbase = nullptr;
+    int idx_rb = 0;
 };
 using CsrView = CsrT<double>;
 using CsrView32 = CsrT<float>;
@@ -134,6 +140,16 @@ void launch_mark_minimal_pattern(int nc, const int32_t* c_points, const int32_t*
                                  const int32_t* afine_ci, const int32_t* p_rp,
                                  const int32_t* p_ci, const int32_t* ac_rp, const int32_t* ac_ci,
                                  uint8_t* in_m, int* missing, hipStream_t st);
+// 16-bit column indices for row blocks of rb rows: cbase[b] = smallest
+// column in block b, ci16[p] = ci[p] - cbase[b]; *wide (zeroed by the
+// caller) counts the blocks whose columns span more than 65535 (then the form
+// is unusable)
+void launch_compress_index(int rows, int rb, const int32_t* rp, const int32_t* ci, uint16_t* ci16,
+                           int32_t* cbase, int* wide, hipStream_t st);
+// rows per block of the LDS-staged kernels on this matrix, 0 if row
+// operations on it run on the subgroup kernels (which read 32-bit indices)
+int stream_block_rows(const CsrView& a);
+
 // m_i = max_{k != i} |a_ik|
 void launch_row_max(int width, const CsrView& a, double* m, hipStream_t st);
 // keep flags and per-row kept counts for tolerance gamma

@@ -1,0 +1,76 @@
+"""16-bit column indices of the fixed operators (amg_set_compact_indices):
+a storage form of the same matrices, so every result is bitwise the one the
+32-bit indices give.  Bars: V-cycles (FP64, FP32) and PCG solves bit for bit
+equal with the indices on and off; the form is used where the spans fit
+(banded 3D Poisson) and refused where they do not (a random graph)."""
+import numpy as np
+import pytest
+
+from paper_1512_04629_amd import inputs as I
+
+from .test_gpu_parity import dev, host
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1512_04629_amd import amg
+    amg.load_library()
+    return amg
+
+
+def _stream_levels(h):
+    return [l for l in range(h.nlev) if h.index_width(l, "A") == 2]
+
+
+def test_compact_indices_bitwise_equal_results(lib):
+    A = I.poisson3d(64)          # levels 0 and 1 run on the LDS-staged kernels
+    b = dev(I.rhs(A.n, 4))
+    h = lib.Hierarchy(A)
+    assert 0 in _stream_levels(h) and 1 in _stream_levels(h)
+    assert h.index_width(0, "R") == 2 and h.index_width(0, "AHAT") == 2
+    h.sparsify(0.1, 2)
+    out = {}
+    for on in (True, False):
+        h.set_compact_indices(on)
+        assert (h.index_width(0, "A") == 2) == on
+        x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+        h.vcycle(b, x)
+        x32 = torch.zeros(A.n, dtype=torch.float32, device="cuda")
+        h.vcycle32(b.float(), x32)
+        xs = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+        r = h.solve(b, xs, method=1, tol=1e-10, maxit=100)
+        xm = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+        rm = h.solve(b, xm, method=1, tol=1e-10, maxit=100, precision=32)
+        out[on] = (host(x), host(x32), host(xs), r.iters, host(xm), rm.iters)
+    a, c = out[True], out[False]
+    for u, v in zip(a, c):
+        if isinstance(u, np.ndarray):
+            assert u.tobytes() == v.tobytes()
+        else:
+            assert u == v
+
+
+def test_wide_spans_keep_32bit_indices(lib):
+    A = I.random_graph_laplacian(300000, degree=6)
+    h = lib.Hierarchy(A)
+    assert h.index_width(0, "A") == 4
+    x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    h.vcycle(dev(I.rhs(A.n, 1)), x)
+    assert torch.isfinite(x).all()
+
+
+def test_toggle_refused_while_a_batch_exists(lib):
+    A = I.poisson3d(20)
+    with torch.cuda.stream(torch.cuda.Stream()):
+        h = lib.Hierarchy(A)
+        eng = h.batch(4, 64)
+        with pytest.raises(lib.AmgError):
+            h.set_compact_indices(False)
+        eng.close()
+        h.set_compact_indices(False)
+        h.close()
