@@ -63,6 +63,8 @@ typedef struct {
     int nlev;
     Level *lv;
     int hybrid;     /* 0: Sparse Galerkin, 1: Hybrid Galerkin (Section 3)   */
+    int relax;      /* 0: weighted Jacobi, 1: hybrid symmetric Gauss-Seidel */
+    int gs_block;   /* rows per block of the hybrid Gauss-Seidel sweep      */
     double omega;
     int nu_pre, nu_post;
     /* coarsest-level dense factor */
@@ -649,6 +651,7 @@ int or_setup(int n, const int *rp, const int *ci, const double *v, double theta,
     Hier *h = (Hier *)calloc(1, sizeof(Hier));
     h->lv = (Level *)calloc((size_t)max_levels, sizeof(Level));
     h->omega = omega; h->nu_pre = nu_pre; h->nu_post = nu_post;
+    h->relax = 0; h->gs_block = 1;
     Mat A0 = {n, n, (int *)rp, (int *)ci, (double *)v};
     if (mat_copy(&h->lv[0].A, &A0)) return OR_ENOMEM;
     int L = 0;
@@ -886,13 +889,64 @@ static void jacobi(const Mat *a, const double *b, double *x, double *tmp, double
     for (int i = 0; i < a->nr; ++i) x[i] = x[i] + omega * tmp[i] / diag_of(a, i);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Hybrid Gauss-Seidel (the relaxation of the paper's experiments, Section  */
+/* 5, there with one block per process): the rows are split into            */
+/* contiguous blocks of `block` rows; inside a block the sweep is           */
+/* Gauss-Seidel (a row uses the new values of the rows of its block visited */
+/* before it), across blocks it is Jacobi (old values).  Forward sweeps     */
+/* visit a block's rows in ascending order, backward sweeps in descending   */
+/* order.  Row i: x_i = (b_i - sum_{j != i} a_ij y_j) / a_ii, the terms     */
+/* subtracted in ascending column order.                                    */
+/* ------------------------------------------------------------------------ */
+static void hybrid_gs(const Mat *a, const double *b, const double *xold, double *xnew, int block,
+                      int forward) {
+    int n = a->nr;
+    for (int r0 = 0; r0 < n; r0 += block) {
+        int r1 = r0 + block < n ? r0 + block : n;
+        for (int t = 0; t < r1 - r0; ++t) {
+            int i = forward ? r0 + t : r1 - 1 - t;
+            double s = b[i], d = 0.0;
+            for (int p = a->rp[i]; p < a->rp[i + 1]; ++p) {
+                int j = a->ci[p];
+                if (j == i) { d = a->v[p]; continue; }
+                int visited = j >= r0 && j < r1 && (forward ? j < i : j > i);
+                s = s - a->v[p] * (visited ? xnew[j] : xold[j]);
+            }
+            xnew[i] = s / d;
+        }
+    }
+}
+
+/* relax: 0 = weighted Jacobi, 1 = hybrid symmetric Gauss-Seidel with blocks
+   of `block` rows (V-cycles sweep forward before the coarse correction and
+   backward after it, so the cycle stays a symmetric preconditioner) */
+int or_set_relaxation(Hier *h, int relax, int block) {
+    if ((relax != 0 && relax != 1) || block < 1) return OR_EINVAL;
+    h->relax = relax;
+    h->gs_block = block;
+    return OR_OK;
+}
+
+/* nu sweeps of the configured relaxation on level l; tmp: n_l scratch */
+static void relax(Hier *h, const Mat *a, const double *b, double *x, double *tmp, int forward, int nu) {
+    for (int s = 0; s < nu; ++s) {
+        if (h->relax == 1) {
+            memcpy(tmp, x, sizeof(double) * (size_t)a->nr);
+            hybrid_gs(a, b, tmp, x, h->gs_block, forward);
+        } else {
+            jacobi(a, b, x, tmp, h->omega);
+        }
+    }
+}
+
 static void vcycle(Hier *h, const double *b0, double *x0) {
     int L = h->nlev - 1;
     memcpy(h->b[0], b0, sizeof(double) * (size_t)h->lv[0].A.nr);
     memcpy(h->x[0], x0, sizeof(double) * (size_t)h->lv[0].A.nr);
     for (int l = 0; l < L; ++l) {
         Level *lv = &h->lv[l];
-        for (int s = 0; s < h->nu_pre; ++s) jacobi(&lv->Ah, h->b[l], h->x[l], h->r[l], h->omega);
+        relax(h, &lv->Ah, h->b[l], h->x[l], h->r[l], 1, h->nu_pre);
         residual(&lv->Ah, h->b[l], h->x[l], h->r[l]);
         spmv(&lv->R, h->r[l], h->b[l + 1]);
         memset(h->x[l + 1], 0, sizeof(double) * (size_t)h->lv[l + 1].A.nr);
@@ -902,7 +956,7 @@ static void vcycle(Hier *h, const double *b0, double *x0) {
         Level *lv = &h->lv[l];
         spmv(&lv->P, h->x[l + 1], h->r[l]);
         for (int i = 0; i < lv->A.nr; ++i) h->x[l][i] += h->r[l][i];
-        for (int s = 0; s < h->nu_post; ++s) jacobi(&lv->Ah, h->b[l], h->x[l], h->r[l], h->omega);
+        relax(h, &lv->Ah, h->b[l], h->x[l], h->r[l], 0, h->nu_post);
     }
     memcpy(x0, h->x[0], sizeof(double) * (size_t)h->lv[0].A.nr);
 }
@@ -1119,6 +1173,7 @@ int or_level_op(Hier *h, int l, int op, const double *in, const double *x, doubl
     case 4: coarse_solve(h, in, out); return OR_OK;
     case 5: spmv(&lv->A, x, out); return OR_OK;
     case 6: spmv(&lv->Ah, x, out); return OR_OK;
+    case 7: case 8: hybrid_gs(&lv->Ah, in, x, out, h->gs_block, op == 7); return OR_OK;
     }
     return OR_EINVAL;
 }

@@ -74,6 +74,7 @@ def _load():
         lib.or_sparsify.argtypes = [P, dp]
         lib.or_reintroduce.argtypes = [P, C.c_int, C.c_double, C.POINTER(C.c_int)]
         lib.or_set_method.argtypes = [P, C.c_int]
+        lib.or_set_relaxation.argtypes = [P, C.c_int, C.c_int]
         lib.or_vcycle.argtypes = [P, dp, dp]
         lib.or_level_op.argtypes = [P, C.c_int, C.c_int, dp, dp, dp]
         lib.or_solve.argtypes = [P, dp, dp, C.c_int, C.c_double, C.c_int, C.c_int, C.c_int,
@@ -206,6 +207,13 @@ class OracleAMG:
         rc = self._lib.or_set_method(self._h, int(bool(hybrid)))
         if rc != OK:
             raise ValueError(f"set_method status {rc}")
+
+    def set_relaxation(self, kind: str = "jacobi", block: int = 1) -> None:
+        """Weighted Jacobi, or hybrid symmetric Gauss-Seidel with blocks of
+        `block` rows, for later V-cycles and solves."""
+        rc = self._lib.or_set_relaxation(self._h, {"jacobi": 0, "hybrid_gs": 1}[kind], int(block))
+        if rc != OK:
+            raise ValueError(f"set_relaxation status {rc}")
 
     def reintroduce(self, s: int = 1, gamma_min: float = 0.01):
         first = C.c_int(-1)
