@@ -194,6 +194,23 @@ amg_status amg_sparsify_levels(amg_handle h, const double* gamma, int32_t count)
    since its M depends on the finer operator).  The hierarchy is not changed
    until the next sparsify. */
 enum { AMG_SPARSE_GALERKIN = 0, AMG_HYBRID_GALERKIN = 1 };
+
+/* Smoother of the V-cycle.  AMG_RELAX_JACOBI (default): weighted Jacobi with
+   omega from the setup parameters.  AMG_RELAX_HYBRID_GS: hybrid Gauss-Seidel,
+   the relaxation of the paper's experiments (Section 5, there with one block
+   per process): the rows are split into contiguous blocks of block_rows
+   rows; inside a block the sweep is Gauss-Seidel (rows visited in order use
+   the new values of their block's rows visited before them), across blocks
+   Jacobi with weight 1; row i becomes (b_i - sum_{j != i} a_ij y_j) / a_ii.
+   Pre-smoothing sweeps forward, post-smoothing backward, so the cycle stays
+   a symmetric preconditioner for CG.  One thread sweeps each block, so
+   there is one row of parallelism per block: large blocks converge better
+   (one block is textbook Gauss-Seidel) and run slower.  Hybrid Gauss-Seidel
+   serves amg_solve with precision 64 and amg_vcycle; the FP32, block and
+   batch entry points return AMG_ERR_INVALID_ARG while it is selected.
+   AMG_ERR_STATE while a batch engine exists. */
+enum { AMG_RELAX_JACOBI = 0, AMG_RELAX_HYBRID_GS = 1 };
+amg_status amg_set_relaxation(amg_handle h, int32_t relaxation, int32_t block_rows);
 amg_status amg_set_method(amg_handle h, int32_t method);
 
 /* Reintroduction (Section 6, adaptive_solve and its Example): find the
@@ -263,10 +280,14 @@ amg_status amg_vcycle_block32(amg_handle h, int32_t nrhs, const float* b, float*
      AMG_OP_INTERPOLATE  out = x + P_l in      (in has n_{l+1} entries)
      AMG_OP_COARSE_SOLVE out = Ahat_L^-1 in    (l ignored)
      AMG_OP_SPMV_A       out = A_l x           (Galerkin operator)
-     AMG_OP_SPMV_AHAT    out = Ahat_l x                                   */
+     AMG_OP_SPMV_AHAT    out = Ahat_l x
+     AMG_OP_GS_FORWARD   out = one forward hybrid Gauss-Seidel sweep on
+                         Ahat_l from x (in = b; out != x)
+     AMG_OP_GS_BACKWARD  the backward sweep                               */
 enum {
     AMG_OP_RESIDUAL = 0, AMG_OP_JACOBI = 1, AMG_OP_RESTRICT = 2, AMG_OP_INTERPOLATE = 3,
-    AMG_OP_COARSE_SOLVE = 4, AMG_OP_SPMV_A = 5, AMG_OP_SPMV_AHAT = 6
+    AMG_OP_COARSE_SOLVE = 4, AMG_OP_SPMV_A = 5, AMG_OP_SPMV_AHAT = 6, AMG_OP_GS_FORWARD = 7,
+    AMG_OP_GS_BACKWARD = 8
 };
 amg_status amg_level_op(amg_handle h, int32_t level, int32_t op, const double* in,
                         const double* x, double* out);

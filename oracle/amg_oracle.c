@@ -918,6 +918,15 @@ static void hybrid_gs(const Mat *a, const double *b, const double *xold, double 
     }
 }
 
+/* one hybrid Gauss-Seidel sweep on a plain CSR matrix (no hierarchy) */
+int or_gs_sweep(int n, const int *rp, const int *ci, const double *v, const double *b, const double *xold,
+                double *xnew, int block, int forward) {
+    if (n <= 0 || block < 1) return OR_EINVAL;
+    Mat a = {n, n, (int *)rp, (int *)ci, (double *)v};
+    hybrid_gs(&a, b, xold, xnew, block, forward);
+    return OR_OK;
+}
+
 /* relax: 0 = weighted Jacobi, 1 = hybrid symmetric Gauss-Seidel with blocks
    of `block` rows (V-cycles sweep forward before the coarse correction and
    backward after it, so the cycle stays a symmetric preconditioner) */

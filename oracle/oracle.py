@@ -75,6 +75,7 @@ def _load():
         lib.or_reintroduce.argtypes = [P, C.c_int, C.c_double, C.POINTER(C.c_int)]
         lib.or_set_method.argtypes = [P, C.c_int]
         lib.or_set_relaxation.argtypes = [P, C.c_int, C.c_int]
+        lib.or_gs_sweep.argtypes = [C.c_int, ip, ip, dp, dp, dp, dp, C.c_int, C.c_int]
         lib.or_vcycle.argtypes = [P, dp, dp]
         lib.or_level_op.argtypes = [P, C.c_int, C.c_int, dp, dp, dp]
         lib.or_solve.argtypes = [P, dp, dp, C.c_int, C.c_double, C.c_int, C.c_int, C.c_int,
@@ -108,6 +109,18 @@ class SolveResult:
     relres: float
     rho_avg: float
     hist: np.ndarray
+
+
+def gs_sweep(A, b, x, block: int, forward: bool) -> np.ndarray:
+    """One hybrid Gauss-Seidel sweep of the plain matrix A from x."""
+    lib = _load()
+    out = np.zeros(A.n, np.float64)
+    rc = lib.or_gs_sweep(int(A.n), np.ascontiguousarray(A.row_ptr, np.int32), np.ascontiguousarray(A.col, np.int32),
+                         np.ascontiguousarray(A.val, np.float64), np.ascontiguousarray(b, np.float64),
+                         np.ascontiguousarray(x, np.float64), out, int(block), int(bool(forward)))
+    if rc != OK:
+        raise ValueError(f"gs_sweep status {rc}")
+    return out
 
 
 class OracleAMG:

@@ -28,7 +28,7 @@ MAT = {"A": 0, "AHAT": 1, "P": 2, "R": 3}
 MASK = {"M": 0, "KEEP": 1}
 VEC = {"ROWMAX": 0, "DINV": 1}
 OP = {"RESIDUAL": 0, "JACOBI": 1, "RESTRICT": 2, "INTERPOLATE": 3, "COARSE_SOLVE": 4,
-      "SPMV_A": 5, "SPMV_AHAT": 6}
+      "SPMV_A": 5, "SPMV_AHAT": 6, "GS_FORWARD": 7, "GS_BACKWARD": 8}
 KERNEL = {"JACOBI": 0, "JACOBI_ZERO": 1, "RESIDUAL": 2, "RESTRICT": 3, "INTERP": 4,
           "COARSE": 5, "SPMV_DOT": 6, "VECTOR": 7, "SPARSIFY": 8}
 
@@ -36,7 +36,7 @@ KERNEL = {"JACOBI": 0, "JACOBI_ZERO": 1, "RESIDUAL": 2, "RESTRICT": 3, "INTERP":
 ABI_SYMBOLS = (
     "amg_setup_params_default", "amg_solve_params_default", "amg_setup_from_csr",
     "amg_setup_nongalerkin_from_csr", "amg_setup_device", "amg_setup_profile_enable", "amg_setup_profile_read",
-    "amg_sparsify", "amg_sparsify_levels", "amg_set_method", "amg_reintroduce", "amg_solve", "amg_vcycle",
+    "amg_sparsify", "amg_sparsify_levels", "amg_set_method", "amg_set_relaxation", "amg_reintroduce", "amg_solve", "amg_vcycle",
     "amg_vcycle32",
     "amg_solve_block", "amg_vcycle_block", "amg_vcycle_block32", "amg_batch_bytes", "amg_batch_create",
     "amg_batch_submit", "amg_batch_step", "amg_batch_poll", "amg_batch_collect", "amg_batch_slots",
@@ -121,6 +121,7 @@ def load_library():
     lib.amg_sparsify_levels.argtypes = [vp, vp, i32]
     lib.amg_reintroduce.argtypes = [vp, i32, f64, P(i32)]
     lib.amg_set_method.argtypes = [vp, i32]
+    lib.amg_set_relaxation.argtypes = [vp, i32, i32]
     lib.amg_solve.argtypes = [vp, vp, vp, P(SolveParams), P(SolveInfo), vp]
     lib.amg_vcycle.argtypes = [vp, vp, vp]
     lib.amg_vcycle32.argtypes = [vp, vp, vp]
@@ -155,7 +156,8 @@ def load_library():
     lib.amg_last_error.argtypes = [vp]
     lib.amg_last_error.restype = C.c_char_p
     for name in ("amg_setup_from_csr", "amg_setup_nongalerkin_from_csr", "amg_setup_device",
-                 "amg_setup_profile_enable", "amg_setup_profile_read", "amg_sparsify", "amg_sparsify_levels", "amg_set_method", "amg_reintroduce",
+                 "amg_setup_profile_enable", "amg_setup_profile_read", "amg_sparsify", "amg_sparsify_levels", "amg_set_method",
+                 "amg_set_relaxation", "amg_reintroduce",
                  "amg_solve", "amg_vcycle", "amg_vcycle32", "amg_solve_block", "amg_vcycle_block",
                  "amg_vcycle_block32", "amg_batch_bytes", "amg_batch_create", "amg_batch_submit",
                  "amg_batch_step", "amg_batch_poll", "amg_batch_collect", "amg_batch_slots", "amg_device_bytes",
@@ -487,6 +489,11 @@ class Hierarchy:
         out = np.zeros(self.level_info(l)["n"], np.int32)
         self._check(self._lib.amg_export_split(self._h, int(l), out.ctypes.data))
         return out
+
+    def set_relaxation(self, kind: str = "jacobi", block_rows: int = 64):
+        """Weighted Jacobi (default) or hybrid symmetric Gauss-Seidel with blocks
+        of block_rows rows for later V-cycles and FP64 solves."""
+        self._check(self._lib.amg_set_relaxation(self._h, {"jacobi": 0, "hybrid_gs": 1}[kind], int(block_rows)))
 
     def set_compact_indices(self, on: bool = True):
         """Builds (default) or drops the 16-bit column indices of A_l, P_l, R_l."""

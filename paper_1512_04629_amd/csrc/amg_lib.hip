@@ -27,6 +27,7 @@
 #include "block_kernels.hpp"
 #include "host_setup.hpp"
 #include "kernels.hpp"
+#include "relax_kernels.hpp"
 #include "setup_kernels.hpp"
 
 using namespace amg355;
@@ -164,6 +165,8 @@ struct amg_ctx {
     int method = AMG_SPARSE_GALERKIN;            // which finer operator the minimal pattern uses
     bool nongalerkin = false;                    // coarse operators sparsified during setup
     bool compact_idx = true;                     // 16-bit column indices where they fit
+    int relax = AMG_RELAX_JACOBI;                // smoother of the V-cycle
+    int gs_block = 64;                           // rows per block of hybrid Gauss-Seidel
     int bcg_k = 0;                               // block CG vectors (FP64, K wide)
     double *bcg_r = nullptr, *bcg_p = nullptr, *bcg_q = nullptr, *bcg_z = nullptr;
     int blk_pack_k = 0;
@@ -742,6 +745,60 @@ void vcycle(amg_ctx* h, const T* b0, T* x0, Guess guess0, int dot_slot) {
     }
 }
 
+// V-cycle with hybrid Gauss-Seidel relaxation (FP64): forward sweeps before
+// the coarse correction, backward sweeps after it, so the cycle is a
+// symmetric preconditioner; guess0 kPrescaled is treated as kZero.  Every
+// level runs level by level (the one-workgroup tail is for Jacobi).
+void gs_sweeps(amg_ctx* h, int l, const double* b, double*& cur, double*& alt, bool forward, int sweeps) {
+    const DevMat& a = h->lv[l].Ah;
+    for (int s = 0; s < sweeps; ++s) {
+        ProfScope ps(h, AMG_K_JACOBI, l);
+        launch_hybrid_gs(forward, a.rows, a.rp, a.ci, a.v, b, cur, alt, h->gs_block, h->stream);
+        check_launch();
+        std::swap(cur, alt);
+    }
+}
+
+void vcycle_gs(amg_ctx* h, const double* b0, double* x0, Guess guess0, int dot_slot) {
+    const int L = (int)h->lv.size() - 1;
+    if (L == 0) {
+        ProfScope ps(h, AMG_K_COARSE, 0);
+        launch_dense_matvec(h->nL, h->coarse_inv, b0, x0, h->stream);
+        check_launch();
+        if (dot_slot >= 0) launch_dot(h->lv[0].n, b0, x0, dot_to(h, dot_slot), h->stream);
+        return;
+    }
+    std::vector<double*> cur(L + 1), alt(L + 1);
+    for (int l = 0; l < L; ++l) {
+        DevLevel& d = h->lv[l];
+        const double* b = l == 0 ? b0 : d.b;
+        cur[l] = l == 0 ? x0 : d.x;
+        alt[l] = d.xt;
+        if (l > 0 || guess0 != Guess::kNonzero) launch_fill_f64(d.n, cur[l], 0.0, h->stream);
+        gs_sweeps(h, l, b, cur[l], alt[l], true, h->sp.nu_pre);
+        row_op(h, AMG_K_RESIDUAL, l, kResid, d.Ah, cur[l], b, nullptr, d.r, nullptr, -1);
+        row_op(h, AMG_K_RESTRICT, l, kSpmv, d.R, d.r, nullptr, nullptr, h->lv[l + 1].b, nullptr, -1);
+    }
+    {
+        DevLevel& c = h->lv[L];
+        ProfScope ps(h, AMG_K_COARSE, L);
+        launch_dense_matvec(h->nL, h->coarse_inv, c.b, c.x, h->stream);
+        check_launch();
+        cur[L] = c.x;
+    }
+    for (int l = L - 1; l >= 0; --l) {
+        DevLevel& d = h->lv[l];
+        const double* b = l == 0 ? b0 : d.b;
+        row_op(h, AMG_K_INTERP, l, kSpmvAdd, d.P, cur[l + 1], cur[l], nullptr, cur[l], nullptr, -1);
+        gs_sweeps(h, l, b, cur[l], alt[l], false, h->sp.nu_post);
+    }
+    if (cur[0] != x0) launch_copy(h->lv[0].n, x0, cur[0], h->stream);
+    if (dot_slot >= 0) launch_dot(h->lv[0].n, b0, x0, dot_to(h, dot_slot), h->stream);
+    check_launch();
+}
+
+bool gs_on(const amg_ctx* h) { return h->relax == AMG_RELAX_HYBRID_GS; }
+
 // FP32 copies of every operator's values, of dinv, and FP32 work vectors
 void ensure_fp32(amg_ctx* h) {
     if (h->fp32) return;
@@ -825,6 +882,10 @@ amg_status do_reintroduce(amg_ctx* h, int s, double gamma_min, int* first) {
 // kZero) and z = (double) z32.
 void precondition(amg_ctx* h, bool mixed, Guess guess, int dot_slot) {
     const int n = h->lv[0].n;
+    if (gs_on(h)) {
+        vcycle_gs(h, h->cg_r, h->cg_z, Guess::kZero, dot_slot);
+        return;
+    }
     if (!mixed) {
         vcycle<double>(h, h->cg_r, h->cg_z, guess, dot_slot);
         return;
@@ -896,7 +957,8 @@ amg_status solve(amg_ctx* h, const double* b, double* x, const amg_solve_params&
                 launch_add_widened(n, x, h->cg_z32, h->stream);
                 row_op(h, AMG_K_RESIDUAL, 0, kResidNorm, A, x, b, nullptr, r, nullptr, S_NR2);
             } else {
-                vcycle<double>(h, b, x, Guess::kNonzero, -1);
+                if (gs_on(h)) vcycle_gs(h, b, x, Guess::kNonzero, -1);
+                else vcycle<double>(h, b, x, Guess::kNonzero, -1);
                 row_op(h, AMG_K_RESIDUAL, 0, kResidNorm, A, x, b, nullptr, r, nullptr, S_NR2);
             }
             const double* sc = read_scalars(h);
@@ -2189,6 +2251,10 @@ std::string& setup_error() {
 template <class T>
 amg_status vcycle_block_abi(amg_handle h, int32_t nrhs, const T* b, T* x) {
     if (!h || h->lv.empty() || h->batch) return AMG_ERR_STATE;
+    if (gs_on(h)) {
+        h->last_error = "hybrid Gauss-Seidel relaxation runs in the FP64 single-vector cycle only";
+        return AMG_ERR_INVALID_ARG;
+    }
     const int64_t n = h->lv[0].n;
     if (!b || !x || (nrhs != 4 && nrhs != 8 && nrhs != 16) || n * nrhs > INT32_MAX ||
         (((uintptr_t)b | (uintptr_t)x) & 15) != 0) {
@@ -2415,6 +2481,10 @@ amg_status amg_solve(amg_handle h, const double* b, double* x, const amg_solve_p
         h->last_error = "invalid solve parameters";
         return AMG_ERR_INVALID_ARG;
     }
+    if (gs_on(h) && p.precision != 64) {
+        h->last_error = "hybrid Gauss-Seidel relaxation runs in the FP64 cycle only";
+        return AMG_ERR_INVALID_ARG;
+    }
     return guarded(h, [&] { return solve(h, b, x, p, info, hist); });
 }
 
@@ -2422,15 +2492,29 @@ amg_status amg_vcycle(amg_handle h, const double* b, double* x) {
     if (!h || h->lv.empty() || h->batch) return AMG_ERR_STATE;
     if (!b || !x) return AMG_ERR_INVALID_ARG;
     return guarded(h, [&] {
-        vcycle<double>(h, b, x, Guess::kNonzero, -1);
+        if (gs_on(h)) vcycle_gs(h, b, x, Guess::kNonzero, -1);
+        else vcycle<double>(h, b, x, Guess::kNonzero, -1);
         prof_collect(h);
         return AMG_OK;
     });
 }
 
+amg_status amg_set_relaxation(amg_handle h, int32_t relaxation, int32_t block_rows) {
+    if (!h || h->lv.empty() || h->batch) return AMG_ERR_STATE;
+    if ((relaxation != AMG_RELAX_JACOBI && relaxation != AMG_RELAX_HYBRID_GS) || block_rows < 1)
+        return AMG_ERR_INVALID_ARG;
+    h->relax = relaxation;
+    h->gs_block = block_rows;
+    return AMG_OK;
+}
+
 amg_status amg_vcycle32(amg_handle h, const float* b, float* x) {
     if (!h || h->lv.empty() || h->batch) return AMG_ERR_STATE;
     if (!b || !x) return AMG_ERR_INVALID_ARG;
+    if (gs_on(h)) {
+        h->last_error = "hybrid Gauss-Seidel relaxation runs in the FP64 single-vector cycle only";
+        return AMG_ERR_INVALID_ARG;
+    }
     return guarded(h, [&] {
         ensure_fp32(h);
         vcycle<float>(h, b, x, Guess::kNonzero, -1);
@@ -2442,6 +2526,10 @@ amg_status amg_vcycle32(amg_handle h, const float* b, float* x) {
 amg_status amg_solve_block(amg_handle h, int32_t nrhs, const double* b, double* x, const amg_solve_params* params,
                            amg_solve_info* info, int32_t* col_iters, double* col_relres) {
     if (!h || h->lv.empty() || h->batch) return AMG_ERR_STATE;
+    if (gs_on(h)) {
+        h->last_error = "hybrid Gauss-Seidel relaxation runs in the FP64 single-vector cycle only";
+        return AMG_ERR_INVALID_ARG;
+    }
     amg_solve_params p;
     amg_solve_params_default(&p);
     if (params) p = *params;
@@ -2539,6 +2627,15 @@ amg_status amg_level_op(amg_handle h, int32_t level, int32_t op, const double* i
                 if (!x) return AMG_ERR_INVALID_ARG;
                 row_op(h, AMG_K_RESIDUAL, level, kSpmv, v.Ah, x, nullptr, nullptr, out, nullptr, -1);
                 break;
+            case AMG_OP_GS_FORWARD:
+            case AMG_OP_GS_BACKWARD: {
+                if (!in || !x || x == out) return AMG_ERR_INVALID_ARG;
+                ProfScope ps(h, AMG_K_JACOBI, level);
+                launch_hybrid_gs(op == AMG_OP_GS_FORWARD, v.n, v.Ah.rp, v.Ah.ci, v.Ah.v, in, x, out, h->gs_block,
+                                 h->stream);
+                check_launch();
+                break;
+            }
             default:
                 return AMG_ERR_INVALID_ARG;
         }
@@ -2690,6 +2787,10 @@ amg_status amg_batch_create(amg_handle h, int32_t slots, int32_t precision, doub
     if (!out) return AMG_ERR_INVALID_ARG;
     *out = nullptr;
     if (!h || h->lv.empty() || h->batch) return AMG_ERR_STATE;
+    if (gs_on(h)) {
+        h->last_error = "hybrid Gauss-Seidel relaxation runs in the FP64 single-vector cycle only";
+        return AMG_ERR_INVALID_ARG;
+    }
     if ((slots != 4 && slots != 8 && slots != 16) || (precision != 32 && precision != 64) || !(rtol >= 0.0) ||
         maxit < 1 || (int64_t)h->lv[0].n * slots > INT32_MAX) {
         h->last_error = "invalid batch parameters (slots 4, 8 or 16; precision 32 or 64; maxit >= 1)";

@@ -1,0 +1,137 @@
+"""Hybrid symmetric Gauss-Seidel relaxation (Section 5's smoother) through the
+C ABI against the oracle with the same block partition.  Bars: single sweeps
+on Galerkin operators bit for bit (both sides sum each row in ascending
+column order in one thread); on sparsified operators, whose lumped diagonal
+agrees to 1e-13 only, normwise 1e-12; V-cycles normwise 1e-12; solves with
+equal iteration counts and the solution within 1e-10; the FP32, block and
+batch paths refuse it."""
+import numpy as np
+import pytest
+
+from paper_1512_04629_amd import inputs as I
+
+from .test_gpu_parity import PROBLEMS, _assert_solve_parity, dev, host
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1512_04629_amd import amg
+    amg.load_library()
+    return amg
+
+
+def pair(A, block):
+    from oracle import oracle as O
+    from paper_1512_04629_amd import amg
+    g, o = amg.Hierarchy(A), O.OracleAMG(A)
+    g.set_relaxation("hybrid_gs", block)
+    o.set_relaxation("hybrid_gs", block)
+    return g, o
+
+
+@pytest.mark.parametrize("name", sorted(PROBLEMS))
+@pytest.mark.parametrize("block", [1, 7, 64, 100000])
+def test_sweeps_bitwise(lib, name, block):
+    A = PROBLEMS[name]()
+    g, o = pair(A, block)
+    rng = np.random.default_rng(5)
+    levels = sorted({0, min(2, o.nlev - 1)})
+
+    def sweeps(exact):
+        for l in levels:
+            n = o.sizes(l)["n"]
+            b, x = rng.standard_normal(n), rng.standard_normal(n)
+            for op, code in (("GS_FORWARD", 7), ("GS_BACKWARD", 8)):
+                out = torch.zeros(n, dtype=torch.float64, device="cuda")
+                g.level_op(l, op, dev(b), dev(x), out)
+                ref = o.level_op(l, code, b, x, n)
+                if exact or l == 0:
+                    assert host(out).tobytes() == ref.tobytes(), (l, op)
+                else:
+                    assert np.linalg.norm(host(out) - ref) <= 1e-12 * np.linalg.norm(ref), (l, op)
+
+    sweeps(True)
+    gam = [0.0, 0.0] + [0.1] * (o.nlev - 2)
+    g.sparsify_levels(gam)
+    o.sparsify(gam)
+    sweeps(False)
+
+
+@pytest.mark.parametrize("name", ["poisson3d_20", "aniso2d_48"])
+def test_vcycle_parity(lib, name):
+    A = PROBLEMS[name]()
+    g, o = pair(A, 32)
+    b = I.rhs(A.n, 3)
+    x0 = np.random.default_rng(2).standard_normal(A.n)
+    xd = dev(x0)
+    g.vcycle(dev(b), xd)
+    ref = o.vcycle(b, x0)
+    assert np.linalg.norm(host(xd) - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("method", [0, 1])
+def test_solve_parity(lib, method):
+    A = I.poisson3d(24)
+    b = I.rhs(A.n, 7)
+    g, o = pair(A, 48)
+    xd = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    kw = dict(method=method, tol=1e-10, maxit=300)
+    rg = g.solve(dev(b), xd, **kw)
+    xo, ro = o.solve(b, **kw)
+    assert ro.converged
+    _assert_solve_parity(host(xd), rg, xo, ro)
+
+
+def test_adaptive_solve_parity(lib):
+    A = I.aniso2d(64)
+    b = I.rhs(A.n, 8)
+    g, o = pair(A, 128)
+    gam = [0.0, 0.0] + [1.0] * (o.nlev - 2)
+    g.sparsify_levels(gam)
+    o.sparsify(gam)
+    kw = dict(method=1, tol=1e-10, maxit=300, adaptive=True, k=2, s=1, rho_max=0.0)
+    xd = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    rg = g.solve(dev(b), xd, **kw)
+    xo, ro = o.solve(b, **kw)
+    assert ro.reintroductions >= 1
+    _assert_solve_parity(host(xd), rg, xo, ro)
+
+
+def test_other_paths_refuse_gauss_seidel(lib):
+    A = I.poisson3d(16)
+    g = lib.Hierarchy(A)
+    g.set_relaxation("hybrid_gs", 16)
+    b = dev(I.rhs(A.n, 1))
+    x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    with pytest.raises(lib.AmgError):
+        g.solve(b, x, precision=32)
+    with pytest.raises(lib.AmgError):
+        g.vcycle32(b.float(), x.float())
+    with pytest.raises(lib.AmgError):
+        g.solve_block(torch.zeros((A.n, 4), dtype=torch.float64, device="cuda"),
+                      torch.zeros((A.n, 4), dtype=torch.float64, device="cuda"), raise_on_error=True)
+    with pytest.raises(lib.AmgError):
+        g.set_relaxation("hybrid_gs", 0)
+    g.set_relaxation("jacobi")
+    r = g.solve(b, x, precision=32, tol=1e-8)
+    assert r.converged
+
+
+def test_full_size_sweep_bitwise(lib):
+    """128^3 7-point Poisson (2,097,152 rows), blocks of 64 rows: the device
+    sweep equals the oracle's plain-matrix sweep bit for bit."""
+    from oracle import oracle as O
+    A = I.poisson3d(128)
+    g = lib.Hierarchy(A)
+    g.set_relaxation("hybrid_gs", 64)
+    rng = np.random.default_rng(9)
+    b, x = rng.standard_normal(A.n), rng.standard_normal(A.n)
+    for op, fwd in (("GS_FORWARD", True), ("GS_BACKWARD", False)):
+        out = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+        g.level_op(0, op, dev(b), dev(x), out)
+        assert host(out).tobytes() == O.gs_sweep(A, b, x, 64, fwd).tobytes(), op
