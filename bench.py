@@ -27,6 +27,8 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1512_04629_amd", "csrc", "kernels.hip")
+BLOCK_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters_fv3d.json")
+BLOCK_KERNEL_SRC = os.path.join(ROOT, "paper_1512_04629_amd", "csrc", "block_kernels.hip")
 
 
 def log(*a):
@@ -69,18 +71,18 @@ def launch_bytes(h, kernel: str, level: int) -> int:
     return 0
 
 
-def kernel_source_sha() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+def kernel_source_sha(src: str = KERNEL_SRC) -> str:
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
 
 
-def traffic_for(kernel: str, level: int):
+def traffic_for(kernel: str, level: int, path: str = TRAFFIC_FILE, src: str = KERNEL_SRC):
     """HBM bytes per launch from committed rocprofv3 counter runs, or None if
     there are none for this kernel or the kernel source changed since."""
     try:
-        data = json.load(open(TRAFFIC_FILE))
+        data = json.load(open(path))
     except (OSError, ValueError):
         return None
-    if data.get("kernel_source_sha") != kernel_source_sha():
+    if data.get("kernel_source_sha") != kernel_source_sha(src):
         return None
     ent = data.get("kernels", {}).get(f"{kernel}@{level}")
     if not ent:
@@ -611,14 +613,15 @@ def bench_fv3d(args):
     reps = max(1, min(args.steps, 3))
     others = {}
     sols = {}
-    for label, prec, method in (("fp64_block_pcg", 64, amg.PCG), ("fp32_block_ir", 32, amg.STATIONARY),
-                                ("fp64_block_ir", 64, amg.STATIONARY)):
+    for label, prec, method in (() if args.no_compare else
+                                (("fp64_block_pcg", 64, amg.PCG), ("fp32_block_ir", 32, amg.STATIONARY),
+                                 ("fp64_block_ir", 64, amg.STATIONARY))):
         ms, r = timed(lambda: step(prec, method), reps)
         sols[label] = X.cpu().numpy()
         others[label] = dict(ms_for_16=round(ms, 3), iters=r.iters, relres=r.relres)
         log(f"[bench] {label}: {ms:.2f} ms, {r.iters} iters")
     xs = torch.zeros(A.n, dtype=torch.float64, device="cuda")
-    for prec in (64, 32):
+    for prec in (() if args.no_compare else (64, 32)):
         def sixteen():
             its = []
             for c in range(K):
@@ -647,15 +650,18 @@ def bench_fv3d(args):
         "compare": others,
         "fp32_vs_fp64_block_pcg_max_rel_diff": float(max(
             np.linalg.norm(Xh[:, c] - sols["fp64_block_pcg"][:, c]) / np.linalg.norm(sols["fp64_block_pcg"][:, c])
-            for c in range(K))),
-        "speedup_vs_16_fp64_single_pcg": round(others["fp64_single_pcg_x16"]["ms_for_16"] / ms_per_step, 4),
-        "speedup_vs_fp64_block_pcg": round(others["fp64_block_pcg"]["ms_for_16"] / ms_per_step, 4),
+            for c in range(K))) if sols else None,
+        "speedup_vs_16_fp64_single_pcg": round(others["fp64_single_pcg_x16"]["ms_for_16"] / ms_per_step, 4)
+        if others else None,
+        "speedup_vs_fp64_block_pcg": round(others["fp64_block_pcg"]["ms_for_16"] / ms_per_step, 4)
+        if others else None,
         "setup_s": round(setup_s, 3),
         "roofline": {
             "bound": "hbm", "kernel": f"{dom_kernel} level {dom_level} (16-column block)",
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "bytes_per_launch": nbytes,
-            "us_per_launch": round(per_launch_s * 1e6, 3), "launches": cnt,
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic_for(dom_kernel, dom_level, BLOCK_TRAFFIC_FILE, BLOCK_KERNEL_SRC),
+            "bytes_per_launch": nbytes, "us_per_launch": round(per_launch_s * 1e6, 3), "launches": cnt,
         },
     }
     if not args.no_cpu_baseline:
