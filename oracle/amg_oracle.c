@@ -64,6 +64,8 @@ typedef struct {
     Level *lv;
     int hybrid;     /* 0: Sparse Galerkin, 1: Hybrid Galerkin (Section 3)   */
     int relax;      /* 0: weighted Jacobi, 1: hybrid symmetric Gauss-Seidel */
+    int lumping;    /* 0: diagonal (Algorithm 3b), 1: strong neighbours      */
+    double theta;   /* strength threshold of the setup                      */
     int gs_block;   /* rows per block of the hybrid Gauss-Seidel sweep      */
     double omega;
     int nu_pre, nu_post;
@@ -652,6 +654,7 @@ int or_setup(int n, const int *rp, const int *ci, const double *v, double theta,
     h->lv = (Level *)calloc((size_t)max_levels, sizeof(Level));
     h->omega = omega; h->nu_pre = nu_pre; h->nu_post = nu_post;
     h->relax = 0; h->gs_block = 1;
+    h->lumping = 0; h->theta = theta;
     Mat A0 = {n, n, (int *)rp, (int *)ci, (double *)v};
     if (mat_copy(&h->lv[0].A, &A0)) return OR_ENOMEM;
     int L = 0;
@@ -757,6 +760,96 @@ static void row_max(const Mat *a, double *m) {
     }
 }
 
+/* ------------------------------------------------------------------------ */
+/* Strong-neighbour lumping (Algorithm 3, second loop: the sparsification   */
+/* of the method of non-Galerkin coarse grids that Section 2.1 starts from; */
+/* Algorithm 3b replaces it by diagonal lumping).  Readings: S is the       */
+/* classical strength of the operator being sparsified (setup theta), with  */
+/* |S_jm| = |a_jm| for its strong entries; every kept entry starts at its   */
+/* value in A (order-free, where the printed loop would overwrite shares    */
+/* already added); a dropped (i,j) is shared among                          */
+/* W = {m : S_jm strong, (i,m) kept} in proportion |a_jm| / sum_W |a_jk|     */
+/* (the sum in ascending k): each share c is added to (i,m) and (m,i) and   */
+/* subtracted from (m,m), or added once to (i,i) when m = i; with W empty    */
+/* the dropped entry goes to the diagonal, as in Algorithm 3b.  Dropped      */
+/* entries are visited in row-major order, so every entry adds its shares in */
+/* ascending order of the dropped entry they come from.  ah: the kept        */
+/* pattern holding the values of a.                                         */
+/* ------------------------------------------------------------------------ */
+static int strong_lump(const Mat *a, const unsigned char *keep, double theta, Mat *ah) {
+    int n = a->nr;
+    double *thr = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    if (!thr) return OR_ENOMEM;
+    for (int j = 0; j < n; ++j) {
+        double big = 0.0;
+        for (int p = a->rp[j]; p < a->rp[j + 1]; ++p)
+            if (a->ci[p] != j && -a->v[p] > big) big = -a->v[p];
+        thr[j] = big > 0.0 ? theta * big : -1.0;   /* -1: no strong entry */
+    }
+#define STRONG(j, r) (a->ci[r] != (j) && thr[j] > 0.0 && -a->v[r] >= thr[j])
+#define KEPT(i, m) (find_pos(a, (i), (m)) >= 0 && keep[find_pos(a, (i), (m))])
+    for (int i = 0; i < n; ++i)
+        for (int p = a->rp[i]; p < a->rp[i + 1]; ++p) {
+            int j = a->ci[p];
+            if (j == i || keep[p]) continue;
+            double aij = a->v[p], den = 0.0;
+            int cnt = 0;
+            for (int r = a->rp[j]; r < a->rp[j + 1]; ++r)
+                if (STRONG(j, r) && KEPT(i, a->ci[r])) { den = den + fabs(a->v[r]); ++cnt; }
+            if (cnt == 0) {
+                ah->v[find_pos(ah, i, i)] += aij;
+                continue;
+            }
+            for (int r = a->rp[j]; r < a->rp[j + 1]; ++r) {
+                if (!(STRONG(j, r) && KEPT(i, a->ci[r]))) continue;
+                int m = a->ci[r];
+                double c = (fabs(a->v[r]) / den) * aij;
+                if (m == i) {
+                    ah->v[find_pos(ah, i, i)] += c;
+                } else {
+                    ah->v[find_pos(ah, i, m)] += c;
+                    ah->v[find_pos(ah, m, i)] += c;
+                    ah->v[find_pos(ah, m, m)] -= c;
+                }
+            }
+        }
+#undef STRONG
+#undef KEPT
+    free(thr);
+    return OR_OK;
+}
+
+/* lumping of later sparsify calls: 0 = diagonal (Algorithm 3b), 1 = strong
+   neighbours (Algorithm 3, second loop) */
+int or_set_lumping(Hier *h, int mode) {
+    if (mode != 0 && mode != 1) return OR_EINVAL;
+    h->lumping = mode;
+    return OR_OK;
+}
+
+/* strong-neighbour lumping of a plain CSR matrix with given keep flags:
+   out receives the values of the kept pattern (row by row, kept entries in
+   column order) */
+int or_strong_lump_csr(int n, const int *rp, const int *ci, const double *v, const unsigned char *keep,
+                       double theta, double *out) {
+    Mat a = {n, n, (int *)rp, (int *)ci, (double *)v};
+    long kept = 0;
+    for (long p = 0; p < rp[n]; ++p) kept += keep[p] != 0;
+    Mat ah;
+    if (mat_alloc(&ah, n, n, kept)) return OR_ENOMEM;
+    long q = 0;
+    for (int i = 0; i < n; ++i) {
+        ah.rp[i] = (int)q;
+        for (int p = rp[i]; p < rp[i + 1]; ++p)
+            if (keep[p]) { ah.ci[q] = ci[p]; ah.v[q] = v[p]; ++q; }
+    }
+    ah.rp[n] = (int)q;
+    int rc = strong_lump(&a, keep, theta, &ah);
+    if (rc == OR_OK) memcpy(out, ah.v, sizeof(double) * (size_t)kept);
+    mat_free(&ah);
+    return rc;
+}
+
 static int sparsify_level(Hier *h, int l, double gamma) {
     Level *lv = &h->lv[l];
     Mat *a = &lv->A;
@@ -794,9 +887,13 @@ static int sparsify_level(Hier *h, int l, double gamma) {
             nh.v[q] = a->v[p];
             ++q;
         }
-        if (dpos >= 0) nh.v[dpos] = d;
+        if (dpos >= 0 && h->lumping == 0) nh.v[dpos] = d;
     }
     nh.rp[n] = (int)q;
+    if (h->lumping == 1) {
+        int rc = strong_lump(a, lv->keep, h->theta, &nh);
+        if (rc) return rc;
+    }
     mat_free(&lv->Ah);
     lv->Ah = nh;
     lv->gamma = gamma;

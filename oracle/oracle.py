@@ -75,6 +75,8 @@ def _load():
         lib.or_reintroduce.argtypes = [P, C.c_int, C.c_double, C.POINTER(C.c_int)]
         lib.or_set_method.argtypes = [P, C.c_int]
         lib.or_set_relaxation.argtypes = [P, C.c_int, C.c_int]
+        lib.or_set_lumping.argtypes = [P, C.c_int]
+        lib.or_strong_lump_csr.argtypes = [C.c_int, ip, ip, dp, up, C.c_double, dp]
         lib.or_gs_sweep.argtypes = [C.c_int, ip, ip, dp, dp, dp, dp, C.c_int, C.c_int]
         lib.or_vcycle.argtypes = [P, dp, dp]
         lib.or_level_op.argtypes = [P, C.c_int, C.c_int, dp, dp, dp]
@@ -109,6 +111,20 @@ class SolveResult:
     relres: float
     rho_avg: float
     hist: np.ndarray
+
+
+def strong_lump(A, keep, theta: float = 0.25) -> np.ndarray:
+    """Values of the kept pattern of the plain matrix A after strong-neighbour
+    lumping of the entries whose keep flag is 0."""
+    lib = _load()
+    keep = np.ascontiguousarray(keep, np.uint8)
+    out = np.zeros(max(int(keep.sum()), 1), np.float64)
+    rc = lib.or_strong_lump_csr(int(A.n), np.ascontiguousarray(A.row_ptr, np.int32),
+                                np.ascontiguousarray(A.col, np.int32), np.ascontiguousarray(A.val, np.float64),
+                                keep, float(theta), out)
+    if rc != OK:
+        raise ValueError(f"strong_lump status {rc}")
+    return out[:int(keep.sum())]
 
 
 def gs_sweep(A, b, x, block: int, forward: bool) -> np.ndarray:
@@ -227,6 +243,15 @@ class OracleAMG:
         rc = self._lib.or_set_relaxation(self._h, {"jacobi": 0, "hybrid_gs": 1}[kind], int(block))
         if rc != OK:
             raise ValueError(f"set_relaxation status {rc}")
+
+    def set_lumping(self, mode: str = "diagonal") -> None:
+        """Where later sparsify calls put dropped entries: "diagonal"
+        (Algorithm 3b) or "strong" (strong neighbours, Algorithm 3)."""
+        if mode not in ("diagonal", "strong"):
+            raise ValueError(f"unknown lumping {mode!r}")
+        rc = self._lib.or_set_lumping(self._h, {"diagonal": 0, "strong": 1}[mode])
+        if rc != OK:
+            raise ValueError(f"set_lumping status {rc}")
 
     def reintroduce(self, s: int = 1, gamma_min: float = 0.01):
         first = C.c_int(-1)
