@@ -195,6 +195,24 @@ amg_status amg_sparsify_levels(amg_handle h, const double* gamma, int32_t count)
    until the next sparsify. */
 enum { AMG_SPARSE_GALERKIN = 0, AMG_HYBRID_GALERKIN = 1 };
 
+/* Where amg_sparsify, amg_sparsify_levels and amg_reintroduce put the
+   entries they drop (from the next such call on; existing sparsified
+   operators are not redone).  AMG_LUMP_DIAGONAL (default): diagonal lumping,
+   Algorithm 3b (Section 3.1).  AMG_LUMP_STRONG: the second loop of
+   Algorithm 3 (the method of non-Galerkin coarse grids): a dropped entry
+   (i,j) is shared among W = {m : S_jm strong, (i,m) kept}, S the classical
+   strength of the operator being sparsified (setup theta), in proportion
+   |a_jm|; each share c is added to (i,m) and (m,i) and subtracted from
+   (m,m) (added once to (i,i) when m = i); with W empty the entry goes to the
+   diagonal.  Kept entries start at their Galerkin values and every entry
+   adds its shares in ascending order of the dropped entry they come from,
+   so the result is symmetric bit for bit.  Row sums are kept; unlike
+   diagonal lumping, positive definiteness is not guaranteed.  The
+   non-Galerkin setup always lumps to the diagonal.  AMG_ERR_STATE while a
+   batch engine exists. */
+enum { AMG_LUMP_DIAGONAL = 0, AMG_LUMP_STRONG = 1 };
+amg_status amg_set_lumping(amg_handle h, int32_t lumping);
+
 /* Smoother of the V-cycle.  AMG_RELAX_JACOBI (default): weighted Jacobi with
    omega from the setup parameters.  AMG_RELAX_HYBRID_GS: hybrid Gauss-Seidel,
    the relaxation of the paper's experiments (Section 5, there with one block

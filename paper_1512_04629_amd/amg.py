@@ -36,7 +36,7 @@ KERNEL = {"JACOBI": 0, "JACOBI_ZERO": 1, "RESIDUAL": 2, "RESTRICT": 3, "INTERP":
 ABI_SYMBOLS = (
     "amg_setup_params_default", "amg_solve_params_default", "amg_setup_from_csr",
     "amg_setup_nongalerkin_from_csr", "amg_setup_device", "amg_setup_profile_enable", "amg_setup_profile_read",
-    "amg_sparsify", "amg_sparsify_levels", "amg_set_method", "amg_set_relaxation", "amg_reintroduce", "amg_solve", "amg_vcycle",
+    "amg_sparsify", "amg_sparsify_levels", "amg_set_method", "amg_set_relaxation", "amg_set_lumping", "amg_reintroduce", "amg_solve", "amg_vcycle",
     "amg_vcycle32",
     "amg_solve_block", "amg_vcycle_block", "amg_vcycle_block32", "amg_batch_bytes", "amg_batch_create",
     "amg_batch_submit", "amg_batch_step", "amg_batch_poll", "amg_batch_collect", "amg_batch_slots",
@@ -122,6 +122,7 @@ def load_library():
     lib.amg_reintroduce.argtypes = [vp, i32, f64, P(i32)]
     lib.amg_set_method.argtypes = [vp, i32]
     lib.amg_set_relaxation.argtypes = [vp, i32, i32]
+    lib.amg_set_lumping.argtypes = [vp, i32]
     lib.amg_solve.argtypes = [vp, vp, vp, P(SolveParams), P(SolveInfo), vp]
     lib.amg_vcycle.argtypes = [vp, vp, vp]
     lib.amg_vcycle32.argtypes = [vp, vp, vp]
@@ -157,7 +158,7 @@ def load_library():
     lib.amg_last_error.restype = C.c_char_p
     for name in ("amg_setup_from_csr", "amg_setup_nongalerkin_from_csr", "amg_setup_device",
                  "amg_setup_profile_enable", "amg_setup_profile_read", "amg_sparsify", "amg_sparsify_levels", "amg_set_method",
-                 "amg_set_relaxation", "amg_reintroduce",
+                 "amg_set_relaxation", "amg_set_lumping", "amg_reintroduce",
                  "amg_solve", "amg_vcycle", "amg_vcycle32", "amg_solve_block", "amg_vcycle_block",
                  "amg_vcycle_block32", "amg_batch_bytes", "amg_batch_create", "amg_batch_submit",
                  "amg_batch_step", "amg_batch_poll", "amg_batch_collect", "amg_batch_slots", "amg_device_bytes",
@@ -489,6 +490,13 @@ class Hierarchy:
         out = np.zeros(self.level_info(l)["n"], np.int32)
         self._check(self._lib.amg_export_split(self._h, int(l), out.ctypes.data))
         return out
+
+    def set_lumping(self, mode: str = "diagonal"):
+        """Where later sparsify / reintroduce calls put dropped entries:
+        "diagonal" (Algorithm 3b) or "strong" (strong neighbours, Algorithm 3)."""
+        if mode not in ("diagonal", "strong"):
+            raise ValueError(f"unknown lumping {mode!r}")
+        self._check(self._lib.amg_set_lumping(self._h, {"diagonal": 0, "strong": 1}[mode]))
 
     def set_relaxation(self, kind: str = "jacobi", block_rows: int = 64):
         """Weighted Jacobi (default) or hybrid symmetric Gauss-Seidel with blocks

@@ -51,7 +51,7 @@ def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     objs = []
     cmds = []
-    for src in ("kernels.hip", "block_kernels.hip", "setup_kernels.hip", "relax_kernels.hip", "amg_lib.hip"):
+    for src in ("kernels.hip", "block_kernels.hip", "setup_kernels.hip", "relax_kernels.hip", "lump_kernels.hip", "amg_lib.hip"):
         obj = os.path.join(BUILD, src.replace(".hip", ".o"))
         cmds.append([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)

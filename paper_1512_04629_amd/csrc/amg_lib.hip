@@ -27,6 +27,7 @@
 #include "block_kernels.hpp"
 #include "host_setup.hpp"
 #include "kernels.hpp"
+#include "lump_kernels.hpp"
 #include "relax_kernels.hpp"
 #include "setup_kernels.hpp"
 
@@ -95,6 +96,8 @@ struct DevLevel {
     uint8_t* in_m = nullptr;      // minimal pattern flags (l >= 1)
     uint8_t* keep = nullptr;      // keep flags of the last sparsification
     double* rowmax = nullptr;     // m_i of A
+    double* lump_thr = nullptr;   // strong-neighbour lumping: strength thresholds of A's rows
+    double* lump_den = nullptr;   //   and share denominators per dropped entry of A
     bool have_m = false;
     bool m_hybrid = false;        // in_m currently holds the Hybrid Galerkin pattern
     bool keep_valid = false;
@@ -166,6 +169,7 @@ struct amg_ctx {
     bool nongalerkin = false;                    // coarse operators sparsified during setup
     bool compact_idx = true;                     // 16-bit column indices where they fit
     int relax = AMG_RELAX_JACOBI;                // smoother of the V-cycle
+    int lumping = AMG_LUMP_DIAGONAL;             // where sparsify puts dropped entries
     int gs_block = 64;                           // rows per block of hybrid Gauss-Seidel
     int bcg_k = 0;                               // block CG vectors (FP64, K wide)
     double *bcg_r = nullptr, *bcg_p = nullptr, *bcg_q = nullptr, *bcg_z = nullptr;
@@ -512,6 +516,10 @@ void sparsify_levels(amg_ctx* h, const std::vector<std::pair<int, double>>& todo
             c.Ahs.width = c.A.width;
         }
         if (h->fp32 && !c.Ahs32) c.Ahs32 = dalloc_n<float>(h, c.A.nnz + kCsrPad);
+        if (h->lumping == AMG_LUMP_STRONG && !c.lump_thr) {
+            c.lump_thr = dalloc_n<double>(h, c.n);
+            c.lump_den = dalloc_n<double>(h, c.A.nnz);
+        }
     }
     bool coarse_changed = false;
     for (auto& t : todo) {
@@ -534,8 +542,20 @@ void sparsify_levels(amg_ctx* h, const std::vector<std::pair<int, double>>& todo
             mark_minimal_pattern(h, l, h->method == AMG_HYBRID_GALERKIN);
             launch_keep_count(c.A.width, c.A.view(), c.in_m, c.rowmax, gamma, c.keep, h->cnt, h->stream);
             launch_exclusive_scan(c.n, h->cnt, c.Ahs.rp, h->scan_scratch, h->stream);
-            launch_compact_lump(c.A.width, c.A.view(), c.keep, c.Ahs.rp, c.Ahs.ci, c.Ahs.v, c.dinv,
-                                h->fp32 ? c.Ahs32 : nullptr, h->fp32 ? c.dinv32 : nullptr, h->stream);
+            if (h->lumping == AMG_LUMP_STRONG) {
+                // Algorithm 3's second loop: dropped entries shared among strong neighbours
+                const DevMat& a = c.A;
+                launch_compact_copy(c.n, a.rp, a.ci, a.v, c.keep, c.Ahs.rp, c.Ahs.ci, c.Ahs.v, h->stream);
+                launch_lump_threshold(c.n, a.rp, a.ci, a.v, h->sp.theta, c.lump_thr, h->stream);
+                launch_lump_den(c.n, a.rp, a.ci, a.v, c.keep, c.lump_thr, c.lump_den, h->stream);
+                launch_strong_lump(c.n, a.rp, a.ci, a.v, c.keep, c.lump_thr, c.lump_den, c.Ahs.rp, c.Ahs.ci,
+                                   c.Ahs.v, h->stream);
+                launch_inverse_diagonal(c.Ahs.view(), c.dinv, h->fp32 ? c.dinv32 : nullptr, h->stream);
+                if (h->fp32) launch_narrow(c.A.nnz, c.Ahs32, c.Ahs.v, h->stream);   // capacity; past nnz unused
+            } else {
+                launch_compact_lump(c.A.width, c.A.view(), c.keep, c.Ahs.rp, c.Ahs.ci, c.Ahs.v, c.dinv,
+                                    h->fp32 ? c.Ahs32 : nullptr, h->fp32 ? c.dinv32 : nullptr, h->stream);
+            }
             c.Ahs.nnz_known = false;
             c.Ah = c.Ahs;
             c.ah_alias = false;
@@ -2192,6 +2212,8 @@ void destroy(amg_ctx* h) {
         dfree(h, d.in_m);
         dfree(h, d.keep);
         dfree(h, d.rowmax);
+        dfree(h, d.lump_thr);
+        dfree(h, d.lump_den);
         dfree(h, d.b);
         dfree(h, d.x);
         dfree(h, d.xt);
@@ -2497,6 +2519,13 @@ amg_status amg_vcycle(amg_handle h, const double* b, double* x) {
         prof_collect(h);
         return AMG_OK;
     });
+}
+
+amg_status amg_set_lumping(amg_handle h, int32_t lumping) {
+    if (!h || h->lv.empty() || h->batch) return AMG_ERR_STATE;
+    if (lumping != AMG_LUMP_DIAGONAL && lumping != AMG_LUMP_STRONG) return AMG_ERR_INVALID_ARG;
+    h->lumping = lumping;
+    return AMG_OK;
 }
 
 amg_status amg_set_relaxation(amg_handle h, int32_t relaxation, int32_t block_rows) {
