@@ -1,6 +1,7 @@
-// Strong-neighbour lumping kernels: one thread per row, every sum and share
-// in the order the definition fixes (ascending columns; shares of a target
-// in ascending order of their source entry), contraction off.
+// Strong-neighbour lumping kernels: every sum and share in the order the
+// definition fixes (ascending columns; shares of a target in ascending order
+// of their source entry), contraction off.  The threshold and the copy run
+// one thread per row, the denominators and the shares one wave per row.
 #include "lump_kernels.hpp"
 
 #include <algorithm>
@@ -13,8 +14,10 @@ namespace amg355 {
 namespace {
 
 constexpr int kLB = 256;
+constexpr int kWaves = kLB / 64;
 
 int grid_of(int n) { return std::max(1, std::min((n + kLB - 1) / kLB, 16384)); }
+int wave_grid_of(int n) { return std::max(1, std::min((n + kWaves - 1) / kWaves, 65536)); }
 
 #define ROW_LOOP(i, n) for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += gridDim.x * blockDim.x)
 
@@ -30,11 +33,6 @@ __device__ inline int find_in_row(const int32_t* ci, int b, int e, int col) {
 
 __device__ inline bool strong_at(const int32_t* ci, const double* v, const double* thr, int j, int r) {
     return ci[r] != j && thr[j] > 0.0 && -v[r] >= thr[j];
-}
-
-__device__ inline bool kept_at(const int32_t* rp, const int32_t* ci, const uint8_t* keep, int i, int m) {
-    const int q = find_in_row(ci, rp[i], rp[i + 1], m);
-    return q >= 0 && keep[q];
 }
 
 __global__ void compact_copy_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
@@ -62,62 +60,113 @@ __global__ void lump_threshold_kernel(int n, const int32_t* __restrict__ rp, con
     }
 }
 
-__global__ void lump_den_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                                const double* __restrict__ v, const uint8_t* __restrict__ keep,
-                                const double* __restrict__ thr, double* __restrict__ den) {
-    ROW_LOOP(i, n) {
-        for (int p = rp[i]; p < rp[i + 1]; ++p) {
+// one wave per row i (kWaves per workgroup), lanes over the row's entries
+#define WAVE_ROW_LOOP(i, n)                                                                         \
+    for (int i = blockIdx.x * kWaves + (int)(threadIdx.x >> 6); i < (n); i += gridDim.x * kWaves)
+
+__global__ void __launch_bounds__(kLB) lump_den_kernel(int n, const int32_t* __restrict__ rp,
+                                                       const int32_t* __restrict__ ci,
+                                                       const double* __restrict__ v,
+                                                       const uint8_t* __restrict__ keep,
+                                                       const double* __restrict__ thr, double* __restrict__ den) {
+    const int lane = threadIdx.x & 63;
+    WAVE_ROW_LOOP(i, n) {
+        const int ib = rp[i], ie = rp[i + 1];
+        for (int p = ib + lane; p < ie; p += 64) {
             const int j = ci[p];
             if (j == i || keep[p]) continue;
+            // strong neighbours m of j in ascending order, matched against
+            // the ascending columns of row i by a merge walk
             double d = 0.0;
-            for (int r = rp[j]; r < rp[j + 1]; ++r)
-                if (strong_at(ci, v, thr, j, r) && kept_at(rp, ci, keep, i, ci[r])) d = d + fabs(v[r]);
+            int w = ib;
+            for (int r = rp[j]; r < rp[j + 1]; ++r) {
+                if (!strong_at(ci, v, thr, j, r)) continue;
+                const int m = ci[r];
+                while (w < ie && ci[w] < m) ++w;
+                if (w < ie && ci[w] == m && keep[w]) d = d + fabs(v[r]);
+            }
             den[p] = d;
         }
     }
 }
 
-// row k pulls the shares of the dropped entries (i,j) of the rows i it keeps
-// (i = k included), visited in ascending (i, j): the same order in which the
-// definition adds them
-__global__ void strong_lump_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                                   const double* __restrict__ v, const uint8_t* __restrict__ keep,
-                                   const double* __restrict__ thr, const double* __restrict__ den,
-                                   const int32_t* __restrict__ hrp, const int32_t* __restrict__ hci,
-                                   double* __restrict__ hv) {
-    ROW_LOOP(k, n) {
+// share of the dropped entry q = (s,j) that goes to node x: (|a_jx| / den) a_sj
+// when x is a strong neighbour of j (x is kept in row s by the caller's
+// choice of targets); false when there is none
+__device__ inline bool share_to(const int32_t* ci, const double* v, const int32_t* rp, const double* thr,
+                                const double* den, int q, int j, int x, double& c) {
+    const double d = den[q];
+    if (d == 0.0) return false;
+    const int r = find_in_row(ci, rp[j], rp[j + 1], x);
+    if (r < 0 || !strong_at(ci, v, thr, j, r)) return false;
+    c = (fabs(v[r]) / d) * v[q];
+    return true;
+}
+
+// Row k of the lumped operator, one wave.  Kept sets are symmetric, so the
+// shares an entry (k,m) receives come from exactly two rows: dropped (k,j)
+// sharing with m, and dropped (m,j) sharing with k.  One lane per entry
+// (k,m), m != k, adds them serially, the lower row first, each row in
+// ascending column order: ascending order of the source entry.  The
+// diagonal receives shares from every row it keeps (itself included); the
+// lanes compute one chunk of a source row at a time and the wave adds the
+// chunk's shares in lane order.
+__global__ void __launch_bounds__(kLB) strong_lump_kernel(int n, const int32_t* __restrict__ rp,
+                                                          const int32_t* __restrict__ ci,
+                                                          const double* __restrict__ v,
+                                                          const uint8_t* __restrict__ keep,
+                                                          const double* __restrict__ thr,
+                                                          const double* __restrict__ den,
+                                                          const int32_t* __restrict__ hrp,
+                                                          const int32_t* __restrict__ hci,
+                                                          double* __restrict__ hv) {
+    const int lane = threadIdx.x & 63;
+    WAVE_ROW_LOOP(k, n) {
         const int hb = hrp[k], he = hrp[k + 1];
-        const int dk = find_in_row(hci, hb, he, k);
-        if (dk < 0) continue;   // every operator stores its diagonal; never taken
-        for (int p = rp[k]; p < rp[k + 1]; ++p) {
-            if (!keep[p]) continue;
-            const int i = ci[p];
-            for (int q = rp[i]; q < rp[i + 1]; ++q) {
-                const int j = ci[q];
-                if (j == i || keep[q]) continue;
-                const double aij = v[q], d = den[q];
-                if (i == k) {
-                    if (d == 0.0) {
-                        hv[dk] = hv[dk] + aij;
-                        continue;
-                    }
-                    for (int r = rp[j]; r < rp[j + 1]; ++r) {
-                        if (!(strong_at(ci, v, thr, j, r) && kept_at(rp, ci, keep, k, ci[r]))) continue;
-                        const double c = (fabs(v[r]) / d) * aij;
-                        const int t = ci[r] == k ? dk : find_in_row(hci, hb, he, ci[r]);
-                        if (t >= 0) hv[t] = hv[t] + c;
-                    }
-                } else {
-                    if (d == 0.0) continue;
-                    const int r = find_in_row(ci, rp[j], rp[j + 1], k);
-                    if (r < 0 || !strong_at(ci, v, thr, j, r)) continue;
-                    const double c = (fabs(v[r]) / d) * aij;
-                    const int t = find_in_row(hci, hb, he, i);
-                    if (t >= 0) hv[t] = hv[t] + c;
-                    hv[dk] = hv[dk] - c;
+        for (int t = hb + lane; t < he; t += 64) {
+            const int m = hci[t];
+            if (m == k) continue;
+            double acc = hv[t];
+            for (int pass = 0; pass < 2; ++pass) {
+                // source row s, sharing with node x
+                const int s = (pass == 0) == (m < k) ? m : k;
+                const int x = s == k ? m : k;
+                for (int q = rp[s]; q < rp[s + 1]; ++q) {
+                    const int j = ci[q];
+                    if (j == s || keep[q]) continue;
+                    double c;
+                    if (share_to(ci, v, rp, thr, den, q, j, x, c)) acc = acc + c;
                 }
             }
+            hv[t] = acc;
         }
+        const int dk = find_in_row(hci, hb, he, k);
+        if (dk < 0) continue;   // every operator stores its diagonal; never taken (uniform over the wave)
+        double acc = hv[dk];
+        for (int p = hb; p < he; ++p) {
+            const int s = hci[p];
+            const int sb = rp[s], se = rp[s + 1];
+            for (int q0 = sb; q0 < se; q0 += 64) {
+                const int q = q0 + lane;
+                bool has = false;
+                double c = 0.0;
+                if (q < se && !keep[q]) {
+                    const int j = ci[q];
+                    if (j != s) {
+                        if (s == k && den[q] == 0.0) {
+                            c = v[q];   // no strong neighbour kept: the whole entry
+                            has = true;
+                        } else if (share_to(ci, v, rp, thr, den, q, j, k, c)) {
+                            if (s != k) c = -c;   // a - c == a + (-c) exactly
+                            has = true;
+                        }
+                    }
+                }
+                for (uint64_t mask = __ballot(has); mask != 0; mask &= mask - 1)
+                    acc = acc + __shfl(c, __builtin_ctzll(mask));
+            }
+        }
+        if (lane == 0) hv[dk] = acc;
     }
 }
 
@@ -136,13 +185,13 @@ void launch_lump_threshold(int n, const int32_t* rp, const int32_t* ci, const do
 
 void launch_lump_den(int n, const int32_t* rp, const int32_t* ci, const double* v, const uint8_t* keep,
                      const double* thr, double* den, hipStream_t st) {
-    hipLaunchKernelGGL(lump_den_kernel, dim3(grid_of(n)), dim3(kLB), 0, st, n, rp, ci, v, keep, thr, den);
+    hipLaunchKernelGGL(lump_den_kernel, dim3(wave_grid_of(n)), dim3(kLB), 0, st, n, rp, ci, v, keep, thr, den);
 }
 
 void launch_strong_lump(int n, const int32_t* rp, const int32_t* ci, const double* v, const uint8_t* keep,
                         const double* thr, const double* den, const int32_t* hrp, const int32_t* hci, double* hv,
                         hipStream_t st) {
-    hipLaunchKernelGGL(strong_lump_kernel, dim3(grid_of(n)), dim3(kLB), 0, st, n, rp, ci, v, keep, thr, den, hrp,
+    hipLaunchKernelGGL(strong_lump_kernel, dim3(wave_grid_of(n)), dim3(kLB), 0, st, n, rp, ci, v, keep, thr, den, hrp,
                        hci, hv);
 }
 
