@@ -29,6 +29,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1512_04629_amd", "csrc", "kernels.hip")
 BLOCK_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters_fv3d.json")
 BLOCK_KERNEL_SRC = os.path.join(ROOT, "paper_1512_04629_amd", "csrc", "block_kernels.hip")
+LUMP_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters_lump.json")
+LUMP_KERNEL_SRC = os.path.join(ROOT, "paper_1512_04629_amd", "csrc", "lump_kernels.hip")
 
 
 def log(*a):
@@ -104,14 +106,15 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=32.0,
                     help="serve: HBM budget for resident hierarchies plus batch engines (GiB)")
     ap.add_argument("--requests", type=int, default=512, help="serve: number of requests")
-    ap.add_argument("--workload", default="poisson3d", choices=("poisson3d", "aniso2d", "fv3d", "serve", "setup"),
+    ap.add_argument("--workload", default="poisson3d", choices=("poisson3d", "aniso2d", "fv3d", "serve", "setup", "lumping"),
                     help="poisson3d: the headline 3D Poisson FP64 AMG-PCG run; aniso2d: rotated "
                          "anisotropic Q1 1024^2, FP32-preconditioned vs FP64 PCG to 1e-10; fv3d: "
                          "lognormal-coefficient FV 192^3 with 16 right-hand sides per launch, FP32 "
                          "correction cycle in FP64 iterative refinement to 1e-10; serve: 512 requests "
                          "over 14 resident hierarchies, continuous batching, FP32-preconditioned vs "
                          "FP64 PCG to 1e-10; setup: device-resident hierarchy setup (PMIS) of the "
-                         "3D Poisson problem, vs the host and RS setups")
+                         "3D Poisson problem, vs the host and RS setups; lumping: sparsification of "
+                         "the 3D Poisson hierarchy with strong-neighbour lumping, vs diagonal lumping")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -137,6 +140,8 @@ def main():
         return bench_serve(args)
     if args.workload == "setup":
         return bench_setup(args)
+    if args.workload == "lumping":
+        return bench_lumping(args)
     N = args.N
     A = I.poisson3d(N)
     b_host = I.rhs(A.n, 2)
@@ -422,6 +427,167 @@ def bench_setup(args):
             "sample": f"one whole setup (PMIS seed 1, same {N}^3 problem) by the single-threaded C oracle",
         }
         log(f"[bench] CPU baseline {cpu_s:.2f} s per setup")
+    print(json.dumps(out), flush=True)
+
+
+def lump_shares_bytes(h, l: int) -> int:
+    """Bytes the strong-lumping share kernel must move on level l at least:
+    row pointers of A_l and of its sparsified pattern, A_l's columns, values
+    and keep flags, the denominators of the dropped entries, the thresholds,
+    the kept columns, and every kept value read and written once."""
+    s = h.level_info(l)
+    n, nnz, kept = s["n"], s["nnz"], s["nnz_hat"]
+    return 8 * (n + 1) + 13 * nnz + 8 * (nnz - kept) + 8 * n + 4 * kept + 16 * kept
+
+
+def bench_lumping(args):
+    """Sparsification with strong-neighbour lumping (Algorithm 3, second loop)
+    of the 3D Poisson hierarchy: one step is one pass over every coarse level
+    (keep flags, copy, thresholds, denominators, shares, inverse diagonal);
+    compared with diagonal lumping (Algorithm 3b) on three problem families."""
+    import numpy as np
+    import torch
+
+    from paper_1512_04629_amd import amg
+    from paper_1512_04629_amd import inputs as I
+
+    N = args.N
+    A = I.poisson3d(N)
+    log(f"[bench] lumping: host setup of 3D Poisson {N}^3 (n={A.n}, nnz={A.nnz})")
+    h = amg.Hierarchy(A)
+    h.set_lumping("strong")
+    for _ in range(args.warmup):
+        h.sparsify(args.gamma, 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        h.sparsify(args.gamma, 2)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = elapsed / args.steps * 1e3
+    log(f"[bench] {args.steps} strong-lumping sparsifications: {ms_per_step:.3f} ms each")
+    levels = [l for l in range(h.nlev) if h.gamma(l) > 0]
+    kinds = ("SPARSIFY", "LUMP_DEN", "LUMP_SHARES")
+    times = {}
+    for kind in kinds:
+        h.profile_enable(True, kind)
+        for _ in range(args.steps):
+            h.sparsify(args.gamma, 2)
+        torch.cuda.synchronize()
+        c = ms = 0
+        for l in range(h.nlev):
+            cl, tl = h.profile_read(kind, l)
+            c += cl
+            ms += tl
+        h.profile_enable(False)
+        times[kind] = (c, ms)
+    cnt, ms = times["LUMP_SHARES"]
+    nbytes = args.steps * sum(lump_shares_bytes(h, l) for l in levels)
+    achieved = nbytes / (ms / 1e3) / 1e9
+    traffic = None   # HBM bytes per launch from the committed counters, if they match this source
+    if os.path.exists(LUMP_TRAFFIC_FILE):
+        tc = json.load(open(LUMP_TRAFFIC_FILE))
+        ent = tc.get("kernels", {}).get("LUMP_SHARES")
+        if ent and tc.get("kernel_source_sha") == kernel_source_sha(LUMP_KERNEL_SRC) \
+                and ent["launches_per_pass"] == len(levels):
+            traffic = round(ent["hbm_bytes_per_pass"] / ent["launches_per_pass"])
+    log(f"[bench] share kernel: {cnt} launches, {ms / args.steps:.3f} ms per pass, {achieved:.1f} GB/s "
+        f"of compulsory bytes; denominators {times['LUMP_DEN'][1] / args.steps:.3f} ms per pass")
+
+    compare = {}
+    if not args.no_compare:
+        for name, make in ((f"poisson3d_{N}", lambda: A), ("aniso2d_1024", lambda: I.aniso2d(1024)),
+                           ("fv3d_lognormal_96", lambda: I.fv3d_lognormal(96))):
+            M = make()
+            hh = h if M is A else amg.Hierarchy(M)
+            b = torch.as_tensor(I.rhs(M.n, 2)).cuda()
+            x = torch.zeros(M.n, dtype=torch.float64, device="cuda")
+            hh.set_lumping("diagonal")
+            hh.sparsify(0.0, 2)
+            x.zero_()
+            g = hh.solve(b, x, method=amg.PCG, tol=1e-8, maxit=300)
+            rows = {"galerkin_pcg_iters": g.iters}
+            for mode in ("diagonal", "strong"):
+                hh.set_lumping(mode)
+                for gam in (0.01, 0.1, 1.0):
+                    hh.sparsify(gam, 2)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    for _ in range(5):
+                        hh.sparsify(gam, 2)
+                    torch.cuda.synchronize()
+                    sp_ms = (time.perf_counter() - t0) / 5 * 1e3
+                    cx = sum(hh.level_info(l)["nnz_hat"] for l in range(hh.nlev)) / M.nnz
+                    x.zero_()
+                    r = hh.solve(b, x, method=amg.PCG, tol=1e-8, maxit=300)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    for _ in range(3):
+                        x.zero_()
+                        r = hh.solve(b, x, method=amg.PCG, tol=1e-8, maxit=300)
+                    torch.cuda.synchronize()
+                    solve_ms = (time.perf_counter() - t0) / 3 * 1e3
+                    rows[f"{mode}_gamma_{gam}"] = dict(sparsify_ms=round(sp_ms, 3), operator_complexity=round(cx, 4),
+                                                       pcg_iters=r.iters, converged=bool(r.converged),
+                                                       solve_ms=round(solve_ms, 3))
+                    log(f"[bench] {name} {mode} gamma {gam}: sparsify {sp_ms:.2f} ms, complexity {cx:.3f}, "
+                        f"PCG {r.iters} it {solve_ms:.2f} ms")
+            compare[name] = rows
+            if hh is not h:
+                hh.close()
+    h.close()
+
+    out = {
+        "metric": "sparsifications per second (Sparse Galerkin with strong-neighbour lumping, every coarse "
+                  "level of the hierarchy)",
+        "value": round(args.steps / elapsed, 4),
+        "unit": "sparsifications/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"3D Poisson 7-point FD {N}^3 (n={A.n}, nnz={A.nnz}), Galerkin hierarchy (RS, direct "
+                        f"interpolation) resident in HBM; gamma={args.gamma} on levels >= 2, dropped entries "
+                        f"shared among strong neighbours (theta=0.25)",
+        },
+        "class_ms_per_step": {k: round(times[k][1] / args.steps, 4) for k in kinds},
+        "compare": compare,
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "strong_lump_kernel (shares)",
+            "achieved": round(achieved, 2),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 5),
+            "traffic": traffic,
+            "bytes_per_launch": round(nbytes / max(cnt, 1)),
+            "us_per_launch": round(ms / max(cnt, 1) * 1e3, 3),
+            "launches": cnt,
+        },
+    }
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        log("[bench] CPU baseline: oracle hierarchy (not timed), then one strong-lumping sparsification ...")
+        o = O.OracleAMG(A)
+        o.set_lumping("strong")
+        t0 = time.perf_counter()
+        o.sparsify_from(args.gamma, 2)
+        cpu_s = time.perf_counter() - t0
+        out["cpu_baseline"] = {
+            "value": round(1.0 / cpu_s, 5),
+            "unit": "sparsifications/s",
+            "cores": 1,
+            "kind": "oracle",
+            "sample": f"one strong-lumping sparsification (gamma {args.gamma}, levels >= 2) of the same "
+                      f"{N}^3 hierarchy by the single-threaded C oracle, its setup excluded",
+        }
+        log(f"[bench] CPU baseline {cpu_s:.2f} s per sparsification")
     print(json.dumps(out), flush=True)
 
 

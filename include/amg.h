@@ -363,7 +363,11 @@ amg_status amg_index_width(amg_handle h, int32_t l, int32_t which, int32_t* byte
 enum {
     AMG_K_JACOBI = 0, AMG_K_JACOBI_ZERO = 1, AMG_K_RESIDUAL = 2, AMG_K_RESTRICT = 3,
     AMG_K_INTERP = 4, AMG_K_COARSE = 5, AMG_K_SPMV_DOT = 6, AMG_K_VECTOR = 7,
-    AMG_K_SPARSIFY = 8, AMG_K_NUM = 9
+    AMG_K_SPARSIFY = 8,
+    /* inside AMG_K_SPARSIFY, strong-neighbour lumping only: the share
+       denominators, and the shares added into the kept entries */
+    AMG_K_LUMP_DEN = 9, AMG_K_LUMP_SHARES = 10,
+    AMG_K_NUM = 11
 };
 amg_status amg_profile_enable(amg_handle h, int32_t enable, int32_t kernel_class, int32_t level);
 amg_status amg_profile_read(amg_handle h, int32_t kernel_class, int32_t level, int64_t* count,

@@ -30,7 +30,8 @@ VEC = {"ROWMAX": 0, "DINV": 1}
 OP = {"RESIDUAL": 0, "JACOBI": 1, "RESTRICT": 2, "INTERPOLATE": 3, "COARSE_SOLVE": 4,
       "SPMV_A": 5, "SPMV_AHAT": 6, "GS_FORWARD": 7, "GS_BACKWARD": 8}
 KERNEL = {"JACOBI": 0, "JACOBI_ZERO": 1, "RESIDUAL": 2, "RESTRICT": 3, "INTERP": 4,
-          "COARSE": 5, "SPMV_DOT": 6, "VECTOR": 7, "SPARSIFY": 8}
+          "COARSE": 5, "SPMV_DOT": 6, "VECTOR": 7, "SPARSIFY": 8, "LUMP_DEN": 9,
+          "LUMP_SHARES": 10}
 
 # every symbol include/amg.h declares
 ABI_SYMBOLS = (
