@@ -90,27 +90,43 @@ __global__ void __launch_bounds__(kLB) lump_den_kernel(int n, const int32_t* __r
     }
 }
 
-// share of the dropped entry q = (s,j) that goes to node x: (|a_jx| / den) a_sj
-// when x is a strong neighbour of j (x is kept in row s by the caller's
-// choice of targets); false when there is none
-__device__ inline bool share_to(const int32_t* ci, const double* v, const int32_t* rp, const double* thr,
-                                const double* den, int q, int j, int x, double& c) {
-    const double d = den[q];
-    if (d == 0.0) return false;
-    const int r = find_in_row(ci, rp[j], rp[j + 1], x);
-    if (r < 0 || !strong_at(ci, v, thr, j, r)) return false;
-    c = (fabs(v[r]) / d) * v[q];
-    return true;
+// Position of column col in the ascending columns ci[w..e), walking w
+// forward (a merge against an ascending sequence of col); -1 if absent.
+__device__ inline int walk_to(const int32_t* ci, int& w, int e, int col) {
+    while (w < e && ci[w] < col) ++w;
+    return (w < e && ci[w] == col) ? w : -1;
+}
+
+// acc plus the shares the dropped entries (s,j) of row s give to node x, in
+// ascending j: (|a_jx| / den) a_sj where (j,x) is strong.  The operator is
+// bitwise symmetric, so a_jx is read as a_xj from row x, found by a merge
+// walk of row s against row x: no row j is touched.  (s,x) is kept, so x
+// belongs to every such W and den > 0.
+__device__ inline double pull_row(const int32_t* rp, const int32_t* ci, const double* v, const uint8_t* keep,
+                                  const double* thr, const double* den, int s, int x, double acc) {
+    int w = rp[x];
+    const int we = rp[x + 1];
+    for (int q = rp[s]; q < rp[s + 1]; ++q) {
+        const int j = ci[q];
+        if (j == s || keep[q]) continue;
+        const int r = walk_to(ci, w, we, j);
+        if (r < 0) continue;
+        const double t = thr[j], ajx = v[r];
+        if (t > 0.0 && -ajx >= t) acc = acc + (fabs(ajx) / den[q]) * v[q];
+    }
+    return acc;
 }
 
 // Row k of the lumped operator, one wave.  Kept sets are symmetric, so the
 // shares an entry (k,m) receives come from exactly two rows: dropped (k,j)
-// sharing with m, and dropped (m,j) sharing with k.  One lane per entry
-// (k,m), m != k, adds them serially, the lower row first, each row in
-// ascending column order: ascending order of the source entry.  The
-// diagonal receives shares from every row it keeps (itself included); the
-// lanes compute one chunk of a source row at a time and the wave adds the
-// chunk's shares in lane order.
+// sharing with m, and dropped (m,j) sharing with k, added in ascending order
+// of the source entry (the lower row first).  (m,k) receives the same shares
+// in the same order from the same start value, so one lane per (k,m) with
+// m > k adds them serially and writes both entries.  The diagonal receives
+// shares from every row it keeps (itself included); the lanes form one chunk
+// of 64 entries of a source row at a time and the wave adds the chunk's
+// shares in lane order.  Requires a bitwise symmetric operator (every
+// Galerkin and non-Galerkin coarse operator is).
 __global__ void __launch_bounds__(kLB) strong_lump_kernel(int n, const int32_t* __restrict__ rp,
                                                           const int32_t* __restrict__ ci,
                                                           const double* __restrict__ v,
@@ -125,23 +141,16 @@ __global__ void __launch_bounds__(kLB) strong_lump_kernel(int n, const int32_t* 
         const int hb = hrp[k], he = hrp[k + 1];
         for (int t = hb + lane; t < he; t += 64) {
             const int m = hci[t];
-            if (m == k) continue;
-            double acc = hv[t];
-            for (int pass = 0; pass < 2; ++pass) {
-                // source row s, sharing with node x
-                const int s = (pass == 0) == (m < k) ? m : k;
-                const int x = s == k ? m : k;
-                for (int q = rp[s]; q < rp[s + 1]; ++q) {
-                    const int j = ci[q];
-                    if (j == s || keep[q]) continue;
-                    double c;
-                    if (share_to(ci, v, rp, thr, den, q, j, x, c)) acc = acc + c;
-                }
-            }
+            if (m <= k) continue;
+            double acc = pull_row(rp, ci, v, keep, thr, den, k, m, hv[t]);
+            acc = pull_row(rp, ci, v, keep, thr, den, m, k, acc);
             hv[t] = acc;
+            const int tm = find_in_row(hci, hrp[m], hrp[m + 1], k);
+            if (tm >= 0) hv[tm] = acc;   // always found: the kept pattern is symmetric
         }
         const int dk = find_in_row(hci, hb, he, k);
         if (dk < 0) continue;   // every operator stores its diagonal; never taken (uniform over the wave)
+        const int kb = rp[k], ke = rp[k + 1];
         double acc = hv[dk];
         for (int p = hb; p < he; ++p) {
             const int s = hci[p];
@@ -152,13 +161,28 @@ __global__ void __launch_bounds__(kLB) strong_lump_kernel(int n, const int32_t* 
                 double c = 0.0;
                 if (q < se && !keep[q]) {
                     const int j = ci[q];
-                    if (j != s) {
-                        if (s == k && den[q] == 0.0) {
+                    const double d = den[q];
+                    if (j != s && s == k) {
+                        if (d == 0.0) {
                             c = v[q];   // no strong neighbour kept: the whole entry
                             has = true;
-                        } else if (share_to(ci, v, rp, thr, den, q, j, k, c)) {
-                            if (s != k) c = -c;   // a - c == a + (-c) exactly
-                            has = true;
+                        } else {
+                            // the share to k itself, with a_jk = a_kj
+                            const double t = thr[j], a = v[q];
+                            if (t > 0.0 && -a >= t) {
+                                c = (fabs(a) / d) * a;
+                                has = true;
+                            }
+                        }
+                    } else if (j != s && d != 0.0) {
+                        // the share of (s,j) to k, with a_jk read as a_kj from row k
+                        const int r = find_in_row(ci, kb, ke, j);
+                        if (r >= 0) {
+                            const double t = thr[j], a = v[r];
+                            if (t > 0.0 && -a >= t) {
+                                c = -((fabs(a) / d) * v[q]);   // a - c == a + (-c) exactly
+                                has = true;
+                            }
                         }
                     }
                 }

@@ -25,7 +25,8 @@ void launch_lump_threshold(int n, const int32_t* rp, const int32_t* ci, const do
 // ascending m, of |a_jm| over m strong for j and kept in row i (0: none)
 void launch_lump_den(int n, const int32_t* rp, const int32_t* ci, const double* v, const uint8_t* keep,
                      const double* thr, double* den, hipStream_t st);
-// adds every row's shares to the copied kept entries hrp / hci / hv
+// adds every row's shares to the copied kept entries hrp / hci / hv; a must
+// be bitwise symmetric with a symmetric keep set (a_jm is read as a_mj)
 void launch_strong_lump(int n, const int32_t* rp, const int32_t* ci, const double* v, const uint8_t* keep,
                         const double* thr, const double* den, const int32_t* hrp, const int32_t* hci, double* hv,
                         hipStream_t st);
