@@ -1,0 +1,129 @@
+"""The mixed-precision and multi-right-hand-side workloads at full size, in the
+launch configuration bench.py times.
+
+* Rotated anisotropic Q1 diffusion, 1024^2 (n = 1,048,576): the hierarchy,
+  minimal patterns, keep flags and sparsified patterns are bit-exact with the
+  oracle's at gamma 0.01 and 0.1; the adaptive AMG-PCG solve to 1e-10 with
+  the FP64 cycle takes the oracle's iteration and reintroduction counts and
+  agrees to 1e-10, and with the FP32 cycle it meets the FP32 bars (true FP64
+  residual <= 1.01e-10 ||b||, ||A (x - x_or)|| <= 2.02e-10 ||b||, at most 3
+  iterations more than the oracle).
+* Lognormal-coefficient FV, 192^3 (n = 7,077,888) with 16 right-hand sides,
+  gamma 0.01: too large for the oracle, so checked by properties that hold at
+  any size.  Block PCG and block iterative refinement with the FP32 cycle
+  bring every column's true FP64 residual, evaluated on the host, to
+  <= 1.01e-10 ||b_c|| (and report a residual within the tolerance); a
+  column solved alone (the other columns zero) equals the same column solved
+  in the full block, bit for bit: with the same iteration count under PCG,
+  which freezes converged columns, and after the block's number of
+  iterations under refinement, which keeps refining them.
+"""
+import numpy as np
+import pytest
+
+from paper_1512_04629_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1512_04629_amd import amg
+    amg.load_library()
+    return amg
+
+
+def _csr(A):
+    import scipy.sparse as sp
+    return sp.csr_matrix((A.val, A.col, A.row_ptr), shape=(A.n, A.n))
+
+
+def test_full_size_aniso2d_1024(lib):
+    from oracle import oracle as O
+    A = I.aniso2d(1024)
+    b = I.rhs(A.n, 3)
+    print(f"aniso2d 1024: n={A.n} nnz={A.nnz}", flush=True)
+    g, o = lib.Hierarchy(A), O.OracleAMG(A)
+    assert g.nlev == o.nlev
+    for l in range(o.nlev):
+        ga, oa = g.export(l, "A"), o.export(l, "A")
+        assert np.array_equal(ga[2], oa.row_ptr) and np.array_equal(ga[3], oa.col), l
+        assert bool(np.array_equal(ga[4].view(np.uint64), oa.val.view(np.uint64))), l
+    S = _csr(A)
+    nb = np.linalg.norm(b)
+    kw = dict(method=1, tol=1e-10, maxit=500, adaptive=True, k=3, s=1)
+    db = torch.as_tensor(b).cuda()
+    for gamma in (0.01, 0.1):
+        g.sparsify(gamma, 2)
+        o.sparsify_from(gamma, 2)
+        for l in range(1, o.nlev):
+            assert np.array_equal(g.mask(l, "M"), o.mask(l, "M")), (gamma, l)
+            assert np.array_equal(g.mask(l, "KEEP"), o.mask(l, "KEEP")), (gamma, l)
+            gh, oh = g.export(l, "AHAT"), o.export(l, "AHAT")
+            assert np.array_equal(gh[2], oh.row_ptr) and np.array_equal(gh[3], oh.col), (gamma, l)
+        print(f"  gamma {gamma}: oracle solve", flush=True)
+        xo, ro = o.solve(b, **kw)
+        assert ro.converged
+        # the solve reintroduces entries: start each precision from this sparsification
+        for prec in (64, 32):
+            print(f"  gamma {gamma}: device solve, FP{prec} cycle", flush=True)
+            g.sparsify(gamma, 2)
+            x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+            rg = g.solve(db, x, precision=prec, **kw)
+            torch.cuda.synchronize()
+            xg = x.cpu().numpy()
+            assert rg.converged, (gamma, prec, rg)
+            true_rel = np.linalg.norm(b - S @ xg) / nb
+            if prec == 64:
+                assert rg.iters == ro.iters and rg.reintroductions == ro.reintroductions, (gamma, rg, ro)
+                assert np.linalg.norm(xg - xo) <= 1e-10 * np.linalg.norm(xo)
+                assert abs(rg.relres - ro.relres) <= 1e-10
+            else:
+                assert rg.iters <= ro.iters + 3, (gamma, rg.iters, ro.iters)
+            assert true_rel <= 1.01e-10, (gamma, prec, true_rel)
+            assert np.linalg.norm(S @ (xg - xo)) <= 2.02e-10 * nb, (gamma, prec)
+        o.sparsify_from(gamma, 2)   # undo the oracle's reintroductions before the next gamma
+
+
+def test_full_size_fv3d_192_16_rhs(lib):
+    A = I.fv3d_lognormal(192, seed=40)
+    K = 16
+    print(f"fv3d 192: n={A.n} nnz={A.nnz}", flush=True)
+    B = np.stack([I.rhs(A.n, 41 + c) for c in range(K)], axis=1)
+    g = lib.Hierarchy(A)
+    g.sparsify(0.01, 2)
+    S = _csr(A)
+    dB = torch.as_tensor(B).cuda()
+    for method in (1, 0):   # block PCG, block iterative refinement
+        print(f"  method {method}: 16-column solve", flush=True)
+        X = torch.zeros(A.n, K, dtype=torch.float64, device="cuda")
+        res = g.solve_block(dB, X, method=method, tol=1e-10, maxit=300, precision=32)
+        assert res.status == 0 and res.converged, (method, res)
+        Xh = X.cpu().numpy()
+        for c in range(K):
+            nb = np.linalg.norm(B[:, c])
+            true_rel = np.linalg.norm(B[:, c] - S @ Xh[:, c]) / nb
+            assert true_rel <= 1.01e-10, (method, c, true_rel)
+            assert res.col_relres[c] <= 1.01e-10, (method, c)
+        print(f"  method {method}: iterations per column {list(res.col_iters)}", flush=True)
+        c = 9
+        Bc = np.zeros_like(B)
+        Bc[:, c] = B[:, c]
+        Xc = torch.zeros(A.n, K, dtype=torch.float64, device="cuda")
+        print(f"  method {method}: column {c} alone", flush=True)
+        if method == 1:
+            # block PCG freezes a column once it has converged
+            rc = g.solve_block(torch.as_tensor(Bc).cuda(), Xc, method=1, tol=1e-10, maxit=300, precision=32)
+            assert rc.converged and rc.col_iters[c] == res.col_iters[c], (rc.col_iters[c], res.col_iters[c])
+        else:
+            # refinement keeps refining converged columns until the last one
+            # converges: compare after the block's number of iterations
+            rc = g.solve_block(torch.as_tensor(Bc).cuda(), Xc, method=0, tol=0.0, maxit=int(res.iters),
+                               precision=32)
+            assert rc.status == -5 and rc.iters == res.iters, (rc.status, rc.iters, res.iters)
+        same = bool(np.array_equal(Xc[:, c].cpu().numpy(), Xh[:, c]))
+        assert same, (method, c)
+        assert torch.count_nonzero(Xc).item() == torch.count_nonzero(Xc[:, c]).item()
