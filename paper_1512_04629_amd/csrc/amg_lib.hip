@@ -779,7 +779,7 @@ void gs_sweeps(amg_ctx* h, int l, const double* b, double*& cur, double*& alt, b
     const DevMat& a = h->lv[l].Ah;
     for (int s = 0; s < sweeps; ++s) {
         ProfScope ps(h, AMG_K_JACOBI, l);
-        launch_hybrid_gs(forward, a.rows, a.rp, a.ci, a.v, b, cur, alt, h->gs_block, h->stream);
+        launch_hybrid_gs(forward, a.rows, a.rp, a.ci, a.v, b, cur, alt, h->gs_block, a.view().mean_row, h->stream);
         check_launch();
         std::swap(cur, alt);
     }
@@ -2667,7 +2667,7 @@ amg_status amg_level_op(amg_handle h, int32_t level, int32_t op, const double* i
                 if (!in || !x || x == out) return AMG_ERR_INVALID_ARG;
                 ProfScope ps(h, AMG_K_JACOBI, level);
                 launch_hybrid_gs(op == AMG_OP_GS_FORWARD, v.n, v.Ah.rp, v.Ah.ci, v.Ah.v, in, x, out, h->gs_block,
-                                 h->stream);
+                                 v.Ah.view().mean_row, h->stream);
                 check_launch();
                 break;
             }

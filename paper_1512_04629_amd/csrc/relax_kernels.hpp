@@ -14,8 +14,10 @@ namespace amg355 {
 //   xnew_i = (b_i - sum_{j != i} a_ij y_j) / a_ii,
 // the terms subtracted in ascending column order, y_j the new value of a row
 // of the same block visited before row i and xold_j otherwise.  Every row of
-// xnew is written; xnew and xold must not overlap.
+// xnew is written; xnew and xold must not overlap.  mean_row (entries per
+// row) only sizes the chunks of the staged form.
 void launch_hybrid_gs(bool forward, int n, const int32_t* rp, const int32_t* ci, const double* v,
-                      const double* b, const double* xold, double* xnew, int block, hipStream_t st);
+                      const double* b, const double* xold, double* xnew, int block, double mean_row,
+                      hipStream_t st);
 
 }  // namespace amg355
