@@ -78,6 +78,8 @@ struct DevMat {
     uint16_t* ci16 = nullptr;
     int32_t* cbase = nullptr;
     int idx_rb = 0;
+    // direction of this operator's next cycle pass (flipped by every pass)
+    mutable int next_rev = 0;
     CsrView view() const {
         return CsrView{rp, ci, v, rows, rows ? (double)shape_nnz / rows : 1.0, ci16, cbase, idx_rb};
     }
@@ -334,14 +336,18 @@ void row_op(amg_ctx* h, int kind, int level, RowOp op, const DevMat& m, const do
             const double* u, const double* dinv, double* y, double* y2, int dot_slot) {
     ProfScope ps(h, kind, level);
     DotTarget dt = dot_slot >= 0 ? dot_to(h, dot_slot) : DotTarget{nullptr, nullptr};
-    launch_row_op(op, m.width, m.view(), g, u, dinv, h->sp.omega, y, y2, dt, h->stream);
+    CsrView cv = m.view();
+    cv.rev = m.next_rev;
+    m.next_rev ^= 1;
+    launch_row_op(op, m.width, cv, g, u, dinv, h->sp.omega, y, y2, dt, h->stream);
     check_launch();
 }
 
 void row_op(amg_ctx* h, int kind, int level, RowOp op, const DevMat& m, const float* vals, const float* g,
             const float* u, const float* dinv, float* y, float* y2) {
     ProfScope ps(h, kind, level);
-    const CsrView32 a32{m.rp, m.ci, vals, m.rows, m.view().mean_row, m.ci16, m.cbase, m.idx_rb};
+    const CsrView32 a32{m.rp, m.ci, vals, m.rows, m.view().mean_row, m.ci16, m.cbase, m.idx_rb, m.next_rev};
+    m.next_rev ^= 1;
     launch_row_op(op, m.width, a32, g, u, dinv, (float)h->sp.omega, y, y2, h->stream);
     check_launch();
 }

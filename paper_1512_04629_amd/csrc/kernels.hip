@@ -316,7 +316,8 @@ __global__ __launch_bounds__(kBlock) void stream_kernel(CsrT<T> a, const T* __re
     const int lb = xcd_logical_block();
     const int lane = threadIdx.x & (W2 - 1);
     double contrib = 0.0;
-    for (int blk = lb; blk < nblk; blk += gridDim.x) {
+    for (int lblk = lb; lblk < nblk; lblk += gridDim.x) {
+        const int blk = a.rev ? nblk - 1 - lblk : lblk;
         const int r0 = blk * RB;
         const int r1 = min(r0 + RB, a.rows);
         const int p0 = a.rp[r0], p1 = a.rp[r1];
@@ -448,7 +449,8 @@ __global__ __launch_bounds__(kBlock) void stream_pipe_kernel(CsrT<T> a, const T*
     const int lane = threadIdx.x & (W2 - 1);
     const int rsub = (int)threadIdx.x / W2;
     double contrib = 0.0;
-    auto meta = [&](int b, int& q0, int& q1, int& rr, bool& ac, int& qb, int& qe, int& cbb) {
+    auto meta = [&](int lbk, int& q0, int& q1, int& rr, bool& ac, int& qb, int& qe, int& cbb) {
+        const int b = a.rev ? nblk - 1 - lbk : lbk;
         const int r0 = b * RB;
         const int r1 = min(r0 + RB, a.rows);
         q0 = a.rp[r0];
@@ -611,11 +613,22 @@ void launch_stream_rbi(RowOp op, const CsrT<T>& a, const T* g, const T* u, const
     }
 }
 
+// Alternating the direction of consecutive passes over one operator lets a
+// pass start on the part of the operator the previous pass left in the
+// Infinity Cache.
+#ifndef AMG_STREAM_ALTERNATE
+#define AMG_STREAM_ALTERNATE 1
+#endif
+
 template <class T, int RB, bool VEC4>
-void launch_stream_rb(RowOp op, const CsrT<T>& a, const T* g, const T* u, const T* dinv,
+void launch_stream_rb(RowOp op, const CsrT<T>& a_in, const T* g, const T* u, const T* dinv,
                       T omega, T* y, T* y2, DotTarget dot, hipStream_t st) {
-    const int nblk = std::max(1, (a.rows + RB - 1) / RB);
+    const int nblk = std::max(1, (a_in.rows + RB - 1) / RB);
     const int grid = round_up8(std::min(nblk, std::min(kRowGridCap, AMG_STREAM_GRID_CAP)));
+    CsrT<T> a = a_in;
+    // a dot product's per-workgroup partials depend on which row blocks a
+    // workgroup visits: those launches keep the ascending order
+    if (!AMG_STREAM_ALTERNATE || op == kResidNorm || op == kJacobiDot || op == kSpmvDot) a.rev = 0;
     if (a.ci16 && a.idx_rb == RB)
         launch_stream_rbi<T, RB, VEC4, true>(op, a, g, u, dinv, omega, y, y2, dot, nblk, grid, st);
     else launch_stream_rbi<T, RB, VEC4, false>(op, a, g, u, dinv, omega, y, y2, dot, nblk, grid, st);

@@ -21,6 +21,9 @@ struct CsrT {
     const uint16_t* ci16 = nullptr;
     const int32_t* cbase = nullptr;
     int idx_rb = 0;
+    // LDS-staged kernels without a dot product visit the row blocks in
+    // descending order (each row's result does not depend on the order)
+    int rev = 0;
 };
 using CsrView = CsrT<double>;
 using CsrView32 = CsrT<float>;
