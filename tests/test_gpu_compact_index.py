@@ -2,7 +2,9 @@
 a storage form of the same matrices, so every result is bitwise the one the
 32-bit indices give.  Bars: V-cycles (FP64, FP32) and PCG solves bit for bit
 equal with the indices on and off; the form is used where the spans fit
-(banded 3D Poisson) and refused where they do not (a random graph)."""
+(banded 3D Poisson) and refused where they do not (a random graph).  The
+LDS-staged kernels alternate the order of their row blocks from pass to
+pass: results bitwise independent of it."""
 import numpy as np
 import pytest
 
@@ -74,3 +76,39 @@ def test_toggle_refused_while_a_batch_exists(lib):
         eng.close()
         h.set_compact_indices(False)
         h.close()
+
+
+def test_stream_direction_does_not_change_results(lib):
+    """Consecutive passes over one operator visit its row blocks in opposite
+    orders (for the Infinity Cache); every row's result is the same either
+    way, so two consecutive launches of a level operation give the same bits,
+    with 16-bit and with 32-bit indices, on the LDS-staged levels."""
+    A = I.poisson3d(64)
+    h = lib.Hierarchy(A)
+    h.sparsify(0.1, 2)
+    levels = _stream_levels(h)
+    assert levels
+    gen = torch.Generator(device="cuda").manual_seed(11)
+    for on in (True, False):
+        h.set_compact_indices(on)
+        for l in levels:
+            n = h.level_info(l)["n"]
+            b = torch.rand(n, dtype=torch.float64, device="cuda", generator=gen)
+            x = torch.rand(n, dtype=torch.float64, device="cuda", generator=gen)
+            for op in ("JACOBI", "RESIDUAL", "SPMV_A", "SPMV_AHAT"):
+                outs = []
+                for _ in range(3):
+                    y = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+                    h.level_op(l, op, inp=b, x=x, out=y)
+                    outs.append(host(y))
+                assert outs[0].tobytes() == outs[1].tobytes() == outs[2].tobytes(), (on, l, op)
+            if l + 1 < h.nlev:
+                nc = h.level_info(l + 1)["n"]
+                xc = torch.rand(nc, dtype=torch.float64, device="cuda", generator=gen)
+                for op, inp, xx, m in (("RESTRICT", x, None, nc), ("INTERPOLATE", xc, x, n)):
+                    outs = []
+                    for _ in range(2):
+                        y = torch.full((m,), float("nan"), dtype=torch.float64, device="cuda")
+                        h.level_op(l, op, inp=inp, x=xx, out=y)
+                        outs.append(host(y))
+                    assert outs[0].tobytes() == outs[1].tobytes(), (on, l, op)
