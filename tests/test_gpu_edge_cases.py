@@ -1,0 +1,111 @@
+"""Degenerate inputs through the C ABI, against the oracle.
+
+* a 1 x 1 system and a diagonal matrix of 500 rows: no strong couplings, so
+  the split is empty and the fine level is the coarsest (solved by the dense
+  inverse); one PCG iteration gives x = D^-1 b;
+* a zero right-hand side: converged at iteration 0 with x = 0 exactly, for
+  PCG and the stationary iteration, with the FP64 and the FP32 cycle;
+* rows without couplings inside a coupled problem (isolated points, which the
+  split makes F points with empty interpolation rows): hierarchy, keep flags
+  and sparsified operators bit-exact under diagonal and strong-neighbour
+  lumping, and the solve at the parity bars.
+"""
+import numpy as np
+import pytest
+
+from paper_1512_04629_amd import inputs as I
+
+from .test_gpu_parity import _assert_solve_parity, _solve_pair, both, dev, host, same_csr
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1512_04629_amd import amg
+    amg.load_library()
+    return amg
+
+
+def _diagonal(d):
+    n = len(d)
+    return I.CSR(n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), np.asarray(d, np.float64))
+
+
+def _isolate(A, rows):
+    """A with every off-diagonal coupling of the given rows (and their mirror
+    entries) removed: still bitwise symmetric."""
+    iso = np.zeros(A.n, bool)
+    iso[list(rows)] = True
+    r = np.repeat(np.arange(A.n), np.diff(A.row_ptr))
+    keep = (r == A.col) | ~(iso[r] | iso[A.col])
+    rp = np.concatenate([[0], np.cumsum(np.bincount(r[keep], minlength=A.n))]).astype(np.int32)
+    return I.CSR(A.n, rp, A.col[keep].astype(np.int32), A.val[keep].copy())
+
+
+@pytest.mark.parametrize("d", [[4.0], list(2.0 + np.arange(500) % 7)], ids=["1x1", "diag500"])
+def test_no_couplings_single_level(lib, d):
+    A = _diagonal(d)
+    b = I.rhs(A.n, 5)
+    xg, rg, xo, ro, g, o = _solve_pair(A, [0.0], b, method=1, tol=1e-10, maxit=10)
+    assert g.nlev == o.nlev == 1
+    assert rg.converged and rg.iters == ro.iters == 1
+    np.testing.assert_allclose(xg, b / np.asarray(d), rtol=1e-14, atol=0)
+    assert np.linalg.norm(xg - xo) <= 1e-14 * np.linalg.norm(xo)
+    g.sparsify(0.1, 2)            # nothing to sparsify on a single level
+    g.set_lumping("strong")
+    g.sparsify(1.0, 1)
+    x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    assert g.solve(dev(b), x, method=1, tol=1e-10, maxit=10).iters == 1
+
+
+@pytest.mark.parametrize("method", [0, 1])
+@pytest.mark.parametrize("precision", [64, 32])
+def test_zero_right_hand_side(lib, method, precision):
+    A = I.poisson2d(16)
+    g, o = both(A)
+    g.sparsify(0.1, 2)
+    o.sparsify_from(0.1, 2)
+    xo, ro = o.solve(np.zeros(A.n), method=method, tol=1e-10, maxit=10)
+    x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    rg = g.solve(torch.zeros(A.n, dtype=torch.float64, device="cuda"), x, method=method, tol=1e-10, maxit=10,
+                 precision=precision)
+    assert rg.converged and rg.iters == ro.iters == 0 and rg.status == ro.status == 0
+    assert torch.count_nonzero(x).item() == 0 and not np.any(xo)
+
+
+@pytest.mark.parametrize("lumping", ["diagonal", "strong"])
+def test_isolated_rows_inside_a_coupled_problem(lib, lumping):
+    A = _isolate(I.poisson3d(12), [0, 17, 100, 863, 1727])
+    b = I.rhs(A.n, 6)
+    g, o = both(A)
+    assert g.nlev == o.nlev
+    for l in range(o.nlev):
+        assert same_csr(g.export(l, "A"), o.export(l, "A")), l
+        if l < o.nlev - 1:
+            assert same_csr(g.export(l, "P"), o.export(l, "P")), l
+    g.set_lumping(lumping)
+    o.set_lumping(lumping)
+    gam = [0.0, 0.0] + [1.0] * (o.nlev - 2)
+    g.sparsify_levels(gam)
+    o.sparsify(gam)
+    for l in range(1, o.nlev):
+        assert np.array_equal(g.mask(l, "KEEP"), o.mask(l, "KEEP")), l
+        gh, oh = g.export(l, "AHAT"), o.export(l, "AHAT")
+        assert np.array_equal(gh[2], oh.row_ptr) and np.array_equal(gh[3], oh.col), l
+        if lumping == "strong":
+            assert gh[4].tobytes() == oh.val.tobytes(), l
+        else:
+            assert np.allclose(gh[4], oh.val, rtol=1e-13, atol=0), l
+    x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    rg = g.solve(dev(b), x, method=1, tol=1e-10, maxit=100)
+    xo, ro = o.solve(b, method=1, tol=1e-10, maxit=100)
+    _assert_solve_parity(host(x), rg, xo, ro)
+    # an isolated row's residual is b_i - a_ii x_i, at most the stopping residual
+    xh, nb = host(x), np.linalg.norm(b)
+    for i in (0, 17, 100, 863, 1727):
+        d = A.val[A.row_ptr[i]]
+        assert abs(xh[i] - b[i] / d) <= 1.01e-10 * nb / d, i
