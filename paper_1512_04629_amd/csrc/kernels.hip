@@ -817,26 +817,33 @@ __device__ __forceinline__ int find_in_row(const int32_t* __restrict__ rp, const
     return -1;
 }
 
+// One wave per coarse row I, lanes over the entries l of the fine row c(I):
+// every (I, J) with J in P's row l is marked together with (J, I).  The marks
+// form a set (idempotent byte stores), so the lanes need no order.
+constexpr int kMarkGridCap = 65536;
+
 __global__ __launch_bounds__(kBlock) void mark_minimal_pattern_kernel(
     int nc, const int32_t* __restrict__ c_points, const int32_t* __restrict__ afine_rp,
     const int32_t* __restrict__ afine_ci, const int32_t* __restrict__ p_rp,
     const int32_t* __restrict__ p_ci, const int32_t* __restrict__ ac_rp,
     const int32_t* __restrict__ ac_ci, uint8_t* in_m, int* missing) {
-    const int I = blockIdx.x * kBlock + threadIdx.x;
-    if (I >= nc) return;
-    const int f = c_points[I];
-    for (int p = afine_rp[f]; p < afine_rp[f + 1]; ++p) {
-        const int l = afine_ci[p];
-        for (int q = p_rp[l]; q < p_rp[l + 1]; ++q) {
-            const int J = p_ci[q];
-            const int a = find_in_row(ac_rp, ac_ci, I, J);
-            const int b = find_in_row(ac_rp, ac_ci, J, I);
-            if (a < 0 || b < 0) {
-                *missing = 1;
-                continue;
+    constexpr int kWaves = kBlock / 64;
+    const int lane = threadIdx.x & 63;
+    for (int I = blockIdx.x * kWaves + (int)(threadIdx.x >> 6); I < nc; I += gridDim.x * kWaves) {
+        const int f = c_points[I];
+        for (int p = afine_rp[f] + lane; p < afine_rp[f + 1]; p += 64) {
+            const int l = afine_ci[p];
+            for (int q = p_rp[l]; q < p_rp[l + 1]; ++q) {
+                const int J = p_ci[q];
+                const int a = find_in_row(ac_rp, ac_ci, I, J);
+                const int b = find_in_row(ac_rp, ac_ci, J, I);
+                if (a < 0 || b < 0) {
+                    *missing = 1;
+                    continue;
+                }
+                in_m[a] = 1;
+                in_m[b] = 1;
             }
-            in_m[a] = 1;
-            in_m[b] = 1;
         }
     }
 }
@@ -1319,8 +1326,10 @@ void launch_mark_minimal_pattern(int nc, const int32_t* c_points, const int32_t*
                                  const int32_t* afine_ci, const int32_t* p_rp,
                                  const int32_t* p_ci, const int32_t* ac_rp, const int32_t* ac_ci,
                                  uint8_t* in_m, int* missing, hipStream_t st) {
-    hipLaunchKernelGGL(mark_minimal_pattern_kernel, dim3((nc + kBlock - 1) / kBlock), dim3(kBlock), 0,
-                       st, nc, c_points, afine_rp, afine_ci, p_rp, p_ci, ac_rp, ac_ci, in_m, missing);
+    if (nc <= 0) return;
+    const int grid = std::min((nc + kBlock / 64 - 1) / (kBlock / 64), kMarkGridCap);
+    hipLaunchKernelGGL(mark_minimal_pattern_kernel, dim3(grid), dim3(kBlock), 0, st, nc, c_points, afine_rp,
+                       afine_ci, p_rp, p_ci, ac_rp, ac_ci, in_m, missing);
 }
 
 #define AMG_WIDTH_SWITCH(width, KERNEL, ...)                                                   \
