@@ -510,9 +510,25 @@ def bench_methods(args):
                 r = run()
                 torch.cuda.synchronize()
                 ts.append((time.perf_counter() - t0) * 1e3)
+            # kernel time per level and iteration (HIP events on every launch of one solve)
+            prepare()
+            x.zero_()
+            h.profile_enable(True)
+            rp_ = h.solve(b, x, **kw)
+            torch.cuda.synchronize()
+            per_level = []
+            for l in range(h.nlev):
+                tot = 0.0
+                for kern in amg.KERNEL:
+                    if kern in ("SPARSIFY", "LUMP_DEN", "LUMP_SHARES"):
+                        continue
+                    tot += h.profile_read(kern, l)[1]
+                per_level.append(round(tot / max(rp_.iters, 1) * 1e3, 2))
+            h.profile_enable(False)
             prepare()
             nnz = [h.level_info(l)["nnz_hat"] for l in range(h.nlev)]
             return dict(ms_to_1e8=round(float(np.median(ts)), 3), ms_min=round(min(ts), 3), iters=r.iters,
+                        us_per_iteration_by_level=per_level,
                         reintroductions=r.reintroductions, converged=bool(r.converged), relres=r.relres,
                         operator_complexity=round(sum(nnz) / A.nnz, 4), bytes_per_vcycle=h.bytes_per_cycle(),
                         nnz_per_level=nnz, levels=h.nlev), run
