@@ -209,7 +209,7 @@ enum { AMG_SPARSE_GALERKIN = 0, AMG_HYBRID_GALERKIN = 1 };
    so the result is symmetric bit for bit.  Row sums are kept; unlike
    diagonal lumping, positive definiteness is not guaranteed.  The
    non-Galerkin setup always lumps to the diagonal.  AMG_ERR_STATE while a
-   batch engine exists. */
+   batch engine exists, AMG_ERR_INVALID_ARG for any other value. */
 enum { AMG_LUMP_DIAGONAL = 0, AMG_LUMP_STRONG = 1 };
 amg_status amg_set_lumping(amg_handle h, int32_t lumping);
 

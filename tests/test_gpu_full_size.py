@@ -17,6 +17,10 @@ launch configuration bench.py times.
   in the full block, bit for bit: with the same iteration count under PCG,
   which freezes converged columns, and after the block's number of
   iterations under refinement, which keeps refining them.
+* 3D Poisson 128^3: the device PMIS hierarchy (the setup workload) and the
+  strong-lumping and Hybrid Galerkin post-passes (the lumping and methods
+  workloads) equal the oracle's bit for bit (Hybrid Galerkin's lumped
+  diagonal to 1e-13, the bar of diagonal lumping).
 """
 import numpy as np
 import pytest
@@ -127,3 +131,54 @@ def test_full_size_fv3d_192_16_rhs(lib):
         same = bool(np.array_equal(Xc[:, c].cpu().numpy(), Xh[:, c]))
         assert same, (method, c)
         assert torch.count_nonzero(Xc).item() == torch.count_nonzero(Xc[:, c]).item()
+
+
+def test_full_size_device_pmis_setup_128(lib):
+    """The setup workload: the device PMIS hierarchy of 3D Poisson 128^3
+    (seed 1) equals the oracle's bit for bit, level by level."""
+    from oracle import oracle as O
+    A = I.poisson3d(128)
+    print("device PMIS setup 128^3", flush=True)
+    g = lib.Hierarchy(A, setup="device", coarsening="pmis", seed=1)
+    print("oracle PMIS setup", flush=True)
+    o = O.OracleAMG(A, coarsening="pmis", seed=1)
+    assert g.nlev == o.nlev
+    for l in range(o.nlev):
+        for which in ("A", "P") if l < o.nlev - 1 else ("A",):
+            ga, oa = g.export(l, which), o.export(l, which)
+            assert np.array_equal(ga[2], oa.row_ptr) and np.array_equal(ga[3], oa.col), (l, which)
+            assert bool(np.array_equal(ga[4].view(np.uint64), oa.val.view(np.uint64))), (l, which)
+
+
+def test_full_size_strong_lumping_and_hybrid_128(lib):
+    """The lumping and methods workloads at 3D Poisson 128^3, gamma 0.1 on
+    levels >= 2: strong-neighbour lumping gives the oracle's sparsified
+    operators bit for bit; Hybrid Galerkin (diagonal lumping) the oracle's
+    minimal patterns, keep flags and sparsified patterns."""
+    from oracle import oracle as O
+    A = I.poisson3d(128)
+    g = lib.Hierarchy(A)
+    print("oracle setup 128^3", flush=True)
+    o = O.OracleAMG(A)
+    g.set_lumping("strong")
+    o.set_lumping("strong")
+    g.sparsify(0.1, 2)
+    o.sparsify_from(0.1, 2)
+    print("strong lumping compared", flush=True)
+    for l in range(2, o.nlev):
+        gh, oh = g.export(l, "AHAT"), o.export(l, "AHAT")
+        assert np.array_equal(gh[2], oh.row_ptr) and np.array_equal(gh[3], oh.col), l
+        assert bool(np.array_equal(gh[4].view(np.uint64), oh.val.view(np.uint64))), l
+    g.set_lumping("diagonal")
+    o.set_lumping("diagonal")
+    g.set_method(True)
+    o.set_method(True)
+    g.sparsify(0.1, 2)
+    o.sparsify_from(0.1, 2)
+    print("hybrid Galerkin compared", flush=True)
+    for l in range(2, o.nlev):
+        assert np.array_equal(g.mask(l, "M"), o.mask(l, "M")), l
+        assert np.array_equal(g.mask(l, "KEEP"), o.mask(l, "KEEP")), l
+        gh, oh = g.export(l, "AHAT"), o.export(l, "AHAT")
+        assert np.array_equal(gh[2], oh.row_ptr) and np.array_equal(gh[3], oh.col), l
+        assert np.allclose(gh[4], oh.val, rtol=1e-13, atol=0), l
