@@ -252,6 +252,20 @@ def main():
             log(f"[bench] {dom_kernel}@{dom_level} alone, {label}: {m3 / c3 * 1e3:.1f} us, {gbs:.0f} GB/s")
         del big, big2
 
+    # practical ceiling: a plain device-to-device copy of 1 GiB (read + written bytes / time)
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 10 * 2 * src.numel() * 8 / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del src, dst
+    log(f"[bench] device copy of 1 GiB: {copy_gbs:.0f} GB/s (read + write)")
+
     # SpMV bandwidth of the fine-level operator (the CG product A p)
     h.profile_enable(True, "SPMV_DOT", 0)
     step(args.gamma)
@@ -288,6 +302,8 @@ def main():
         "speedup_vs_galerkin": round(compare["0.0"]["ms_to_1e8"] / compare[str(args.gamma)]["ms_to_1e8"], 4)
         if str(args.gamma) in compare and "0.0" in compare else None,
         "spmv_gbs_level0": round(spmv_gbs, 1) if spmv_gbs else None,
+        "practical_ceiling": {"copy_gbs": round(copy_gbs, 1),
+                              "how": "1 GiB device-to-device copy, bytes read + written per second"},
         "roofline": {
             "bound": "hbm",
             "kernel": f"{dom_kernel} level {dom_level}",
