@@ -73,6 +73,27 @@ def launch_bytes(h, kernel: str, level: int) -> int:
     return 0
 
 
+def launch_bytes32(h, kernel: str, level: int) -> int:
+    """launch_bytes for the FP32 cycle: 4-byte values and vectors, the same
+    column indices."""
+    li = h.level_info(level)
+    n, nnz_hat, nc, nnz_p = li["n"], li["nnz_hat"], li["n_coarse"], li["nnz_P"]
+
+    def entry(which):
+        return 4 + h.index_width(level, which)
+
+    if kernel == "JACOBI":
+        return entry("AHAT") * nnz_hat + 4 * (n + 1) + 16 * n
+    if kernel in ("JACOBI_ZERO", "RESIDUAL"):
+        return entry("AHAT") * nnz_hat + 4 * (n + 1) + 12 * n
+    if kernel == "RESTRICT":
+        extra = 8 * nc if level + 2 < h.nlev else 0
+        return entry("R") * nnz_p + 4 * (nc + 1) + 4 * n + 4 * nc + extra
+    if kernel == "INTERP":
+        return entry("P") * nnz_p + 4 * (n + 1) + 4 * nc + 8 * n
+    return 0
+
+
 def kernel_source_sha(src: str = KERNEL_SRC) -> str:
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
 
@@ -883,13 +904,53 @@ def bench_aniso(args):
                                                       iters=res.iters, relres=res.relres,
                                                       reintroductions=res.reintroductions)
             log(f"[bench] gamma={gamma} fp{prec}: {ms:.2f} ms, {res.iters} iters, relres {res.relres:.2e}")
+    # dominant kernel of the FP32-cycle solve at gamma 0.1, timed with HIP events
+    h.sparsify(0.1, 2)
+
+    def solve32():
+        x.zero_()
+        return h.solve(b, x, precision=32, **kw)
+
+    h.profile_enable(True)
+    solve32()
+    dom = None
+    for kern in ("JACOBI", "JACOBI_ZERO", "RESIDUAL", "RESTRICT", "INTERP", "SPMV_DOT"):
+        for l in range(h.nlev):
+            c, ms = h.profile_read(kern, l)
+            if c and (dom is None or ms > dom[2]):
+                dom = (kern, l, ms)
+    h.profile_enable(False)
+    h.profile_enable(True, dom[0], dom[1])
+    for _ in range(args.steps):
+        solve32()
+    torch.cuda.synchronize()
+    cnt, ms_total = h.profile_read(dom[0], dom[1])
+    h.profile_enable(False)
+    # the outer product and residual stay FP64; the cycle's kernels are FP32
+    fp64_kernel = dom[0] == "SPMV_DOT" or (dom[0] == "RESIDUAL" and dom[1] == 0)
+    nbytes = launch_bytes(h, dom[0], dom[1]) if fp64_kernel else launch_bytes32(h, dom[0], dom[1])
+    per_launch_s = ms_total / max(cnt, 1) / 1e3
+    achieved = nbytes / per_launch_s / 1e9
+    log(f"[bench] FP32-cycle solve: dominant {dom[0]}@{dom[1]} ({'FP64' if fp64_kernel else 'FP32'}) "
+        f"{per_launch_s * 1e6:.1f} us, {achieved:.0f} GB/s")
+    roofline = {"bound": "hbm", "kernel": f"{dom[0]} level {dom[1]} ({'FP64' if fp64_kernel else 'FP32'})",
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "bytes_per_launch": nbytes,
+                "us_per_launch": round(per_launch_s * 1e6, 3), "launches": cnt}
+    cpu_baseline = None
     if not args.no_cpu_baseline:
         from oracle import oracle as O
         log("[bench] FP64 oracle solutions for the error report ...")
         o = O.OracleAMG(A)
         for gamma in (0.01, 0.1):
             o.sparsify_from(gamma, 2)
+            t0 = time.perf_counter()
             xo, ro = o.solve(b_host, method=O.PCG, tol=1e-10, maxit=500)
+            cpu_s = time.perf_counter() - t0
+            if gamma == 0.1:
+                cpu_baseline = {"value": round(1.0 / cpu_s, 5), "unit": "solves/s", "cores": 1, "kind": "oracle",
+                                "sample": f"one FP64 AMG-PCG solve to 1e-10 (gamma 0.1) of the same {N}^2 problem "
+                                          f"by the single-threaded C oracle, its setup excluded"}
             for prec in (64, 32):
                 d = results[f"gamma={gamma},fp{prec}"]
                 d["rel_err_vs_fp64_oracle"] = float(np.linalg.norm(sols[(gamma, prec)] - xo) / np.linalg.norm(xo))
@@ -908,7 +969,10 @@ def bench_aniso(args):
         "runs": results,
         "fp32_speedup_gamma0.1": round(results["gamma=0.1,fp64"]["ms"] / best["ms"], 4),
         "fp32_speedup_gamma0.01": round(results["gamma=0.01,fp64"]["ms"] / results["gamma=0.01,fp32"]["ms"], 4),
+        "roofline": roofline,
     }
+    if cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline
     h.close()
     print(json.dumps(out), flush=True)
 

@@ -82,3 +82,12 @@ def test_traffic_reported_only_for_the_measured_source(tmp_path):
     src.write_text("// kernel source, changed\n")
     assert bench.traffic_for("JACOBI", 1, str(counters), str(src)) is None
     assert bench.traffic_for("JACOBI", 1, str(tmp_path / "missing.json"), str(src)) is None
+
+
+def test_fp32_cycle_launch_bytes():
+    h = StubHierarchy({(1, "AHAT"): 2, (0, "R"): 2, (0, "P"): 2})
+    # 4-byte values and vectors, 2-byte indices where the level keeps them
+    assert bench.launch_bytes32(h, "JACOBI", 1) == 6 * 9000 + 4 * 501 + 16 * 500
+    assert bench.launch_bytes32(h, "JACOBI_ZERO", 1) == 6 * 9000 + 4 * 501 + 12 * 500
+    assert bench.launch_bytes32(h, "RESTRICT", 0) == 6 * 1800 + 4 * 501 + 4 * 1000 + 4 * 500 + 8 * 500
+    assert bench.launch_bytes32(h, "INTERP", 0) == 6 * 1800 + 4 * 1001 + 4 * 500 + 8 * 1000
