@@ -1290,6 +1290,41 @@ def bench_serve(args):
         "setup_s": round(setup_s, 2),
         "resident_gib": round(srv.device_bytes() / 2**30, 3),
     }
+    # the kernels the server runs, measured alone: the largest problem's engine with all 16 slots
+    # busy, FP32 cycle, iterations launched one by one so that HIP events can bracket them
+    srv.close_engines()
+    big = max(srv.hier, key=lambda k: srv.hier[k].n)
+    hb = srv.hier[big]
+    bt = hb.batch(16, 32, 1e-10, 300, graphs=False)
+    rhs16 = [torch.as_tensor(I.rhs(hb.n, 9000 + i)).cuda() for i in range(16)]
+    torch.cuda.synchronize()   # the copies ran on the default stream, the engine reads on its own
+    for t in rhs16:
+        bt.submit(t)
+    bt.step(2)
+    bt.poll(True)
+    hb.profile_enable(True)
+    bt.step(3)
+    bt.poll(True)
+    dom = None
+    for kern in ("JACOBI", "JACOBI_ZERO", "RESIDUAL", "RESTRICT", "INTERP", "SPMV_DOT"):
+        for l in range(hb.nlev):
+            c, ms = hb.profile_read(kern, l)
+            if c and (dom is None or ms > dom[2]):
+                dom = (kern, l, ms)
+    hb.profile_enable(True, dom[0], dom[1])
+    bt.step(8)
+    bt.poll(True)
+    cnt, ms_total = hb.profile_read(dom[0], dom[1])
+    hb.profile_enable(False)
+    bt.close()
+    nbytes = block_launch_bytes(hb, dom[0], dom[1], 16, 4)
+    per_launch_s = ms_total / max(cnt, 1) / 1e3
+    achieved = nbytes / per_launch_s / 1e9
+    log(f"[bench] {big} engine alone: dominant {dom[0]}@{dom[1]} {per_launch_s * 1e6:.1f} us, {achieved:.0f} GB/s")
+    out["roofline"] = {"bound": "hbm", "kernel": f"{dom[0]} level {dom[1]} (16-column block, {big})",
+                       "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "bytes_per_launch": nbytes,
+                       "us_per_launch": round(per_launch_s * 1e6, 3), "launches": cnt}
     if not args.no_cpu_baseline:
         from oracle import oracle as O
         log("[bench] CPU baseline: oracle PCG on the requests in order (setups untimed) ...")
