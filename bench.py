@@ -829,7 +829,7 @@ def bench_lumping(args):
         "compare": compare,
         "roofline": {
             "bound": "hbm",
-            "kernel": "strong_lump_kernel (shares)",
+            "kernel": "strong_lump_wide_kernel (shares)",
             "achieved": round(achieved, 2),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

@@ -555,12 +555,13 @@ void sparsify_levels(amg_ctx* h, const std::vector<std::pair<int, double>>& todo
                 launch_lump_threshold(c.n, a.rp, a.ci, a.v, h->sp.theta, c.lump_thr, h->stream);
                 {
                     ProfScope pd(h, AMG_K_LUMP_DEN, l);
-                    launch_lump_den(c.n, a.rp, a.ci, a.v, c.keep, c.lump_thr, c.lump_den, h->stream);
+                    launch_lump_den(c.n, a.rp, a.ci, a.v, c.keep, c.lump_thr, c.lump_den, a.view().mean_row,
+                                    h->stream);
                 }
                 {
                     ProfScope pl(h, AMG_K_LUMP_SHARES, l);
                     launch_strong_lump(c.n, a.rp, a.ci, a.v, c.keep, c.lump_thr, c.lump_den, c.Ahs.rp, c.Ahs.ci,
-                                       c.Ahs.v, h->stream);
+                                       c.Ahs.v, a.view().mean_row, h->stream);
                 }
                 launch_inverse_diagonal(c.Ahs.view(), c.dinv, h->fp32 ? c.dinv32 : nullptr, h->stream);
                 if (h->fp32) launch_narrow(c.A.nnz, c.Ahs32, c.Ahs.v, h->stream);   // capacity; past nnz unused

@@ -1,11 +1,14 @@
 // Strong-neighbour lumping kernels: every sum and share in the order the
 // definition fixes (ascending columns; shares of a target in ascending order
 // of their source entry), contraction off.  The threshold and the copy run
-// one thread per row, the denominators and the shares one wave per row.
+// one thread per row; the denominators and the shares a workgroup per row
+// with the row staged in LDS (rows longer than the stage, and a launch forced
+// to it, one wave per row).
 #include "lump_kernels.hpp"
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 
 #pragma clang fp contract(off)
 
@@ -15,6 +18,12 @@ namespace {
 
 constexpr int kLB = 256;
 constexpr int kWaves = kLB / 64;
+constexpr int kWideCap = 512;   // row entries a workgroup stages in LDS
+// mean entries per row from which a workgroup per row is used: every level
+// (it was the faster on every level of the 3D Poisson hierarchies measured,
+// 34 to 108 entries per row); a larger value, from the environment, selects
+// the one-wave kernels, which tests compare against
+constexpr double kWideMeanRow = 0.0;
 
 int grid_of(int n) { return std::max(1, std::min((n + kLB - 1) / kLB, 16384)); }
 int wave_grid_of(int n) { return std::max(1, std::min((n + kWaves - 1) / kWaves, 65536)); }
@@ -64,28 +73,102 @@ __global__ void lump_threshold_kernel(int n, const int32_t* __restrict__ rp, con
 #define WAVE_ROW_LOOP(i, n)                                                                         \
     for (int i = blockIdx.x * kWaves + (int)(threadIdx.x >> 6); i < (n); i += gridDim.x * kWaves)
 
+// den of every dropped entry of row i, one wave: a lane per dropped entry;
+// the strong neighbours m of j in ascending order are matched against the
+// ascending columns of row i by a merge walk
+__device__ inline void lump_den_row(int i, int lane, const int32_t* rp, const int32_t* ci, const double* v,
+                                    const uint8_t* keep, const double* thr, double* den) {
+    const int ib = rp[i], ie = rp[i + 1];
+    for (int p = ib + lane; p < ie; p += 64) {
+        const int j = ci[p];
+        if (j == i || keep[p]) continue;
+        double d = 0.0;
+        int w = ib;
+        for (int r = rp[j]; r < rp[j + 1]; ++r) {
+            if (!strong_at(ci, v, thr, j, r)) continue;
+            const int m = ci[r];
+            while (w < ie && ci[w] < m) ++w;
+            if (w < ie && ci[w] == m && keep[w]) d = d + fabs(v[r]);
+        }
+        den[p] = d;
+    }
+}
+
 __global__ void __launch_bounds__(kLB) lump_den_kernel(int n, const int32_t* __restrict__ rp,
                                                        const int32_t* __restrict__ ci,
                                                        const double* __restrict__ v,
                                                        const uint8_t* __restrict__ keep,
                                                        const double* __restrict__ thr, double* __restrict__ den) {
     const int lane = threadIdx.x & 63;
-    WAVE_ROW_LOOP(i, n) {
-        const int ib = rp[i], ie = rp[i + 1];
-        for (int p = ib + lane; p < ie; p += 64) {
-            const int j = ci[p];
-            if (j == i || keep[p]) continue;
-            // strong neighbours m of j in ascending order, matched against
-            // the ascending columns of row i by a merge walk
+    WAVE_ROW_LOOP(i, n) { lump_den_row(i, lane, rp, ci, v, keep, thr, den); }
+}
+
+// First position w in the ascending a[0..len) with a[w] >= col.
+__device__ inline int lower_bound_lds(const int32_t* a, int len, int col) {
+    int lo = 0, hi = len;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] < col) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Ordered sum of the lanes' x where has is set, in lane order, onto acc
+// (the same value in every lane).
+__device__ inline double ordered_add(double acc, bool has, double x) {
+    for (uint64_t mask = __ballot(has); mask != 0; mask &= mask - 1) acc = acc + __shfl(x, __builtin_ctzll(mask));
+    return acc;
+}
+
+// Rows with many entries: one workgroup per row i, its columns and keep flags
+// staged in LDS; each wave takes a dropped entry (i,j) at a time, its lanes
+// over the entries of row j (coalesced), and finds m among the staged columns
+// by a binary search in LDS; the wave adds the terms in lane order, which is
+// ascending m.  Rows longer than the stage take the one-wave path.
+__global__ void __launch_bounds__(kLB) lump_den_wide_kernel(int n, const int32_t* __restrict__ rp,
+                                                            const int32_t* __restrict__ ci,
+                                                            const double* __restrict__ v,
+                                                            const uint8_t* __restrict__ keep,
+                                                            const double* __restrict__ thr,
+                                                            double* __restrict__ den) {
+    __shared__ int32_t sc[kWideCap];
+    __shared__ uint8_t sk[kWideCap];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    for (int i = blockIdx.x; i < n; i += gridDim.x) {
+        const int ib = rp[i], ie = rp[i + 1], len = ie - ib;
+        if (len > kWideCap) {
+            if (wave == 0) lump_den_row(i, lane, rp, ci, v, keep, thr, den);
+            continue;
+        }
+        __syncthreads();   // the previous row's readers are done
+        for (int t = threadIdx.x; t < len; t += kLB) {
+            sc[t] = ci[ib + t];
+            sk[t] = keep[ib + t];
+        }
+        __syncthreads();
+        for (int u = wave; u < len; u += kWaves) {
+            const int j = sc[u];
+            if (j == i || sk[u]) continue;
+            const int jb = rp[j], je = rp[j + 1];
+            const double t = thr[j];
             double d = 0.0;
-            int w = ib;
-            for (int r = rp[j]; r < rp[j + 1]; ++r) {
-                if (!strong_at(ci, v, thr, j, r)) continue;
-                const int m = ci[r];
-                while (w < ie && ci[w] < m) ++w;
-                if (w < ie && ci[w] == m && keep[w]) d = d + fabs(v[r]);
+            for (int r0 = jb; r0 < je; r0 += 64) {
+                const int r = r0 + lane;
+                bool has = false;
+                double a = 0.0;
+                if (r < je && t > 0.0) {
+                    const int m = ci[r];
+                    a = v[r];
+                    if (m != j && -a >= t) {
+                        const int w = lower_bound_lds(sc, len, m);
+                        has = w < len && sc[w] == m && sk[w];
+                    }
+                }
+                d = ordered_add(d, has, fabs(a));
             }
-            den[p] = d;
+            if (lane == 0) den[ib + u] = d;
         }
     }
 }
@@ -127,6 +210,63 @@ __device__ inline double pull_row(const int32_t* rp, const int32_t* ci, const do
 // of 64 entries of a source row at a time and the wave adds the chunk's
 // shares in lane order.  Requires a bitwise symmetric operator (every
 // Galerkin and non-Galerkin coarse operator is).
+__device__ inline void strong_lump_row(int k, int lane, const int32_t* rp, const int32_t* ci, const double* v,
+                                       const uint8_t* keep, const double* thr, const double* den,
+                                       const int32_t* hrp, const int32_t* hci, double* hv) {
+    const int hb = hrp[k], he = hrp[k + 1];
+    for (int t = hb + lane; t < he; t += 64) {
+        const int m = hci[t];
+        if (m <= k) continue;
+        double acc = pull_row(rp, ci, v, keep, thr, den, k, m, hv[t]);
+        acc = pull_row(rp, ci, v, keep, thr, den, m, k, acc);
+        hv[t] = acc;
+        const int tm = find_in_row(hci, hrp[m], hrp[m + 1], k);
+        if (tm >= 0) hv[tm] = acc;   // always found: the kept pattern is symmetric
+    }
+    const int dk = find_in_row(hci, hb, he, k);
+    if (dk < 0) return;   // every operator stores its diagonal; never taken (uniform over the wave)
+    const int kb = rp[k], ke = rp[k + 1];
+    double acc = hv[dk];
+    for (int p = hb; p < he; ++p) {
+        const int s = hci[p];
+        const int sb = rp[s], se = rp[s + 1];
+        for (int q0 = sb; q0 < se; q0 += 64) {
+            const int q = q0 + lane;
+            bool has = false;
+            double c = 0.0;
+            if (q < se && !keep[q]) {
+                const int j = ci[q];
+                const double d = den[q];
+                if (j != s && s == k) {
+                    if (d == 0.0) {
+                        c = v[q];   // no strong neighbour kept: the whole entry
+                        has = true;
+                    } else {
+                        // the share to k itself, with a_jk = a_kj
+                        const double t = thr[j], a = v[q];
+                        if (t > 0.0 && -a >= t) {
+                            c = (fabs(a) / d) * a;
+                            has = true;
+                        }
+                    }
+                } else if (j != s && d != 0.0) {
+                    // the share of (s,j) to k, with a_jk read as a_kj from row k
+                    const int r = find_in_row(ci, kb, ke, j);
+                    if (r >= 0) {
+                        const double t = thr[j], a = v[r];
+                        if (t > 0.0 && -a >= t) {
+                            c = -((fabs(a) / d) * v[q]);   // a - c == a + (-c) exactly
+                            has = true;
+                        }
+                    }
+                }
+            }
+            acc = ordered_add(acc, has, c);
+        }
+    }
+    if (lane == 0) hv[dk] = acc;
+}
+
 __global__ void __launch_bounds__(kLB) strong_lump_kernel(int n, const int32_t* __restrict__ rp,
                                                           const int32_t* __restrict__ ci,
                                                           const double* __restrict__ v,
@@ -137,60 +277,225 @@ __global__ void __launch_bounds__(kLB) strong_lump_kernel(int n, const int32_t* 
                                                           const int32_t* __restrict__ hci,
                                                           double* __restrict__ hv) {
     const int lane = threadIdx.x & 63;
-    WAVE_ROW_LOOP(k, n) {
-        const int hb = hrp[k], he = hrp[k + 1];
-        for (int t = hb + lane; t < he; t += 64) {
-            const int m = hci[t];
-            if (m <= k) continue;
-            double acc = pull_row(rp, ci, v, keep, thr, den, k, m, hv[t]);
-            acc = pull_row(rp, ci, v, keep, thr, den, m, k, acc);
-            hv[t] = acc;
-            const int tm = find_in_row(hci, hrp[m], hrp[m + 1], k);
-            if (tm >= 0) hv[tm] = acc;   // always found: the kept pattern is symmetric
+    WAVE_ROW_LOOP(k, n) { strong_lump_row(k, lane, rp, ci, v, keep, thr, den, hrp, hci, hv); }
+}
+
+// Rows with many entries: one workgroup per row k, row k of A (columns,
+// values, keep flags, denominators, and the thresholds of its columns)
+// staged in LDS.
+// * (k,m), m > k, one wave each, its lanes over row m (coalesced): a lane
+//   finds its column j in the staged row k by a binary search in LDS and
+//   forms the share of dropped (k,j) (with a_jm read as a_mj); the wave adds
+//   them in lane order, then, in a second pass, the shares of dropped (m,j)
+//   (a_jk read as a_kj).  Every share needs j in row k, so its threshold is
+//   a staged one.  Same terms, same order as the one-wave path.
+// * the diagonal: the kept rows s of row k are laid end to end (offsets by a
+//   scan), the workgroup computes kDiagPer x 256 consecutive entries' shares
+//   at a time into LDS (a_kj by a binary search of the staged row k) and the
+//   first wave adds them in order.
+// Rows longer than the stage take the one-wave path.
+constexpr int kDiagPer = 2;
+
+__global__ void __launch_bounds__(kLB) strong_lump_wide_kernel(int n, const int32_t* __restrict__ rp,
+                                                               const int32_t* __restrict__ ci,
+                                                               const double* __restrict__ v,
+                                                               const uint8_t* __restrict__ keep,
+                                                               const double* __restrict__ thr,
+                                                               const double* __restrict__ den,
+                                                               const int32_t* __restrict__ hrp,
+                                                               const int32_t* __restrict__ hci,
+                                                               double* __restrict__ hv) {
+    __shared__ int32_t kc[kWideCap];
+    __shared__ double kv[kWideCap];
+    __shared__ double kd[kWideCap];
+    __shared__ double kt[kWideCap];         // thr of the columns of row k
+    __shared__ uint8_t kk[kWideCap];
+    __shared__ int32_t ks[kWideCap];        // the kept columns s of row k
+    __shared__ int32_t sb[kWideCap];        // rp[s]
+    __shared__ int32_t off[kWideCap + 1];   // their rows' offsets, end to end
+    __shared__ double slot_c[kDiagPer * kLB];
+    __shared__ uint8_t slot_h[kDiagPer * kLB];
+    __shared__ int wsum[kWaves];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    for (int k = blockIdx.x; k < n; k += gridDim.x) {
+        const int kb = rp[k], ke = rp[k + 1], len = ke - kb;
+        if (len > kWideCap) {
+            if (wave == 0) strong_lump_row(k, lane, rp, ci, v, keep, thr, den, hrp, hci, hv);
+            continue;
         }
-        const int dk = find_in_row(hci, hb, he, k);
-        if (dk < 0) continue;   // every operator stores its diagonal; never taken (uniform over the wave)
-        const int kb = rp[k], ke = rp[k + 1];
-        double acc = hv[dk];
-        for (int p = hb; p < he; ++p) {
-            const int s = hci[p];
-            const int sb = rp[s], se = rp[s + 1];
-            for (int q0 = sb; q0 < se; q0 += 64) {
+        const int hb = hrp[k], he = hrp[k + 1], nk = he - hb;   // nk <= len
+        __syncthreads();   // the previous row's readers are done
+        for (int t = threadIdx.x; t < len; t += kLB) {
+            const int p = kb + t;
+            const int j = ci[p];
+            kc[t] = j;
+            kv[t] = v[p];
+            kk[t] = keep[p];
+            kd[t] = keep[p] ? 0.0 : den[p];   // den is written for dropped entries only
+            kt[t] = thr[j];
+        }
+        // kept columns and their row lengths, scanned end to end
+        int carry = 0;
+        for (int base = 0; base < nk; base += kLB) {
+            const int idx = base + (int)threadIdx.x;
+            int x = 0;
+            if (idx < nk) {
+                const int s = hci[hb + idx];
+                const int s0 = rp[s];
+                ks[idx] = s;
+                sb[idx] = s0;
+                x = rp[s + 1] - s0;
+            }
+            int incl = x;
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(incl, o);
+                if (lane >= o) incl += y;
+            }
+            if (lane == 63) wsum[wave] = incl;
+            __syncthreads();
+            int before = 0, total = 0;
+            for (int w = 0; w < kWaves; ++w) {
+                before += w < wave ? wsum[w] : 0;
+                total += wsum[w];
+            }
+            if (idx < nk) off[idx] = carry + before + incl - x;
+            carry += total;
+            __syncthreads();   // wsum is reused
+        }
+        if (threadIdx.x == 0) off[nk] = carry;
+        __syncthreads();
+        const int dpos = lower_bound_lds(ks, nk, k);
+        if (dpos >= nk || ks[dpos] != k) continue;   // every operator stores its diagonal; never taken
+        const int dk = hb + dpos;
+        // off-diagonals (k,m), m > k: a wave per target, its lanes over row m;
+        // the terms of dropped (k,j) first, then those of dropped (m,j), each
+        // in ascending j (lane order)
+        for (int t = dk + 1 + wave; t < he; t += kWaves) {
+            const int m = ks[t - hb];
+            const int mb = sb[t - hb], me = mb + off[t - hb + 1] - off[t - hb];
+            double acc = hv[t];
+            for (int r0 = mb; r0 < me; r0 += 64) {   // (k,j) dropped, (j,m) strong: a_jm read as a_mj
+                const int r = r0 + lane;
+                bool has = false;
+                double c = 0.0;
+                if (r < me) {
+                    const int j = ci[r];
+                    const double ajm = v[r];
+                    const int w = lower_bound_lds(kc, len, j);
+                    if (w < len && kc[w] == j && j != k && !kk[w]) {
+                        const double th = kt[w];
+                        if (th > 0.0 && -ajm >= th) {
+                            c = (fabs(ajm) / kd[w]) * kv[w];
+                            has = true;
+                        }
+                    }
+                }
+                acc = ordered_add(acc, has, c);
+            }
+            for (int q0 = mb; q0 < me; q0 += 64) {   // (m,j) dropped, (j,k) strong: a_jk read as a_kj
                 const int q = q0 + lane;
                 bool has = false;
                 double c = 0.0;
-                if (q < se && !keep[q]) {
+                if (q < me) {
                     const int j = ci[q];
-                    const double d = den[q];
+                    if (j != m && !keep[q]) {
+                        const int w = lower_bound_lds(kc, len, j);
+                        if (w < len && kc[w] == j) {
+                            const double th = kt[w], a = kv[w];
+                            if (th > 0.0 && -a >= th) {
+                                c = (fabs(a) / den[q]) * v[q];
+                                has = true;
+                            }
+                        }
+                    }
+                }
+                acc = ordered_add(acc, has, c);
+            }
+            // (m,k): the same value; its position by a coalesced search of row m
+            const int hm0 = hrp[m], hm1 = hrp[m + 1];
+            int tm = -1;
+            for (int c0 = hm0; c0 < hm1 && tm < 0; c0 += 64) {
+                const int idx = c0 + lane;
+                const uint64_t hit = __ballot(idx < hm1 && hci[idx] == k);
+                if (hit) tm = c0 + __builtin_ctzll(hit);
+            }
+            if (lane == 0) {
+                hv[t] = acc;
+                if (tm >= 0) hv[tm] = acc;   // always found: the kept pattern is symmetric
+            }
+        }
+        // the diagonal
+        double acc = hv[dk];
+        const int total = off[nk];
+        for (int g = 0; g < total; g += kDiagPer * kLB) {
+            int qq[kDiagPer], ss[kDiagPer];
+#pragma unroll
+            for (int e = 0; e < kDiagPer; ++e) {
+                const int f = g + e * kLB + (int)threadIdx.x;
+                qq[e] = -1;
+                ss[e] = 0;
+                if (f < total) {
+                    int lo = 0, hi = nk;   // off[lo] <= f < off[lo + 1]
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (off[mid] <= f) lo = mid;
+                        else hi = mid;
+                    }
+                    ss[e] = ks[lo];
+                    qq[e] = sb[lo] + (f - off[lo]);
+                }
+            }
+            int jj[kDiagPer];
+            uint8_t kp[kDiagPer];
+            double dd[kDiagPer], aa[kDiagPer];
+#pragma unroll
+            for (int e = 0; e < kDiagPer; ++e) {
+                const int q = qq[e] < 0 ? kb : qq[e];   // a valid entry; unused when qq < 0
+                jj[e] = ci[q];
+                kp[e] = keep[q];
+                dd[e] = den[q];
+                aa[e] = v[q];
+            }
+#pragma unroll
+            for (int e = 0; e < kDiagPer; ++e) {
+                bool has = false;
+                double c = 0.0;
+                if (qq[e] >= 0 && !kp[e]) {
+                    const int s = ss[e], j = jj[e];
+                    const double d = dd[e];
                     if (j != s && s == k) {
                         if (d == 0.0) {
-                            c = v[q];   // no strong neighbour kept: the whole entry
+                            c = aa[e];   // no strong neighbour kept: the whole entry
                             has = true;
                         } else {
-                            // the share to k itself, with a_jk = a_kj
-                            const double t = thr[j], a = v[q];
+                            const double t = kt[qq[e] - kb], a = aa[e];   // the share to k itself, a_jk = a_kj
                             if (t > 0.0 && -a >= t) {
                                 c = (fabs(a) / d) * a;
                                 has = true;
                             }
                         }
                     } else if (j != s && d != 0.0) {
-                        // the share of (s,j) to k, with a_jk read as a_kj from row k
-                        const int r = find_in_row(ci, kb, ke, j);
-                        if (r >= 0) {
-                            const double t = thr[j], a = v[r];
+                        const int r = lower_bound_lds(kc, len, j);
+                        if (r < len && kc[r] == j) {
+                            const double t = kt[r], a = kv[r];
                             if (t > 0.0 && -a >= t) {
-                                c = -((fabs(a) / d) * v[q]);   // a - c == a + (-c) exactly
+                                c = -((fabs(a) / d) * aa[e]);   // a - c == a + (-c) exactly
                                 has = true;
                             }
                         }
                     }
                 }
-                for (uint64_t mask = __ballot(has); mask != 0; mask &= mask - 1)
-                    acc = acc + __shfl(c, __builtin_ctzll(mask));
+                slot_c[e * kLB + threadIdx.x] = c;
+                slot_h[e * kLB + threadIdx.x] = has ? 1 : 0;
             }
+            __syncthreads();
+            if (wave == 0)
+                for (int w = 0; w < kDiagPer * kWaves; ++w)
+                    acc = ordered_add(acc, slot_h[w * 64 + lane] != 0, slot_c[w * 64 + lane]);
+            __syncthreads();   // the slots are reused
         }
-        if (lane == 0) hv[dk] = acc;
+        if (threadIdx.x == 0) hv[dk] = acc;
     }
 }
 
@@ -207,16 +512,36 @@ void launch_lump_threshold(int n, const int32_t* rp, const int32_t* ci, const do
     hipLaunchKernelGGL(lump_threshold_kernel, dim3(grid_of(n)), dim3(kLB), 0, st, n, rp, ci, v, theta, thr);
 }
 
+namespace {
+
+bool use_wide(double mean_row) {
+    const char* e = std::getenv("AMG_LUMP_WIDE_ROW");
+    const double lim = e ? std::atof(e) : kWideMeanRow;
+    return mean_row >= lim;
+}
+
+int row_grid_of(int n) { return std::max(1, std::min(n, 65536)); }
+
+}  // namespace
+
 void launch_lump_den(int n, const int32_t* rp, const int32_t* ci, const double* v, const uint8_t* keep,
-                     const double* thr, double* den, hipStream_t st) {
-    hipLaunchKernelGGL(lump_den_kernel, dim3(wave_grid_of(n)), dim3(kLB), 0, st, n, rp, ci, v, keep, thr, den);
+                     const double* thr, double* den, double mean_row, hipStream_t st) {
+    if (use_wide(mean_row))
+        hipLaunchKernelGGL(lump_den_wide_kernel, dim3(row_grid_of(n)), dim3(kLB), 0, st, n, rp, ci, v, keep, thr,
+                           den);
+    else
+        hipLaunchKernelGGL(lump_den_kernel, dim3(wave_grid_of(n)), dim3(kLB), 0, st, n, rp, ci, v, keep, thr, den);
 }
 
 void launch_strong_lump(int n, const int32_t* rp, const int32_t* ci, const double* v, const uint8_t* keep,
                         const double* thr, const double* den, const int32_t* hrp, const int32_t* hci, double* hv,
-                        hipStream_t st) {
-    hipLaunchKernelGGL(strong_lump_kernel, dim3(wave_grid_of(n)), dim3(kLB), 0, st, n, rp, ci, v, keep, thr, den, hrp,
-                       hci, hv);
+                        double mean_row, hipStream_t st) {
+    if (use_wide(mean_row))
+        hipLaunchKernelGGL(strong_lump_wide_kernel, dim3(row_grid_of(n)), dim3(kLB), 0, st, n, rp, ci, v, keep, thr,
+                           den, hrp, hci, hv);
+    else
+        hipLaunchKernelGGL(strong_lump_kernel, dim3(wave_grid_of(n)), dim3(kLB), 0, st, n, rp, ci, v, keep, thr, den,
+                           hrp, hci, hv);
 }
 
 }  // namespace amg355

@@ -24,11 +24,15 @@ void launch_lump_threshold(int n, const int32_t* rp, const int32_t* ci, const do
 // den[p] for every dropped off-diagonal entry p = (i,j): the sum, in
 // ascending m, of |a_jm| over m strong for j and kept in row i (0: none)
 void launch_lump_den(int n, const int32_t* rp, const int32_t* ci, const double* v, const uint8_t* keep,
-                     const double* thr, double* den, hipStream_t st);
+                     const double* thr, double* den, double mean_row, hipStream_t st);
 // adds every row's shares to the copied kept entries hrp / hci / hv; a must
-// be bitwise symmetric with a symmetric keep set (a_jm is read as a_mj)
+// be bitwise symmetric with a symmetric keep set (a_jm is read as a_mj).
+// Both launches run a workgroup per row with the row staged in LDS, or one
+// wave per row when mean_row (nnz / n) is below the threshold that the
+// environment variable AMG_LUMP_WIDE_ROW sets (default 0: never): the same
+// bits either way.
 void launch_strong_lump(int n, const int32_t* rp, const int32_t* ci, const double* v, const uint8_t* keep,
                         const double* thr, const double* den, const int32_t* hrp, const int32_t* hci, double* hv,
-                        hipStream_t st);
+                        double mean_row, hipStream_t st);
 
 }  // namespace amg355

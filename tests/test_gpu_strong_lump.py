@@ -1,8 +1,11 @@
 """Strong-neighbour lumping (Algorithm 3, second loop) on the device against
 the oracle.  Every entry of a sparsified operator is its Galerkin value plus
-its shares added in ascending order of their source entry, one thread per
-row on the device, so the operators agree bit for bit, diagonal included.
-Solves: equal iteration counts, solution within 1e-10."""
+its shares added in ascending order of their source entry, on the device as
+in the oracle, so the operators agree bit for bit, diagonal included; this
+holds for both launch shapes (a wave per row, and a workgroup per row with
+the row staged in LDS, whose rows longer than the stage go the one-wave
+way), each forced in turn.  Solves: equal iteration counts, solution within
+1e-10."""
 import numpy as np
 import pytest
 
@@ -50,6 +53,39 @@ def test_sparsify_bitwise(lib, name, gamma, hybrid):
     A = PROBLEMS[name]()
     g, o = pair(A, hybrid)
     gam = [0.0] + [gamma] * (o.nlev - 1)
+    g.sparsify_levels(gam)
+    o.sparsify(gam)
+    same_operators(g, o)
+
+
+FORCE = {"wave": "1e300", "workgroup": "0"}
+
+
+@pytest.mark.parametrize("name", sorted(PROBLEMS))
+@pytest.mark.parametrize("path", sorted(FORCE))
+def test_both_launch_shapes_bitwise(lib, monkeypatch, name, path):
+    monkeypatch.setenv("AMG_LUMP_WIDE_ROW", FORCE[path])
+    A = PROBLEMS[name]()
+    g, o = pair(A)
+    gam = [0.0] + [0.1] * (o.nlev - 1)
+    g.sparsify_levels(gam)
+    o.sparsify(gam)
+    same_operators(g, o)
+
+
+@pytest.mark.parametrize("path", ["default", "wave"])
+def test_rows_longer_than_the_stage(lib, monkeypatch, path):
+    """A graph whose first coarse level has 571 nearly full rows: 554 longer
+    than the 512 entries a workgroup stages, 17 shorter, so one launch takes
+    both branches of the workgroup-per-row kernels."""
+    if path == "wave":
+        monkeypatch.setenv("AMG_LUMP_WIDE_ROW", FORCE["wave"])
+    A = I.random_graph_laplacian(4500, degree=12)
+    g, o = pair(A)
+    a = o.export(1, "A")
+    lens = np.diff(a.row_ptr)
+    assert (lens > 512).sum() > 0 and (lens <= 512).sum() > 0
+    gam = [0.0, 0.1]
     g.sparsify_levels(gam)
     o.sparsify(gam)
     same_operators(g, o)
