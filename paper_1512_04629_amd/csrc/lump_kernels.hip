@@ -374,46 +374,63 @@ __global__ void __launch_bounds__(kLB) strong_lump_wide_kernel(int n, const int3
         for (int t = dk + 1 + wave; t < he; t += kWaves) {
             const int m = ks[t - hb];
             const int mb = sb[t - hb], me = mb + off[t - hb + 1] - off[t - hb];
+            // every load of the first 64 entries of row m, issued together (a
+            // kept entry's den is never written and is not used)
+            const int hm0 = hrp[m], hm1 = hrp[m + 1];
             double acc = hv[t];
-            for (int r0 = mb; r0 < me; r0 += 64) {   // (k,j) dropped, (j,m) strong: a_jm read as a_mj
-                const int r = r0 + lane;
+            const int r0 = min(mb + lane, me - 1);
+            const int j0 = ci[r0];
+            const double a0 = v[r0], d0 = den[r0];
+            const uint8_t kp0 = keep[r0];
+            const int w0 = lower_bound_lds(kc, len, j0);
+            const bool at0 = w0 < len && kc[w0] == j0;   // j0 in row k
+            for (int c0 = mb; c0 < me; c0 += 64) {   // (k,j) dropped, (j,m) strong: a_jm read as a_mj
+                int j = j0, w = w0;
+                double ajm = a0;
+                bool at = at0;
+                if (c0 != mb) {
+                    const int r = min(c0 + lane, me - 1);
+                    j = ci[r];
+                    ajm = v[r];
+                    w = lower_bound_lds(kc, len, j);
+                    at = w < len && kc[w] == j;
+                }
                 bool has = false;
                 double c = 0.0;
-                if (r < me) {
-                    const int j = ci[r];
-                    const double ajm = v[r];
-                    const int w = lower_bound_lds(kc, len, j);
-                    if (w < len && kc[w] == j && j != k && !kk[w]) {
-                        const double th = kt[w];
-                        if (th > 0.0 && -ajm >= th) {
-                            c = (fabs(ajm) / kd[w]) * kv[w];
-                            has = true;
-                        }
+                if (c0 + lane < me && at && j != k && !kk[w]) {
+                    const double th = kt[w];
+                    if (th > 0.0 && -ajm >= th) {
+                        c = (fabs(ajm) / kd[w]) * kv[w];
+                        has = true;
                     }
                 }
                 acc = ordered_add(acc, has, c);
             }
-            for (int q0 = mb; q0 < me; q0 += 64) {   // (m,j) dropped, (j,k) strong: a_jk read as a_kj
-                const int q = q0 + lane;
+            for (int c0 = mb; c0 < me; c0 += 64) {   // (m,j) dropped, (j,k) strong: a_jk read as a_kj
+                int j = j0, w = w0;
+                double a = a0, d = d0;
+                bool at = at0, kp = kp0 != 0;
+                if (c0 != mb) {
+                    const int q = min(c0 + lane, me - 1);
+                    j = ci[q];
+                    a = v[q];
+                    d = den[q];
+                    kp = keep[q] != 0;
+                    w = lower_bound_lds(kc, len, j);
+                    at = w < len && kc[w] == j;
+                }
                 bool has = false;
                 double c = 0.0;
-                if (q < me) {
-                    const int j = ci[q];
-                    if (j != m && !keep[q]) {
-                        const int w = lower_bound_lds(kc, len, j);
-                        if (w < len && kc[w] == j) {
-                            const double th = kt[w], a = kv[w];
-                            if (th > 0.0 && -a >= th) {
-                                c = (fabs(a) / den[q]) * v[q];
-                                has = true;
-                            }
-                        }
+                if (c0 + lane < me && j != m && !kp && at) {
+                    const double th = kt[w], akj = kv[w];
+                    if (th > 0.0 && -akj >= th) {
+                        c = (fabs(akj) / d) * a;
+                        has = true;
                     }
                 }
                 acc = ordered_add(acc, has, c);
             }
             // (m,k): the same value; its position by a coalesced search of row m
-            const int hm0 = hrp[m], hm1 = hrp[m + 1];
             int tm = -1;
             for (int c0 = hm0; c0 < hm1 && tm < 0; c0 += 64) {
                 const int idx = c0 + lane;
