@@ -1,7 +1,7 @@
 // Strong-neighbour lumping kernels: every sum and share in the order the
 // definition fixes (ascending columns; shares of a target in ascending order
 // of their source entry), contraction off.  The threshold and the copy run
-// one thread per row; the denominators and the shares a workgroup per row
+// one wave per row; the denominators and the shares a workgroup per row
 // with the row staged in LDS (rows longer than the stage, and a launch forced
 // to it, one wave per row).
 #include "lump_kernels.hpp"
@@ -25,10 +25,7 @@ constexpr int kWideCap = 512;   // row entries a workgroup stages in LDS
 // the one-wave kernels, which tests compare against
 constexpr double kWideMeanRow = 0.0;
 
-int grid_of(int n) { return std::max(1, std::min((n + kLB - 1) / kLB, 16384)); }
 int wave_grid_of(int n) { return std::max(1, std::min((n + kWaves - 1) / kWaves, 65536)); }
-
-#define ROW_LOOP(i, n) for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += gridDim.x * blockDim.x)
 
 __device__ inline int find_in_row(const int32_t* ci, int b, int e, int col) {
     int lo = b, hi = e;
@@ -44,34 +41,55 @@ __device__ inline bool strong_at(const int32_t* ci, const double* v, const doubl
     return ci[r] != j && thr[j] > 0.0 && -v[r] >= thr[j];
 }
 
-__global__ void compact_copy_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                                    const double* __restrict__ v, const uint8_t* __restrict__ keep,
-                                    const int32_t* __restrict__ new_rp, int32_t* __restrict__ new_ci,
-                                    double* __restrict__ new_v) {
-    ROW_LOOP(i, n) {
-        int w = new_rp[i];
-        for (int p = rp[i]; p < rp[i + 1]; ++p)
-            if (keep[p]) {
-                new_ci[w] = ci[p];
-                new_v[w] = v[p];
-                ++w;
-            }
-    }
-}
-
-__global__ void lump_threshold_kernel(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                                      const double* __restrict__ v, double theta, double* __restrict__ thr) {
-    ROW_LOOP(j, n) {
-        double big = 0.0;
-        for (int p = rp[j]; p < rp[j + 1]; ++p)
-            if (ci[p] != j && -v[p] > big) big = -v[p];
-        thr[j] = big > 0.0 ? theta * big : -1.0;
-    }
-}
-
 // one wave per row i (kWaves per workgroup), lanes over the row's entries
 #define WAVE_ROW_LOOP(i, n)                                                                         \
     for (int i = blockIdx.x * kWaves + (int)(threadIdx.x >> 6); i < (n); i += gridDim.x * kWaves)
+
+// one wave per row: the kept entries of each 64-entry chunk go to the next
+// free places in order (ballot, count of the lower lanes' kept entries)
+__global__ void __launch_bounds__(kLB) compact_copy_kernel(int n, const int32_t* __restrict__ rp,
+                                                           const int32_t* __restrict__ ci,
+                                                           const double* __restrict__ v,
+                                                           const uint8_t* __restrict__ keep,
+                                                           const int32_t* __restrict__ new_rp,
+                                                           int32_t* __restrict__ new_ci, double* __restrict__ new_v) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = (1ull << lane) - 1;
+    WAVE_ROW_LOOP(i, n) {
+        const int ie = rp[i + 1];
+        int w = new_rp[i];
+        for (int p0 = rp[i]; p0 < ie; p0 += 64) {
+            const int p = p0 + lane;
+            const bool kp = p < ie && keep[p];
+            const uint64_t mask = __ballot(kp);
+            if (kp) {
+                const int at = w + __popcll(mask & below);
+                new_ci[at] = ci[p];
+                new_v[at] = v[p];
+            }
+            w += __popcll(mask);
+        }
+    }
+}
+
+// one wave per row: the largest -a_jm off the diagonal (a maximum, the same
+// in any order)
+__global__ void __launch_bounds__(kLB) lump_threshold_kernel(int n, const int32_t* __restrict__ rp,
+                                                             const int32_t* __restrict__ ci,
+                                                             const double* __restrict__ v, double theta,
+                                                             double* __restrict__ thr) {
+    const int lane = threadIdx.x & 63;
+    WAVE_ROW_LOOP(j, n) {
+        double big = 0.0;
+        for (int p = rp[j] + lane; p < rp[j + 1]; p += 64)
+            if (ci[p] != j && -v[p] > big) big = -v[p];
+        for (int o = 32; o > 0; o >>= 1) {
+            const double other = __shfl_xor(big, o);
+            if (other > big) big = other;
+        }
+        if (lane == 0) thr[j] = big > 0.0 ? theta * big : -1.0;
+    }
+}
 
 // den of every dropped entry of row i, one wave: a lane per dropped entry;
 // the strong neighbours m of j in ascending order are matched against the
@@ -520,13 +538,13 @@ __global__ void __launch_bounds__(kLB) strong_lump_wide_kernel(int n, const int3
 
 void launch_compact_copy(int n, const int32_t* rp, const int32_t* ci, const double* v, const uint8_t* keep,
                          const int32_t* new_rp, int32_t* new_ci, double* new_v, hipStream_t st) {
-    hipLaunchKernelGGL(compact_copy_kernel, dim3(grid_of(n)), dim3(kLB), 0, st, n, rp, ci, v, keep, new_rp, new_ci,
-                       new_v);
+    hipLaunchKernelGGL(compact_copy_kernel, dim3(wave_grid_of(n)), dim3(kLB), 0, st, n, rp, ci, v, keep, new_rp,
+                       new_ci, new_v);
 }
 
 void launch_lump_threshold(int n, const int32_t* rp, const int32_t* ci, const double* v, double theta,
                            double* thr, hipStream_t st) {
-    hipLaunchKernelGGL(lump_threshold_kernel, dim3(grid_of(n)), dim3(kLB), 0, st, n, rp, ci, v, theta, thr);
+    hipLaunchKernelGGL(lump_threshold_kernel, dim3(wave_grid_of(n)), dim3(kLB), 0, st, n, rp, ci, v, theta, thr);
 }
 
 namespace {
