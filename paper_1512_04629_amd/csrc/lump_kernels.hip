@@ -18,7 +18,7 @@ namespace {
 
 constexpr int kLB = 256;
 constexpr int kWaves = kLB / 64;
-constexpr int kWideCap = 512;   // row entries a workgroup stages in LDS
+constexpr int kWideCap = 256;   // row entries a workgroup stages in LDS (15 KB: eight workgroups a CU)
 // mean entries per row from which a workgroup per row is used: every level
 // (it was the faster on every level of the 3D Poisson hierarchies measured,
 // 34 to 108 entries per row); a larger value, from the environment, selects

@@ -75,16 +75,16 @@ def test_both_launch_shapes_bitwise(lib, monkeypatch, name, path):
 
 @pytest.mark.parametrize("path", ["default", "wave"])
 def test_rows_longer_than_the_stage(lib, monkeypatch, path):
-    """A graph whose first coarse level has 571 nearly full rows: 554 longer
-    than the 512 entries a workgroup stages, 17 shorter, so one launch takes
-    both branches of the workgroup-per-row kernels."""
+    """A graph whose first coarse level has 259 nearly full rows: 148 longer
+    than the 256 entries a workgroup stages, 111 not, so one launch takes both
+    branches of the workgroup-per-row kernels."""
     if path == "wave":
         monkeypatch.setenv("AMG_LUMP_WIDE_ROW", FORCE["wave"])
-    A = I.random_graph_laplacian(4500, degree=12)
+    A = I.random_graph_laplacian(1800, degree=10)
     g, o = pair(A)
     a = o.export(1, "A")
     lens = np.diff(a.row_ptr)
-    assert (lens > 512).sum() > 0 and (lens <= 512).sum() > 0
+    assert (lens > 256).sum() > 0 and (lens <= 256).sum() > 0
     gam = [0.0, 0.1]
     g.sparsify_levels(gam)
     o.sparsify(gam)
