@@ -139,11 +139,11 @@ __device__ inline double ordered_add(double acc, bool has, double x) {
     return acc;
 }
 
-// Rows with many entries: one workgroup per row i, its columns and keep flags
-// staged in LDS; each wave takes a dropped entry (i,j) at a time, its lanes
-// over the entries of row j (coalesced), and finds m among the staged columns
-// by a binary search in LDS; the wave adds the terms in lane order, which is
-// ascending m.  Rows longer than the stage take the one-wave path.
+// One workgroup per row i, its columns and keep flags staged in LDS; each
+// wave takes a dropped entry (i,j) at a time, its lanes over the entries of
+// row j (coalesced), and finds m among the staged columns by a binary search
+// in LDS; the wave adds the terms in lane order, which is ascending m.  Rows
+// longer than the stage take the one-wave path.
 __global__ void __launch_bounds__(kLB) lump_den_wide_kernel(int n, const int32_t* __restrict__ rp,
                                                             const int32_t* __restrict__ ci,
                                                             const double* __restrict__ v,
@@ -298,9 +298,8 @@ __global__ void __launch_bounds__(kLB) strong_lump_kernel(int n, const int32_t* 
     WAVE_ROW_LOOP(k, n) { strong_lump_row(k, lane, rp, ci, v, keep, thr, den, hrp, hci, hv); }
 }
 
-// Rows with many entries: one workgroup per row k, row k of A (columns,
-// values, keep flags, denominators, and the thresholds of its columns)
-// staged in LDS.
+// One workgroup per row k, row k of A (columns, values, keep flags,
+// denominators, and the thresholds of its columns) staged in LDS.
 // * (k,m), m > k, one wave each, its lanes over row m (coalesced): a lane
 //   finds its column j in the staged row k by a binary search in LDS and
 //   forms the share of dropped (k,j) (with a_jm read as a_mj); the wave adds
