@@ -313,7 +313,8 @@ __global__ void __launch_bounds__(kLB) strong_lump_kernel(int n, const int32_t* 
 // Rows longer than the stage take the one-wave path.
 constexpr int kDiagPer = 2;
 
-__global__ void __launch_bounds__(kLB) strong_lump_wide_kernel(int n, const int32_t* __restrict__ rp,
+// eight waves a SIMD (63 registers, no spills): eight workgroups a CU
+__global__ void __launch_bounds__(kLB) __attribute__((amdgpu_waves_per_eu(8, 8))) strong_lump_wide_kernel(int n, const int32_t* __restrict__ rp,
                                                                const int32_t* __restrict__ ci,
                                                                const double* __restrict__ v,
                                                                const uint8_t* __restrict__ keep,
@@ -388,17 +389,42 @@ __global__ void __launch_bounds__(kLB) strong_lump_wide_kernel(int n, const int3
         // off-diagonals (k,m), m > k: a wave per target, its lanes over row m;
         // the terms of dropped (k,j) first, then those of dropped (m,j), each
         // in ascending j (lane order)
+        // a target's loads: its start value, the bounds of row m's kept
+        // columns, and the first 64 entries of row m (a kept entry's den is
+        // never written and is not used)
+        struct Target {
+            int m, mb, me, hm0, hm1, j0;
+            double acc, a0, d0;
+            uint8_t kp0;
+        };
+        auto fetch = [&](int tt) {
+            Target g;
+            g.m = ks[tt - hb];
+            g.mb = sb[tt - hb];
+            g.me = g.mb + off[tt - hb + 1] - off[tt - hb];
+            g.hm0 = hrp[g.m];
+            g.hm1 = hrp[g.m + 1];
+            g.acc = hv[tt];
+            const int r0 = min(g.mb + lane, g.me - 1);
+            g.j0 = ci[r0];
+            g.a0 = v[r0];
+            g.d0 = den[r0];
+            g.kp0 = keep[r0];
+            return g;
+        };
+        Target nxt{};
+        if (dk + 1 + wave < he) nxt = fetch(dk + 1 + wave);
         for (int t = dk + 1 + wave; t < he; t += kWaves) {
-            const int m = ks[t - hb];
-            const int mb = sb[t - hb], me = mb + off[t - hb + 1] - off[t - hb];
-            // every load of the first 64 entries of row m, issued together (a
-            // kept entry's den is never written and is not used)
-            const int hm0 = hrp[m], hm1 = hrp[m + 1];
-            double acc = hv[t];
-            const int r0 = min(mb + lane, me - 1);
-            const int j0 = ci[r0];
-            const double a0 = v[r0], d0 = den[r0];
-            const uint8_t kp0 = keep[r0];
+            const Target cur = nxt;
+            // the first chunk of the mirror row, then the next target's
+            // loads: both in flight while this target's shares are formed
+            const int hidx = cur.hm0 + lane;
+            const int hc0 = hidx < cur.hm1 ? hci[hidx] : -1;
+            if (t + kWaves < he) nxt = fetch(t + kWaves);
+            const int m = cur.m, mb = cur.mb, me = cur.me, hm0 = cur.hm0, hm1 = cur.hm1, j0 = cur.j0;
+            const double a0 = cur.a0, d0 = cur.d0;
+            const uint8_t kp0 = cur.kp0;
+            double acc = cur.acc;
             const int w0 = lower_bound_lds(kc, len, j0);
             const bool at0 = w0 < len && kc[w0] == j0;   // j0 in row k
             for (int c0 = mb; c0 < me; c0 += 64) {   // (k,j) dropped, (j,m) strong: a_jm read as a_mj
@@ -451,7 +477,8 @@ __global__ void __launch_bounds__(kLB) strong_lump_wide_kernel(int n, const int3
             int tm = -1;
             for (int c0 = hm0; c0 < hm1 && tm < 0; c0 += 64) {
                 const int idx = c0 + lane;
-                const uint64_t hit = __ballot(idx < hm1 && hci[idx] == k);
+                const int col = c0 == hm0 ? hc0 : (idx < hm1 ? hci[idx] : -1);
+                const uint64_t hit = __ballot(idx < hm1 && col == k);
                 if (hit) tm = c0 + __builtin_ctzll(hit);
             }
             if (lane == 0) {
