@@ -1,9 +1,10 @@
 // Strong-neighbour lumping kernels: every sum and share in the order the
 // definition fixes (ascending columns; shares of a target in ascending order
 // of their source entry), contraction off.  The threshold and the copy run
-// one wave per row; the denominators and the shares a workgroup per row
-// with the row staged in LDS (rows longer than the stage, and a launch forced
-// to it, one wave per row).
+// one wave per row; the shares a workgroup per row with the row staged in
+// LDS, the denominators the same or, on levels of short rows, a wave per row
+// with its own stage (rows longer than the stage, and a launch forced to it,
+// one wave per row without a stage).
 #include "lump_kernels.hpp"
 
 #include <algorithm>
@@ -24,6 +25,14 @@ constexpr int kWideCap = 256;   // row entries a workgroup stages in LDS (15 KB:
 // 34 to 108 entries per row); a larger value, from the environment, selects
 // the one-wave kernels, which tests compare against
 constexpr double kWideMeanRow = 0.0;
+// below this mean row length, on levels with enough rows to fill the device
+// with waves, the denominators run a wave per row with its own LDS stage
+// (measured on 3D Poisson: faster at 174,772 and 27,542 rows of 34 and 57
+// entries, slower at 129 rows of 65 and from 108 entries a row);
+// AMG_LUMP_DEN_WAVE_ROW in the environment replaces both conditions by
+// mean_row < its value
+constexpr double kDenWaveMeanRow = 80.0;
+constexpr int kDenWaveMinRows = 16384;
 
 int wave_grid_of(int n) { return std::max(1, std::min((n + kWaves - 1) / kWaves, 65536)); }
 
@@ -167,6 +176,64 @@ __global__ void __launch_bounds__(kLB) lump_den_wide_kernel(int n, const int32_t
         }
         __syncthreads();
         for (int u = wave; u < len; u += kWaves) {
+            const int j = sc[u];
+            if (j == i || sk[u]) continue;
+            const int jb = rp[j], je = rp[j + 1];
+            const double t = thr[j];
+            double d = 0.0;
+            for (int r0 = jb; r0 < je; r0 += 64) {
+                const int r = r0 + lane;
+                bool has = false;
+                double a = 0.0;
+                if (r < je && t > 0.0) {
+                    const int m = ci[r];
+                    a = v[r];
+                    if (m != j && -a >= t) {
+                        const int w = lower_bound_lds(sc, len, m);
+                        has = w < len && sc[w] == m && sk[w];
+                    }
+                }
+                d = ordered_add(d, has, fabs(a));
+            }
+            if (lane == 0) den[ib + u] = d;
+        }
+    }
+}
+
+// Short rows: the same per dropped entry, but one wave per row (each wave
+// its own slice of LDS, so four rows of a workgroup are in flight at once);
+// a row's stage is written and read by its own wave only.
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ void __launch_bounds__(kLB) lump_den_wave_kernel(int n, const int32_t* __restrict__ rp,
+                                                            const int32_t* __restrict__ ci,
+                                                            const double* __restrict__ v,
+                                                            const uint8_t* __restrict__ keep,
+                                                            const double* __restrict__ thr,
+                                                            double* __restrict__ den) {
+    __shared__ int32_t scw[kWaves][kWideCap];
+    __shared__ uint8_t skw[kWaves][kWideCap];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    int32_t* sc = scw[wave];
+    uint8_t* sk = skw[wave];
+    WAVE_ROW_LOOP(i, n) {
+        const int ib = rp[i], ie = rp[i + 1], len = ie - ib;
+        if (len > kWideCap) {
+            lump_den_row(i, lane, rp, ci, v, keep, thr, den);
+            continue;
+        }
+        wave_lds_sync();   // the previous row's reads are done
+        for (int t = lane; t < len; t += 64) {
+            sc[t] = ci[ib + t];
+            sk[t] = keep[ib + t];
+        }
+        wave_lds_sync();
+        for (int u = 0; u < len; ++u) {
             const int j = sc[u];
             if (j == i || sk[u]) continue;
             const int jb = rp[j], je = rp[j + 1];
@@ -581,13 +648,22 @@ bool use_wide(double mean_row) {
     return mean_row >= lim;
 }
 
+bool use_den_wave(int n, double mean_row) {
+    const char* e = std::getenv("AMG_LUMP_DEN_WAVE_ROW");
+    if (e) return mean_row < std::atof(e);
+    return n >= kDenWaveMinRows && mean_row < kDenWaveMeanRow;
+}
+
 int row_grid_of(int n) { return std::max(1, std::min(n, 65536)); }
 
 }  // namespace
 
 void launch_lump_den(int n, const int32_t* rp, const int32_t* ci, const double* v, const uint8_t* keep,
                      const double* thr, double* den, double mean_row, hipStream_t st) {
-    if (use_wide(mean_row))
+    if (use_wide(mean_row) && use_den_wave(n, mean_row))
+        hipLaunchKernelGGL(lump_den_wave_kernel, dim3(wave_grid_of(n)), dim3(kLB), 0, st, n, rp, ci, v, keep, thr,
+                           den);
+    else if (use_wide(mean_row))
         hipLaunchKernelGGL(lump_den_wide_kernel, dim3(row_grid_of(n)), dim3(kLB), 0, st, n, rp, ci, v, keep, thr,
                            den);
     else

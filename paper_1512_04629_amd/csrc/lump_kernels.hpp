@@ -29,8 +29,11 @@ void launch_lump_den(int n, const int32_t* rp, const int32_t* ci, const double* 
 // be bitwise symmetric with a symmetric keep set (a_jm is read as a_mj).
 // Both launches run a workgroup per row with the row staged in LDS, or one
 // wave per row when mean_row (nnz / n) is below the threshold that the
-// environment variable AMG_LUMP_WIDE_ROW sets (default 0: never): the same
-// bits either way.
+// environment variable AMG_LUMP_WIDE_ROW sets (default 0: never); the
+// denominators of levels with at least 16,384 rows of fewer than 80 entries
+// on average (the environment variable AMG_LUMP_DEN_WAVE_ROW replaces both
+// conditions by mean_row below its value) run a wave per row with its own
+// LDS stage.  The same bits every way.
 void launch_strong_lump(int n, const int32_t* rp, const int32_t* ci, const double* v, const uint8_t* keep,
                         const double* thr, const double* den, const int32_t* hrp, const int32_t* hci, double* hv,
                         double mean_row, hipStream_t st);

@@ -4,7 +4,8 @@ its shares added in ascending order of their source entry, on the device as
 in the oracle, so the operators agree bit for bit, diagonal included; this
 holds for both launch shapes (a wave per row, and a workgroup per row with
 the row staged in LDS, whose rows longer than the stage go the one-wave
-way), each forced in turn.  Solves: equal iteration counts, solution within
+way), each forced in turn, and for the denominators' wave-per-row stage that
+levels of short rows take.  Solves: equal iteration counts, solution within
 1e-10."""
 import numpy as np
 import pytest
@@ -58,7 +59,7 @@ def test_sparsify_bitwise(lib, name, gamma, hybrid):
     same_operators(g, o)
 
 
-FORCE = {"wave": "1e300", "workgroup": "0"}
+FORCE = {"wave": "1e300", "workgroup": "0"}   # AMG_LUMP_WIDE_ROW
 
 
 @pytest.mark.parametrize("name", sorted(PROBLEMS))
@@ -73,13 +74,16 @@ def test_both_launch_shapes_bitwise(lib, monkeypatch, name, path):
     same_operators(g, o)
 
 
-@pytest.mark.parametrize("path", ["default", "wave"])
+@pytest.mark.parametrize("path", ["default", "wave", "staged_wave_denominators"])
 def test_rows_longer_than_the_stage(lib, monkeypatch, path):
     """A graph whose first coarse level has 259 nearly full rows: 148 longer
-    than the 256 entries a workgroup stages, 111 not, so one launch takes both
-    branches of the workgroup-per-row kernels."""
+    than the 256 entries a row's stage holds, 111 not, so one launch takes
+    both branches of the staged kernels (the denominators' wave-per-row stage
+    forced onto it in the third case)."""
     if path == "wave":
         monkeypatch.setenv("AMG_LUMP_WIDE_ROW", FORCE["wave"])
+    if path == "staged_wave_denominators":
+        monkeypatch.setenv("AMG_LUMP_DEN_WAVE_ROW", "1e300")
     A = I.random_graph_laplacian(1800, degree=10)
     g, o = pair(A)
     a = o.export(1, "A")
