@@ -380,8 +380,10 @@ __global__ void __launch_bounds__(kLB) strong_lump_kernel(int n, const int32_t* 
 // Rows longer than the stage take the one-wave path.
 constexpr int kDiagPer = 2;
 
-// eight waves a SIMD (63 registers, no spills): eight workgroups a CU
-__global__ void __launch_bounds__(kLB) __attribute__((amdgpu_waves_per_eu(8, 8))) strong_lump_wide_kernel(int n, const int32_t* __restrict__ rp,
+// LB threads a workgroup: LB, or 1024 on levels too small to fill the
+// device otherwise; eight waves a SIMD (at most 64 registers, no spills)
+template <int LB>
+__global__ void __launch_bounds__(LB) __attribute__((amdgpu_waves_per_eu(8, 8))) strong_lump_wide_kernel(int n, const int32_t* __restrict__ rp,
                                                                const int32_t* __restrict__ ci,
                                                                const double* __restrict__ v,
                                                                const uint8_t* __restrict__ keep,
@@ -398,9 +400,9 @@ __global__ void __launch_bounds__(kLB) __attribute__((amdgpu_waves_per_eu(8, 8))
     __shared__ int32_t ks[kWideCap];        // the kept columns s of row k
     __shared__ int32_t sb[kWideCap];        // rp[s]
     __shared__ int32_t off[kWideCap + 1];   // their rows' offsets, end to end
-    __shared__ double slot_c[kDiagPer * kLB];
-    __shared__ uint8_t slot_h[kDiagPer * kLB];
-    __shared__ int wsum[kWaves];
+    __shared__ double slot_c[kDiagPer * LB];
+    __shared__ uint8_t slot_h[kDiagPer * LB];
+    __shared__ int wsum[(LB / 64)];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     for (int k = blockIdx.x; k < n; k += gridDim.x) {
@@ -411,7 +413,7 @@ __global__ void __launch_bounds__(kLB) __attribute__((amdgpu_waves_per_eu(8, 8))
         }
         const int hb = hrp[k], he = hrp[k + 1], nk = he - hb;   // nk <= len
         __syncthreads();   // the previous row's readers are done
-        for (int t = threadIdx.x; t < len; t += kLB) {
+        for (int t = threadIdx.x; t < len; t += LB) {
             const int p = kb + t;
             const int j = ci[p];
             kc[t] = j;
@@ -422,7 +424,7 @@ __global__ void __launch_bounds__(kLB) __attribute__((amdgpu_waves_per_eu(8, 8))
         }
         // kept columns and their row lengths, scanned end to end
         int carry = 0;
-        for (int base = 0; base < nk; base += kLB) {
+        for (int base = 0; base < nk; base += LB) {
             const int idx = base + (int)threadIdx.x;
             int x = 0;
             if (idx < nk) {
@@ -440,7 +442,7 @@ __global__ void __launch_bounds__(kLB) __attribute__((amdgpu_waves_per_eu(8, 8))
             if (lane == 63) wsum[wave] = incl;
             __syncthreads();
             int before = 0, total = 0;
-            for (int w = 0; w < kWaves; ++w) {
+            for (int w = 0; w < (LB / 64); ++w) {
                 before += w < wave ? wsum[w] : 0;
                 total += wsum[w];
             }
@@ -481,13 +483,13 @@ __global__ void __launch_bounds__(kLB) __attribute__((amdgpu_waves_per_eu(8, 8))
         };
         Target nxt{};
         if (dk + 1 + wave < he) nxt = fetch(dk + 1 + wave);
-        for (int t = dk + 1 + wave; t < he; t += kWaves) {
+        for (int t = dk + 1 + wave; t < he; t += (LB / 64)) {
             const Target cur = nxt;
             // the first chunk of the mirror row, then the next target's
             // loads: both in flight while this target's shares are formed
             const int hidx = cur.hm0 + lane;
             const int hc0 = hidx < cur.hm1 ? hci[hidx] : -1;
-            if (t + kWaves < he) nxt = fetch(t + kWaves);
+            if (t + (LB / 64) < he) nxt = fetch(t + (LB / 64));
             const int m = cur.m, mb = cur.mb, me = cur.me, hm0 = cur.hm0, hm1 = cur.hm1, j0 = cur.j0;
             const double a0 = cur.a0, d0 = cur.d0;
             const uint8_t kp0 = cur.kp0;
@@ -556,11 +558,11 @@ __global__ void __launch_bounds__(kLB) __attribute__((amdgpu_waves_per_eu(8, 8))
         // the diagonal
         double acc = hv[dk];
         const int total = off[nk];
-        for (int g = 0; g < total; g += kDiagPer * kLB) {
+        for (int g = 0; g < total; g += kDiagPer * LB) {
             int qq[kDiagPer], ss[kDiagPer];
 #pragma unroll
             for (int e = 0; e < kDiagPer; ++e) {
-                const int f = g + e * kLB + (int)threadIdx.x;
+                const int f = g + e * LB + (int)threadIdx.x;
                 qq[e] = -1;
                 ss[e] = 0;
                 if (f < total) {
@@ -614,12 +616,12 @@ __global__ void __launch_bounds__(kLB) __attribute__((amdgpu_waves_per_eu(8, 8))
                         }
                     }
                 }
-                slot_c[e * kLB + threadIdx.x] = c;
-                slot_h[e * kLB + threadIdx.x] = has ? 1 : 0;
+                slot_c[e * LB + threadIdx.x] = c;
+                slot_h[e * LB + threadIdx.x] = has ? 1 : 0;
             }
             __syncthreads();
             if (wave == 0)
-                for (int w = 0; w < kDiagPer * kWaves; ++w)
+                for (int w = 0; w < kDiagPer * (LB / 64); ++w)
                     acc = ordered_add(acc, slot_h[w * 64 + lane] != 0, slot_c[w * 64 + lane]);
             __syncthreads();   // the slots are reused
         }
@@ -654,6 +656,14 @@ bool use_den_wave(int n, double mean_row) {
     return n >= kDenWaveMinRows && mean_row < kDenWaveMeanRow;
 }
 
+// levels with fewer rows give the share kernel 1024 threads a row (measured
+// on 3D Poisson: 821 and 129 rows 263 -> 156 and 141 -> 90 us; 5,191 rows
+// 372 -> 542 us); AMG_LUMP_SMALL_ROWS in the environment overrides it
+int small_level_rows() {
+    const char* e = std::getenv("AMG_LUMP_SMALL_ROWS");
+    return e ? std::atoi(e) : 4096;
+}
+
 int row_grid_of(int n) { return std::max(1, std::min(n, 65536)); }
 
 }  // namespace
@@ -673,9 +683,12 @@ void launch_lump_den(int n, const int32_t* rp, const int32_t* ci, const double* 
 void launch_strong_lump(int n, const int32_t* rp, const int32_t* ci, const double* v, const uint8_t* keep,
                         const double* thr, const double* den, const int32_t* hrp, const int32_t* hci, double* hv,
                         double mean_row, hipStream_t st) {
-    if (use_wide(mean_row))
-        hipLaunchKernelGGL(strong_lump_wide_kernel, dim3(row_grid_of(n)), dim3(kLB), 0, st, n, rp, ci, v, keep, thr,
-                           den, hrp, hci, hv);
+    if (use_wide(mean_row) && n < small_level_rows())
+        hipLaunchKernelGGL(strong_lump_wide_kernel<1024>, dim3(row_grid_of(n)), dim3(1024), 0, st, n, rp, ci, v, keep,
+                           thr, den, hrp, hci, hv);
+    else if (use_wide(mean_row))
+        hipLaunchKernelGGL(strong_lump_wide_kernel<kLB>, dim3(row_grid_of(n)), dim3(kLB), 0, st, n, rp, ci, v, keep,
+                           thr, den, hrp, hci, hv);
     else
         hipLaunchKernelGGL(strong_lump_kernel, dim3(wave_grid_of(n)), dim3(kLB), 0, st, n, rp, ci, v, keep, thr, den,
                            hrp, hci, hv);

@@ -33,7 +33,9 @@ void launch_lump_den(int n, const int32_t* rp, const int32_t* ci, const double* 
 // denominators of levels with at least 16,384 rows of fewer than 80 entries
 // on average (the environment variable AMG_LUMP_DEN_WAVE_ROW replaces both
 // conditions by mean_row below its value) run a wave per row with its own
-// LDS stage.  The same bits every way.
+// LDS stage; the share kernel's workgroups have 1,024 threads on levels of
+// fewer than 4,096 rows (the environment variable AMG_LUMP_SMALL_ROWS
+// overrides the bound), 256 otherwise.  The same bits every way.
 void launch_strong_lump(int n, const int32_t* rp, const int32_t* ci, const double* v, const uint8_t* keep,
                         const double* thr, const double* den, const int32_t* hrp, const int32_t* hci, double* hv,
                         double mean_row, hipStream_t st);

@@ -63,9 +63,15 @@ FORCE = {"wave": "1e300", "workgroup": "0"}   # AMG_LUMP_WIDE_ROW
 
 
 @pytest.mark.parametrize("name", sorted(PROBLEMS))
-@pytest.mark.parametrize("path", sorted(FORCE))
+@pytest.mark.parametrize("path", sorted(FORCE) + ["workgroup_256"])
 def test_both_launch_shapes_bitwise(lib, monkeypatch, name, path):
-    monkeypatch.setenv("AMG_LUMP_WIDE_ROW", FORCE[path])
+    """workgroup_256: the share kernel's 256-thread workgroups on every level
+    (by default levels of fewer than 4,096 rows, most of these problems',
+    take 1,024)."""
+    if path == "workgroup_256":
+        monkeypatch.setenv("AMG_LUMP_SMALL_ROWS", "0")
+    else:
+        monkeypatch.setenv("AMG_LUMP_WIDE_ROW", FORCE[path])
     A = PROBLEMS[name]()
     g, o = pair(A)
     gam = [0.0] + [0.1] * (o.nlev - 1)
