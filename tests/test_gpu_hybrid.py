@@ -89,7 +89,7 @@ def test_hybrid_adaptive_solve_parity(lib):
     rg = g.solve(dev(b), xd, **kw)
     xo, ro = o.solve(b, **kw)
     assert ro.reintroductions >= 3
-    _assert_solve_parity(host(xd), rg, xo, ro)
+    _assert_solve_parity(host(xd), rg, xo, ro, kw["tol"])
     compare_levels(g, o)
 
 

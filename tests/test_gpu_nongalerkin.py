@@ -56,7 +56,7 @@ def test_nongalerkin_solve_parity(lib, method):
     rg = g.solve(dev(b), xd, **kw)
     xo, ro = o.solve(b, **kw)
     assert ro.converged
-    _assert_solve_parity(host(xd), rg, xo, ro)
+    _assert_solve_parity(host(xd), rg, xo, ro, kw["tol"])
 
 
 def test_sparse_galerkin_post_pass_on_a_nongalerkin_hierarchy(lib):

@@ -216,7 +216,21 @@ def _solve_pair(A, gam, b, **kw):
     return host(xd), rg, xo, ro, g, o
 
 
-def _assert_solve_parity(xg, rg, xo, ro):
+def crossing_margin(res, tol):
+    """Smallest |log(rho_k / tol)| over the stop tests a solve took, rho_k the
+    relative residual after iteration k: how far the iteration count is from
+    flipping under a rounding-level change of the residuals."""
+    rel = np.asarray(res.hist[1:], float) / res.hist[0]
+    rel = rel[np.isfinite(rel) & (rel > 0)]
+    return float(np.min(np.abs(np.log(rel / tol)))) if rel.size else float("inf")
+
+
+def _assert_solve_parity(xg, rg, xo, ro, tol=None):
+    if tol is not None:
+        m = crossing_margin(ro, tol)
+        print(f"crossing margin |log(rho/tol)| = {m:.3e} over {ro.iters} iterations", flush=True)
+        if m < 1e-9:
+            pytest.skip(f"ill-conditioned for count parity: crossing margin {m:.2e} < 1e-9")
     assert rg.status == ro.status
     assert rg.iters == ro.iters, (rg.iters, ro.iters, rg.hist, ro.hist)
     assert rg.reintroductions == ro.reintroductions and rg.restarts == ro.restarts
@@ -233,7 +247,7 @@ def test_config1_stationary_poisson2d_64(lib):
         gam = [0.0, 0.0] + [gamma] * 10
         xg, rg, xo, ro, g, o = _solve_pair(A, gam, b, method=0, tol=1e-8, maxit=100)
         assert ro.converged and rg.converged
-        _assert_solve_parity(xg, rg, xo, ro)
+        _assert_solve_parity(xg, rg, xo, ro, 1e-8)
 
 
 @pytest.mark.parametrize("name", sorted(PROBLEMS))
@@ -247,7 +261,7 @@ def test_solve_parity(lib, name, method):
     xg, rg, xo, ro, g, o = _solve_pair(A, gam, b, method=method, tol=1e-8, maxit=300)
     if ro.status == -5:
         pytest.skip("oracle did not converge in 300 iterations for this case")
-    _assert_solve_parity(xg, rg, xo, ro)
+    _assert_solve_parity(xg, rg, xo, ro, 1e-8)
 
 
 def test_adaptive_forced_reintroduction(lib):
@@ -259,7 +273,7 @@ def test_adaptive_forced_reintroduction(lib):
     xg, rg, xo, ro, g, o = _solve_pair(A, gam, b, method=1, tol=1e-12, maxit=200, adaptive=True,
                                        k=2, s=1, rho_max=0.0)
     assert ro.reintroductions >= 3
-    _assert_solve_parity(xg, rg, xo, ro)
+    _assert_solve_parity(xg, rg, xo, ro, 1e-12)
     for l in range(nlev):
         assert g.gamma(l) == o.gamma(l)
 
@@ -272,7 +286,7 @@ def test_adaptive_diverged_window_reverts(lib):
     gam = [0.0] + [1.0] * (nlev - 1)
     xg, rg, xo, ro, g, o = _solve_pair(A, gam, b, method=0, tol=1e-14, maxit=5, adaptive=True, k=3, s=1)
     assert ro.reintroductions == 1 and ro.status == -5
-    _assert_solve_parity(xg, rg, xo, ro)
+    _assert_solve_parity(xg, rg, xo, ro, 1e-14)
 
 
 def test_single_level_hierarchy(lib):
@@ -374,30 +388,128 @@ def test_solve_parity_large(lib, name):
     gam = [0.0, 0.0] + [0.1] * (nlev - 2)
     xg, rg, xo, ro, g, o = _solve_pair(A, gam, b, method=1, tol=1e-8, maxit=200, adaptive=True, k=3, s=1)
     assert ro.converged
-    _assert_solve_parity(xg, rg, xo, ro)
+    _assert_solve_parity(xg, rg, xo, ro, 1e-8)
 
 
 def test_full_size_poisson3d_128(lib):
     """The benchmark workload at full size (n = 2,097,152): hierarchy, minimal
     patterns, keep flags and sparsified patterns bit-exact; the adaptive
-    AMG-PCG solve at gamma = 0.1 takes the oracle's iteration count and agrees
-    to 1e-10."""
+    AMG-PCG solve (k = 3, s = 1, rho_max = 0.5) takes the oracle's iteration
+    count and agrees to 1e-10 at every gamma of the comparison (0.1, 0.01 and
+    0, the Galerkin hierarchy), and with gamma = 1 and every window forced to
+    reintroduce (rho_max = 0), which walks the gamma ladder at full size."""
+    from oracle import oracle as O
     A = I.poisson3d(128)
     b = I.rhs(A.n, 2)
     g, o = both(A)
     assert g.nlev == o.nlev == 8
-    g.sparsify(0.1, 2)
-    o.sparsify_from(0.1, 2)
     for l in range(o.nlev):
         ga, oa = g.export(l, "A"), o.export(l, "A")
         assert same_csr(ga, oa), l
-        if l >= 1:
-            assert np.array_equal(g.mask(l, "M"), o.mask(l, "M")), l
-            assert np.array_equal(g.mask(l, "KEEP"), o.mask(l, "KEEP")), l
+    kw = dict(method=1, tol=1e-8, maxit=200, adaptive=True, k=3, s=1)
+    runs = [(0.1, 0.5), (0.01, 0.5), (0.0, 0.5), (1.0, 0.0)]
+    for gamma, rho_max in runs:
+        print(f"128^3 gamma {gamma} rho_max {rho_max}", flush=True)
+        g.sparsify(gamma, 2)
+        o.sparsify_from(gamma, 2)
+        for l in range(1, o.nlev):
+            if gamma == 0.1:
+                assert np.array_equal(g.mask(l, "M"), o.mask(l, "M")), l
+            assert np.array_equal(g.mask(l, "KEEP"), o.mask(l, "KEEP")), (gamma, l)
             gh, oh = g.export(l, "AHAT"), o.export(l, "AHAT")
-            assert np.array_equal(gh[2], oh.row_ptr) and np.array_equal(gh[3], oh.col), l
+            assert np.array_equal(gh[2], oh.row_ptr) and np.array_equal(gh[3], oh.col), (gamma, l)
+        x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+        rg = g.solve(dev(b), x, rho_max=rho_max, **kw)
+        xo, ro = o.solve(b, rho_max=rho_max, **kw)
+        print(f"  iterations {rg.iters}/{ro.iters}, reintroductions {rg.reintroductions}/{ro.reintroductions}",
+              flush=True)
+        _assert_solve_parity(host(x), rg, xo, ro, kw["tol"])
+        assert rg.converged and rg.relres <= 1e-8
+        if rho_max == 0.0:
+            assert ro.reintroductions >= 3
+            for l in range(o.nlev):
+                assert g.gamma(l) == o.gamma(l), l
+            for l in range(1, o.nlev):
+                gh, oh = g.export(l, "AHAT"), o.export(l, "AHAT")
+                assert np.array_equal(gh[2], oh.row_ptr) and np.array_equal(gh[3], oh.col), l
+
+
+def test_full_size_aniso2d_1024_adaptive_reintroduction(lib):
+    """Rotated anisotropic Q1 1024^2 (n = 1,048,576), gamma = 0.1 on levels
+    >= 2, adaptive AMG-PCG (k = 3, s = 1, rho_max = 0.5) to 1e-8: the windowed
+    convergence factor exceeds 0.5 and the solve reintroduces dropped entries
+    many times; the device takes the oracle's iterations, reintroductions and
+    restarts, agrees to 1e-10 and ends on the oracle's gamma ladder and
+    sparsified patterns."""
+    from oracle import oracle as O
+    A = I.aniso2d(1024)
+    b = I.rhs(A.n, 3)
+    g, o = both(A)
+    g.sparsify(0.1, 2)
+    o.sparsify_from(0.1, 2)
+    kw = dict(method=1, tol=1e-8, maxit=300, adaptive=True, k=3, s=1, rho_max=0.5)
     x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
-    rg = g.solve(dev(b), x, method=1, tol=1e-8, maxit=200, adaptive=True, k=3, s=1)
-    xo, ro = o.solve(b, method=1, tol=1e-8, maxit=200, adaptive=True, k=3, s=1)
-    _assert_solve_parity(host(x), rg, xo, ro)
-    assert rg.converged and rg.relres <= 1e-8
+    print("aniso 1024^2 adaptive: device solve", flush=True)
+    rg = g.solve(dev(b), x, **kw)
+    print("aniso 1024^2 adaptive: oracle solve", flush=True)
+    xo, ro = o.solve(b, **kw)
+    print(f"  iterations {rg.iters}/{ro.iters}, reintroductions {rg.reintroductions}/{ro.reintroductions}",
+          flush=True)
+    assert ro.converged and ro.reintroductions >= 5
+    _assert_solve_parity(host(x), rg, xo, ro, kw["tol"])
+    for l in range(o.nlev):
+        assert g.gamma(l) == o.gamma(l), l
+    for l in range(1, o.nlev):
+        gh, oh = g.export(l, "AHAT"), o.export(l, "AHAT")
+        assert np.array_equal(gh[2], oh.row_ptr) and np.array_equal(gh[3], oh.col), l
+
+
+def _shifted_poisson2d(N, sigma):
+    from tests.test_oracle_coarse_lu import shifted_poisson2d
+    return shifted_poisson2d(N, sigma)
+
+
+def test_indefinite_coarsest_operator(lib):
+    """Coarsest operators that are not positive definite, where the oracle
+    leaves Cholesky for partial pivoting: a dense symmetric indefinite 40 x 40
+    matrix (one level) and 2D Poisson 16^2 shifted by -0.1 (three levels, the
+    coarsest Galerkin operator indefinite).  The coarsest solve (device:
+    Gauss-Jordan inverse with partial pivoting; oracle: LU with partial
+    pivoting) agrees normwise to 64 n eps cond, the forward-error bound of
+    either; the V-cycle to 1e-12; stationary AMG takes the oracle's
+    iterations, and CG breaks down where the oracle's does."""
+    eps = np.finfo(np.float64).eps
+    from tests.test_oracle_coarse_lu import dense_indefinite
+    D = dense_indefinite(40, 13)
+    g, o = both(D)
+    assert g.nlev == o.nlev == 1
+    kappa = np.linalg.cond(D.to_dense())
+    for rs in (1, 2):
+        bb = I.rhs(40, rs)
+        out = torch.empty(40, dtype=torch.float64, device="cuda")
+        g.level_op(0, "COARSE_SOLVE", dev(bb), None, out)
+        ref = o.level_op(0, 4, bb, None, 40)
+        assert np.linalg.norm(host(out) - ref) <= 64 * 40 * eps * kappa * np.linalg.norm(ref)
+    A = _shifted_poisson2d(16, 0.1)
+    g, o = both(A)
+    assert g.nlev == o.nlev == 3
+    L = o.nlev - 1
+    DL = o.export(L, "AHAT").to_dense()
+    assert np.linalg.eigvalsh(DL).min() < 0
+    nL = DL.shape[0]
+    bL = I.rhs(nL, 5)
+    out = torch.empty(nL, dtype=torch.float64, device="cuda")
+    g.level_op(L, "COARSE_SOLVE", dev(bL), None, out)
+    ref = o.level_op(L, 4, bL, None, nL)
+    assert np.linalg.norm(host(out) - ref) <= 64 * nL * eps * np.linalg.cond(DL) * np.linalg.norm(ref)
+    b = I.rhs(A.n, 1)
+    for xin in (np.zeros(A.n), I.rhs(A.n, 8)):
+        xd = dev(xin)
+        g.vcycle(dev(b), xd)
+        ref = o.vcycle(b, xin)
+        assert np.linalg.norm(host(xd) - ref) <= 1e-12 * np.linalg.norm(ref)
+    xg, rg, xo, ro, g2, o2 = _solve_pair(A, [0.0], b, method=0, tol=1e-10, maxit=100)
+    assert ro.converged
+    _assert_solve_parity(xg, rg, xo, ro, 1e-10)
+    xg, rg, xo, ro, g2, o2 = _solve_pair(A, [0.0], b, method=1, tol=1e-10, maxit=100)
+    assert ro.status == rg.status == -6 and rg.iters == ro.iters

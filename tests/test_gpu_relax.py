@@ -84,7 +84,7 @@ def test_solve_parity(lib, method):
     rg = g.solve(dev(b), xd, **kw)
     xo, ro = o.solve(b, **kw)
     assert ro.converged
-    _assert_solve_parity(host(xd), rg, xo, ro)
+    _assert_solve_parity(host(xd), rg, xo, ro, kw["tol"])
 
 
 def test_adaptive_solve_parity(lib):
@@ -99,7 +99,7 @@ def test_adaptive_solve_parity(lib):
     rg = g.solve(dev(b), xd, **kw)
     xo, ro = o.solve(b, **kw)
     assert ro.reintroductions >= 1
-    _assert_solve_parity(host(xd), rg, xo, ro)
+    _assert_solve_parity(host(xd), rg, xo, ro, kw["tol"])
 
 
 def test_other_paths_refuse_gauss_seidel(lib):

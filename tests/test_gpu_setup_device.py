@@ -110,7 +110,7 @@ def test_pmis_solve_and_sparsify_parity(lib):
         rg = g.solve(dev(b), xd, **kw)
         xo, ro = o.solve(b, **kw)
         assert ro.converged
-        _assert_solve_parity(host(xd), rg, xo, ro)
+        _assert_solve_parity(host(xd), rg, xo, ro, kw["tol"])
 
 
 def test_pmis_adaptive_reintroduction_parity(lib):
@@ -126,7 +126,7 @@ def test_pmis_adaptive_reintroduction_parity(lib):
     rg = g.solve(dev(b), xd, **kw)
     xo, ro = o.solve(b, **kw)
     assert ro.reintroductions >= 1
-    _assert_solve_parity(host(xd), rg, xo, ro)
+    _assert_solve_parity(host(xd), rg, xo, ro, kw["tol"])
     compare_levels(g, o)
 
 

@@ -113,7 +113,7 @@ def test_adaptive_solve_parity(lib):
     rg = g.solve(dev(b), xd, **kw)
     xo, ro = o.solve(b, **kw)
     assert ro.reintroductions >= 1
-    _assert_solve_parity(host(xd), rg, xo, ro)
+    _assert_solve_parity(host(xd), rg, xo, ro, kw["tol"])
     same_operators(g, o)
 
 
