@@ -213,6 +213,19 @@ enum { AMG_SPARSE_GALERKIN = 0, AMG_HYBRID_GALERKIN = 1 };
 enum { AMG_LUMP_DIAGONAL = 0, AMG_LUMP_STRONG = 1 };
 amg_status amg_set_lumping(amg_handle h, int32_t lumping);
 
+/* Testing hook: the launch shapes of the strong-lumping kernels on this
+   handle for later sparsify / reintroduce calls.  Every shape gives the same
+   bits; tests use it to compare them.  Rows of mean length >= wide_mean_row
+   (default 0) run a workgroup per row with the row staged in LDS, shorter
+   ones a wave per row; den_wave_mean_row < 0 (default -1) keeps the library's
+   rule for the denominators' wave-per-row stage (levels of at least 16,384
+   rows of fewer than 80 entries), a value >= 0 uses that stage wherever the
+   mean row length is below it; levels of fewer than small_rows rows (default
+   4,096) give the share kernel 1,024-thread workgroups.  AMG_ERR_STATE without
+   a hierarchy, AMG_ERR_INVALID_ARG for NaN or small_rows < 0. */
+amg_status amg_set_lump_shapes(amg_handle h, double wide_mean_row, double den_wave_mean_row,
+                               int32_t small_rows);
+
 /* Smoother of the V-cycle.  AMG_RELAX_JACOBI (default): weighted Jacobi with
    omega from the setup parameters.  AMG_RELAX_HYBRID_GS: hybrid Gauss-Seidel,
    the relaxation of the paper's experiments (Section 5, there with one block

@@ -37,7 +37,7 @@ KERNEL = {"JACOBI": 0, "JACOBI_ZERO": 1, "RESIDUAL": 2, "RESTRICT": 3, "INTERP":
 ABI_SYMBOLS = (
     "amg_setup_params_default", "amg_solve_params_default", "amg_setup_from_csr",
     "amg_setup_nongalerkin_from_csr", "amg_setup_device", "amg_setup_profile_enable", "amg_setup_profile_read",
-    "amg_sparsify", "amg_sparsify_levels", "amg_set_method", "amg_set_relaxation", "amg_set_lumping", "amg_reintroduce", "amg_solve", "amg_vcycle",
+    "amg_sparsify", "amg_sparsify_levels", "amg_set_method", "amg_set_relaxation", "amg_set_lumping", "amg_set_lump_shapes", "amg_reintroduce", "amg_solve", "amg_vcycle",
     "amg_vcycle32",
     "amg_solve_block", "amg_vcycle_block", "amg_vcycle_block32", "amg_batch_bytes", "amg_batch_create",
     "amg_batch_submit", "amg_batch_step", "amg_batch_poll", "amg_batch_collect", "amg_batch_slots",
@@ -124,6 +124,7 @@ def load_library():
     lib.amg_set_method.argtypes = [vp, i32]
     lib.amg_set_relaxation.argtypes = [vp, i32, i32]
     lib.amg_set_lumping.argtypes = [vp, i32]
+    lib.amg_set_lump_shapes.argtypes = [vp, f64, f64, i32]
     lib.amg_solve.argtypes = [vp, vp, vp, P(SolveParams), P(SolveInfo), vp]
     lib.amg_vcycle.argtypes = [vp, vp, vp]
     lib.amg_vcycle32.argtypes = [vp, vp, vp]
@@ -159,7 +160,7 @@ def load_library():
     lib.amg_last_error.restype = C.c_char_p
     for name in ("amg_setup_from_csr", "amg_setup_nongalerkin_from_csr", "amg_setup_device",
                  "amg_setup_profile_enable", "amg_setup_profile_read", "amg_sparsify", "amg_sparsify_levels", "amg_set_method",
-                 "amg_set_relaxation", "amg_set_lumping", "amg_reintroduce",
+                 "amg_set_relaxation", "amg_set_lumping", "amg_set_lump_shapes", "amg_reintroduce",
                  "amg_solve", "amg_vcycle", "amg_vcycle32", "amg_solve_block", "amg_vcycle_block",
                  "amg_vcycle_block32", "amg_batch_bytes", "amg_batch_create", "amg_batch_submit",
                  "amg_batch_step", "amg_batch_poll", "amg_batch_collect", "amg_batch_slots", "amg_device_bytes",
@@ -499,6 +500,13 @@ class Hierarchy:
             raise ValueError(f"unknown lumping {mode!r}")
         self._check(self._lib.amg_set_lumping(self._h, {"diagonal": 0, "strong": 1}[mode]))
 
+    def set_lump_shapes(self, wide_mean_row: float = 0.0, den_wave_mean_row: float = -1.0,
+                        small_rows: int = 4096):
+        """Testing hook: launch shapes of the strong-lumping kernels (the same
+        bits every way); the defaults are the library's."""
+        self._check(self._lib.amg_set_lump_shapes(self._h, float(wide_mean_row), float(den_wave_mean_row),
+                                                  int(small_rows)))
+
     def set_relaxation(self, kind: str = "jacobi", block_rows: int = 64):
         """Weighted Jacobi (default) or hybrid symmetric Gauss-Seidel with blocks
         of block_rows rows for later V-cycles and FP64 solves."""
@@ -567,7 +575,9 @@ class Batch:
             self.hier._batch = None
 
     def submit(self, rhs) -> int:
-        """Copies rhs (float64 CUDA tensor of n entries) into a free slot."""
+        """Copies rhs (float64 CUDA tensor of n entries) into a free slot.  The
+        copy runs on the engine's stream: work that produced rhs on another
+        stream must be ordered before it (e.g. engine_stream.wait_stream)."""
         slot = C.c_int32(-1)
         self._check(self._lib.amg_batch_submit(self._b, _dptr(rhs, self.hier.n, "rhs"), C.byref(slot)))
         return slot.value
@@ -590,7 +600,9 @@ class Batch:
 
     def collect(self, slot: int, x):
         """Copies a finished slot's solution into x (float64 CUDA tensor, on the
-        hierarchy's stream) and frees the slot: (iterations, relres, status)."""
+        hierarchy's stream) and frees the slot: (iterations, relres, status).
+        Earlier writes to x on other streams must be ordered before this call,
+        and later readers on other streams must wait for the engine's stream."""
         it, rr, st = C.c_int32(), C.c_double(), C.c_int32()
         self._check(self._lib.amg_batch_collect(self._b, int(slot), _dptr(x, self.hier.n, "x"), C.byref(it),
                                                 C.byref(rr), C.byref(st)))

@@ -157,7 +157,8 @@ struct amg_ctx {
     double* pinned = nullptr;
     int32_t* scan_scratch = nullptr;
     int32_t* cnt = nullptr;
-    int* missing = nullptr;
+    int* missing = nullptr;          // minimal-pattern and index-width checks
+    int* singular = nullptr;         // zero pivot met by the device inversion of the coarsest operator
     double *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_q = nullptr;
     double *xw = nullptr, *rt = nullptr;
     bool fp32 = false;
@@ -172,12 +173,13 @@ struct amg_ctx {
     bool compact_idx = true;                     // 16-bit column indices where they fit
     int relax = AMG_RELAX_JACOBI;                // smoother of the V-cycle
     int lumping = AMG_LUMP_DIAGONAL;             // where sparsify puts dropped entries
+    LumpShapes lump_shapes;                      // launch shapes of the strong-lumping kernels
     int gs_block = 64;                           // rows per block of hybrid Gauss-Seidel
     int bcg_k = 0;                               // block CG vectors (FP64, K wide)
     double *bcg_r = nullptr, *bcg_p = nullptr, *bcg_q = nullptr, *bcg_z = nullptr;
     int blk_pack_k = 0;
     std::string last_error;
-    bool check_singular = false;   // a device inversion wrote h->missing
+    bool check_singular = false;   // a device inversion wrote h->singular, not read back yet
     bool profiling = false;
     int prof_kind = -1, prof_level = -1;
     std::vector<PendingEvent> pending;
@@ -441,8 +443,8 @@ void refresh_coarse_inverse(amg_ctx* h) {
     h->nL = n;
     if (n <= dense_invert_max()) {
         // on the device, stream ordered after the operator it inverts
-        launch_fill_u32(1, reinterpret_cast<unsigned*>(h->missing), 0u, h->stream);
-        launch_dense_invert(c.Ah.view(), h->coarse_inv, h->missing, h->stream);
+        launch_fill_u32(1, reinterpret_cast<unsigned*>(h->singular), 0u, h->stream);
+        launch_dense_invert(c.Ah.view(), h->coarse_inv, h->singular, h->stream);
         check_launch();
         h->check_singular = true;
         return;
@@ -556,12 +558,12 @@ void sparsify_levels(amg_ctx* h, const std::vector<std::pair<int, double>>& todo
                 {
                     ProfScope pd(h, AMG_K_LUMP_DEN, l);
                     launch_lump_den(c.n, a.rp, a.ci, a.v, c.keep, c.lump_thr, c.lump_den, a.view().mean_row,
-                                    h->stream);
+                                    h->lump_shapes, h->stream);
                 }
                 {
                     ProfScope pl(h, AMG_K_LUMP_SHARES, l);
                     launch_strong_lump(c.n, a.rp, a.ci, a.v, c.keep, c.lump_thr, c.lump_den, c.Ahs.rp, c.Ahs.ci,
-                                       c.Ahs.v, a.view().mean_row, h->stream);
+                                       c.Ahs.v, a.view().mean_row, h->lump_shapes, h->stream);
                 }
                 launch_inverse_diagonal(c.Ahs.view(), c.dinv, h->fp32 ? c.dinv32 : nullptr, h->stream);
                 if (h->fp32) launch_narrow(c.A.nnz, c.Ahs32, c.Ahs.v, h->stream);   // capacity; past nnz unused
@@ -947,7 +949,7 @@ amg_status solve(amg_ctx* h, const double* b, double* x, const amg_solve_params&
     launch_fill_f64(S_COUNT, h->scal, 0.0, h->stream);
     row_op(h, AMG_K_RESIDUAL, 0, kResidNorm, A, x, b, nullptr, r, nullptr, S_NR2);
     int singular = 0;
-    if (h->check_singular) download(h, &singular, h->missing, 1);
+    if (h->check_singular) download(h, &singular, h->singular, 1);
     const double nr0 = std::sqrt(read_scalars(h)[S_NR2]);
     if (h->check_singular) {
         h->check_singular = false;
@@ -1241,7 +1243,7 @@ amg_status solve_block(amg_ctx* h, int k, int nrhs, const double* b, double* x, 
     launch_fill_f64(1, h->scal + S_LIVE, (double)nrhs, h->stream);
     block_outer<T>(h, k, b, x);
     int singular = 0;
-    if (h->check_singular) download(h, &singular, h->missing, 1);
+    if (h->check_singular) download(h, &singular, h->singular, 1);
     const double* sc = read_scalars(h);
     if (h->check_singular) {
         h->check_singular = false;
@@ -1342,7 +1344,7 @@ amg_status solve_block_pcg(amg_ctx* h, int k, int nrhs, const double* b, double*
     launch_fill_f64(1, h->scal + S_LIVE, (double)nrhs, h->stream);
     block_outer<T>(h, k, b, x, h->bcg_r);
     int singular = 0;
-    if (h->check_singular) download(h, &singular, h->missing, 1);
+    if (h->check_singular) download(h, &singular, h->singular, 1);
     const double* sc = read_scalars(h);
     if (h->check_singular) {
         h->check_singular = false;
@@ -1760,6 +1762,7 @@ void finish_setup(amg_ctx* h) {
     const int64_t n = h->lv[0].n;
     int partial_need = vector_launch_blocks(std::max(1, (int)n));
     h->missing = dalloc_n<int>(h, 1);
+    h->singular = dalloc_n<int>(h, 1);
     for (int l = 0; l <= L; ++l) {
         DevLevel& d = h->lv[l];
         compress_indices(h, d.A);
@@ -2244,7 +2247,7 @@ void destroy(amg_ctx* h) {
     dfree(h, h->blk_x);
     for (void* q : {(void*)h->bcg_r, (void*)h->bcg_p, (void*)h->bcg_q, (void*)h->bcg_z}) dfree(h, q);
     for (void* p : {(void*)h->coarse_inv, (void*)h->scal, (void*)h->partials,
-                    (void*)h->scan_scratch, (void*)h->cnt, (void*)h->missing, (void*)h->cg_r,
+                    (void*)h->scan_scratch, (void*)h->cnt, (void*)h->missing, (void*)h->singular, (void*)h->cg_r,
                     (void*)h->cg_z, (void*)h->cg_p, (void*)h->cg_q, (void*)h->xw, (void*)h->rt})
         dfree(h, p);
     if (h->pinned) (void)hipHostFree(h->pinned);
@@ -2538,6 +2541,15 @@ amg_status amg_set_lumping(amg_handle h, int32_t lumping) {
     if (!h || h->lv.empty() || h->batch) return AMG_ERR_STATE;
     if (lumping != AMG_LUMP_DIAGONAL && lumping != AMG_LUMP_STRONG) return AMG_ERR_INVALID_ARG;
     h->lumping = lumping;
+    return AMG_OK;
+}
+
+amg_status amg_set_lump_shapes(amg_handle h, double wide_mean_row, double den_wave_mean_row, int32_t small_rows) {
+    if (!h || h->lv.empty()) return AMG_ERR_STATE;
+    if (std::isnan(wide_mean_row) || std::isnan(den_wave_mean_row) || small_rows < 0) return AMG_ERR_INVALID_ARG;
+    h->lump_shapes.wide_mean_row = wide_mean_row;
+    h->lump_shapes.den_wave_mean_row = den_wave_mean_row;
+    h->lump_shapes.small_rows = small_rows;
     return AMG_OK;
 }
 

@@ -20,17 +20,10 @@ namespace {
 constexpr int kLB = 256;
 constexpr int kWaves = kLB / 64;
 constexpr int kWideCap = 256;   // row entries a workgroup stages in LDS (15 KB: eight workgroups a CU)
-// mean entries per row from which a workgroup per row is used: every level
-// (it was the faster on every level of the 3D Poisson hierarchies measured,
-// 34 to 108 entries per row); a larger value, from the environment, selects
-// the one-wave kernels, which tests compare against
-constexpr double kWideMeanRow = 0.0;
 // below this mean row length, on levels with enough rows to fill the device
 // with waves, the denominators run a wave per row with its own LDS stage
 // (measured on 3D Poisson: faster at 174,772 and 27,542 rows of 34 and 57
-// entries, slower at 129 rows of 65 and from 108 entries a row);
-// AMG_LUMP_DEN_WAVE_ROW in the environment replaces both conditions by
-// mean_row < its value
+// entries, slower at 129 rows of 65 and from 108 entries a row)
 constexpr double kDenWaveMeanRow = 80.0;
 constexpr int kDenWaveMinRows = 16384;
 
@@ -644,24 +637,11 @@ void launch_lump_threshold(int n, const int32_t* rp, const int32_t* ci, const do
 
 namespace {
 
-bool use_wide(double mean_row) {
-    const char* e = std::getenv("AMG_LUMP_WIDE_ROW");
-    const double lim = e ? std::atof(e) : kWideMeanRow;
-    return mean_row >= lim;
-}
+bool use_wide(const LumpShapes& ls, double mean_row) { return mean_row >= ls.wide_mean_row; }
 
-bool use_den_wave(int n, double mean_row) {
-    const char* e = std::getenv("AMG_LUMP_DEN_WAVE_ROW");
-    if (e) return mean_row < std::atof(e);
+bool use_den_wave(const LumpShapes& ls, int n, double mean_row) {
+    if (ls.den_wave_mean_row >= 0.0) return mean_row < ls.den_wave_mean_row;
     return n >= kDenWaveMinRows && mean_row < kDenWaveMeanRow;
-}
-
-// levels with fewer rows give the share kernel 1024 threads a row (measured
-// on 3D Poisson: 821 and 129 rows 263 -> 156 and 141 -> 90 us; 5,191 rows
-// 372 -> 542 us); AMG_LUMP_SMALL_ROWS in the environment overrides it
-int small_level_rows() {
-    const char* e = std::getenv("AMG_LUMP_SMALL_ROWS");
-    return e ? std::atoi(e) : 4096;
 }
 
 int row_grid_of(int n) { return std::max(1, std::min(n, 65536)); }
@@ -669,11 +649,11 @@ int row_grid_of(int n) { return std::max(1, std::min(n, 65536)); }
 }  // namespace
 
 void launch_lump_den(int n, const int32_t* rp, const int32_t* ci, const double* v, const uint8_t* keep,
-                     const double* thr, double* den, double mean_row, hipStream_t st) {
-    if (use_wide(mean_row) && use_den_wave(n, mean_row))
+                     const double* thr, double* den, double mean_row, const LumpShapes& ls, hipStream_t st) {
+    if (use_wide(ls, mean_row) && use_den_wave(ls, n, mean_row))
         hipLaunchKernelGGL(lump_den_wave_kernel, dim3(wave_grid_of(n)), dim3(kLB), 0, st, n, rp, ci, v, keep, thr,
                            den);
-    else if (use_wide(mean_row))
+    else if (use_wide(ls, mean_row))
         hipLaunchKernelGGL(lump_den_wide_kernel, dim3(row_grid_of(n)), dim3(kLB), 0, st, n, rp, ci, v, keep, thr,
                            den);
     else
@@ -682,11 +662,11 @@ void launch_lump_den(int n, const int32_t* rp, const int32_t* ci, const double* 
 
 void launch_strong_lump(int n, const int32_t* rp, const int32_t* ci, const double* v, const uint8_t* keep,
                         const double* thr, const double* den, const int32_t* hrp, const int32_t* hci, double* hv,
-                        double mean_row, hipStream_t st) {
-    if (use_wide(mean_row) && n < small_level_rows())
+                        double mean_row, const LumpShapes& ls, hipStream_t st) {
+    if (use_wide(ls, mean_row) && n < ls.small_rows)
         hipLaunchKernelGGL(strong_lump_wide_kernel<1024>, dim3(row_grid_of(n)), dim3(1024), 0, st, n, rp, ci, v, keep,
                            thr, den, hrp, hci, hv);
-    else if (use_wide(mean_row))
+    else if (use_wide(ls, mean_row))
         hipLaunchKernelGGL(strong_lump_wide_kernel<kLB>, dim3(row_grid_of(n)), dim3(kLB), 0, st, n, rp, ci, v, keep,
                            thr, den, hrp, hci, hv);
     else

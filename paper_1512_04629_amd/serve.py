@@ -139,12 +139,21 @@ class SolveServer:
         self.hier = {}
 
     # -- serving -----------------------------------------------------------------
+    def _after_caller(self):
+        """Orders every engine stream after the work the caller has enqueued so
+        far on its current stream (the requests' right-hand sides and solution
+        buffers are produced there); the streams' copies read b and write x."""
+        caller = amg._torch().cuda.current_stream()
+        for s in self.streams.values():
+            s.wait_stream(caller)
+
     def run(self, requests) -> ServeStats:
         """Serves `requests` (their `arrival` times are honoured in real time;
         all zeros = everything queued at once).  Each request's `x` must be
         a preallocated float64 CUDA tensor; on return it holds the solution
         and the request its timing and status."""
         torch = amg._torch()
+        self._after_caller()
         self.stats = ServeStats()
         order = sorted(requests, key=lambda r: (r.arrival, r.rid))
         queues = collections.defaultdict(collections.deque)
@@ -216,6 +225,7 @@ class SolveServer:
         (single right-hand side amg_solve), honouring arrival times."""
         torch = amg._torch()
         self.close_engines()
+        self._after_caller()
         self.stats = ServeStats()
         order = sorted(requests, key=lambda r: (r.arrival, r.rid))
         t0 = time.perf_counter()

@@ -109,3 +109,20 @@ def test_isolated_rows_inside_a_coupled_problem(lib, lumping):
     for i in (0, 17, 100, 863, 1727):
         d = A.val[A.row_ptr[i]]
         assert abs(xh[i] - b[i] / d) <= 1.01e-10 * nb / d, i
+
+
+def test_singular_coarsest_reported_after_index_toggle(lib):
+    """[[1, -1], [-1, 1]] passes validation (symmetric, positive diagonal) but
+    is singular; the device inversion of the coarsest operator meets a zero
+    pivot.  The pending flag survives rebuilding and dropping the 16-bit
+    column indices (which use a device word of their own) and the next solve
+    reports the matrix as bad."""
+    A = I.CSR(2, np.array([0, 2, 4], np.int32), np.array([0, 1, 0, 1], np.int32),
+              np.array([1.0, -1.0, -1.0, 1.0]))
+    g = lib.Hierarchy(A)
+    g.set_compact_indices(False)
+    g.set_compact_indices(True)
+    x = torch.zeros(2, dtype=torch.float64, device="cuda")
+    with pytest.raises(lib.AmgError) as e:
+        g.solve(dev(np.array([1.0, 2.0])), x, method=1, tol=1e-10, maxit=5)
+    assert e.value.status == -2 and "singular" in str(e.value)

@@ -59,21 +59,20 @@ def test_sparsify_bitwise(lib, name, gamma, hybrid):
     same_operators(g, o)
 
 
-FORCE = {"wave": "1e300", "workgroup": "0"}   # AMG_LUMP_WIDE_ROW
+SHAPES = {"wave": dict(wide_mean_row=1e300), "workgroup": dict(wide_mean_row=0.0),
+          "workgroup_256": dict(small_rows=0)}
 
 
 @pytest.mark.parametrize("name", sorted(PROBLEMS))
-@pytest.mark.parametrize("path", sorted(FORCE) + ["workgroup_256"])
-def test_both_launch_shapes_bitwise(lib, monkeypatch, name, path):
-    """workgroup_256: the share kernel's 256-thread workgroups on every level
-    (by default levels of fewer than 4,096 rows, most of these problems',
-    take 1,024)."""
-    if path == "workgroup_256":
-        monkeypatch.setenv("AMG_LUMP_SMALL_ROWS", "0")
-    else:
-        monkeypatch.setenv("AMG_LUMP_WIDE_ROW", FORCE[path])
+@pytest.mark.parametrize("path", sorted(SHAPES))
+def test_both_launch_shapes_bitwise(lib, name, path):
+    """wave: one wave per row on every level; workgroup: a workgroup per row
+    (the default); workgroup_256: the share kernel's 256-thread workgroups on
+    every level (by default levels of fewer than 4,096 rows, most of these
+    problems', take 1,024)."""
     A = PROBLEMS[name]()
     g, o = pair(A)
+    g.set_lump_shapes(**SHAPES[path])
     gam = [0.0] + [0.1] * (o.nlev - 1)
     g.sparsify_levels(gam)
     o.sparsify(gam)
@@ -81,17 +80,17 @@ def test_both_launch_shapes_bitwise(lib, monkeypatch, name, path):
 
 
 @pytest.mark.parametrize("path", ["default", "wave", "staged_wave_denominators"])
-def test_rows_longer_than_the_stage(lib, monkeypatch, path):
+def test_rows_longer_than_the_stage(lib, path):
     """A graph whose first coarse level has 259 nearly full rows: 148 longer
     than the 256 entries a row's stage holds, 111 not, so one launch takes
     both branches of the staged kernels (the denominators' wave-per-row stage
     forced onto it in the third case)."""
-    if path == "wave":
-        monkeypatch.setenv("AMG_LUMP_WIDE_ROW", FORCE["wave"])
-    if path == "staged_wave_denominators":
-        monkeypatch.setenv("AMG_LUMP_DEN_WAVE_ROW", "1e300")
     A = I.random_graph_laplacian(1800, degree=10)
     g, o = pair(A)
+    if path == "wave":
+        g.set_lump_shapes(wide_mean_row=1e300)
+    if path == "staged_wave_denominators":
+        g.set_lump_shapes(den_wave_mean_row=1e300)
     a = o.export(1, "A")
     lens = np.diff(a.row_ptr)
     assert (lens > 256).sum() > 0 and (lens <= 256).sum() > 0
