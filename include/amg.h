@@ -266,6 +266,24 @@ amg_status amg_reintroduce(amg_handle h, int32_t s, double gamma_min,
 amg_status amg_solve(amg_handle h, const double* b, double* x, const amg_solve_params* params,
                      amg_solve_info* info, double* hist);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): amg_solve
+   with the same arguments, results and error codes, bit for bit, that
+   allocates nothing.  Its work memory (the CG vectors r, z, p, q, the
+   window-start x and the window's true residual, the dot-product partials
+   and the scalar slots) lives in a static device array of the library, about
+   96 MiB, that each GPU the library runs on holds until the process ends.
+   Limits: n <= 2,097,152 rows and precision 64, else AMG_ERR_INVALID_ARG;
+   AMG_ERR_STATE while kernel profiling is on, or when an adaptive solve
+   under strong lumping could reintroduce on a level sparsified with diagonal
+   lumping (whose strong-lumping buffers do not exist yet).  The hierarchy,
+   its sparsified operators and the caller's b and x are used as they are.
+   Every call on one GPU shares that GPU's array: calls that overlap on one
+   GPU (other streams, other threads) race; calls on one stream, or
+   synchronised with each other, do not. */
+amg_status amg_solve_noalloc(amg_handle h, const double* b, double* x, const amg_solve_params* params,
+                             amg_solve_info* info, double* hist);
+
 /* One V-cycle (Section 2, amg_solve) in place: x <- V(b, x); device arrays. */
 amg_status amg_vcycle(amg_handle h, const double* b, double* x);
 

@@ -37,7 +37,7 @@ KERNEL = {"JACOBI": 0, "JACOBI_ZERO": 1, "RESIDUAL": 2, "RESTRICT": 3, "INTERP":
 ABI_SYMBOLS = (
     "amg_setup_params_default", "amg_solve_params_default", "amg_setup_from_csr",
     "amg_setup_nongalerkin_from_csr", "amg_setup_device", "amg_setup_profile_enable", "amg_setup_profile_read",
-    "amg_sparsify", "amg_sparsify_levels", "amg_set_method", "amg_set_relaxation", "amg_set_lumping", "amg_set_lump_shapes", "amg_reintroduce", "amg_solve", "amg_vcycle",
+    "amg_sparsify", "amg_sparsify_levels", "amg_set_method", "amg_set_relaxation", "amg_set_lumping", "amg_set_lump_shapes", "amg_reintroduce", "amg_solve", "amg_solve_noalloc", "amg_vcycle",
     "amg_vcycle32",
     "amg_solve_block", "amg_vcycle_block", "amg_vcycle_block32", "amg_batch_bytes", "amg_batch_create",
     "amg_batch_submit", "amg_batch_step", "amg_batch_poll", "amg_batch_collect", "amg_batch_slots",
@@ -126,6 +126,7 @@ def load_library():
     lib.amg_set_lumping.argtypes = [vp, i32]
     lib.amg_set_lump_shapes.argtypes = [vp, f64, f64, i32]
     lib.amg_solve.argtypes = [vp, vp, vp, P(SolveParams), P(SolveInfo), vp]
+    lib.amg_solve_noalloc.argtypes = [vp, vp, vp, P(SolveParams), P(SolveInfo), vp]
     lib.amg_vcycle.argtypes = [vp, vp, vp]
     lib.amg_vcycle32.argtypes = [vp, vp, vp]
     lib.amg_solve_block.argtypes = [vp, i32, vp, vp, P(SolveParams), P(SolveInfo), vp, vp]
@@ -161,7 +162,7 @@ def load_library():
     for name in ("amg_setup_from_csr", "amg_setup_nongalerkin_from_csr", "amg_setup_device",
                  "amg_setup_profile_enable", "amg_setup_profile_read", "amg_sparsify", "amg_sparsify_levels", "amg_set_method",
                  "amg_set_relaxation", "amg_set_lumping", "amg_set_lump_shapes", "amg_reintroduce",
-                 "amg_solve", "amg_vcycle", "amg_vcycle32", "amg_solve_block", "amg_vcycle_block",
+                 "amg_solve", "amg_solve_noalloc", "amg_vcycle", "amg_vcycle32", "amg_solve_block", "amg_vcycle_block",
                  "amg_vcycle_block32", "amg_batch_bytes", "amg_batch_create", "amg_batch_submit",
                  "amg_batch_step", "amg_batch_poll", "amg_batch_collect", "amg_batch_slots", "amg_device_bytes",
                  "amg_level_op", "amg_num_levels", "amg_get_level",
@@ -386,14 +387,17 @@ class Hierarchy:
 
     # -- solve -------------------------------------------------------------
     def solve(self, b, x, method=PCG, tol=1e-8, maxit=200, adaptive=False, k=3, s=1,
-              rho_max=0.5, gamma_min=0.01, precision=64, raise_on_error=False) -> SolveResult:
-        """precision=32 runs the V-cycle in FP32 inside the FP64 iteration."""
+              rho_max=0.5, gamma_min=0.01, precision=64, raise_on_error=False, noalloc=False) -> SolveResult:
+        """precision=32 runs the V-cycle in FP32 inside the FP64 iteration.
+        noalloc=True calls amg_solve_noalloc (work memory in the library's
+        static device array; FP64 only, n <= 2,097,152)."""
         p = SolveParams(int(method), float(tol), int(maxit), int(bool(adaptive)), int(k), int(s),
                         float(rho_max), float(gamma_min), int(precision))
         info = SolveInfo()
         hist = np.full(maxit + 1, np.nan)
-        st = self._lib.amg_solve(self._h, _dptr(b, self.n, "b"), _dptr(x, self.n, "x"), C.byref(p),
-                                 C.byref(info), hist.ctypes.data)
+        fn = self._lib.amg_solve_noalloc if noalloc else self._lib.amg_solve
+        st = fn(self._h, _dptr(b, self.n, "b"), _dptr(x, self.n, "x"), C.byref(p), C.byref(info),
+                hist.ctypes.data)
         if st not in (OK, -5, -6) or raise_on_error:
             self._check(st)
         return SolveResult(st, info.iters, info.restarts, info.reintroductions, bool(info.converged),

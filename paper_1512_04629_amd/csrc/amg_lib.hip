@@ -2259,6 +2259,73 @@ void destroy(amg_ctx* h) {
     delete h;
 }
 
+// ---------------------------------------------------------------------------
+// work memory of the allocation-free solve: a file-scope device array that
+// every GPU the library runs on holds until the process ends.  Layout, in
+// doubles: the scalar slots, the per-workgroup dot partials, then the six
+// n-vectors of the solve (r, z, p, q, the window-start x, the window's true
+// residual), each starting on a 256-byte boundary.  Every call on a GPU uses
+// that GPU's copy, so calls that overlap on one GPU race.
+// ---------------------------------------------------------------------------
+constexpr int64_t kNoAllocMaxRows = 2097152;     // 2^21: 3D Poisson 128^3
+constexpr int64_t kNoAllocScalars = 256;         // >= S_COUNT
+constexpr int64_t kNoAllocPartials = 8192;       // >= every launch's workgroup count
+constexpr int64_t kNoAllocVectors = 6;
+constexpr int64_t kNoAllocDoubles = kNoAllocScalars + kNoAllocPartials + kNoAllocVectors * kNoAllocMaxRows + 32;
+static_assert(S_COUNT <= kNoAllocScalars, "scalar slots do not fit the allocation-free work memory");
+
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+constexpr int kNoAllocMaxDevices = 64;
+
+// device address of this GPU's scratch (the array's name in host code is a
+// host-side stand-in, never passed to a kernel); looked up once per device
+// with that device current
+double* noalloc_scratch(int device) {
+    static std::mutex mu;
+    static double* addr[kNoAllocMaxDevices] = {};
+    if (device < 0 || device >= kNoAllocMaxDevices)
+        throw AmgFailure{AMG_ERR_DEVICE, "device index out of range for the allocation-free solve"};
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        int cur = 0;
+        HIP_CHECK(hipGetDevice(&cur));
+        if (cur != device) HIP_CHECK(hipSetDevice(device));
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur != device) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !ptr)
+            throw AmgFailure{AMG_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e)};
+        addr[device] = static_cast<double*>(ptr);
+    }
+    return addr[device];
+}
+
+// points the handle's solve work memory into the scratch array for the
+// lifetime of the object and restores the handle's own buffers afterwards
+struct NoAllocWork {
+    amg_ctx* h;
+    double *r, *z, *p, *q, *xw, *rt, *partials, *scal;
+    NoAllocWork(amg_ctx* hh, double* base, int64_t n) : h(hh) {
+        r = h->cg_r; z = h->cg_z; p = h->cg_p; q = h->cg_q; xw = h->xw; rt = h->rt;
+        partials = h->partials; scal = h->scal;
+        const int64_t stride = (n + 31) / 32 * 32;
+        double* v = base + kNoAllocScalars + kNoAllocPartials;
+        h->scal = base;
+        h->partials = base + kNoAllocScalars;
+        h->cg_r = v;
+        h->cg_z = v + stride;
+        h->cg_p = v + 2 * stride;
+        h->cg_q = v + 3 * stride;
+        h->xw = v + 4 * stride;
+        h->rt = v + 5 * stride;
+    }
+    ~NoAllocWork() {
+        h->cg_r = r; h->cg_z = z; h->cg_p = p; h->cg_q = q; h->xw = xw; h->rt = rt;
+        h->partials = partials; h->scal = scal;
+    }
+};
+
 template <class F>
 amg_status guarded(amg_ctx* h, F&& f) {
     try {
@@ -2524,6 +2591,42 @@ amg_status amg_solve(amg_handle h, const double* b, double* x, const amg_solve_p
         return AMG_ERR_INVALID_ARG;
     }
     return guarded(h, [&] { return solve(h, b, x, p, info, hist); });
+}
+
+amg_status amg_solve_noalloc(amg_handle h, const double* b, double* x, const amg_solve_params* params,
+                             amg_solve_info* info, double* hist) {
+    if (!h || h->lv.empty() || h->batch) return AMG_ERR_STATE;
+    if (!b || !x) return AMG_ERR_INVALID_ARG;
+    amg_solve_params p;
+    amg_solve_params_default(&p);
+    if (params) p = *params;
+    if ((p.method != AMG_PCG && p.method != AMG_STATIONARY) || p.maxit < 0 || !(p.rtol >= 0.0) ||
+        (p.adaptive && (p.k < 1 || p.s < 1)) || p.precision != 64) {
+        h->last_error = "invalid solve parameters (the allocation-free solve runs the FP64 cycle only)";
+        return AMG_ERR_INVALID_ARG;
+    }
+    const int64_t n = h->lv[0].n;
+    if (n > kNoAllocMaxRows || h->partial_cap > kNoAllocPartials) {
+        h->last_error = "the allocation-free solve takes at most " + std::to_string(kNoAllocMaxRows) +
+                        " rows; this problem has " + std::to_string(n);
+        return AMG_ERR_INVALID_ARG;
+    }
+    if (h->profiling) {
+        h->last_error = "the allocation-free solve does not run with kernel profiling enabled";
+        return AMG_ERR_STATE;
+    }
+    if (p.adaptive && h->lumping == AMG_LUMP_STRONG)
+        for (size_t l = 1; l < h->lv.size(); ++l)
+            if (h->lv[l].gamma > 0.0 && !h->lv[l].lump_thr) {
+                h->last_error = "reintroduction under strong lumping would allocate: level " + std::to_string(l) +
+                                " was sparsified with diagonal lumping";
+                return AMG_ERR_STATE;
+            }
+    return guarded(h, [&] {
+        double* base = noalloc_scratch(h->device);
+        NoAllocWork work(h, base, n);
+        return solve(h, b, x, p, info, hist);
+    });
 }
 
 amg_status amg_vcycle(amg_handle h, const double* b, double* x) {
