@@ -272,7 +272,7 @@ amg_status amg_solve(amg_handle h, const double* b, double* x, const amg_solve_p
    allocates nothing.  Its work memory (the CG vectors r, z, p, q, the
    window-start x and the window's true residual, the dot-product partials
    and the scalar slots) lives in a static device array of the library, about
-   96 MiB, that each GPU the library runs on holds until the process ends.
+   97 MiB, that each GPU the library runs on holds until the process ends.
    Limits: n <= 2,097,152 rows and precision 64, else AMG_ERR_INVALID_ARG;
    AMG_ERR_STATE while kernel profiling is on, or when an adaptive solve
    under strong lumping could reintroduce on a level sparsified with diagonal
@@ -380,10 +380,22 @@ amg_status amg_export_split(amg_handle h, int32_t l, int32_t* cf);
    does for banded operators, e.g. the 7-point stencil up to 181^3): the
    kernels then move 10 instead of 12 bytes per entry.  Results are bitwise the same either way.  enable = 0 drops the
    copies (frees their memory), 1 builds them; AMG_ERR_STATE while a batch
-   engine exists.  amg_index_width reports the bytes per column index the row
-   kernels read for matrix `which` (AMG_MAT_*) of level l: 2 or 4. */
+   engine exists.  amg_index_width reports the bytes per column index the
+   LDS-staged row kernels read for matrix `which` (AMG_MAT_*) of level l: 2 or
+   4 (they serve the FP32 cycle, and the FP64 cycle on operators without a
+   SELL-64 copy, see amg_row_format). */
 amg_status amg_set_compact_indices(amg_handle h, int32_t enable);
 amg_status amg_index_width(amg_handle h, int32_t l, int32_t which, int32_t* bytes);
+
+/* Which FP64 row kernel serves matrix `which` (AMG_MAT_*) of level l:
+   AMG_FORMAT_ROW, a subgroup of lanes per CSR row (small levels, long rows);
+   AMG_FORMAT_STREAM, CSR row blocks staged through LDS (large levels with
+   short rows); AMG_FORMAT_SELL, a SELL-64 copy built at setup (large levels
+   with short rows whose slices pad the entries by at most a tenth: one lane
+   per row, a wavefront per slice of 64 rows, coalesced loads of every
+   entry).  Results do not depend on it beyond rounding of the row sums. */
+enum { AMG_FORMAT_ROW = 0, AMG_FORMAT_STREAM = 1, AMG_FORMAT_SELL = 2 };
+amg_status amg_row_format(amg_handle h, int32_t l, int32_t which, int32_t* format);
 
 /* Kernel timing with HIP events on the handle's stream.  While enabled,
    every launch of a kernel of class kernel_class (-1: every class) on level

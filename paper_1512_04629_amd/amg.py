@@ -42,7 +42,7 @@ ABI_SYMBOLS = (
     "amg_solve_block", "amg_vcycle_block", "amg_vcycle_block32", "amg_batch_bytes", "amg_batch_create",
     "amg_batch_submit", "amg_batch_step", "amg_batch_poll", "amg_batch_collect", "amg_batch_slots",
     "amg_batch_destroy", "amg_device_bytes", "amg_level_op", "amg_num_levels", "amg_get_level", "amg_export_level", "amg_export_mask",
-    "amg_export_vector", "amg_export_split", "amg_set_compact_indices", "amg_index_width",
+    "amg_export_vector", "amg_export_split", "amg_set_compact_indices", "amg_index_width", "amg_row_format",
     "amg_profile_enable", "amg_profile_read",
     "amg_destroy", "amg_status_string", "amg_last_error",
 )
@@ -151,6 +151,7 @@ def load_library():
     lib.amg_export_split.argtypes = [vp, i32, vp]
     lib.amg_set_compact_indices.argtypes = [vp, i32]
     lib.amg_index_width.argtypes = [vp, i32, i32, P(i32)]
+    lib.amg_row_format.argtypes = [vp, i32, i32, P(i32)]
     lib.amg_profile_enable.argtypes = [vp, i32, i32, i32]
     lib.amg_profile_read.argtypes = [vp, i32, i32, P(i64), P(f64)]
     lib.amg_destroy.argtypes = [vp]
@@ -167,7 +168,8 @@ def load_library():
                  "amg_batch_step", "amg_batch_poll", "amg_batch_collect", "amg_batch_slots", "amg_device_bytes",
                  "amg_level_op", "amg_num_levels", "amg_get_level",
                  "amg_export_level", "amg_export_mask", "amg_export_vector", "amg_export_split",
-                 "amg_set_compact_indices", "amg_index_width", "amg_profile_enable", "amg_profile_read"):
+                 "amg_set_compact_indices", "amg_index_width", "amg_row_format", "amg_profile_enable",
+                 "amg_profile_read"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -519,6 +521,12 @@ class Hierarchy:
     def set_compact_indices(self, on: bool = True):
         """Builds (default) or drops the 16-bit column indices of A_l, P_l, R_l."""
         self._check(self._lib.amg_set_compact_indices(self._h, int(bool(on))))
+
+    def row_format(self, l: int, which: str) -> str:
+        """FP64 row kernel of matrix `which` of level l: "row", "stream" or "sell"."""
+        f = C.c_int32()
+        self._check(self._lib.amg_row_format(self._h, int(l), MAT[which], C.byref(f)))
+        return ("row", "stream", "sell")[f.value]
 
     def index_width(self, l: int, which: str) -> int:
         """Bytes per column index the row kernels read for matrix `which` of level l."""

@@ -78,10 +78,16 @@ struct DevMat {
     uint16_t* ci16 = nullptr;
     int32_t* cbase = nullptr;
     int idx_rb = 0;
+    // SELL-64 copy for the row operations (null: not built)
+    int32_t* sl_off = nullptr;
+    int32_t* sl_col = nullptr;
+    double* sl_val = nullptr;
+    int sl_maxw = 0;
     // direction of this operator's next cycle pass (flipped by every pass)
     mutable int next_rev = 0;
     CsrView view() const {
-        return CsrView{rp, ci, v, rows, rows ? (double)shape_nnz / rows : 1.0, ci16, cbase, idx_rb};
+        return CsrView{rp, ci, v, rows, rows ? (double)shape_nnz / rows : 1.0, ci16, cbase, idx_rb, 0,
+                       sl_off, sl_col, sl_val, sl_maxw};
     }
 };
 
@@ -225,6 +231,9 @@ void free_mat(amg_ctx* h, DevMat& m) {
     dfree(h, m.v);
     dfree(h, m.ci16);
     dfree(h, m.cbase);
+    dfree(h, m.sl_off);
+    dfree(h, m.sl_col);
+    dfree(h, m.sl_val);
     m = DevMat{};
 }
 
@@ -1740,6 +1749,38 @@ void compress_indices(amg_ctx* h, DevMat& m) {
     if (nwide > 0) drop_indices(h, m);
 }
 
+// SELL-64 copy of a large operator with short rows, kept if its padding
+// adds at most a tenth to the stored entries (structured stencils: a few
+// percent; interpolation operators, whose C and F rows alternate, not)
+constexpr double kSellMaxPadding = 0.10;
+
+void build_sell(amg_ctx* h, DevMat& m) {
+    if (m.sl_off || m.nnz <= 0 || !sell_candidate(m.view())) return;
+    const int ns = sell_slices(m.rows);
+    int32_t* off = dalloc_n<int32_t>(h, ns + 1);
+    launch_sell_widths(m.rows, m.rp, h->cnt, h->stream);
+    launch_exclusive_scan(ns, h->cnt, off, h->scan_scratch, h->stream);
+    check_launch();
+    int32_t total = 0;
+    download(h, &total, off + ns, 1);
+    sync(h);
+    if ((double)total > (1.0 + kSellMaxPadding) * (double)m.nnz) {
+        dfree(h, off);
+        return;
+    }
+    std::vector<int32_t> offs(ns + 1);
+    download(h, offs.data(), off, ns + 1);
+    sync(h);
+    int maxw = 0;
+    for (int s = 0; s < ns; ++s) maxw = std::max(maxw, (offs[s + 1] - offs[s]) / 64);
+    m.sl_off = off;
+    m.sl_col = dalloc_n<int32_t>(h, total);
+    m.sl_val = dalloc_n<double>(h, total);
+    m.sl_maxw = maxw;
+    launch_sell_fill(m.rows, m.rp, m.ci, m.v, off, m.sl_col, m.sl_val, h->stream);
+    check_launch();
+}
+
 // builds or drops the 16-bit indices of every level's A, P and R (the
 // sparsified operators keep 32-bit indices)
 void set_compact_indices(amg_ctx* h, bool on) {
@@ -1763,12 +1804,18 @@ void finish_setup(amg_ctx* h) {
     int partial_need = vector_launch_blocks(std::max(1, (int)n));
     h->missing = dalloc_n<int>(h, 1);
     h->singular = dalloc_n<int>(h, 1);
+    int nmax = 0;
+    for (auto& d : h->lv) nmax = std::max(nmax, d.n);
+    h->cnt = dalloc_n<int32_t>(h, nmax + 1);
+    h->scan_scratch = dalloc_n<int32_t>(h, scan_scratch_ints(nmax));
     for (int l = 0; l <= L; ++l) {
         DevLevel& d = h->lv[l];
         compress_indices(h, d.A);
+        build_sell(h, d.A);
         if (l < L) {
             compress_indices(h, d.P);
             compress_indices(h, d.R);
+            build_sell(h, d.R);
         }
         d.Ah = d.A;
         d.ah_alias = true;
@@ -1790,10 +1837,6 @@ void finish_setup(amg_ctx* h) {
     h->partial_cap = partial_need;
     h->partials = dalloc_n<double>(h, partial_need);
     h->scal = dalloc_n<double>(h, S_COUNT);
-    int nmax = 0;
-    for (auto& d : h->lv) nmax = std::max(nmax, d.n);
-    h->cnt = dalloc_n<int32_t>(h, nmax + 1);
-    h->scan_scratch = dalloc_n<int32_t>(h, scan_scratch_ints(nmax));
     launch_fill_f64(S_COUNT, h->scal, 0.0, h->stream);
     check_launch();
     HIP_CHECK(hipHostMalloc((void**)&h->pinned, sizeof(double) * S_COUNT, hipHostMallocDefault));
@@ -2269,7 +2312,7 @@ void destroy(amg_ctx* h) {
 // ---------------------------------------------------------------------------
 constexpr int64_t kNoAllocMaxRows = 2097152;     // 2^21: 3D Poisson 128^3
 constexpr int64_t kNoAllocScalars = 256;         // >= S_COUNT
-constexpr int64_t kNoAllocPartials = 8192;       // >= every launch's workgroup count
+constexpr int64_t kNoAllocPartials = 65536;      // >= every launch's workgroup count
 constexpr int64_t kNoAllocVectors = 6;
 constexpr int64_t kNoAllocDoubles = kNoAllocScalars + kNoAllocPartials + kNoAllocVectors * kNoAllocMaxRows + 32;
 static_assert(S_COUNT <= kNoAllocScalars, "scalar slots do not fit the allocation-free work memory");
@@ -2497,6 +2540,17 @@ amg_status amg_index_width(amg_handle h, int32_t l, int32_t which, int32_t* byte
     const DevLevel& d = h->lv[l];
     const DevMat& m = which == AMG_MAT_A ? d.A : which == AMG_MAT_AHAT ? d.Ah : which == AMG_MAT_P ? d.P : d.R;
     *bytes = m.ci16 ? 2 : 4;
+    return AMG_OK;
+}
+
+amg_status amg_row_format(amg_handle h, int32_t l, int32_t which, int32_t* format) {
+    if (!h || h->lv.empty()) return AMG_ERR_STATE;
+    if (l < 0 || l >= (int)h->lv.size() || !format || which < AMG_MAT_A || which > AMG_MAT_R)
+        return AMG_ERR_INVALID_ARG;
+    const DevLevel& d = h->lv[l];
+    const DevMat& m = which == AMG_MAT_A ? d.A : which == AMG_MAT_AHAT ? d.Ah : which == AMG_MAT_P ? d.P : d.R;
+    if (!m.rp) return AMG_ERR_INVALID_ARG;
+    *format = m.sl_off ? AMG_FORMAT_SELL : stream_block_rows(m.view()) ? AMG_FORMAT_STREAM : AMG_FORMAT_ROW;
     return AMG_OK;
 }
 

@@ -151,11 +151,9 @@ __device__ __forceinline__ void store_block_partial(double v, double* partials, 
 __global__ __launch_bounds__(kBlock) void dot_finish_kernel(int nparts, const double* __restrict__ partials,
                                                             double* __restrict__ result) {
     __shared__ double slice[kBlock];
-    const int per = (nparts + kBlock - 1) / kBlock;
-    const int lo = threadIdx.x * per;
-    const int hi = min(nparts, lo + per);
+    // thread t adds partials t, t + 256, ... in that order (coalesced)
     double s = 0.0;
-    for (int i = lo; i < hi; ++i) s += partials[i];
+    for (int i = threadIdx.x; i < nparts; i += kBlock) s += partials[i];
     slice[threadIdx.x] = s;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -635,6 +633,201 @@ void launch_stream_rb(RowOp op, const CsrT<T>& a_in, const T* g, const T* u, con
     if (op == kResidNorm || op == kJacobiDot || op == kSpmvDot) finish_dot(dot, grid, st);
 }
 
+
+// ---- SELL-64 row kernel ------------------------------------------------------
+// One wavefront per slice of 64 consecutive rows, one lane per row.  Entry k
+// of every row of a slice is one contiguous stretch (256 bytes of column
+// indices, 512 of values), and a lane requests its whole row (U entries, the
+// slice width rounded up) before it forms a product: no LDS staging and no
+// barriers, and each lane has U independent gathers in flight.  Entries
+// beyond the slice width re-read the last one (same cache line, no extra
+// traffic) and are masked out; padding inside the width carries value 0.  A
+// lane sums its row in ascending column order.  Rows wider than U are taken
+// U entries at a time.
+#ifndef AMG_SELL
+#define AMG_SELL 1
+#endif
+// one workgroup per four slices, up to 65,536 workgroups (16.7M rows; larger
+// operators loop): the hardware hands out the workgroups as others finish.
+// Measured on 3D Poisson 192^3, against 2,048, 4,096 and 8,192 workgroups
+// looping over the slices: A_1 Jacobi sweep 195 -> 171 us, A_0 residual 152
+// -> 140 us (back to back); no change at 128^3.
+#ifndef AMG_SELL_GRID_CAP
+#define AMG_SELL_GRID_CAP 65536
+#endif
+constexpr int kSellRows = 64;
+constexpr int kSellSlicesPerBlock = kBlock / kSellRows;
+
+template <bool NT, class T>
+__device__ __forceinline__ T sell_ld(const T* p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
+template <class T, int U, int OP, bool NT>
+__global__ __launch_bounds__(kBlock) void sell_kernel(CsrT<T> a, const T* __restrict__ g, const T* u,
+                                                      const T* __restrict__ dinv, T omega, T* y, T* y2,
+                                                      DotTarget dot, int nslices) {
+    const int lb = xcd_logical_block();
+    const int wv = (int)threadIdx.x / kSellRows;
+    const int lane = (int)threadIdx.x & (kSellRows - 1);
+    double contrib = 0.0;
+    for (int ls = lb * kSellSlicesPerBlock + wv; ls < nslices; ls += gridDim.x * kSellSlicesPerBlock) {
+        const int sl = a.rev ? nslices - 1 - ls : ls;
+        const int o0 = a.sl_off[sl];
+        const int w = (a.sl_off[sl + 1] - o0) / kSellRows;
+        const int r = sl * kSellRows + lane;
+        const bool act = r < a.rows;
+        T ui = T(0), gi = T(0), di = T(0);
+        if (act) {
+            if constexpr (OP != kSpmv && OP != kSpmvDot && OP != kSpmvScale) ui = u[r];
+            if constexpr (OP == kJacobi || OP == kJacobiDot || OP == kSpmvDot) gi = g[r];
+            if constexpr (OP == kJacobi || OP == kJacobiDot || OP == kZeroJacobiResid || OP == kSpmvScale)
+                di = dinv[r];
+        }
+        T acc = T(0);
+        for (int k0 = 0; k0 < w; k0 += U) {
+            int jj[U];
+            T vv[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const int p = o0 + min(k0 + k, w - 1) * kSellRows + lane;
+                jj[k] = sell_ld<NT>(a.sl_col + p);
+                vv[k] = sell_ld<NT>(a.sl_val + p);
+            }
+            T gg[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const int j = jj[k];
+                if constexpr (OP == kZeroJacobiResid) gg[k] = omega * (dinv[j] * u[j]);
+                else gg[k] = g[j];
+            }
+#pragma unroll
+            for (int k = 0; k < U; ++k)
+                if (k0 + k < w) acc += vv[k] * gg[k];
+        }
+        if (act) {
+            if constexpr (OP == kSpmv) {
+                y[r] = acc;
+            } else if constexpr (OP == kSpmvAdd) {
+                y[r] = ui + acc;
+            } else if constexpr (OP == kResid || OP == kResidNorm) {
+                const T rr = ui - acc;
+                y[r] = rr;
+                if constexpr (OP == kResidNorm) contrib += (double)rr * (double)rr;
+            } else if constexpr (OP == kJacobi || OP == kJacobiDot) {
+                const T xn = gi + omega * di * (ui - acc);
+                y[r] = xn;
+                if constexpr (OP == kJacobiDot) contrib += (double)ui * (double)xn;
+            } else if constexpr (OP == kZeroJacobiResid) {
+                y2[r] = omega * (di * ui);
+                y[r] = ui - acc;
+            } else if constexpr (OP == kSpmvDot) {
+                y[r] = acc;
+                contrib += (double)gi * (double)acc;
+            } else if constexpr (OP == kSpmvScale) {
+                y[r] = acc;
+                y2[r] = omega * (di * acc);
+            }
+        }
+    }
+    if constexpr (op_has_dot<OP>()) store_block_partial(contrib, dot.partials, lb);
+}
+
+// Matrices larger than this stream their entries with non-temporal loads:
+// they cannot stay in the 256 MB Infinity Cache between passes, and the
+// entries then do not displace the gathered vectors; smaller ones are loaded
+// normally so that a later pass can find them there.
+#ifndef AMG_SELL_NT_BYTES
+#define AMG_SELL_NT_BYTES (256ll << 20)
+#endif
+
+int sell_grid(int rows) {
+    const int nslices = (rows + kSellRows - 1) / kSellRows;
+    const int blocks = (nslices + kSellSlicesPerBlock - 1) / kSellSlicesPerBlock;
+    return round_up8(std::max(1, std::min(blocks, (int)AMG_SELL_GRID_CAP)));
+}
+
+template <class T, int U>
+void launch_sell_u(RowOp op, const CsrT<T>& a_in, const T* g, const T* u, const T* dinv, T omega, T* y, T* y2,
+                   DotTarget dot, hipStream_t st) {
+    const int nslices = (a_in.rows + kSellRows - 1) / kSellRows;
+    const int grid = sell_grid(a_in.rows);
+    CsrT<T> a = a_in;
+    // per-workgroup dot partials depend on which slices a workgroup visits
+    if (!AMG_STREAM_ALTERNATE || op == kResidNorm || op == kJacobiDot || op == kSpmvDot) a.rev = 0;
+    const long long entries = (long long)a.rows * (long long)(a.mean_row + 0.5);
+    const bool nt = entries * (long long)(sizeof(T) + 4) > (long long)AMG_SELL_NT_BYTES;
+    switch (op) {
+#define AMG_SELL_CASE(OPV)                                                                             \
+    case OPV:                                                                                          \
+        if (nt)                                                                                        \
+            hipLaunchKernelGGL((sell_kernel<T, U, OPV, true>), dim3(grid), dim3(kBlock), 0, st, a, g, u, dinv, \
+                               omega, y, y2, dot, nslices);                                            \
+        else                                                                                           \
+            hipLaunchKernelGGL((sell_kernel<T, U, OPV, false>), dim3(grid), dim3(kBlock), 0, st, a, g, u, dinv, \
+                               omega, y, y2, dot, nslices);                                            \
+        break;
+        AMG_SELL_CASE(kSpmv)
+        AMG_SELL_CASE(kSpmvAdd)
+        AMG_SELL_CASE(kResid)
+        AMG_SELL_CASE(kResidNorm)
+        AMG_SELL_CASE(kJacobi)
+        AMG_SELL_CASE(kJacobiDot)
+        AMG_SELL_CASE(kZeroJacobiResid)
+        AMG_SELL_CASE(kSpmvDot)
+        AMG_SELL_CASE(kSpmvScale)
+#undef AMG_SELL_CASE
+        default: break;
+    }
+    if (op == kResidNorm || op == kJacobiDot || op == kSpmvDot) finish_dot(dot, grid, st);
+}
+
+template <class T>
+void launch_sell(RowOp op, const CsrT<T>& a, const T* g, const T* u, const T* dinv, T omega, T* y, T* y2,
+                 DotTarget dot, hipStream_t st) {
+    const int w = a.sl_maxw;
+    if (w <= 8) launch_sell_u<T, 8>(op, a, g, u, dinv, omega, y, y2, dot, st);
+    else if (w <= 12) launch_sell_u<T, 12>(op, a, g, u, dinv, omega, y, y2, dot, st);
+    else if (w <= 16) launch_sell_u<T, 16>(op, a, g, u, dinv, omega, y, y2, dot, st);
+    else if (w <= 20) launch_sell_u<T, 20>(op, a, g, u, dinv, omega, y, y2, dot, st);
+    else launch_sell_u<T, 24>(op, a, g, u, dinv, omega, y, y2, dot, st);
+}
+
+// one wavefront per slice: 64 x the longest row
+__global__ __launch_bounds__(kBlock) void sell_width_kernel(int rows, const int32_t* __restrict__ rp,
+                                                            int32_t* __restrict__ width64) {
+    const int nslices = (rows + kSellRows - 1) / kSellRows;
+    const int sl = blockIdx.x * kSellSlicesPerBlock + (int)threadIdx.x / kSellRows;
+    if (sl >= nslices) return;
+    const int r = sl * kSellRows + ((int)threadIdx.x & (kSellRows - 1));
+    int len = r < rows ? rp[r + 1] - rp[r] : 0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) len = max(len, __shfl_xor(len, o, 64));
+    if (((int)threadIdx.x & (kSellRows - 1)) == 0) width64[sl] = len * kSellRows;
+}
+
+__global__ __launch_bounds__(kBlock) void sell_fill_kernel(int rows, const int32_t* __restrict__ rp,
+                                                           const int32_t* __restrict__ ci,
+                                                           const double* __restrict__ v,
+                                                           const int32_t* __restrict__ off,
+                                                           int32_t* __restrict__ col, double* __restrict__ val) {
+    const int nslices = (rows + kSellRows - 1) / kSellRows;
+    const int sl = blockIdx.x * kSellSlicesPerBlock + (int)threadIdx.x / kSellRows;
+    if (sl >= nslices) return;
+    const int lane = (int)threadIdx.x & (kSellRows - 1);
+    const int r = sl * kSellRows + lane;
+    const int o0 = off[sl];
+    const int w = (off[sl + 1] - o0) / kSellRows;
+    const int b = r < rows ? rp[r] : 0;
+    const int len = r < rows ? rp[r + 1] - b : 0;
+    const int last = len > 0 ? ci[b + len - 1] : 0;
+    for (int k = 0; k < w; ++k) {
+        const int p = o0 + k * kSellRows + lane;
+        col[p] = k < len ? ci[b + k] : last;
+        val[p] = k < len ? v[b + k] : 0.0;
+    }
+}
 
 // ---- vector kernels --------------------------------------------------------
 
@@ -1196,7 +1389,7 @@ int pick_width(double mean) {
     return std::max(AMG_MIN_WIDTH, std::min(64, w));
 }
 
-int max_row_launch_blocks() { return kRowGridCap; }
+int max_row_launch_blocks() { return std::max(kRowGridCap, (int)AMG_SELL_GRID_CAP); }
 
 int row_launch_blocks(int rows, int width) {
     const int rpb = kBlock / width;
@@ -1208,6 +1401,12 @@ int row_launch_blocks(int rows, int width) {
 template <class T>
 void launch_row_op_t(RowOp op, int width, const CsrT<T>& a, const T* g, const T* u,
                      const T* dinv, T omega, T* y, T* y2, DotTarget dot, hipStream_t st) {
+    if constexpr (sizeof(T) == 8) {
+        if (AMG_SELL && a.sl_off) {
+            launch_sell(op, a, g, u, dinv, omega, y, y2, dot, st);
+            return;
+        }
+    }
     if (use_stream_kernel(a)) {
         launch_stream_any(op, a, g, u, dinv, omega, y, y2, dot, st);
         return;
@@ -1417,6 +1616,21 @@ void launch_compress_index(int rows, int rb, const int32_t* rp, const int32_t* c
 }
 
 int stream_block_rows(const CsrView& a) { return use_stream_kernel(a) ? stream_rows_per_block(a.mean_row) : 0; }
+
+bool sell_candidate(const CsrView& a) { return AMG_SELL && use_stream_kernel(a); }
+
+int sell_slices(int rows) { return (rows + kSellRows - 1) / kSellRows; }
+
+void launch_sell_widths(int rows, const int32_t* rp, int32_t* width64, hipStream_t st) {
+    const int blocks = std::max(1, (sell_slices(rows) + kSellSlicesPerBlock - 1) / kSellSlicesPerBlock);
+    hipLaunchKernelGGL(sell_width_kernel, dim3(blocks), dim3(kBlock), 0, st, rows, rp, width64);
+}
+
+void launch_sell_fill(int rows, const int32_t* rp, const int32_t* ci, const double* v, const int32_t* off,
+                      int32_t* col, double* val, hipStream_t st) {
+    const int blocks = std::max(1, (sell_slices(rows) + kSellSlicesPerBlock - 1) / kSellSlicesPerBlock);
+    hipLaunchKernelGGL(sell_fill_kernel, dim3(blocks), dim3(kBlock), 0, st, rows, rp, ci, v, off, col, val);
+}
 
 void launch_exclusive_scan(int n, const int32_t* cnt, int32_t* out, int32_t* scratch,
                            hipStream_t st) {

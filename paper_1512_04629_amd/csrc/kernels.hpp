@@ -24,6 +24,15 @@ struct CsrT {
     // LDS-staged kernels without a dot product visit the row blocks in
     // descending order (each row's result does not depend on the order)
     int rev = 0;
+    // optional SELL-64 copy of the matrix (FP64 values only), used by the row
+    // operations when present: rows in slices of 64 (one wavefront, one lane
+    // per row); entry k of row 64 s + lane at sl_off[s] + 64 k + lane, slice
+    // s holding (sl_off[s + 1] - sl_off[s]) / 64 entries per row; rows
+    // shorter than their slice padded with zero values
+    const int32_t* sl_off = nullptr;
+    const int32_t* sl_col = nullptr;
+    const T* sl_val = nullptr;
+    int sl_maxw = 0;     // widest slice, host side launch configuration only
 };
 using CsrView = CsrT<double>;
 using CsrView32 = CsrT<float>;
@@ -152,6 +161,19 @@ void launch_compress_index(int rows, int rb, const int32_t* rp, const int32_t* c
 // rows per block of the LDS-staged kernels on this matrix, 0 if row
 // operations on it run on the subgroup kernels (which read 32-bit indices)
 int stream_block_rows(const CsrView& a);
+
+// SELL-64 copy of a CSR matrix (see CsrT).  launch_sell_widths writes 64
+// times the longest row of every slice into width64[0..nslices); after an
+// exclusive scan of those into off[0..nslices], launch_sell_fill writes the
+// entries: a row's entries in column order, then (value 0, column of the
+// row's last entry, or 0 for an empty row) up to its slice's width.
+int sell_slices(int rows);
+void launch_sell_widths(int rows, const int32_t* rp, int32_t* width64, hipStream_t st);
+void launch_sell_fill(int rows, const int32_t* rp, const int32_t* ci, const double* v, const int32_t* off,
+                      int32_t* col, double* val, hipStream_t st);
+// the row operations take the SELL copy of an operator that use_stream_kernel
+// would stream (large, rows of at most 24 entries on average)
+bool sell_candidate(const CsrView& a);
 
 // m_i = max_{k != i} |a_ik|
 void launch_row_max(int width, const CsrView& a, double* m, hipStream_t st);
