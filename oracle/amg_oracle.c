@@ -5,7 +5,11 @@
  * checked against.  Only the test suite, the smoke check and the CPU-baseline
  * leg of the benchmark may load it; the product never calls it and shares no
  * code with it.  Built with -O2 -ffp-contract=off (no fused multiply-add, no
- * fast-math), single threaded.
+ * fast-math), single threaded (the parity build).  A second build with
+ * -fopenmp (the timing build of the CPU baseline) runs the solve phase's row
+ * loops and the blocks of the inner products on all host cores; every row is
+ * still summed by one thread in column order and the inner products add
+ * fixed blocks in block order, so both builds give the same bits.
  *
  * Paper: Bienz, Falgout, Gropp, Olson, Schroder, "Reducing Parallel
  * Communication in Algebraic Multigrid through Sparsification" (2016).
@@ -138,14 +142,35 @@ static int mat_transpose(const Mat *a, Mat *t) {
     return OR_OK;
 }
 
+/* Inner product in fixed blocks of 8,192 entries: each block summed in index
+   order, the block sums added in block order, so that the result does not
+   depend on how many threads form the block sums. */
+#define OR_DOT_BLOCK 8192
 static double dot(int n, const double *a, const double *b) {
+    int nb = (n + OR_DOT_BLOCK - 1) / OR_DOT_BLOCK;
+    double part_small[64];
+    double *part = nb <= 64 ? part_small : (double *)malloc(sizeof(double) * (size_t)nb);
+    if (!part) return NAN;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
+    for (int k = 0; k < nb; ++k) {
+        int lo = k * OR_DOT_BLOCK, hi = lo + OR_DOT_BLOCK < n ? lo + OR_DOT_BLOCK : n;
+        double s = 0.0;
+        for (int i = lo; i < hi; ++i) s += a[i] * b[i];
+        part[k] = s;
+    }
     double s = 0.0;
-    for (int i = 0; i < n; ++i) s += a[i] * b[i];
+    for (int k = 0; k < nb; ++k) s += part[k];
+    if (part != part_small) free(part);
     return s;
 }
 
 /* y = M x, each row summed in ascending column order */
 static void spmv(const Mat *m, const double *x, double *y) {
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
     for (int i = 0; i < m->nr; ++i) {
         double s = 0.0;
         for (int p = m->rp[i]; p < m->rp[i + 1]; ++p) s += m->v[p] * x[m->ci[p]];
@@ -155,6 +180,9 @@ static void spmv(const Mat *m, const double *x, double *y) {
 
 /* r = b - M x */
 static void residual(const Mat *m, const double *b, const double *x, double *r) {
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
     for (int i = 0; i < m->nr; ++i) {
         double s = 0.0;
         for (int p = m->rp[i]; p < m->rp[i + 1]; ++p) s += m->v[p] * x[m->ci[p]];
@@ -983,6 +1011,9 @@ int or_reintroduce(Hier *h, int s, double gamma_min, int *first_changed) {
 /* ------------------------------------------------------------------------ */
 static void jacobi(const Mat *a, const double *b, double *x, double *tmp, double omega) {
     residual(a, b, x, tmp);
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
     for (int i = 0; i < a->nr; ++i) x[i] = x[i] + omega * tmp[i] / diag_of(a, i);
 }
 
@@ -1061,6 +1092,9 @@ static void vcycle(Hier *h, const double *b0, double *x0) {
     for (int l = L - 1; l >= 0; --l) {
         Level *lv = &h->lv[l];
         spmv(&lv->P, h->x[l + 1], h->r[l]);
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
         for (int i = 0; i < lv->A.nr; ++i) h->x[l][i] += h->r[l][i];
         relax(h, &lv->Ah, h->b[l], h->x[l], h->r[l], 0, h->nu_post);
     }
@@ -1119,8 +1153,13 @@ int or_solve(Hier *h, const double *b, double *x, int method, double tol, int ma
             double pq = dot(n, p, q);
             if (!(pq > 0.0) || !isfinite(pq)) { rc = OR_EBREAK; break; }
             double alpha = rz / pq;
-            for (int i = 0; i < n; ++i) x[i] = x[i] + alpha * p[i];
-            for (int i = 0; i < n; ++i) r[i] = r[i] - alpha * q[i];
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
+            for (int i = 0; i < n; ++i) {
+                x[i] = x[i] + alpha * p[i];
+                r[i] = r[i] - alpha * q[i];
+            }
         } else {
             vcycle(h, b, x);
             residual(A, b, x, r);
@@ -1166,6 +1205,9 @@ int or_solve(Hier *h, const double *b, double *x, int method, double tol, int ma
                 memcpy(p, z, sizeof(double) * (size_t)n);
             } else {
                 double beta = rz_new / rz;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
                 for (int i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
             }
             rz = rz_new;

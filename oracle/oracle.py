@@ -18,6 +18,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "amg_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
+# timing build of the CPU baseline: the same source with OpenMP row loops
+LIB_OMP = os.path.join(HERE, "liboracle_omp.so")
 
 CFLAGS = ["-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
 
@@ -26,13 +28,15 @@ OK, NOTHING, EINVAL, EMATRIX, ENOMEM, ENOTCONV, EBREAK = 0, 1, -1, -2, -3, -5, -
 WHICH = {"A": 0, "AHAT": 1, "P": 2, "R": 3, "S": 4}
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (single-threaded, no FMA contraction)."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, SRC, "-lm"])
-        os.replace(tmp, LIB)
-    return LIB
+def build(force: bool = True, parallel: bool = False) -> str:
+    """Compile the oracle with gcc (no FMA contraction): the single-threaded
+    parity build, or with parallel=True the OpenMP timing build (same bits)."""
+    lib = LIB_OMP if parallel else LIB
+    if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(SRC):
+        tmp = lib + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, *(["-fopenmp"] if parallel else []), "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, lib)
+    return lib
 
 
 class _Info(C.Structure):
@@ -40,16 +44,16 @@ class _Info(C.Structure):
                 ("converged", C.c_int), ("relres", C.c_double), ("rho_avg", C.c_double)]
 
 
-_lib = None
+_libs = {}
 COARSENINGS = {"rs": 0, "pmis": 1}
 
 
-def _load():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-            build(force=True)
-        lib = C.CDLL(LIB)
+def _load(parallel: bool = False):
+    if parallel not in _libs:
+        path = LIB_OMP if parallel else LIB
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(SRC):
+            build(force=True, parallel=parallel)
+        lib = C.CDLL(path)
         P = C.c_void_p
         ip = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
         dp = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
@@ -82,8 +86,8 @@ def _load():
         lib.or_level_op.argtypes = [P, C.c_int, C.c_int, dp, dp, dp]
         lib.or_solve.argtypes = [P, dp, dp, C.c_int, C.c_double, C.c_int, C.c_int, C.c_int,
                                  C.c_int, C.c_double, C.c_double, C.POINTER(_Info), P]
-        _lib = lib
-    return _lib
+        _libs[parallel] = lib
+    return _libs[parallel]
 
 
 @dataclass
@@ -143,14 +147,15 @@ class OracleAMG:
     """Oracle hierarchy: Galerkin setup, Sparse Galerkin sparsify, solves."""
 
     def __init__(self, A, theta=0.25, max_coarse=49, max_levels=25, omega=2.0 / 3.0,
-                 nu_pre=1, nu_post=1, nongalerkin_gamma=None, coarsening="rs", seed=0):
+                 nu_pre=1, nu_post=1, nongalerkin_gamma=None, coarsening="rs", seed=0, parallel=False):
         """nongalerkin_gamma: per-level tolerances of the method of non-Galerkin
         coarse grids (each coarse product sparsified during setup); None for the
         Galerkin hierarchy.  coarsening: "rs" (Ruge-Stueben first pass) or
-        "pmis" (weights of level l from the SplitMix64 stream seed + l)."""
+        "pmis" (weights of level l from the SplitMix64 stream seed + l).
+        parallel: the OpenMP timing build (the same results, bit for bit)."""
         if coarsening not in COARSENINGS:
             raise ValueError(f"unknown coarsening {coarsening!r}")
-        lib = _load()
+        lib = _load(parallel)
         self._lib = lib
         self.n = int(A.n)
         h = C.c_void_p()

@@ -208,3 +208,20 @@ def test_adaptive_diverged_window_reverts(oracle_mod):
     assert ref.reintroduce(s=1)[0] == 0
     x_ref, _ = ref.solve(b, method=0, tol=1e-14, maxit=2)   # from the reverted x = 0
     assert x_ad.tobytes() == x_ref.tobytes()
+
+
+def test_openmp_timing_build_gives_the_same_bits(oracle_mod):
+    """The OpenMP timing build of the oracle (the CPU baseline) returns the
+    parity build's results bit for bit: row loops are split between threads
+    but every row and every fixed 8,192-entry block of an inner product is
+    summed by one thread in index order."""
+    A = I.poisson3d(24)           # 13,824 rows: two dot-product blocks
+    b = I.rhs(A.n, 2)
+    out = []
+    for parallel in (False, True):
+        h = oracle_mod.OracleAMG(A, parallel=parallel)
+        h.sparsify_from(0.1, 2)
+        x, res = h.solve(b, method=1, tol=1e-10, maxit=100, adaptive=True, k=3, s=1)
+        xs, rs = h.solve(b, method=0, tol=1e-8, maxit=100)
+        out.append((x.tobytes(), res.iters, res.hist.tobytes(), xs.tobytes(), rs.iters))
+    assert out[0] == out[1]
