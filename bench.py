@@ -38,17 +38,17 @@ def log(*a):
 
 
 def launch_bytes(h, kernel: str, level: int) -> int:
-    """Algorithmic HBM bytes of one launch: FP64 values, the column indices in
-    the width the kernel reads (4 bytes, or 2 where the library keeps 16-bit
-    indices; their per-row-block bases, at most a sixteenth of the row
-    pointers' bytes, are not counted), each array entry counted once (a
-    gathered vector is counted as n entries)."""
+    """Algorithmic HBM bytes of one launch: what the method must move, FP64
+    values and int32 column indices and row pointers, each array entry counted
+    once (a gathered vector is counted as n entries).  This is the figure the
+    roofline fraction uses, whatever storage the kernel reads (a SELL-64 copy
+    with padding, 16-bit column offsets): the HBM counters report that."""
     li = h.level_info(level)
     n, nnz_hat, nc, nnz_p = li["n"], li["nnz_hat"], li["n_coarse"], li["nnz_P"]
     nnz_a = li["nnz"]
 
     def entry(which):
-        return 8 + h.index_width(level, which)
+        return 12
 
     if kernel == "JACOBI":
         # x gathered, b, dinv read, x' written
@@ -98,16 +98,18 @@ def kernel_source_sha(src: str = KERNEL_SRC) -> str:
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
 
 
-def traffic_for(kernel: str, level: int, path: str = TRAFFIC_FILE, src: str = KERNEL_SRC):
+def traffic_for(kernel: str, level: int, path: str = TRAFFIC_FILE, src: str = KERNEL_SRC, N: int | None = None):
     """HBM bytes per launch from committed rocprofv3 counter runs, or None if
-    there are none for this kernel or the kernel source changed since."""
+    there are none for this kernel (on the 3D Poisson N^3 hierarchy, if N is
+    given) or the kernel source changed since."""
     try:
         data = json.load(open(path))
     except (OSError, ValueError):
         return None
     if data.get("kernel_source_sha") != kernel_source_sha(src):
         return None
-    ent = data.get("kernels", {}).get(f"{kernel}@{level}")
+    key = f"{kernel}@{level}" if N is None else f"N{N}:{kernel}@{level}"
+    ent = data.get("kernels", {}).get(key)
     if not ent:
         return None
     return ent.get("hbm_bytes_per_launch")
@@ -122,6 +124,10 @@ def main():
     ap.add_argument("--gamma", type=float, default=0.1, help="drop tolerance on levels >= 2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--seeds", type=int, default=8, help="right-hand sides of the gamma comparison")
+    ap.add_argument("--reps", type=int, default=5, help="timed solves per right-hand side in the gamma comparison")
+    ap.add_argument("--hbm-steps", type=int, default=10, help="timed steps of the 192^3 HBM-only figure")
+    ap.add_argument("--no-hbm-only", action="store_true", help="skip the 192^3 HBM-only figure")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the per-gamma time-to-solution comparison (short profiler runs)")
     ap.add_argument("--budget-gb", type=float, default=32.0,
@@ -167,6 +173,89 @@ def main():
         return bench_lumping(args)
     if args.workload == "methods":
         return bench_methods(args)
+    return bench_poisson(args)
+
+
+def crossing_margin(hist, tol: float) -> float:
+    """Smallest |log(rho_k / tol)| over the stop tests a solve took (rho_k its
+    relative residual after iteration k): how far its iteration count is from
+    flipping under a rounding-level change of the residuals."""
+    import numpy as np
+    h = np.asarray(hist, float)
+    rel = h[1:] / h[0]
+    rel = rel[np.isfinite(rel) & (rel > 0)]
+    return float(np.min(np.abs(np.log(rel / tol)))) if rel.size else float("inf")
+
+
+def host_description() -> dict:
+    """The host the CPU baseline ran on: nproc, the cores this process may use,
+    and lscpu's model, sockets, cores and threads."""
+    import subprocess
+    d = {"nproc": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0)),
+         "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core", "CPU(s)",
+                             "CPU max MHz"):
+                d["lscpu " + k.strip()] = v.strip()
+    except (OSError, subprocess.SubprocessError):
+        d["lscpu"] = "unavailable"
+    return d
+
+
+def omp_threads() -> int:
+    v = os.environ.get("OMP_NUM_THREADS")
+    try:
+        return max(1, int(v.split(",")[0])) if v else len(os.sched_getaffinity(0))
+    except ValueError:
+        return len(os.sched_getaffinity(0))
+
+
+def dominant_kernel(h, step):
+    """(kernel class, level) with the most HIP-event time over one step."""
+    h.profile_enable(True)
+    step()
+    best = None
+    for kern in ("JACOBI", "JACOBI_ZERO", "RESIDUAL", "RESTRICT", "INTERP", "SPMV_DOT"):
+        for l in range(h.nlev):
+            cnt, ms = h.profile_read(kern, l)
+            if cnt and (best is None or ms > best[2]):
+                best = (kern, l, ms, cnt)
+    h.profile_enable(False)
+    return best[0], best[1]
+
+
+def timed_steps(h, step, steps, warmup, kern, level):
+    """Times `steps` steps after `warmup` untimed ones; the launches of one
+    kernel class on one level are bracketed by HIP events on the handle's
+    stream.  (ms per step, last result, launches, ms in those launches)."""
+    import torch
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    h.profile_enable(True, kern, level)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    cnt, ms_total = h.profile_read(kern, level)
+    h.profile_enable(False)
+    return elapsed / steps * 1e3, res, cnt, ms_total
+
+
+def bench_poisson(args):
+    """The headline workload: 3D Poisson 7-point N^3, Sparse Galerkin
+    sparsification at gamma on levels >= 2 + adaptive AMG-PCG to 1e-8."""
+    import numpy as np
+    import torch
+
+    from paper_1512_04629_amd import amg
+    from paper_1512_04629_amd import inputs as I
+
     N = args.N
     A = I.poisson3d(N)
     b_host = I.rhs(A.n, 2)
@@ -181,65 +270,69 @@ def main():
     setup_s = time.perf_counter() - t0
     log(f"[bench] setup done in {setup_s:.2f} s, {h.nlev} levels")
 
-    def step(gamma):
+    def step(gamma=args.gamma, rhs=b):
         h.sparsify(gamma, 2)
         x.zero_()
-        return h.solve(b, x, **solve_kw)
+        return h.solve(rhs, x, **solve_kw)
 
-    # sparsified vs Galerkin: time-to-1e-8 per gamma
+    # sparsified vs Galerkin: time-to-1e-8 per gamma over several right-hand
+    # sides, with the crossing margin of every solve's iteration count
     compare = {}
-    for gamma in (() if args.no_compare else (0.0, 0.01, 0.1)):
-        for _ in range(2):
-            res = step(gamma)
-        torch.cuda.synchronize()
-        times = []
-        for _ in range(10):
-            t0 = time.perf_counter()
-            res = step(gamma)
+    seeds = list(range(2, 2 + args.seeds))
+    rhs = {sd: torch.as_tensor(I.rhs(A.n, sd)).cuda() for sd in seeds}
+    for gamma in (() if args.no_compare else (0.0, 0.01, 0.1, 1.0)):
+        h.sparsify(gamma, 2)
+        bpc = h.bytes_per_cycle()
+        nnz_levels = [h.level_info(l)["nnz_hat"] for l in range(h.nlev)]
+        per_seed = []
+        for sd in seeds:
+            res = step(gamma, rhs[sd])
             torch.cuda.synchronize()
-            times.append((time.perf_counter() - t0) * 1e3)
-        ms = float(np.median(times))
+            times = []
+            for _ in range(args.reps):
+                t0 = time.perf_counter()
+                res = step(gamma, rhs[sd])
+                torch.cuda.synchronize()
+                times.append((time.perf_counter() - t0) * 1e3)
+            ms = float(np.median(times))
+            per_seed.append(dict(seed=sd, ms=round(ms, 3), iters=res.iters, reintroductions=res.reintroductions,
+                                 relres=res.relres, converged=res.converged,
+                                 margin=round(crossing_margin(res.hist, solve_kw["tol"]), 5),
+                                 ms_per_iter=round(ms / max(res.iters, 1), 4)))
+        med = lambda k: float(np.median([r[k] for r in per_seed]))  # noqa: E731
         compare[str(gamma)] = dict(
-            ms_to_1e8=round(ms, 3), ms_min=round(min(times), 3), reps=len(times),
-            iters=res.iters, reintroductions=res.reintroductions,
-            relres=res.relres, converged=res.converged,
-            nnz_per_level=[h.level_info(l)["nnz_hat"] for l in range(h.nlev)],
-            gamma_after=[h.gamma(l) for l in range(h.nlev)],
-            bytes_per_vcycle=h.bytes_per_cycle())
-        log(f"[bench] gamma={gamma}: {ms:.2f} ms, {res.iters} iters, relres {res.relres:.2e}")
+            ms_to_1e8=round(med("ms"), 3), ms_min=round(min(r["ms"] for r in per_seed), 3),
+            iters=med("iters"), ms_per_iter=round(med("ms_per_iter"), 4), reps=args.reps,
+            min_margin=min(r["margin"] for r in per_seed), converged=all(r["converged"] for r in per_seed),
+            nnz_per_level=nnz_levels, bytes_per_vcycle=bpc, per_seed=per_seed)
+        log(f"[bench] gamma={gamma}: median {med('ms'):.2f} ms, {med('iters'):.0f} iters, "
+            f"{med('ms_per_iter'):.3f} ms/iter, {bpc / 1e6:.0f} MB/cycle, "
+            f"min margin {compare[str(gamma)]['min_margin']:.3g}")
+    summary = None
+    g0, gg = compare.get("0.0"), compare.get(str(args.gamma))
+    if g0 and gg:
+        wins = sum(1 for a, c in zip(g0["per_seed"], gg["per_seed"]) if c["ms"] < a["ms"])
+        fewer = sum(1 for a, c in zip(g0["per_seed"], gg["per_seed"]) if c["iters"] < a["iters"])
+        more = sum(1 for a, c in zip(g0["per_seed"], gg["per_seed"]) if c["iters"] > a["iters"])
+        summary = dict(
+            gamma=args.gamma, seeds=len(seeds),
+            speedup_median=round(g0["ms_to_1e8"] / gg["ms_to_1e8"], 4),
+            per_iteration_speedup=round(g0["ms_per_iter"] / gg["ms_per_iter"], 4),
+            iteration_ratio=round(g0["iters"] / gg["iters"], 4),
+            bytes_per_cycle_ratio=round(gg["bytes_per_vcycle"] / g0["bytes_per_vcycle"], 4),
+            seeds_faster=wins, seeds_fewer_iterations=fewer, seeds_more_iterations=more)
+        log(f"[bench] gamma={args.gamma} vs Galerkin: {summary}")
 
-    # find the dominant kernel (class, level) by HIP-event time over one step
-    h.profile_enable(True)
-    step(args.gamma)
-    best = None
-    for kern in ("JACOBI", "JACOBI_ZERO", "RESIDUAL", "RESTRICT", "INTERP", "SPMV_DOT"):
-        for l in range(h.nlev):
-            cnt, ms = h.profile_read(kern, l)
-            if cnt and (best is None or ms > best[2]):
-                best = (kern, l, ms, cnt)
-    h.profile_enable(False)
-    dom_kernel, dom_level = best[0], best[1]
+    # timed region: K steps (right-hand side seed 2), the dominant kernel's
+    # launches bracketed by HIP events
+    dom_kernel, dom_level = dominant_kernel(h, step)
     log(f"[bench] dominant kernel {dom_kernel} on level {dom_level}")
-
-    # timed region: K steps, the dominant kernel bracketed by HIP events
-    for _ in range(args.warmup):
-        step(args.gamma)
-    torch.cuda.synchronize()
-    h.profile_enable(True, dom_kernel, dom_level)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        res = step(args.gamma)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    cnt, ms_total = h.profile_read(dom_kernel, dom_level)
-    h.profile_enable(False)
-    ms_per_step = elapsed / args.steps * 1e3
-    value = args.steps / elapsed
+    ms_per_step, res, cnt, ms_total = timed_steps(h, step, args.steps, args.warmup, dom_kernel, dom_level)
+    value = 1e3 / ms_per_step
     per_launch_s = ms_total / max(cnt, 1) / 1e3
     nbytes = launch_bytes(h, dom_kernel, dom_level)
     achieved = nbytes / per_launch_s / 1e9
-    traffic = traffic_for(dom_kernel, dom_level)
+    traffic = traffic_for(dom_kernel, dom_level, N=N)
     log(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step; {dom_kernel}@{dom_level}: "
         f"{per_launch_s * 1e6:.1f} us/launch, {achieved:.0f} GB/s")
 
@@ -289,10 +382,20 @@ def main():
 
     # SpMV bandwidth of the fine-level operator (the CG product A p)
     h.profile_enable(True, "SPMV_DOT", 0)
-    step(args.gamma)
+    step()
     c2, m2 = h.profile_read("SPMV_DOT", 0)
     h.profile_enable(False)
     spmv_gbs = launch_bytes(h, "SPMV_DOT", 0) / (m2 / c2 / 1e3) / 1e9 if c2 else None
+    nlev = h.nlev
+    h.close()
+    del x, b, rhs
+
+    # the same step on 3D Poisson 192^3, whose fine operators (A_0 592 MB,
+    # A_1 926 MB of algorithmic bytes) are several times the 256 MB Infinity
+    # Cache: its dominant kernel's rate is an HBM-only figure
+    hbm_only = None
+    if N < 192 and not args.no_hbm_only:
+        hbm_only = hbm_only_roofline(args, 192)
 
     out = {
         "metric": "solves/s to 1e-8 relative residual (Sparse Galerkin sparsify + adaptive AMG-PCG); "
@@ -313,15 +416,15 @@ def main():
                         f"RS theta=0.25, direct interpolation, coarsen to <50 rows; Sparse Galerkin "
                         f"gamma={args.gamma} on levels>=2 with diagonal lumping; V(1,1) Jacobi "
                         f"omega=2/3; adaptive AMG-PCG (k=3, s=1, rho_max=0.5) to 1e-8",
-            "levels": h.nlev,
+            "levels": nlev,
             "gamma": args.gamma,
         },
         "iters": res.iters,
         "relres": res.relres,
         "setup_s": round(setup_s, 3),
         "time_to_1e8_ms": compare,
-        "speedup_vs_galerkin": round(compare["0.0"]["ms_to_1e8"] / compare[str(args.gamma)]["ms_to_1e8"], 4)
-        if str(args.gamma) in compare and "0.0" in compare else None,
+        "sparsified_vs_galerkin": summary,
+        "speedup_vs_galerkin": summary["speedup_median"] if summary else None,
         "spmv_gbs_level0": round(spmv_gbs, 1) if spmv_gbs else None,
         "practical_ceiling": {"copy_gbs": round(copy_gbs, 1),
                               "how": "1 GiB device-to-device copy, bytes read + written per second"},
@@ -334,37 +437,98 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
             "bytes_per_launch": nbytes,
+            "bytes_rule": "12 nnz + 4 (n+1) + 32 n (Jacobi; 24 n residual): FP64 values, int32 indices",
             "us_per_launch": round(per_launch_s * 1e6, 3),
             "launches": cnt,
             "alone": cache_runs,
+            "hbm_only": hbm_only,
         },
     }
-
     if not args.no_cpu_baseline:
-        from oracle import oracle as O
-        log("[bench] CPU baseline: oracle setup (untimed) ...")
-        o = O.OracleAMG(A)
-        steps_done = 0
-        t0 = time.perf_counter()
-        while steps_done < args.cpu_steps:
-            o.sparsify_from(args.gamma, 2)
-            o.solve(b_host, method=O.PCG, tol=1e-8, maxit=200, adaptive=True, k=3, s=1)
-            steps_done += 1
-            if time.perf_counter() - t0 > 30.0:
-                break
-        cpu_s = time.perf_counter() - t0
-        out["cpu_baseline"] = {
-            "value": round(steps_done / cpu_s, 5),
-            "unit": "solves/s",
-            "cores": 1,
-            "kind": "oracle",
-            "sample": f"{steps_done} full steps (sparsify gamma={args.gamma} + adaptive PCG to 1e-8) "
-                      f"of the same {N}^3 workload, single-threaded C oracle, setup excluded",
-        }
-        log(f"[bench] CPU baseline {steps_done / cpu_s:.4f} solves/s")
-
-    h.close()
+        out["cpu_baseline"] = cpu_baseline(args, A, b_host)
     print(json.dumps(out), flush=True)
+
+
+def hbm_only_roofline(args, N2: int) -> dict:
+    """The headline step on 3D Poisson N2^3: its dominant kernel timed with
+    HIP events over `steps` timed steps, against the algorithmic bytes."""
+    import torch
+
+    from paper_1512_04629_amd import amg
+    from paper_1512_04629_amd import inputs as I
+
+    A = I.poisson3d(N2)
+    log(f"[bench] HBM-only figure: setup 3D Poisson {N2}^3 (n={A.n}, nnz={A.nnz})")
+    h = amg.Hierarchy(A)
+    b = torch.as_tensor(I.rhs(A.n, 2)).cuda()
+    x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    kw = dict(method=amg.PCG, tol=1e-8, maxit=200, adaptive=True, k=3, s=1, rho_max=0.5, gamma_min=0.01)
+
+    def step():
+        h.sparsify(args.gamma, 2)
+        x.zero_()
+        return h.solve(b, x, **kw)
+
+    kern, lvl = dominant_kernel(h, step)
+    ms_step, res, cnt, ms_total = timed_steps(h, step, args.hbm_steps, 2, kern, lvl)
+    per = ms_total / max(cnt, 1) / 1e3
+    nb = launch_bytes(h, kern, lvl)
+    li = h.level_info(lvl)
+    ach = nb / per / 1e9
+    log(f"[bench] {N2}^3: {ms_step:.3f} ms/step, {res.iters} iters; {kern}@{lvl}: {per * 1e6:.1f} us, "
+        f"{ach:.0f} GB/s, frac {ach / HBM_PEAK_GBS:.3f}")
+    out = dict(workload=f"3D Poisson 7-point {N2}^3 (n={A.n}, nnz={A.nnz}), the same step", kernel=f"{kern} level {lvl}",
+               operator_mb=round(12 * li["nnz_hat"] / 1e6, 1), bytes_per_launch=nb, us_per_launch=round(per * 1e6, 3),
+               launches=cnt, achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 4),
+               traffic=traffic_for(kern, lvl, N=N2), ms_per_step=round(ms_step, 4), iters=res.iters,
+               steps=args.hbm_steps)
+    h.close()
+    return out
+
+
+def cpu_baseline(args, A, b_host) -> dict:
+    """The oracle on the host's cores, setup excluded: the OpenMP timing build
+    on every core this process may use, and the single-threaded parity build,
+    each on a bounded number of full steps (sparsify + adaptive PCG); both
+    builds must return the same bits."""
+    from oracle import oracle as O
+    runs = {}
+    for parallel in (True, False):
+        if not parallel and A.n > 3_000_000:
+            continue
+        label = "openmp" if parallel else "single_thread"
+        log(f"[bench] CPU baseline ({label}): oracle setup (untimed) ...")
+        o = O.OracleAMG(A, parallel=parallel)
+        done, xs = 0, None
+        t0 = time.perf_counter()
+        while done < args.cpu_steps:
+            o.sparsify_from(args.gamma, 2)
+            xs, r = o.solve(b_host, method=O.PCG, tol=1e-8, maxit=200, adaptive=True, k=3, s=1)
+            done += 1
+            if time.perf_counter() - t0 > 20.0:
+                break
+        sec = time.perf_counter() - t0
+        runs[label] = dict(value=round(done / sec, 5), steps=done, seconds=round(sec, 3),
+                           cores=omp_threads() if parallel else 1, x=xs)
+        log(f"[bench] CPU baseline ({label}): {done / sec:.4f} solves/s over {done} steps")
+        del o
+    same = None
+    if "single_thread" in runs:
+        same = runs["openmp"]["x"].tobytes() == runs["single_thread"]["x"].tobytes()
+    for r in runs.values():
+        r.pop("x")
+    omp = runs["openmp"]
+    return {
+        "value": omp["value"],
+        "unit": "solves/s",
+        "cores": omp["cores"],
+        "kind": "oracle",
+        "sample": f"{omp['steps']} full steps (sparsify gamma={args.gamma} + adaptive PCG to 1e-8) of the same "
+                  f"workload, C oracle OpenMP timing build, setup excluded",
+        "single_thread": runs.get("single_thread"),
+        "same_bits_as_single_thread": same,
+        "host": host_description(),
+    }
 
 
 def bench_setup(args):

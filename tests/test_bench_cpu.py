@@ -49,8 +49,10 @@ def test_workloads_listed():
 
 @pytest.mark.parametrize("idx", [4, 2])
 def test_launch_bytes_follow_the_kernel_table(idx):
+    """Algorithmic bytes: FP64 values and int32 indices whatever index width
+    the kernel reads."""
     h = StubHierarchy({(0, "A"): idx, (0, "AHAT"): idx, (0, "R"): idx, (0, "P"): idx, (1, "AHAT"): idx})
-    e = 8 + idx
+    e = 12
     # Jacobi: entries, row pointers, x gathered, b, dinv read, x' written
     assert bench.launch_bytes(h, "JACOBI", 0) == e * 7000 + 4 * 1001 + 32 * 1000
     # zero-guess residual: the prescaled sweep gathered, b read, r written
@@ -76,12 +78,24 @@ def test_traffic_reported_only_for_the_measured_source(tmp_path):
     sha = bench.kernel_source_sha(str(src))
     counters = tmp_path / "counters.json"
     counters.write_text(json.dumps({"kernel_source_sha": sha, "kernels": {
-        "JACOBI@1": {"hbm_bytes_per_launch": 123456}}}))
+        "JACOBI@1": {"hbm_bytes_per_launch": 123456}, "N192:JACOBI@1": {"hbm_bytes_per_launch": 654321}}}))
     assert bench.traffic_for("JACOBI", 1, str(counters), str(src)) == 123456
+    assert bench.traffic_for("JACOBI", 1, str(counters), str(src), N=192) == 654321
+    assert bench.traffic_for("JACOBI", 1, str(counters), str(src), N=128) is None
     assert bench.traffic_for("JACOBI", 0, str(counters), str(src)) is None
     src.write_text("// kernel source, changed\n")
     assert bench.traffic_for("JACOBI", 1, str(counters), str(src)) is None
     assert bench.traffic_for("JACOBI", 1, str(tmp_path / "missing.json"), str(src)) is None
+
+
+def test_crossing_margin_and_host_description():
+    import math
+    # relative residuals 0.1, 1e-5, 2e-9 against tol 1e-8: the closest is the last
+    assert abs(bench.crossing_margin([1.0, 0.1, 1e-5, 2e-9], 1e-8) - abs(math.log(0.2))) < 1e-12
+    assert bench.crossing_margin([1.0], 1e-8) == float("inf")
+    d = bench.host_description()
+    assert d["nproc"] >= 1 and d["affinity_cpus"] >= 1
+    assert bench.omp_threads() >= 1
 
 
 def test_fp32_cycle_launch_bytes():
