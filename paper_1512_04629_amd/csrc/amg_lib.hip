@@ -78,16 +78,19 @@ struct DevMat {
     uint16_t* ci16 = nullptr;
     int32_t* cbase = nullptr;
     int idx_rb = 0;
-    // SELL-64 copy for the row operations (null: not built)
+    // SELL-64 copy for the row operations (null: not built); its columns in
+    // 32 bits (sl_col) or as 16-bit offsets from a base per slice
     int32_t* sl_off = nullptr;
     int32_t* sl_col = nullptr;
     double* sl_val = nullptr;
     int sl_maxw = 0;
+    uint16_t* sl_col16 = nullptr;
+    int32_t* sl_base = nullptr;
     // direction of this operator's next cycle pass (flipped by every pass)
     mutable int next_rev = 0;
     CsrView view() const {
         return CsrView{rp, ci, v, rows, rows ? (double)shape_nnz / rows : 1.0, ci16, cbase, idx_rb, 0,
-                       sl_off, sl_col, sl_val, sl_maxw};
+                       sl_off, sl_col, sl_val, sl_maxw, sl_col16, sl_base};
     }
 };
 
@@ -234,6 +237,8 @@ void free_mat(amg_ctx* h, DevMat& m) {
     dfree(h, m.sl_off);
     dfree(h, m.sl_col);
     dfree(h, m.sl_val);
+    dfree(h, m.sl_col16);
+    dfree(h, m.sl_base);
     m = DevMat{};
 }
 
@@ -1779,6 +1784,35 @@ void build_sell(amg_ctx* h, DevMat& m) {
     m.sl_maxw = maxw;
     launch_sell_fill(m.rows, m.rp, m.ci, m.v, off, m.sl_col, m.sl_val, h->stream);
     check_launch();
+    if (!h->compact_idx) return;
+    // 16-bit offsets from a base per slice where every slice's columns span
+    // at most 65535 (banded operators); then the 32-bit columns go
+    m.sl_col16 = dalloc_n<uint16_t>(h, total);
+    m.sl_base = dalloc_n<int32_t>(h, ns);
+    launch_fill_u32(1, reinterpret_cast<unsigned*>(h->missing), 0u, h->stream);
+    launch_sell_compress(m.rows, off, m.sl_col, m.sl_col16, m.sl_base, h->missing, h->stream);
+    check_launch();
+    int nwide = 0;
+    download(h, &nwide, h->missing, 1);
+    sync(h);
+    if (nwide > 0) {
+        dfree(h, m.sl_col16);
+        dfree(h, m.sl_base);
+        m.sl_col16 = nullptr;
+        m.sl_base = nullptr;
+    } else {
+        dfree(h, m.sl_col);
+        m.sl_col = nullptr;
+    }
+}
+
+void drop_sell(amg_ctx* h, DevMat& m) {
+    for (void* p : {(void*)m.sl_off, (void*)m.sl_col, (void*)m.sl_val, (void*)m.sl_col16, (void*)m.sl_base})
+        dfree(h, p);
+    m.sl_off = m.sl_col = m.sl_base = nullptr;
+    m.sl_val = nullptr;
+    m.sl_col16 = nullptr;
+    m.sl_maxw = 0;
 }
 
 // builds or drops the 16-bit indices of every level's A, P and R (the
@@ -1790,6 +1824,11 @@ void set_compact_indices(amg_ctx* h, bool on) {
             if (!m->rp) continue;
             if (on) compress_indices(h, *m);
             else drop_indices(h, *m);
+            if (m->sl_off && (m->sl_col16 != nullptr) != on) {
+                // rebuilt in the other column width
+                drop_sell(h, *m);
+                build_sell(h, *m);
+            }
         }
         if (d.ah_alias) d.Ah = d.A;
     }
@@ -2539,7 +2578,7 @@ amg_status amg_index_width(amg_handle h, int32_t l, int32_t which, int32_t* byte
         return AMG_ERR_INVALID_ARG;
     const DevLevel& d = h->lv[l];
     const DevMat& m = which == AMG_MAT_A ? d.A : which == AMG_MAT_AHAT ? d.Ah : which == AMG_MAT_P ? d.P : d.R;
-    *bytes = m.ci16 ? 2 : 4;
+    *bytes = m.sl_off ? (m.sl_col16 ? 2 : 4) : m.ci16 ? 2 : 4;
     return AMG_OK;
 }
 

@@ -664,7 +664,7 @@ __device__ __forceinline__ T sell_ld(const T* p) {
     else return *p;
 }
 
-template <class T, int U, int OP, bool NT>
+template <class T, int U, int OP, bool NT, bool IDX16>
 __global__ __launch_bounds__(kBlock) void sell_kernel(CsrT<T> a, const T* __restrict__ g, const T* u,
                                                       const T* __restrict__ dinv, T omega, T* y, T* y2,
                                                       DotTarget dot, int nslices) {
@@ -676,6 +676,7 @@ __global__ __launch_bounds__(kBlock) void sell_kernel(CsrT<T> a, const T* __rest
         const int sl = a.rev ? nslices - 1 - ls : ls;
         const int o0 = a.sl_off[sl];
         const int w = (a.sl_off[sl + 1] - o0) / kSellRows;
+        const int cb = IDX16 ? a.sl_base[sl] : 0;
         const int r = sl * kSellRows + lane;
         const bool act = r < a.rows;
         T ui = T(0), gi = T(0), di = T(0);
@@ -692,7 +693,8 @@ __global__ __launch_bounds__(kBlock) void sell_kernel(CsrT<T> a, const T* __rest
 #pragma unroll
             for (int k = 0; k < U; ++k) {
                 const int p = o0 + min(k0 + k, w - 1) * kSellRows + lane;
-                jj[k] = sell_ld<NT>(a.sl_col + p);
+                if constexpr (IDX16) jj[k] = cb + (int)sell_ld<NT>(a.sl_col16 + p);
+                else jj[k] = sell_ld<NT>(a.sl_col + p);
                 vv[k] = sell_ld<NT>(a.sl_val + p);
             }
             T gg[U];
@@ -756,17 +758,19 @@ void launch_sell_u(RowOp op, const CsrT<T>& a_in, const T* g, const T* u, const 
     CsrT<T> a = a_in;
     // per-workgroup dot partials depend on which slices a workgroup visits
     if (!AMG_STREAM_ALTERNATE || op == kResidNorm || op == kJacobiDot || op == kSpmvDot) a.rev = 0;
+    const bool idx16 = a.sl_col16 != nullptr;
     const long long entries = (long long)a.rows * (long long)(a.mean_row + 0.5);
-    const bool nt = entries * (long long)(sizeof(T) + 4) > (long long)AMG_SELL_NT_BYTES;
+    const bool nt = entries * (long long)(sizeof(T) + (idx16 ? 2 : 4)) > (long long)AMG_SELL_NT_BYTES;
     switch (op) {
+#define AMG_SELL_LAUNCH(OPV, NTV, I16)                                                                   \
+    hipLaunchKernelGGL((sell_kernel<T, U, OPV, NTV, I16>), dim3(grid), dim3(kBlock), 0, st, a, g, u, dinv, \
+                       omega, y, y2, dot, nslices)
 #define AMG_SELL_CASE(OPV)                                                                             \
     case OPV:                                                                                          \
-        if (nt)                                                                                        \
-            hipLaunchKernelGGL((sell_kernel<T, U, OPV, true>), dim3(grid), dim3(kBlock), 0, st, a, g, u, dinv, \
-                               omega, y, y2, dot, nslices);                                            \
-        else                                                                                           \
-            hipLaunchKernelGGL((sell_kernel<T, U, OPV, false>), dim3(grid), dim3(kBlock), 0, st, a, g, u, dinv, \
-                               omega, y, y2, dot, nslices);                                            \
+        if (nt && idx16) AMG_SELL_LAUNCH(OPV, true, true);                                             \
+        else if (nt) AMG_SELL_LAUNCH(OPV, true, false);                                                \
+        else if (idx16) AMG_SELL_LAUNCH(OPV, false, true);                                             \
+        else AMG_SELL_LAUNCH(OPV, false, false);                                                       \
         break;
         AMG_SELL_CASE(kSpmv)
         AMG_SELL_CASE(kSpmvAdd)
@@ -778,6 +782,7 @@ void launch_sell_u(RowOp op, const CsrT<T>& a_in, const T* g, const T* u, const 
         AMG_SELL_CASE(kSpmvDot)
         AMG_SELL_CASE(kSpmvScale)
 #undef AMG_SELL_CASE
+#undef AMG_SELL_LAUNCH
         default: break;
     }
     if (op == kResidNorm || op == kJacobiDot || op == kSpmvDot) finish_dot(dot, grid, st);
@@ -827,6 +832,35 @@ __global__ __launch_bounds__(kBlock) void sell_fill_kernel(int rows, const int32
         col[p] = k < len ? ci[b + k] : last;
         val[p] = k < len ? v[b + k] : 0.0;
     }
+}
+
+// one wavefront per slice: smallest and largest column by shuffles, then
+// the 16-bit offsets
+__global__ __launch_bounds__(kBlock) void sell_compress_kernel(int rows, const int32_t* __restrict__ off,
+                                                               const int32_t* __restrict__ col,
+                                                               uint16_t* __restrict__ col16,
+                                                               int32_t* __restrict__ base, int* wide) {
+    const int nslices = (rows + kSellRows - 1) / kSellRows;
+    const int sl = blockIdx.x * kSellSlicesPerBlock + (int)threadIdx.x / kSellRows;
+    if (sl >= nslices) return;
+    const int lane = (int)threadIdx.x & (kSellRows - 1);
+    const int o0 = off[sl], o1 = off[sl + 1];
+    int mn = INT_MAX, mx = INT_MIN;
+    for (int p = o0 + lane; p < o1; p += kSellRows) {
+        mn = min(mn, col[p]);
+        mx = max(mx, col[p]);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        mn = min(mn, __shfl_xor(mn, o, 64));
+        mx = max(mx, __shfl_xor(mx, o, 64));
+    }
+    const bool fits = o1 == o0 || (int64_t)mx - (int64_t)mn <= 65535;
+    if (lane == 0) {
+        base[sl] = o1 > o0 ? mn : 0;
+        if (!fits) atomicAdd(wide, 1);
+    }
+    for (int p = o0 + lane; p < o1; p += kSellRows) col16[p] = fits ? (uint16_t)(col[p] - mn) : (uint16_t)0;
 }
 
 // ---- vector kernels --------------------------------------------------------
@@ -1624,6 +1658,12 @@ int sell_slices(int rows) { return (rows + kSellRows - 1) / kSellRows; }
 void launch_sell_widths(int rows, const int32_t* rp, int32_t* width64, hipStream_t st) {
     const int blocks = std::max(1, (sell_slices(rows) + kSellSlicesPerBlock - 1) / kSellSlicesPerBlock);
     hipLaunchKernelGGL(sell_width_kernel, dim3(blocks), dim3(kBlock), 0, st, rows, rp, width64);
+}
+
+void launch_sell_compress(int rows, const int32_t* off, const int32_t* col, uint16_t* col16, int32_t* base,
+                          int* wide, hipStream_t st) {
+    const int blocks = std::max(1, (sell_slices(rows) + kSellSlicesPerBlock - 1) / kSellSlicesPerBlock);
+    hipLaunchKernelGGL(sell_compress_kernel, dim3(blocks), dim3(kBlock), 0, st, rows, off, col, col16, base, wide);
 }
 
 void launch_sell_fill(int rows, const int32_t* rp, const int32_t* ci, const double* v, const int32_t* off,

@@ -33,6 +33,10 @@ struct CsrT {
     const int32_t* sl_col = nullptr;
     const T* sl_val = nullptr;
     int sl_maxw = 0;     // widest slice, host side launch configuration only
+    // 16-bit form of sl_col (then sl_col is null): the column of an entry of
+    // slice s is sl_base[s] + sl_col16[p]
+    const uint16_t* sl_col16 = nullptr;
+    const int32_t* sl_base = nullptr;
 };
 using CsrView = CsrT<double>;
 using CsrView32 = CsrT<float>;
@@ -168,6 +172,11 @@ int stream_block_rows(const CsrView& a);
 // entries: a row's entries in column order, then (value 0, column of the
 // row's last entry, or 0 for an empty row) up to its slice's width.
 int sell_slices(int rows);
+// 16-bit columns of a SELL-64 copy: base[s] = smallest column of slice s,
+// col16[p] = col[p] - base[s]; *wide (zeroed by the caller) counts the slices
+// whose columns span more than 65535 (then the form is unusable)
+void launch_sell_compress(int rows, const int32_t* off, const int32_t* col, uint16_t* col16, int32_t* base,
+                          int* wide, hipStream_t st);
 void launch_sell_widths(int rows, const int32_t* rp, int32_t* width64, hipStream_t st);
 void launch_sell_fill(int rows, const int32_t* rp, const int32_t* ci, const double* v, const int32_t* off,
                       int32_t* col, double* val, hipStream_t st);
