@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
@@ -86,8 +87,10 @@ struct DevMat {
     int sl_maxw = 0;
     uint16_t* sl_col16 = nullptr;
     int32_t* sl_base = nullptr;
-    // direction of this operator's next cycle pass (flipped by every pass)
-    mutable int next_rev = 0;
+    // direction of this operator's next cycle pass (flipped by every pass),
+    // shared with the copies that alias the operator (Ah = A), so that
+    // passes alternate whichever copy they go through
+    std::shared_ptr<int> next_rev = std::make_shared<int>(0);
     CsrView view() const {
         return CsrView{rp, ci, v, rows, rows ? (double)shape_nnz / rows : 1.0, ci16, cbase, idx_rb, 0,
                        sl_off, sl_col, sl_val, sl_maxw, sl_col16, sl_base};
@@ -353,8 +356,8 @@ void row_op(amg_ctx* h, int kind, int level, RowOp op, const DevMat& m, const do
     ProfScope ps(h, kind, level);
     DotTarget dt = dot_slot >= 0 ? dot_to(h, dot_slot) : DotTarget{nullptr, nullptr};
     CsrView cv = m.view();
-    cv.rev = m.next_rev;
-    m.next_rev ^= 1;
+    cv.rev = *m.next_rev;
+    *m.next_rev ^= 1;
     launch_row_op(op, m.width, cv, g, u, dinv, h->sp.omega, y, y2, dt, h->stream);
     check_launch();
 }
@@ -362,8 +365,8 @@ void row_op(amg_ctx* h, int kind, int level, RowOp op, const DevMat& m, const do
 void row_op(amg_ctx* h, int kind, int level, RowOp op, const DevMat& m, const float* vals, const float* g,
             const float* u, const float* dinv, float* y, float* y2) {
     ProfScope ps(h, kind, level);
-    const CsrView32 a32{m.rp, m.ci, vals, m.rows, m.view().mean_row, m.ci16, m.cbase, m.idx_rb, m.next_rev};
-    m.next_rev ^= 1;
+    const CsrView32 a32{m.rp, m.ci, vals, m.rows, m.view().mean_row, m.ci16, m.cbase, m.idx_rb, *m.next_rev};
+    *m.next_rev ^= 1;
     launch_row_op(op, m.width, a32, g, u, dinv, (float)h->sp.omega, y, y2, h->stream);
     check_launch();
 }

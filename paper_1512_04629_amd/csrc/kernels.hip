@@ -671,9 +671,17 @@ __global__ __launch_bounds__(kBlock) void sell_kernel(CsrT<T> a, const T* __rest
     const int lb = xcd_logical_block();
     const int wv = (int)threadIdx.x / kSellRows;
     const int lane = (int)threadIdx.x & (kSellRows - 1);
+    const int nblocks = (nslices + kSellSlicesPerBlock - 1) / kSellSlicesPerBlock;
     double contrib = 0.0;
-    for (int ls = lb * kSellSlicesPerBlock + wv; ls < nslices; ls += gridDim.x * kSellSlicesPerBlock) {
-        const int sl = a.rev ? nslices - 1 - ls : ls;
+    // a workgroup takes blocks of four slices, in descending block order when
+    // a.rev; with one block per workgroup a dot product's partial goes to the
+    // block's own index, so it is the same in both orders
+    int pidx = lb;
+    for (int lblk = lb; lblk < nblocks; lblk += gridDim.x) {
+        const int blk = a.rev ? nblocks - 1 - lblk : lblk;
+        if (nblocks <= (int)gridDim.x) pidx = blk;
+        const int sl = blk * kSellSlicesPerBlock + wv;
+        if (sl >= nslices) continue;
         const int o0 = a.sl_off[sl];
         const int w = (a.sl_off[sl + 1] - o0) / kSellRows;
         const int cb = IDX16 ? a.sl_base[sl] : 0;
@@ -733,7 +741,7 @@ __global__ __launch_bounds__(kBlock) void sell_kernel(CsrT<T> a, const T* __rest
             }
         }
     }
-    if constexpr (op_has_dot<OP>()) store_block_partial(contrib, dot.partials, lb);
+    if constexpr (op_has_dot<OP>()) store_block_partial(contrib, dot.partials, pidx);
 }
 
 // Matrices larger than this stream their entries with non-temporal loads:
@@ -756,8 +764,11 @@ void launch_sell_u(RowOp op, const CsrT<T>& a_in, const T* g, const T* u, const 
     const int nslices = (a_in.rows + kSellRows - 1) / kSellRows;
     const int grid = sell_grid(a_in.rows);
     CsrT<T> a = a_in;
-    // per-workgroup dot partials depend on which slices a workgroup visits
-    if (!AMG_STREAM_ALTERNATE || op == kResidNorm || op == kJacobiDot || op == kSpmvDot) a.rev = 0;
+    // a dot product's partials are independent of the order only with one
+    // block of four slices per workgroup
+    const bool dot_op = op == kResidNorm || op == kJacobiDot || op == kSpmvDot;
+    if (!AMG_STREAM_ALTERNATE || (dot_op && (nslices + kSellSlicesPerBlock - 1) / kSellSlicesPerBlock > grid))
+        a.rev = 0;
     const bool idx16 = a.sl_col16 != nullptr;
     const long long entries = (long long)a.rows * (long long)(a.mean_row + 0.5);
     const bool nt = entries * (long long)(sizeof(T) + (idx16 ? 2 : 4)) > (long long)AMG_SELL_NT_BYTES;

@@ -112,3 +112,22 @@ def test_stream_direction_does_not_change_results(lib):
                         h.level_op(l, op, inp=inp, x=xx, out=y)
                         outs.append(host(y))
                     assert outs[0].tobytes() == outs[1].tobytes(), (on, l, op)
+
+
+def test_repeated_solves_give_the_same_bits(lib):
+    """Every pass over an operator flips its direction, also through the
+    copies that alias it and in the launches that form dot products (their
+    per-block partials go to the block's own index): the same PCG solve run
+    three times in a row on one handle, each starting with the passes in the
+    other directions, gives the same iterate, residual history and dots."""
+    A = I.poisson3d(64)
+    b = dev(I.rhs(A.n, 4))
+    h = lib.Hierarchy(A)
+    assert h.row_format(0, "A") == "sell"
+    h.sparsify(0.1, 2)
+    outs = []
+    for _ in range(3):
+        x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+        r = h.solve(b, x, method=1, tol=1e-10, maxit=100, adaptive=True, k=3, s=1)
+        outs.append((host(x).tobytes(), r.iters, r.hist.tobytes(), r.relres))
+    assert outs[0] == outs[1] == outs[2]
