@@ -380,13 +380,16 @@ amg_status amg_export_split(amg_handle h, int32_t l, int32_t* cf);
    does for banded operators, e.g. the 7-point stencil up to 181^3): the
    kernels then move 10 instead of 12 bytes per entry.  Results are bitwise the same either way.  enable = 0 drops the
    copies (frees their memory), 1 builds them; AMG_ERR_STATE while a batch
-   engine exists.  The SELL-64 copies (see amg_row_format) likewise keep their
-   columns as 16-bit offsets from a base per slice of 64 rows where every
-   slice spans at most 65535 columns, and are rebuilt in 32 bits when the
-   form is switched off.  amg_index_width reports the bytes per column index
-   the FP64 row kernels read for matrix `which` (AMG_MAT_*) of level l: 2 or
-   4 (of the SELL-64 copy where one exists; the FP32 cycle reads the CSR
-   form's). */
+   engine exists.  The SELL-64 copies (see amg_row_format) are compressed
+   too: a square operator whose every slice of 64 rows has at most 64
+   distinct offsets column - row (stencil-like operators) keeps one byte per
+   entry, the position of its offset in a table of the slice's offsets;
+   otherwise the columns are kept as 16-bit offsets from a base per slice
+   where every slice spans at most 65535 columns; they are rebuilt in 32
+   bits when the form is switched off.  amg_index_width reports the bytes
+   per column index the FP64 row kernels read for matrix `which` (AMG_MAT_*)
+   of level l: 1, 2 or 4 (of the SELL-64 copy where one exists; the FP32
+   cycle reads the CSR form's). */
 amg_status amg_set_compact_indices(amg_handle h, int32_t enable);
 amg_status amg_index_width(amg_handle h, int32_t l, int32_t which, int32_t* bytes);
 

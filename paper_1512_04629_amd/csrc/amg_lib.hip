@@ -87,13 +87,15 @@ struct DevMat {
     int sl_maxw = 0;
     uint16_t* sl_col16 = nullptr;
     int32_t* sl_base = nullptr;
+    uint8_t* sl_idx8 = nullptr;       // or 8-bit positions in a table of offsets per slice
+    int32_t* sl_tab = nullptr;
     // direction of this operator's next cycle pass (flipped by every pass),
     // shared with the copies that alias the operator (Ah = A), so that
     // passes alternate whichever copy they go through
     std::shared_ptr<int> next_rev = std::make_shared<int>(0);
     CsrView view() const {
         return CsrView{rp, ci, v, rows, rows ? (double)shape_nnz / rows : 1.0, ci16, cbase, idx_rb, 0,
-                       sl_off, sl_col, sl_val, sl_maxw, sl_col16, sl_base};
+                       sl_off, sl_col, sl_val, sl_maxw, sl_col16, sl_base, sl_idx8, sl_tab};
     }
 };
 
@@ -242,6 +244,8 @@ void free_mat(amg_ctx* h, DevMat& m) {
     dfree(h, m.sl_val);
     dfree(h, m.sl_col16);
     dfree(h, m.sl_base);
+    dfree(h, m.sl_idx8);
+    dfree(h, m.sl_tab);
     m = DevMat{};
 }
 
@@ -1788,6 +1792,28 @@ void build_sell(amg_ctx* h, DevMat& m) {
     launch_sell_fill(m.rows, m.rp, m.ci, m.v, off, m.sl_col, m.sl_val, h->stream);
     check_launch();
     if (!h->compact_idx) return;
+    // square operators whose every slice has at most 64 distinct offsets
+    // column - row (stencil-like operators): 8-bit positions in a table of
+    // offsets per slice; then the 32-bit columns go
+    if (m.rows == m.cols) {
+        m.sl_idx8 = dalloc_n<uint8_t>(h, total);
+        m.sl_tab = dalloc_n<int32_t>(h, (int64_t)ns * 64);
+        launch_fill_u32(1, reinterpret_cast<unsigned*>(h->missing), 0u, h->stream);
+        launch_sell_dictionary(m.rows, off, m.sl_col, m.sl_idx8, m.sl_tab, h->missing, h->stream);
+        check_launch();
+        int over = 0;
+        download(h, &over, h->missing, 1);
+        sync(h);
+        if (over == 0) {
+            dfree(h, m.sl_col);
+            m.sl_col = nullptr;
+            return;
+        }
+        dfree(h, m.sl_idx8);
+        dfree(h, m.sl_tab);
+        m.sl_idx8 = nullptr;
+        m.sl_tab = nullptr;
+    }
     // 16-bit offsets from a base per slice where every slice's columns span
     // at most 65535 (banded operators); then the 32-bit columns go
     m.sl_col16 = dalloc_n<uint16_t>(h, total);
@@ -1810,11 +1836,13 @@ void build_sell(amg_ctx* h, DevMat& m) {
 }
 
 void drop_sell(amg_ctx* h, DevMat& m) {
-    for (void* p : {(void*)m.sl_off, (void*)m.sl_col, (void*)m.sl_val, (void*)m.sl_col16, (void*)m.sl_base})
+    for (void* p : {(void*)m.sl_off, (void*)m.sl_col, (void*)m.sl_val, (void*)m.sl_col16, (void*)m.sl_base,
+                    (void*)m.sl_idx8, (void*)m.sl_tab})
         dfree(h, p);
-    m.sl_off = m.sl_col = m.sl_base = nullptr;
+    m.sl_off = m.sl_col = m.sl_base = m.sl_tab = nullptr;
     m.sl_val = nullptr;
     m.sl_col16 = nullptr;
+    m.sl_idx8 = nullptr;
     m.sl_maxw = 0;
 }
 
@@ -1827,7 +1855,7 @@ void set_compact_indices(amg_ctx* h, bool on) {
             if (!m->rp) continue;
             if (on) compress_indices(h, *m);
             else drop_indices(h, *m);
-            if (m->sl_off && (m->sl_col16 != nullptr) != on) {
+            if (m->sl_off && (m->sl_col == nullptr) != on) {
                 // rebuilt in the other column width
                 drop_sell(h, *m);
                 build_sell(h, *m);
@@ -2581,7 +2609,7 @@ amg_status amg_index_width(amg_handle h, int32_t l, int32_t which, int32_t* byte
         return AMG_ERR_INVALID_ARG;
     const DevLevel& d = h->lv[l];
     const DevMat& m = which == AMG_MAT_A ? d.A : which == AMG_MAT_AHAT ? d.Ah : which == AMG_MAT_P ? d.P : d.R;
-    *bytes = m.sl_off ? (m.sl_col16 ? 2 : 4) : m.ci16 ? 2 : 4;
+    *bytes = m.sl_off ? (m.sl_idx8 ? 1 : m.sl_col16 ? 2 : 4) : m.ci16 ? 2 : 4;
     return AMG_OK;
 }
 

@@ -664,7 +664,9 @@ __device__ __forceinline__ T sell_ld(const T* p) {
     else return *p;
 }
 
-template <class T, int U, int OP, bool NT, bool IDX16>
+// IDXW: bytes per column index read, 4 (sl_col), 2 (sl_base + sl_col16) or 1
+// (the slice's offset table, sl_idx8)
+template <class T, int U, int OP, bool NT, int IDXW>
 __global__ __launch_bounds__(kBlock) void sell_kernel(CsrT<T> a, const T* __restrict__ g, const T* u,
                                                       const T* __restrict__ dinv, T omega, T* y, T* y2,
                                                       DotTarget dot, int nslices) {
@@ -684,7 +686,8 @@ __global__ __launch_bounds__(kBlock) void sell_kernel(CsrT<T> a, const T* __rest
         if (sl >= nslices) continue;
         const int o0 = a.sl_off[sl];
         const int w = (a.sl_off[sl + 1] - o0) / kSellRows;
-        const int cb = IDX16 ? a.sl_base[sl] : 0;
+        const int cb = IDXW == 2 ? a.sl_base[sl] : 0;
+        const int tabv = IDXW == 1 ? a.sl_tab[sl * kSellRows + lane] : 0;
         const int r = sl * kSellRows + lane;
         const bool act = r < a.rows;
         T ui = T(0), gi = T(0), di = T(0);
@@ -701,8 +704,14 @@ __global__ __launch_bounds__(kBlock) void sell_kernel(CsrT<T> a, const T* __rest
 #pragma unroll
             for (int k = 0; k < U; ++k) {
                 const int p = o0 + min(k0 + k, w - 1) * kSellRows + lane;
-                if constexpr (IDX16) jj[k] = cb + (int)sell_ld<NT>(a.sl_col16 + p);
-                else jj[k] = sell_ld<NT>(a.sl_col + p);
+                if constexpr (IDXW == 1) {
+                    const int d = __shfl(tabv, (int)sell_ld<NT>(a.sl_idx8 + p), 64);
+                    jj[k] = act ? r + d : 0;
+                } else if constexpr (IDXW == 2) {
+                    jj[k] = cb + (int)sell_ld<NT>(a.sl_col16 + p);
+                } else {
+                    jj[k] = sell_ld<NT>(a.sl_col + p);
+                }
                 vv[k] = sell_ld<NT>(a.sl_val + p);
             }
             T gg[U];
@@ -769,19 +778,25 @@ void launch_sell_u(RowOp op, const CsrT<T>& a_in, const T* g, const T* u, const 
     const bool dot_op = op == kResidNorm || op == kJacobiDot || op == kSpmvDot;
     if (!AMG_STREAM_ALTERNATE || (dot_op && (nslices + kSellSlicesPerBlock - 1) / kSellSlicesPerBlock > grid))
         a.rev = 0;
-    const bool idx16 = a.sl_col16 != nullptr;
+    const int iw = a.sl_idx8 ? 1 : a.sl_col16 ? 2 : 4;
     const long long entries = (long long)a.rows * (long long)(a.mean_row + 0.5);
-    const bool nt = entries * (long long)(sizeof(T) + (idx16 ? 2 : 4)) > (long long)AMG_SELL_NT_BYTES;
+    const bool nt = entries * (long long)(sizeof(T) + iw) > (long long)AMG_SELL_NT_BYTES;
     switch (op) {
-#define AMG_SELL_LAUNCH(OPV, NTV, I16)                                                                   \
-    hipLaunchKernelGGL((sell_kernel<T, U, OPV, NTV, I16>), dim3(grid), dim3(kBlock), 0, st, a, g, u, dinv, \
+#define AMG_SELL_LAUNCH(OPV, NTV, IW)                                                                    \
+    hipLaunchKernelGGL((sell_kernel<T, U, OPV, NTV, IW>), dim3(grid), dim3(kBlock), 0, st, a, g, u, dinv, \
                        omega, y, y2, dot, nslices)
 #define AMG_SELL_CASE(OPV)                                                                             \
     case OPV:                                                                                          \
-        if (nt && idx16) AMG_SELL_LAUNCH(OPV, true, true);                                             \
-        else if (nt) AMG_SELL_LAUNCH(OPV, true, false);                                                \
-        else if (idx16) AMG_SELL_LAUNCH(OPV, false, true);                                             \
-        else AMG_SELL_LAUNCH(OPV, false, false);                                                       \
+        if (iw == 1) {                                                                                 \
+            if (nt) AMG_SELL_LAUNCH(OPV, true, 1);                                                     \
+            else AMG_SELL_LAUNCH(OPV, false, 1);                                                       \
+        } else if (iw == 2) {                                                                          \
+            if (nt) AMG_SELL_LAUNCH(OPV, true, 2);                                                     \
+            else AMG_SELL_LAUNCH(OPV, false, 2);                                                       \
+        } else {                                                                                       \
+            if (nt) AMG_SELL_LAUNCH(OPV, true, 4);                                                     \
+            else AMG_SELL_LAUNCH(OPV, false, 4);                                                       \
+        }                                                                                              \
         break;
         AMG_SELL_CASE(kSpmv)
         AMG_SELL_CASE(kSpmvAdd)
@@ -843,6 +858,50 @@ __global__ __launch_bounds__(kBlock) void sell_fill_kernel(int rows, const int32
         col[p] = k < len ? ci[b + k] : last;
         val[p] = k < len ? v[b + k] : 0.0;
     }
+}
+
+// one wavefront per slice: the slice's distinct offsets column - row in
+// order of first appearance (entry slot by slot, lanes in order), added one
+// at a time from the lowest lane that misses; then each entry's position
+__global__ __launch_bounds__(kBlock) void sell_dictionary_kernel(int rows, const int32_t* __restrict__ off,
+                                                                 const int32_t* __restrict__ col,
+                                                                 uint8_t* __restrict__ idx8,
+                                                                 int32_t* __restrict__ tab, int* wide) {
+    __shared__ int table[kSellSlicesPerBlock][kSellRows];
+    const int nslices = (rows + kSellRows - 1) / kSellRows;
+    const int wv = (int)threadIdx.x / kSellRows;
+    const int sl = blockIdx.x * kSellSlicesPerBlock + wv;
+    if (sl >= nslices) return;
+    const int lane = (int)threadIdx.x & (kSellRows - 1);
+    const int r = sl * kSellRows + lane;
+    const bool act = r < rows;
+    const int o0 = off[sl];
+    const int w = (off[sl + 1] - o0) / kSellRows;
+    table[wv][lane] = 0;
+    int cnt = 0;
+    bool overflow = false;
+    for (int k = 0; k < w && !overflow; ++k) {
+        const int p = o0 + k * kSellRows + lane;
+        const int d = act ? col[p] - r : 0;
+        int pos = act ? -1 : 0;
+        for (int t = 0; t < cnt && pos < 0; ++t)
+            if (table[wv][t] == d) pos = t;
+        for (;;) {
+            const unsigned long long miss = __ballot(pos < 0);
+            if (!miss) break;
+            if (cnt == kSellRows) {
+                overflow = true;
+                break;
+            }
+            const int dl = __shfl(d, __ffsll((long long)miss) - 1, 64);
+            if (lane == 0) table[wv][cnt] = dl;
+            if (pos < 0 && d == dl) pos = cnt;
+            ++cnt;
+        }
+        idx8[p] = overflow ? (uint8_t)0 : (uint8_t)pos;
+    }
+    if (lane == 0 && overflow) atomicAdd(wide, 1);
+    tab[sl * kSellRows + lane] = table[wv][lane];
 }
 
 // one wavefront per slice: smallest and largest column by shuffles, then
@@ -1669,6 +1728,12 @@ int sell_slices(int rows) { return (rows + kSellRows - 1) / kSellRows; }
 void launch_sell_widths(int rows, const int32_t* rp, int32_t* width64, hipStream_t st) {
     const int blocks = std::max(1, (sell_slices(rows) + kSellSlicesPerBlock - 1) / kSellSlicesPerBlock);
     hipLaunchKernelGGL(sell_width_kernel, dim3(blocks), dim3(kBlock), 0, st, rows, rp, width64);
+}
+
+void launch_sell_dictionary(int rows, const int32_t* off, const int32_t* col, uint8_t* idx8, int32_t* tab,
+                            int* wide, hipStream_t st) {
+    const int blocks = std::max(1, (sell_slices(rows) + kSellSlicesPerBlock - 1) / kSellSlicesPerBlock);
+    hipLaunchKernelGGL(sell_dictionary_kernel, dim3(blocks), dim3(kBlock), 0, st, rows, off, col, idx8, tab, wide);
 }
 
 void launch_sell_compress(int rows, const int32_t* off, const int32_t* col, uint16_t* col16, int32_t* base,

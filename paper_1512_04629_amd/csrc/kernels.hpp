@@ -37,6 +37,11 @@ struct CsrT {
     // slice s is sl_base[s] + sl_col16[p]
     const uint16_t* sl_col16 = nullptr;
     const int32_t* sl_base = nullptr;
+    // 8-bit form (then sl_col and sl_col16 are null): every slice s lists at
+    // most 64 distinct offsets column - row in sl_tab[64 s .. 64 s + 63], and
+    // the column of entry p of row r is r + sl_tab[64 s + sl_idx8[p]]
+    const uint8_t* sl_idx8 = nullptr;
+    const int32_t* sl_tab = nullptr;
 };
 using CsrView = CsrT<double>;
 using CsrView32 = CsrT<float>;
@@ -172,6 +177,12 @@ int stream_block_rows(const CsrView& a);
 // entries: a row's entries in column order, then (value 0, column of the
 // row's last entry, or 0 for an empty row) up to its slice's width.
 int sell_slices(int rows);
+// 8-bit columns of a SELL-64 copy: tab[64 s ..] lists the distinct offsets
+// column - row of slice s (rows past the end excluded), idx8[p] the position
+// of entry p's offset there; *wide (zeroed by the caller) counts the slices
+// with more than 64 distinct offsets (then the form is unusable)
+void launch_sell_dictionary(int rows, const int32_t* off, const int32_t* col, uint8_t* idx8, int32_t* tab,
+                            int* wide, hipStream_t st);
 // 16-bit columns of a SELL-64 copy: base[s] = smallest column of slice s,
 // col16[p] = col[p] - base[s]; *wide (zeroed by the caller) counts the slices
 // whose columns span more than 65535 (then the form is unusable)
