@@ -128,6 +128,8 @@ def main():
     ap.add_argument("--reps", type=int, default=5, help="timed solves per right-hand side in the gamma comparison")
     ap.add_argument("--hbm-steps", type=int, default=10, help="timed steps of the 192^3 HBM-only figure")
     ap.add_argument("--no-hbm-only", action="store_true", help="skip the 192^3 HBM-only figure")
+    ap.add_argument("--no-alone", action="store_true",
+                    help="skip the dominant kernel's launches outside the cycle (profiler runs of the cycle alone)")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the per-gamma time-to-solution comparison (short profiler runs)")
     ap.add_argument("--budget-gb", type=float, default=32.0,
@@ -341,7 +343,7 @@ def bench_poisson(args):
     # and with 1 GiB streamed between launches so that every launch reads it
     # from HBM
     cache_runs = {}
-    if dom_kernel in ("JACOBI", "RESIDUAL"):
+    if dom_kernel in ("JACOBI", "RESIDUAL") and not args.no_alone:
         nl = h.level_info(dom_level)["n"]
         gen = torch.Generator(device="cuda").manual_seed(5)
         bl = torch.rand(nl, dtype=torch.float64, device="cuda", generator=gen)
@@ -377,8 +379,19 @@ def bench_poisson(args):
     e1.record()
     torch.cuda.synchronize()
     copy_gbs = 10 * 2 * src.numel() * 8 / (e0.elapsed_time(e1) / 1e3) / 1e9
+    # and a read-only pass: a sum over the same 1 GiB (warmed up with the same
+    # expression: the first use of the elementwise add stalls the host)
+    acc = src.sum()
+    acc = acc + src.sum()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(10):
+        acc = acc + src.sum()
+    e1.record()
+    torch.cuda.synchronize()
+    read_gbs = 10 * src.numel() * 8 / (e0.elapsed_time(e1) / 1e3) / 1e9
     del src, dst
-    log(f"[bench] device copy of 1 GiB: {copy_gbs:.0f} GB/s (read + write)")
+    log(f"[bench] device copy of 1 GiB: {copy_gbs:.0f} GB/s (read + write); sum of 1 GiB: {read_gbs:.0f} GB/s")
 
     # SpMV bandwidth of the fine-level operator (the CG product A p)
     h.profile_enable(True, "SPMV_DOT", 0)
@@ -426,8 +439,9 @@ def bench_poisson(args):
         "sparsified_vs_galerkin": summary,
         "speedup_vs_galerkin": summary["speedup_median"] if summary else None,
         "spmv_gbs_level0": round(spmv_gbs, 1) if spmv_gbs else None,
-        "practical_ceiling": {"copy_gbs": round(copy_gbs, 1),
-                              "how": "1 GiB device-to-device copy, bytes read + written per second"},
+        "practical_ceiling": {"copy_gbs": round(copy_gbs, 1), "read_gbs": round(read_gbs, 1),
+                              "how": "1 GiB device-to-device copy, bytes read + written per second; "
+                                     "sum over 1 GiB, bytes read per second"},
         "roofline": {
             "bound": "hbm",
             "kernel": f"{dom_kernel} level {dom_level}",

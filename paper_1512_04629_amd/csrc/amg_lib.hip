@@ -305,19 +305,36 @@ HostCsr download_mat(amg_ctx* h, const DevMat& d) {
 // ---------------------------------------------------------------------------
 // profiling: events around launches of one kernel class on one level
 // ---------------------------------------------------------------------------
+// kernel_events: the scope holds one row-kernel launch, whose own start and
+// end the events record (hipExtLaunchKernel); otherwise they are recorded on
+// the stream around everything the scope launches
 struct ProfScope {
     amg_ctx* h;
     int kind, level;
     hipEvent_t stop = nullptr;
-    ProfScope(amg_ctx* hh, int k, int l) : h(hh), kind(k), level(l) {
+    bool armed = false;
+    ProfScope(amg_ctx* hh, int k, int l, bool kernel_events = false) : h(hh), kind(k), level(l) {
         if (!h->profiling) return;
         if ((h->prof_kind >= 0 && h->prof_kind != k) || (h->prof_level >= 0 && h->prof_level != l)) return;
         hipEvent_t start = take_event();
         stop = take_event();
-        HIP_CHECK(hipEventRecord(start, h->stream));
+        if (kernel_events) {
+            set_launch_events(start, stop);
+            armed = true;
+        } else {
+            HIP_CHECK(hipEventRecord(start, h->stream));
+        }
         h->pending.push_back(PendingEvent{kind, level, start, stop});
     }
     ~ProfScope() {
+        if (armed) {
+            // a launch that did not take the events (none happens) leaves them unrecorded
+            if (clear_launch_events()) {
+                (void)hipEventRecord(h->pending.back().start, h->stream);
+                (void)hipEventRecord(stop, h->stream);
+            }
+            return;
+        }
         if (stop) (void)hipEventRecord(stop, h->stream);
     }
     hipEvent_t take_event() {
@@ -357,18 +374,26 @@ DotTarget dot_to(amg_ctx* h, int slot) { return DotTarget{h->partials, h->scal +
 
 void row_op(amg_ctx* h, int kind, int level, RowOp op, const DevMat& m, const double* g,
             const double* u, const double* dinv, double* y, double* y2, int dot_slot) {
-    ProfScope ps(h, kind, level);
     DotTarget dt = dot_slot >= 0 ? dot_to(h, dot_slot) : DotTarget{nullptr, nullptr};
     CsrView cv = m.view();
     cv.rev = *m.next_rev;
     *m.next_rev ^= 1;
-    launch_row_op(op, m.width, cv, g, u, dinv, h->sp.omega, y, y2, dt, h->stream);
-    check_launch();
+    int nparts = 0;
+    {
+        // the events time the row kernel alone; the dot's finishing launch follows
+        ProfScope ps(h, kind, level, true);
+        nparts = launch_row_op(op, m.width, cv, g, u, dinv, h->sp.omega, y, y2, dt, h->stream);
+        check_launch();
+    }
+    if (nparts > 0) {
+        launch_dot_finish(dt, nparts, h->stream);
+        check_launch();
+    }
 }
 
 void row_op(amg_ctx* h, int kind, int level, RowOp op, const DevMat& m, const float* vals, const float* g,
             const float* u, const float* dinv, float* y, float* y2) {
-    ProfScope ps(h, kind, level);
+    ProfScope ps(h, kind, level, true);
     const CsrView32 a32{m.rp, m.ci, vals, m.rows, m.view().mean_row, m.ci16, m.cbase, m.idx_rb, *m.next_rev};
     *m.next_rev ^= 1;
     launch_row_op(op, m.width, a32, g, u, dinv, (float)h->sp.omega, y, y2, h->stream);

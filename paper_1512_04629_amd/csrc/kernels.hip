@@ -9,6 +9,8 @@
 // into the same pass so that every vector is read once.
 #include "kernels.hpp"
 
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 #include <climits>
 #include <cmath>
@@ -93,6 +95,22 @@ __device__ __forceinline__ int xcd_logical_block() {
 
 int round_up8(int b) { return (b + kXcds - 1) / kXcds * kXcds; }
 
+// Events armed by set_launch_events: the next row-kernel launch records its
+// own start and end in them (hipExtLaunchKernel), so that a timing of it
+// covers the kernel as a profiler's kernel trace does.
+thread_local hipEvent_t t_ev_start = nullptr, t_ev_stop = nullptr;
+
+template <class K, class... Args>
+void launch_row_kernel(K kernel, dim3 grid, dim3 block, hipStream_t st, Args... args) {
+    if (t_ev_start) {
+        hipEvent_t a = t_ev_start, b = t_ev_stop;
+        t_ev_start = t_ev_stop = nullptr;
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, st, a, b, 0, args...);
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, 0, st, args...);
+    }
+}
+
 // column of entry p of a row block whose 16-bit base is cb
 template <bool IDX16, class T>
 __device__ __forceinline__ int load_col(const CsrT<T>& a, int p, int cb) {
@@ -139,7 +157,7 @@ __device__ __forceinline__ double block_sum(double v, double* lds) {
 }
 
 // Deterministic grid reduction, first pass: every block stores its partial
-// sum; dot_finish_kernel adds the partials in index order.  (A single-pass
+// sum; dot_finish_kernel adds the partials in a fixed order.  (A single-pass
 // last-block scheme would need an agent-scope release fence per block, which
 // on gfx950 writes back the XCD's L2 and stalls the block.)
 __device__ __forceinline__ void store_block_partial(double v, double* partials, int lb) {
@@ -148,23 +166,40 @@ __device__ __forceinline__ void store_block_partial(double v, double* partials, 
     if (threadIdx.x == 0) partials[lb] = t;
 }
 
-__global__ __launch_bounds__(kBlock) void dot_finish_kernel(int nparts, const double* __restrict__ partials,
-                                                            double* __restrict__ result) {
-    __shared__ double slice[kBlock];
-    // thread t adds partials t, t + 256, ... in that order (coalesced)
-    double s = 0.0;
-    for (int i = threadIdx.x; i < nparts; i += kBlock) s += partials[i];
-    slice[threadIdx.x] = s;
+constexpr int kFinishBlock = 1024;
+
+__global__ __launch_bounds__(kFinishBlock) void dot_finish_kernel(int nparts, const double* __restrict__ partials,
+                                                                  double* __restrict__ result) {
+    __shared__ double wsum[kFinishBlock / 64];
+    // thread t takes partials t, t + 1024, ... into four accumulators in turn
+    // (independent loads in flight), adds them pairwise, then a fixed shuffle
+    // tree per wave and the wave sums in wave order
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int i = threadIdx.x;
+    for (; i + 3 * kFinishBlock < nparts; i += 4 * kFinishBlock) {
+        a0 += partials[i];
+        a1 += partials[i + kFinishBlock];
+        a2 += partials[i + 2 * kFinishBlock];
+        a3 += partials[i + 3 * kFinishBlock];
+    }
+    if (i < nparts) a0 += partials[i];
+    if (i + kFinishBlock < nparts) a1 += partials[i + kFinishBlock];
+    if (i + 2 * kFinishBlock < nparts) a2 += partials[i + 2 * kFinishBlock];
+    double s = (a0 + a1) + (a2 + a3);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = s;
     __syncthreads();
     if (threadIdx.x == 0) {
-        double tot = 0.0;
-        for (int i = 0; i < kBlock; ++i) tot += slice[i];
+        double tot = wsum[0];
+#pragma unroll
+        for (int w = 1; w < kFinishBlock / 64; ++w) tot += wsum[w];
         *result = tot;
     }
 }
 
 void finish_dot(const DotTarget& dot, int nparts, hipStream_t st) {
-    hipLaunchKernelGGL(dot_finish_kernel, dim3(1), dim3(kBlock), 0, st, nparts, dot.partials, dot.result);
+    hipLaunchKernelGGL(dot_finish_kernel, dim3(1), dim3(kFinishBlock), 0, st, nparts, dot.partials, dot.result);
 }
 
 template <int OP>
@@ -271,8 +306,8 @@ __global__ __launch_bounds__(kBlock) void row_kernel(CsrT<T> a, const T* __restr
 }
 
 template <class T, int W>
-void launch_row_w(RowOp op, const CsrT<T>& a, const T* g, const T* u, const T* dinv,
-                  T omega, T* y, T* y2, DotTarget dot, hipStream_t st) {
+int launch_row_w(RowOp op, const CsrT<T>& a, const T* g, const T* u, const T* dinv,
+                 T omega, T* y, T* y2, DotTarget dot, hipStream_t st) {
     constexpr int kRowsPerBlock = kBlock / W;
     constexpr int R = rows_in_flight<W>();
     const int ntiles = std::max(1, (a.rows + kRowsPerBlock - 1) / kRowsPerBlock);
@@ -281,8 +316,8 @@ void launch_row_w(RowOp op, const CsrT<T>& a, const T* g, const T* u, const T* d
     switch (op) {
 #define AMG_ROW_CASE(OPV)                                                                      \
     case OPV:                                                                                  \
-        hipLaunchKernelGGL((row_kernel<T, W, OPV>), dim3(grid), dim3(kBlock), 0, st, a, g, u, dinv, \
-                           omega, y, y2, dot, ntiles);                                         \
+        launch_row_kernel(row_kernel<T, W, OPV>, dim3(grid), dim3(kBlock), st, a, g, u, dinv, omega, y, y2, \
+                          dot, ntiles);                                                        \
         break;
         AMG_ROW_CASE(kSpmv)
         AMG_ROW_CASE(kSpmvAdd)
@@ -296,7 +331,7 @@ void launch_row_w(RowOp op, const CsrT<T>& a, const T* g, const T* u, const T* d
 #undef AMG_ROW_CASE
         default: break;
     }
-    if (op == kResidNorm || op == kJacobiDot || op == kSpmvDot) finish_dot(dot, grid, st);
+    return (op == kResidNorm || op == kJacobiDot || op == kSpmvDot) ? grid : 0;
 }
 
 // CSR-stream variant: a block owns RB consecutive rows; its threads load the
@@ -591,11 +626,11 @@ void launch_stream_rbi(RowOp op, const CsrT<T>& a, const T* g, const T* u, const
 #define AMG_STREAM_CASE(OPV)                                                                      \
     case OPV:                                                                                     \
         if (AMG_PIPE && !VEC4)                                                                    \
-            hipLaunchKernelGGL((stream_pipe_kernel<T, RB, OPV, IDX16>), dim3(grid), dim3(kBlock), 0, st, a, g, \
-                               u, dinv, omega, y, y2, dot, nblk);                                 \
+            launch_row_kernel(stream_pipe_kernel<T, RB, OPV, IDX16>, dim3(grid), dim3(kBlock), st, a, g, u, \
+                              dinv, omega, y, y2, dot, nblk);                                     \
         else                                                                                      \
-            hipLaunchKernelGGL((stream_kernel<T, RB, OPV, VEC4, IDX16>), dim3(grid), dim3(kBlock), 0, st, a, \
-                               g, u, dinv, omega, y, y2, dot, nblk);                              \
+            launch_row_kernel(stream_kernel<T, RB, OPV, VEC4, IDX16>, dim3(grid), dim3(kBlock), st, a, g, u, \
+                              dinv, omega, y, y2, dot, nblk);                                     \
         break;
         AMG_STREAM_CASE(kSpmv)
         AMG_STREAM_CASE(kSpmvAdd)
@@ -619,8 +654,8 @@ void launch_stream_rbi(RowOp op, const CsrT<T>& a, const T* g, const T* u, const
 #endif
 
 template <class T, int RB, bool VEC4>
-void launch_stream_rb(RowOp op, const CsrT<T>& a_in, const T* g, const T* u, const T* dinv,
-                      T omega, T* y, T* y2, DotTarget dot, hipStream_t st) {
+int launch_stream_rb(RowOp op, const CsrT<T>& a_in, const T* g, const T* u, const T* dinv,
+                     T omega, T* y, T* y2, DotTarget dot, hipStream_t st) {
     const int nblk = std::max(1, (a_in.rows + RB - 1) / RB);
     const int grid = round_up8(std::min(nblk, std::min(kRowGridCap, AMG_STREAM_GRID_CAP)));
     CsrT<T> a = a_in;
@@ -630,7 +665,7 @@ void launch_stream_rb(RowOp op, const CsrT<T>& a_in, const T* g, const T* u, con
     if (a.ci16 && a.idx_rb == RB)
         launch_stream_rbi<T, RB, VEC4, true>(op, a, g, u, dinv, omega, y, y2, dot, nblk, grid, st);
     else launch_stream_rbi<T, RB, VEC4, false>(op, a, g, u, dinv, omega, y, y2, dot, nblk, grid, st);
-    if (op == kResidNorm || op == kJacobiDot || op == kSpmvDot) finish_dot(dot, grid, st);
+    return (op == kResidNorm || op == kJacobiDot || op == kSpmvDot) ? grid : 0;
 }
 
 
@@ -768,8 +803,8 @@ int sell_grid(int rows) {
 }
 
 template <class T, int U>
-void launch_sell_u(RowOp op, const CsrT<T>& a_in, const T* g, const T* u, const T* dinv, T omega, T* y, T* y2,
-                   DotTarget dot, hipStream_t st) {
+int launch_sell_u(RowOp op, const CsrT<T>& a_in, const T* g, const T* u, const T* dinv, T omega, T* y, T* y2,
+                  DotTarget dot, hipStream_t st) {
     const int nslices = (a_in.rows + kSellRows - 1) / kSellRows;
     const int grid = sell_grid(a_in.rows);
     CsrT<T> a = a_in;
@@ -783,8 +818,8 @@ void launch_sell_u(RowOp op, const CsrT<T>& a_in, const T* g, const T* u, const 
     const bool nt = entries * (long long)(sizeof(T) + iw) > (long long)AMG_SELL_NT_BYTES;
     switch (op) {
 #define AMG_SELL_LAUNCH(OPV, NTV, IW)                                                                    \
-    hipLaunchKernelGGL((sell_kernel<T, U, OPV, NTV, IW>), dim3(grid), dim3(kBlock), 0, st, a, g, u, dinv, \
-                       omega, y, y2, dot, nslices)
+    launch_row_kernel(sell_kernel<T, U, OPV, NTV, IW>, dim3(grid), dim3(kBlock), st, a, g, u, dinv, omega, y, \
+                      y2, dot, nslices)
 #define AMG_SELL_CASE(OPV)                                                                             \
     case OPV:                                                                                          \
         if (iw == 1) {                                                                                 \
@@ -811,18 +846,19 @@ void launch_sell_u(RowOp op, const CsrT<T>& a_in, const T* g, const T* u, const 
 #undef AMG_SELL_LAUNCH
         default: break;
     }
-    if (op == kResidNorm || op == kJacobiDot || op == kSpmvDot) finish_dot(dot, grid, st);
+    return (op == kResidNorm || op == kJacobiDot || op == kSpmvDot) ? grid : 0;
 }
 
 template <class T>
-void launch_sell(RowOp op, const CsrT<T>& a, const T* g, const T* u, const T* dinv, T omega, T* y, T* y2,
-                 DotTarget dot, hipStream_t st) {
+int launch_sell(RowOp op, const CsrT<T>& a, const T* g, const T* u, const T* dinv, T omega, T* y, T* y2,
+                DotTarget dot, hipStream_t st) {
     const int w = a.sl_maxw;
-    if (w <= 8) launch_sell_u<T, 8>(op, a, g, u, dinv, omega, y, y2, dot, st);
-    else if (w <= 12) launch_sell_u<T, 12>(op, a, g, u, dinv, omega, y, y2, dot, st);
-    else if (w <= 16) launch_sell_u<T, 16>(op, a, g, u, dinv, omega, y, y2, dot, st);
-    else if (w <= 20) launch_sell_u<T, 20>(op, a, g, u, dinv, omega, y, y2, dot, st);
-    else launch_sell_u<T, 24>(op, a, g, u, dinv, omega, y, y2, dot, st);
+    if (w <= 8) return launch_sell_u<T, 8>(op, a, g, u, dinv, omega, y, y2, dot, st);
+    if (w <= 12) return launch_sell_u<T, 12>(op, a, g, u, dinv, omega, y, y2, dot, st);
+    if (w <= 16) return launch_sell_u<T, 16>(op, a, g, u, dinv, omega, y, y2, dot, st);
+    if (w <= 20) return launch_sell_u<T, 20>(op, a, g, u, dinv, omega, y, y2, dot, st);
+    if (w <= 24) return launch_sell_u<T, 24>(op, a, g, u, dinv, omega, y, y2, dot, st);
+    return launch_sell_u<T, 32>(op, a, g, u, dinv, omega, y, y2, dot, st);
 }
 
 // one wavefront per slice: 64 x the longest row
@@ -852,7 +888,10 @@ __global__ __launch_bounds__(kBlock) void sell_fill_kernel(int rows, const int32
     const int w = (off[sl + 1] - o0) / kSellRows;
     const int b = r < rows ? rp[r] : 0;
     const int len = r < rows ? rp[r + 1] - b : 0;
-    const int last = len > 0 ? ci[b + len - 1] : 0;
+    // padding repeats the row's last column (an empty row: the row's own
+    // index, a valid column of these operators, which have at least as many
+    // columns as rows)
+    const int last = len > 0 ? ci[b + len - 1] : (r < rows ? r : 0);
     for (int k = 0; k < w; ++k) {
         const int p = o0 + k * kSellRows + lane;
         col[p] = k < len ? ci[b + k] : last;
@@ -1457,27 +1496,27 @@ bool use_stream_kernel(const CsrT<T>& a) {
 // 16-byte packed loads pay off on the operators with the shortest rows
 // (measured: A_0, P_l, R_0 gain 5-8%; the 19-point A_1 loses).
 template <class T, bool VEC4>
-void launch_stream_v(RowOp op, const CsrT<T>& a, const T* g, const T* u, const T* dinv,
-                     T omega, T* y, T* y2, DotTarget dot, hipStream_t st) {
+int launch_stream_v(RowOp op, const CsrT<T>& a, const T* g, const T* u, const T* dinv,
+                    T omega, T* y, T* y2, DotTarget dot, hipStream_t st) {
     switch (stream_rows_per_block(a.mean_row)) {
-        case 256: launch_stream_rb<T, 256, VEC4>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
-        case 128: launch_stream_rb<T, 128, VEC4>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
-        case 64: launch_stream_rb<T, 64, VEC4>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
-        case 32: launch_stream_rb<T, 32, VEC4>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
-        default: launch_stream_rb<T, 16, VEC4>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
+        case 256: return launch_stream_rb<T, 256, VEC4>(op, a, g, u, dinv, omega, y, y2, dot, st);
+        case 128: return launch_stream_rb<T, 128, VEC4>(op, a, g, u, dinv, omega, y, y2, dot, st);
+        case 64: return launch_stream_rb<T, 64, VEC4>(op, a, g, u, dinv, omega, y, y2, dot, st);
+        case 32: return launch_stream_rb<T, 32, VEC4>(op, a, g, u, dinv, omega, y, y2, dot, st);
+        default: return launch_stream_rb<T, 16, VEC4>(op, a, g, u, dinv, omega, y, y2, dot, st);
     }
 }
 
 template <class T>
-void launch_stream_any(RowOp op, const CsrT<T>& a, const T* g, const T* u, const T* dinv,
-                       T omega, T* y, T* y2, DotTarget dot, hipStream_t st) {
+int launch_stream_any(RowOp op, const CsrT<T>& a, const T* g, const T* u, const T* dinv,
+                      T omega, T* y, T* y2, DotTarget dot, hipStream_t st) {
 #if AMG_VEC4 >= 0
     constexpr bool kForce = AMG_VEC4 != 0;
-    if (kForce) launch_stream_v<T, true>(op, a, g, u, dinv, omega, y, y2, dot, st);
-    else launch_stream_v<T, false>(op, a, g, u, dinv, omega, y, y2, dot, st);
+    if (kForce) return launch_stream_v<T, true>(op, a, g, u, dinv, omega, y, y2, dot, st);
+    return launch_stream_v<T, false>(op, a, g, u, dinv, omega, y, y2, dot, st);
 #else
-    if (a.mean_row <= 10.0) launch_stream_v<T, true>(op, a, g, u, dinv, omega, y, y2, dot, st);
-    else launch_stream_v<T, false>(op, a, g, u, dinv, omega, y, y2, dot, st);
+    if (a.mean_row <= 10.0) return launch_stream_v<T, true>(op, a, g, u, dinv, omega, y, y2, dot, st);
+    return launch_stream_v<T, false>(op, a, g, u, dinv, omega, y, y2, dot, st);
 #endif
 }
 
@@ -1503,38 +1542,45 @@ int row_launch_blocks(int rows, int width) {
 }
 
 template <class T>
-void launch_row_op_t(RowOp op, int width, const CsrT<T>& a, const T* g, const T* u,
-                     const T* dinv, T omega, T* y, T* y2, DotTarget dot, hipStream_t st) {
+int launch_row_op_t(RowOp op, int width, const CsrT<T>& a, const T* g, const T* u,
+                    const T* dinv, T omega, T* y, T* y2, DotTarget dot, hipStream_t st) {
     if constexpr (sizeof(T) == 8) {
-        if (AMG_SELL && a.sl_off) {
-            launch_sell(op, a, g, u, dinv, omega, y, y2, dot, st);
-            return;
-        }
+        if (AMG_SELL && a.sl_off) return launch_sell(op, a, g, u, dinv, omega, y, y2, dot, st);
     }
-    if (use_stream_kernel(a)) {
-        launch_stream_any(op, a, g, u, dinv, omega, y, y2, dot, st);
-        return;
-    }
+    if (use_stream_kernel(a)) return launch_stream_any(op, a, g, u, dinv, omega, y, y2, dot, st);
     switch (width) {
-        case 1: launch_row_w<T, 1>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
-        case 2: launch_row_w<T, 2>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
-        case 4: launch_row_w<T, 4>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
-        case 8: launch_row_w<T, 8>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
-        case 16: launch_row_w<T, 16>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
-        case 32: launch_row_w<T, 32>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
-        default: launch_row_w<T, 64>(op, a, g, u, dinv, omega, y, y2, dot, st); break;
+        case 1: return launch_row_w<T, 1>(op, a, g, u, dinv, omega, y, y2, dot, st);
+        case 2: return launch_row_w<T, 2>(op, a, g, u, dinv, omega, y, y2, dot, st);
+        case 4: return launch_row_w<T, 4>(op, a, g, u, dinv, omega, y, y2, dot, st);
+        case 8: return launch_row_w<T, 8>(op, a, g, u, dinv, omega, y, y2, dot, st);
+        case 16: return launch_row_w<T, 16>(op, a, g, u, dinv, omega, y, y2, dot, st);
+        case 32: return launch_row_w<T, 32>(op, a, g, u, dinv, omega, y, y2, dot, st);
+        default: return launch_row_w<T, 64>(op, a, g, u, dinv, omega, y, y2, dot, st);
     }
 }
 
-void launch_row_op(RowOp op, int width, const CsrView& a, const double* g, const double* u,
-                   const double* dinv, double omega, double* y, double* y2, DotTarget dot,
-                   hipStream_t st) {
-    launch_row_op_t<double>(op, width, a, g, u, dinv, omega, y, y2, dot, st);
+int launch_row_op(RowOp op, int width, const CsrView& a, const double* g, const double* u,
+                  const double* dinv, double omega, double* y, double* y2, DotTarget dot,
+                  hipStream_t st) {
+    return launch_row_op_t<double>(op, width, a, g, u, dinv, omega, y, y2, dot, st);
 }
 
 void launch_row_op(RowOp op, int width, const CsrView32& a, const float* g, const float* u,
                    const float* dinv, float omega, float* y, float* y2, hipStream_t st) {
     launch_row_op_t<float>(op, width, a, g, u, dinv, omega, y, y2, DotTarget{nullptr, nullptr}, st);
+}
+
+void launch_dot_finish(const DotTarget& dot, int nparts, hipStream_t st) { finish_dot(dot, nparts, st); }
+
+void set_launch_events(hipEvent_t start, hipEvent_t stop) {
+    t_ev_start = start;
+    t_ev_stop = stop;
+}
+
+bool clear_launch_events() {
+    const bool pending = t_ev_start != nullptr;
+    t_ev_start = t_ev_stop = nullptr;
+    return pending;
 }
 
 void launch_cg_update_xr(int n, double* x, double* r, const double* p, const double* q,

@@ -78,9 +78,18 @@ int pick_width(double mean_row_len);
 int row_launch_blocks(int rows, int width);
 int max_row_launch_blocks();
 
-void launch_row_op(RowOp op, int width, const CsrView& a, const double* g, const double* u,
-                   const double* dinv, double omega, double* y, double* y2, DotTarget dot,
-                   hipStream_t st);
+// Returns, for the ops that form a dot product (kResidNorm, kJacobiDot,
+// kSpmvDot), the number of per-workgroup partials written to dot.partials,
+// which launch_dot_finish then adds in order into *dot.result; 0 otherwise.
+int launch_row_op(RowOp op, int width, const CsrView& a, const double* g, const double* u,
+                  const double* dinv, double omega, double* y, double* y2, DotTarget dot,
+                  hipStream_t st);
+void launch_dot_finish(const DotTarget& dot, int nparts, hipStream_t st);
+// Arms two events for the next launch_row_op on this thread: its row kernel
+// records its own start and end in them (not the dot's finishing launch).
+// clear_launch_events disarms them and tells whether they were still armed.
+void set_launch_events(hipEvent_t start, hipEvent_t stop);
+bool clear_launch_events();
 // single precision: values, vectors and accumulation in FP32 (no dot ops)
 void launch_row_op(RowOp op, int width, const CsrView32& a, const float* g, const float* u,
                    const float* dinv, float omega, float* y, float* y2, hipStream_t st);
