@@ -89,6 +89,8 @@ struct DevMat {
     int32_t* sl_base = nullptr;
     uint8_t* sl_idx8 = nullptr;       // or 8-bit positions in a table of offsets per slice
     int32_t* sl_tab = nullptr;
+    int64_t sl_cap = 0;               // entries the SELL-64 arrays hold
+    float* sl_val32 = nullptr;        // FP32 values of the copy (FP32 cycle; built with the FP32 mirror)
     // direction of this operator's next cycle pass (flipped by every pass),
     // shared with the copies that alias the operator (Ah = A), so that
     // passes alternate whichever copy they go through
@@ -246,6 +248,7 @@ void free_mat(amg_ctx* h, DevMat& m) {
     dfree(h, m.sl_base);
     dfree(h, m.sl_idx8);
     dfree(h, m.sl_tab);
+    dfree(h, m.sl_val32);
     m = DevMat{};
 }
 
@@ -394,7 +397,10 @@ void row_op(amg_ctx* h, int kind, int level, RowOp op, const DevMat& m, const do
 void row_op(amg_ctx* h, int kind, int level, RowOp op, const DevMat& m, const float* vals, const float* g,
             const float* u, const float* dinv, float* y, float* y2) {
     ProfScope ps(h, kind, level, true);
-    const CsrView32 a32{m.rp, m.ci, vals, m.rows, m.view().mean_row, m.ci16, m.cbase, m.idx_rb, *m.next_rev};
+    // the SELL-64 copy's FP32 values are the same narrowed values in slice order
+    const CsrView32 a32{m.rp, m.ci, vals, m.rows, m.view().mean_row, m.ci16, m.cbase, m.idx_rb, *m.next_rev,
+                        m.sl_val32 ? m.sl_off : nullptr, m.sl_col, m.sl_val32, m.sl_maxw, m.sl_col16, m.sl_base,
+                        m.sl_idx8, m.sl_tab};
     *m.next_rev ^= 1;
     launch_row_op(op, m.width, a32, g, u, dinv, (float)h->sp.omega, y, y2, h->stream);
     check_launch();
@@ -880,6 +886,8 @@ void vcycle_gs(amg_ctx* h, const double* b0, double* x0, Guess guess0, int dot_s
 
 bool gs_on(const amg_ctx* h) { return h->relax == AMG_RELAX_HYBRID_GS; }
 
+void sell_fp32(amg_ctx* h, DevMat& m);
+
 // FP32 copies of every operator's values, of dinv, and FP32 work vectors
 void ensure_fp32(amg_ctx* h) {
     if (h->fp32) return;
@@ -904,6 +912,9 @@ void ensure_fp32(amg_ctx* h) {
     h->cg_z32 = dalloc_n<float>(h, h->lv[0].n);
     for (int l = 0; l <= L; ++l) {
         DevLevel& v = h->lv[l];
+        sell_fp32(h, v.A);
+        if (l < L) sell_fp32(h, v.R);
+        if (v.ah_alias) v.Ah = v.A;
         launch_narrow(v.A.nnz, v.A32, v.A.v, h->stream);
         launch_narrow(v.n, v.dinv32, v.dinv, h->stream);
         if (v.Ahs32) launch_narrow(v.A.nnz, v.Ahs32, v.Ahs.v, h->stream);   // capacity; entries past nnz unused
@@ -1814,6 +1825,7 @@ void build_sell(amg_ctx* h, DevMat& m) {
     m.sl_col = dalloc_n<int32_t>(h, total);
     m.sl_val = dalloc_n<double>(h, total);
     m.sl_maxw = maxw;
+    m.sl_cap = total;
     launch_sell_fill(m.rows, m.rp, m.ci, m.v, off, m.sl_col, m.sl_val, h->stream);
     check_launch();
     if (!h->compact_idx) return;
@@ -1862,13 +1874,23 @@ void build_sell(amg_ctx* h, DevMat& m) {
 
 void drop_sell(amg_ctx* h, DevMat& m) {
     for (void* p : {(void*)m.sl_off, (void*)m.sl_col, (void*)m.sl_val, (void*)m.sl_col16, (void*)m.sl_base,
-                    (void*)m.sl_idx8, (void*)m.sl_tab})
+                    (void*)m.sl_idx8, (void*)m.sl_tab, (void*)m.sl_val32})
         dfree(h, p);
     m.sl_off = m.sl_col = m.sl_base = m.sl_tab = nullptr;
     m.sl_val = nullptr;
+    m.sl_val32 = nullptr;
+    m.sl_cap = 0;
     m.sl_col16 = nullptr;
     m.sl_idx8 = nullptr;
     m.sl_maxw = 0;
+}
+
+// FP32 values of a SELL-64 copy, for the FP32 cycle
+void sell_fp32(amg_ctx* h, DevMat& m) {
+    if (!m.sl_off || m.sl_val32) return;
+    m.sl_val32 = dalloc_n<float>(h, m.sl_cap);
+    launch_narrow(m.sl_cap, m.sl_val32, m.sl_val, h->stream);
+    check_launch();
 }
 
 // builds or drops the 16-bit indices of every level's A, P and R (the
@@ -1884,6 +1906,7 @@ void set_compact_indices(amg_ctx* h, bool on) {
                 // rebuilt in the other column width
                 drop_sell(h, *m);
                 build_sell(h, *m);
+                if (h->fp32) sell_fp32(h, *m);
             }
         }
         if (d.ah_alias) d.Ah = d.A;

@@ -822,6 +822,7 @@ int launch_sell_u(RowOp op, const CsrT<T>& a_in, const T* g, const T* u, const T
                       y2, dot, nslices)
 #define AMG_SELL_CASE(OPV)                                                                             \
     case OPV:                                                                                          \
+        if constexpr (sizeof(T) == 4 && op_has_dot<OPV>()) break;   /* the FP32 cycle forms no dots */ \
         if (iw == 1) {                                                                                 \
             if (nt) AMG_SELL_LAUNCH(OPV, true, 1);                                                     \
             else AMG_SELL_LAUNCH(OPV, false, 1);                                                       \
@@ -1544,9 +1545,7 @@ int row_launch_blocks(int rows, int width) {
 template <class T>
 int launch_row_op_t(RowOp op, int width, const CsrT<T>& a, const T* g, const T* u,
                     const T* dinv, T omega, T* y, T* y2, DotTarget dot, hipStream_t st) {
-    if constexpr (sizeof(T) == 8) {
-        if (AMG_SELL && a.sl_off) return launch_sell(op, a, g, u, dinv, omega, y, y2, dot, st);
-    }
+    if (AMG_SELL && a.sl_off) return launch_sell(op, a, g, u, dinv, omega, y, y2, dot, st);
     if (use_stream_kernel(a)) return launch_stream_any(op, a, g, u, dinv, omega, y, y2, dot, st);
     switch (width) {
         case 1: return launch_row_w<T, 1>(op, a, g, u, dinv, omega, y, y2, dot, st);
