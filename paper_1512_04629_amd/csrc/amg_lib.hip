@@ -796,10 +796,11 @@ void vcycle(amg_ctx* h, const T* b0, T* x0, Guess guess0, int dot_slot) {
         for (int k = 0; k < ta.count; ++k) {
             LevelView<T> v = level_view(h, tail + k, (T*)nullptr);
             TailLevel<T>& t = ta.lv[k];
-            t.A = CsrT<T>{v.Ah->rp, v.Ah->ci, v.ahv, v.Ah->rows, 0.0};
+            // a sparsified operator's arrays hold the Galerkin operator's entry count
+            t.A = TailCsr<T>{v.Ah->rp, v.Ah->ci, v.ahv, v.Ah->rows, (int)v.Ah->shape_nnz};
             if (tail + k < L) {
-                t.R = CsrT<T>{v.R->rp, v.R->ci, v.rv, v.R->rows, 0.0};
-                t.P = CsrT<T>{v.P->rp, v.P->ci, v.pv, v.P->rows, 0.0};
+                t.R = TailCsr<T>{v.R->rp, v.R->ci, v.rv, v.R->rows, (int)v.R->nnz};
+                t.P = TailCsr<T>{v.P->rp, v.P->ci, v.pv, v.P->rows, (int)v.P->nnz};
             }
             t.dinv = v.dinv;
             t.b = v.b;

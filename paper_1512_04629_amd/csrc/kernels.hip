@@ -1336,12 +1336,29 @@ __global__ __launch_bounds__(kBlock) void dense_invert_kernel(CsrView a, double*
 
 // Single-workgroup tail of the V-cycle (see kernels.hpp).  Rows are handled
 // by 8-lane subgroups; every step ends with a workgroup barrier, which also
-// makes the step's global writes visible to the next step.
+// makes the step's writes visible to the next step.  The cycle runs either on
+// the arrays in memory (LDS = false) or on copies in LDS (LDS = true), whose
+// generic pointers tail_ld / tail_st turn into LDS addresses so that the
+// accesses are LDS instructions rather than flat ones (a flat access counts
+// against the LDS wait counter as well and keeps the next LDS access waiting
+// for it).
 constexpr int kTailBlock = 1024;
 constexpr int kTailW = 8;
 
-template <class T, int OPT>
-__device__ __forceinline__ void tail_rows(const CsrT<T>& a, const T* __restrict__ g,
+template <bool LDS, class U>
+__device__ __forceinline__ U tail_ld(const U* p, int i) {
+    if constexpr (LDS) return ((const __attribute__((address_space(3))) U*)p)[i];
+    else return p[i];
+}
+
+template <bool LDS, class U>
+__device__ __forceinline__ void tail_st(U* p, int i, U v) {
+    if constexpr (LDS) ((__attribute__((address_space(3))) U*)p)[i] = v;
+    else p[i] = v;
+}
+
+template <class T, int OPT, bool LDS>
+__device__ __forceinline__ void tail_rows(const TailCsr<T>& a, const T* __restrict__ g,
                                           const T* u, const T* __restrict__ dinv,
                                           T omega, T* y, T* y2) {
     // OPT 0: y = u - A g        (residual)
@@ -1350,31 +1367,51 @@ __device__ __forceinline__ void tail_rows(const CsrT<T>& a, const T* __restrict_
     // OPT 3: y = u + A g        (interpolation and correction, in place)
     // OPT 4: y = g + omega dinv (u - A g)   (post-smoothing sweep)
     const int lane = threadIdx.x & (kTailW - 1);
-    for (int row0 = threadIdx.x / kTailW; row0 < a.rows; row0 += kTailBlock / kTailW) {
-        const int row = row0;
+    for (int row = threadIdx.x / kTailW; row < a.rows; row += kTailBlock / kTailW) {
+        const int end = tail_ld<LDS>(a.rp, row + 1);
+        int p = tail_ld<LDS>(a.rp, row) + lane;
         T s = T(0);
-        for (int p = a.rp[row] + lane; p < a.rp[row + 1]; p += kTailW) s += a.v[p] * g[a.ci[p]];
+        // four entries' loads issued before their products are summed (in
+        // entry order, as the one-entry loop below does)
+        for (; p + 3 * kTailW < end; p += 4 * kTailW) {
+            int c[4];
+            T v[4], x[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                c[q] = tail_ld<LDS>(a.ci, p + q * kTailW);
+                v[q] = tail_ld<LDS>(a.v, p + q * kTailW);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) x[q] = tail_ld<LDS>(g, c[q]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) s += v[q] * x[q];
+        }
+        for (; p < end; p += kTailW) s += tail_ld<LDS>(a.v, p) * tail_ld<LDS>(g, tail_ld<LDS>(a.ci, p));
         s = sub_sum<kTailW>(s);
         if (lane == 0) {
-            if constexpr (OPT == 0) y[row] = u[row] - s;
-            else if constexpr (OPT == 1) { y[row] = s; y2[row] = omega * (dinv[row] * s); }
-            else if constexpr (OPT == 2) y[row] = s;
-            else if constexpr (OPT == 3) y[row] = u[row] + s;
-            else y[row] = g[row] + omega * dinv[row] * (u[row] - s);
+            if constexpr (OPT == 0) tail_st<LDS>(y, row, tail_ld<LDS>(u, row) - s);
+            else if constexpr (OPT == 1) {
+                tail_st<LDS>(y, row, s);
+                tail_st<LDS>(y2, row, omega * (tail_ld<LDS>(dinv, row) * s));
+            } else if constexpr (OPT == 2) tail_st<LDS>(y, row, s);
+            else if constexpr (OPT == 3) tail_st<LDS>(y, row, tail_ld<LDS>(u, row) + s);
+            else
+                tail_st<LDS>(y, row, tail_ld<LDS>(g, row) +
+                                         omega * tail_ld<LDS>(dinv, row) * (tail_ld<LDS>(u, row) - s));
         }
     }
 }
 
-template <class T>
-__global__ __launch_bounds__(kTailBlock) void coarse_tail_kernel(TailArgs<T> t) {
+template <class T, bool LDS>
+__device__ __forceinline__ void tail_cycle(const TailArgs<T>& t) {
     const int last = t.count - 1;
     for (int k = 0; k < last; ++k) {
         const TailLevel<T>& L = t.lv[k];
-        tail_rows<T, 0>(L.A, L.x, L.b, nullptr, t.omega, L.r, nullptr);
+        tail_rows<T, 0, LDS>(L.A, L.x, L.b, nullptr, t.omega, L.r, nullptr);
         __syncthreads();
         const TailLevel<T>& N = t.lv[k + 1];
-        if (k + 1 < last) tail_rows<T, 1>(L.R, L.r, nullptr, N.dinv, t.omega, N.b, N.x);
-        else tail_rows<T, 2>(L.R, L.r, nullptr, nullptr, t.omega, N.b, nullptr);
+        if (k + 1 < last) tail_rows<T, 1, LDS>(L.R, L.r, nullptr, N.dinv, t.omega, N.b, N.x);
+        else tail_rows<T, 2, LDS>(L.R, L.r, nullptr, nullptr, t.omega, N.b, nullptr);
         __syncthreads();
     }
     {
@@ -1382,20 +1419,180 @@ __global__ __launch_bounds__(kTailBlock) void coarse_tail_kernel(TailArgs<T> t) 
         const int n = C.A.rows;
         for (int i = threadIdx.x; i < n; i += kTailBlock) {
             double s = 0.0;
-            const double* row = t.coarse_inv + (size_t)i * n;
-            for (int j = 0; j < n; ++j) s += row[j] * (double)C.b[j];
-            C.x[i] = (T)s;
+            for (int j = 0; j < n; ++j)
+                s += tail_ld<LDS>(t.coarse_inv, i * n + j) * (double)tail_ld<LDS>(C.b, j);
+            tail_st<LDS>(C.x, i, (T)s);
         }
         __syncthreads();
     }
     for (int k = last - 1; k >= 0; --k) {
         const TailLevel<T>& L = t.lv[k];
         const T* xc = (k + 1 == last) ? t.lv[k + 1].x : t.lv[k + 1].xt;
-        tail_rows<T, 3>(L.P, xc, L.x, nullptr, t.omega, L.x, nullptr);
+        tail_rows<T, 3, LDS>(L.P, xc, L.x, nullptr, t.omega, L.x, nullptr);
         __syncthreads();
-        tail_rows<T, 4>(L.A, L.x, L.b, L.dinv, t.omega, L.xt, nullptr);
+        tail_rows<T, 4, LDS>(L.A, L.x, L.b, L.dinv, t.omega, L.xt, nullptr);
         __syncthreads();
     }
+}
+
+template <class T>
+__global__ __launch_bounds__(kTailBlock) void coarse_tail_kernel(TailArgs<T> t) {
+    tail_cycle<T, false>(t);
+}
+
+// The staged tail: the host lays the arrays out in LDS (every array on a
+// 16-byte boundary, level by level A's row pointers, columns and values,
+// dinv, b, x, xt, r, then R's and P's arrays; last the coarsest inverse) and
+// lists the runs of 4-byte words to copy there, cut into chunks of 64 words
+// (one wave-wide load each) numbered in one flat order.
+constexpr int kTailLdsLevels = 6;
+constexpr int kTailLdsSegs = 10 * kTailLdsLevels + 3;
+constexpr int kTailWaves = kTailBlock / 64;
+struct TailSeg {
+    const uint32_t* src;
+    uint32_t begin;        // the run's first chunk in the flat order
+    uint32_t words;
+    uint32_t dst;          // its byte offset in LDS
+};
+struct TailLdsOff {        // byte offsets in LDS of one level's arrays
+    uint32_t a_rp, a_ci, a_v, dinv, b, x, xt, r, r_rp, r_ci, r_v, p_rp, p_ci, p_v;
+};
+template <class T>
+struct TailLdsArgs {
+    TailArgs<T> t;         // the arrays in memory
+    TailLdsOff off[kTailLdsLevels];
+    uint32_t inv_off;
+    uint32_t chunks;       // chunks copied; wave w takes the w-th of kTailWaves equal ranges
+    int nseg;
+    int wave_seg[kTailWaves];            // the run holding each wave's first chunk
+    TailSeg seg[kTailLdsSegs + 1];       // closed by a run that begins at chunks
+};
+
+inline size_t tail_align(size_t b) { return (b + 15) & ~(size_t)15; }
+
+// Fills a's layout and copy list; returns the LDS bytes the layout takes.
+template <class T>
+size_t tail_lds_plan(const TailArgs<T>& t, TailLdsArgs<T>& a) {
+    a.t = t;
+    size_t off = 0;
+    uint32_t chunks = 0;
+    int count = 0;
+    auto place = [&](const void* src, size_t bytes) {
+        const uint32_t at = (uint32_t)off;
+        if (src && bytes) {
+            const uint32_t words = (uint32_t)(bytes / 4);
+            a.seg[count++] = TailSeg{static_cast<const uint32_t*>(src), chunks, words, at};
+            chunks += (words + 63) / 64;
+        }
+        off += tail_align(bytes);
+        return at;
+    };
+    for (int k = 0; k < t.count; ++k) {
+        const TailLevel<T>& G = t.lv[k];
+        TailLdsOff& o = a.off[k];
+        const size_t n = (size_t)G.A.rows;
+        o.a_rp = place(G.A.rp, (n + 1) * 4);
+        o.a_ci = place(G.A.ci, (size_t)G.A.cap * 4);
+        o.a_v = place(G.A.v, (size_t)G.A.cap * sizeof(T));
+        o.dinv = place(G.dinv, n * sizeof(T));
+        o.b = place(k == 0 ? G.b : nullptr, n * sizeof(T));
+        o.x = place(k == 0 ? G.x : nullptr, n * sizeof(T));
+        o.xt = place(nullptr, n * sizeof(T));
+        o.r = place(nullptr, n * sizeof(T));
+        o.r_rp = o.r_ci = o.r_v = o.p_rp = o.p_ci = o.p_v = 0;
+        if (k + 1 < t.count) {
+            o.r_rp = place(G.R.rp, ((size_t)G.R.rows + 1) * 4);
+            o.r_ci = place(G.R.ci, (size_t)G.R.cap * 4);
+            o.r_v = place(G.R.v, (size_t)G.R.cap * sizeof(T));
+            o.p_rp = place(G.P.rp, ((size_t)G.P.rows + 1) * 4);
+            o.p_ci = place(G.P.ci, (size_t)G.P.cap * 4);
+            o.p_v = place(G.P.v, (size_t)G.P.cap * sizeof(T));
+        }
+    }
+    const size_t nl = (size_t)t.lv[t.count - 1].A.rows;
+    a.inv_off = place(t.coarse_inv, nl * nl * 8);
+    a.seg[count] = TailSeg{nullptr, chunks, 0, 0};
+    a.nseg = count;
+    a.chunks = chunks;
+    const uint32_t per = (chunks + kTailWaves - 1) / kTailWaves;
+    for (int w = 0, si = 0; w < kTailWaves; ++w) {
+        const uint32_t c = (uint32_t)w * per;
+        while (si + 1 < count && c >= a.seg[si + 1].begin) ++si;
+        a.wave_seg[w] = si;
+    }
+    return off;
+}
+
+template <class T>
+__global__ __launch_bounds__(kTailBlock) void coarse_tail_lds_kernel(TailLdsArgs<T> a) {
+    extern __shared__ __align__(16) unsigned char tail_smem[];
+    // the arguments with their pointers redirected into LDS, and the copy list
+    // closed by a run that starts at the end
+    __shared__ __align__(16) unsigned char args_raw[sizeof(TailArgs<T>)];
+    __shared__ TailSeg segs[kTailLdsSegs + 1];
+    TailArgs<T>& s = *reinterpret_cast<TailArgs<T>*>(args_raw);
+    const TailArgs<T>& t = a.t;
+    const int tid = threadIdx.x;
+    if (tid < t.count) {
+        const TailLevel<T>& G = t.lv[tid];
+        const TailLdsOff& o = a.off[tid];
+        TailLevel<T> L;
+        L.A = TailCsr<T>{reinterpret_cast<const int32_t*>(tail_smem + o.a_rp),
+                         reinterpret_cast<const int32_t*>(tail_smem + o.a_ci),
+                         reinterpret_cast<const T*>(tail_smem + o.a_v), G.A.rows, G.A.cap};
+        L.R = TailCsr<T>{reinterpret_cast<const int32_t*>(tail_smem + o.r_rp),
+                         reinterpret_cast<const int32_t*>(tail_smem + o.r_ci),
+                         reinterpret_cast<const T*>(tail_smem + o.r_v), G.R.rows, G.R.cap};
+        L.P = TailCsr<T>{reinterpret_cast<const int32_t*>(tail_smem + o.p_rp),
+                         reinterpret_cast<const int32_t*>(tail_smem + o.p_ci),
+                         reinterpret_cast<const T*>(tail_smem + o.p_v), G.P.rows, G.P.cap};
+        L.dinv = reinterpret_cast<const T*>(tail_smem + o.dinv);
+        L.b = reinterpret_cast<T*>(tail_smem + o.b);
+        L.x = reinterpret_cast<T*>(tail_smem + o.x);
+        L.xt = reinterpret_cast<T*>(tail_smem + o.xt);
+        L.r = reinterpret_cast<T*>(tail_smem + o.r);
+        s.lv[tid] = L;
+    }
+    if (tid == 0) {
+        s.count = t.count;
+        s.coarse_inv = reinterpret_cast<const double*>(tail_smem + a.inv_off);
+        s.omega = t.omega;
+    }
+    if (tid <= a.nseg) segs[tid] = a.seg[tid];
+    __syncthreads();
+    // the copy: each wave takes a range of chunks and loads each straight
+    // into LDS with one wave-wide load, none waited for until the end
+    {
+        const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+        const uint32_t per = (a.chunks + kTailWaves - 1) / kTailWaves;
+        uint32_t c = (uint32_t)wave * per;
+        const uint32_t cend = min(a.chunks, c + per);
+        int si = a.wave_seg[wave];
+        while (c < cend) {
+            const uint32_t next = __builtin_amdgcn_readfirstlane(segs[si + 1].begin);
+            if (c >= next) {
+                ++si;
+                continue;
+            }
+            const uint32_t begin = __builtin_amdgcn_readfirstlane(segs[si].begin);
+            const uint32_t words = __builtin_amdgcn_readfirstlane(segs[si].words);
+            const uint32_t dst = __builtin_amdgcn_readfirstlane(segs[si].dst);
+            const uint32_t* src = segs[si].src;
+            for (const uint32_t stop = min(next, cend); c < stop; ++c) {
+                const uint32_t w = (c - begin) * 64;
+                if (w + lane < words)
+                    __builtin_amdgcn_global_load_lds(
+                        (const __attribute__((address_space(1))) void*)(src + w + lane),
+                        (__attribute__((address_space(3))) void*)(tail_smem + dst + w * 4), 4, 0, 0);
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+    }
+    __syncthreads();
+    tail_cycle<T, true>(s);
+    const int n0 = t.lv[0].A.rows;
+    const T* xt = s.lv[0].xt;
+    for (int i = tid; i < n0; i += kTailBlock) t.lv[0].xt[i] = tail_ld<true>(xt, i);
 }
 
 // exclusive scan: 1024 items per block in pass 1 and 3
@@ -1711,13 +1908,42 @@ void launch_compact_lump(int width, const CsrView& a, const uint8_t* keep, const
 
 int dense_invert_max() { return kDenseInvMax; }
 
-void launch_coarse_tail(const TailArgs<double>& t, hipStream_t st) {
-    hipLaunchKernelGGL(coarse_tail_kernel<double>, dim3(1), dim3(kTailBlock), 0, st, t);
+// Dynamic LDS the staged tail may take: the device's limit per workgroup less
+// the kernel's static LDS (its arguments and copy list); 0 if the limit
+// cannot be read or raised.
+template <class T>
+size_t tail_lds_limit() {
+    static const size_t limit = [] {
+        int dev = 0, per_block = 0;
+        hipFuncAttributes fa{};
+        const void* k = reinterpret_cast<const void*>(coarse_tail_lds_kernel<T>);
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+            hipFuncGetAttributes(&fa, k) != hipSuccess || (size_t)per_block <= fa.sharedSizeBytes)
+            return (size_t)0;
+        const size_t dyn = (size_t)per_block - fa.sharedSizeBytes;
+        if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn) != hipSuccess) return (size_t)0;
+        return dyn;
+    }();
+    return limit;
 }
 
-void launch_coarse_tail(const TailArgs<float>& t, hipStream_t st) {
-    hipLaunchKernelGGL(coarse_tail_kernel<float>, dim3(1), dim3(kTailBlock), 0, st, t);
+template <class T>
+void launch_coarse_tail_t(const TailArgs<T>& t, hipStream_t st) {
+    if (t.count <= kTailLdsLevels) {
+        TailLdsArgs<T> a;
+        const size_t bytes = tail_lds_plan(t, a);
+        if (bytes <= tail_lds_limit<T>()) {
+            hipLaunchKernelGGL(coarse_tail_lds_kernel<T>, dim3(1), dim3(kTailBlock), bytes, st, a);
+            return;
+        }
+    }
+    hipLaunchKernelGGL(coarse_tail_kernel<T>, dim3(1), dim3(kTailBlock), 0, st, t);
 }
+
+void launch_coarse_tail(const TailArgs<double>& t, hipStream_t st) { launch_coarse_tail_t<double>(t, st); }
+
+void launch_coarse_tail(const TailArgs<float>& t, hipStream_t st) { launch_coarse_tail_t<float>(t, st); }
 
 void launch_dense_invert(const CsrView& a, double* inv, int* singular, hipStream_t st) {
     hipLaunchKernelGGL(dense_invert_kernel, dim3(1), dim3(kBlock), 0, st, a, inv, singular);

@@ -147,9 +147,17 @@ void launch_fill_f32(int64_t n, float* p, float v, hipStream_t st);
 // level-t result is in lv[0].xt.
 constexpr int kTailMaxLevels = 12;
 template <class T>
+struct TailCsr {
+    const int32_t* rp;
+    const int32_t* ci;
+    const T* v;
+    int rows;
+    int cap;             // entries ci and v hold (for a sparsified operator its capacity)
+};
+template <class T>
 struct TailLevel {
-    CsrT<T> A;           // sparsified operator of the level
-    CsrT<T> R, P;        // restriction to / interpolation from the next level
+    TailCsr<T> A;        // sparsified operator of the level
+    TailCsr<T> R, P;     // restriction to / interpolation from the next level
     const T* dinv;
     T *b, *x, *xt, *r;
 };
@@ -160,6 +168,12 @@ struct TailArgs {
     const double* coarse_inv;   // FP64 in both precisions
     T omega;
 };
+// When the tail has at most 6 levels and everything it touches fits the
+// workgroup's LDS, the launch first copies the operators, the coarsest
+// inverse and the level-t right-hand side and sweep there (every entry an
+// operator's capacity holds, so the copy needs no count from the device) and
+// runs the cycle on the copies, writing only the level-t result back;
+// otherwise the cycle runs on the arrays in memory.
 void launch_coarse_tail(const TailArgs<double>& t, hipStream_t st);
 void launch_coarse_tail(const TailArgs<float>& t, hipStream_t st);
 
