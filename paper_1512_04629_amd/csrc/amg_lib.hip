@@ -1017,6 +1017,7 @@ amg_status solve(amg_ctx* h, const double* b, double* x, const amg_solve_params&
     double nws = nr0;
     int inwin = 0;
     int rz_slot = S_RZ0;
+    double nrf_read = -1.0;   // the final true residual norm, when the loop has read it
     if (!std::isfinite(nr0)) {
         st = AMG_ERR_BREAKDOWN;
     } else if (nr0 == 0.0) {
@@ -1054,6 +1055,12 @@ amg_status solve(amg_ctx* h, const double* b, double* x, const amg_solve_params&
                 else vcycle<double>(h, b, x, Guess::kNonzero, -1);
                 row_op(h, AMG_K_RESIDUAL, 0, kResidNorm, A, x, b, nullptr, r, nullptr, S_NR2);
             }
+            // the last iteration of an adaptive window needs the true
+            // residual whatever its outcome (for the window test, or as the
+            // final residual if it converges): computed before, read back
+            // with the iteration's scalars
+            const bool window_end = p.adaptive && inwin + 1 == p.k;
+            if (window_end) row_op(h, AMG_K_RESIDUAL, 0, kResidNorm, A, x, b, nullptr, h->rt, nullptr, S_NRT);
             const double* sc = read_scalars(h);
             if (pcg && sc[S_FLAG] != 0.0) { st = AMG_ERR_BREAKDOWN; break; }
             const double nr = std::sqrt(sc[S_NR2]);
@@ -1061,11 +1068,15 @@ amg_status solve(amg_ctx* h, const double* b, double* x, const amg_solve_params&
             inwin++;
             if (hist) hist[info.iters] = nr;
             if (!std::isfinite(nr)) { st = AMG_ERR_BREAKDOWN; break; }
-            if (nr <= p.rtol * nr0) { info.converged = 1; st = AMG_OK; break; }
+            if (nr <= p.rtol * nr0) {
+                info.converged = 1;
+                st = AMG_OK;
+                if (window_end) nrf_read = std::sqrt(sc[S_NRT]);
+                break;
+            }
             bool restart = false;
-            if (p.adaptive && inwin == p.k) {
-                row_op(h, AMG_K_RESIDUAL, 0, kResidNorm, A, x, b, nullptr, h->rt, nullptr, S_NRT);
-                double nrt = std::sqrt(read_scalars(h)[S_NRT]);
+            if (window_end) {
+                double nrt = std::sqrt(sc[S_NRT]);
                 const double rho = std::pow(nrt / nws, 1.0 / (double)p.k);
                 bool any = false;
                 for (size_t l = 1; l < h->lv.size(); ++l) any = any || h->lv[l].gamma > 0.0;
@@ -1105,8 +1116,11 @@ amg_status solve(amg_ctx* h, const double* b, double* x, const amg_solve_params&
             }
         }
     }
-    row_op(h, AMG_K_RESIDUAL, 0, kResidNorm, A, x, b, nullptr, r, nullptr, S_NRT);
-    const double nrf = std::sqrt(read_scalars(h)[S_NRT]);
+    double nrf = nrf_read;
+    if (nrf < 0.0) {
+        row_op(h, AMG_K_RESIDUAL, 0, kResidNorm, A, x, b, nullptr, r, nullptr, S_NRT);
+        nrf = std::sqrt(read_scalars(h)[S_NRT]);
+    }
     info.relres = nr0 > 0.0 ? nrf / nr0 : 0.0;
     info.rho_avg = (info.iters > 0 && info.relres > 0.0) ? std::pow(info.relres, 1.0 / info.iters) : 0.0;
     if (info_out) *info_out = info;
