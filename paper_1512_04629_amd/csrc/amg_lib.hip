@@ -170,7 +170,11 @@ struct amg_ctx {
     double* scal = nullptr;
     double* partials = nullptr;
     int partial_cap = 0;
-    double* pinned = nullptr;
+    double* pinned = nullptr;        // host-coherent: the scalar slots, then the readback sequence word
+    double* pinned_dev = nullptr;    // its device address
+    uint32_t* flag_host = nullptr;
+    uint32_t* flag_dev = nullptr;
+    uint32_t pub_seq = 0;
     int32_t* scan_scratch = nullptr;
     int32_t* cnt = nullptr;
     int* missing = nullptr;          // minimal-pattern and index-width checks
@@ -941,10 +945,25 @@ void ensure_solve_buffers(amg_ctx* h) {
     if (!h->rt) h->rt = dalloc_n<double>(h, n);
 }
 
-// reads the scalar slots into host memory
+// Reads the scalar slots into host memory: a one-workgroup kernel writes
+// them into the handle's host-coherent buffer and then a sequence number;
+// the host polls for that number (a fault or a failed launch ends the wait
+// through the stream's status) instead of waiting for a copy and a stream
+// synchronization.  Only the slots are guaranteed on return: a caller that
+// needs another download complete synchronizes the stream itself.
 const double* read_scalars(amg_ctx* h) {
-    download(h, h->pinned, h->scal, S_COUNT);
-    sync(h);
+    const uint32_t seq = ++h->pub_seq;
+    launch_publish_scalars(S_COUNT, h->scal, h->pinned_dev, h->flag_dev, seq, h->stream);
+    check_launch();
+    const uint32_t* flag = h->flag_host;
+    for (uint64_t k = 1; __atomic_load_n(flag, __ATOMIC_ACQUIRE) != seq; ++k) {
+        if ((k & 4095) != 0) continue;
+        const hipError_t e = hipStreamQuery(h->stream);
+        if (e == hipErrorNotReady) continue;
+        if (e != hipSuccess) throw AmgFailure{AMG_ERR_DEVICE, std::string("device error: ") + hipGetErrorString(e)};
+        if (__atomic_load_n(flag, __ATOMIC_ACQUIRE) != seq)
+            throw AmgFailure{AMG_ERR_DEVICE, "scalar readback: the stream finished without publishing"};
+    }
     return h->pinned;
 }
 
@@ -1007,7 +1026,10 @@ amg_status solve(amg_ctx* h, const double* b, double* x, const amg_solve_params&
     launch_fill_f64(S_COUNT, h->scal, 0.0, h->stream);
     row_op(h, AMG_K_RESIDUAL, 0, kResidNorm, A, x, b, nullptr, r, nullptr, S_NR2);
     int singular = 0;
-    if (h->check_singular) download(h, &singular, h->singular, 1);
+    if (h->check_singular) {
+        download(h, &singular, h->singular, 1);
+        sync(h);
+    }
     const double nr0 = std::sqrt(read_scalars(h)[S_NR2]);
     if (h->check_singular) {
         h->check_singular = false;
@@ -1315,7 +1337,10 @@ amg_status solve_block(amg_ctx* h, int k, int nrhs, const double* b, double* x, 
     launch_fill_f64(1, h->scal + S_LIVE, (double)nrhs, h->stream);
     block_outer<T>(h, k, b, x);
     int singular = 0;
-    if (h->check_singular) download(h, &singular, h->singular, 1);
+    if (h->check_singular) {
+        download(h, &singular, h->singular, 1);
+        sync(h);
+    }
     const double* sc = read_scalars(h);
     if (h->check_singular) {
         h->check_singular = false;
@@ -1416,7 +1441,10 @@ amg_status solve_block_pcg(amg_ctx* h, int k, int nrhs, const double* b, double*
     launch_fill_f64(1, h->scal + S_LIVE, (double)nrhs, h->stream);
     block_outer<T>(h, k, b, x, h->bcg_r);
     int singular = 0;
-    if (h->check_singular) download(h, &singular, h->singular, 1);
+    if (h->check_singular) {
+        download(h, &singular, h->singular, 1);
+        sync(h);
+    }
     const double* sc = read_scalars(h);
     if (h->check_singular) {
         h->check_singular = false;
@@ -1972,7 +2000,14 @@ void finish_setup(amg_ctx* h) {
     h->scal = dalloc_n<double>(h, S_COUNT);
     launch_fill_f64(S_COUNT, h->scal, 0.0, h->stream);
     check_launch();
-    HIP_CHECK(hipHostMalloc((void**)&h->pinned, sizeof(double) * S_COUNT, hipHostMallocDefault));
+    // the scalar slots, then the readback's sequence word, host-coherent so
+    // that the device's writes reach the host without a copy
+    HIP_CHECK(hipHostMalloc((void**)&h->pinned, sizeof(double) * S_COUNT + 64,
+                            hipHostMallocCoherent | hipHostMallocMapped));
+    h->flag_host = reinterpret_cast<uint32_t*>(h->pinned + S_COUNT);
+    *h->flag_host = 0;
+    HIP_CHECK(hipHostGetDevicePointer((void**)&h->pinned_dev, h->pinned, 0));
+    h->flag_dev = reinterpret_cast<uint32_t*>(h->pinned_dev + S_COUNT);
     sync(h);
     refresh_coarse_inverse(h);
     h->prof.assign((size_t)AMG_K_NUM * h->lv.size(), ProfAcc{});
