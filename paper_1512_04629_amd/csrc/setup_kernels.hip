@@ -4,9 +4,6 @@
 // hierarchy is bitwise the host one (for the same C/F split).
 #include "setup_kernels.hpp"
 
-#include <rocprim/device/device_radix_sort.hpp>
-#include <rocprim/device/device_scan.hpp>
-
 #include <algorithm>
 #include <climits>
 
@@ -517,19 +514,278 @@ void launch_symmetrize(int n, const int32_t* rp, const int32_t* ci, const double
     hipLaunchKernelGGL(symmetrize_kernel, dim3(grid_of(n)), dim3(kSB), 0, st, n, rp, ci, v, out, err);
 }
 
+namespace {
+
+// ---------------------------------------------------------------------------
+// Exclusive scan of int64 counts and a stable LSD radix sort of (key, value)
+// pairs: the sort that groups the Galerkin product's terms by (row, column)
+// and the transpose's entries by (column, row).
+// ---------------------------------------------------------------------------
+
+// scan: 4,096 entries per block (256 threads, 16 consecutive entries each)
+constexpr int kScanPer = 16;
+constexpr int kScanTile64 = kSB * kScanPer;
+
+// block-wide exclusive scan of one int64 per thread (wave shuffles, then the
+// four wave totals through LDS); *total receives the block's sum
+__device__ __forceinline__ int64_t block_exclusive_scan64(int64_t v, int64_t* wsum, int64_t* total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int64_t incl = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += t;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    int64_t before = 0, all = 0;
+#pragma unroll
+    for (int k = 0; k < kSB / 64; ++k) {
+        if (k < w) before += wsum[k];
+        all += wsum[k];
+    }
+    *total = all;
+    __syncthreads();
+    return before + incl - v;
+}
+
+__global__ __launch_bounds__(kSB) void scan64_reduce_kernel(int64_t n, const int64_t* __restrict__ in,
+                                                            int64_t* __restrict__ bsum) {
+    __shared__ int64_t wsum[kSB / 64];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile64;
+    int64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        const int64_t i = base + (int64_t)k * kSB + threadIdx.x;
+        if (i < n) s += in[i];
+    }
+    int64_t tot;
+    block_exclusive_scan64(s, wsum, &tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+// the block sums, scanned in place by one workgroup of 1,024 threads, each
+// owning a contiguous range
+__global__ __launch_bounds__(1024) void scan64_blocks_kernel(int64_t nb, int64_t* bsum) {
+    __shared__ int64_t part[1024];
+    const int64_t per = (nb + 1023) / 1024;
+    const int64_t lo = threadIdx.x * per, hi = std::min<int64_t>(nb, lo + per);
+    int64_t s = 0;
+    for (int64_t i = lo; i < hi; ++i) s += bsum[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const int64_t t = threadIdx.x >= o ? part[threadIdx.x - o] : 0;
+        __syncthreads();
+        part[threadIdx.x] += t;
+        __syncthreads();
+    }
+    int64_t run = part[threadIdx.x] - s;
+    for (int64_t i = lo; i < hi; ++i) {
+        const int64_t v = bsum[i];
+        bsum[i] = run;
+        run += v;
+    }
+}
+
+// each thread scans its 16 consecutive entries after the block-wide scan of
+// the thread sums; entries staged through LDS so that both the loads and the
+// stores are coalesced
+__global__ __launch_bounds__(kSB) void scan64_apply_kernel(int64_t n, const int64_t* __restrict__ in,
+                                                           const int64_t* __restrict__ boff,
+                                                           int64_t* __restrict__ out) {
+    __shared__ int64_t tile[kScanTile64 + kScanTile64 / 32];
+    __shared__ int64_t wsum[kSB / 64];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile64;
+    // padded index: one spare slot every 32 entries keeps a thread's 16
+    // consecutive entries off each other's LDS banks
+    auto at = [](int i) { return i + (i >> 5); };
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        const int i = k * kSB + threadIdx.x;
+        tile[at(i)] = base + i < n ? in[base + i] : 0;
+    }
+    __syncthreads();
+    int64_t v[kScanPer];
+    int64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        v[k] = tile[at(threadIdx.x * kScanPer + k)];
+        s += v[k];
+    }
+    int64_t tot;
+    int64_t run = block_exclusive_scan64(s, wsum, &tot) + boff[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        tile[at(threadIdx.x * kScanPer + k)] = run;
+        run += v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        const int i = k * kSB + threadIdx.x;
+        if (base + i < n) out[base + i] = tile[at(i)];
+    }
+}
+
+int64_t scan64_blocks(int64_t n) { return std::max<int64_t>(1, (n + kScanTile64 - 1) / kScanTile64); }
+
+void launch_scan64(int64_t n, const int64_t* in, int64_t* out, int64_t* bsum, hipStream_t st) {
+    const int64_t nb = scan64_blocks(n);
+    hipLaunchKernelGGL(scan64_reduce_kernel, dim3((unsigned)nb), dim3(kSB), 0, st, n, in, bsum);
+    hipLaunchKernelGGL(scan64_blocks_kernel, dim3(1), dim3(1024), 0, st, nb, bsum);
+    hipLaunchKernelGGL(scan64_apply_kernel, dim3((unsigned)nb), dim3(kSB), 0, st, n, in, bsum, out);
+}
+
+// radix sort: 8-bit digits, 4,096 pairs per block (16 rounds of 256, pair
+// r * 256 + t of the block held by thread t), so that a block's pairs in
+// round order are its pairs in input order
+constexpr int kRadixBits = 8;
+constexpr int kRadixBins = 1 << kRadixBits;
+constexpr int kRadixRounds = 16;
+constexpr int kRadixTile = kSB * kRadixRounds;
+static_assert(kRadixBins == kSB, "one digit per thread in the offset steps");
+
+// lanes of this wave holding the same digit (lanes with valid = false take
+// part in no group); eight ballots, one per digit bit
+__device__ __forceinline__ uint64_t same_digit_lanes(int d, bool valid) {
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < kRadixBits; ++b) {
+        const uint64_t ones = __ballot((d >> b) & 1);
+        peers &= ((d >> b) & 1) ? ones : ~ones;
+    }
+    return peers;
+}
+
+__device__ __forceinline__ uint64_t lanes_below() {
+    return (1ull << (threadIdx.x & 63)) - 1ull;
+}
+
+// per-block digit counts, digit-major: cnt[d * nb + block]
+__global__ __launch_bounds__(kSB) void radix_count_kernel(int64_t m, int shift, const uint64_t* __restrict__ keys,
+                                                          int64_t* __restrict__ cnt, int64_t nb) {
+    __shared__ int hist[kRadixBins];
+    hist[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+    uint64_t k[kRadixRounds];
+#pragma unroll
+    for (int r = 0; r < kRadixRounds; ++r) {
+        const int64_t e = base + (int64_t)r * kSB + threadIdx.x;
+        k[r] = e < m ? keys[e] : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < kRadixRounds; ++r) {
+        const bool valid = base + (int64_t)r * kSB + threadIdx.x < m;
+        const int d = (int)((k[r] >> shift) & (kRadixBins - 1));
+        const uint64_t peers = same_digit_lanes(d, valid);
+        // the lowest lane of each group adds the group's size
+        if (valid && (peers & lanes_below()) == 0) atomicAdd(&hist[d], __popcll(peers));
+    }
+    __syncthreads();
+    cnt[(int64_t)threadIdx.x * nb + blockIdx.x] = hist[threadIdx.x];
+}
+
+// stable scatter: pair (r, t) of the block goes to
+//   first[d] (the scanned count of digit d before this block)
+//   + the pairs of digit d in earlier rounds of this block
+//   + those of earlier waves in this round + those of lower lanes in this wave
+__global__ __launch_bounds__(kSB) void radix_scatter_kernel(int64_t m, int shift,
+                                                            const uint64_t* __restrict__ kin,
+                                                            const double* __restrict__ vin,
+                                                            uint64_t* __restrict__ kout,
+                                                            double* __restrict__ vout,
+                                                            const int64_t* __restrict__ first, int64_t nb) {
+    constexpr int kWaves = kSB / 64;
+    __shared__ int64_t next[kRadixBins];          // next free position per digit
+    __shared__ int wcnt[kWaves][kRadixBins];      // this round's count per wave and digit
+    __shared__ int64_t wpos[kWaves][kRadixBins];  // this round's first position per wave and digit
+    const int t = threadIdx.x, w = t >> 6;
+    next[t] = first[(int64_t)t * nb + blockIdx.x];
+#pragma unroll
+    for (int q = 0; q < kWaves; ++q) wcnt[q][t] = 0;
+    const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+    uint64_t k[kRadixRounds];
+    double v[kRadixRounds];
+#pragma unroll
+    for (int r = 0; r < kRadixRounds; ++r) {
+        const int64_t e = base + (int64_t)r * kSB + t;
+        k[r] = e < m ? kin[e] : 0;
+        v[r] = e < m ? vin[e] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRadixRounds; ++r) {
+        const bool valid = base + (int64_t)r * kSB + t < m;
+        const int d = (int)((k[r] >> shift) & (kRadixBins - 1));
+        const uint64_t peers = same_digit_lanes(d, valid);
+        const int rank = __popcll(peers & lanes_below());
+        if (valid && rank == 0) wcnt[w][d] = __popcll(peers);
+        __syncthreads();
+        {
+            // thread t owns digit t: positions of its waves, then clear
+            int64_t p = next[t];
+#pragma unroll
+            for (int q = 0; q < kWaves; ++q) {
+                wpos[q][t] = p;
+                p += wcnt[q][t];
+                wcnt[q][t] = 0;
+            }
+            next[t] = p;
+        }
+        __syncthreads();
+        if (valid) {
+            const int64_t pos = wpos[w][d] + rank;
+            kout[pos] = k[r];
+            vout[pos] = v[r];
+        }
+    }
+}
+
+size_t align_up(size_t b) { return (b + 255) & ~(size_t)255; }
+
+}  // namespace
+
 hipError_t sort_pairs(void* temp, size_t& temp_bytes, uint64_t* keys[2], double* vals[2], int64_t m, int bits,
                       int& result, hipStream_t st) {
-    rocprim::double_buffer<uint64_t> kb(keys[0], keys[1]);
-    rocprim::double_buffer<double> vb(vals[0], vals[1]);
-    const hipError_t e = rocprim::radix_sort_pairs(temp, temp_bytes, kb, vb, (size_t)m, 0u, (unsigned)bits, st);
-    result = kb.current() == keys[0] ? 0 : 1;
-    return e;
+    const int64_t nb = std::max<int64_t>(1, (m + kRadixTile - 1) / kRadixTile);
+    const int64_t ncnt = nb * kRadixBins;
+    const size_t cnt_bytes = align_up(sizeof(int64_t) * (size_t)ncnt);
+    const size_t need = 2 * cnt_bytes + align_up(sizeof(int64_t) * (size_t)scan64_blocks(ncnt));
+    const int passes = (std::max(bits, 0) + kRadixBits - 1) / kRadixBits;
+    result = passes & 1;
+    if (temp == nullptr) {
+        temp_bytes = need;
+        return hipSuccess;
+    }
+    if (temp_bytes < need) return hipErrorInvalidValue;
+    if (m <= 0) return hipSuccess;
+    if (nb > INT_MAX) return hipErrorInvalidValue;
+    int64_t* cnt = static_cast<int64_t*>(temp);
+    int64_t* first = reinterpret_cast<int64_t*>(static_cast<char*>(temp) + cnt_bytes);
+    int64_t* bsum = reinterpret_cast<int64_t*>(static_cast<char*>(temp) + 2 * cnt_bytes);
+    for (int p = 0; p < passes; ++p) {
+        const int src = p & 1, dst = src ^ 1, shift = p * kRadixBits;
+        hipLaunchKernelGGL(radix_count_kernel, dim3((unsigned)nb), dim3(kSB), 0, st, m, shift, keys[src], cnt, nb);
+        launch_scan64(ncnt, cnt, first, bsum, st);
+        hipLaunchKernelGGL(radix_scatter_kernel, dim3((unsigned)nb), dim3(kSB), 0, st, m, shift, keys[src],
+                           vals[src], keys[dst], vals[dst], first, nb);
+    }
+    return hipGetLastError();
 }
 
 hipError_t scan_counts(void* temp, size_t& temp_bytes, const int64_t* in, int64_t* out, int64_t m,
                        hipStream_t st) {
-    return rocprim::exclusive_scan(temp, temp_bytes, in, out, (int64_t)0, (size_t)(m + 1), rocprim::plus<int64_t>(),
-                                   st);
+    const int64_t n = m + 1;
+    const size_t need = align_up(sizeof(int64_t) * (size_t)scan64_blocks(n));
+    if (temp == nullptr) {
+        temp_bytes = need;
+        return hipSuccess;
+    }
+    if (temp_bytes < need || scan64_blocks(n) > INT_MAX) return hipErrorInvalidValue;
+    launch_scan64(n, in, out, static_cast<int64_t*>(temp), st);
+    return hipGetLastError();
 }
 
 }  // namespace amg355
