@@ -109,23 +109,86 @@ __device__ __forceinline__ void add_to_fp64(double* acc, const v2d& v) {
     st16(acc, a);
 }
 
-// s = sum_p a_ip G[j_p, c0 .. c0+V) over the row [beg, end), two independent
-// accumulation chains so that two gathers are in flight per lane
-template <class T, int K>
+// s = sum_p a_ip G[j_p, c0 .. c0+V) over the row [beg, end).  The row's
+// LPR lanes (one per 16 bytes of columns) each load one entry of the row,
+// and the entries are handed round the group with lane shuffles: one column
+// index and one value load per lane for up to LPR entries, where loading
+// each entry in every lane of the group would cost an index and a value
+// load per entry (the kernels are bound by the count of vector memory
+// instructions, the gathers included, more than by their bytes).  Entries
+// at even and odd positions of the row go to two accumulators, added at the
+// end, with two gathers in flight (the chunks of LPR entries start at even
+// positions; a row of one lane takes its entries two at a time).  With DIAG, *gd receives G[i, c0 ..
+// c0+V) from the gather of the row's diagonal entry (loaded if the row has
+// none), so a sweep does not load its own x_i again.
+template <class T, int K, bool DIAG = false>
 __device__ __forceinline__ typename Vec16<T>::type row_gather_sum(const CsrT<T>& a, const T* __restrict__ g,
-                                                                  int beg, int end, int c0) {
+                                                                  int beg, int end, int c0, int i = 0,
+                                                                  typename Vec16<T>::type* gd = nullptr) {
     using VT = typename Vec16<T>::type;
-    VT s0{}, s1{};
-    int p = beg;
-    for (; p + 1 < end; p += 2) {
-        const int j0 = mat_ld(a.ci + p), j1 = mat_ld(a.ci + p + 1);
-        const T v0 = mat_ld(a.v + p), v1 = mat_ld(a.v + p + 1);
-        const VT g0 = ld16<VT>(g + j0 * K + c0);
-        const VT g1 = ld16<VT>(g + j1 * K + c0);
-        s0 += v0 * g0;
-        s1 += v1 * g1;
+    constexpr int LPR = K / Vec16<T>::n;
+    const int q = threadIdx.x & (LPR - 1);
+    VT s0{}, s1{}, dg{};
+    bool found = false;
+    if constexpr (LPR == 1) {
+        // a lane per row (4 FP32 columns): its own loads, two entries a step
+        int p = beg;
+        for (; p + 1 < end; p += 2) {
+            const int j0 = mat_ld(a.ci + p), j1 = mat_ld(a.ci + p + 1);
+            const T v0 = mat_ld(a.v + p), v1 = mat_ld(a.v + p + 1);
+            const VT g0 = ld16<VT>(g + j0 * K + c0);
+            const VT g1 = ld16<VT>(g + j1 * K + c0);
+            s0 += v0 * g0;
+            s1 += v1 * g1;
+            if constexpr (DIAG) {
+                if (j0 == i) dg = g0;
+                if (j1 == i) dg = g1;
+                found = found || j0 == i || j1 == i;
+            }
+        }
+        if (p < end) {
+            const int j0 = mat_ld(a.ci + p);
+            const VT g0 = ld16<VT>(g + j0 * K + c0);
+            s0 += mat_ld(a.v + p) * g0;
+            if constexpr (DIAG) {
+                if (j0 == i) dg = g0;
+                found = found || j0 == i;
+            }
+        }
+    } else
+    for (int p = beg; p < end; p += LPR) {
+        const int qq = min(p + q, end - 1);
+        const int myj = mat_ld(a.ci + qq);
+        const T myv = mat_ld(a.v + qq);
+        const int cnt = min(LPR, end - p);
+        int k = 0;
+        for (; k + 1 < cnt; k += 2) {
+            const int j0 = __shfl(myj, k, LPR), j1 = __shfl(myj, k + 1, LPR);
+            const T v0 = __shfl(myv, k, LPR), v1 = __shfl(myv, k + 1, LPR);
+            const VT g0 = ld16<VT>(g + j0 * K + c0);
+            const VT g1 = ld16<VT>(g + j1 * K + c0);
+            s0 += v0 * g0;
+            s1 += v1 * g1;
+            if constexpr (DIAG) {
+                if (j0 == i) dg = g0;
+                if (j1 == i) dg = g1;
+                found = found || j0 == i || j1 == i;
+            }
+        }
+        if (k < cnt) {
+            const int j0 = __shfl(myj, k, LPR);
+            const VT g0 = ld16<VT>(g + j0 * K + c0);
+            s0 += __shfl(myv, k, LPR) * g0;
+            if constexpr (DIAG) {
+                if (j0 == i) dg = g0;
+                found = found || j0 == i;
+            }
+        }
     }
-    if (p < end) s0 += mat_ld(a.v + p) * ld16<VT>(g + mat_ld(a.ci + p) * K + c0);
+    if constexpr (DIAG) {
+        if (!found) dg = ld16<VT>(g + i * K + c0);
+        *gd = dg;
+    }
     return s0 + s1;
 }
 
@@ -141,12 +204,17 @@ __global__ __launch_bounds__(kBlk) void block_row_kernel(CsrT<T> a, const T* __r
     const int lb = logical_block();
     const int sub = threadIdx.x / LPR;
     const int c0 = (threadIdx.x % LPR) * V;
-    if (live && c0 >= (int)*live) return;   // columns past the live prefix are left as they are
+    // columns past the live prefix are left as they are; their lanes still
+    // load and hand round their rows' entries (gathering the first columns)
+    const bool dead = live && c0 >= (int)*live;
     for (TileWalk w = tile_walk(ntiles); w.t < w.end; w.t += w.stride) {
         const int t = w.t;
         const int i = t * RPT + sub;
         if (i >= a.rows) break;
-        const VT s = row_gather_sum<T, K>(a, g, a.rp[i], a.rp[i + 1], c0);
+        constexpr bool kSweep = OP == kBJacobi || OP == kBJacobiAccum;
+        VT gi;
+        const VT s = row_gather_sum<T, K, kSweep>(a, g, a.rp[i], a.rp[i + 1], dead ? 0 : c0, i, &gi);
+        if (dead) continue;
         const int o = i * K + c0;
         if constexpr (OP == kBSpmv) {
             st16(y + o, s);
@@ -158,7 +226,7 @@ __global__ __launch_bounds__(kBlk) void block_row_kernel(CsrT<T> a, const T* __r
         } else if constexpr (OP == kBResid) {
             st16(y + o, ld16<VT>(u + o) - s);
         } else {
-            const VT xn = ld16<VT>(g + o) + omega * dinv[i] * (ld16<VT>(u + o) - s);
+            const VT xn = gi + omega * dinv[i] * (ld16<VT>(u + o) - s);
             if constexpr (OP == kBJacobi) st16(y + o, xn);
             else add_to_fp64(acc + o, xn);
         }
@@ -205,13 +273,14 @@ __global__ __launch_bounds__(kBlk) void block_outer_kernel(CsrView a, const doub
     const int lb = logical_block();
     const int sub = threadIdx.x / LPR;
     const int c0 = (threadIdx.x % LPR) * 2;
-    const int nt = (live && c0 >= (int)*live) ? 0 : ntiles;
+    const bool dead = live && c0 >= (int)*live;   // see block_row_kernel
     double n0 = 0.0, n1 = 0.0;
-    for (TileWalk w = tile_walk(nt); w.t < w.end; w.t += w.stride) {
+    for (TileWalk w = tile_walk(ntiles); w.t < w.end; w.t += w.stride) {
         const int t = w.t;
         const int i = t * RPT + sub;
         if (i >= a.rows) break;
-        const v2d s = row_gather_sum<double, K>(a, x, a.rp[i], a.rp[i + 1], c0);
+        const v2d s = row_gather_sum<double, K>(a, x, a.rp[i], a.rp[i + 1], dead ? 0 : c0);
+        if (dead) continue;
         const int o = i * K + c0;
         const v2d r = ld16<v2d>(b + o) - s;
         n0 += r.x * r.x;
@@ -228,20 +297,43 @@ __global__ __launch_bounds__(kBlk) void block_outer_kernel(CsrView a, const doub
     store_column_partials<K, 2>(nn, partials, lb);
 }
 
-// out[c] = sum over workgroups of partials[b * K + c], in a fixed order
+// out[c] = sum over workgroups of partials[b * K + c], in a fixed order: one
+// workgroup of kFinishThreads; thread t takes column t % K and the partials
+// b = t / K + S m (S = kFinishThreads / K), into four accumulators (m mod 4)
+// so that four loads are in flight; the four are added, then the S threads
+// of a column in order (the ones in a wave with shuffles, then the waves).
+constexpr int kFinishThreads = 1024;
+
 template <int K>
-__global__ __launch_bounds__(kBlk) void block_norm_finish_kernel(int nparts, const double* __restrict__ partials,
-                                                                 double* __restrict__ out) {
-    constexpr int S = kBlk / K;
-    __shared__ double slice[kBlk];
-    const int c = threadIdx.x % K, sl = threadIdx.x / K;
-    double s = 0.0;
-    for (int b = sl; b < nparts; b += S) s += partials[b * K + c];
-    slice[threadIdx.x] = s;
+__global__ __launch_bounds__(kFinishThreads) void block_norm_finish_kernel(int nparts,
+                                                                           const double* __restrict__ partials,
+                                                                           double* __restrict__ out) {
+    constexpr int S = kFinishThreads / K;
+    constexpr int W = kFinishThreads / 64;
+    __shared__ double wsum[W][K];
+    const int c = threadIdx.x % K;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int b = threadIdx.x / K;
+    for (; b + 3 * S < nparts; b += 4 * S) {
+        a0 += partials[b * K + c];
+        a1 += partials[(b + S) * K + c];
+        a2 += partials[(b + 2 * S) * K + c];
+        a3 += partials[(b + 3 * S) * K + c];
+    }
+    if (b < nparts) a0 += partials[b * K + c];
+    if (b + S < nparts) a1 += partials[(b + S) * K + c];
+    if (b + 2 * S < nparts) a2 += partials[(b + 2 * S) * K + c];
+    double v = (a0 + a1) + (a2 + a3);
+    // lanes of one wave holding the same column are K apart
+#pragma unroll
+    for (int off = K; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+    const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+    if (lane < K) wsum[w][lane] = v;
     __syncthreads();
     if ((int)threadIdx.x < K) {
-        double t = 0.0;
-        for (int k = 0; k < S; ++k) t += slice[k * K + threadIdx.x];
+        double t = wsum[0][threadIdx.x];
+#pragma unroll
+        for (int k = 1; k < W; ++k) t += wsum[k][threadIdx.x];
         out[threadIdx.x] = t;
     }
 }
@@ -257,16 +349,17 @@ __global__ __launch_bounds__(kBlk) void block_spmv_dot_kernel(CsrView a, const d
     const int lb = logical_block();
     const int sub = threadIdx.x / LPR;
     const int c0 = (threadIdx.x % LPR) * 2;
-    const int nt = (live && c0 >= (int)*live) ? 0 : ntiles;
+    const bool dead = live && c0 >= (int)*live;   // see block_row_kernel
     double d[2] = {0.0, 0.0};
-    for (TileWalk w = tile_walk(nt); w.t < w.end; w.t += w.stride) {
+    for (TileWalk w = tile_walk(ntiles); w.t < w.end; w.t += w.stride) {
         const int t = w.t;
         const int i = t * RPT + sub;
         if (i >= a.rows) break;
-        const v2d s = row_gather_sum<double, K>(a, p, a.rp[i], a.rp[i + 1], c0);
+        v2d pi;
+        const v2d s = row_gather_sum<double, K, true>(a, p, a.rp[i], a.rp[i + 1], dead ? 0 : c0, i, &pi);
+        if (dead) continue;
         const int o = i * K + c0;
         st16(q + o, s);
-        const v2d pi = ld16<v2d>(p + o);
         d[0] += pi.x * s.x;
         d[1] += pi.y * s.y;
     }
@@ -449,17 +542,19 @@ __global__ __launch_bounds__(kBlk) void block_sweep_dot_kernel(CsrT<T> a, const 
     const int lb = logical_block();
     const int sub = threadIdx.x / LPR;
     const int c0 = (threadIdx.x % LPR) * V;
-    const int nt = (live && c0 >= (int)*live) ? 0 : ntiles;
+    const bool dead = live && c0 >= (int)*live;   // see block_row_kernel
     double d[V];
 #pragma unroll
     for (int e = 0; e < V; ++e) d[e] = 0.0;
-    for (TileWalk w = tile_walk(nt); w.t < w.end; w.t += w.stride) {
+    for (TileWalk w = tile_walk(ntiles); w.t < w.end; w.t += w.stride) {
         const int t = w.t;
         const int i = t * RPT + sub;
         if (i >= a.rows) break;
-        const VT s = row_gather_sum<T, K>(a, g, a.rp[i], a.rp[i + 1], c0);
+        VT gi;
+        const VT s = row_gather_sum<T, K, true>(a, g, a.rp[i], a.rp[i + 1], dead ? 0 : c0, i, &gi);
+        if (dead) continue;
         const int o = i * K + c0;
-        const VT xn = ld16<VT>(g + o) + omega * dinv[i] * (ld16<VT>(u + o) - s);
+        const VT xn = gi + omega * dinv[i] * (ld16<VT>(u + o) - s);
         st16(zt + o, xn);
 #pragma unroll
         for (int e = 0; e < V; e += 2) {
@@ -627,7 +722,8 @@ int fp64_tiles(int rows) {
 
 template <int K>
 void finish(int grid, const ColumnDots& dot, hipStream_t st) {
-    hipLaunchKernelGGL((block_norm_finish_kernel<K>), dim3(1), dim3(kBlk), 0, st, grid, dot.partials, dot.result);
+    hipLaunchKernelGGL((block_norm_finish_kernel<K>), dim3(1), dim3(kFinishThreads), 0, st, grid, dot.partials,
+                       dot.result);
 }
 
 // calls f.template operator()<K>() with the compile-time width
