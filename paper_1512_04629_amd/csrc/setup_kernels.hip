@@ -687,24 +687,48 @@ __global__ __launch_bounds__(kSB) void radix_count_kernel(int64_t m, int shift, 
     cnt[(int64_t)threadIdx.x * nb + blockIdx.x] = hist[threadIdx.x];
 }
 
-// stable scatter: pair (r, t) of the block goes to
-//   first[d] (the scanned count of digit d before this block)
-//   + the pairs of digit d in earlier rounds of this block
-//   + those of earlier waves in this round + those of lower lanes in this wave
+// block-wide exclusive scan of one int per thread (kSB threads)
+__device__ __forceinline__ int block_exclusive_scan_i32(int v, int* wsum) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int incl = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += t;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    int before = 0;
+#pragma unroll
+    for (int k = 0; k < kSB / 64; ++k)
+        if (k < w) before += wsum[k];
+    __syncthreads();
+    return before + incl - v;
+}
+
+// stable scatter.  Pair (r, t) of the block (held by thread t in round r)
+// takes slot tstart[d] + (pairs of digit d in earlier rounds) + (in earlier
+// waves of this round) + (in lower lanes of its wave) of the block's tile,
+// tstart the block's exclusive scan of its digit counts, so that the slots
+// hold the tile's pairs sorted stably by digit.  The pairs are staged in LDS
+// in slot order, keys and then values, and written out slot by slot: slot q
+// of digit d goes to first[d] + q - tstart[d], so consecutive threads write
+// consecutive positions of one digit's run.
 __global__ __launch_bounds__(kSB) void radix_scatter_kernel(int64_t m, int shift,
                                                             const uint64_t* __restrict__ kin,
                                                             const double* __restrict__ vin,
                                                             uint64_t* __restrict__ kout,
                                                             double* __restrict__ vout,
+                                                            const int64_t* __restrict__ cnt,
                                                             const int64_t* __restrict__ first, int64_t nb) {
     constexpr int kWaves = kSB / 64;
-    __shared__ int64_t next[kRadixBins];          // next free position per digit
+    __shared__ int next[kRadixBins];              // next free slot per digit
     __shared__ int wcnt[kWaves][kRadixBins];      // this round's count per wave and digit
-    __shared__ int64_t wpos[kWaves][kRadixBins];  // this round's first position per wave and digit
+    __shared__ int wpos[kWaves][kRadixBins];      // this round's first slot per wave and digit
+    __shared__ int64_t gbase[kRadixBins];         // output position of slot 0 of each digit
+    __shared__ int wsum[kWaves];
+    __shared__ uint64_t stage[kRadixTile];
     const int t = threadIdx.x, w = t >> 6;
-    next[t] = first[(int64_t)t * nb + blockIdx.x];
-#pragma unroll
-    for (int q = 0; q < kWaves; ++q) wcnt[q][t] = 0;
     const int64_t base = (int64_t)blockIdx.x * kRadixTile;
     uint64_t k[kRadixRounds];
     double v[kRadixRounds];
@@ -714,7 +738,14 @@ __global__ __launch_bounds__(kSB) void radix_scatter_kernel(int64_t m, int shift
         k[r] = e < m ? kin[e] : 0;
         v[r] = e < m ? vin[e] : 0.0;
     }
+    const int64_t ci = (int64_t)t * nb + blockIdx.x;
+    const int tstart = block_exclusive_scan_i32((int)cnt[ci], wsum);
+    next[t] = tstart;
+    gbase[t] = first[ci] - tstart;
+#pragma unroll
+    for (int q = 0; q < kWaves; ++q) wcnt[q][t] = 0;
     __syncthreads();
+    int slot[kRadixRounds];
 #pragma unroll
     for (int r = 0; r < kRadixRounds; ++r) {
         const bool valid = base + (int64_t)r * kSB + t < m;
@@ -724,8 +755,8 @@ __global__ __launch_bounds__(kSB) void radix_scatter_kernel(int64_t m, int shift
         if (valid && rank == 0) wcnt[w][d] = __popcll(peers);
         __syncthreads();
         {
-            // thread t owns digit t: positions of its waves, then clear
-            int64_t p = next[t];
+            // thread t owns digit t: first slots of its waves, then clear
+            int p = next[t];
 #pragma unroll
             for (int q = 0; q < kWaves; ++q) {
                 wpos[q][t] = p;
@@ -735,11 +766,33 @@ __global__ __launch_bounds__(kSB) void radix_scatter_kernel(int64_t m, int shift
             next[t] = p;
         }
         __syncthreads();
-        if (valid) {
-            const int64_t pos = wpos[w][d] + rank;
-            kout[pos] = k[r];
-            vout[pos] = v[r];
+        slot[r] = valid ? wpos[w][d] + rank : -1;
+    }
+#pragma unroll
+    for (int r = 0; r < kRadixRounds; ++r)
+        if (slot[r] >= 0) stage[slot[r]] = k[r];
+    __syncthreads();
+    const int here = (int)min<int64_t>(kRadixTile, m - base);
+    int dq[kRadixRounds];
+#pragma unroll
+    for (int q = 0; q < kRadixRounds; ++q) {
+        const int idx = q * kSB + t;
+        dq[q] = 0;
+        if (idx < here) {
+            const uint64_t key = stage[idx];
+            dq[q] = (int)((key >> shift) & (kRadixBins - 1));
+            kout[gbase[dq[q]] + idx] = key;
         }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRadixRounds; ++r)
+        if (slot[r] >= 0) stage[slot[r]] = __double_as_longlong(v[r]);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kRadixRounds; ++q) {
+        const int idx = q * kSB + t;
+        if (idx < here) vout[gbase[dq[q]] + idx] = __longlong_as_double((long long)stage[idx]);
     }
 }
 
@@ -770,7 +823,7 @@ hipError_t sort_pairs(void* temp, size_t& temp_bytes, uint64_t* keys[2], double*
         hipLaunchKernelGGL(radix_count_kernel, dim3((unsigned)nb), dim3(kSB), 0, st, m, shift, keys[src], cnt, nb);
         launch_scan64(ncnt, cnt, first, bsum, st);
         hipLaunchKernelGGL(radix_scatter_kernel, dim3((unsigned)nb), dim3(kSB), 0, st, m, shift, keys[src],
-                           vals[src], keys[dst], vals[dst], first, nb);
+                           vals[src], keys[dst], vals[dst], cnt, first, nb);
     }
     return hipGetLastError();
 }
