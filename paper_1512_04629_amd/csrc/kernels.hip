@@ -1295,12 +1295,31 @@ __global__ __launch_bounds__(kBlock) void dense_invert_kernel(CsrView a, double*
         for (int p = a.rp[i]; p < a.rp[i + 1]; ++p) M[i][a.ci[p]] = a.v[p];
     __syncthreads();
     for (int c = 0; c < n; ++c) {
-        if (threadIdx.x == 0) {
-            int best = c;
-            for (int i = c + 1; i < n; ++i)
-                if (fabs(M[i][c]) > fabs(M[best][c])) best = i;
-            piv = best;
-            if (M[best][c] == 0.0) *singular = 1;
+        if (threadIdx.x < 64) {
+            // pivot: the first row i >= c of largest |M[i][c]| (a NaN never
+            // wins, except at row c, where the scan starts), found by one wave:
+            // lane l holds row c + l (n <= 64), and a shuffle tree keeps the
+            // larger magnitude, the smaller row on ties
+            const int i = c + (int)threadIdx.x;
+            double key = -1.0;
+            if (i < n) {
+                const double m = fabs(M[i][c]);
+                key = m != m ? (i == c ? HUGE_VAL : -1.0) : m;
+            }
+            int best = i;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const double ok = __shfl_xor(key, off, 64);
+                const int ob = __shfl_xor(best, off, 64);
+                if (ok > key || (ok == key && ob < best)) {
+                    key = ok;
+                    best = ob;
+                }
+            }
+            if (threadIdx.x == 0) {
+                piv = best;
+                if (M[best][c] == 0.0) *singular = 1;
+            }
         }
         __syncthreads();
         const int pr = piv;
