@@ -113,6 +113,8 @@ struct DevLevel {
     double* dinv = nullptr;       // 1 / diag(Ah)
     uint8_t* in_m = nullptr;      // minimal pattern flags (l >= 1)
     uint8_t* keep = nullptr;      // keep flags of the last sparsification
+    int32_t* kcnt = nullptr;      // kept entries per row, and per block of the keep_count launch
+    int32_t* kbsum = nullptr;     //   (regions of the handle's sp_cnt / sp_bsum)
     double* rowmax = nullptr;     // m_i of A
     double* lump_thr = nullptr;   // strong-neighbour lumping: strength thresholds of A's rows
     double* lump_den = nullptr;   //   and share denominators per dropped entry of A
@@ -177,6 +179,8 @@ struct amg_ctx {
     uint32_t pub_seq = 0;
     int32_t* scan_scratch = nullptr;
     int32_t* cnt = nullptr;
+    int32_t* sp_cnt = nullptr;    // every level's kcnt
+    int32_t* sp_bsum = nullptr;   // every level's kbsum
     int* missing = nullptr;          // minimal-pattern and index-width checks
     int* singular = nullptr;         // zero pivot met by the device inversion of the coarsest operator
     double *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_q = nullptr;
@@ -586,27 +590,41 @@ void sparsify_levels(amg_ctx* h, const std::vector<std::pair<int, double>>& todo
         }
     }
     bool coarse_changed = false;
-    for (auto& t : todo) {
-        const int l = t.first;
-        const double gamma = t.second;
-        DevLevel& c = h->lv[l];
-        ProfScope ps(h, AMG_K_SPARSIFY, l);
-        if (gamma == 0.0) {
-            if (!c.ah_alias) {
-                c.Ah = c.A;
-                c.ah_alias = true;
-                launch_inverse_diagonal(c.A.view(), c.dinv, h->fp32 ? c.dinv32 : nullptr, h->stream);
-                if (l == (int)h->lv.size() - 1) coarse_changed = true;
+    // Diagonal lumping in three steps over the levels: keep flags with row and
+    // block counts (one launch per level), the scans of every level's block
+    // counts (one launch), compaction (one launch per level, row pointers
+    // from the block offsets).  A Hybrid Galerkin pattern needs the finer
+    // operator this call has just rebuilt, so there the levels go one at a
+    // time; strong-neighbour lumping keeps its own steps.
+    const bool one_by_one = h->method == AMG_HYBRID_GALERKIN;
+    size_t next = 0;
+    while (next < todo.size()) {
+        const size_t first = next;
+        size_t last = one_by_one ? next + 1 : todo.size();
+        ScanJobs jobs;
+        for (size_t q = first; q < last; ++q) {
+            const int l = todo[q].first;
+            const double gamma = todo[q].second;
+            DevLevel& c = h->lv[l];
+            ProfScope ps(h, AMG_K_SPARSIFY, l);
+            if (gamma == 0.0) {
+                if (!c.ah_alias) {
+                    c.Ah = c.A;
+                    c.ah_alias = true;
+                    launch_inverse_diagonal(c.A.view(), c.dinv, h->fp32 ? c.dinv32 : nullptr, h->stream);
+                    if (l == (int)h->lv.size() - 1) coarse_changed = true;
+                }
+                c.gamma = 0.0;
+                c.keep_valid = false;
+                continue;
             }
-            c.gamma = 0.0;
-            c.keep_valid = false;
-        } else {
             // levels are processed finest first, so a Hybrid pattern sees the
             // finer operator this call has just rebuilt
             mark_minimal_pattern(h, l, h->method == AMG_HYBRID_GALERKIN);
-            launch_keep_count(c.A.width, c.A.view(), c.in_m, c.rowmax, gamma, c.keep, h->cnt, h->stream);
-            launch_exclusive_scan(c.n, h->cnt, c.Ahs.rp, h->scan_scratch, h->stream);
             if (h->lumping == AMG_LUMP_STRONG) {
+                launch_keep_count(c.A.width, c.A.view(), c.in_m, c.rowmax, gamma, c.keep, c.kcnt, nullptr,
+                                  h->stream);
+                launch_exclusive_scan(c.n, c.kcnt, c.Ahs.rp, h->scan_scratch, h->stream);
                 // Algorithm 3's second loop: dropped entries shared among strong neighbours
                 const DevMat& a = c.A;
                 launch_compact_copy(c.n, a.rp, a.ci, a.v, c.keep, c.Ahs.rp, c.Ahs.ci, c.Ahs.v, h->stream);
@@ -624,17 +642,35 @@ void sparsify_levels(amg_ctx* h, const std::vector<std::pair<int, double>>& todo
                 launch_inverse_diagonal(c.Ahs.view(), c.dinv, h->fp32 ? c.dinv32 : nullptr, h->stream);
                 if (h->fp32) launch_narrow(c.A.nnz, c.Ahs32, c.Ahs.v, h->stream);   // capacity; past nnz unused
             } else {
-                launch_compact_lump(c.A.width, c.A.view(), c.keep, c.Ahs.rp, c.Ahs.ci, c.Ahs.v, c.dinv,
-                                    h->fp32 ? c.Ahs32 : nullptr, h->fp32 ? c.dinv32 : nullptr, h->stream);
+                launch_keep_count(c.A.width, c.A.view(), c.in_m, c.rowmax, gamma, c.keep, c.kcnt, c.kbsum,
+                                  h->stream);
+                jobs.data[jobs.count] = c.kbsum;
+                jobs.n[jobs.count] = keep_count_blocks(c.A.width, c.n);
+                ++jobs.count;
+                if (jobs.count == kMaxScanJobs) last = q + 1;   // the rest in the next round
             }
+            check_launch();
+        }
+        launch_scan_jobs(jobs, h->stream);
+        for (size_t q = first; q < last; ++q) {
+            const int l = todo[q].first;
+            const double gamma = todo[q].second;
+            if (gamma == 0.0) continue;
+            DevLevel& c = h->lv[l];
+            ProfScope ps(h, AMG_K_SPARSIFY, l);
+            if (h->lumping != AMG_LUMP_STRONG)
+                launch_compact_lump(c.A.width, c.A.view(), c.keep, c.kcnt, c.kbsum, c.Ahs.rp, c.Ahs.ci, c.Ahs.v,
+                                    c.dinv, h->fp32 ? c.Ahs32 : nullptr, h->fp32 ? c.dinv32 : nullptr,
+                                    h->stream);
             c.Ahs.nnz_known = false;
             c.Ah = c.Ahs;
             c.ah_alias = false;
             c.gamma = gamma;
             c.keep_valid = true;
             if (l == (int)h->lv.size() - 1) coarse_changed = true;
+            check_launch();
         }
-        check_launch();
+        next = last;
     }
     if (coarse_changed) refresh_coarse_inverse(h);
 }
@@ -1969,6 +2005,22 @@ void finish_setup(amg_ctx* h) {
     for (auto& d : h->lv) nmax = std::max(nmax, d.n);
     h->cnt = dalloc_n<int32_t>(h, nmax + 1);
     h->scan_scratch = dalloc_n<int32_t>(h, scan_scratch_ints(nmax));
+    {
+        int64_t ncnt = 0, nbsum = 0;
+        for (auto& d : h->lv) {
+            ncnt += d.n + 1;
+            nbsum += keep_count_blocks(d.A.width, d.n) + 1;
+        }
+        h->sp_cnt = dalloc_n<int32_t>(h, ncnt);
+        h->sp_bsum = dalloc_n<int32_t>(h, nbsum);
+        ncnt = nbsum = 0;
+        for (auto& d : h->lv) {
+            d.kcnt = h->sp_cnt + ncnt;
+            d.kbsum = h->sp_bsum + nbsum;
+            ncnt += d.n + 1;
+            nbsum += keep_count_blocks(d.A.width, d.n) + 1;
+        }
+    }
     for (int l = 0; l <= L; ++l) {
         DevLevel& d = h->lv[l];
         compress_indices(h, d.A);
@@ -2458,7 +2510,7 @@ void destroy(amg_ctx* h) {
     dfree(h, h->blk_x);
     for (void* q : {(void*)h->bcg_r, (void*)h->bcg_p, (void*)h->bcg_q, (void*)h->bcg_z}) dfree(h, q);
     for (void* p : {(void*)h->coarse_inv, (void*)h->scal, (void*)h->partials,
-                    (void*)h->scan_scratch, (void*)h->cnt, (void*)h->missing, (void*)h->singular, (void*)h->cg_r,
+                    (void*)h->scan_scratch, (void*)h->cnt, (void*)h->sp_cnt, (void*)h->sp_bsum, (void*)h->missing, (void*)h->singular, (void*)h->cg_r,
                     (void*)h->cg_z, (void*)h->cg_p, (void*)h->cg_q, (void*)h->xw, (void*)h->rt})
         dfree(h, p);
     if (h->pinned) (void)hipHostFree(h->pinned);

@@ -1201,7 +1201,8 @@ template <int W>
 __global__ __launch_bounds__(kBlock) void keep_count_kernel(CsrView a, const uint8_t* __restrict__ in_m,
                                                             const double* __restrict__ m, double gamma,
                                                             uint8_t* __restrict__ keep,
-                                                            int32_t* __restrict__ cnt) {
+                                                            int32_t* __restrict__ cnt,
+                                                            int32_t* __restrict__ bsum) {
     const int row = blockIdx.x * (kBlock / W) + threadIdx.x / W;
     const int lane = threadIdx.x & (W - 1);
     int c = 0;
@@ -1219,18 +1220,55 @@ __global__ __launch_bounds__(kBlock) void keep_count_kernel(CsrView a, const uin
     }
     c = sub_sum_int<W>(c);
     if (row < a.rows && lane == 0) cnt[row] = c;
+    if (bsum) {
+        // the block's kept entries (its kBlock / W <= 64 rows added by one wave)
+        __shared__ int rows_c[kBlock / W];
+        if (lane == 0) rows_c[threadIdx.x / W] = row < a.rows ? c : 0;
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            int v = (int)threadIdx.x < kBlock / W ? rows_c[threadIdx.x] : 0;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            if (threadIdx.x == 0) bsum[blockIdx.x] = v;
+        }
+    }
 }
 
+// The first position of each row in the compacted operator: the block's
+// offset (the exclusive scan of the blocks' kept counts, boff) plus the
+// kept counts of the block's earlier rows (a shuffle scan over its <= 64
+// rows); the row pointers of the compacted operator are written here too.
 template <int W>
 __global__ __launch_bounds__(kBlock) void compact_lump_kernel(CsrView a, const uint8_t* __restrict__ keep,
-                                                              const int32_t* __restrict__ new_rp,
+                                                              const int32_t* __restrict__ cnt,
+                                                              const int32_t* __restrict__ boff,
+                                                              int32_t* __restrict__ new_rp,
                                                               int32_t* __restrict__ new_ci,
                                                               double* __restrict__ new_v,
                                                               double* __restrict__ dinv,
                                                               float* __restrict__ new_v32,
                                                               float* __restrict__ dinv32) {
-    const int row = blockIdx.x * (kBlock / W) + threadIdx.x / W;
+    constexpr int R = kBlock / W;   // rows per block
+    __shared__ int row_out[R];
+    const int row = blockIdx.x * R + threadIdx.x / W;
     const int lane = threadIdx.x & (W - 1);
+    if (threadIdx.x < 64) {
+        const int r = blockIdx.x * R + (int)threadIdx.x;
+        const int c = ((int)threadIdx.x < R && r < a.rows) ? cnt[r] : 0;
+        int incl = c;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int t = __shfl_up(incl, off, 64);
+            if ((int)threadIdx.x >= off) incl += t;
+        }
+        if ((int)threadIdx.x < R) {
+            const int o = boff[blockIdx.x] + incl - c;
+            row_out[threadIdx.x] = o;
+            if (r < a.rows) new_rp[r] = o;
+            if (r == a.rows - 1) new_rp[a.rows] = o + c;
+        }
+    }
+    __syncthreads();
     const int shift = (threadIdx.x & 63) & ~(W - 1);
     const unsigned long long lanes_below = (lane == 0) ? 0ull : ((1ull << lane) - 1ull);
     double dropped = 0.0, diag = 0.0;
@@ -1238,7 +1276,7 @@ __global__ __launch_bounds__(kBlock) void compact_lump_kernel(CsrView a, const u
     int written = 0;
     const int beg = row < a.rows ? a.rp[row] : 0;
     const int end = row < a.rows ? a.rp[row + 1] : 0;
-    const int out0 = row < a.rows ? new_rp[row] : 0;
+    const int out0 = row < a.rows ? row_out[threadIdx.x / W] : 0;
     for (int base = beg; base < end; base += W) {
         const int p = base + lane;
         bool k = false;
@@ -1668,6 +1706,32 @@ __global__ __launch_bounds__(1024) void scan_pass2_kernel(int nb, int32_t* bsum)
     }
 }
 
+// in-place exclusive scans of several arrays, one workgroup of 1,024 threads
+// each (every thread a contiguous range)
+__global__ __launch_bounds__(1024) void scan_jobs_kernel(ScanJobs jobs) {
+    __shared__ int lds[1024];
+    int32_t* data = jobs.data[blockIdx.x];
+    const int nb = jobs.n[blockIdx.x];
+    const int per = (nb + 1023) / 1024;
+    const int lo = min(nb, (int)threadIdx.x * per), hi = min(nb, lo + per);
+    int s = 0;
+    for (int i = lo; i < hi; ++i) s += data[i];
+    lds[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const int t = threadIdx.x >= o ? lds[threadIdx.x - o] : 0;
+        __syncthreads();
+        lds[threadIdx.x] += t;
+        __syncthreads();
+    }
+    int run = lds[threadIdx.x] - s;
+    for (int i = lo; i < hi; ++i) {
+        const int v = data[i];
+        data[i] = run;
+        run += v;
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void scan_pass3_kernel(int n, const int32_t* __restrict__ cnt,
                                                             const int32_t* __restrict__ boff,
                                                             int32_t* __restrict__ out) {
@@ -1926,16 +1990,28 @@ void launch_row_max(int width, const CsrView& a, double* m, hipStream_t st) {
 }
 
 void launch_keep_count(int width, const CsrView& a, const uint8_t* in_m, const double* m,
-                       double gamma, uint8_t* keep, int32_t* cnt, hipStream_t st) {
+                       double gamma, uint8_t* keep, int32_t* cnt, int32_t* bsum, hipStream_t st) {
     if (a.rows <= 0) return;
-    AMG_WIDTH_SWITCH(width, keep_count_kernel, a, in_m, m, gamma, keep, cnt);
+    AMG_WIDTH_SWITCH(width, keep_count_kernel, a, in_m, m, gamma, keep, cnt, bsum);
 }
 
-void launch_compact_lump(int width, const CsrView& a, const uint8_t* keep, const int32_t* new_rp,
-                         int32_t* new_ci, double* new_v, double* dinv, float* new_v32, float* dinv32,
-                         hipStream_t st) {
+int keep_count_blocks(int width, int rows) {
+    const int w = width == 4 || width == 8 || width == 16 || width == 32 ? width : 64;
+    const int r = kBlock / w;
+    return (rows + r - 1) / r;
+}
+
+void launch_scan_jobs(const ScanJobs& jobs, hipStream_t st) {
+    if (jobs.count <= 0) return;
+    hipLaunchKernelGGL(scan_jobs_kernel, dim3(jobs.count), dim3(1024), 0, st, jobs);
+}
+
+void launch_compact_lump(int width, const CsrView& a, const uint8_t* keep, const int32_t* cnt,
+                         const int32_t* boff, int32_t* new_rp, int32_t* new_ci, double* new_v, double* dinv,
+                         float* new_v32, float* dinv32, hipStream_t st) {
     if (a.rows <= 0) return;
-    AMG_WIDTH_SWITCH(width, compact_lump_kernel, a, keep, new_rp, new_ci, new_v, dinv, new_v32, dinv32);
+    AMG_WIDTH_SWITCH(width, compact_lump_kernel, a, keep, cnt, boff, new_rp, new_ci, new_v, dinv, new_v32,
+                     dinv32);
 }
 
 int dense_invert_max() { return kDenseInvMax; }

@@ -223,17 +223,30 @@ bool sell_candidate(const CsrView& a);
 
 // m_i = max_{k != i} |a_ik|
 void launch_row_max(int width, const CsrView& a, double* m, hipStream_t st);
-// keep flags and per-row kept counts for tolerance gamma
+// keep flags and per-row kept counts for tolerance gamma; bsum (may be
+// null) receives the kept count of each of the launch's keep_count_blocks
+// blocks of rows
 void launch_keep_count(int width, const CsrView& a, const uint8_t* in_m, const double* m,
-                       double gamma, uint8_t* keep, int32_t* cnt, hipStream_t st);
+                       double gamma, uint8_t* keep, int32_t* cnt, int32_t* bsum, hipStream_t st);
+int keep_count_blocks(int width, int rows);
+// in-place exclusive scans of up to kMaxScanJobs int32 arrays, one launch
+constexpr int kMaxScanJobs = 16;
+struct ScanJobs {
+    int32_t* data[kMaxScanJobs];
+    int n[kMaxScanJobs];
+    int count = 0;
+};
+void launch_scan_jobs(const ScanJobs& jobs, hipStream_t st);
 // exclusive scan of cnt[0..n) into out[0..n], out[n] = total; scratch >= scan_scratch_ints(n)
 int64_t scan_scratch_ints(int n);
 void launch_exclusive_scan(int n, const int32_t* cnt, int32_t* out, int32_t* scratch,
                            hipStream_t st);
 // compaction of the kept entries with the dropped ones added to the diagonal
-// (new_v32/dinv32 not null: also the FP32 copies)
-void launch_compact_lump(int width, const CsrView& a, const uint8_t* keep,
-                         const int32_t* new_rp, int32_t* new_ci, double* new_v, double* dinv,
+// (new_v32/dinv32 not null: also the FP32 copies); cnt: the rows' kept
+// counts, boff: the exclusive scan of the keep_count launch's block sums
+// (same width); writes the row pointers new_rp[0..rows]
+void launch_compact_lump(int width, const CsrView& a, const uint8_t* keep, const int32_t* cnt,
+                         const int32_t* boff, int32_t* new_rp, int32_t* new_ci, double* new_v, double* dinv,
                          float* new_v32, float* dinv32, hipStream_t st);
 
 }  // namespace amg355
