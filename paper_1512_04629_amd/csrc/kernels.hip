@@ -1314,22 +1314,30 @@ __global__ __launch_bounds__(kBlock) void compact_lump_kernel(CsrView a, const u
 
 // Inverse of the dense coarsest operator (n <= kDenseInvMax) by Gauss-Jordan
 // elimination with partial pivoting in LDS, one block.  *singular = 1 if a
-// pivot is zero.
+// pivot is zero.  Per column c, three steps between barriers: the pivot row
+// (one wave, a shuffle tree), then the scaled pivot row P = M[pr] / d (and
+// V's), the multipliers F[i] = M[i][c] and the row swap, then every element
+// M[i][j] -= F[i] P[j] (V likewise), row c = P and column c zeroed.  The
+// operations on every element are those of the textbook order (swap, scale
+// row c, eliminate with the scaled row, zero column c).
 constexpr int kDenseInvMax = 64;
+constexpr int kDenseInvThreads = 1024;
 
-__global__ __launch_bounds__(kBlock) void dense_invert_kernel(CsrView a, double* __restrict__ inv,
-                                                              int* singular) {
+__global__ __launch_bounds__(kDenseInvThreads) void dense_invert_kernel(CsrView a, double* __restrict__ inv,
+                                                                        int* singular) {
     __shared__ double M[kDenseInvMax][kDenseInvMax + 1];
     __shared__ double V[kDenseInvMax][kDenseInvMax + 1];
+    __shared__ double P[kDenseInvMax], PV[kDenseInvMax], F[kDenseInvMax];
     __shared__ int piv;
+    __shared__ double pivd;
     const int n = a.rows;
-    for (int t = threadIdx.x; t < n * n; t += kBlock) {
+    for (int t = threadIdx.x; t < n * n; t += kDenseInvThreads) {
         const int i = t / n, j = t % n;
         M[i][j] = 0.0;
         V[i][j] = (i == j) ? 1.0 : 0.0;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < n; i += kBlock)
+    for (int i = threadIdx.x; i < n; i += kDenseInvThreads)
         for (int p = a.rp[i]; p < a.rp[i + 1]; ++p) M[i][a.ci[p]] = a.v[p];
     __syncthreads();
     for (int c = 0; c < n; ++c) {
@@ -1356,39 +1364,44 @@ __global__ __launch_bounds__(kBlock) void dense_invert_kernel(CsrView a, double*
             }
             if (threadIdx.x == 0) {
                 piv = best;
+                pivd = M[best][c];
                 if (M[best][c] == 0.0) *singular = 1;
             }
         }
         __syncthreads();
         const int pr = piv;
-        if (pr != c)
-            for (int j = threadIdx.x; j < n; j += kBlock) {
-                const double t1 = M[c][j]; M[c][j] = M[pr][j]; M[pr][j] = t1;
-                const double t2 = V[c][j]; V[c][j] = V[pr][j]; V[pr][j] = t2;
+        const double d = pivd;
+        const int t = threadIdx.x;
+        if (t < n) {
+            // column t of the pivot row, scaled; the old row c moves to row pr
+            const double mp = M[pr][t], vp = V[pr][t];
+            P[t] = mp / d;
+            PV[t] = vp / d;
+            if (pr != c) {
+                M[pr][t] = M[c][t];
+                V[pr][t] = V[c][t];
             }
-        __syncthreads();
-        const double d = M[c][c];
-        __syncthreads();
-        for (int j = threadIdx.x; j < n; j += kBlock) {
-            M[c][j] = M[c][j] / d;
-            V[c][j] = V[c][j] / d;
+        } else if (t >= 64 && t - 64 < n) {
+            // multiplier of row i after the swap
+            const int i = t - 64;
+            F[i] = (i == pr) ? M[c][c] : M[i][c];
         }
         __syncthreads();
-        for (int t = threadIdx.x; t < n * n; t += kBlock) {
-            const int i = t / n, j = t % n;
-            if (i == c) continue;
-            const double f = M[i][c];
-            if (j != c) {
-                M[i][j] -= f * M[c][j];
+        for (int e = threadIdx.x; e < n * n; e += kDenseInvThreads) {
+            const int i = e / n, j = e % n;
+            if (i == c) {
+                M[c][j] = P[j];
+                V[c][j] = PV[j];
+            } else {
+                const double f = F[i];
+                if (j == c) M[i][c] = 0.0;
+                else M[i][j] -= f * P[j];
+                V[i][j] -= f * PV[j];
             }
-            V[i][j] -= f * V[c][j];
         }
-        __syncthreads();
-        for (int i = threadIdx.x; i < n; i += kBlock)
-            if (i != c) M[i][c] = 0.0;
         __syncthreads();
     }
-    for (int t = threadIdx.x; t < n * n; t += kBlock) inv[t] = V[t / n][t % n];
+    for (int t = threadIdx.x; t < n * n; t += kDenseInvThreads) inv[t] = V[t / n][t % n];
 }
 
 // Single-workgroup tail of the V-cycle (see kernels.hpp).  Rows are handled
@@ -2054,7 +2067,7 @@ void launch_coarse_tail(const TailArgs<double>& t, hipStream_t st) { launch_coar
 void launch_coarse_tail(const TailArgs<float>& t, hipStream_t st) { launch_coarse_tail_t<float>(t, st); }
 
 void launch_dense_invert(const CsrView& a, double* inv, int* singular, hipStream_t st) {
-    hipLaunchKernelGGL(dense_invert_kernel, dim3(1), dim3(kBlock), 0, st, a, inv, singular);
+    hipLaunchKernelGGL(dense_invert_kernel, dim3(1), dim3(kDenseInvThreads), 0, st, a, inv, singular);
 }
 
 // one wavefront per row block: its smallest and largest column by shuffles,
