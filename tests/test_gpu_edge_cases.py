@@ -8,7 +8,9 @@
 * rows without couplings inside a coupled problem (isolated points, which the
   split makes F points with empty interpolation rows): hierarchy, keep flags
   and sparsified operators bit-exact under diagonal and strong-neighbour
-  lumping, and the solve at the parity bars.
+  lumping, and the solve at the parity bars;
+* a hierarchy with more sparsified levels than one launch of the count scans
+  takes: every operator as sparsified alone, row sums kept.
 """
 import numpy as np
 import pytest
@@ -126,3 +128,35 @@ def test_singular_coarsest_reported_after_index_toggle(lib):
     with pytest.raises(lib.AmgError) as e:
         g.solve(dev(np.array([1.0, 2.0])), x, method=1, tol=1e-10, maxit=5)
     assert e.value.status == -2 and "singular" in str(e.value)
+
+
+def test_sparsify_more_levels_than_one_scan_launch(lib):
+    """1D Poisson on 2^23 points: 19 levels, 17 of them sparsified (levels >=
+    2), more than one launch of the per-level count scans takes (16), so the
+    levels go in two rounds.  Every sparsified operator must be bitwise the
+    one a call sparsifying that level alone produces, and its lumped rows must
+    keep the Galerkin row sums (Section 3.1)."""
+    n = 1 << 23
+    A = I._structured((n,), [(0,), (-1,), (1,)], [2.0, -1.0, -1.0])
+    g = lib.Hierarchy(A)
+    L = g.nlev
+    assert L - 2 > 16, L
+    gam = [0.0, 0.0] + [0.1] * (L - 2)
+    g.sparsify_levels(gam)
+    together = {l: g.export(l, "AHAT") for l in range(2, L)}
+    for l in range(2, L):
+        one = [0.0] * L
+        one[l] = 0.1
+        g.sparsify_levels(one)
+        alone = g.export(l, "AHAT")
+        for a, b in zip(together[l], alone):
+            assert np.asarray(a).tobytes() == np.asarray(b).tobytes(), l
+        nr, nc, rp, ci, v = alone
+        Al = g.export(l, "A")
+        rows = np.repeat(np.arange(nr), np.diff(rp))
+        arows = np.repeat(np.arange(Al[0]), np.diff(Al[2]))
+        rs_hat = np.bincount(rows, weights=v, minlength=nr)
+        rs = np.bincount(arows, weights=Al[4], minlength=nr)
+        scale = np.bincount(arows, weights=np.abs(Al[4]), minlength=nr)
+        assert np.all(np.abs(rs_hat - rs) <= 1e-13 * scale), l
+    g.close()
