@@ -118,18 +118,33 @@ __device__ __forceinline__ void add_to_fp64(double* acc, const v2d& v) {
 // instructions, the gathers included, more than by their bytes).  Entries
 // at even and odd positions of the row go to two accumulators, added at the
 // end, with two gathers in flight (the chunks of LPR entries start at even
-// positions; a row of one lane takes its entries two at a time).  With DIAG, *gd receives G[i, c0 ..
-// c0+V) from the gather of the row's diagonal entry (loaded if the row has
-// none), so a sweep does not load its own x_i again.
+// positions; a row of one lane takes its entries two at a time).  With
+// DIAG, *gd receives G[i, c0 .. c0+V) from the gather of the row's diagonal
+// entry (loaded if the row has none), so a sweep does not load its own x_i
+// again.
+template <class T, int K, bool DIAG>
+struct RowAcc {
+    using VT = typename Vec16<T>::type;
+    VT s0{}, s1{}, dg{};
+    bool found = false;
+    // entry (j, v) at an even (odd = false) or odd position of the row
+    __device__ __forceinline__ void add(bool odd, int j, T v, const VT& gj, int i) {
+        if (odd) s1 += v * gj;
+        else s0 += v * gj;
+        if constexpr (DIAG) {
+            if (j == i) dg = gj;
+            found = found || j == i;
+        }
+    }
+};
+
 template <class T, int K, bool DIAG = false>
 __device__ __forceinline__ typename Vec16<T>::type row_gather_sum(const CsrT<T>& a, const T* __restrict__ g,
                                                                   int beg, int end, int c0, int i = 0,
                                                                   typename Vec16<T>::type* gd = nullptr) {
     using VT = typename Vec16<T>::type;
     constexpr int LPR = K / Vec16<T>::n;
-    const int q = threadIdx.x & (LPR - 1);
-    VT s0{}, s1{}, dg{};
-    bool found = false;
+    RowAcc<T, K, DIAG> acc;
     if constexpr (LPR == 1) {
         // a lane per row (4 FP32 columns): its own loads, two entries a step
         int p = beg;
@@ -138,58 +153,37 @@ __device__ __forceinline__ typename Vec16<T>::type row_gather_sum(const CsrT<T>&
             const T v0 = mat_ld(a.v + p), v1 = mat_ld(a.v + p + 1);
             const VT g0 = ld16<VT>(g + j0 * K + c0);
             const VT g1 = ld16<VT>(g + j1 * K + c0);
-            s0 += v0 * g0;
-            s1 += v1 * g1;
-            if constexpr (DIAG) {
-                if (j0 == i) dg = g0;
-                if (j1 == i) dg = g1;
-                found = found || j0 == i || j1 == i;
-            }
+            acc.add(false, j0, v0, g0, i);
+            acc.add(true, j1, v1, g1, i);
         }
         if (p < end) {
             const int j0 = mat_ld(a.ci + p);
-            const VT g0 = ld16<VT>(g + j0 * K + c0);
-            s0 += mat_ld(a.v + p) * g0;
-            if constexpr (DIAG) {
-                if (j0 == i) dg = g0;
-                found = found || j0 == i;
-            }
+            acc.add(false, j0, mat_ld(a.v + p), ld16<VT>(g + j0 * K + c0), i);
         }
-    } else
-    for (int p = beg; p < end; p += LPR) {
-        const int qq = min(p + q, end - 1);
-        const int myj = mat_ld(a.ci + qq);
-        const T myv = mat_ld(a.v + qq);
-        const int cnt = min(LPR, end - p);
-        int k = 0;
-        for (; k + 1 < cnt; k += 2) {
-            const int j0 = __shfl(myj, k, LPR), j1 = __shfl(myj, k + 1, LPR);
-            const T v0 = __shfl(myv, k, LPR), v1 = __shfl(myv, k + 1, LPR);
-            const VT g0 = ld16<VT>(g + j0 * K + c0);
-            const VT g1 = ld16<VT>(g + j1 * K + c0);
-            s0 += v0 * g0;
-            s1 += v1 * g1;
-            if constexpr (DIAG) {
-                if (j0 == i) dg = g0;
-                if (j1 == i) dg = g1;
-                found = found || j0 == i || j1 == i;
+    } else {
+        const int q = threadIdx.x & (LPR - 1);
+        for (int p = beg; p < end; p += LPR) {
+            const int qq = min(p + q, end - 1);
+            const int myj = mat_ld(a.ci + qq);
+            const T myv = mat_ld(a.v + qq);
+            const int cnt = min(LPR, end - p);
+            int k = 0;
+            for (; k + 1 < cnt; k += 2) {
+                const int j0 = __shfl(myj, k, LPR), j1 = __shfl(myj, k + 1, LPR);
+                const T v0 = __shfl(myv, k, LPR), v1 = __shfl(myv, k + 1, LPR);
+                const VT g0 = ld16<VT>(g + j0 * K + c0);
+                const VT g1 = ld16<VT>(g + j1 * K + c0);
+                acc.add(false, j0, v0, g0, i);
+                acc.add(true, j1, v1, g1, i);
             }
-        }
-        if (k < cnt) {
-            const int j0 = __shfl(myj, k, LPR);
-            const VT g0 = ld16<VT>(g + j0 * K + c0);
-            s0 += __shfl(myv, k, LPR) * g0;
-            if constexpr (DIAG) {
-                if (j0 == i) dg = g0;
-                found = found || j0 == i;
+            if (k < cnt) {
+                const int j0 = __shfl(myj, k, LPR);
+                acc.add(false, j0, __shfl(myv, k, LPR), ld16<VT>(g + j0 * K + c0), i);
             }
         }
     }
-    if constexpr (DIAG) {
-        if (!found) dg = ld16<VT>(g + i * K + c0);
-        *gd = dg;
-    }
-    return s0 + s1;
+    if constexpr (DIAG) *gd = acc.found ? acc.dg : ld16<VT>(g + i * K + c0);
+    return acc.s0 + acc.s1;
 }
 
 template <class T, int K, int OP>
