@@ -338,6 +338,25 @@ def bench_poisson(args):
     log(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step; {dom_kernel}@{dom_level}: "
         f"{per_launch_s * 1e6:.1f} us/launch, {achieved:.0f} GB/s")
 
+    # the step's two phases timed apart with HIP events on the library's stream
+    # (torch's current stream): the sparsify pass over every coarse level, and
+    # the adaptive solve
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    sp_ms, so_ms = [], []
+    for _ in range(max(args.steps // 2, 3)):
+        ev[0].record()
+        h.sparsify(args.gamma, 2)
+        ev[1].record()
+        x.zero_()
+        h.solve(b, x, **solve_kw)
+        ev[2].record()
+        torch.cuda.synchronize()
+        sp_ms.append(ev[0].elapsed_time(ev[1]))
+        so_ms.append(ev[1].elapsed_time(ev[2]))
+    phases = dict(sparsify_ms=round(float(np.median(sp_ms)), 4), solve_ms=round(float(np.median(so_ms)), 4),
+                  runs=len(sp_ms), how="medians; HIP events around amg_sparsify and around x = 0 + amg_solve")
+    log(f"[bench] phases: sparsify {phases['sparsify_ms']:.3f} ms, solve {phases['solve_ms']:.3f} ms")
+
     # the dominant kernel alone on its operator, launched through amg_level_op:
     # back to back (the 256 MB Infinity Cache may hold part of the operator),
     # and with 1 GiB streamed between launches so that every launch reads it
@@ -435,6 +454,7 @@ def bench_poisson(args):
         "iters": res.iters,
         "relres": res.relres,
         "setup_s": round(setup_s, 3),
+        "phases": phases,
         "time_to_1e8_ms": compare,
         "sparsified_vs_galerkin": summary,
         "speedup_vs_galerkin": summary["speedup_median"] if summary else None,
