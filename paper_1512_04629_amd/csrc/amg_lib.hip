@@ -570,6 +570,12 @@ void mark_minimal_pattern(amg_ctx* h, int l, bool hybrid) {
 // sparsified operator is allocated once with the capacity of the Galerkin
 // operator, so after the first call nothing is allocated and nothing waits
 // for the device; any allocation happens before a level is modified.
+// levels of at most this many rows are sparsified together, one launch for
+// their keep flags and one for their compaction (their launches cost more
+// than their work)
+constexpr int kMergeRows = 8192;
+bool merge_level(const DevLevel& c) { return c.n <= kMergeRows; }
+
 void sparsify_levels(amg_ctx* h, const std::vector<std::pair<int, double>>& todo) {
     for (auto& t : todo) {
         DevLevel& c = h->lv[t.first];
@@ -602,6 +608,8 @@ void sparsify_levels(amg_ctx* h, const std::vector<std::pair<int, double>>& todo
         const size_t first = next;
         size_t last = one_by_one ? next + 1 : todo.size();
         ScanJobs jobs;
+        SparsifyLevels merged;
+        std::vector<char> in_merged(todo.size(), 0);
         for (size_t q = first; q < last; ++q) {
             const int l = todo[q].first;
             const double gamma = todo[q].second;
@@ -641,24 +649,53 @@ void sparsify_levels(amg_ctx* h, const std::vector<std::pair<int, double>>& todo
                 }
                 launch_inverse_diagonal(c.Ahs.view(), c.dinv, h->fp32 ? c.dinv32 : nullptr, h->stream);
                 if (h->fp32) launch_narrow(c.A.nnz, c.Ahs32, c.Ahs.v, h->stream);   // capacity; past nnz unused
+            } else if (merge_level(c) && merged.count < kMaxMergedLevels) {
+                // small levels: one launch for all of them, below
+                in_merged[q] = 1;
+                SparsifyLevel& v = merged.lv[merged.count++];
+                v.a = c.A.view();
+                v.in_m = c.in_m;
+                v.m = c.rowmax;
+                v.gamma = gamma;
+                v.keep = c.keep;
+                v.cnt = c.kcnt;
+                v.bsum = c.kbsum;
+                v.new_rp = c.Ahs.rp;
+                v.new_ci = c.Ahs.ci;
+                v.new_v = c.Ahs.v;
+                v.dinv = c.dinv;
+                v.new_v32 = h->fp32 ? c.Ahs32 : nullptr;
+                v.dinv32 = h->fp32 ? c.dinv32 : nullptr;
+                jobs.data[jobs.count] = c.kbsum;
+                jobs.n[jobs.count] = keep_count_blocks(64, c.n);
+                ++jobs.count;
             } else {
                 launch_keep_count(c.A.width, c.A.view(), c.in_m, c.rowmax, gamma, c.keep, c.kcnt, c.kbsum,
                                   h->stream);
                 jobs.data[jobs.count] = c.kbsum;
                 jobs.n[jobs.count] = keep_count_blocks(c.A.width, c.n);
                 ++jobs.count;
-                if (jobs.count == kMaxScanJobs) last = q + 1;   // the rest in the next round
             }
+            if (jobs.count == kMaxScanJobs) last = q + 1;   // the rest in the next round
             check_launch();
         }
+        if (merged.count > 0) {
+            ProfScope ps(h, AMG_K_SPARSIFY, todo[first].first);
+            launch_keep_count_merged(merged, h->stream);
+        }
         launch_scan_jobs(jobs, h->stream);
+        if (merged.count > 0) {
+            ProfScope ps(h, AMG_K_SPARSIFY, todo[first].first);
+            launch_compact_lump_merged(merged, h->stream);
+        }
+        check_launch();
         for (size_t q = first; q < last; ++q) {
             const int l = todo[q].first;
             const double gamma = todo[q].second;
             if (gamma == 0.0) continue;
             DevLevel& c = h->lv[l];
             ProfScope ps(h, AMG_K_SPARSIFY, l);
-            if (h->lumping != AMG_LUMP_STRONG)
+            if (h->lumping != AMG_LUMP_STRONG && !in_merged[q])
                 launch_compact_lump(c.A.width, c.A.view(), c.keep, c.kcnt, c.kbsum, c.Ahs.rp, c.Ahs.ci, c.Ahs.v,
                                     c.dinv, h->fp32 ? c.Ahs32 : nullptr, h->fp32 ? c.dinv32 : nullptr,
                                     h->stream);
@@ -2007,9 +2044,11 @@ void finish_setup(amg_ctx* h) {
     h->scan_scratch = dalloc_n<int32_t>(h, scan_scratch_ints(nmax));
     {
         int64_t ncnt = 0, nbsum = 0;
+        // block counts at 64 lanes a row (the most blocks any width gives), so
+        // that a level fits whether it runs alone or merged with others
         for (auto& d : h->lv) {
             ncnt += d.n + 1;
-            nbsum += keep_count_blocks(d.A.width, d.n) + 1;
+            nbsum += keep_count_blocks(64, d.n) + 1;
         }
         h->sp_cnt = dalloc_n<int32_t>(h, ncnt);
         h->sp_bsum = dalloc_n<int32_t>(h, nbsum);
@@ -2018,7 +2057,7 @@ void finish_setup(amg_ctx* h) {
             d.kcnt = h->sp_cnt + ncnt;
             d.kbsum = h->sp_bsum + nbsum;
             ncnt += d.n + 1;
-            nbsum += keep_count_blocks(d.A.width, d.n) + 1;
+            nbsum += keep_count_blocks(64, d.n) + 1;
         }
     }
     for (int l = 0; l <= L; ++l) {

@@ -1198,12 +1198,11 @@ __global__ __launch_bounds__(kBlock) void row_max_kernel(CsrView a, double* __re
 }
 
 template <int W>
-__global__ __launch_bounds__(kBlock) void keep_count_kernel(CsrView a, const uint8_t* __restrict__ in_m,
-                                                            const double* __restrict__ m, double gamma,
-                                                            uint8_t* __restrict__ keep,
-                                                            int32_t* __restrict__ cnt,
-                                                            int32_t* __restrict__ bsum) {
-    const int row = blockIdx.x * (kBlock / W) + threadIdx.x / W;
+__device__ __forceinline__ void keep_count_rows(const CsrView& a, const uint8_t* __restrict__ in_m,
+                                                const double* __restrict__ m, double gamma,
+                                                uint8_t* __restrict__ keep, int32_t* __restrict__ cnt,
+                                                int32_t* __restrict__ bsum, int blk) {
+    const int row = blk * (kBlock / W) + threadIdx.x / W;
     const int lane = threadIdx.x & (W - 1);
     int c = 0;
     if (row < a.rows) {
@@ -1229,9 +1228,18 @@ __global__ __launch_bounds__(kBlock) void keep_count_kernel(CsrView a, const uin
             int v = (int)threadIdx.x < kBlock / W ? rows_c[threadIdx.x] : 0;
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-            if (threadIdx.x == 0) bsum[blockIdx.x] = v;
+            if (threadIdx.x == 0) bsum[blk] = v;
         }
     }
+}
+
+template <int W>
+__global__ __launch_bounds__(kBlock) void keep_count_kernel(CsrView a, const uint8_t* __restrict__ in_m,
+                                                            const double* __restrict__ m, double gamma,
+                                                            uint8_t* __restrict__ keep,
+                                                            int32_t* __restrict__ cnt,
+                                                            int32_t* __restrict__ bsum) {
+    keep_count_rows<W>(a, in_m, m, gamma, keep, cnt, bsum, blockIdx.x);
 }
 
 // The first position of each row in the compacted operator: the block's
@@ -1239,21 +1247,19 @@ __global__ __launch_bounds__(kBlock) void keep_count_kernel(CsrView a, const uin
 // kept counts of the block's earlier rows (a shuffle scan over its <= 64
 // rows); the row pointers of the compacted operator are written here too.
 template <int W>
-__global__ __launch_bounds__(kBlock) void compact_lump_kernel(CsrView a, const uint8_t* __restrict__ keep,
-                                                              const int32_t* __restrict__ cnt,
-                                                              const int32_t* __restrict__ boff,
-                                                              int32_t* __restrict__ new_rp,
-                                                              int32_t* __restrict__ new_ci,
-                                                              double* __restrict__ new_v,
-                                                              double* __restrict__ dinv,
-                                                              float* __restrict__ new_v32,
-                                                              float* __restrict__ dinv32) {
+__device__ __forceinline__ void compact_lump_rows(const CsrView& a, const uint8_t* __restrict__ keep,
+                                                  const int32_t* __restrict__ cnt,
+                                                  const int32_t* __restrict__ boff,
+                                                  int32_t* __restrict__ new_rp, int32_t* __restrict__ new_ci,
+                                                  double* __restrict__ new_v, double* __restrict__ dinv,
+                                                  float* __restrict__ new_v32, float* __restrict__ dinv32,
+                                                  int blk) {
     constexpr int R = kBlock / W;   // rows per block
     __shared__ int row_out[R];
-    const int row = blockIdx.x * R + threadIdx.x / W;
+    const int row = blk * R + threadIdx.x / W;
     const int lane = threadIdx.x & (W - 1);
     if (threadIdx.x < 64) {
-        const int r = blockIdx.x * R + (int)threadIdx.x;
+        const int r = blk * R + (int)threadIdx.x;
         const int c = ((int)threadIdx.x < R && r < a.rows) ? cnt[r] : 0;
         int incl = c;
 #pragma unroll
@@ -1262,7 +1268,7 @@ __global__ __launch_bounds__(kBlock) void compact_lump_kernel(CsrView a, const u
             if ((int)threadIdx.x >= off) incl += t;
         }
         if ((int)threadIdx.x < R) {
-            const int o = boff[blockIdx.x] + incl - c;
+            const int o = boff[blk] + incl - c;
             row_out[threadIdx.x] = o;
             if (r < a.rows) new_rp[r] = o;
             if (r == a.rows - 1) new_rp[a.rows] = o + c;
@@ -1310,6 +1316,40 @@ __global__ __launch_bounds__(kBlock) void compact_lump_kernel(CsrView a, const u
             dinv32[row] = (float)(1.0 / d);
         }
     }
+}
+
+template <int W>
+__global__ __launch_bounds__(kBlock) void compact_lump_kernel(CsrView a, const uint8_t* __restrict__ keep,
+                                                              const int32_t* __restrict__ cnt,
+                                                              const int32_t* __restrict__ boff,
+                                                              int32_t* __restrict__ new_rp,
+                                                              int32_t* __restrict__ new_ci,
+                                                              double* __restrict__ new_v,
+                                                              double* __restrict__ dinv,
+                                                              float* __restrict__ new_v32,
+                                                              float* __restrict__ dinv32) {
+    compact_lump_rows<W>(a, keep, cnt, boff, new_rp, new_ci, new_v, dinv, new_v32, dinv32, blockIdx.x);
+}
+
+// Several small levels in one launch each (64 lanes a row): block b belongs to
+// the last level whose first block is <= b, and runs that level's rows as
+// the per-level kernels do.
+__device__ __forceinline__ int merged_level(const SparsifyLevels& L) {
+    int li = 0;
+    for (int k = 1; k < L.count; ++k)
+        if ((int)blockIdx.x >= L.lv[k].block0) li = k;
+    return li;
+}
+
+__global__ __launch_bounds__(kBlock) void keep_count_merged_kernel(SparsifyLevels L) {
+    const SparsifyLevel& v = L.lv[merged_level(L)];
+    keep_count_rows<64>(v.a, v.in_m, v.m, v.gamma, v.keep, v.cnt, v.bsum, (int)blockIdx.x - v.block0);
+}
+
+__global__ __launch_bounds__(kBlock) void compact_lump_merged_kernel(SparsifyLevels L) {
+    const SparsifyLevel& v = L.lv[merged_level(L)];
+    compact_lump_rows<64>(v.a, v.keep, v.cnt, v.bsum, v.new_rp, v.new_ci, v.new_v, v.dinv, v.new_v32, v.dinv32,
+                          (int)blockIdx.x - v.block0);
 }
 
 // Inverse of the dense coarsest operator (n <= kDenseInvMax) by Gauss-Jordan
@@ -2012,6 +2052,24 @@ int keep_count_blocks(int width, int rows) {
     const int w = width == 4 || width == 8 || width == 16 || width == 32 ? width : 64;
     const int r = kBlock / w;
     return (rows + r - 1) / r;
+}
+
+void launch_keep_count_merged(SparsifyLevels& L, hipStream_t st) {
+    int b = 0;
+    for (int k = 0; k < L.count; ++k) {
+        L.lv[k].block0 = b;
+        b += keep_count_blocks(64, L.lv[k].a.rows);
+    }
+    if (L.count > 0 && b > 0) hipLaunchKernelGGL(keep_count_merged_kernel, dim3(b), dim3(kBlock), 0, st, L);
+}
+
+void launch_compact_lump_merged(SparsifyLevels& L, hipStream_t st) {
+    int b = 0;
+    for (int k = 0; k < L.count; ++k) {
+        L.lv[k].block0 = b;
+        b += keep_count_blocks(64, L.lv[k].a.rows);
+    }
+    if (L.count > 0 && b > 0) hipLaunchKernelGGL(compact_lump_merged_kernel, dim3(b), dim3(kBlock), 0, st, L);
 }
 
 void launch_scan_jobs(const ScanJobs& jobs, hipStream_t st) {

@@ -237,6 +237,32 @@ struct ScanJobs {
     int count = 0;
 };
 void launch_scan_jobs(const ScanJobs& jobs, hipStream_t st);
+// several small levels' keep flags (and later their compaction) in one launch,
+// 64 lanes a row (keep_count_blocks(64, rows) blocks a level): bsum receives
+// the level's block counts, and compaction reads their scan from it
+constexpr int kMaxMergedLevels = 8;
+struct SparsifyLevel {
+    CsrView a;
+    const uint8_t* in_m;
+    const double* m;
+    double gamma;
+    uint8_t* keep;
+    int32_t* cnt;
+    int32_t* bsum;
+    int32_t* new_rp;
+    int32_t* new_ci;
+    double* new_v;
+    double* dinv;
+    float* new_v32;
+    float* dinv32;
+    int block0;   // set by the launchers
+};
+struct SparsifyLevels {
+    SparsifyLevel lv[kMaxMergedLevels];
+    int count = 0;
+};
+void launch_keep_count_merged(SparsifyLevels& L, hipStream_t st);
+void launch_compact_lump_merged(SparsifyLevels& L, hipStream_t st);
 // exclusive scan of cnt[0..n) into out[0..n], out[n] = total; scratch >= scan_scratch_ints(n)
 int64_t scan_scratch_ints(int n);
 void launch_exclusive_scan(int n, const int32_t* cnt, int32_t* out, int32_t* scratch,
