@@ -46,51 +46,48 @@ def launch_bytes(h, kernel: str, level: int) -> int:
     li = h.level_info(level)
     n, nnz_hat, nc, nnz_p = li["n"], li["nnz_hat"], li["n_coarse"], li["nnz_P"]
     nnz_a = li["nnz"]
-
-    def entry(which):
-        return 12
+    e = 12  # an FP64 value and an int32 column index per entry
 
     if kernel == "JACOBI":
         # x gathered, b, dinv read, x' written
-        return entry("AHAT") * nnz_hat + 4 * (n + 1) + 32 * n
+        return e * nnz_hat + 4 * (n + 1) + 32 * n
     if kernel == "JACOBI_ZERO":
         # zero-guess level: residual of the prescaled sweep omega D^-1 b that
         # the producer (restriction / CG update) wrote: x gathered, b read, r
         # written (the fused first-iteration form moves 8n more; counted as
         # this lower figure)
-        return entry("AHAT") * nnz_hat + 4 * (n + 1) + 24 * n
+        return e * nnz_hat + 4 * (n + 1) + 24 * n
     if kernel == "RESIDUAL":
-        nz, e = (nnz_a, entry("A")) if level == 0 else (nnz_hat, entry("AHAT"))
+        # level 0 is the Galerkin A_0 (never sparsified), below it Ahat_l
+        nz = nnz_a if level == 0 else nnz_hat
         return e * nz + 4 * (n + 1) + 24 * n
     if kernel == "SPMV_DOT":
-        return entry("A") * nnz_a + 4 * (n + 1) + 16 * n
+        return e * nnz_a + 4 * (n + 1) + 16 * n
     if kernel == "RESTRICT":
         # b_c = R r; below the coarsest level also x_c = omega dinv_c b_c
         extra = 16 * nc if level + 2 < h.nlev else 0
-        return entry("R") * nnz_p + 4 * (nc + 1) + 8 * n + 8 * nc + extra
+        return e * nnz_p + 4 * (nc + 1) + 8 * n + 8 * nc + extra
     if kernel == "INTERP":
-        return entry("P") * nnz_p + 4 * (n + 1) + 8 * nc + 16 * n
+        return e * nnz_p + 4 * (n + 1) + 8 * nc + 16 * n
     return 0
 
 
 def launch_bytes32(h, kernel: str, level: int) -> int:
-    """launch_bytes for the FP32 cycle: 4-byte values and vectors, the same
-    column indices."""
+    """launch_bytes for the FP32 cycle: 4-byte values and vectors, int32 column
+    indices and row pointers (whatever index width the kernel reads)."""
     li = h.level_info(level)
     n, nnz_hat, nc, nnz_p = li["n"], li["nnz_hat"], li["n_coarse"], li["nnz_P"]
-
-    def entry(which):
-        return 4 + h.index_width(level, which)
+    e = 8  # an FP32 value and an int32 column index per entry
 
     if kernel == "JACOBI":
-        return entry("AHAT") * nnz_hat + 4 * (n + 1) + 16 * n
+        return e * nnz_hat + 4 * (n + 1) + 16 * n
     if kernel in ("JACOBI_ZERO", "RESIDUAL"):
-        return entry("AHAT") * nnz_hat + 4 * (n + 1) + 12 * n
+        return e * nnz_hat + 4 * (n + 1) + 12 * n
     if kernel == "RESTRICT":
         extra = 8 * nc if level + 2 < h.nlev else 0
-        return entry("R") * nnz_p + 4 * (nc + 1) + 4 * n + 4 * nc + extra
+        return e * nnz_p + 4 * (nc + 1) + 4 * n + 4 * nc + extra
     if kernel == "INTERP":
-        return entry("P") * nnz_p + 4 * (n + 1) + 4 * nc + 8 * n
+        return e * nnz_p + 4 * (n + 1) + 4 * nc + 8 * n
     return 0
 
 
@@ -360,9 +357,12 @@ def bench_poisson(args):
     # the dominant kernel alone on its operator, launched through amg_level_op:
     # back to back (the 256 MB Infinity Cache may hold part of the operator),
     # and with 1 GiB streamed between launches so that every launch reads it
-    # from HBM
+    # from HBM.  The zero-guess sweep has no level operation of its own; the
+    # sweep with a guess streams the same operator and stands in for it.
     cache_runs = {}
-    if dom_kernel in ("JACOBI", "RESIDUAL") and not args.no_alone:
+    alone_kernel = {"JACOBI": "JACOBI", "RESIDUAL": "RESIDUAL", "JACOBI_ZERO": "JACOBI"}.get(dom_kernel)
+    if alone_kernel and not args.no_alone:
+        alone_bytes = launch_bytes(h, alone_kernel, dom_level)
         nl = h.level_info(dom_level)["n"]
         gen = torch.Generator(device="cuda").manual_seed(5)
         bl = torch.rand(nl, dtype=torch.float64, device="cuda", generator=gen)
@@ -370,21 +370,26 @@ def bench_poisson(args):
         ol = torch.empty_like(xl)
         big = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
         big2 = torch.empty_like(big)
+        cache_runs["kernel"] = f"{alone_kernel} level {dom_level}"
+        cache_runs["bytes_per_launch"] = alone_bytes
+        cache_runs["how"] = ("back_to_back: 10 launches in a row, the operator partly or wholly read from the "
+                             "256 MB Infinity Cache (frac may exceed 1 against the HBM peak); mall_flushed: a "
+                             "1 GiB copy before each launch, so the operator comes from HBM")
         for label, flush in (("back_to_back", False), ("mall_flushed", True)):
-            h.level_op(dom_level, dom_kernel, inp=bl, x=xl, out=ol)
+            h.level_op(dom_level, alone_kernel, inp=bl, x=xl, out=ol)
             torch.cuda.synchronize()
-            h.profile_enable(True, dom_kernel, dom_level)
+            h.profile_enable(True, alone_kernel, dom_level)
             for _ in range(10):
                 if flush:
                     big2.copy_(big)
-                h.level_op(dom_level, dom_kernel, inp=bl, x=xl, out=ol)
+                h.level_op(dom_level, alone_kernel, inp=bl, x=xl, out=ol)
             torch.cuda.synchronize()
-            c3, m3 = h.profile_read(dom_kernel, dom_level)
+            c3, m3 = h.profile_read(alone_kernel, dom_level)
             h.profile_enable(False)
-            gbs = nbytes / (m3 / c3 / 1e3) / 1e9
+            gbs = alone_bytes / (m3 / c3 / 1e3) / 1e9
             cache_runs[label] = dict(us_per_launch=round(m3 / c3 * 1e3, 3), achieved=round(gbs, 1),
                                      frac=round(gbs / HBM_PEAK_GBS, 4), launches=c3)
-            log(f"[bench] {dom_kernel}@{dom_level} alone, {label}: {m3 / c3 * 1e3:.1f} us, {gbs:.0f} GB/s")
+            log(f"[bench] {alone_kernel}@{dom_level} alone, {label}: {m3 / c3 * 1e3:.1f} us, {gbs:.0f} GB/s")
         del big, big2
 
     # practical ceiling: a plain device-to-device copy of 1 GiB (read + written bytes / time)

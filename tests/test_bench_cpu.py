@@ -100,8 +100,8 @@ def test_crossing_margin_and_host_description():
 
 def test_fp32_cycle_launch_bytes():
     h = StubHierarchy({(1, "AHAT"): 2, (0, "R"): 2, (0, "P"): 2})
-    # 4-byte values and vectors, 2-byte indices where the level keeps them
-    assert bench.launch_bytes32(h, "JACOBI", 1) == 6 * 9000 + 4 * 501 + 16 * 500
-    assert bench.launch_bytes32(h, "JACOBI_ZERO", 1) == 6 * 9000 + 4 * 501 + 12 * 500
-    assert bench.launch_bytes32(h, "RESTRICT", 0) == 6 * 1800 + 4 * 501 + 4 * 1000 + 4 * 500 + 8 * 500
-    assert bench.launch_bytes32(h, "INTERP", 0) == 6 * 1800 + 4 * 1001 + 4 * 500 + 8 * 1000
+    # 4-byte values and vectors, int32 indices even where the level keeps 2-byte ones
+    assert bench.launch_bytes32(h, "JACOBI", 1) == 8 * 9000 + 4 * 501 + 16 * 500
+    assert bench.launch_bytes32(h, "JACOBI_ZERO", 1) == 8 * 9000 + 4 * 501 + 12 * 500
+    assert bench.launch_bytes32(h, "RESTRICT", 0) == 8 * 1800 + 4 * 501 + 4 * 1000 + 4 * 500 + 8 * 500
+    assert bench.launch_bytes32(h, "INTERP", 0) == 8 * 1800 + 4 * 1001 + 4 * 500 + 8 * 1000
