@@ -49,6 +49,13 @@ constexpr int kRowGridCap = AMG_ROW_GRID_CAP;   // row kernels loop over tiles b
 #ifndef AMG_STREAM_CAP
 #define AMG_STREAM_CAP 2048
 #endif
+// Longest mean row the LDS-staged kernel takes.  Measured on the 128^3
+// hierarchy, whose level 2 has rows of 30 entries: the level-2 sweep 18.3 ->
+// 16.5 us and its zero-guess residual 21.8 -> 20.5 us against the subgroup
+// kernel.
+#ifndef AMG_STREAM_MAX_ROW
+#define AMG_STREAM_MAX_ROW 48.0
+#endif
 #ifndef AMG_STREAM_FILL
 #define AMG_STREAM_FILL 0.85
 #endif
@@ -1814,16 +1821,17 @@ int stream_rows_per_block(double mean) {
     return rb;
 }
 
-// The LDS-staged kernel wins on the large fine-level operators with short
-// rows (measured on the 128^3 hierarchy: A_0, A_1, P_0, R_0, R_1); with long
-// rows or too few row blocks to fill 256 CUs the subgroup kernel wins.
+// The LDS-staged kernel wins on the large operators with rows of up to a few
+// dozen entries (measured on the 128^3 hierarchy: A_0, A_1, P_0, R_0, R_1 and
+// the sparsified level 2); with longer rows or too few row blocks to fill 256
+// CUs the subgroup kernel wins.
 template <class T>
 bool use_stream_kernel(const CsrT<T>& a) {
 #if AMG_USE_STREAM >= 0
     return AMG_USE_STREAM != 0;
 #else
     const int rb = stream_rows_per_block(a.mean_row);
-    return a.mean_row <= 24.0 && (a.rows + rb - 1) / rb >= 1024;
+    return a.mean_row <= AMG_STREAM_MAX_ROW && (a.rows + rb - 1) / rb >= 1024;
 #endif
 }
 
@@ -2171,7 +2179,15 @@ void launch_compress_index(int rows, int rb, const int32_t* rp, const int32_t* c
 
 int stream_block_rows(const CsrView& a) { return use_stream_kernel(a) ? stream_rows_per_block(a.mean_row) : 0; }
 
-bool sell_candidate(const CsrView& a) { return AMG_SELL && use_stream_kernel(a); }
+// SELL-64 copies only for rows of at most this mean length: on the 128^3
+// Galerkin level 2 (rows of 34 entries) the SELL kernel's zero-guess residual
+// took 31.4 us against 27.8 us for the subgroup kernel.
+#ifndef AMG_SELL_MAX_ROW
+#define AMG_SELL_MAX_ROW 24.0
+#endif
+bool sell_candidate(const CsrView& a) {
+    return AMG_SELL && a.mean_row <= AMG_SELL_MAX_ROW && use_stream_kernel(a);
+}
 
 int sell_slices(int rows) { return (rows + kSellRows - 1) / kSellRows; }
 
