@@ -50,11 +50,11 @@ constexpr int kRowGridCap = AMG_ROW_GRID_CAP;   // row kernels loop over tiles b
 #define AMG_STREAM_CAP 2048
 #endif
 // Longest mean row the LDS-staged kernel takes.  Measured on the 128^3
-// hierarchy, whose level 2 has rows of 30 entries: the level-2 sweep 18.3 ->
-// 16.5 us and its zero-guess residual 21.8 -> 20.5 us against the subgroup
-// kernel.
+// hierarchy against the subgroup kernel: level 2 (rows of 30-34 entries)
+// sweep 18.3 -> 16.5 us, zero-guess residual 21.8 -> 20.5 us; level 3 (rows
+// of 41-57 entries) 6.3 -> 5.0 us and 7.7 -> 5.8 us.
 #ifndef AMG_STREAM_MAX_ROW
-#define AMG_STREAM_MAX_ROW 48.0
+#define AMG_STREAM_MAX_ROW 64.0
 #endif
 #ifndef AMG_STREAM_FILL
 #define AMG_STREAM_FILL 0.85
