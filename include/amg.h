@@ -87,6 +87,11 @@ typedef struct {
                             the correction of FP64 iterative refinement for
                             AMG_STATIONARY; residuals, dot products and the stop test
                             stay FP64 */
+    int32_t zero_guess;  /* 1: start from x0 = 0 whatever x holds on entry (the
+                            method's initial guess): x is set to zero and the
+                            initial residual is b itself, with no product by the
+                            zero vector.  0 (default): x holds x0.  amg_solve and
+                            amg_solve_noalloc only; amg_solve_block rejects 1 */
 } amg_solve_params;
 
 typedef struct {
@@ -262,7 +267,8 @@ amg_status amg_reintroduce(amg_handle h, int32_t s, double gamma_min,
    if the window diverged, and CG restarts.  params NULL = defaults.  info
    (nullable) is filled on every return that ran iterations.  hist (nullable,
    host, maxit+1 doubles) receives ||r_0|| and the residual norm after each
-   iteration. */
+   iteration.  With params->zero_guess = 1 the solve starts from x0 = 0
+   whatever x holds (x is zeroed, r_0 = b). */
 amg_status amg_solve(amg_handle h, const double* b, double* x, const amg_solve_params* params,
                      amg_solve_info* info, double* hist);
 

@@ -85,7 +85,8 @@ class SetupParams(C.Structure):
 class SolveParams(C.Structure):
     _fields_ = [("method", C.c_int32), ("rtol", C.c_double), ("maxit", C.c_int32),
                 ("adaptive", C.c_int32), ("k", C.c_int32), ("s", C.c_int32),
-                ("rho_max", C.c_double), ("gamma_min", C.c_double), ("precision", C.c_int32)]
+                ("rho_max", C.c_double), ("gamma_min", C.c_double), ("precision", C.c_int32),
+                ("zero_guess", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -389,12 +390,14 @@ class Hierarchy:
 
     # -- solve -------------------------------------------------------------
     def solve(self, b, x, method=PCG, tol=1e-8, maxit=200, adaptive=False, k=3, s=1,
-              rho_max=0.5, gamma_min=0.01, precision=64, raise_on_error=False, noalloc=False) -> SolveResult:
+              rho_max=0.5, gamma_min=0.01, precision=64, raise_on_error=False, noalloc=False,
+              zero_guess=False) -> SolveResult:
         """precision=32 runs the V-cycle in FP32 inside the FP64 iteration.
         noalloc=True calls amg_solve_noalloc (work memory in the library's
-        static device array; FP64 only, n <= 2,097,152)."""
+        static device array; FP64 only, n <= 2,097,152).  zero_guess=True
+        starts from x0 = 0 whatever x holds (x is zeroed, r0 = b)."""
         p = SolveParams(int(method), float(tol), int(maxit), int(bool(adaptive)), int(k), int(s),
-                        float(rho_max), float(gamma_min), int(precision))
+                        float(rho_max), float(gamma_min), int(precision), int(bool(zero_guess)))
         info = SolveInfo()
         hist = np.full(maxit + 1, np.nan)
         fn = self._lib.amg_solve_noalloc if noalloc else self._lib.amg_solve

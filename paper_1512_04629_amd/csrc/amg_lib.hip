@@ -1097,7 +1097,14 @@ amg_status solve(amg_ctx* h, const double* b, double* x, const amg_solve_params&
     amg_status st = AMG_ERR_NOT_CONVERGED;
     double* r = h->cg_r;
     launch_fill_f64(S_COUNT, h->scal, 0.0, h->stream);
-    row_op(h, AMG_K_RESIDUAL, 0, kResidNorm, A, x, b, nullptr, r, nullptr, S_NR2);
+    if (p.zero_guess) {
+        // x0 = 0: r0 = b - A 0 = b
+        ProfScope ps(h, AMG_K_VECTOR, 0);
+        launch_zero_start(n, b, x, r, dot_to(h, S_NR2), h->stream);
+        check_launch();
+    } else {
+        row_op(h, AMG_K_RESIDUAL, 0, kResidNorm, A, x, b, nullptr, r, nullptr, S_NR2);
+    }
     int singular = 0;
     if (h->check_singular) {
         download(h, &singular, h->singular, 1);
@@ -2742,6 +2749,7 @@ void amg_solve_params_default(amg_solve_params* p) {
     p->rho_max = 0.5;
     p->gamma_min = 0.01;
     p->precision = 64;
+    p->zero_guess = 0;
 }
 
 amg_status amg_setup_from_csr(int64_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
@@ -2895,7 +2903,8 @@ amg_status amg_solve(amg_handle h, const double* b, double* x, const amg_solve_p
     amg_solve_params_default(&p);
     if (params) p = *params;
     if ((p.method != AMG_PCG && p.method != AMG_STATIONARY) || p.maxit < 0 || !(p.rtol >= 0.0) ||
-        (p.adaptive && (p.k < 1 || p.s < 1)) || (p.precision != 64 && p.precision != 32)) {
+        (p.adaptive && (p.k < 1 || p.s < 1)) || (p.precision != 64 && p.precision != 32) ||
+        (p.zero_guess != 0 && p.zero_guess != 1)) {
         h->last_error = "invalid solve parameters";
         return AMG_ERR_INVALID_ARG;
     }
@@ -2914,7 +2923,7 @@ amg_status amg_solve_noalloc(amg_handle h, const double* b, double* x, const amg
     amg_solve_params_default(&p);
     if (params) p = *params;
     if ((p.method != AMG_PCG && p.method != AMG_STATIONARY) || p.maxit < 0 || !(p.rtol >= 0.0) ||
-        (p.adaptive && (p.k < 1 || p.s < 1)) || p.precision != 64) {
+        (p.adaptive && (p.k < 1 || p.s < 1)) || p.precision != 64 || (p.zero_guess != 0 && p.zero_guess != 1)) {
         h->last_error = "invalid solve parameters (the allocation-free solve runs the FP64 cycle only)";
         return AMG_ERR_INVALID_ARG;
     }
@@ -3006,8 +3015,8 @@ amg_status amg_solve_block(amg_handle h, int32_t nrhs, const double* b, double* 
     const int64_t n = h->lv[0].n;
     if (!b || !x || nrhs < 1 || nrhs > kMaxBlockRhs || n * block_width(nrhs) > INT32_MAX ||
         (p.method != AMG_STATIONARY && p.method != AMG_PCG) || p.adaptive || p.maxit < 0 || !(p.rtol >= 0.0) ||
-        (p.precision != 64 && p.precision != 32)) {
-        h->last_error = "invalid block solve arguments (1 <= nrhs <= 16, not adaptive)";
+        (p.precision != 64 && p.precision != 32) || p.zero_guess != 0) {
+        h->last_error = "invalid block solve arguments (1 <= nrhs <= 16, not adaptive, zero_guess 0)";
         return AMG_ERR_INVALID_ARG;
     }
     const int k = block_width(nrhs);

@@ -1119,6 +1119,21 @@ __global__ __launch_bounds__(kBlock) void dot_kernel(int n, const double* __rest
     store_block_partial(s, dot.partials, blockIdx.x);
 }
 
+// Start from x0 = 0: x = 0, r = b (the residual of the zero vector) and the
+// block partials of ||b||^2.
+__global__ __launch_bounds__(kBlock) void zero_start_kernel(int n, const double* __restrict__ b,
+                                                            double* __restrict__ x, double* __restrict__ r,
+                                                            DotTarget dot) {
+    double s = 0.0;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        const double bi = b[i];
+        x[i] = 0.0;
+        r[i] = bi;
+        s += bi * bi;
+    }
+    store_block_partial(s, dot.partials, blockIdx.x);
+}
+
 __global__ __launch_bounds__(kBlock) void dense_matvec_kernel(int n, const double* __restrict__ ainv,
                                                               const double* __restrict__ b,
                                                               double* __restrict__ y) {
@@ -2009,6 +2024,11 @@ void launch_fill_f64(int64_t n, double* p, double v, hipStream_t st) {
 
 void launch_dot(int n, const double* a, const double* b, DotTarget dot, hipStream_t st) {
     hipLaunchKernelGGL(dot_kernel, dim3(vec_grid(n)), dim3(kBlock), 0, st, n, a, b, dot);
+    finish_dot(dot, vec_grid(n), st);
+}
+
+void launch_zero_start(int n, const double* b, double* x, double* r, DotTarget dot, hipStream_t st) {
+    hipLaunchKernelGGL(zero_start_kernel, dim3(vec_grid(n)), dim3(kBlock), 0, st, n, b, x, r, dot);
     finish_dot(dot, vec_grid(n), st);
 }
 

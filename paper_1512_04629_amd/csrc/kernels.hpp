@@ -118,6 +118,8 @@ void launch_publish_scalars(int n, const double* scal, double* host, uint32_t* f
 void launch_fill_f64(int64_t n, double* p, double v, hipStream_t st);
 // dot -> sum_i a_i b_i
 void launch_dot(int n, const double* a, const double* b, DotTarget dot, hipStream_t st);
+// x = 0, r = b, dot = ||b||^2: the start of a solve from the zero vector
+void launch_zero_start(int n, const double* b, double* x, double* r, DotTarget dot, hipStream_t st);
 // number of blocks of a vector-kernel launch over n entries (for partial buffers)
 int vector_launch_blocks(int n);
 void launch_fill_u8(int64_t n, uint8_t* p, uint8_t v, hipStream_t st);

@@ -34,8 +34,10 @@ def test_defaults_and_status_strings():
     assert (sp.theta, sp.max_coarse, sp.max_levels, sp.nu_pre, sp.nu_post) == (0.25, 49, 25, 1, 1)
     assert abs(sp.omega - 2.0 / 3.0) < 1e-16
     pp = amg.SolveParams()
+    pp.zero_guess = 7
     lib.amg_solve_params_default(C.byref(pp))
     assert (pp.method, pp.rtol, pp.maxit, pp.k, pp.s, pp.rho_max, pp.gamma_min) == (1, 1e-8, 200, 3, 1, 0.5, 0.01)
+    assert (pp.precision, pp.zero_guess) == (64, 0)
     for st in (0, 1, 2, -1, -2, -3, -4, -5, -6, -7):
         assert lib.amg_status_string(st)
 

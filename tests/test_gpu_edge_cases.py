@@ -10,8 +10,13 @@
   and sparsified operators bit-exact under diagonal and strong-neighbour
   lumping, and the solve at the parity bars;
 * a hierarchy with more sparsified levels than one launch of the count scans
-  takes: every operator as sparsified alone, row sums kept.
+  takes: every operator as sparsified alone, row sums kept;
+* the zero initial guess (zero_guess): the iterates of the solve from a
+  zeroed x, whatever x held; rejected by the block solve and for values
+  other than 0 and 1.
 """
+import ctypes as C
+
 import numpy as np
 import pytest
 
@@ -77,6 +82,47 @@ def test_zero_right_hand_side(lib, method, precision):
                  precision=precision)
     assert rg.converged and rg.iters == ro.iters == 0 and rg.status == ro.status == 0
     assert torch.count_nonzero(x).item() == 0 and not np.any(xo)
+
+
+@pytest.mark.parametrize("noalloc", [False, True])
+def test_zero_guess_start(lib, noalloc):
+    """zero_guess: the solve starts from x0 = 0 whatever x holds (x zeroed,
+    r0 = b with no product by the zero vector): the iterations, the
+    reintroductions and the iterates are those of the solve from an explicitly
+    zeroed x, and the result meets the oracle's parity bars."""
+    A = I.poisson3d(20)
+    b = I.rhs(A.n, 3)
+    g, o = both(A)
+    kw = dict(method=1, tol=1e-8, maxit=100, adaptive=True, k=3, s=1, rho_max=0.5)
+    g.sparsify(0.1, 2)
+    x0 = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    r0 = g.solve(dev(b), x0, noalloc=noalloc, **kw)
+    g.sparsify(0.1, 2)
+    gen = torch.Generator(device="cuda").manual_seed(11)
+    x1 = 10.0 * torch.randn(A.n, dtype=torch.float64, device="cuda", generator=gen)
+    r1 = g.solve(dev(b), x1, noalloc=noalloc, zero_guess=True, **kw)
+    assert r1.converged and (r1.iters, r1.reintroductions) == (r0.iters, r0.reintroductions)
+    assert torch.equal(x1, x0)
+    nb = float(np.linalg.norm(b))
+    assert abs(r1.hist[0] - nb) <= 1e-13 * nb
+    assert abs(r1.relres - r0.relres) <= 1e-12 * r0.relres
+    o.sparsify_from(0.1, 2)
+    xo, ro = o.solve(b, **kw)
+    _assert_solve_parity(host(x1), r1, xo, ro, kw["tol"])
+
+
+def test_zero_guess_rejected_by_block_solve(lib):
+    A = I.poisson2d(16)
+    g = lib.Hierarchy(A)
+    p = lib.SolveParams(0, 1e-10, 10, 0, 3, 1, 0.5, 0.01, 64, 1)
+    b = torch.zeros((A.n, 4), dtype=torch.float64, device="cuda")
+    x = torch.zeros_like(b)
+    assert g._lib.amg_solve_block(g._h, 4, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), C.byref(p),
+                                  None, None, None) == -1
+    p.zero_guess = 2
+    assert g._lib.amg_solve(g._h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), C.byref(p), None,
+                            None) == -1
+    g.close()
 
 
 @pytest.mark.parametrize("lumping", ["diagonal", "strong"])
