@@ -1024,9 +1024,11 @@ void ensure_solve_buffers(amg_ctx* h) {
 // through the stream's status) instead of waiting for a copy and a stream
 // synchronization.  Only the slots are guaranteed on return: a caller that
 // needs another download complete synchronizes the stream itself.
-const double* read_scalars(amg_ctx* h) {
+// The scalar slots as the device holds them once the stream reaches this
+// point; with extra, slot S_COUNT of the result holds *extra.
+const double* read_scalars(amg_ctx* h, const int* extra = nullptr) {
     const uint32_t seq = ++h->pub_seq;
-    launch_publish_scalars(S_COUNT, h->scal, h->pinned_dev, h->flag_dev, seq, h->stream);
+    launch_publish_scalars(S_COUNT, h->scal, h->pinned_dev, h->flag_dev, seq, extra, h->stream);
     check_launch();
     const uint32_t* flag = h->flag_host;
     for (uint64_t k = 1; __atomic_load_n(flag, __ATOMIC_ACQUIRE) != seq; ++k) {
@@ -1105,15 +1107,14 @@ amg_status solve(amg_ctx* h, const double* b, double* x, const amg_solve_params&
     } else {
         row_op(h, AMG_K_RESIDUAL, 0, kResidNorm, A, x, b, nullptr, r, nullptr, S_NR2);
     }
-    int singular = 0;
-    if (h->check_singular) {
-        download(h, &singular, h->singular, 1);
-        sync(h);
-    }
-    const double nr0 = std::sqrt(read_scalars(h)[S_NR2]);
-    if (h->check_singular) {
+    // a pivot flag of the coarsest inversion not read yet comes back with the
+    // initial residual norm
+    const bool check = h->check_singular;
+    const double* sc0 = read_scalars(h, check ? h->singular : nullptr);
+    const double nr0 = std::sqrt(sc0[S_NR2]);
+    if (check) {
         h->check_singular = false;
-        if (singular) throw AmgFailure{AMG_ERR_BAD_MATRIX, "coarsest operator is singular"};
+        if (sc0[S_COUNT] != 0.0) throw AmgFailure{AMG_ERR_BAD_MATRIX, "coarsest operator is singular"};
     }
     if (hist) hist[0] = nr0;
     double nws = nr0;
@@ -1416,15 +1417,11 @@ amg_status solve_block(amg_ctx* h, int k, int nrhs, const double* b, double* x, 
     launch_fill_f64(S_COUNT, h->scal, 0.0, h->stream);
     launch_fill_f64(1, h->scal + S_LIVE, (double)nrhs, h->stream);
     block_outer<T>(h, k, b, x);
-    int singular = 0;
-    if (h->check_singular) {
-        download(h, &singular, h->singular, 1);
-        sync(h);
-    }
-    const double* sc = read_scalars(h);
-    if (h->check_singular) {
+    const bool check = h->check_singular;
+    const double* sc = read_scalars(h, check ? h->singular : nullptr);
+    if (check) {
         h->check_singular = false;
-        if (singular) throw AmgFailure{AMG_ERR_BAD_MATRIX, "coarsest operator is singular"};
+        if (sc[S_COUNT] != 0.0) throw AmgFailure{AMG_ERR_BAD_MATRIX, "coarsest operator is singular"};
     }
     double nr0[kMaxBlockRhs], rel[kMaxBlockRhs];
     int first[kMaxBlockRhs];
@@ -1520,15 +1517,11 @@ amg_status solve_block_pcg(amg_ctx* h, int k, int nrhs, const double* b, double*
     launch_fill_f64(S_COUNT, h->scal, 0.0, h->stream);
     launch_fill_f64(1, h->scal + S_LIVE, (double)nrhs, h->stream);
     block_outer<T>(h, k, b, x, h->bcg_r);
-    int singular = 0;
-    if (h->check_singular) {
-        download(h, &singular, h->singular, 1);
-        sync(h);
-    }
-    const double* sc = read_scalars(h);
-    if (h->check_singular) {
+    const bool check = h->check_singular;
+    const double* sc = read_scalars(h, check ? h->singular : nullptr);
+    if (check) {
         h->check_singular = false;
-        if (singular) throw AmgFailure{AMG_ERR_BAD_MATRIX, "coarsest operator is singular"};
+        if (sc[S_COUNT] != 0.0) throw AmgFailure{AMG_ERR_BAD_MATRIX, "coarsest operator is singular"};
     }
     double nr0[kMaxBlockRhs], rel[kMaxBlockRhs];
     int first[kMaxBlockRhs];
@@ -2100,12 +2093,12 @@ void finish_setup(amg_ctx* h) {
     check_launch();
     // the scalar slots, then the readback's sequence word, host-coherent so
     // that the device's writes reach the host without a copy
-    HIP_CHECK(hipHostMalloc((void**)&h->pinned, sizeof(double) * S_COUNT + 64,
+    HIP_CHECK(hipHostMalloc((void**)&h->pinned, sizeof(double) * (S_COUNT + 1) + 64,
                             hipHostMallocCoherent | hipHostMallocMapped));
-    h->flag_host = reinterpret_cast<uint32_t*>(h->pinned + S_COUNT);
+    h->flag_host = reinterpret_cast<uint32_t*>(h->pinned + S_COUNT + 1);
     *h->flag_host = 0;
     HIP_CHECK(hipHostGetDevicePointer((void**)&h->pinned_dev, h->pinned, 0));
-    h->flag_dev = reinterpret_cast<uint32_t*>(h->pinned_dev + S_COUNT);
+    h->flag_dev = reinterpret_cast<uint32_t*>(h->pinned_dev + S_COUNT + 1);
     sync(h);
     refresh_coarse_inverse(h);
     h->prof.assign((size_t)AMG_K_NUM * h->lv.size(), ProfAcc{});

@@ -1959,16 +1959,19 @@ void launch_scaled_copy(int n, double* y, const double* dinv, const double* x, d
 }
 
 __global__ __launch_bounds__(256) void publish_scalars_kernel(int n, const double* __restrict__ scal,
-                                                            double* host, uint32_t* flag, uint32_t seq) {
+                                                            double* host, uint32_t* flag, uint32_t seq,
+                                                            const int* extra) {
     for (int i = threadIdx.x; i < n; i += 256) host[i] = scal[i];
+    if (threadIdx.x == 0) host[n] = extra ? (double)*extra : 0.0;
     // every thread's writes reach the system before the workgroup's flag
     __threadfence_system();
     __syncthreads();
     if (threadIdx.x == 0) __hip_atomic_store(flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-void launch_publish_scalars(int n, const double* scal, double* host, uint32_t* flag, uint32_t seq, hipStream_t st) {
-    hipLaunchKernelGGL(publish_scalars_kernel, dim3(1), dim3(256), 0, st, n, scal, host, flag, seq);
+void launch_publish_scalars(int n, const double* scal, double* host, uint32_t* flag, uint32_t seq,
+                            const int* extra, hipStream_t st) {
+    hipLaunchKernelGGL(publish_scalars_kernel, dim3(1), dim3(256), 0, st, n, scal, host, flag, seq, extra);
 }
 
 void launch_copy(int n, double* y, const double* x, hipStream_t st) {

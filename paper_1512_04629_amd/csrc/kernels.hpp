@@ -112,9 +112,11 @@ void launch_cg_update_p(int n, double* p, const double* z, const double* scal, i
 void launch_scaled_copy(int n, double* y, const double* dinv, const double* x, double omega,
                         hipStream_t st);
 void launch_copy(int n, double* y, const double* x, hipStream_t st);
-// host[0..n) = scal[0..n) into host-coherent memory, then *flag = seq (one
-// workgroup; the values are visible to the host before the flag)
-void launch_publish_scalars(int n, const double* scal, double* host, uint32_t* flag, uint32_t seq, hipStream_t st);
+// host[0..n) = scal[0..n) and host[n] = *extra (0 if extra is null) into
+// host-coherent memory, then *flag = seq (one workgroup; the values are
+// visible to the host before the flag)
+void launch_publish_scalars(int n, const double* scal, double* host, uint32_t* flag, uint32_t seq,
+                            const int* extra, hipStream_t st);
 void launch_fill_f64(int64_t n, double* p, double v, hipStream_t st);
 // dot -> sum_i a_i b_i
 void launch_dot(int n, const double* a, const double* b, DotTarget dot, hipStream_t st);
