@@ -1377,13 +1377,39 @@ __global__ __launch_bounds__(kBlock) void compact_lump_merged_kernel(SparsifyLev
 // Inverse of the dense coarsest operator (n <= kDenseInvMax) by Gauss-Jordan
 // elimination with partial pivoting in LDS, one block.  *singular = 1 if a
 // pivot is zero.  Per column c, three steps between barriers: the pivot row
-// (one wave, a shuffle tree), then the scaled pivot row P = M[pr] / d (and
-// V's), the multipliers F[i] = M[i][c] and the row swap, then every element
-// M[i][j] -= F[i] P[j] (V likewise), row c = P and column c zeroed.  The
-// operations on every element are those of the textbook order (swap, scale
-// row c, eliminate with the scaled row, zero column c).
+// (one wave, a DPP maximum and a ballot), then the scaled pivot row
+// P = M[pr] / d (and V's), the multipliers F[i] = M[i][c] and the row swap,
+// then every element M[i][j] -= F[i] P[j] (V likewise), row c = P and column
+// c zeroed.  The operations on every element are those of the textbook order
+// (swap, scale row c, eliminate with the scaled row, zero column c).
 constexpr int kDenseInvMax = 64;
 constexpr int kDenseInvThreads = 1024;
+constexpr int kDenseInvPerThread = kDenseInvMax * kDenseInvMax / kDenseInvThreads;
+
+// The largest unsigned 64-bit value of the wave, in every lane: an inclusive
+// maximum scan within each row of 16 lanes (DPP row_shr 1, 2, 4, 8), then
+// row_bcast 15 and 31 carry the row maxima up to lane 63, which is read
+// back.  A lane whose DPP source does not exist receives 0, the identity.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long v) {
+    const int lo = (int)(unsigned)v, hi = (int)(unsigned)(v >> 32);
+    const unsigned l2 = (unsigned)__builtin_amdgcn_update_dpp(0, lo, CTRL, ROW_MASK, 0xf, false);
+    const unsigned h2 = (unsigned)__builtin_amdgcn_update_dpp(0, hi, CTRL, ROW_MASK, 0xf, false);
+    return ((unsigned long long)h2 << 32) | l2;
+}
+
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+    unsigned long long t;
+    t = dpp_u64<0x111, 0xf>(v); v = t > v ? t : v;   // row_shr:1
+    t = dpp_u64<0x112, 0xf>(v); v = t > v ? t : v;   // row_shr:2
+    t = dpp_u64<0x114, 0xf>(v); v = t > v ? t : v;   // row_shr:4
+    t = dpp_u64<0x118, 0xf>(v); v = t > v ? t : v;   // row_shr:8
+    t = dpp_u64<0x142, 0xa>(v); v = t > v ? t : v;   // row_bcast:15 into rows 1, 3
+    t = dpp_u64<0x143, 0xc>(v); v = t > v ? t : v;   // row_bcast:31 into rows 2, 3
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, 63);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), 63);
+    return ((unsigned long long)hi << 32) | lo;
+}
 
 __global__ __launch_bounds__(kDenseInvThreads) void dense_invert_kernel(CsrView a, double* __restrict__ inv,
                                                                         int* singular) {
@@ -1401,29 +1427,32 @@ __global__ __launch_bounds__(kDenseInvThreads) void dense_invert_kernel(CsrView 
     __syncthreads();
     for (int i = threadIdx.x; i < n; i += kDenseInvThreads)
         for (int p = a.rp[i]; p < a.rp[i + 1]; ++p) M[i][a.ci[p]] = a.v[p];
+    // the elements this thread updates, (row, column) in row-major order
+    int ei[kDenseInvPerThread], ej[kDenseInvPerThread];
+#pragma unroll
+    for (int q = 0; q < kDenseInvPerThread; ++q) {
+        const int e = (int)threadIdx.x + q * kDenseInvThreads;
+        ei[q] = e < n * n ? e / n : -1;
+        ej[q] = e < n * n ? e % n : 0;
+    }
     __syncthreads();
     for (int c = 0; c < n; ++c) {
         if (threadIdx.x < 64) {
             // pivot: the first row i >= c of largest |M[i][c]| (a NaN never
             // wins, except at row c, where the scan starts), found by one wave:
-            // lane l holds row c + l (n <= 64), and a shuffle tree keeps the
-            // larger magnitude, the smaller row on ties
+            // lane l holds row c + l (n <= 64) with the key 0 (no candidate) or
+            // the magnitude's bit pattern + 1, which orders non-negative
+            // doubles as their values; the wave's largest key, then the lowest
+            // lane holding it
             const int i = c + (int)threadIdx.x;
-            double key = -1.0;
+            unsigned long long key = 0ull;
             if (i < n) {
                 const double m = fabs(M[i][c]);
-                key = m != m ? (i == c ? HUGE_VAL : -1.0) : m;
+                if (m == m) key = (unsigned long long)__double_as_longlong(m) + 1ull;
+                else if (i == c) key = (unsigned long long)__double_as_longlong(HUGE_VAL) + 1ull;
             }
-            int best = i;
-#pragma unroll
-            for (int off = 1; off < 64; off <<= 1) {
-                const double ok = __shfl_xor(key, off, 64);
-                const int ob = __shfl_xor(best, off, 64);
-                if (ok > key || (ok == key && ob < best)) {
-                    key = ok;
-                    best = ob;
-                }
-            }
+            const unsigned long long hits = __ballot(key == wave_max_u64(key));
+            const int best = c + (__ffsll((long long)hits) - 1);
             if (threadIdx.x == 0) {
                 piv = best;
                 pivd = M[best][c];
@@ -1449,8 +1478,10 @@ __global__ __launch_bounds__(kDenseInvThreads) void dense_invert_kernel(CsrView 
             F[i] = (i == pr) ? M[c][c] : M[i][c];
         }
         __syncthreads();
-        for (int e = threadIdx.x; e < n * n; e += kDenseInvThreads) {
-            const int i = e / n, j = e % n;
+#pragma unroll
+        for (int q = 0; q < kDenseInvPerThread; ++q) {
+            const int i = ei[q], j = ej[q];
+            if (i < 0) continue;
             if (i == c) {
                 M[c][j] = P[j];
                 V[c][j] = PV[j];
