@@ -812,8 +812,11 @@ T* zero_start(amg_ctx* h, int l, T* x0) {
 // the first sweep omega D^-1 b0 (written by the CG update).  dot_slot >= 0
 // (FP64 only): accumulate b0 . x0 (the CG inner product r.z) into that slot.
 // The result is left in x0.
+// l0_resid_ready: with guess0 = kPrescaled and one pre-sweep, the level-0
+// residual of the prescaled sweep is already in level 0's r (formed together
+// with the window's true residual), so the cycle does not form it again.
 template <class T>
-void vcycle(amg_ctx* h, const T* b0, T* x0, Guess guess0, int dot_slot) {
+void vcycle(amg_ctx* h, const T* b0, T* x0, Guess guess0, int dot_slot, bool l0_resid_ready = false) {
     const int L = (int)h->lv.size() - 1;
     const int pre = h->sp.nu_pre, post = h->sp.nu_post;
     const T omega = (T)h->sp.omega;
@@ -853,7 +856,8 @@ void vcycle(amg_ctx* h, const T* b0, T* x0, Guess guess0, int dot_slot) {
         } else {
             jacobi_sweeps<T>(h, l, v, b, cur[l], alt[l], pre, -1);
         }
-        if (!have_resid) {
+        const bool ready0 = l == 0 && l0_resid_ready && zero && pre == 1 && prescaled;
+        if (!have_resid && !ready0) {
             const int kind = (zero && pre == 1) ? AMG_K_JACOBI_ZERO : AMG_K_RESIDUAL;
             row_op_t(h, kind, l, kResid, *v.Ah, v.ahv, cur[l], b, nullptr, v.r, nullptr, -1);
         }
@@ -1067,14 +1071,14 @@ amg_status do_reintroduce(amg_ctx* h, int s, double gamma_min, int* first) {
 // z = V(r, 0) for CG, with r.z accumulated into dot_slot.  Mixed: the cycle
 // runs on r32 = (float) r (written by the CG update, or here when the guess is
 // kZero) and z = (double) z32.
-void precondition(amg_ctx* h, bool mixed, Guess guess, int dot_slot) {
+void precondition(amg_ctx* h, bool mixed, Guess guess, int dot_slot, bool l0_resid_ready = false) {
     const int n = h->lv[0].n;
     if (gs_on(h)) {
         vcycle_gs(h, h->cg_r, h->cg_z, Guess::kZero, dot_slot);
         return;
     }
     if (!mixed) {
-        vcycle<double>(h, h->cg_r, h->cg_z, guess, dot_slot);
+        vcycle<double>(h, h->cg_r, h->cg_z, guess, dot_slot, l0_resid_ready);
         return;
     }
     if (guess == Guess::kZero) launch_narrow(n, h->cg_r32, h->cg_r, h->stream);
@@ -1163,7 +1167,34 @@ amg_status solve(amg_ctx* h, const double* b, double* x, const amg_solve_params&
             // final residual if it converges): computed before, read back
             // with the iteration's scalars
             const bool window_end = p.adaptive && inwin + 1 == p.k;
-            if (window_end) row_op(h, AMG_K_RESIDUAL, 0, kResidNorm, A, x, b, nullptr, h->rt, nullptr, S_NRT);
+            // In the FP64 PCG with one pre-sweep, the next preconditioner's
+            // first step is the level-0 residual r - A (omega D^-1 r): it is
+            // formed in the same pass over A_0's SELL-64 copy as the true
+            // residual (used unless CG restarts).
+            bool l0_ready = false;
+            if (window_end) {
+                DevLevel& f0 = h->lv[0];
+                const bool fuse = pcg && !mixed && !gs_on(h) && h->sp.nu_pre == 1 && h->lv.size() > 1 &&
+                                  f0.ah_alias && A.sl_off != nullptr;
+                if (fuse) {
+                    const DotTarget dt = dot_to(h, S_NRT);
+                    CsrView cv = A.view();
+                    cv.rev = *A.next_rev;
+                    *A.next_rev ^= 1;
+                    int nparts = 0;
+                    {
+                        ProfScope ps(h, AMG_K_RESIDUAL, 0, true);
+                        nparts = launch_sell_dual_resid(cv, zero_start<double>(h, 0, h->cg_z), r, f0.r, x, b,
+                                                        h->rt, dt, h->stream);
+                        check_launch();
+                    }
+                    launch_dot_finish(dt, nparts, h->stream);
+                    check_launch();
+                    l0_ready = nparts > 0;
+                } else {
+                    row_op(h, AMG_K_RESIDUAL, 0, kResidNorm, A, x, b, nullptr, h->rt, nullptr, S_NRT);
+                }
+            }
             const double* sc = read_scalars(h);
             if (pcg && sc[S_FLAG] != 0.0) { st = AMG_ERR_BREAKDOWN; break; }
             const double nr = std::sqrt(sc[S_NR2]);
@@ -1204,7 +1235,7 @@ amg_status solve(amg_ctx* h, const double* b, double* x, const amg_solve_params&
             if (pcg) {
                 const int new_slot = rz_slot == S_RZ0 ? S_RZ1 : S_RZ0;
                 // after a restart r was rebuilt, so the prescaled sweep is stale
-                precondition(h, mixed, restart ? Guess::kZero : Guess::kPrescaled, new_slot);
+                precondition(h, mixed, restart ? Guess::kZero : Guess::kPrescaled, new_slot, l0_ready && !restart);
                 if (restart) {
                     info.restarts++;
                     launch_copy(n, h->cg_p, h->cg_z, h->stream);

@@ -795,6 +795,79 @@ __global__ __launch_bounds__(kBlock) void sell_kernel(CsrT<T> a, const T* __rest
     if constexpr (op_has_dot<OP>()) store_block_partial(contrib, dot.partials, pidx);
 }
 
+// Two residuals of one operator in one pass over its SELL-64 copy:
+// y = u - A g and y2 = u2 - A g2 with the block partials of ||y2||^2.  Each
+// entry is loaded once and both vectors gathered; every row is summed in the
+// order sell_kernel sums it and the partials go to the same indices, so both
+// results are those of the kResid and kResidNorm launches bit for bit.
+template <int U, bool NT, int IDXW>
+__global__ __launch_bounds__(kBlock) void sell_dual_resid_kernel(CsrView a, const double* __restrict__ g,
+                                                                 const double* u, double* y,
+                                                                 const double* __restrict__ g2,
+                                                                 const double* u2, double* y2, DotTarget dot,
+                                                                 int nslices) {
+    const int lb = xcd_logical_block();
+    const int wv = (int)threadIdx.x / kSellRows;
+    const int lane = (int)threadIdx.x & (kSellRows - 1);
+    const int nblocks = (nslices + kSellSlicesPerBlock - 1) / kSellSlicesPerBlock;
+    double contrib = 0.0;
+    int pidx = lb;
+    for (int lblk = lb; lblk < nblocks; lblk += gridDim.x) {
+        const int blk = a.rev ? nblocks - 1 - lblk : lblk;
+        if (nblocks <= (int)gridDim.x) pidx = blk;
+        const int sl = blk * kSellSlicesPerBlock + wv;
+        if (sl >= nslices) continue;
+        const int o0 = a.sl_off[sl];
+        const int w = (a.sl_off[sl + 1] - o0) / kSellRows;
+        const int cb = IDXW == 2 ? a.sl_base[sl] : 0;
+        const int tabv = IDXW == 1 ? a.sl_tab[sl * kSellRows + lane] : 0;
+        const int r = sl * kSellRows + lane;
+        const bool act = r < a.rows;
+        double ui = 0.0, u2i = 0.0;
+        if (act) {
+            ui = u[r];
+            u2i = u2[r];
+        }
+        double acc = 0.0, acc2 = 0.0;
+        for (int k0 = 0; k0 < w; k0 += U) {
+            int jj[U];
+            double vv[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const int p = o0 + min(k0 + k, w - 1) * kSellRows + lane;
+                if constexpr (IDXW == 1) {
+                    const int d = __shfl(tabv, (int)sell_ld<NT>(a.sl_idx8 + p), 64);
+                    jj[k] = act ? r + d : 0;
+                } else if constexpr (IDXW == 2) {
+                    jj[k] = cb + (int)sell_ld<NT>(a.sl_col16 + p);
+                } else {
+                    jj[k] = sell_ld<NT>(a.sl_col + p);
+                }
+                vv[k] = sell_ld<NT>(a.sl_val + p);
+            }
+            double gg[U], gg2[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                gg[k] = g[jj[k]];
+                gg2[k] = g2[jj[k]];
+            }
+#pragma unroll
+            for (int k = 0; k < U; ++k)
+                if (k0 + k < w) {
+                    acc += vv[k] * gg[k];
+                    acc2 += vv[k] * gg2[k];
+                }
+        }
+        if (act) {
+            y[r] = ui - acc;
+            const double rr = u2i - acc2;
+            y2[r] = rr;
+            contrib += rr * rr;
+        }
+    }
+    store_block_partial(contrib, dot.partials, pidx);
+}
+
 // Matrices larger than this stream their entries with non-temporal loads:
 // they cannot stay in the 256 MB Infinity Cache between passes, and the
 // entries then do not displace the gathered vectors; smaller ones are loaded
@@ -856,6 +929,35 @@ int launch_sell_u(RowOp op, const CsrT<T>& a_in, const T* g, const T* u, const T
     }
     return (op == kResidNorm || op == kJacobiDot || op == kSpmvDot) ? grid : 0;
 }
+
+template <int U>
+int launch_sell_dual_u(const CsrView& a_in, const double* g, const double* u, double* y, const double* g2,
+                       const double* u2, double* y2, DotTarget dot, hipStream_t st) {
+    const int nslices = (a_in.rows + kSellRows - 1) / kSellRows;
+    const int grid = sell_grid(a_in.rows);
+    CsrView a = a_in;
+    // as for every launch that forms a dot product (launch_sell_u)
+    if (!AMG_STREAM_ALTERNATE || (nslices + kSellSlicesPerBlock - 1) / kSellSlicesPerBlock > grid) a.rev = 0;
+    const int iw = a.sl_idx8 ? 1 : a.sl_col16 ? 2 : 4;
+    const long long entries = (long long)a.rows * (long long)(a.mean_row + 0.5);
+    const bool nt = entries * (long long)(sizeof(double) + iw) > (long long)AMG_SELL_NT_BYTES;
+#define AMG_DUAL_LAUNCH(NTV, IW)                                                                       \
+    launch_row_kernel(sell_dual_resid_kernel<U, NTV, IW>, dim3(grid), dim3(kBlock), st, a, g, u, y, g2, u2, y2, \
+                      dot, nslices)
+    if (iw == 1) {
+        if (nt) AMG_DUAL_LAUNCH(true, 1);
+        else AMG_DUAL_LAUNCH(false, 1);
+    } else if (iw == 2) {
+        if (nt) AMG_DUAL_LAUNCH(true, 2);
+        else AMG_DUAL_LAUNCH(false, 2);
+    } else {
+        if (nt) AMG_DUAL_LAUNCH(true, 4);
+        else AMG_DUAL_LAUNCH(false, 4);
+    }
+#undef AMG_DUAL_LAUNCH
+    return grid;
+}
+
 
 template <class T>
 int launch_sell(RowOp op, const CsrT<T>& a, const T* g, const T* u, const T* dinv, T omega, T* y, T* y2,
@@ -2059,6 +2161,18 @@ void launch_fill_f64(int64_t n, double* p, double v, hipStream_t st) {
 void launch_dot(int n, const double* a, const double* b, DotTarget dot, hipStream_t st) {
     hipLaunchKernelGGL(dot_kernel, dim3(vec_grid(n)), dim3(kBlock), 0, st, n, a, b, dot);
     finish_dot(dot, vec_grid(n), st);
+}
+
+int launch_sell_dual_resid(const CsrView& a, const double* g, const double* u, double* y, const double* g2,
+                           const double* u2, double* y2, DotTarget dot, hipStream_t st) {
+    if (!AMG_SELL || !a.sl_off) return 0;
+    const int w = a.sl_maxw;
+    if (w <= 8) return launch_sell_dual_u<8>(a, g, u, y, g2, u2, y2, dot, st);
+    if (w <= 12) return launch_sell_dual_u<12>(a, g, u, y, g2, u2, y2, dot, st);
+    if (w <= 16) return launch_sell_dual_u<16>(a, g, u, y, g2, u2, y2, dot, st);
+    if (w <= 20) return launch_sell_dual_u<20>(a, g, u, y, g2, u2, y2, dot, st);
+    if (w <= 24) return launch_sell_dual_u<24>(a, g, u, y, g2, u2, y2, dot, st);
+    return launch_sell_dual_u<32>(a, g, u, y, g2, u2, y2, dot, st);
 }
 
 void launch_zero_start(int n, const double* b, double* x, double* r, DotTarget dot, hipStream_t st) {

@@ -120,6 +120,12 @@ void launch_publish_scalars(int n, const double* scal, double* host, uint32_t* f
 void launch_fill_f64(int64_t n, double* p, double v, hipStream_t st);
 // dot -> sum_i a_i b_i
 void launch_dot(int n, const double* a, const double* b, DotTarget dot, hipStream_t st);
+// y = u - A g and y2 = u2 - A g2 with ||y2||^2 into dot, in one pass over the
+// SELL-64 copy of A (the bits of the two separate residual launches);
+// returns the number of partials to finish, 0 (nothing launched) when A has
+// no SELL-64 copy
+int launch_sell_dual_resid(const CsrView& a, const double* g, const double* u, double* y, const double* g2,
+                           const double* u2, double* y2, DotTarget dot, hipStream_t st);
 // x = 0, r = b, dot = ||b||^2: the start of a solve from the zero vector
 void launch_zero_start(int n, const double* b, double* x, double* r, DotTarget dot, hipStream_t st);
 // number of blocks of a vector-kernel launch over n entries (for partial buffers)

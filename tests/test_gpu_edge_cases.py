@@ -13,7 +13,9 @@
   takes: every operator as sparsified alone, row sums kept;
 * the zero initial guess (zero_guess): the iterates of the solve from a
   zeroed x, whatever x held; rejected by the block solve and for values
-  other than 0 and 1.
+  other than 0 and 1;
+* the adaptive windows' fused residual pass: without a reintroduction the
+  iterates of the plain PCG, bit for bit.
 """
 import ctypes as C
 
@@ -109,6 +111,30 @@ def test_zero_guess_start(lib, noalloc):
     o.sparsify_from(0.1, 2)
     xo, ro = o.solve(b, **kw)
     _assert_solve_parity(host(x1), r1, xo, ro, kw["tol"])
+
+
+def test_adaptive_windows_keep_the_pcg_iterates(lib):
+    """The adaptive solve forms the true residual every k iterations, in one
+    pass over A_0's SELL-64 copy together with the next preconditioner's
+    level-0 residual.  Without a reintroduction (rho_max out of reach) the
+    iterates and the residual history are those of the plain PCG bit for
+    bit."""
+    A = I.poisson3d(72)
+    b = I.rhs(A.n, 4)
+    g = lib.Hierarchy(A)
+    assert g.row_format(0, "A") == "sell"
+    kw = dict(method=1, tol=1e-10, maxit=100)
+    g.sparsify(0.1, 2)
+    x1 = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    r1 = g.solve(dev(b), x1, **kw)
+    g.sparsify(0.1, 2)
+    x2 = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    r2 = g.solve(dev(b), x2, adaptive=True, k=3, s=1, rho_max=1e9, **kw)
+    assert r1.converged and r2.converged and r2.reintroductions == 0
+    assert r1.iters == r2.iters and r1.iters >= 6
+    assert np.array_equal(r1.hist, r2.hist)
+    assert torch.equal(x1, x2)
+    g.close()
 
 
 def test_zero_guess_rejected_by_block_solve(lib):
