@@ -1106,7 +1106,7 @@ amg_status solve(amg_ctx* h, const double* b, double* x, const amg_solve_params&
     if (p.zero_guess) {
         // x0 = 0: r0 = b - A 0 = b
         ProfScope ps(h, AMG_K_VECTOR, 0);
-        launch_zero_start(n, b, x, r, dot_to(h, S_NR2), h->stream);
+        launch_zero_guess_start(n, b, x, r, dot_to(h, S_NR2), h->stream);
         check_launch();
     } else {
         row_op(h, AMG_K_RESIDUAL, 0, kResidNorm, A, x, b, nullptr, r, nullptr, S_NR2);

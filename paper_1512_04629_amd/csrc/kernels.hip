@@ -1223,9 +1223,9 @@ __global__ __launch_bounds__(kBlock) void dot_kernel(int n, const double* __rest
 
 // Start from x0 = 0: x = 0, r = b (the residual of the zero vector) and the
 // block partials of ||b||^2.
-__global__ __launch_bounds__(kBlock) void zero_start_kernel(int n, const double* __restrict__ b,
-                                                            double* __restrict__ x, double* __restrict__ r,
-                                                            DotTarget dot) {
+__global__ __launch_bounds__(kBlock) void zero_guess_start_kernel(int n, const double* __restrict__ b,
+                                                                  double* __restrict__ x, double* __restrict__ r,
+                                                                  DotTarget dot) {
     double s = 0.0;
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
         const double bi = b[i];
@@ -2175,8 +2175,8 @@ int launch_sell_dual_resid(const CsrView& a, const double* g, const double* u, d
     return launch_sell_dual_u<32>(a, g, u, y, g2, u2, y2, dot, st);
 }
 
-void launch_zero_start(int n, const double* b, double* x, double* r, DotTarget dot, hipStream_t st) {
-    hipLaunchKernelGGL(zero_start_kernel, dim3(vec_grid(n)), dim3(kBlock), 0, st, n, b, x, r, dot);
+void launch_zero_guess_start(int n, const double* b, double* x, double* r, DotTarget dot, hipStream_t st) {
+    hipLaunchKernelGGL(zero_guess_start_kernel, dim3(vec_grid(n)), dim3(kBlock), 0, st, n, b, x, r, dot);
     finish_dot(dot, vec_grid(n), st);
 }
 

@@ -127,7 +127,7 @@ void launch_dot(int n, const double* a, const double* b, DotTarget dot, hipStrea
 int launch_sell_dual_resid(const CsrView& a, const double* g, const double* u, double* y, const double* g2,
                            const double* u2, double* y2, DotTarget dot, hipStream_t st);
 // x = 0, r = b, dot = ||b||^2: the start of a solve from the zero vector
-void launch_zero_start(int n, const double* b, double* x, double* r, DotTarget dot, hipStream_t st);
+void launch_zero_guess_start(int n, const double* b, double* x, double* r, DotTarget dot, hipStream_t st);
 // number of blocks of a vector-kernel launch over n entries (for partial buffers)
 int vector_launch_blocks(int n);
 void launch_fill_u8(int64_t n, uint8_t* p, uint8_t v, hipStream_t st);
