@@ -1188,12 +1188,13 @@ amg_status solve(amg_ctx* h, const double* b, double* x, const amg_solve_params&
                                                         h->rt, dt, h->stream);
                         check_launch();
                     }
-                    launch_dot_finish(dt, nparts, h->stream);
-                    check_launch();
-                    l0_ready = nparts > 0;
-                } else {
-                    row_op(h, AMG_K_RESIDUAL, 0, kResidNorm, A, x, b, nullptr, h->rt, nullptr, S_NRT);
+                    if (nparts > 0) {
+                        launch_dot_finish(dt, nparts, h->stream);
+                        check_launch();
+                        l0_ready = true;
+                    }
                 }
+                if (!l0_ready) row_op(h, AMG_K_RESIDUAL, 0, kResidNorm, A, x, b, nullptr, h->rt, nullptr, S_NRT);
             }
             const double* sc = read_scalars(h);
             if (pcg && sc[S_FLAG] != 0.0) { st = AMG_ERR_BREAKDOWN; break; }
